@@ -1,0 +1,198 @@
+/*
+ * dfisher - damped Fisher solves on AMD Instinct MI355X (gfx950).
+ *
+ * Solves the damped Fisher system of Eq. 1 of Chen, Xie & Wang, "Efficient Numerical
+ * Algorithm for Large-Scale Damped Natural Gradient Descent" (arXiv 2310.17556):
+ *
+ *     (S^T S + lambda I_m) x = v,     S in R^{n x m} (n samples, m parameters), lambda > 0,
+ *
+ * with Algorithm 1 (Section 2): W = S S^T + lambda I_n, L = Chol(W), and
+ * x = (v - S^T L^-T L^-1 S v) / lambda evaluated right to left with triangular solves
+ * (the inlined form recommended after Algorithm 1), so that Q = L^-1 S is never formed.
+ *
+ * Conventions shared by every entry point
+ *   Memory     S, v, x, V, X, W, L, b, y are DEVICE pointers owned by the caller. The library
+ *              allocates only its own workspace, held by the context. Sizes are int64.
+ *   Layout     S is row-major n x m FP32 with row stride lds >= m elements (row i is sample
+ *              i's scaled score vector). n x n matrices (W, L) are row-major FP64 with row
+ *              stride n. Vectors are dense.
+ *   Streams    `stream` is a hipStream_t passed as void*; NULL is the default stream. All
+ *              device work of a call is enqueued on that stream.
+ *   Sync       Calls that factor W (dfisher_solve, dfisher_factor_create, dfisher_potrf,
+ *              dfisher_solve_batched, dfisher_solve_uneven) synchronise the stream once per
+ *              factorisation to read the Cholesky status. The others return without
+ *              synchronising.
+ *   Errors     Every call returns a dfisher_status and never aborts or throws. Arguments are
+ *              validated on the host before any device call: null pointers, n < 1, m < 1,
+ *              lds < m, lambda not finite or not > 0, and unknown enum values return
+ *              DFISHER_E_INVALID_ARG. A missing device or any HIP runtime error returns
+ *              DFISHER_E_DEVICE. dfisher_last_error() gives a per-thread message for the
+ *              last failure.
+ *   Threads    Calls on one context must not overlap. Different contexts are independent.
+ */
+#ifndef DFISHER_H
+#define DFISHER_H
+
+#include <stdint.h>
+
+#if defined(__GNUC__) || defined(__clang__)
+#define DFISHER_API __attribute__((visibility("default")))
+#else
+#define DFISHER_API
+#endif
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum dfisher_status {
+  DFISHER_OK = 0,
+  DFISHER_E_INVALID_ARG = 1,   /* rejected on the host; nothing was enqueued            */
+  DFISHER_E_NOT_SPD = 2,       /* Cholesky met a pivot that is not > 0 (info says where) */
+  DFISHER_E_NO_MEMORY = 3,     /* workspace allocation failed                            */
+  DFISHER_E_DEVICE = 4,        /* no usable device, or a HIP runtime error               */
+  DFISHER_E_UNSUPPORTED = 5    /* valid request this build does not implement            */
+} dfisher_status;
+
+/* Arithmetic of the Gram S S^T (Algorithm 1 step 1, the O(n^2 m) term of Section 2).
+ * All forms multiply on the matrix cores with FP32 accumulation inside a K-chunk and FP64
+ * accumulation across chunks; the diagonal is always the exact FP64 squared row norm. */
+typedef enum dfisher_gram_prec {
+  DFISHER_GRAM_FP32 = 0,    /* FP32 inputs, FP32 matrix-core products                      */
+  DFISHER_GRAM_BF16X3 = 1   /* split-BF16: S = hi + lo, keeps hi.hi + hi.lo + lo.hi        */
+} dfisher_gram_prec;
+
+/* What to do when the Cholesky of the computed W meets a pivot that is not > 0 (the computed
+ * Gram can lose definiteness along directions where W's eigenvalue is close to lambda). */
+typedef enum dfisher_shift_policy {
+  DFISHER_SHIFT_NONE = 0,        /* fail with DFISHER_E_NOT_SPD                                 */
+  DFISHER_SHIFT_ON_FAILURE = 1   /* refactor W + tau I with growing tau (reported in info);
+                                    refinement sweeps then correct against the unshifted W   */
+} dfisher_shift_policy;
+
+typedef struct dfisher_options {
+  int32_t gram_prec;     /* dfisher_gram_prec                                               */
+  int32_t sweeps;        /* FP64 iterative-refinement sweeps on W y = S v, 0..16: each sweep
+                            forms r = S v - lambda y - S (S^T y) with FP64 accumulation and
+                            adds L^-T L^-1 r to y                                            */
+  int32_t shift_policy;  /* dfisher_shift_policy                                            */
+  int32_t x_fp64;        /* 0: x (and X) are float*, 1: double*                             */
+} dfisher_options;
+
+/* Defaults: FP32 Gram, 0 sweeps, shift on failure, FP32 output. */
+#define DFISHER_OPTIONS_DEFAULT {DFISHER_GRAM_FP32, 0, DFISHER_SHIFT_ON_FAILURE, 0}
+
+typedef struct dfisher_info {
+  int64_t potrf_info;    /* 0, or the 1-based index of the first pivot that is not > 0 in the
+                            last factorisation attempt                                       */
+  double shift;          /* tau added to W's diagonal by the successful factorisation (0: none) */
+  int32_t attempts;      /* number of factorisations run                                      */
+  int32_t sweeps_done;   /* refinement sweeps applied                                         */
+} dfisher_info;
+
+typedef struct dfisher_ctx dfisher_ctx;        /* device id, workspace, pinned status buffer  */
+typedef struct dfisher_factor dfisher_factor;  /* owns L (FP64 n x n); borrows S              */
+
+/* Create a context on HIP device `device` (>= 0). Returns DFISHER_E_DEVICE if the device does
+ * not exist. The context owns the workspace of every call made with it. */
+DFISHER_API dfisher_status dfisher_ctx_create(int device, dfisher_ctx** out);
+/* Release a context and its workspace (NULL is accepted). Waits for the device to be idle. */
+DFISHER_API dfisher_status dfisher_ctx_destroy(dfisher_ctx* ctx);
+
+/* Per-stage device timing of the last dfisher_solve / dfisher_factor_create / dfisher_gram call
+ * made with this context: HIP events recorded on that call's stream around each stage (only
+ * while enabled; recording adds no synchronisation). dfisher_ctx_last_timing waits for the
+ * events and returns milliseconds; stages a call did not run read 0. */
+typedef struct dfisher_timing {
+  double rowpass_ms;      /* b = S v and squared row norms (one pass over S)   */
+  double gram_ms;         /* matrix-core Gram kernel (split-K partial tiles)   */
+  double gram_reduce_ms;  /* FP64 reduction of the partial tiles into W        */
+  double potrf_ms;        /* Cholesky, including any shifted retries           */
+  double trsv_ms;         /* first L^-1 / L^-T application                     */
+  double refine_ms;       /* all refinement sweeps                              */
+  double apply_ms;        /* x = (v - S^T y) / lambda (one pass over S)        */
+  double total_ms;        /* first to last event                                */
+} dfisher_timing;
+
+DFISHER_API dfisher_status dfisher_ctx_enable_timing(dfisher_ctx* ctx, int32_t enable);
+DFISHER_API dfisher_status dfisher_ctx_last_timing(dfisher_ctx* ctx, dfisher_timing* out);
+
+/* Algorithm 1 step 1: W = S S^T + lambda I_n.
+ * Writes the full symmetric n x n FP64 matrix W (row-major, both triangles). lambda >= 0 is
+ * allowed here (lambda = 0 gives the Gram G = S S^T). Off-diagonal entries use `prec`; the
+ * diagonal is the FP64 squared row norm plus lambda. */
+DFISHER_API dfisher_status dfisher_gram(dfisher_ctx* ctx, const float* S, int64_t n, int64_t m, int64_t lds,
+                            int32_t prec, double lambda, double* W, void* stream);
+
+/* Algorithm 1 step 2: in-place Cholesky W = L L^T of an n x n FP64 SPD matrix (row-major,
+ * row stride n). Reads the lower triangle only; writes L to the lower triangle and zeros the
+ * strict upper triangle. *info (host pointer) receives 0 or the 1-based index of the first
+ * pivot d with !(d > 0) (NaN fails); the call then returns DFISHER_E_NOT_SPD and the
+ * matrix contents are unspecified. Synchronises the stream. */
+DFISHER_API dfisher_status dfisher_potrf(dfisher_ctx* ctx, double* W, int64_t n, int64_t* info, void* stream);
+
+/* b = S v (FP32 inputs, FP64 accumulation, FP64 output of length n): the first product of the
+ * right-to-left evaluation of S^T L^-T L^-1 S v (Section 2, after Algorithm 1). */
+DFISHER_API dfisher_status dfisher_gemv(dfisher_ctx* ctx, const float* S, int64_t n, int64_t m, int64_t lds,
+                            const float* v, double* b, void* stream);
+
+/* Triangular solves with the Cholesky factor (row-major n x n FP64, lower triangle used):
+ * trans = 0: y = L^-1 b (forward substitution); trans = 1: y = L^-T b (back substitution).
+ * b and y are FP64 device vectors of length n and may alias. */
+DFISHER_API dfisher_status dfisher_trsv(dfisher_ctx* ctx, const double* L, int64_t n, int32_t trans,
+                            const double* b, double* y, void* stream);
+
+/* Final step of Algorithm 1 with Q inlined: x = (v - S^T y) / lambda, FP64 accumulation over the
+ * n samples. y is FP64 (length n); x is FP32 (x_fp64 = 0) or FP64 (x_fp64 = 1), length m, and
+ * may alias v when both are FP32. */
+DFISHER_API dfisher_status dfisher_apply(dfisher_ctx* ctx, const float* S, int64_t n, int64_t m, int64_t lds,
+                             const float* v, const double* y, double lambda, void* x, int32_t x_fp64,
+                             void* stream);
+
+/* Algorithm 1 end to end: x solving (S^T S + lambda I) x = v. v is FP32 (length m); x is FP32
+ * or FP64 per opt->x_fp64 and may alias v when FP32. opt NULL = defaults; info may be NULL. */
+DFISHER_API dfisher_status dfisher_solve(dfisher_ctx* ctx, const float* S, int64_t n, int64_t m, int64_t lds,
+                             const float* v, double lambda, void* x, const dfisher_options* opt,
+                             void* stream, dfisher_info* info);
+
+/* Factor reuse: steps 1-2 of Algorithm 1 once (Gram + Cholesky, with the shift policy), then
+ * any number of right-hand sides. The factor BORROWS S: S must stay valid and unchanged until
+ * dfisher_factor_destroy. The factor keeps a pointer to ctx, which must outlive it. */
+DFISHER_API dfisher_status dfisher_factor_create(dfisher_ctx* ctx, const float* S, int64_t n, int64_t m, int64_t lds,
+                                     double lambda, const dfisher_options* opt, void* stream,
+                                     dfisher_factor** out, dfisher_info* info);
+/* Solve for nrhs right-hand sides: V is nrhs x m FP32 (row r = v_r, row stride ldv >= m);
+ * X is nrhs x m (row stride ldx >= m), FP32 or FP64 per the factor's options. */
+DFISHER_API dfisher_status dfisher_factor_solve(dfisher_factor* f, const float* V, int64_t nrhs, int64_t ldv,
+                                    void* X, int64_t ldx, void* stream, dfisher_info* info);
+/* Copy the factor's L (n x n FP64 row-major, zero strict upper triangle) to device memory. */
+DFISHER_API dfisher_status dfisher_factor_copy_L(const dfisher_factor* f, double* L, void* stream);
+DFISHER_API dfisher_status dfisher_factor_destroy(dfisher_factor* f);
+
+/* Many damping values and right-hand sides sharing one Gram: for every lambda_l (nlam values,
+ * host array) and every row v_r of V (nrhs x m FP32, stride ldv), X[(l * nrhs + r) * ldx + k]
+ * holds x_{l,r} solving (S^T S + lambda_l I) x = v_r. infos (host, may be NULL) has nlam
+ * entries. The Gram is formed once; each lambda_l gets its own Cholesky of G + lambda_l I. */
+DFISHER_API dfisher_status dfisher_solve_batched(dfisher_ctx* ctx, const float* S, int64_t n, int64_t m, int64_t lds,
+                                     const double* lambdas, int32_t nlam, const float* V, int32_t nrhs,
+                                     int64_t ldv, void* X, int64_t ldx, const dfisher_options* opt,
+                                     void* stream, dfisher_info* infos);
+
+/* Independent problems of different sizes (for example per-layer Fisher blocks): problem p
+ * solves (S_p^T S_p + lambda_p I) x_p = v_p with S_p n[p] x m[p] (stride lds[p]). All arrays
+ * of length nprob are HOST arrays of device pointers / sizes. infos (host, may be NULL) has
+ * nprob entries. */
+DFISHER_API dfisher_status dfisher_solve_uneven(dfisher_ctx* ctx, int32_t nprob, const float* const* S, const int64_t* n,
+                                    const int64_t* m, const int64_t* lds, const float* const* v,
+                                    const double* lambda, void* const* x, const dfisher_options* opt,
+                                    void* stream, dfisher_info* infos);
+
+/* Static text for a status code. */
+DFISHER_API const char* dfisher_status_string(dfisher_status s);
+/* Message describing the last failure on the calling thread ("" if none). */
+DFISHER_API const char* dfisher_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DFISHER_H */

@@ -1,0 +1,730 @@
+// C ABI of the dfisher library: argument checks, workspace, and the order of device work for
+// Algorithm 1 (Section 2) with the Q-inlined right-to-left apply, the Cholesky shift policy and
+// FP64 iterative refinement on W y = S v. All arithmetic runs in the HIP kernels of this
+// directory; this file only validates, plans, allocates and launches.
+#include "dfisher.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "dfisher_internal.h"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+dfisher_status fail(dfisher_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return s;
+}
+
+#define HIP_TRY(expr)                                                                          \
+  do {                                                                                         \
+    hipError_t e_ = (expr);                                                                    \
+    if (e_ != hipSuccess)                                                                      \
+      return fail(DFISHER_E_DEVICE, "%s failed: %s (%s:%d)", #expr, hipGetErrorString(e_),     \
+                  __FILE__, __LINE__);                                                         \
+  } while (0)
+
+#define DF_TRY(expr)                   \
+  do {                                 \
+    dfisher_status s_ = (expr);        \
+    if (s_ != DFISHER_OK) return s_;   \
+  } while (0)
+
+constexpr int64_t TRSV_MAX_N = 15000;   // the triangular solves keep the solution in LDS
+constexpr int MAX_SWEEPS = 16;
+constexpr int MAX_SHIFT_ATTEMPTS = 10;
+
+size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
+
+}  // namespace
+
+constexpr int NEV = 8;  // stage boundaries: rowpass | gram | reduce | potrf | trsv | refine | apply |
+
+struct dfisher_ctx {
+  int device = 0;
+  bool timing = false;
+  bool ev_used[NEV] = {};
+  hipEvent_t ev[NEV] = {};
+  void* ws = nullptr;
+  size_t ws_bytes = 0;
+  int64_t* h_status = nullptr;  // pinned: [0] potrf info
+  double* h_scalar = nullptr;   // pinned: [0] diagonal max
+  int64_t* d_info = nullptr;
+  int32_t* d_flag = nullptr;
+  double* d_scalar = nullptr;
+};
+
+struct dfisher_factor {
+  dfisher_ctx* ctx = nullptr;
+  const float* S = nullptr;
+  int64_t n = 0, m = 0, lds = 0;
+  double lambda = 0.0;
+  dfisher_options opt{};
+  double* L = nullptr;  // owned
+  double shift = 0.0;
+};
+
+namespace {
+
+// Records stage-boundary events on the call's stream when timing is enabled.
+struct StageClock {
+  dfisher_ctx* ctx;
+  hipStream_t st;
+  StageClock(dfisher_ctx* c, hipStream_t s) : ctx(c), st(s) {
+    for (int i = 0; i < NEV; ++i) ctx->ev_used[i] = false;
+  }
+  void mark(int i) {
+    if (ctx->timing && hipEventRecord(ctx->ev[i], st) == hipSuccess) ctx->ev_used[i] = true;
+  }
+};
+
+struct DeviceGuard {
+  int prev = -1;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+    (void)hipSetDevice(dev);
+  }
+  ~DeviceGuard() {
+    if (prev >= 0) (void)hipSetDevice(prev);
+  }
+};
+
+dfisher_status ensure_ws(dfisher_ctx* ctx, size_t bytes) {
+  if (bytes <= ctx->ws_bytes) return DFISHER_OK;
+  if (ctx->ws) {
+    HIP_TRY(hipDeviceSynchronize());
+    HIP_TRY(hipFree(ctx->ws));
+    ctx->ws = nullptr;
+    ctx->ws_bytes = 0;
+  }
+  hipError_t e = hipMalloc(&ctx->ws, bytes);
+  if (e != hipSuccess) {
+    ctx->ws = nullptr;
+    (void)hipGetLastError();
+    return fail(DFISHER_E_NO_MEMORY, "workspace allocation of %zu bytes failed: %s", bytes, hipGetErrorString(e));
+  }
+  ctx->ws_bytes = bytes;
+  return DFISHER_OK;
+}
+
+// Carves aligned sub-buffers out of one workspace block.
+struct Carver {
+  size_t off = 0;
+  char* base = nullptr;
+  template <typename T>
+  T* take(size_t count) {
+    T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+    off += align_up(count * sizeof(T));
+    return p;
+  }
+};
+
+bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
+
+dfisher_status check_ctx(dfisher_ctx* ctx) {
+  if (!ctx) return fail(DFISHER_E_INVALID_ARG, "ctx is NULL");
+  return DFISHER_OK;
+}
+
+dfisher_status check_S(const float* S, int64_t n, int64_t m, int64_t lds) {
+  if (!S) return fail(DFISHER_E_INVALID_ARG, "S is NULL");
+  if (n < 1) return fail(DFISHER_E_INVALID_ARG, "n = %lld < 1", (long long)n);
+  if (m < 1) return fail(DFISHER_E_INVALID_ARG, "m = %lld < 1", (long long)m);
+  if (lds < m) return fail(DFISHER_E_INVALID_ARG, "lds = %lld < m = %lld", (long long)lds, (long long)m);
+  return DFISHER_OK;
+}
+
+dfisher_status check_opt(const dfisher_options* opt, dfisher_options* out) {
+  dfisher_options d = DFISHER_OPTIONS_DEFAULT;
+  if (opt) d = *opt;
+  if (d.gram_prec != DFISHER_GRAM_FP32 && d.gram_prec != DFISHER_GRAM_BF16X3)
+    return fail(DFISHER_E_INVALID_ARG, "unknown gram_prec %d", d.gram_prec);
+  if (d.sweeps < 0 || d.sweeps > MAX_SWEEPS)
+    return fail(DFISHER_E_INVALID_ARG, "sweeps = %d outside 0..%d", d.sweeps, MAX_SWEEPS);
+  if (d.shift_policy != DFISHER_SHIFT_NONE && d.shift_policy != DFISHER_SHIFT_ON_FAILURE)
+    return fail(DFISHER_E_INVALID_ARG, "unknown shift_policy %d", d.shift_policy);
+  if (d.x_fp64 != 0 && d.x_fp64 != 1) return fail(DFISHER_E_INVALID_ARG, "x_fp64 must be 0 or 1");
+  *out = d;
+  return DFISHER_OK;
+}
+
+dfisher_status check_trsv_n(int64_t n) {
+  if (n > TRSV_MAX_N)
+    return fail(DFISHER_E_UNSUPPORTED, "n = %lld exceeds the triangular-solve limit %lld", (long long)n,
+                (long long)TRSV_MAX_N);
+  return DFISHER_OK;
+}
+
+hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+// Everything one factorisation + solve needs, carved from the workspace.
+struct SolveBufs {
+  double* W;       // n x n, unshifted W (lower triangle)
+  double* L;       // n x n factor (unless the caller supplies one)
+  float* gpart;    // Gram partial tiles
+  double* rpart;   // row-pass partials
+  double* cpart;   // column-pass partials
+  double* b;       // S v
+  double* d;       // squared row norms
+  double* z;       // work
+  double* y;       // W^-1 S v
+  double* r;       // refinement residual
+  double* t;       // S^T y (m, FP64)
+  size_t bytes;
+};
+
+SolveBufs carve(char* base, int64_t n, int64_t m, const dfi::GramPlan* gp, const dfi::RowPassPlan& rp,
+                const dfi::ColPassPlan& cp, bool need_L, bool need_t) {
+  Carver c;
+  c.base = base;
+  SolveBufs s{};
+  s.W = gp ? c.take<double>((size_t)(n * n)) : nullptr;
+  s.L = need_L ? c.take<double>((size_t)(n * n)) : nullptr;
+  s.gpart = gp ? c.take<float>(gp->part_bytes / sizeof(float)) : nullptr;
+  s.rpart = c.take<double>(rp.part_bytes / sizeof(double) + 1);
+  s.cpart = c.take<double>(cp.part_bytes / sizeof(double) + 1);
+  s.b = c.take<double>((size_t)n);
+  s.d = c.take<double>((size_t)n);
+  s.z = c.take<double>((size_t)n);
+  s.y = c.take<double>((size_t)n);
+  s.r = c.take<double>((size_t)n);
+  s.t = need_t ? c.take<double>((size_t)m) : nullptr;
+  s.bytes = c.off;
+  return s;
+}
+
+// Cholesky of W (+ tau I) into L following the shift policy. Synchronises once per attempt.
+dfisher_status factor_with_policy(dfisher_ctx* ctx, const double* W, double* L, int64_t n, int policy,
+                                  hipStream_t st, double* shift_out, int64_t* info_out, int32_t* attempts_out) {
+  double tau = 0.0;
+  double base = 0.0;
+  int attempts = 0;
+  int64_t info = 0;
+  for (;;) {
+    HIP_TRY(dfi::shift_copy(W, L, n, tau, st));
+    HIP_TRY(dfi::potrf_launch(L, n, ctx->d_info, ctx->d_flag, st));
+    HIP_TRY(hipMemcpyAsync(ctx->h_status, ctx->d_info, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    ++attempts;
+    info = ctx->h_status[0];
+    if (info == 0 || policy == DFISHER_SHIFT_NONE || attempts >= MAX_SHIFT_ATTEMPTS) break;
+    if (base == 0.0) {
+      HIP_TRY(dfi::diag_max(W, n, ctx->d_scalar, st));
+      HIP_TRY(hipMemcpyAsync(ctx->h_scalar, ctx->d_scalar, sizeof(double), hipMemcpyDeviceToHost, st));
+      HIP_TRY(hipStreamSynchronize(st));
+      const double dmax = ctx->h_scalar[0];
+      if (!std::isfinite(dmax)) break;  // NaN/Inf in W: shifting cannot help
+      // about the size of the rounding error of an FP32-accumulated Gram entry, times sqrt(n)
+      base = std::sqrt((double)n) * std::ldexp(dmax, -24);
+      if (!(base > 0.0)) base = std::ldexp(1.0, -24);
+      tau = base;
+    } else {
+      tau *= 8.0;
+    }
+  }
+  HIP_TRY(dfi::zero_upper(L, n, st));
+  *shift_out = (info == 0) ? tau : 0.0;
+  *info_out = info;
+  *attempts_out = attempts;
+  if (info != 0)
+    return fail(DFISHER_E_NOT_SPD, "Cholesky failed at pivot %lld after %d attempt(s)", (long long)info, attempts);
+  return DFISHER_OK;
+}
+
+// y = W^-1 b through the factor, then `sweeps` refinement sweeps against the exact operator
+// W = S S^T + lambda I: r = b - lambda y - S (S^T y) (FP64 accumulation), y += L^-T L^-1 r.
+dfisher_status solve_y(const float* S, int64_t n, int64_t m, int64_t lds, double lambda, const double* L,
+                       const SolveBufs& B, const dfi::RowPassPlan& rp, const dfi::ColPassPlan& cp, int sweeps,
+                       hipStream_t st, StageClock* clk = nullptr) {
+  HIP_TRY(dfi::trsv_launch(L, n, 0, B.b, B.z, st));
+  HIP_TRY(dfi::trsv_launch(L, n, 1, B.z, B.y, st));
+  if (clk) clk->mark(5);
+  for (int s = 0; s < sweeps; ++s) {
+    HIP_TRY(dfi::colpass_launch(cp, S, n, m, lds, B.y, nullptr, 1.0, B.t, 2, B.cpart, st));
+    HIP_TRY(dfi::rowpass_launch(rp, S, nullptr, B.t, true, false, B.rpart, st));
+    HIP_TRY(dfi::rowpass_reduce(rp, B.rpart, true, false, B.r, nullptr, B.b, B.y, lambda, st));
+    HIP_TRY(dfi::trsv_launch(L, n, 0, B.r, B.z, st));
+    HIP_TRY(dfi::trsv_launch(L, n, 1, B.z, B.r, st));
+    HIP_TRY(dfi::axpy_inplace(B.y, B.r, n, st));
+  }
+  if (clk) clk->mark(6);
+  return DFISHER_OK;
+}
+
+// Per-device kernel attributes (called with the device current).
+dfisher_status init_kernels() {
+  HIP_TRY(dfi::trsv_prepare());
+  return DFISHER_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* dfisher_status_string(dfisher_status s) {
+  switch (s) {
+    case DFISHER_OK: return "ok";
+    case DFISHER_E_INVALID_ARG: return "invalid argument";
+    case DFISHER_E_NOT_SPD: return "matrix not positive definite";
+    case DFISHER_E_NO_MEMORY: return "out of device memory";
+    case DFISHER_E_DEVICE: return "device or HIP runtime error";
+    case DFISHER_E_UNSUPPORTED: return "unsupported request";
+  }
+  return "unknown status";
+}
+
+const char* dfisher_last_error(void) { return g_last_error.c_str(); }
+
+dfisher_status dfisher_ctx_create(int device, dfisher_ctx** out) {
+  if (!out) return fail(DFISHER_E_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  if (device < 0) return fail(DFISHER_E_INVALID_ARG, "device = %d < 0", device);
+  int count = 0;
+  hipError_t e = hipGetDeviceCount(&count);
+  if (e != hipSuccess || count == 0) {
+    (void)hipGetLastError();
+    return fail(DFISHER_E_DEVICE, "no HIP device available (%s)", hipGetErrorString(e));
+  }
+  if (device >= count) return fail(DFISHER_E_DEVICE, "device %d does not exist (%d present)", device, count);
+  DeviceGuard g(device);
+  dfisher_ctx* c = new dfisher_ctx();
+  c->device = device;
+  void* dstat = nullptr;
+  if (hipMalloc(&dstat, 256) != hipSuccess || hipHostMalloc((void**)&c->h_status, 64, hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc((void**)&c->h_scalar, 64, hipHostMallocDefault) != hipSuccess) {
+    (void)hipGetLastError();
+    if (dstat) (void)hipFree(dstat);
+    if (c->h_status) (void)hipHostFree(c->h_status);
+    if (c->h_scalar) (void)hipHostFree(c->h_scalar);
+    delete c;
+    return fail(DFISHER_E_NO_MEMORY, "context allocation failed");
+  }
+  c->d_info = reinterpret_cast<int64_t*>(dstat);
+  c->d_flag = reinterpret_cast<int32_t*>(reinterpret_cast<char*>(dstat) + 64);
+  c->d_scalar = reinterpret_cast<double*>(reinterpret_cast<char*>(dstat) + 128);
+  for (int i = 0; i < NEV; ++i) {
+    if (hipEventCreate(&c->ev[i]) != hipSuccess) {
+      (void)hipGetLastError();
+      c->ev[i] = nullptr;
+    }
+  }
+  dfisher_status si = init_kernels();
+  if (si != DFISHER_OK) {
+    (void)hipFree(dstat);
+    (void)hipHostFree(c->h_status);
+    (void)hipHostFree(c->h_scalar);
+    delete c;
+    return si;
+  }
+  *out = c;
+  return DFISHER_OK;
+}
+
+dfisher_status dfisher_ctx_destroy(dfisher_ctx* ctx) {
+  if (!ctx) return DFISHER_OK;
+  DeviceGuard g(ctx->device);
+  (void)hipDeviceSynchronize();
+  if (ctx->ws) (void)hipFree(ctx->ws);
+  for (int i = 0; i < NEV; ++i)
+    if (ctx->ev[i]) (void)hipEventDestroy(ctx->ev[i]);
+  if (ctx->d_info) (void)hipFree(ctx->d_info);
+  if (ctx->h_status) (void)hipHostFree(ctx->h_status);
+  if (ctx->h_scalar) (void)hipHostFree(ctx->h_scalar);
+  delete ctx;
+  return DFISHER_OK;
+}
+
+dfisher_status dfisher_ctx_enable_timing(dfisher_ctx* ctx, int32_t enable) {
+  DF_TRY(check_ctx(ctx));
+  for (int i = 0; i < NEV; ++i)
+    if (!ctx->ev[i]) return fail(DFISHER_E_DEVICE, "timing events unavailable");
+  ctx->timing = enable != 0;
+  return DFISHER_OK;
+}
+
+dfisher_status dfisher_ctx_last_timing(dfisher_ctx* ctx, dfisher_timing* out) {
+  DF_TRY(check_ctx(ctx));
+  if (!out) return fail(DFISHER_E_INVALID_ARG, "out is NULL");
+  DeviceGuard g(ctx->device);
+  double ms[NEV - 1] = {};
+  int first = -1, last = -1;
+  for (int i = 0; i < NEV; ++i) {
+    if (!ctx->ev_used[i]) continue;
+    HIP_TRY(hipEventSynchronize(ctx->ev[i]));
+    if (first < 0) first = i;
+    last = i;
+  }
+  // a stage's time runs from its start event to the next recorded event
+  for (int i = 0; i + 1 < NEV; ++i) {
+    if (!ctx->ev_used[i]) continue;
+    int j = i + 1;
+    while (j < NEV && !ctx->ev_used[j]) ++j;
+    if (j >= NEV) break;
+    float t = 0.f;
+    HIP_TRY(hipEventElapsedTime(&t, ctx->ev[i], ctx->ev[j]));
+    ms[i] = t;
+  }
+  out->rowpass_ms = ms[0];
+  out->gram_ms = ms[1];
+  out->gram_reduce_ms = ms[2];
+  out->potrf_ms = ms[3];
+  out->trsv_ms = ms[4];
+  out->refine_ms = ms[5];
+  out->apply_ms = ms[6];
+  out->total_ms = 0.0;
+  if (first >= 0 && last > first) {
+    float t = 0.f;
+    HIP_TRY(hipEventElapsedTime(&t, ctx->ev[first], ctx->ev[last]));
+    out->total_ms = t;
+  }
+  return DFISHER_OK;
+}
+
+dfisher_status dfisher_gram(dfisher_ctx* ctx, const float* S, int64_t n, int64_t m, int64_t lds, int32_t prec,
+                            double lambda, double* W, void* stream) {
+  DF_TRY(check_ctx(ctx));
+  DF_TRY(check_S(S, n, m, lds));
+  if (!W) return fail(DFISHER_E_INVALID_ARG, "W is NULL");
+  if (prec != DFISHER_GRAM_FP32 && prec != DFISHER_GRAM_BF16X3)
+    return fail(DFISHER_E_INVALID_ARG, "unknown gram precision %d", prec);
+  if (!(std::isfinite(lambda) && lambda >= 0.0)) return fail(DFISHER_E_INVALID_ARG, "lambda must be finite and >= 0");
+  DeviceGuard g(ctx->device);
+  hipStream_t st = as_stream(stream);
+  const dfi::GramPlan gp = dfi::gram_plan(n, m, lds, prec);
+  const dfi::RowPassPlan rp = dfi::rowpass_plan(n, m, lds);
+  Carver c;
+  float* gpart = c.take<float>(gp.part_bytes / sizeof(float));
+  double* rpart = c.take<double>(rp.part_bytes / sizeof(double));
+  double* d = c.take<double>((size_t)n);
+  DF_TRY(ensure_ws(ctx, c.off));
+  char* base = static_cast<char*>(ctx->ws);
+  c = Carver{};
+  c.base = base;
+  gpart = c.take<float>(gp.part_bytes / sizeof(float));
+  rpart = c.take<double>(rp.part_bytes / sizeof(double));
+  d = c.take<double>((size_t)n);
+  StageClock clk(ctx, st);
+  clk.mark(0);
+  HIP_TRY(dfi::rowpass_launch(rp, S, nullptr, nullptr, false, true, rpart, st));
+  HIP_TRY(dfi::rowpass_reduce(rp, rpart, false, true, nullptr, d, nullptr, nullptr, 0.0, st));
+  clk.mark(1);
+  HIP_TRY(dfi::gram_launch(gp, S, gpart, st));
+  clk.mark(2);
+  HIP_TRY(dfi::gram_reduce(gp, gpart, d, lambda, W, 1, st));
+  clk.mark(3);
+  return DFISHER_OK;
+}
+
+dfisher_status dfisher_potrf(dfisher_ctx* ctx, double* W, int64_t n, int64_t* info, void* stream) {
+  DF_TRY(check_ctx(ctx));
+  if (!W) return fail(DFISHER_E_INVALID_ARG, "W is NULL");
+  if (!info) return fail(DFISHER_E_INVALID_ARG, "info is NULL");
+  if (n < 1) return fail(DFISHER_E_INVALID_ARG, "n = %lld < 1", (long long)n);
+  *info = 0;
+  DeviceGuard g(ctx->device);
+  hipStream_t st = as_stream(stream);
+  HIP_TRY(dfi::potrf_launch(W, n, ctx->d_info, ctx->d_flag, st));
+  HIP_TRY(hipMemcpyAsync(ctx->h_status, ctx->d_info, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  *info = ctx->h_status[0];
+  if (*info != 0) return fail(DFISHER_E_NOT_SPD, "Cholesky failed at pivot %lld", (long long)*info);
+  HIP_TRY(dfi::zero_upper(W, n, st));
+  return DFISHER_OK;
+}
+
+dfisher_status dfisher_gemv(dfisher_ctx* ctx, const float* S, int64_t n, int64_t m, int64_t lds, const float* v,
+                            double* b, void* stream) {
+  DF_TRY(check_ctx(ctx));
+  DF_TRY(check_S(S, n, m, lds));
+  if (!v || !b) return fail(DFISHER_E_INVALID_ARG, "v or b is NULL");
+  DeviceGuard g(ctx->device);
+  hipStream_t st = as_stream(stream);
+  const dfi::RowPassPlan rp = dfi::rowpass_plan(n, m, lds);
+  DF_TRY(ensure_ws(ctx, align_up(rp.part_bytes)));
+  double* rpart = static_cast<double*>(ctx->ws);
+  HIP_TRY(dfi::rowpass_launch(rp, S, v, nullptr, true, false, rpart, st));
+  HIP_TRY(dfi::rowpass_reduce(rp, rpart, true, false, b, nullptr, nullptr, nullptr, 0.0, st));
+  return DFISHER_OK;
+}
+
+dfisher_status dfisher_trsv(dfisher_ctx* ctx, const double* L, int64_t n, int32_t trans, const double* b, double* y,
+                            void* stream) {
+  DF_TRY(check_ctx(ctx));
+  if (!L || !b || !y) return fail(DFISHER_E_INVALID_ARG, "L, b or y is NULL");
+  if (n < 1) return fail(DFISHER_E_INVALID_ARG, "n = %lld < 1", (long long)n);
+  if (trans != 0 && trans != 1) return fail(DFISHER_E_INVALID_ARG, "trans must be 0 or 1");
+  DF_TRY(check_trsv_n(n));
+  DeviceGuard g(ctx->device);
+  HIP_TRY(dfi::trsv_launch(L, n, trans, b, y, as_stream(stream)));
+  return DFISHER_OK;
+}
+
+dfisher_status dfisher_apply(dfisher_ctx* ctx, const float* S, int64_t n, int64_t m, int64_t lds, const float* v,
+                             const double* y, double lambda, void* x, int32_t x_fp64, void* stream) {
+  DF_TRY(check_ctx(ctx));
+  DF_TRY(check_S(S, n, m, lds));
+  if (!v || !y || !x) return fail(DFISHER_E_INVALID_ARG, "v, y or x is NULL");
+  if (!finite_pos(lambda)) return fail(DFISHER_E_INVALID_ARG, "lambda must be finite and > 0");
+  if (x_fp64 != 0 && x_fp64 != 1) return fail(DFISHER_E_INVALID_ARG, "x_fp64 must be 0 or 1");
+  DeviceGuard g(ctx->device);
+  const dfi::ColPassPlan cp = dfi::colpass_plan(n, m);
+  DF_TRY(ensure_ws(ctx, align_up(cp.part_bytes + 8)));
+  HIP_TRY(dfi::colpass_launch(cp, S, n, m, lds, y, v, lambda, x, x_fp64 ? 1 : 0, static_cast<double*>(ctx->ws),
+                              as_stream(stream)));
+  return DFISHER_OK;
+}
+
+dfisher_status dfisher_factor_create(dfisher_ctx* ctx, const float* S, int64_t n, int64_t m, int64_t lds,
+                                     double lambda, const dfisher_options* opt, void* stream, dfisher_factor** out,
+                                     dfisher_info* info) {
+  DF_TRY(check_ctx(ctx));
+  if (!out) return fail(DFISHER_E_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  DF_TRY(check_S(S, n, m, lds));
+  if (!finite_pos(lambda)) return fail(DFISHER_E_INVALID_ARG, "lambda must be finite and > 0");
+  dfisher_options o;
+  DF_TRY(check_opt(opt, &o));
+  DF_TRY(check_trsv_n(n));
+  DeviceGuard g(ctx->device);
+  hipStream_t st = as_stream(stream);
+  const dfi::GramPlan gp = dfi::gram_plan(n, m, lds, o.gram_prec);
+  const dfi::RowPassPlan rp = dfi::rowpass_plan(n, m, lds);
+  const dfi::ColPassPlan cp = dfi::colpass_plan(n, m);
+  SolveBufs B = carve(nullptr, n, m, &gp, rp, cp, false, false);
+  DF_TRY(ensure_ws(ctx, B.bytes));
+  B = carve(static_cast<char*>(ctx->ws), n, m, &gp, rp, cp, false, false);
+  dfisher_factor* f = new dfisher_factor();
+  f->ctx = ctx;
+  f->S = S;
+  f->n = n;
+  f->m = m;
+  f->lds = lds;
+  f->lambda = lambda;
+  f->opt = o;
+  if (hipMalloc(&f->L, (size_t)(n * n) * sizeof(double)) != hipSuccess) {
+    (void)hipGetLastError();
+    delete f;
+    return fail(DFISHER_E_NO_MEMORY, "factor allocation failed");
+  }
+  auto cleanup = [&](dfisher_status s) {
+    (void)hipFree(f->L);
+    delete f;
+    return s;
+  };
+  if (dfi::rowpass_launch(rp, S, nullptr, nullptr, false, true, B.rpart, st) != hipSuccess ||
+      dfi::rowpass_reduce(rp, B.rpart, false, true, nullptr, B.d, nullptr, nullptr, 0.0, st) != hipSuccess ||
+      dfi::gram_launch(gp, S, B.gpart, st) != hipSuccess ||
+      dfi::gram_reduce(gp, B.gpart, B.d, lambda, B.W, 0, st) != hipSuccess)
+    return cleanup(fail(DFISHER_E_DEVICE, "kernel launch failed: %s", hipGetErrorString(hipGetLastError())));
+  dfisher_info inf{};
+  dfisher_status s = factor_with_policy(ctx, B.W, f->L, n, o.shift_policy, st, &inf.shift, &inf.potrf_info, &inf.attempts);
+  if (info) *info = inf;
+  if (s != DFISHER_OK) return cleanup(s);
+  f->shift = inf.shift;
+  *out = f;
+  return DFISHER_OK;
+}
+
+dfisher_status dfisher_factor_solve(dfisher_factor* f, const float* V, int64_t nrhs, int64_t ldv, void* X, int64_t ldx,
+                                    void* stream, dfisher_info* info) {
+  if (!f) return fail(DFISHER_E_INVALID_ARG, "factor is NULL");
+  if (!V || !X) return fail(DFISHER_E_INVALID_ARG, "V or X is NULL");
+  if (nrhs < 1) return fail(DFISHER_E_INVALID_ARG, "nrhs = %lld < 1", (long long)nrhs);
+  if (ldv < f->m || ldx < f->m) return fail(DFISHER_E_INVALID_ARG, "ldv/ldx < m");
+  dfisher_ctx* ctx = f->ctx;
+  DeviceGuard g(ctx->device);
+  hipStream_t st = as_stream(stream);
+  const int64_t n = f->n, m = f->m;
+  const dfi::RowPassPlan rp = dfi::rowpass_plan(n, m, f->lds);
+  const dfi::ColPassPlan cp = dfi::colpass_plan(n, m);
+  const bool need_t = f->opt.sweeps > 0;
+  SolveBufs B = carve(nullptr, n, m, nullptr, rp, cp, false, need_t);
+  DF_TRY(ensure_ws(ctx, B.bytes));
+  B = carve(static_cast<char*>(ctx->ws), n, m, nullptr, rp, cp, false, need_t);
+  const size_t xel = f->opt.x_fp64 ? sizeof(double) : sizeof(float);
+  for (int64_t r = 0; r < nrhs; ++r) {
+    const float* v = V + r * ldv;
+    void* x = static_cast<char*>(X) + (size_t)(r * ldx) * xel;
+    HIP_TRY(dfi::rowpass_launch(rp, f->S, v, nullptr, true, false, B.rpart, st));
+    HIP_TRY(dfi::rowpass_reduce(rp, B.rpart, true, false, B.b, nullptr, nullptr, nullptr, 0.0, st));
+    DF_TRY(solve_y(f->S, n, m, f->lds, f->lambda, f->L, B, rp, cp, f->opt.sweeps, st));
+    HIP_TRY(dfi::colpass_launch(cp, f->S, n, m, f->lds, B.y, v, f->lambda, x, f->opt.x_fp64 ? 1 : 0, B.cpart, st));
+  }
+  if (info) {
+    info->potrf_info = 0;
+    info->shift = f->shift;
+    info->attempts = 0;
+    info->sweeps_done = f->opt.sweeps;
+  }
+  return DFISHER_OK;
+}
+
+dfisher_status dfisher_factor_copy_L(const dfisher_factor* f, double* L, void* stream) {
+  if (!f || !L) return fail(DFISHER_E_INVALID_ARG, "factor or L is NULL");
+  DeviceGuard g(f->ctx->device);
+  HIP_TRY(hipMemcpyAsync(L, f->L, (size_t)(f->n * f->n) * sizeof(double), hipMemcpyDeviceToDevice,
+                         as_stream(stream)));
+  return DFISHER_OK;
+}
+
+dfisher_status dfisher_factor_destroy(dfisher_factor* f) {
+  if (!f) return DFISHER_OK;
+  DeviceGuard g(f->ctx->device);
+  (void)hipDeviceSynchronize();
+  (void)hipFree(f->L);
+  delete f;
+  return DFISHER_OK;
+}
+
+dfisher_status dfisher_solve(dfisher_ctx* ctx, const float* S, int64_t n, int64_t m, int64_t lds, const float* v,
+                             double lambda, void* x, const dfisher_options* opt, void* stream, dfisher_info* info) {
+  DF_TRY(check_ctx(ctx));
+  DF_TRY(check_S(S, n, m, lds));
+  if (!v || !x) return fail(DFISHER_E_INVALID_ARG, "v or x is NULL");
+  if (!finite_pos(lambda)) return fail(DFISHER_E_INVALID_ARG, "lambda must be finite and > 0");
+  dfisher_options o;
+  DF_TRY(check_opt(opt, &o));
+  DF_TRY(check_trsv_n(n));
+  DeviceGuard g(ctx->device);
+  hipStream_t st = as_stream(stream);
+  const dfi::GramPlan gp = dfi::gram_plan(n, m, lds, o.gram_prec);
+  const dfi::RowPassPlan rp = dfi::rowpass_plan(n, m, lds);
+  const dfi::ColPassPlan cp = dfi::colpass_plan(n, m);
+  const bool need_t = o.sweeps > 0;
+  SolveBufs B = carve(nullptr, n, m, &gp, rp, cp, true, need_t);
+  DF_TRY(ensure_ws(ctx, B.bytes));
+  B = carve(static_cast<char*>(ctx->ws), n, m, &gp, rp, cp, true, need_t);
+  StageClock clk(ctx, st);
+  // one pass over S: b = S v and the exact diagonal |s_i|^2
+  clk.mark(0);
+  HIP_TRY(dfi::rowpass_launch(rp, S, v, nullptr, true, true, B.rpart, st));
+  HIP_TRY(dfi::rowpass_reduce(rp, B.rpart, true, true, B.b, B.d, nullptr, nullptr, 0.0, st));
+  // Algorithm 1 step 1
+  clk.mark(1);
+  HIP_TRY(dfi::gram_launch(gp, S, B.gpart, st));
+  clk.mark(2);
+  HIP_TRY(dfi::gram_reduce(gp, B.gpart, B.d, lambda, B.W, 0, st));
+  // step 2 (with the shift policy)
+  clk.mark(3);
+  dfisher_info inf{};
+  DF_TRY(factor_with_policy(ctx, B.W, B.L, n, o.shift_policy, st, &inf.shift, &inf.potrf_info, &inf.attempts));
+  // steps 3-4 inlined: y = W^-1 S v (+ refinement), x = (v - S^T y) / lambda
+  clk.mark(4);
+  DF_TRY(solve_y(S, n, m, lds, lambda, B.L, B, rp, cp, o.sweeps, st, &clk));
+  HIP_TRY(dfi::colpass_launch(cp, S, n, m, lds, B.y, v, lambda, x, o.x_fp64, B.cpart, st));
+  clk.mark(7);
+  inf.sweeps_done = o.sweeps;
+  if (info) *info = inf;
+  return DFISHER_OK;
+}
+
+dfisher_status dfisher_solve_batched(dfisher_ctx* ctx, const float* S, int64_t n, int64_t m, int64_t lds,
+                                     const double* lambdas, int32_t nlam, const float* V, int32_t nrhs, int64_t ldv,
+                                     void* X, int64_t ldx, const dfisher_options* opt, void* stream,
+                                     dfisher_info* infos) {
+  DF_TRY(check_ctx(ctx));
+  DF_TRY(check_S(S, n, m, lds));
+  if (!lambdas || !V || !X) return fail(DFISHER_E_INVALID_ARG, "lambdas, V or X is NULL");
+  if (nlam < 1 || nrhs < 1) return fail(DFISHER_E_INVALID_ARG, "nlam and nrhs must be >= 1");
+  if (ldv < m || ldx < m) return fail(DFISHER_E_INVALID_ARG, "ldv/ldx < m");
+  for (int32_t l = 0; l < nlam; ++l)
+    if (!finite_pos(lambdas[l])) return fail(DFISHER_E_INVALID_ARG, "lambdas[%d] must be finite and > 0", l);
+  dfisher_options o;
+  DF_TRY(check_opt(opt, &o));
+  DF_TRY(check_trsv_n(n));
+  DeviceGuard g(ctx->device);
+  hipStream_t st = as_stream(stream);
+  const dfi::GramPlan gp = dfi::gram_plan(n, m, lds, o.gram_prec);
+  const dfi::RowPassPlan rp = dfi::rowpass_plan(n, m, lds);
+  const dfi::ColPassPlan cp = dfi::colpass_plan(n, m);
+  const bool need_t = o.sweeps > 0;
+  SolveBufs B = carve(nullptr, n, m, &gp, rp, cp, true, need_t);
+  Carver extra;
+  extra.off = B.bytes;
+  double* G = extra.take<double>((size_t)(n * n));
+  double* Bs = extra.take<double>((size_t)(n * nrhs));
+  DF_TRY(ensure_ws(ctx, extra.off));
+  char* base = static_cast<char*>(ctx->ws);
+  B = carve(base, n, m, &gp, rp, cp, true, need_t);
+  extra = Carver{};
+  extra.base = base;
+  extra.off = B.bytes;
+  G = extra.take<double>((size_t)(n * n));
+  Bs = extra.take<double>((size_t)(n * nrhs));
+  // shared Gram G = S S^T (exact diagonal, no lambda)
+  HIP_TRY(dfi::rowpass_launch(rp, S, nullptr, nullptr, false, true, B.rpart, st));
+  HIP_TRY(dfi::rowpass_reduce(rp, B.rpart, false, true, nullptr, B.d, nullptr, nullptr, 0.0, st));
+  HIP_TRY(dfi::gram_launch(gp, S, B.gpart, st));
+  HIP_TRY(dfi::gram_reduce(gp, B.gpart, B.d, 0.0, G, 0, st));
+  // b_r = S v_r for every right-hand side, shared by all lambdas
+  for (int32_t r = 0; r < nrhs; ++r) {
+    HIP_TRY(dfi::rowpass_launch(rp, S, V + (int64_t)r * ldv, nullptr, true, false, B.rpart, st));
+    HIP_TRY(dfi::rowpass_reduce(rp, B.rpart, true, false, Bs + (int64_t)r * n, nullptr, nullptr, nullptr, 0.0, st));
+  }
+  const size_t xel = o.x_fp64 ? sizeof(double) : sizeof(float);
+  dfisher_status worst = DFISHER_OK;
+  for (int32_t l = 0; l < nlam; ++l) {
+    const double lam = lambdas[l];
+    HIP_TRY(dfi::shift_copy(G, B.W, n, lam, st));
+    dfisher_info inf{};
+    dfisher_status s = factor_with_policy(ctx, B.W, B.L, n, o.shift_policy, st, &inf.shift, &inf.potrf_info, &inf.attempts);
+    if (s == DFISHER_OK) {
+      for (int32_t r = 0; r < nrhs; ++r) {
+        HIP_TRY(hipMemcpyAsync(B.b, Bs + (int64_t)r * n, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, st));
+        DF_TRY(solve_y(S, n, m, lds, lam, B.L, B, rp, cp, o.sweeps, st));
+        void* x = static_cast<char*>(X) + (size_t)(((int64_t)l * nrhs + r) * ldx) * xel;
+        HIP_TRY(dfi::colpass_launch(cp, S, n, m, lds, B.y, V + (int64_t)r * ldv, lam, x, o.x_fp64, B.cpart, st));
+      }
+      inf.sweeps_done = o.sweeps;
+    } else if (s == DFISHER_E_NOT_SPD) {
+      worst = s;
+    } else {
+      return s;
+    }
+    if (infos) infos[l] = inf;
+  }
+  if (worst != DFISHER_OK) return fail(worst, "at least one lambda failed to factor");
+  return DFISHER_OK;
+}
+
+dfisher_status dfisher_solve_uneven(dfisher_ctx* ctx, int32_t nprob, const float* const* S, const int64_t* n,
+                                    const int64_t* m, const int64_t* lds, const float* const* v, const double* lambda,
+                                    void* const* x, const dfisher_options* opt, void* stream, dfisher_info* infos) {
+  DF_TRY(check_ctx(ctx));
+  if (nprob < 1) return fail(DFISHER_E_INVALID_ARG, "nprob = %d < 1", nprob);
+  if (!S || !n || !m || !lds || !v || !lambda || !x) return fail(DFISHER_E_INVALID_ARG, "NULL array argument");
+  dfisher_options o;
+  DF_TRY(check_opt(opt, &o));
+  for (int32_t p = 0; p < nprob; ++p) {
+    dfisher_status s = check_S(S[p], n[p], m[p], lds[p]);
+    if (s != DFISHER_OK) return fail(s, "problem %d: %s", p, g_last_error.c_str());
+    if (!v[p] || !x[p]) return fail(DFISHER_E_INVALID_ARG, "problem %d: v or x is NULL", p);
+    if (!finite_pos(lambda[p])) return fail(DFISHER_E_INVALID_ARG, "problem %d: lambda must be finite and > 0", p);
+    DF_TRY(check_trsv_n(n[p]));
+  }
+  dfisher_status worst = DFISHER_OK;
+  for (int32_t p = 0; p < nprob; ++p) {
+    dfisher_info inf{};
+    dfisher_status s = dfisher_solve(ctx, S[p], n[p], m[p], lds[p], v[p], lambda[p], x[p], &o, stream, &inf);
+    if (infos) infos[p] = inf;
+    if (s == DFISHER_E_NOT_SPD) worst = s;
+    else if (s != DFISHER_OK) return s;
+  }
+  if (worst != DFISHER_OK) return fail(worst, "at least one problem failed to factor");
+  return DFISHER_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,320 @@
+// HBM-streaming passes over S for the right-to-left evaluation of x = (v - S^T L^-T L^-1 S v)/lambda
+// (Section 2, the inlined form of Algorithm 1 steps 3-4). Every pass reads S exactly once with
+// 16-byte loads; products of FP32 values are accumulated in FP64.
+//
+// Row pass   b = S v (and/or the exact squared row norms d_i = |s_i|^2, the diagonal of S S^T).
+//            A wave owns RPW rows and a group of columns; it walks the group in sub-chunks of
+//            2048 columns (8 x 16-byte loads per lane, each load covering 1 KB of one row),
+//            keeps the sub-chunk of v in registers and reuses it for all RPW rows, and keeps one
+//            FP64 accumulator per row per lane. At the end each row is reduced across the wave
+//            and one FP64 partial per (row, column group) is stored; a second kernel adds the
+//            column groups in fixed order.
+// Column pass t = S^T y. A workgroup owns 1024 consecutive columns (one float4 per lane) and
+//            walks the rows; y_i is wave-uniform. When m is small the rows are split across
+//            workgroups and FP64 partials are added in fixed order by a finalize kernel.
+#include "dfisher_internal.h"
+
+#include <algorithm>
+
+namespace dfi {
+namespace {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr int RP_WAVES = 4;     // waves per workgroup (each its own row group)
+constexpr int RP_RPW = 16;      // rows per wave
+constexpr int RP_U = 8;         // float4 loads per lane per row and sub-chunk
+constexpr int RP_SUB = 64 * 4 * RP_U;  // 2048 columns per sub-chunk
+
+__device__ __forceinline__ double wave_sum(double x) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+  return x;
+}
+
+template <typename VT>
+__device__ __forceinline__ void load_vec4(const VT* __restrict__ v, int64_t col, int64_t m, bool vec, double (&out)[4]) {
+  if (vec && col + 4 <= m) {
+    if constexpr (sizeof(VT) == 4) {
+      const f32x4 t = *reinterpret_cast<const f32x4*>(v + col);
+      out[0] = t[0]; out[1] = t[1]; out[2] = t[2]; out[3] = t[3];
+    } else {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) out[e] = v[col + e];
+    }
+  } else {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) out[e] = (col + e < m) ? (double)v[col + e] : 0.0;
+  }
+}
+
+__device__ __forceinline__ void load_s4(const float* __restrict__ p, int64_t col, int64_t m, bool vec, f32x4& out) {
+  if (vec && col + 4 <= m) {
+    out = *reinterpret_cast<const f32x4*>(p);
+  } else {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) out[e] = (col + e < m) ? p[e] : 0.f;
+  }
+}
+
+// Grid: x = row blocks of RP_WAVES * RP_RPW rows, y = column groups of `cg` columns (multiple
+// of RP_SUB). part layout: part_b[g * n + i], part_d[(ngroups + g) * n + i].
+template <typename VT, bool WANT_B, bool WANT_D>
+__global__ void __launch_bounds__(64 * RP_WAVES)
+rowpass_kernel(const float* __restrict__ S, int64_t n, int64_t m, int64_t lds, const VT* __restrict__ v,
+               int64_t cg, int64_t ngroups, double* __restrict__ part, int vec) {
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int64_t row0 = ((int64_t)blockIdx.x * RP_WAVES + wave) * RP_RPW;
+  const int64_t g = blockIdx.y;
+  const int64_t c0 = g * cg;
+  const int64_t c1 = min(m, c0 + cg);
+  if (row0 >= n) return;
+  const int nr = (int)min<int64_t>(RP_RPW, n - row0);
+
+  double ab[RP_RPW], ad[RP_RPW];
+#pragma unroll
+  for (int r = 0; r < RP_RPW; ++r) { ab[r] = 0.0; ad[r] = 0.0; }
+
+  for (int64_t cs = c0; cs < c1; cs += RP_SUB) {
+    double vv[RP_U][4];
+    if constexpr (WANT_B) {
+#pragma unroll
+      for (int u = 0; u < RP_U; ++u) load_vec4<VT>(v, cs + 256 * u + 4 * lane, c1, vec, vv[u]);
+    }
+#pragma unroll
+    for (int r = 0; r < RP_RPW; ++r) {
+      if (r < nr) {
+        const float* rowp = S + (row0 + r) * lds;
+        f32x4 sv[RP_U];
+#pragma unroll
+        for (int u = 0; u < RP_U; ++u) {
+          const int64_t col = cs + 256 * u + 4 * lane;
+          load_s4(rowp + col, col, c1, vec, sv[u]);
+        }
+#pragma unroll
+        for (int u = 0; u < RP_U; ++u)
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const double s = (double)sv[u][e];
+            if constexpr (WANT_B) ab[r] = fma(s, vv[u][e], ab[r]);
+            if constexpr (WANT_D) ad[r] = fma(s, s, ad[r]);
+          }
+      }
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < RP_RPW; ++r) {
+    if (r < nr) {
+      if constexpr (WANT_B) {
+        const double t = wave_sum(ab[r]);
+        if (lane == 0) part[g * n + row0 + r] = t;
+      }
+      if constexpr (WANT_D) {
+        const double t = wave_sum(ad[r]);
+        if (lane == 0) part[(ngroups + g) * n + row0 + r] = t;
+      }
+    }
+  }
+}
+
+// b_i = sum_g part_b[g][i] (or r0_i - lam y_i - sum_g part_b[g][i]); d_i = sum_g part_d[g][i].
+__global__ void rowpass_reduce_kernel(const double* __restrict__ part, int64_t n, int64_t ngroups, int want_b,
+                                      int want_d, double* __restrict__ b, double* __restrict__ d,
+                                      const double* __restrict__ r0, const double* __restrict__ y, double lam) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  if (want_b) {
+    double s = 0.0;
+    for (int64_t g = 0; g < ngroups; ++g) s += part[g * n + i];
+    b[i] = r0 ? (r0[i] - lam * y[i]) - s : s;
+  }
+  if (want_d) {
+    double s = 0.0;
+    for (int64_t g = 0; g < ngroups; ++g) s += part[(ngroups + g) * n + i];
+    d[i] = s;
+  }
+}
+
+// ---------------------------------------------------------------------------- column pass
+constexpr int CP_THREADS = 256;
+constexpr int CP_COLS = CP_THREADS * 4;  // 1024 columns per workgroup
+constexpr int CP_UNROLL = 8;
+
+template <int MODE>
+__device__ __forceinline__ void colpass_store(void* out, const float* v, double lam, int64_t col, int64_t m,
+                                              const double (&t)[4], bool vec) {
+  // MODE 0: x = (v - t) / lam as FP32; 1: as FP64; 2: t as FP64.
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    if (col + e >= m) break;
+    if constexpr (MODE == 2) {
+      static_cast<double*>(out)[col + e] = t[e];
+    } else {
+      const double x = ((double)v[col + e] - t[e]) / lam;
+      if constexpr (MODE == 0) static_cast<float*>(out)[col + e] = (float)x;
+      else static_cast<double*>(out)[col + e] = x;
+    }
+  }
+  (void)vec;
+}
+
+// Grid: x = column blocks of CP_COLS, y = row splits of `rps` rows. nsplit == 1 stores the final
+// result; otherwise FP64 partial sums go to part[split * m + col].
+template <int MODE>
+__global__ void __launch_bounds__(CP_THREADS)
+colpass_kernel(const float* __restrict__ S, int64_t n, int64_t m, int64_t lds, const double* __restrict__ y,
+               const float* v, double lam, void* out, double* __restrict__ part, int64_t rps, int vec) {
+  const int64_t col = (int64_t)blockIdx.x * CP_COLS + 4 * threadIdx.x;
+  const int64_t r0 = (int64_t)blockIdx.y * rps;
+  const int64_t r1 = min(n, r0 + rps);
+  double t[4] = {0.0, 0.0, 0.0, 0.0};
+  const bool full = vec && (col + 4 <= m);
+  if (col < m) {
+    int64_t i = r0;
+    for (; i + CP_UNROLL <= r1; i += CP_UNROLL) {
+      f32x4 sv[CP_UNROLL];
+      double yy[CP_UNROLL];
+#pragma unroll
+      for (int u = 0; u < CP_UNROLL; ++u) {
+        const float* p = S + (i + u) * lds + col;
+        if (full) sv[u] = *reinterpret_cast<const f32x4*>(p);
+        else {
+#pragma unroll
+          for (int e = 0; e < 4; ++e) sv[u][e] = (col + e < m) ? p[e] : 0.f;
+        }
+        yy[u] = y[i + u];
+      }
+#pragma unroll
+      for (int u = 0; u < CP_UNROLL; ++u)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) t[e] = fma((double)sv[u][e], yy[u], t[e]);
+    }
+    for (; i < r1; ++i) {
+      const float* p = S + i * lds + col;
+      f32x4 s;
+      if (full) s = *reinterpret_cast<const f32x4*>(p);
+      else {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) s[e] = (col + e < m) ? p[e] : 0.f;
+      }
+      const double yi = y[i];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) t[e] = fma((double)s[e], yi, t[e]);
+    }
+  }
+  if (col >= m) return;
+  if (part == nullptr) {
+    colpass_store<MODE>(out, v, lam, col, m, t, vec);
+  } else {
+    double* pp = part + (int64_t)blockIdx.y * m;
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+      if (col + e < m) pp[col + e] = t[e];
+  }
+}
+
+template <int MODE>
+__global__ void colpass_finalize_kernel(const double* __restrict__ part, int64_t nsplit, int64_t m, const float* v,
+                                        double lam, void* out) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= m) return;
+  double t = 0.0;
+  for (int64_t s = 0; s < nsplit; ++s) t += part[s * m + k];
+  if constexpr (MODE == 2) {
+    static_cast<double*>(out)[k] = t;
+  } else {
+    const double x = ((double)v[k] - t) / lam;
+    if constexpr (MODE == 0) static_cast<float*>(out)[k] = (float)x;
+    else static_cast<double*>(out)[k] = x;
+  }
+}
+
+bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
+
+}  // namespace
+
+RowPassPlan rowpass_plan(int64_t n, int64_t m, int64_t lds) {
+  RowPassPlan p{};
+  p.n = n;
+  p.m = m;
+  p.lds = lds;
+  const int64_t rowblocks = (n + RP_WAVES * RP_RPW - 1) / (RP_WAVES * RP_RPW);
+  // aim for ~8192 waves in flight over the whole grid
+  const int64_t target_groups = std::max<int64_t>(1, 2048 / rowblocks);
+  const int64_t max_groups = (m + RP_SUB - 1) / RP_SUB;
+  p.nchunk = std::max<int64_t>(1, std::min(target_groups, max_groups));
+  int64_t cg = (m + p.nchunk - 1) / p.nchunk;
+  cg = (cg + RP_SUB - 1) / RP_SUB * RP_SUB;
+  p.chunk = cg;
+  p.nchunk = (m + cg - 1) / cg;
+  p.part_bytes = (size_t)2 * (size_t)p.nchunk * (size_t)n * sizeof(double);
+  return p;
+}
+
+hipError_t rowpass_launch(const RowPassPlan& p, const float* S, const float* v, const double* vd, bool want_b,
+                          bool want_d, double* part, hipStream_t st) {
+  const bool vec = ((p.lds & 3) == 0) && aligned16(S) && (v ? aligned16(v) : true) && (vd ? aligned16(vd) : true);
+  const dim3 grid((unsigned)((p.n + RP_WAVES * RP_RPW - 1) / (RP_WAVES * RP_RPW)), (unsigned)p.nchunk);
+  const dim3 block(64 * RP_WAVES);
+  const int iv = vec ? 1 : 0;
+  if (want_b && vd) {
+    if (want_d)
+      hipLaunchKernelGGL((rowpass_kernel<double, true, true>), grid, block, 0, st, S, p.n, p.m, p.lds, vd, p.chunk, p.nchunk, part, iv);
+    else
+      hipLaunchKernelGGL((rowpass_kernel<double, true, false>), grid, block, 0, st, S, p.n, p.m, p.lds, vd, p.chunk, p.nchunk, part, iv);
+  } else if (want_b) {
+    if (want_d)
+      hipLaunchKernelGGL((rowpass_kernel<float, true, true>), grid, block, 0, st, S, p.n, p.m, p.lds, v, p.chunk, p.nchunk, part, iv);
+    else
+      hipLaunchKernelGGL((rowpass_kernel<float, true, false>), grid, block, 0, st, S, p.n, p.m, p.lds, v, p.chunk, p.nchunk, part, iv);
+  } else if (want_d) {
+    hipLaunchKernelGGL((rowpass_kernel<float, false, true>), grid, block, 0, st, S, p.n, p.m, p.lds, (const float*)nullptr, p.chunk, p.nchunk, part, iv);
+  }
+  return hipGetLastError();
+}
+
+hipError_t rowpass_reduce(const RowPassPlan& p, const double* part, bool want_b, bool want_d, double* b, double* d,
+                          const double* r0, const double* y, double lam, hipStream_t st) {
+  const dim3 grid((unsigned)((p.n + 255) / 256));
+  hipLaunchKernelGGL(rowpass_reduce_kernel, grid, dim3(256), 0, st, part, p.n, p.nchunk, want_b ? 1 : 0,
+                     want_d ? 1 : 0, b, d, r0, y, lam);
+  return hipGetLastError();
+}
+
+ColPassPlan colpass_plan(int64_t n, int64_t m) {
+  ColPassPlan p{};
+  const int64_t cblocks = (m + CP_COLS - 1) / CP_COLS;
+  int64_t nsplit = 1;
+  // split the rows when there are too few column blocks to fill the device
+  if (cblocks < 2048) nsplit = std::min<int64_t>((2048 + cblocks - 1) / cblocks, std::max<int64_t>(1, n / 64));
+  p.nsplit = std::max<int64_t>(1, nsplit);
+  p.rps = (n + p.nsplit - 1) / p.nsplit;
+  p.nsplit = (n + p.rps - 1) / p.rps;
+  p.part_bytes = p.nsplit > 1 ? (size_t)p.nsplit * (size_t)m * sizeof(double) : 0;
+  return p;
+}
+
+hipError_t colpass_launch(const ColPassPlan& p, const float* S, int64_t n, int64_t m, int64_t lds, const double* y,
+                          const float* v, double lambda, void* out, int mode, double* part, hipStream_t st) {
+  const bool vec = ((lds & 3) == 0) && aligned16(S);
+  const dim3 grid((unsigned)((m + CP_COLS - 1) / CP_COLS), (unsigned)p.nsplit);
+  double* pp = p.nsplit > 1 ? part : nullptr;
+  const int iv = vec ? 1 : 0;
+  switch (mode) {
+    case 0: hipLaunchKernelGGL(colpass_kernel<0>, grid, dim3(CP_THREADS), 0, st, S, n, m, lds, y, v, lambda, out, pp, p.rps, iv); break;
+    case 1: hipLaunchKernelGGL(colpass_kernel<1>, grid, dim3(CP_THREADS), 0, st, S, n, m, lds, y, v, lambda, out, pp, p.rps, iv); break;
+    default: hipLaunchKernelGGL(colpass_kernel<2>, grid, dim3(CP_THREADS), 0, st, S, n, m, lds, y, v, lambda, out, pp, p.rps, iv); break;
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || p.nsplit == 1) return e;
+  const dim3 g2((unsigned)((m + 255) / 256));
+  switch (mode) {
+    case 0: hipLaunchKernelGGL(colpass_finalize_kernel<0>, g2, dim3(256), 0, st, part, p.nsplit, m, v, lambda, out); break;
+    case 1: hipLaunchKernelGGL(colpass_finalize_kernel<1>, g2, dim3(256), 0, st, part, p.nsplit, m, v, lambda, out); break;
+    default: hipLaunchKernelGGL(colpass_finalize_kernel<2>, g2, dim3(256), 0, st, part, p.nsplit, m, v, lambda, out); break;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace dfi

@@ -1,0 +1,123 @@
+"""Host-side checks of the C ABI that need no GPU: the library loads, exports every entry point
+declared in include/dfisher.h, rejects invalid arguments before touching a device, and reports
+a missing device as DFISHER_E_DEVICE."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _header_functions():
+    with open(os.path.join(ROOT, "include", "dfisher.h")) as f:
+        text = f.read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(dfisher_[A-Za-z_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def dfl():
+    import paper_2310_17556_amd as dfl
+    return dfl
+
+
+def test_header_declares_entry_points():
+    names = _header_functions()
+    for required in ["dfisher_ctx_create", "dfisher_ctx_destroy", "dfisher_gram", "dfisher_potrf",
+                     "dfisher_gemv", "dfisher_trsv", "dfisher_apply", "dfisher_solve", "dfisher_factor_create",
+                     "dfisher_factor_solve", "dfisher_factor_copy_L", "dfisher_factor_destroy",
+                     "dfisher_solve_batched", "dfisher_solve_uneven", "dfisher_status_string",
+                     "dfisher_last_error"]:
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol(dfl):
+    lib = ctypes.CDLL(dfl.LIB_PATH)
+    for name in _header_functions():
+        assert hasattr(lib, name), f"{name} declared in dfisher.h but not exported"
+
+
+def test_binding_names_match_abi(dfl):
+    for name in _header_functions():
+        assert hasattr(dfl, name), f"binding lacks {name}"
+
+
+def test_status_strings(dfl):
+    for code in range(6):
+        assert dfl.dfisher_status_string(code) != "unknown status"
+    assert dfl.dfisher_status_string(99) == "unknown status"
+
+
+FAKE_CTX = ctypes.c_void_p(0x1000)   # never dereferenced: every call below fails validation first
+FAKE_DEV = ctypes.c_void_p(0x2000)
+
+
+def _opts(dfl, prec=0, sweeps=0, shift=1, x64=0):
+    return dfl._Options(prec, sweeps, shift, x64)
+
+
+def test_invalid_arguments_rejected_on_host(dfl):
+    lib = dfl.lib
+    E = dfl.DFISHER_E_INVALID_ARG
+    P = FAKE_DEV
+    st = ctypes.c_void_p(0)
+    # null context
+    assert lib.dfisher_gram(None, P, 4, 8, 8, 0, 0.0, P, st) == E
+    # bad sizes and strides
+    assert lib.dfisher_gram(FAKE_CTX, P, 0, 8, 8, 0, 0.0, P, st) == E
+    assert lib.dfisher_gram(FAKE_CTX, P, 4, 0, 8, 0, 0.0, P, st) == E
+    assert lib.dfisher_gram(FAKE_CTX, P, 4, 8, 7, 0, 0.0, P, st) == E
+    assert lib.dfisher_gram(FAKE_CTX, None, 4, 8, 8, 0, 0.0, P, st) == E
+    assert lib.dfisher_gram(FAKE_CTX, P, 4, 8, 8, 0, 0.0, None, st) == E
+    assert lib.dfisher_gram(FAKE_CTX, P, 4, 8, 8, 7, 0.0, P, st) == E      # unknown precision
+    assert lib.dfisher_gram(FAKE_CTX, P, 4, 8, 8, 0, -1.0, P, st) == E     # lambda < 0
+    assert lib.dfisher_gram(FAKE_CTX, P, 4, 8, 8, 0, float("nan"), P, st) == E
+    info = dfl.Info()
+    for lam in [0.0, -1e-3, float("inf"), float("nan")]:
+        assert lib.dfisher_solve(FAKE_CTX, P, 4, 8, 8, P, lam, P, None, st, ctypes.byref(info)) == E
+    for o in [_opts(dfl, prec=5), _opts(dfl, sweeps=-1), _opts(dfl, sweeps=17), _opts(dfl, shift=3),
+              _opts(dfl, x64=2)]:
+        assert lib.dfisher_solve(FAKE_CTX, P, 4, 8, 8, P, 1.0, P, ctypes.byref(o), st, None) == E
+    assert lib.dfisher_solve(FAKE_CTX, P, 4, 8, 8, None, 1.0, P, None, st, None) == E
+    assert lib.dfisher_solve(FAKE_CTX, P, 4, 8, 8, P, 1.0, None, None, st, None) == E
+    i64 = ctypes.c_int64(0)
+    assert lib.dfisher_potrf(FAKE_CTX, P, 0, ctypes.byref(i64), st) == E
+    assert lib.dfisher_potrf(FAKE_CTX, P, 4, None, st) == E
+    assert lib.dfisher_trsv(FAKE_CTX, P, 4, 2, P, P, st) == E
+    assert lib.dfisher_trsv(FAKE_CTX, P, 0, 0, P, P, st) == E
+    assert lib.dfisher_apply(FAKE_CTX, P, 4, 8, 8, P, P, 0.0, P, 0, st) == E
+    assert lib.dfisher_apply(FAKE_CTX, P, 4, 8, 8, P, P, 1.0, P, 3, st) == E
+    assert lib.dfisher_gemv(FAKE_CTX, P, 4, 8, 8, None, P, st) == E
+    out = ctypes.c_void_p()
+    assert lib.dfisher_factor_create(FAKE_CTX, P, 4, 8, 8, 0.0, None, st, ctypes.byref(out), None) == E
+    assert lib.dfisher_factor_create(FAKE_CTX, P, 4, 8, 8, 1.0, None, st, None, None) == E
+    assert lib.dfisher_factor_solve(None, P, 1, 8, P, 8, st, None) == E
+    lams = (ctypes.c_double * 2)(1e-3, -1.0)
+    assert lib.dfisher_solve_batched(FAKE_CTX, P, 4, 8, 8, lams, 2, P, 1, 8, P, 8, None, st, None) == E
+    lams = (ctypes.c_double * 1)(1e-3)
+    assert lib.dfisher_solve_batched(FAKE_CTX, P, 4, 8, 8, lams, 0, P, 1, 8, P, 8, None, st, None) == E
+    assert lib.dfisher_solve_batched(FAKE_CTX, P, 4, 8, 8, lams, 1, P, 1, 7, P, 8, None, st, None) == E
+    assert lib.dfisher_solve_uneven(FAKE_CTX, 0, None, None, None, None, None, None, None, None, st, None) == E
+    assert "NULL" in dfl.dfisher_last_error() or dfl.dfisher_last_error() != ""
+
+
+def test_too_large_n_for_triangular_solves_is_unsupported(dfl):
+    st = ctypes.c_void_p(0)
+    assert dfl.lib.dfisher_trsv(FAKE_CTX, FAKE_DEV, 20000, 0, FAKE_DEV, FAKE_DEV, st) == dfl.DFISHER_E_UNSUPPORTED
+
+
+def test_context_on_missing_device(dfl):
+    torch = pytest.importorskip("torch")
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    out = ctypes.c_void_p()
+    assert dfl.lib.dfisher_ctx_create(0, ctypes.byref(out)) == dfl.DFISHER_E_DEVICE
+    assert out.value is None
+    assert dfl.lib.dfisher_ctx_create(-1, ctypes.byref(out)) == dfl.DFISHER_E_INVALID_ARG
+    assert dfl.lib.dfisher_ctx_create(0, None) == dfl.DFISHER_E_INVALID_ARG
+    with pytest.raises(dfl.DfisherError) as ei:
+        dfl.dfisher_ctx_create(0)
+    assert ei.value.status == dfl.DFISHER_E_DEVICE
+    assert dfl.lib.dfisher_ctx_destroy(None) == dfl.DFISHER_OK

@@ -1,0 +1,298 @@
+"""GPU parity of every stage of the HIP path against the FP64 CPU oracle, through the C ABI.
+
+Sizes are chosen so the oracle finishes in seconds while the GPU kernels still span several
+256 x 256 Gram tiles, several 64-row Cholesky / triangular-solve blocks, several GEMV column
+groups, and ragged tails in n, m and the row stride (including a stride that is not a multiple
+of 4, which takes the scalar-load path).
+
+Tolerances (derived from the arithmetic):
+* Gram (FP32 or split-BF16 products, FP32 accumulation within a k-slice, FP64 across slices):
+  max_ij |dW_ij| / sqrt(W_ii W_jj) <= 2e-6 against the oracle's Gram of the same products
+  (exact Gram for FP32, the three-product split Gram for BF16x3); the diagonal is FP64.
+* FP64 stages (Cholesky, triangular solves, GEMVs with exact FP32 x FP32 products): relative
+  errors at the 1e-12 level, scaled by the conditioning where it matters.
+* End to end: relative error ||x - x*|| / ||x*|| <= 1e-6 with at least one refinement sweep.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def dfl():
+    import paper_2310_17556_amd as dfl
+    return dfl
+
+
+@pytest.fixture(scope="module")
+def ctx(dfl):
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = dfl.dfisher_ctx_create(0)
+    yield c
+    c.close()
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def dev_strided(S, ld):
+    """Upload S (n x m) into a wider buffer with row stride ld and return the (n, m) view."""
+    n, m = S.shape
+    buf = torch.full((n, ld), float("nan"), dtype=torch.float32, device="cuda")
+    buf[:, :m] = torch.from_numpy(S).cuda()
+    return buf[:, :m]
+
+
+def rel(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def scaled_err(W, Wref):
+    d = np.sqrt(np.abs(np.outer(np.diag(Wref), np.diag(Wref))))
+    return float(np.max(np.abs(W - Wref) / d))
+
+
+GRAM_SHAPES = [
+    # n, m, ld, kind
+    (32, 1024, 1024, "iid"),        # smallest workload: one partial tile
+    (300, 5000, 5003, "iid"),       # ragged n, stride not a multiple of 4 (scalar loads)
+    (513, 20001, 20004, "scaled"),  # 3 tile rows, ragged m and n
+    (1, 777, 777, "iid"),           # single row
+    (700, 3000, 3072, "iid"),       # 3 tile rows, padded stride
+]
+
+
+@pytest.mark.parametrize("n,m,ld,kind", GRAM_SHAPES)
+def test_gram_fp32(dfl, ctx, oracle_mod, n, m, ld, kind):
+    print(f"[gram fp32] n={n} m={m} ld={ld}", flush=True)
+    S = synth.make_S(n, m, synth.seed(20, n), kind)
+    lam = 1e-3
+    W = dfl.dfisher_gram(ctx, dev_strided(S, ld), dfl.DFISHER_GRAM_FP32, lam).cpu().numpy()
+    Wref = oracle_mod.gram(S, lam)
+    assert np.array_equal(W, W.T)
+    np.testing.assert_allclose(np.diag(W), np.diag(Wref), rtol=1e-13)
+    assert scaled_err(W, Wref) <= 2e-6
+
+
+@pytest.mark.parametrize("n,m,ld,kind", GRAM_SHAPES)
+def test_gram_bf16x3(dfl, ctx, oracle_mod, n, m, ld, kind):
+    print(f"[gram bf16x3] n={n} m={m} ld={ld}", flush=True)
+    S = synth.make_S(n, m, synth.seed(21, n), kind)
+    W = dfl.dfisher_gram(ctx, dev_strided(S, ld), dfl.DFISHER_GRAM_BF16X3, 0.0).cpu().numpy()
+    hi, lo = oracle_mod.split_bf16(S)
+    W3 = oracle_mod.gram3(hi, lo, 0.0)
+    Wex = oracle_mod.gram(S, 0.0)
+    np.fill_diagonal(W3, np.diag(Wex))          # the library's diagonal is the exact row norm
+    np.testing.assert_allclose(np.diag(W), np.diag(Wex), rtol=1e-13)
+    assert scaled_err(W, W3) <= 2e-6            # same products as the split definition
+    assert scaled_err(W, Wex) <= 3e-5           # within the split's 2^-16-level product error
+
+
+@pytest.mark.parametrize("n", [1, 5, 64, 65, 130, 1000])
+def test_potrf(dfl, ctx, oracle_mod, n):
+    print(f"[potrf] n={n}", flush=True)
+    S = synth.make_S(n, 3 * n + 7, synth.seed(22, n))
+    W = oracle_mod.gram(S, 0.5)
+    Lref, info = oracle_mod.cholesky(W)
+    assert info == 0
+    Wd = dev(W)
+    assert dfl.dfisher_potrf(ctx, Wd) == 0
+    L = Wd.cpu().numpy()
+    assert np.all(np.triu(L, 1) == 0)
+    assert rel(L, Lref) <= 1e-12
+    assert rel(L @ L.T, W) <= 1e-13
+
+
+@pytest.mark.parametrize("n,bad", [(130, 71), (70, 1), (200, 200), (64, 64), (65, 65)])
+def test_potrf_breakdown_index(dfl, ctx, oracle_mod, n, bad):
+    """A matrix whose first non-positive pivot is at a known index: the device reports the same
+    1-based index as the oracle (an integer result: exact)."""
+    print(f"[potrf breakdown] n={n} bad={bad}", flush=True)
+    rng = np.random.default_rng(n + bad)
+    A = rng.standard_normal((n, n)) / math.sqrt(n)
+    W = A @ A.T + np.eye(n)
+    W[bad - 1, bad - 1] -= 1e6          # pivot bad-1 goes negative, earlier ones are untouched
+    _, info_ref = oracle_mod.cholesky(W)
+    assert info_ref == bad
+    assert dfl.dfisher_potrf(ctx, dev(W)) == info_ref
+    Wn = W.copy()
+    Wn[3 % n, 3 % n] = np.nan
+    _, info_nan = oracle_mod.cholesky(Wn)
+    assert dfl.dfisher_potrf(ctx, dev(Wn)) == info_nan
+
+
+@pytest.mark.parametrize("n", [1, 63, 64, 65, 300, 2000])
+def test_trsv(dfl, ctx, oracle_mod, n):
+    print(f"[trsv] n={n}", flush=True)
+    S = synth.make_S(n, 2 * n + 3, synth.seed(23, n))
+    L, info = oracle_mod.cholesky(oracle_mod.gram(S, 1.0))
+    assert info == 0
+    b = np.random.default_rng(n).standard_normal(n)
+    Ld = dev(L)
+    z = dfl.dfisher_trsv(ctx, Ld, dev(b), 0).cpu().numpy()
+    y = dfl.dfisher_trsv(ctx, Ld, dev(b), 1).cpu().numpy()
+    assert rel(z, oracle_mod.forward(L, b)) <= 1e-12
+    assert rel(y, oracle_mod.backward(L, b)) <= 1e-12
+    # in place (b and y alias)
+    bd = dev(b)
+    dfl.dfisher_trsv(ctx, Ld, bd, 0, y=bd)
+    assert rel(bd.cpu().numpy(), oracle_mod.forward(L, b)) <= 1e-12
+
+
+@pytest.mark.parametrize("n,m,ld", [(32, 1024, 1024), (300, 50001, 50004), (77, 2049, 2051), (1000, 40000, 40000)])
+def test_gemv(dfl, ctx, oracle_mod, n, m, ld):
+    print(f"[gemv] n={n} m={m} ld={ld}", flush=True)
+    S = synth.make_S(n, m, synth.seed(24, n), "scaled")
+    v = synth.make_v(S, synth.seed(24, n))
+    b = dfl.dfisher_gemv(ctx, dev_strided(S, ld), dev(v)).cpu().numpy()
+    bref = oracle_mod.gemv(S, v)
+    # products of FP32 values are exact in FP64: only the summation order differs
+    scale = np.abs(S.astype(np.float64)) @ np.abs(v.astype(np.float64))
+    assert np.all(np.abs(b - bref) <= 1e-13 * scale + 1e-300)
+
+
+@pytest.mark.parametrize("n,m,ld", [(32, 1024, 1024), (300, 50001, 50004), (1000, 3000, 3001)])
+def test_apply(dfl, ctx, oracle_mod, n, m, ld):
+    print(f"[apply] n={n} m={m} ld={ld}", flush=True)
+    S = synth.make_S(n, m, synth.seed(25, n))
+    v = synth.make_v(S, synth.seed(25, n))
+    y = np.random.default_rng(n).standard_normal(n)
+    lam = 1e-3
+    x64 = dfl.dfisher_apply(ctx, dev_strided(S, ld), dev(v), dev(y), lam, x_fp64=True).cpu().numpy()
+    xref = oracle_mod.apply(S, v, y, lam)
+    scale = (np.abs(v.astype(np.float64)) + np.abs(S.astype(np.float64)).T @ np.abs(y)) / lam
+    assert np.all(np.abs(x64 - xref) <= 1e-13 * scale)
+    x32 = dfl.dfisher_apply(ctx, dev_strided(S, ld), dev(v), dev(y), lam).cpu().numpy()
+    assert np.all(np.abs(x32.astype(np.float64) - xref) <= 2.0 ** -24 * np.abs(xref) + 1e-13 * scale)
+
+
+SOLVE_CASES = [
+    # n, m, lam, prec, sweeps, kind, bound
+    (32, 1024, 1e-2, 0, 0, "iid", 1e-5),       # the smallest workload, plain FP32 path
+    (32, 1024, 1e-2, 0, 1, "iid", 1e-6),
+    (32, 1024, 1e-2, 1, 1, "iid", 1e-6),
+    (300, 20001, 1e-2, 1, 1, "iid", 1e-6),
+    (300, 20001, 1e-4, 1, 2, "iid", 1e-6),
+    (300, 20001, 1e-6, 1, 2, "iid", 1e-6),
+    (257, 30000, 1e-3, 0, 1, "scaled", 1e-6),   # row-space-heavy v (cancellation in v - S^T y)
+    (257, 30000, 1e-3, 1, 2, "scaled", 1e-6),
+    (600, 12000, 1e-4, 0, 2, "iid", 1e-6),
+]
+
+
+@pytest.mark.parametrize("n,m,lam,prec,sweeps,kind,bound", SOLVE_CASES)
+def test_solve(dfl, ctx, oracle_mod, n, m, lam, prec, sweeps, kind, bound):
+    print(f"[solve] n={n} m={m} lam={lam} prec={prec} sweeps={sweeps} kind={kind}", flush=True)
+    S = synth.make_S(n, m, synth.seed(26, n), kind)
+    v = synth.make_v(S, synth.seed(26, n), kind)
+    xref = oracle_mod.solve(S, v, lam)
+    x, info = dfl.dfisher_solve(ctx, dev(S), dev(v), lam, gram_prec=prec, sweeps=sweeps, x_fp64=True)
+    err = rel(x.cpu().numpy(), xref)
+    print(f"    rel err {err:.3e}  info {info}", flush=True)
+    assert info["sweeps_done"] == sweeps
+    assert err <= bound
+    # FP32 output: the same solution rounded once
+    x32, _ = dfl.dfisher_solve(ctx, dev(S), dev(v), lam, gram_prec=prec, sweeps=sweeps)
+    assert rel(x32.cpu().numpy(), xref) <= bound + 2.0 ** -23
+
+
+def test_solve_deterministic(dfl, ctx):
+    S = synth.make_S(300, 20001, 27)
+    v = synth.make_v(S, 27)
+    Sd, vd = dev(S), dev(v)
+    x1, _ = dfl.dfisher_solve(ctx, Sd, vd, 1e-3, gram_prec=1, sweeps=1)
+    x2, _ = dfl.dfisher_solve(ctx, Sd, vd, 1e-3, gram_prec=1, sweeps=1)
+    assert torch.equal(x1, x2)
+
+
+def test_solve_x_aliases_v(dfl, ctx, oracle_mod):
+    S = synth.make_S(64, 4096, 28)
+    v = synth.make_v(S, 28)
+    xref = oracle_mod.solve(S, v, 1e-2)
+    vd = dev(v)
+    dfl.dfisher_solve(ctx, dev(S), vd, 1e-2, sweeps=1, x=vd)
+    assert rel(vd.cpu().numpy(), xref) <= 1e-6
+
+
+def test_solve_strided_S(dfl, ctx, oracle_mod):
+    S = synth.make_S(200, 9999, 29)
+    v = synth.make_v(S, 29)
+    xref = oracle_mod.solve(S, v, 1e-3)
+    x, _ = dfl.dfisher_solve(ctx, dev_strided(S, 10001), dev(v), 1e-3, sweeps=1, x_fp64=True)
+    assert rel(x.cpu().numpy(), xref) <= 1e-6
+
+
+def test_factor_reuse(dfl, ctx, oracle_mod):
+    S = synth.make_S(200, 10000, 30)
+    V = synth.make_V(10000, 3, 30)
+    lam = 1e-3
+    Sd = dev(S)
+    f, info = dfl.dfisher_factor_create(ctx, Sd, lam, gram_prec=1, sweeps=1, x_fp64=True)
+    X = dfl.dfisher_factor_solve(f, dev(V)).cpu().numpy()
+    for r in range(3):
+        assert rel(X[r], oracle_mod.solve(S, V[r], lam)) <= 1e-6
+    # the factor is Cholesky of the (BF16x3) Gram + lambda: compare with the oracle's factor
+    L = dfl.dfisher_factor_copy_L(f).cpu().numpy()
+    Lref, _ = oracle_mod.cholesky(oracle_mod.gram(S, lam))
+    assert rel(L, Lref) <= 1e-4
+    x1, _ = dfl.dfisher_solve(ctx, Sd, dev(V[1]), lam, gram_prec=1, sweeps=1, x_fp64=True)
+    assert torch.equal(x1.cpu(), torch.from_numpy(X[1]))
+    dfl.dfisher_factor_destroy(f)
+
+
+def test_batched(dfl, ctx, oracle_mod):
+    n, m = 150, 8000
+    S = synth.make_S(n, m, 31)
+    V = synth.make_V(m, 2, 31)
+    lams = [1e-6, 1e-4, 1e-1]
+    X, infos = dfl.dfisher_solve_batched(ctx, dev(S), lams, dev(V), gram_prec=1, sweeps=2, x_fp64=True)
+    Xref = oracle_mod.solve_batched(S, lams, V)
+    X = X.cpu().numpy()
+    for li in range(len(lams)):
+        for r in range(2):
+            err = rel(X[li, r], Xref[li, r])
+            print(f"    lam={lams[li]} rhs={r} rel err {err:.3e} info {infos[li]}", flush=True)
+            assert err <= 1e-6
+
+
+def test_uneven(dfl, ctx, oracle_mod):
+    shapes = [(40, 3000, 1e-3), (300, 9000, 1e-5), (1, 500, 1e-2), (129, 7777, 3e-4)]
+    Ss = [synth.make_S(n, m, synth.seed(32, p)) for p, (n, m, _) in enumerate(shapes)]
+    vs = [synth.make_v(S, synth.seed(32, p)) for p, S in enumerate(Ss)]
+    xs, infos = dfl.dfisher_solve_uneven(ctx, [dev(S) for S in Ss], [dev(v) for v in vs], [s[2] for s in shapes],
+                                         gram_prec=1, sweeps=2, x_fp64=True)
+    for p, (S, v, (_, _, lam)) in enumerate(zip(Ss, vs, shapes)):
+        err = rel(xs[p].cpu().numpy(), oracle_mod.solve(S, v, lam))
+        print(f"    problem {p} rel err {err:.3e}", flush=True)
+        assert err <= 1e-6
+
+
+def test_nan_input_reports_not_spd(dfl, ctx):
+    S = synth.make_S(64, 1000, 33)
+    S[5, 17] = np.nan
+    v = synth.make_v(S, 33)
+    for policy in (dfl.DFISHER_SHIFT_NONE, dfl.DFISHER_SHIFT_ON_FAILURE):
+        with pytest.raises(dfl.DfisherError) as ei:
+            dfl.dfisher_solve(ctx, dev(S), dev(v), 1e-2, shift_policy=policy)
+        assert ei.value.status == dfl.DFISHER_E_NOT_SPD
+
+
+def test_stage_timing(dfl, ctx):
+    S = synth.make_S(300, 20001, 34)
+    v = synth.make_v(S, 34)
+    dfl.dfisher_ctx_enable_timing(ctx, True)
+    dfl.dfisher_solve(ctx, dev(S), dev(v), 1e-3, sweeps=1)
+    t = dfl.dfisher_ctx_last_timing(ctx)
+    dfl.dfisher_ctx_enable_timing(ctx, False)
+    assert t["gram_ms"] > 0 and t["total_ms"] >= t["gram_ms"]
