@@ -76,7 +76,7 @@ GRAM_SHAPES = [
 @pytest.mark.parametrize("n,m,ld,kind", GRAM_SHAPES)
 def test_gram_fp32(dfl, ctx, oracle_mod, n, m, ld, kind):
     print(f"[gram fp32] n={n} m={m} ld={ld}", flush=True)
-    S = synth.make_S(n, m, synth.seed(20, n), kind)
+    S = synth.make_S(n, m, synth.seed(20, n), kind, center=n > 1)   # one centered row is all zeros
     lam = 1e-3
     W = dfl.dfisher_gram(ctx, dev_strided(S, ld), dfl.DFISHER_GRAM_FP32, lam).cpu().numpy()
     Wref = oracle_mod.gram(S, lam)
@@ -88,7 +88,7 @@ def test_gram_fp32(dfl, ctx, oracle_mod, n, m, ld, kind):
 @pytest.mark.parametrize("n,m,ld,kind", GRAM_SHAPES)
 def test_gram_bf16x3(dfl, ctx, oracle_mod, n, m, ld, kind):
     print(f"[gram bf16x3] n={n} m={m} ld={ld}", flush=True)
-    S = synth.make_S(n, m, synth.seed(21, n), kind)
+    S = synth.make_S(n, m, synth.seed(21, n), kind, center=n > 1)   # one centered row is all zeros
     W = dfl.dfisher_gram(ctx, dev_strided(S, ld), dfl.DFISHER_GRAM_BF16X3, 0.0).cpu().numpy()
     hi, lo = oracle_mod.split_bf16(S)
     W3 = oracle_mod.gram3(hi, lo, 0.0)
