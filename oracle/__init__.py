@@ -15,6 +15,7 @@ Every function states the passage of the paper it follows:
 * :func:`solve`      - Algorithm 1 end to end.
 * :func:`residual`   - v - lambda x - S^T S x, the identity of Proposition 1 (Appendix A).
 * :func:`split_bf16`, :func:`gram3` - definition of the split-BF16 Gram (three products).
+* :func:`quant_mxfp8` - definition of the block-scaled FP8 inputs of the scaled-FP8 Gram.
 """
 from __future__ import annotations
 
@@ -62,6 +63,7 @@ def _load():
             "oracle_split_bf16": ([P, I, I, I, P, P], None),
             "oracle_gram3": ([P, P, I, I, D, P], None),
             "oracle_row_norms": ([P, I, I, I, P], None),
+            "oracle_quant_mxfp8": ([P, I, I, I, P, P], None),
             "oracle_gram_entries": ([P, I, I, D, P, P, I, P], None),
             "oracle_num_threads": ([], ctypes.c_int),
         }
@@ -198,6 +200,17 @@ def gram3(hi, lo, lam: float = 0.0) -> np.ndarray:
     W = np.empty((n, n), dtype=np.float64)
     _load().oracle_gram3(_p(hi), _p(lo), n, m, float(lam), _p(W))
     return W
+
+
+def quant_mxfp8(S) -> tuple[np.ndarray, np.ndarray]:
+    """Block-scaled FP8 (E4M3) form of S: 32-column blocks per row, power-of-two scale 2^e with the
+    smallest e such that no element exceeds 448 * 2^e, elements rounded to nearest even.
+    Returns (deq, e): deq = q * 2^e as float32 (n x m), e as int32 (n x ceil(m/32))."""
+    S, n, m, lds = _S(S)
+    deq = np.empty((n, m), dtype=np.float32)
+    e = np.empty((n, (m + 31) // 32), dtype=np.int32)
+    _load().oracle_quant_mxfp8(_p(S), n, m, lds, _p(deq), _p(e))
+    return deq, e
 
 
 def row_norms(S) -> np.ndarray:

@@ -220,6 +220,54 @@ EXPORT void oracle_gram3(const float* hi, const float* lo, int64_t n, int64_t m,
   }
 }
 
+/* Round a finite value to the nearest OCP FP8 E4M3 value, ties to even (1 sign, 4 exponent bits
+ * with bias 7, 3 mantissa bits; normals 2^-6 .. 448, subnormals k * 2^-9). The caller keeps
+ * |a| <= 448, so no saturation is needed. From the definition: the spacing of representable
+ * values at magnitude |a| is 2^(floor(log2|a|) - 3) for |a| >= 2^-6 and 2^-9 below. */
+static double round_e4m3(double a) {
+  if (a == 0.0 || !isfinite(a)) return a;
+  double q;
+  if (fabs(a) < ldexp(1.0, -6)) {
+    q = ldexp(1.0, -9);
+  } else {
+    int e;
+    frexp(a, &e);               /* |a| = f 2^e, 0.5 <= f < 1, so floor(log2|a|) = e - 1 */
+    q = ldexp(1.0, e - 1 - 3);
+  }
+  return nearbyint(a / q) * q;
+}
+
+/* Block-scaled FP8 representation of S (the scaled-FP8 form of the Gram's inputs). Row i is cut
+ * into blocks of 32 consecutive columns [32b, 32b + 32) (the last may be shorter). Each block
+ * gets a power-of-two scale 2^e with e the smallest integer such that amax <= 448 * 2^e
+ * (amax = max |S_ik| over the block; e = -127 for an all-zero block), clamped to [-127, 127];
+ * each element becomes q = round_e4m3(S_ik / 2^e). Outputs: deq (n x m, FP32) = q * 2^e, the
+ * value the products use, and sexp (n x ceil(m/32), int32) = e. */
+EXPORT void oracle_quant_mxfp8(const float* S, int64_t n, int64_t m, int64_t lds, float* deq, int32_t* sexp) {
+  const int64_t nblk = (m + 31) / 32;
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < n; ++i) {
+    for (int64_t b = 0; b < nblk; ++b) {
+      const int64_t k0 = 32 * b, k1 = (k0 + 32 < m) ? k0 + 32 : m;
+      double amax = 0.0;
+      for (int64_t k = k0; k < k1; ++k) {
+        const double a = fabs(sd(S, lds, i, k));
+        if (a > amax) amax = a;
+      }
+      int e = -127;
+      if (amax > 0.0) {
+        e = -127;
+        while (e < 127 && amax > 448.0 * ldexp(1.0, e)) ++e;
+      }
+      sexp[i * nblk + b] = e;
+      for (int64_t k = k0; k < k1; ++k) {
+        const double q = round_e4m3(ldexp(sd(S, lds, i, k), -e));
+        deq[i * m + k] = (float)ldexp(q, e);
+      }
+    }
+  }
+}
+
 /* Squared row norms d_i = sum_k S_ik^2 (the exact diagonal of S S^T). */
 EXPORT void oracle_row_norms(const float* S, int64_t n, int64_t m, int64_t lds, double* d) {
 #pragma omp parallel for schedule(static)

@@ -390,3 +390,79 @@ def test_gram3_against_blas(oracle_mod):
     W = oracle_mod.gram(S, 0.5)
     dd = np.sqrt(np.outer(np.diag(W), np.diag(W)))
     assert np.max(np.abs(oracle_mod.gram3(hi, lo, 0.5) - W) / dd) <= 2.0 ** -15
+
+
+# ------------------------------------------------------------------ scaled-FP8 (E4M3 + E8M0) form
+def _e4m3_table():
+    """Every finite non-negative E4M3 value, from the bit layout: exponent field E (bias 7) and
+    mantissa field M; E = 0 is subnormal (M * 2^-9); E = 15, M = 7 is NaN, so 448 is the largest."""
+    vals = []
+    for E in range(16):
+        for M in range(8):
+            if E == 15 and M == 7:
+                continue
+            vals.append(M * 2.0 ** -9 if E == 0 else (1 + M / 8) * 2.0 ** (E - 7))
+    return np.array(sorted(set(vals)))
+
+
+def test_quant_mxfp8_matches_torch_e4m3_cast(oracle_mod):
+    """A block whose largest magnitude lies in (224, 448] has scale 2^0, so its codes must equal
+    torch's round-to-nearest-even cast to float8_e4m3fn."""
+    torch = pytest.importorskip("torch")
+    rng = np.random.default_rng(7)
+    S = (rng.standard_normal((6, 96)) * 60.0).astype(np.float32)
+    S[:, ::32] = np.float32(300.0)      # pins every block's maximum into (224, 448]
+    S[1, 1:9] = [0.0, -0.0, 2.0 ** -10, 3 * 2.0 ** -10, 1.0625, 1.1875, -440.0, 2.0 ** -7 * 1.0625]
+    deq, e = oracle_mod.quant_mxfp8(S)
+    assert np.all(e == 0)
+    ref = torch.from_numpy(S).to(torch.float8_e4m3fn).to(torch.float32).numpy()
+    np.testing.assert_array_equal(deq, ref)
+
+
+def test_quant_mxfp8_hand_values(oracle_mod):
+    """Hand-computed roundings (block scale 2^0): ties go to the even mantissa."""
+    S = np.zeros((1, 32), dtype=np.float32)
+    S[0, :10] = [448.0, 1.0625, 1.1875, 3 * 2.0 ** -10, 2.0 ** -10, 5 * 2.0 ** -10, 17.0, 19.0, -0.0, -1.0625]
+    want = [448.0, 1.0, 1.25, 2 * 2.0 ** -9, 0.0, 2 * 2.0 ** -9, 16.0, 20.0, 0.0, -1.0]
+    deq, e = oracle_mod.quant_mxfp8(S)
+    assert e[0, 0] == 0
+    np.testing.assert_array_equal(deq[0, :10], np.array(want, dtype=np.float32))
+
+
+def test_quant_mxfp8_scale_is_smallest_power(oracle_mod):
+    """Scale exponent: smallest e with amax <= 448 * 2^e (-127 for an all-zero block), and every
+    dequantised value is 2^e times a finite E4M3 value nearest to S / 2^e."""
+    rng = np.random.default_rng(11)
+    n, m = 5, 200
+    S = (rng.standard_normal((n, m)) * 10.0 ** rng.uniform(-6, 3, size=(n, 1))).astype(np.float32)
+    S[2, 32:64] = 0.0
+    S[3, 64:96] = 448.0 * 2.0 ** -20      # amax exactly on a power-of-two boundary
+    deq, e = oracle_mod.quant_mxfp8(S)
+    table = _e4m3_table()
+    for i in range(n):
+        for b in range((m + 31) // 32):
+            blk = S[i, 32 * b:32 * b + 32].astype(np.float64)
+            amax = np.abs(blk).max()
+            eb = int(e[i, b])
+            if amax == 0.0:
+                assert eb == -127
+                continue
+            assert amax <= 448.0 * 2.0 ** eb and amax > 448.0 * 2.0 ** (eb - 1)
+            x = np.abs(blk) / 2.0 ** eb
+            q = np.abs(deq[i, 32 * b:32 * b + 32].astype(np.float64)) / 2.0 ** eb
+            assert np.all(np.isin(q, table))
+            # nearest: no table value is strictly closer than the chosen one
+            dist = np.abs(table[None, :] - x[:, None]).min(axis=1)
+            np.testing.assert_array_equal(np.abs(q - x), dist)
+            assert np.all(np.sign(deq[i, 32 * b:32 * b + 32]) * np.sign(blk) >= 0)
+    assert e[3, 2] == -20
+
+
+def test_quant_mxfp8_power_of_two_scaling(oracle_mod):
+    """Scaling S by 2^k shifts every block exponent by k and scales the result exactly."""
+    rng = np.random.default_rng(5)
+    S = rng.standard_normal((3, 130)).astype(np.float32)
+    d1, e1 = oracle_mod.quant_mxfp8(S)
+    d2, e2 = oracle_mod.quant_mxfp8(S * np.float32(2.0 ** 13))
+    np.testing.assert_array_equal(e2, e1 + 13)
+    np.testing.assert_array_equal(d2, d1 * np.float32(2.0 ** 13))
