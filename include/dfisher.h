@@ -59,15 +59,25 @@ typedef enum dfisher_status {
  * accumulation across chunks; the diagonal is always the exact FP64 squared row norm. */
 typedef enum dfisher_gram_prec {
   DFISHER_GRAM_FP32 = 0,    /* FP32 inputs, FP32 matrix-core products                      */
-  DFISHER_GRAM_BF16X3 = 1   /* split-BF16: S = hi + lo, keeps hi.hi + hi.lo + lo.hi        */
+  DFISHER_GRAM_BF16X3 = 1,  /* split-BF16: S = hi + lo, keeps hi.hi + hi.lo + lo.hi        */
+  DFISHER_GRAM_MXFP8 = 2    /* scaled FP8: E4M3 codes with one power-of-two scale per row
+                               and 32-column block (see dfisher_quantize_mxfp8); needs rows
+                               aligned to 16 bytes (lds a multiple of 4)                   */
 } dfisher_gram_prec;
 
 /* What to do when the Cholesky of the computed W meets a pivot that is not > 0 (the computed
  * Gram can lose definiteness along directions where W's eigenvalue is close to lambda). */
 typedef enum dfisher_shift_policy {
   DFISHER_SHIFT_NONE = 0,        /* fail with DFISHER_E_NOT_SPD                                 */
-  DFISHER_SHIFT_ON_FAILURE = 1   /* refactor W + tau I with growing tau (reported in info);
+  DFISHER_SHIFT_ON_FAILURE = 1,  /* refactor W + tau I with growing tau (reported in info);
                                     refinement sweeps then correct against the unshifted W   */
+  DFISHER_SHIFT_ALWAYS = 2       /* factor W + tau I from the start, tau = 2 sqrt(n) u max_i W_ii
+                                    with u = 2^-24 for the FP32 and split-BF16 Grams and
+                                    u = 0.25 / sqrt(m) for the scaled-FP8 Gram (above the
+                                    rounding error of the computed Gram), so the factored
+                                    matrix dominates the exact W and every refinement sweep
+                                    contracts; grows like DFISHER_SHIFT_ON_FAILURE if the
+                                    Cholesky still fails. Meant for sweeps >= 1.              */
 } dfisher_shift_policy;
 
 typedef struct dfisher_options {
@@ -123,6 +133,18 @@ DFISHER_API dfisher_status dfisher_ctx_last_timing(dfisher_ctx* ctx, dfisher_tim
  * diagonal is the FP64 squared row norm plus lambda. */
 DFISHER_API dfisher_status dfisher_gram(dfisher_ctx* ctx, const float* S, int64_t n, int64_t m, int64_t lds,
                             int32_t prec, double lambda, double* W, void* stream);
+
+/* The scaled-FP8 form of S used by DFISHER_GRAM_MXFP8 (the precision preparation of the Gram's
+ * inputs). Row i is cut into 32-column blocks; block b gets the scale 2^e with the smallest
+ * integer e such that max_k |S_ik| <= 448 * 2^e over the block (e in [-127, 127], -127 for an
+ * all-zero block), and each element becomes the E4M3 code (OCP FP8, 1-4-3, bias 7, max 448)
+ * of S_ik / 2^e rounded to nearest even. Outputs (device): codes[i * ldq + k] for k < m
+ * (ldq a multiple of 64, >= m; bytes k >= m of a row are unspecified) and
+ * scales[i * (ldq / 32) + b] = e + 127 (E8M0). Needs 16-byte aligned rows (lds % 4 == 0 and
+ * S 16-byte aligned), else DFISHER_E_UNSUPPORTED. */
+DFISHER_API dfisher_status dfisher_quantize_mxfp8(dfisher_ctx* ctx, const float* S, int64_t n, int64_t m,
+                                                  int64_t lds, uint8_t* codes, int64_t ldq, uint8_t* scales,
+                                                  void* stream);
 
 /* Algorithm 1 step 2: in-place Cholesky W = L L^T of an n x n FP64 SPD matrix (row-major,
  * row stride n). Reads the lower triangle only; writes L to the lower triangle and zeros the

@@ -15,10 +15,10 @@ import os
 __all__ = [
     "DfisherError", "Info", "Timing", "lib",
     "DFISHER_OK", "DFISHER_E_INVALID_ARG", "DFISHER_E_NOT_SPD", "DFISHER_E_NO_MEMORY", "DFISHER_E_DEVICE",
-    "DFISHER_E_UNSUPPORTED", "DFISHER_GRAM_FP32", "DFISHER_GRAM_BF16X3", "DFISHER_SHIFT_NONE",
-    "DFISHER_SHIFT_ON_FAILURE",
+    "DFISHER_E_UNSUPPORTED", "DFISHER_GRAM_FP32", "DFISHER_GRAM_BF16X3", "DFISHER_GRAM_MXFP8", "DFISHER_SHIFT_NONE",
+    "DFISHER_SHIFT_ON_FAILURE", "DFISHER_SHIFT_ALWAYS",
     "dfisher_ctx_create", "dfisher_ctx_destroy", "dfisher_ctx_enable_timing", "dfisher_ctx_last_timing",
-    "dfisher_gram", "dfisher_potrf", "dfisher_gemv",
+    "dfisher_gram", "dfisher_quantize_mxfp8", "dfisher_potrf", "dfisher_gemv",
     "dfisher_trsv", "dfisher_apply", "dfisher_solve", "dfisher_factor_create", "dfisher_factor_solve",
     "dfisher_factor_copy_L", "dfisher_factor_destroy", "dfisher_solve_batched", "dfisher_solve_uneven",
     "dfisher_status_string", "dfisher_last_error",
@@ -32,8 +32,10 @@ DFISHER_E_DEVICE = 4
 DFISHER_E_UNSUPPORTED = 5
 DFISHER_GRAM_FP32 = 0
 DFISHER_GRAM_BF16X3 = 1
+DFISHER_GRAM_MXFP8 = 2
 DFISHER_SHIFT_NONE = 0
 DFISHER_SHIFT_ON_FAILURE = 1
+DFISHER_SHIFT_ALWAYS = 2
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libdfisher.so")
@@ -73,6 +75,7 @@ def _load():
         "dfisher_ctx_destroy": ([P], I32),
         "dfisher_gram": ([P, P, I64, I64, I64, I32, D, P, P], I32),
         "dfisher_potrf": ([P, P, I64, ctypes.POINTER(I64), P], I32),
+        "dfisher_quantize_mxfp8": ([P, P, I64, I64, I64, P, I64, P, P], I32),
         "dfisher_gemv": ([P, P, I64, I64, I64, P, P, P], I32),
         "dfisher_trsv": ([P, P, I64, I32, P, P, P], I32),
         "dfisher_apply": ([P, P, I64, I64, I64, P, P, D, P, I32, P], I32),
@@ -232,6 +235,18 @@ def dfisher_gram(ctx, S, prec: int = DFISHER_GRAM_FP32, lam: float = 0.0, W=None
     _check(_lib().dfisher_gram(ctx.ptr, _ptr(S), n, m, lds, int(prec), float(lam), _ptr(W), _stream(stream)),
            "dfisher_gram")
     return W
+
+
+def dfisher_quantize_mxfp8(ctx, S, stream=None):
+    """Scaled-FP8 form of S: returns (codes uint8 (n, ldq), scales uint8 (n, ldq // 32), ldq)."""
+    torch = _torch()
+    n, m, lds = _S_args(S)
+    ldq = (m + 63) // 64 * 64
+    codes = torch.empty((n, ldq), dtype=torch.uint8, device=S.device)
+    scales = torch.empty((n, ldq // 32), dtype=torch.uint8, device=S.device)
+    _check(_lib().dfisher_quantize_mxfp8(ctx.ptr, _ptr(S), n, m, lds, _ptr(codes), ldq, _ptr(scales),
+                                         _stream(stream)), "dfisher_quantize_mxfp8")
+    return codes, scales, ldq
 
 
 def dfisher_potrf(ctx, W, stream=None) -> int:

@@ -43,7 +43,6 @@ dfisher_status fail(dfisher_status s, const char* fmt, ...) {
     if (s_ != DFISHER_OK) return s_;   \
   } while (0)
 
-constexpr int64_t TRSV_MAX_N = 15000;   // the triangular solves keep the solution in LDS
 constexpr int MAX_SWEEPS = 16;
 constexpr int MAX_SHIFT_ATTEMPTS = 10;
 
@@ -73,7 +72,8 @@ struct dfisher_factor {
   int64_t n = 0, m = 0, lds = 0;
   double lambda = 0.0;
   dfisher_options opt{};
-  double* L = nullptr;  // owned
+  double* L = nullptr;     // owned: n x n
+  double* Dinv = nullptr;  // owned: inverses of the 64 x 64 diagonal blocks of L
   double shift = 0.0;
 };
 
@@ -150,25 +150,35 @@ dfisher_status check_S(const float* S, int64_t n, int64_t m, int64_t lds) {
 dfisher_status check_opt(const dfisher_options* opt, dfisher_options* out) {
   dfisher_options d = DFISHER_OPTIONS_DEFAULT;
   if (opt) d = *opt;
-  if (d.gram_prec != DFISHER_GRAM_FP32 && d.gram_prec != DFISHER_GRAM_BF16X3)
+  if (d.gram_prec != DFISHER_GRAM_FP32 && d.gram_prec != DFISHER_GRAM_BF16X3 && d.gram_prec != DFISHER_GRAM_MXFP8)
     return fail(DFISHER_E_INVALID_ARG, "unknown gram_prec %d", d.gram_prec);
   if (d.sweeps < 0 || d.sweeps > MAX_SWEEPS)
     return fail(DFISHER_E_INVALID_ARG, "sweeps = %d outside 0..%d", d.sweeps, MAX_SWEEPS);
-  if (d.shift_policy != DFISHER_SHIFT_NONE && d.shift_policy != DFISHER_SHIFT_ON_FAILURE)
+  if (d.shift_policy != DFISHER_SHIFT_NONE && d.shift_policy != DFISHER_SHIFT_ON_FAILURE &&
+      d.shift_policy != DFISHER_SHIFT_ALWAYS)
     return fail(DFISHER_E_INVALID_ARG, "unknown shift_policy %d", d.shift_policy);
   if (d.x_fp64 != 0 && d.x_fp64 != 1) return fail(DFISHER_E_INVALID_ARG, "x_fp64 must be 0 or 1");
   *out = d;
   return DFISHER_OK;
 }
 
-dfisher_status check_trsv_n(int64_t n) {
-  if (n > TRSV_MAX_N)
-    return fail(DFISHER_E_UNSUPPORTED, "n = %lld exceeds the triangular-solve limit %lld", (long long)n,
-                (long long)TRSV_MAX_N);
+hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+bool rows_aligned16(const float* S, int64_t lds) {
+  return (lds % 4) == 0 && (reinterpret_cast<uintptr_t>(S) & 15) == 0;
+}
+
+dfisher_status check_prec_layout(int prec, const float* S, int64_t lds) {
+  if (prec == DFISHER_GRAM_MXFP8 && !rows_aligned16(S, lds))
+    return fail(DFISHER_E_UNSUPPORTED, "the scaled-FP8 Gram needs 16-byte aligned rows (lds %% 4 == 0)");
   return DFISHER_OK;
 }
 
-hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+// Rounding unit of the computed Gram's entries, relative to max_i W_ii, used by the up-front shift.
+double gram_unit(int prec, int64_t m) {
+  if (prec == DFISHER_GRAM_MXFP8) return 0.25 / std::sqrt((double)m);
+  return std::ldexp(1.0, -24);
+}
 
 // Everything one factorisation + solve needs, carved from the workspace.
 struct SolveBufs {
@@ -183,6 +193,14 @@ struct SolveBufs {
   double* y;       // W^-1 S v
   double* r;       // refinement residual
   double* t;       // S^T y (m, FP64)
+  double* Dinv;    // inverses of L's 64 x 64 diagonal blocks
+  double* dkk;     // Cholesky scratch: current diagonal block inverse
+  double* tw;      // triangular-solve work vector (n)
+  uint8_t* q8;     // scaled-FP8 codes of S (n x ldq), when the Gram is MXFP8
+  uint8_t* sc8;    // their E8M0 scales (n x ldq/32)
+  int64_t ldq;
+  uint16_t* hi;    // split-BF16 planes of S (n x gp->ldh each), when the Gram uses them
+  uint16_t* lo;
   size_t bytes;
 };
 
@@ -202,41 +220,46 @@ SolveBufs carve(char* base, int64_t n, int64_t m, const dfi::GramPlan* gp, const
   s.y = c.take<double>((size_t)n);
   s.r = c.take<double>((size_t)n);
   s.t = need_t ? c.take<double>((size_t)m) : nullptr;
+  s.Dinv = c.take<double>(dfi::trsv_dinv_bytes(n) / sizeof(double));
+  s.dkk = c.take<double>(dfi::POTRF_DKK_BYTES / sizeof(double));
+  s.tw = c.take<double>((size_t)n);
+  s.ldq = dfi::fp8_ldq(m);
+  const bool fp8 = gp && gp->prec == DFISHER_GRAM_MXFP8;
+  s.q8 = fp8 ? c.take<uint8_t>((size_t)(n * s.ldq)) : nullptr;
+  s.sc8 = fp8 ? c.take<uint8_t>((size_t)(n * (s.ldq / 32))) : nullptr;
+  const bool split = gp && gp->prec == DFISHER_GRAM_BF16X3 && gp->ldh > 0;
+  s.hi = split ? c.take<uint16_t>((size_t)(n * gp->ldh)) : nullptr;
+  s.lo = split ? c.take<uint16_t>((size_t)(n * gp->ldh)) : nullptr;
   s.bytes = c.off;
   return s;
 }
 
 // Cholesky of W (+ tau I) into L following the shift policy. Synchronises once per attempt.
-dfisher_status factor_with_policy(dfisher_ctx* ctx, const double* W, double* L, int64_t n, int policy,
-                                  hipStream_t st, double* shift_out, int64_t* info_out, int32_t* attempts_out) {
-  double tau = 0.0;
-  double base = 0.0;
+dfisher_status factor_with_policy(dfisher_ctx* ctx, const double* W, double* L, double* dkk, int64_t n, int policy,
+                                  double unit, hipStream_t st, double* shift_out, int64_t* info_out,
+                                  int32_t* attempts_out) {
+  // base shift: about sqrt(n) times the rounding unit of a computed Gram entry
+  const double base_scale = std::sqrt((double)n) * unit;
+  double scale = 0.0;  // tau = scale * max_i W_ii, evaluated on the device
+  if (policy == DFISHER_SHIFT_ALWAYS) scale = 2.0 * base_scale;
   int attempts = 0;
   int64_t info = 0;
+  if (policy != DFISHER_SHIFT_NONE) HIP_TRY(dfi::diag_max(W, n, ctx->d_scalar, st));
   for (;;) {
-    HIP_TRY(dfi::shift_copy(W, L, n, tau, st));
-    HIP_TRY(dfi::potrf_launch(L, n, ctx->d_info, ctx->d_flag, st));
+    HIP_TRY(dfi::shift_copy(W, L, n, scale, ctx->d_scalar, st));
+    HIP_TRY(dfi::potrf_launch(L, n, ctx->d_info, ctx->d_flag, dkk, st));
     HIP_TRY(hipMemcpyAsync(ctx->h_status, ctx->d_info, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    if (policy != DFISHER_SHIFT_NONE)
+      HIP_TRY(hipMemcpyAsync(ctx->h_scalar, ctx->d_scalar, sizeof(double), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
     ++attempts;
     info = ctx->h_status[0];
     if (info == 0 || policy == DFISHER_SHIFT_NONE || attempts >= MAX_SHIFT_ATTEMPTS) break;
-    if (base == 0.0) {
-      HIP_TRY(dfi::diag_max(W, n, ctx->d_scalar, st));
-      HIP_TRY(hipMemcpyAsync(ctx->h_scalar, ctx->d_scalar, sizeof(double), hipMemcpyDeviceToHost, st));
-      HIP_TRY(hipStreamSynchronize(st));
-      const double dmax = ctx->h_scalar[0];
-      if (!std::isfinite(dmax)) break;  // NaN/Inf in W: shifting cannot help
-      // about the size of the rounding error of an FP32-accumulated Gram entry, times sqrt(n)
-      base = std::sqrt((double)n) * std::ldexp(dmax, -24);
-      if (!(base > 0.0)) base = std::ldexp(1.0, -24);
-      tau = base;
-    } else {
-      tau *= 8.0;
-    }
+    if (!std::isfinite(ctx->h_scalar[0])) break;  // NaN/Inf in W: shifting cannot help
+    scale = (scale == 0.0) ? base_scale : 8.0 * scale;
   }
   HIP_TRY(dfi::zero_upper(L, n, st));
-  *shift_out = (info == 0) ? tau : 0.0;
+  *shift_out = (info == 0 && policy != DFISHER_SHIFT_NONE) ? scale * ctx->h_scalar[0] : 0.0;
   *info_out = info;
   *attempts_out = attempts;
   if (info != 0)
@@ -244,31 +267,54 @@ dfisher_status factor_with_policy(dfisher_ctx* ctx, const double* W, double* L, 
   return DFISHER_OK;
 }
 
+// Row pass (b = S v when v != nullptr, the exact row norms, and for the scaled-FP8 Gram its codes),
+// then the Gram of `prec` reduced into W (lower triangle; upper too if mirror) with lambda added.
+dfisher_status gram_stage(const float* S, const float* v, const dfi::GramPlan& gp, const dfi::RowPassPlan& rp,
+                          const SolveBufs& B, double lambda, double* W, int mirror, hipStream_t st, StageClock* clk) {
+  if (clk) clk->mark(0);
+  if (gp.prec == DFISHER_GRAM_MXFP8) {
+    HIP_TRY(dfi::rowpass_launch(rp, S, v, nullptr, v != nullptr, true, B.rpart, st, B.q8, B.sc8, B.ldq));
+  } else if (B.hi) {
+    HIP_TRY(dfi::rowpass_launch_split(rp, S, v, B.rpart, B.hi, B.lo, gp.ldh, st));
+  } else {
+    HIP_TRY(dfi::rowpass_launch(rp, S, v, nullptr, v != nullptr, true, B.rpart, st));
+  }
+  HIP_TRY(dfi::rowpass_reduce(rp, B.rpart, v != nullptr, true, B.b, B.d, nullptr, nullptr, 0.0, st));
+  if (clk) clk->mark(1);
+  if (gp.prec == DFISHER_GRAM_MXFP8) {
+    HIP_TRY(dfi::gram_launch_fp8(gp, B.q8, B.sc8, B.ldq, B.gpart, st));
+  } else if (B.hi) {
+    HIP_TRY(dfi::gram_launch_split(gp, B.hi, B.lo, B.gpart, st));
+  } else {
+    HIP_TRY(dfi::gram_launch(gp, S, B.gpart, st));
+  }
+  if (clk) clk->mark(2);
+  HIP_TRY(dfi::gram_reduce(gp, S, B.gpart, B.d, lambda, W, mirror, st));
+  return DFISHER_OK;
+}
+
 // y = W^-1 b through the factor, then `sweeps` refinement sweeps against the exact operator
 // W = S S^T + lambda I: r = b - lambda y - S (S^T y) (FP64 accumulation), y += L^-T L^-1 r.
 dfisher_status solve_y(const float* S, int64_t n, int64_t m, int64_t lds, double lambda, const double* L,
-                       const SolveBufs& B, const dfi::RowPassPlan& rp, const dfi::ColPassPlan& cp, int sweeps,
-                       hipStream_t st, StageClock* clk = nullptr) {
-  HIP_TRY(dfi::trsv_launch(L, n, 0, B.b, B.z, st));
-  HIP_TRY(dfi::trsv_launch(L, n, 1, B.z, B.y, st));
+                       const double* Dinv, const SolveBufs& B, const dfi::RowPassPlan& rp, const dfi::ColPassPlan& cp,
+                       int sweeps, hipStream_t st, StageClock* clk = nullptr) {
+  HIP_TRY(dfi::trsv_launch(L, Dinv, n, 0, B.b, B.z, B.tw, st));
+  HIP_TRY(dfi::trsv_launch(L, Dinv, n, 1, B.z, B.y, B.tw, st));
   if (clk) clk->mark(5);
   for (int s = 0; s < sweeps; ++s) {
     HIP_TRY(dfi::colpass_launch(cp, S, n, m, lds, B.y, nullptr, 1.0, B.t, 2, B.cpart, st));
     HIP_TRY(dfi::rowpass_launch(rp, S, nullptr, B.t, true, false, B.rpart, st));
     HIP_TRY(dfi::rowpass_reduce(rp, B.rpart, true, false, B.r, nullptr, B.b, B.y, lambda, st));
-    HIP_TRY(dfi::trsv_launch(L, n, 0, B.r, B.z, st));
-    HIP_TRY(dfi::trsv_launch(L, n, 1, B.z, B.r, st));
+    HIP_TRY(dfi::trsv_launch(L, Dinv, n, 0, B.r, B.z, B.tw, st));
+    HIP_TRY(dfi::trsv_launch(L, Dinv, n, 1, B.z, B.r, B.tw, st));
     HIP_TRY(dfi::axpy_inplace(B.y, B.r, n, st));
   }
   if (clk) clk->mark(6);
   return DFISHER_OK;
 }
 
-// Per-device kernel attributes (called with the device current).
-dfisher_status init_kernels() {
-  HIP_TRY(dfi::trsv_prepare());
-  return DFISHER_OK;
-}
+// Per-device kernel set-up (called with the device current). Nothing to do at present.
+dfisher_status init_kernels() { return DFISHER_OK; }
 
 }  // namespace
 
@@ -398,33 +444,37 @@ dfisher_status dfisher_gram(dfisher_ctx* ctx, const float* S, int64_t n, int64_t
   DF_TRY(check_ctx(ctx));
   DF_TRY(check_S(S, n, m, lds));
   if (!W) return fail(DFISHER_E_INVALID_ARG, "W is NULL");
-  if (prec != DFISHER_GRAM_FP32 && prec != DFISHER_GRAM_BF16X3)
+  if (prec != DFISHER_GRAM_FP32 && prec != DFISHER_GRAM_BF16X3 && prec != DFISHER_GRAM_MXFP8)
     return fail(DFISHER_E_INVALID_ARG, "unknown gram precision %d", prec);
   if (!(std::isfinite(lambda) && lambda >= 0.0)) return fail(DFISHER_E_INVALID_ARG, "lambda must be finite and >= 0");
+  DF_TRY(check_prec_layout(prec, S, lds));
   DeviceGuard g(ctx->device);
   hipStream_t st = as_stream(stream);
-  const dfi::GramPlan gp = dfi::gram_plan(n, m, lds, prec);
+  const dfi::GramPlan gp = dfi::gram_plan(n, m, lds, prec, rows_aligned16(S, lds));
   const dfi::RowPassPlan rp = dfi::rowpass_plan(n, m, lds);
-  Carver c;
-  float* gpart = c.take<float>(gp.part_bytes / sizeof(float));
-  double* rpart = c.take<double>(rp.part_bytes / sizeof(double));
-  double* d = c.take<double>((size_t)n);
-  DF_TRY(ensure_ws(ctx, c.off));
-  char* base = static_cast<char*>(ctx->ws);
-  c = Carver{};
-  c.base = base;
-  gpart = c.take<float>(gp.part_bytes / sizeof(float));
-  rpart = c.take<double>(rp.part_bytes / sizeof(double));
-  d = c.take<double>((size_t)n);
+  const dfi::ColPassPlan cp = dfi::colpass_plan(n, m);
+  SolveBufs B = carve(nullptr, n, m, &gp, rp, cp, false, false);
+  DF_TRY(ensure_ws(ctx, B.bytes));
+  B = carve(static_cast<char*>(ctx->ws), n, m, &gp, rp, cp, false, false);
   StageClock clk(ctx, st);
-  clk.mark(0);
-  HIP_TRY(dfi::rowpass_launch(rp, S, nullptr, nullptr, false, true, rpart, st));
-  HIP_TRY(dfi::rowpass_reduce(rp, rpart, false, true, nullptr, d, nullptr, nullptr, 0.0, st));
-  clk.mark(1);
-  HIP_TRY(dfi::gram_launch(gp, S, gpart, st));
-  clk.mark(2);
-  HIP_TRY(dfi::gram_reduce(gp, gpart, d, lambda, W, 1, st));
+  DF_TRY(gram_stage(S, nullptr, gp, rp, B, lambda, W, 1, st, &clk));
   clk.mark(3);
+  return DFISHER_OK;
+}
+
+dfisher_status dfisher_quantize_mxfp8(dfisher_ctx* ctx, const float* S, int64_t n, int64_t m, int64_t lds,
+                                      uint8_t* codes, int64_t ldq, uint8_t* scales, void* stream) {
+  DF_TRY(check_ctx(ctx));
+  DF_TRY(check_S(S, n, m, lds));
+  if (!codes || !scales) return fail(DFISHER_E_INVALID_ARG, "codes or scales is NULL");
+  if (ldq < m || ldq % 64 != 0) return fail(DFISHER_E_INVALID_ARG, "ldq must be a multiple of 64 and >= m");
+  DF_TRY(check_prec_layout(DFISHER_GRAM_MXFP8, S, lds));
+  DeviceGuard g(ctx->device);
+  hipStream_t st = as_stream(stream);
+  const dfi::RowPassPlan rp = dfi::rowpass_plan(n, m, lds);
+  DF_TRY(ensure_ws(ctx, align_up(rp.part_bytes)));
+  HIP_TRY(dfi::rowpass_launch(rp, S, nullptr, nullptr, false, true, static_cast<double*>(ctx->ws), st, codes, scales,
+                              ldq));
   return DFISHER_OK;
 }
 
@@ -436,7 +486,8 @@ dfisher_status dfisher_potrf(dfisher_ctx* ctx, double* W, int64_t n, int64_t* in
   *info = 0;
   DeviceGuard g(ctx->device);
   hipStream_t st = as_stream(stream);
-  HIP_TRY(dfi::potrf_launch(W, n, ctx->d_info, ctx->d_flag, st));
+  DF_TRY(ensure_ws(ctx, dfi::POTRF_DKK_BYTES));
+  HIP_TRY(dfi::potrf_launch(W, n, ctx->d_info, ctx->d_flag, static_cast<double*>(ctx->ws), st));
   HIP_TRY(hipMemcpyAsync(ctx->h_status, ctx->d_info, sizeof(int64_t), hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
   *info = ctx->h_status[0];
@@ -466,9 +517,18 @@ dfisher_status dfisher_trsv(dfisher_ctx* ctx, const double* L, int64_t n, int32_
   if (!L || !b || !y) return fail(DFISHER_E_INVALID_ARG, "L, b or y is NULL");
   if (n < 1) return fail(DFISHER_E_INVALID_ARG, "n = %lld < 1", (long long)n);
   if (trans != 0 && trans != 1) return fail(DFISHER_E_INVALID_ARG, "trans must be 0 or 1");
-  DF_TRY(check_trsv_n(n));
   DeviceGuard g(ctx->device);
-  HIP_TRY(dfi::trsv_launch(L, n, trans, b, y, as_stream(stream)));
+  hipStream_t st = as_stream(stream);
+  Carver c;
+  double* Dinv = c.take<double>(dfi::trsv_dinv_bytes(n) / sizeof(double));
+  double* work = c.take<double>((size_t)n);
+  DF_TRY(ensure_ws(ctx, c.off));
+  c = Carver{};
+  c.base = static_cast<char*>(ctx->ws);
+  Dinv = c.take<double>(dfi::trsv_dinv_bytes(n) / sizeof(double));
+  work = c.take<double>((size_t)n);
+  HIP_TRY(dfi::trsv_diag_inv(L, n, Dinv, st));
+  HIP_TRY(dfi::trsv_launch(L, Dinv, n, trans, b, y, work, st));
   return DFISHER_OK;
 }
 
@@ -497,10 +557,10 @@ dfisher_status dfisher_factor_create(dfisher_ctx* ctx, const float* S, int64_t n
   if (!finite_pos(lambda)) return fail(DFISHER_E_INVALID_ARG, "lambda must be finite and > 0");
   dfisher_options o;
   DF_TRY(check_opt(opt, &o));
-  DF_TRY(check_trsv_n(n));
+  DF_TRY(check_prec_layout(o.gram_prec, S, lds));
   DeviceGuard g(ctx->device);
   hipStream_t st = as_stream(stream);
-  const dfi::GramPlan gp = dfi::gram_plan(n, m, lds, o.gram_prec);
+  const dfi::GramPlan gp = dfi::gram_plan(n, m, lds, o.gram_prec, rows_aligned16(S, lds));
   const dfi::RowPassPlan rp = dfi::rowpass_plan(n, m, lds);
   const dfi::ColPassPlan cp = dfi::colpass_plan(n, m);
   SolveBufs B = carve(nullptr, n, m, &gp, rp, cp, false, false);
@@ -514,25 +574,30 @@ dfisher_status dfisher_factor_create(dfisher_ctx* ctx, const float* S, int64_t n
   f->lds = lds;
   f->lambda = lambda;
   f->opt = o;
-  if (hipMalloc(&f->L, (size_t)(n * n) * sizeof(double)) != hipSuccess) {
+  if (hipMalloc(&f->L, (size_t)(n * n) * sizeof(double)) != hipSuccess ||
+      hipMalloc(&f->Dinv, dfi::trsv_dinv_bytes(n)) != hipSuccess) {
     (void)hipGetLastError();
+    if (f->L) (void)hipFree(f->L);
     delete f;
     return fail(DFISHER_E_NO_MEMORY, "factor allocation failed");
   }
   auto cleanup = [&](dfisher_status s) {
     (void)hipFree(f->L);
+    (void)hipFree(f->Dinv);
     delete f;
     return s;
   };
-  if (dfi::rowpass_launch(rp, S, nullptr, nullptr, false, true, B.rpart, st) != hipSuccess ||
-      dfi::rowpass_reduce(rp, B.rpart, false, true, nullptr, B.d, nullptr, nullptr, 0.0, st) != hipSuccess ||
-      dfi::gram_launch(gp, S, B.gpart, st) != hipSuccess ||
-      dfi::gram_reduce(gp, B.gpart, B.d, lambda, B.W, 0, st) != hipSuccess)
-    return cleanup(fail(DFISHER_E_DEVICE, "kernel launch failed: %s", hipGetErrorString(hipGetLastError())));
+  {
+    const dfisher_status sg = gram_stage(S, nullptr, gp, rp, B, lambda, B.W, 0, st, nullptr);
+    if (sg != DFISHER_OK) return cleanup(sg);
+  }
   dfisher_info inf{};
-  dfisher_status s = factor_with_policy(ctx, B.W, f->L, n, o.shift_policy, st, &inf.shift, &inf.potrf_info, &inf.attempts);
+  dfisher_status s = factor_with_policy(ctx, B.W, f->L, B.dkk, n, o.shift_policy, gram_unit(o.gram_prec, m), st, &inf.shift, &inf.potrf_info,
+                                       &inf.attempts);
   if (info) *info = inf;
   if (s != DFISHER_OK) return cleanup(s);
+  if (dfi::trsv_diag_inv(f->L, n, f->Dinv, st) != hipSuccess)
+    return cleanup(fail(DFISHER_E_DEVICE, "kernel launch failed: %s", hipGetErrorString(hipGetLastError())));
   f->shift = inf.shift;
   *out = f;
   return DFISHER_OK;
@@ -560,7 +625,7 @@ dfisher_status dfisher_factor_solve(dfisher_factor* f, const float* V, int64_t n
     void* x = static_cast<char*>(X) + (size_t)(r * ldx) * xel;
     HIP_TRY(dfi::rowpass_launch(rp, f->S, v, nullptr, true, false, B.rpart, st));
     HIP_TRY(dfi::rowpass_reduce(rp, B.rpart, true, false, B.b, nullptr, nullptr, nullptr, 0.0, st));
-    DF_TRY(solve_y(f->S, n, m, f->lds, f->lambda, f->L, B, rp, cp, f->opt.sweeps, st));
+    DF_TRY(solve_y(f->S, n, m, f->lds, f->lambda, f->L, f->Dinv, B, rp, cp, f->opt.sweeps, st));
     HIP_TRY(dfi::colpass_launch(cp, f->S, n, m, f->lds, B.y, v, f->lambda, x, f->opt.x_fp64 ? 1 : 0, B.cpart, st));
   }
   if (info) {
@@ -585,6 +650,7 @@ dfisher_status dfisher_factor_destroy(dfisher_factor* f) {
   DeviceGuard g(f->ctx->device);
   (void)hipDeviceSynchronize();
   (void)hipFree(f->L);
+  (void)hipFree(f->Dinv);
   delete f;
   return DFISHER_OK;
 }
@@ -597,10 +663,10 @@ dfisher_status dfisher_solve(dfisher_ctx* ctx, const float* S, int64_t n, int64_
   if (!finite_pos(lambda)) return fail(DFISHER_E_INVALID_ARG, "lambda must be finite and > 0");
   dfisher_options o;
   DF_TRY(check_opt(opt, &o));
-  DF_TRY(check_trsv_n(n));
+  DF_TRY(check_prec_layout(o.gram_prec, S, lds));
   DeviceGuard g(ctx->device);
   hipStream_t st = as_stream(stream);
-  const dfi::GramPlan gp = dfi::gram_plan(n, m, lds, o.gram_prec);
+  const dfi::GramPlan gp = dfi::gram_plan(n, m, lds, o.gram_prec, rows_aligned16(S, lds));
   const dfi::RowPassPlan rp = dfi::rowpass_plan(n, m, lds);
   const dfi::ColPassPlan cp = dfi::colpass_plan(n, m);
   const bool need_t = o.sweeps > 0;
@@ -608,22 +674,17 @@ dfisher_status dfisher_solve(dfisher_ctx* ctx, const float* S, int64_t n, int64_
   DF_TRY(ensure_ws(ctx, B.bytes));
   B = carve(static_cast<char*>(ctx->ws), n, m, &gp, rp, cp, true, need_t);
   StageClock clk(ctx, st);
-  // one pass over S: b = S v and the exact diagonal |s_i|^2
-  clk.mark(0);
-  HIP_TRY(dfi::rowpass_launch(rp, S, v, nullptr, true, true, B.rpart, st));
-  HIP_TRY(dfi::rowpass_reduce(rp, B.rpart, true, true, B.b, B.d, nullptr, nullptr, 0.0, st));
-  // Algorithm 1 step 1
-  clk.mark(1);
-  HIP_TRY(dfi::gram_launch(gp, S, B.gpart, st));
-  clk.mark(2);
-  HIP_TRY(dfi::gram_reduce(gp, B.gpart, B.d, lambda, B.W, 0, st));
+  // one pass over S (b = S v, the exact diagonal |s_i|^2, the FP8 codes if used), then step 1
+  DF_TRY(gram_stage(S, v, gp, rp, B, lambda, B.W, 0, st, &clk));
   // step 2 (with the shift policy)
   clk.mark(3);
   dfisher_info inf{};
-  DF_TRY(factor_with_policy(ctx, B.W, B.L, n, o.shift_policy, st, &inf.shift, &inf.potrf_info, &inf.attempts));
+  DF_TRY(factor_with_policy(ctx, B.W, B.L, B.dkk, n, o.shift_policy, gram_unit(o.gram_prec, m), st, &inf.shift, &inf.potrf_info,
+                            &inf.attempts));
+  HIP_TRY(dfi::trsv_diag_inv(B.L, n, B.Dinv, st));
   // steps 3-4 inlined: y = W^-1 S v (+ refinement), x = (v - S^T y) / lambda
   clk.mark(4);
-  DF_TRY(solve_y(S, n, m, lds, lambda, B.L, B, rp, cp, o.sweeps, st, &clk));
+  DF_TRY(solve_y(S, n, m, lds, lambda, B.L, B.Dinv, B, rp, cp, o.sweeps, st, &clk));
   HIP_TRY(dfi::colpass_launch(cp, S, n, m, lds, B.y, v, lambda, x, o.x_fp64, B.cpart, st));
   clk.mark(7);
   inf.sweeps_done = o.sweeps;
@@ -644,10 +705,10 @@ dfisher_status dfisher_solve_batched(dfisher_ctx* ctx, const float* S, int64_t n
     if (!finite_pos(lambdas[l])) return fail(DFISHER_E_INVALID_ARG, "lambdas[%d] must be finite and > 0", l);
   dfisher_options o;
   DF_TRY(check_opt(opt, &o));
-  DF_TRY(check_trsv_n(n));
+  DF_TRY(check_prec_layout(o.gram_prec, S, lds));
   DeviceGuard g(ctx->device);
   hipStream_t st = as_stream(stream);
-  const dfi::GramPlan gp = dfi::gram_plan(n, m, lds, o.gram_prec);
+  const dfi::GramPlan gp = dfi::gram_plan(n, m, lds, o.gram_prec, rows_aligned16(S, lds));
   const dfi::RowPassPlan rp = dfi::rowpass_plan(n, m, lds);
   const dfi::ColPassPlan cp = dfi::colpass_plan(n, m);
   const bool need_t = o.sweeps > 0;
@@ -665,10 +726,7 @@ dfisher_status dfisher_solve_batched(dfisher_ctx* ctx, const float* S, int64_t n
   G = extra.take<double>((size_t)(n * n));
   Bs = extra.take<double>((size_t)(n * nrhs));
   // shared Gram G = S S^T (exact diagonal, no lambda)
-  HIP_TRY(dfi::rowpass_launch(rp, S, nullptr, nullptr, false, true, B.rpart, st));
-  HIP_TRY(dfi::rowpass_reduce(rp, B.rpart, false, true, nullptr, B.d, nullptr, nullptr, 0.0, st));
-  HIP_TRY(dfi::gram_launch(gp, S, B.gpart, st));
-  HIP_TRY(dfi::gram_reduce(gp, B.gpart, B.d, 0.0, G, 0, st));
+  DF_TRY(gram_stage(S, nullptr, gp, rp, B, 0.0, G, 0, st, nullptr));
   // b_r = S v_r for every right-hand side, shared by all lambdas
   for (int32_t r = 0; r < nrhs; ++r) {
     HIP_TRY(dfi::rowpass_launch(rp, S, V + (int64_t)r * ldv, nullptr, true, false, B.rpart, st));
@@ -678,13 +736,15 @@ dfisher_status dfisher_solve_batched(dfisher_ctx* ctx, const float* S, int64_t n
   dfisher_status worst = DFISHER_OK;
   for (int32_t l = 0; l < nlam; ++l) {
     const double lam = lambdas[l];
-    HIP_TRY(dfi::shift_copy(G, B.W, n, lam, st));
+    HIP_TRY(dfi::add_diag_copy(G, B.W, n, lam, st));
     dfisher_info inf{};
-    dfisher_status s = factor_with_policy(ctx, B.W, B.L, n, o.shift_policy, st, &inf.shift, &inf.potrf_info, &inf.attempts);
+    dfisher_status s = factor_with_policy(ctx, B.W, B.L, B.dkk, n, o.shift_policy, gram_unit(o.gram_prec, m), st, &inf.shift, &inf.potrf_info,
+                                         &inf.attempts);
     if (s == DFISHER_OK) {
+      HIP_TRY(dfi::trsv_diag_inv(B.L, n, B.Dinv, st));
       for (int32_t r = 0; r < nrhs; ++r) {
         HIP_TRY(hipMemcpyAsync(B.b, Bs + (int64_t)r * n, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, st));
-        DF_TRY(solve_y(S, n, m, lds, lam, B.L, B, rp, cp, o.sweeps, st));
+        DF_TRY(solve_y(S, n, m, lds, lam, B.L, B.Dinv, B, rp, cp, o.sweeps, st));
         void* x = static_cast<char*>(X) + (size_t)(((int64_t)l * nrhs + r) * ldx) * xel;
         HIP_TRY(dfi::colpass_launch(cp, S, n, m, lds, B.y, V + (int64_t)r * ldv, lam, x, o.x_fp64, B.cpart, st));
       }
@@ -713,7 +773,6 @@ dfisher_status dfisher_solve_uneven(dfisher_ctx* ctx, int32_t nprob, const float
     if (s != DFISHER_OK) return fail(s, "problem %d: %s", p, g_last_error.c_str());
     if (!v[p] || !x[p]) return fail(DFISHER_E_INVALID_ARG, "problem %d: v or x is NULL", p);
     if (!finite_pos(lambda[p])) return fail(DFISHER_E_INVALID_ARG, "problem %d: lambda must be finite and > 0", p);
-    DF_TRY(check_trsv_n(n[p]));
   }
   dfisher_status worst = DFISHER_OK;
   for (int32_t p = 0; p < nprob; ++p) {

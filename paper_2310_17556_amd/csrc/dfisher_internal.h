@@ -18,14 +18,28 @@ struct GramPlan {
   int64_t ntri;       // lower-triangle tiles = ntile (ntile + 1) / 2
   int64_t nslice;     // k-slices (split-K factor)
   int64_t kslice;     // columns per slice (multiple of GRAM_KSTEP)
-  int prec;           // dfisher_gram_prec
+  int prec;           // dfisher_gram_prec (0 FP32, 1 split-BF16, 2 scaled FP8)
+  int64_t ldh;        // split-BF16 from pre-split planes: their row stride (0: split inside the tile kernel)
   size_t part_bytes;  // FP32 partial tiles: nslice * ntri * TILE * TILE * 4
 };
 
-GramPlan gram_plan(int64_t n, int64_t m, int64_t lds, int prec);
+// aligned16: rows of S start on 16-byte boundaries (lds % 4 == 0 and S 16-byte aligned). For
+// split-BF16 on aligned rows the plan uses planes hi/lo written by the row pass (ldh > 0).
+GramPlan gram_plan(int64_t n, int64_t m, int64_t lds, int prec, bool aligned16);
 hipError_t gram_launch(const GramPlan& p, const float* S, float* part, hipStream_t st);
+// Row stride (bf16 elements) of the split-BF16 planes for m columns.
+inline int64_t split_ldh(int64_t m) { return (m + 63) / 64 * 64; }
+// Split-BF16 Gram from the planes hi = bf16(S), lo = bf16(S - hi) (n x ldh each, p.ldh > 0).
+hipError_t gram_launch_split(const GramPlan& p, const uint16_t* hi, const uint16_t* lo, float* part, hipStream_t st);
+// Scaled-FP8 Gram from the row pass's codes (n x ldq bytes) and E8M0 scales (n x ldq/32 bytes).
+hipError_t gram_launch_fp8(const GramPlan& p, const uint8_t* q, const uint8_t* sc, int64_t ldq, float* part,
+                           hipStream_t st);
+// Row stride of the FP8 codes for m columns (a multiple of 64).
+inline int64_t fp8_ldq(int64_t m) { return (m + 127) / 128 * 128; }   // scale rows: whole 4-byte words
 // W = sum of slices (lower triangle; also upper if mirror), diagonal = d + lambda (d = FP64 row norms).
-hipError_t gram_reduce(const GramPlan& p, const float* part, const double* d, double lambda,
+// S is needed for the products of the last few columns (m mod 4, 8 or 16), which the tile kernels
+// that stream whole 16-byte chunks leave out.
+hipError_t gram_reduce(const GramPlan& p, const float* S, const float* part, const double* d, double lambda,
                        double* W, int mirror, hipStream_t st);
 
 // ----------------------------------------------------------------------------- streaming GEMVs
@@ -39,8 +53,17 @@ struct RowPassPlan {
   size_t part_bytes;  // 2 * nchunk * n * 8
 };
 RowPassPlan rowpass_plan(int64_t n, int64_t m, int64_t lds);
+// With q != nullptr the pass also writes the scaled-FP8 copy of S (codes n x ldq bytes, E8M0
+// scale bytes n x ldq/32; ldq a multiple of 64, >= m; needs 16-byte aligned rows and want_d;
+// the scaled-FP8 Gram kernel further needs ldq a multiple of 128, see fp8_ldq).
 hipError_t rowpass_launch(const RowPassPlan& p, const float* S, const float* v, const double* vd,
-                          bool want_b, bool want_d, double* part, hipStream_t st);
+                          bool want_b, bool want_d, double* part, hipStream_t st, uint8_t* q = nullptr,
+                          uint8_t* sc = nullptr, int64_t ldq = 0);
+// Row pass that also writes the split-BF16 planes of S: hi = bf16_rne(S), lo = bf16_rne(S - hi),
+// n x ldh each (ldh a multiple of 64, >= m; entries k >= m are zero). Needs 16-byte aligned rows;
+// always computes d, and b when v != nullptr.
+hipError_t rowpass_launch_split(const RowPassPlan& p, const float* S, const float* v, double* part, uint16_t* hi,
+                                uint16_t* lo, int64_t ldh, hipStream_t st);
 // Reduce: b_i = sum_c part_b[c][i]; when r0 != nullptr: b_i = r0_i - lam * y_i - sum_c part_b[c][i]
 hipError_t rowpass_reduce(const RowPassPlan& p, const double* part, bool want_b, bool want_d, double* b,
                           double* d, const double* r0, const double* y, double lam, hipStream_t st);
@@ -60,17 +83,24 @@ hipError_t colpass_launch(const ColPassPlan& p, const float* S, int64_t n, int64
 
 // ----------------------------------------------------------------------------- Cholesky
 // In-place blocked FP64 Cholesky (row-major, lower). info_dev: device int64, 0 or 1-based
-// index of the first bad pivot. flag_dev: device int32 scratch (stop flag).
-hipError_t potrf_launch(double* A, int64_t n, int64_t* info_dev, int32_t* flag_dev, hipStream_t st);
+// index of the first bad pivot. flag_dev: device int32 scratch (stop flag). dkk: device
+// scratch of 64 x 64 doubles (the current diagonal block's inverse).
+constexpr size_t POTRF_DKK_BYTES = 64 * 64 * sizeof(double);
+hipError_t potrf_launch(double* A, int64_t n, int64_t* info_dev, int32_t* flag_dev, double* dkk, hipStream_t st);
 
 // ----------------------------------------------------------------------------- triangular solves
-hipError_t trsv_launch(const double* L, int64_t n, int trans, const double* b, double* y, hipStream_t st);
-size_t trsv_lds_bytes(int64_t n, int trans);
-hipError_t trsv_prepare();  // once per device, before the first launch
+// Inverses of the 64 x 64 diagonal blocks of L (Dinv: trsv_dinv_bytes(n)), computed once per factor.
+size_t trsv_dinv_bytes(int64_t n);
+hipError_t trsv_diag_inv(const double* L, int64_t n, double* Dinv, hipStream_t st);
+// y = L^-1 b (trans 0) or L^-T b (trans 1); work: n doubles, not aliasing b or y; b may alias y.
+hipError_t trsv_launch(const double* L, const double* Dinv, int64_t n, int trans, const double* b, double* y,
+                       double* work, hipStream_t st);
 
 // ----------------------------------------------------------------------------- small helpers
-// dst = src + tau * I (n x n, row-major), copies the full matrix.
-hipError_t shift_copy(const double* src, double* dst, int64_t n, double tau, hipStream_t st);
+// dst = src + scale * dmax[0] * I (n x n, row-major; dmax a device scalar, unread if scale == 0).
+hipError_t shift_copy(const double* src, double* dst, int64_t n, double scale, const double* dmax, hipStream_t st);
+// dst = src + lam * I
+hipError_t add_diag_copy(const double* src, double* dst, int64_t n, double lam, hipStream_t st);
 // y += d (length n)
 hipError_t axpy_inplace(double* y, const double* d, int64_t n, hipStream_t st);
 // max_i W_ii

@@ -20,9 +20,10 @@ namespace dfi {
 namespace {
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 
 constexpr int RP_WAVES = 4;     // waves per workgroup (each its own row group)
-constexpr int RP_RPW = 16;      // rows per wave
+constexpr int RP_RPW = 8;       // rows per wave (few enough registers for 4 waves per SIMD)
 constexpr int RP_U = 8;         // float4 loads per lane per row and sub-chunk
 constexpr int RP_SUB = 64 * 4 * RP_U;  // 2048 columns per sub-chunk
 
@@ -32,19 +33,46 @@ __device__ __forceinline__ double wave_sum(double x) {
   return x;
 }
 
+// Block scale exponent of the scaled-FP8 form: the smallest e with amax <= 448 * 2^e, clamped to
+// [-127, 127] (e = -127 for amax == 0). With amax = f 2^E, 1 <= f < 2: amax <= 1.75 * 2^(8+e)
+// holds for e = E - 8 when f <= 1.75, else e = E - 7. Exact, from the FP32 bit pattern.
+__device__ __forceinline__ int mx_scale_exp(float amax) {
+  const uint32_t u = __float_as_uint(amax);
+  const int ebits = (int)((u >> 23) & 0xFF);
+  if (ebits == 0) return -127;                       // zero or FP32-subnormal block maximum
+  const int E = ebits - 127;
+  const uint32_t mant = u & 0x7FFFFF;
+  int e = E - 8 + ((mant > 0x600000u) ? 1 : 0);       // 1.75 = 1 + 0x600000 / 2^23
+  return e < -127 ? -127 : (e > 127 ? 127 : e);
+}
+
+// 2^-e as a float, for e in [-127, 127] (2^127 is the largest; 2^-127 is an FP32 subnormal).
+__device__ __forceinline__ float pow2_neg(int e) { return ldexpf(1.0f, -e); }
+
+// Four consecutive vector entries; an FP32 vector stays FP32 (widened where it is used).
 template <typename VT>
-__device__ __forceinline__ void load_vec4(const VT* __restrict__ v, int64_t col, int64_t m, bool vec, double (&out)[4]) {
-  if (vec && col + 4 <= m) {
-    if constexpr (sizeof(VT) == 4) {
-      const f32x4 t = *reinterpret_cast<const f32x4*>(v + col);
-      out[0] = t[0]; out[1] = t[1]; out[2] = t[2]; out[3] = t[3];
+struct Vec4;
+template <>
+struct Vec4<float> {
+  f32x4 x;
+};
+template <>
+struct Vec4<double> {
+  double x[4];
+};
+
+template <typename VT>
+__device__ __forceinline__ void load_vec4(const VT* __restrict__ v, int64_t col, int64_t m, bool vec, Vec4<VT>& out) {
+  if constexpr (sizeof(VT) == 4) {
+    if (vec && col + 4 <= m) {
+      out.x = *reinterpret_cast<const f32x4*>(v + col);
     } else {
 #pragma unroll
-      for (int e = 0; e < 4; ++e) out[e] = v[col + e];
+      for (int e = 0; e < 4; ++e) out.x[e] = (col + e < m) ? v[col + e] : 0.f;
     }
   } else {
 #pragma unroll
-    for (int e = 0; e < 4; ++e) out[e] = (col + e < m) ? (double)v[col + e] : 0.0;
+    for (int e = 0; e < 4; ++e) out.x[e] = (col + e < m) ? v[col + e] : 0.0;
   }
 }
 
@@ -59,10 +87,18 @@ __device__ __forceinline__ void load_s4(const float* __restrict__ p, int64_t col
 
 // Grid: x = row blocks of RP_WAVES * RP_RPW rows, y = column groups of `cg` columns (multiple
 // of RP_SUB). part layout: part_b[g * n + i], part_d[(ngroups + g) * n + i].
-template <typename VT, bool WANT_B, bool WANT_D>
+// QM selects an extra output, written for every column k < ldq (zero input beyond m); both need the
+// vectorised path:
+//   QM = 1: the scaled-FP8 form of S: codes q[i * ldq + k] (E4M3, round to nearest even) and scale
+//           exponents sc[i * (ldq / 32) + k / 32] (E8M0 byte e + 127) per 32-column block; a block
+//           is 8 consecutive lanes of one 16-byte load.
+//   QM = 2: the split-BF16 planes hi[i * ldq + k] = bf16_rne(S_ik), lo[...] = bf16_rne(S_ik - hi)
+//           (S_ik - hi is exact in FP32); hi and lo are passed in q and sc as bf16 arrays.
+template <typename VT, bool WANT_B, bool WANT_D, int QM>
 __global__ void __launch_bounds__(64 * RP_WAVES)
 rowpass_kernel(const float* __restrict__ S, int64_t n, int64_t m, int64_t lds, const VT* __restrict__ v,
-               int64_t cg, int64_t ngroups, double* __restrict__ part, int vec) {
+               int64_t cg, int64_t ngroups, double* __restrict__ part, int vec, uint8_t* __restrict__ q,
+               uint8_t* __restrict__ sc, int64_t ldq) {
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int64_t row0 = ((int64_t)blockIdx.x * RP_WAVES + wave) * RP_RPW;
@@ -77,10 +113,10 @@ rowpass_kernel(const float* __restrict__ S, int64_t n, int64_t m, int64_t lds, c
   for (int r = 0; r < RP_RPW; ++r) { ab[r] = 0.0; ad[r] = 0.0; }
 
   for (int64_t cs = c0; cs < c1; cs += RP_SUB) {
-    double vv[RP_U][4];
+    Vec4<VT> vv[RP_U];
     if constexpr (WANT_B) {
 #pragma unroll
-      for (int u = 0; u < RP_U; ++u) load_vec4<VT>(v, cs + 256 * u + 4 * lane, c1, vec, vv[u]);
+      for (int u = 0; u < RP_U; ++u) load_vec4<VT>(v, cs + 256 * u + 4 * lane, c1, (vec & 2) != 0, vv[u]);
     }
 #pragma unroll
     for (int r = 0; r < RP_RPW; ++r) {
@@ -90,16 +126,53 @@ rowpass_kernel(const float* __restrict__ S, int64_t n, int64_t m, int64_t lds, c
 #pragma unroll
         for (int u = 0; u < RP_U; ++u) {
           const int64_t col = cs + 256 * u + 4 * lane;
-          load_s4(rowp + col, col, c1, vec, sv[u]);
+          load_s4(rowp + col, col, c1, (vec & 1) != 0, sv[u]);
         }
 #pragma unroll
         for (int u = 0; u < RP_U; ++u)
 #pragma unroll
           for (int e = 0; e < 4; ++e) {
             const double s = (double)sv[u][e];
-            if constexpr (WANT_B) ab[r] = fma(s, vv[u][e], ab[r]);
+            if constexpr (WANT_B) ab[r] = fma(s, (double)vv[u].x[e], ab[r]);
             if constexpr (WANT_D) ad[r] = fma(s, s, ad[r]);
           }
+        if constexpr (QM == 2) {
+#pragma unroll
+          for (int u = 0; u < RP_U; ++u) {
+            const int64_t col = cs + 256 * u + 4 * lane;
+            bf16x4 h, l;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+              const __bf16 hb = (__bf16)sv[u][e];        // round to nearest even
+              h[e] = hb;
+              l[e] = (__bf16)(sv[u][e] - (float)hb);
+            }
+            if (col < ldq) {
+              *reinterpret_cast<bf16x4*>(reinterpret_cast<__bf16*>(q) + (row0 + r) * ldq + col) = h;
+              *reinterpret_cast<bf16x4*>(reinterpret_cast<__bf16*>(sc) + (row0 + r) * ldq + col) = l;
+            }
+          }
+        }
+        if constexpr (QM == 1) {
+#pragma unroll
+          for (int u = 0; u < RP_U; ++u) {
+            const int64_t col = cs + 256 * u + 4 * lane;
+            float amax = fmaxf(fmaxf(fabsf(sv[u][0]), fabsf(sv[u][1])), fmaxf(fabsf(sv[u][2]), fabsf(sv[u][3])));
+            amax = fmaxf(amax, __shfl_xor(amax, 1, 64));
+            amax = fmaxf(amax, __shfl_xor(amax, 2, 64));
+            amax = fmaxf(amax, __shfl_xor(amax, 4, 64));
+            const int ex = mx_scale_exp(amax);
+            const float inv = pow2_neg(ex);
+            // |sv * inv| <= 448 by the choice of ex; the conversion rounds to nearest even
+            int packed = __builtin_amdgcn_cvt_pk_fp8_f32(sv[u][0] * inv, sv[u][1] * inv, 0, false);
+            packed = __builtin_amdgcn_cvt_pk_fp8_f32(sv[u][2] * inv, sv[u][3] * inv, packed, true);
+            if (col < ldq) {
+              uint8_t* rowq = q + (row0 + r) * ldq;
+              *reinterpret_cast<int*>(rowq + col) = packed;
+              if ((lane & 7) == 0) sc[(row0 + r) * (ldq >> 5) + (col >> 5)] = (uint8_t)(ex + 127);
+            }
+          }
+        }
       }
     }
   }
@@ -253,24 +326,53 @@ RowPassPlan rowpass_plan(int64_t n, int64_t m, int64_t lds) {
 }
 
 hipError_t rowpass_launch(const RowPassPlan& p, const float* S, const float* v, const double* vd, bool want_b,
-                          bool want_d, double* part, hipStream_t st) {
-  const bool vec = ((p.lds & 3) == 0) && aligned16(S) && (v ? aligned16(v) : true) && (vd ? aligned16(vd) : true);
+                          bool want_d, double* part, hipStream_t st, uint8_t* q, uint8_t* sc, int64_t ldq) {
+  // bit 0: rows of S are 16-byte aligned; bit 1: the vector is 16-byte aligned as well
+  const bool vec = ((p.lds & 3) == 0) && aligned16(S);
+  const bool vecv = vec && (v ? aligned16(v) : true) && (vd ? aligned16(vd) : true);
   const dim3 grid((unsigned)((p.n + RP_WAVES * RP_RPW - 1) / (RP_WAVES * RP_RPW)), (unsigned)p.nchunk);
   const dim3 block(64 * RP_WAVES);
-  const int iv = vec ? 1 : 0;
+  const int iv = (vec ? 1 : 0) | (vecv ? 2 : 0);
+  if (q) {
+    // fused quantisation: b = S v (optional), row norms, and the scaled-FP8 copy of S
+    if (!vec || !want_d || vd || (ldq & 63) != 0) return hipErrorInvalidValue;
+    if (want_b)
+      hipLaunchKernelGGL((rowpass_kernel<float, true, true, 1>), grid, block, 0, st, S, p.n, p.m, p.lds, v, p.chunk, p.nchunk, part, iv, q, sc, ldq);
+    else
+      hipLaunchKernelGGL((rowpass_kernel<float, false, true, 1>), grid, block, 0, st, S, p.n, p.m, p.lds, (const float*)nullptr, p.chunk, p.nchunk, part, iv, q, sc, ldq);
+    return hipGetLastError();
+  }
+  uint8_t* nq = nullptr;
   if (want_b && vd) {
     if (want_d)
-      hipLaunchKernelGGL((rowpass_kernel<double, true, true>), grid, block, 0, st, S, p.n, p.m, p.lds, vd, p.chunk, p.nchunk, part, iv);
+      hipLaunchKernelGGL((rowpass_kernel<double, true, true, 0>), grid, block, 0, st, S, p.n, p.m, p.lds, vd, p.chunk, p.nchunk, part, iv, nq, nq, ldq);
     else
-      hipLaunchKernelGGL((rowpass_kernel<double, true, false>), grid, block, 0, st, S, p.n, p.m, p.lds, vd, p.chunk, p.nchunk, part, iv);
+      hipLaunchKernelGGL((rowpass_kernel<double, true, false, 0>), grid, block, 0, st, S, p.n, p.m, p.lds, vd, p.chunk, p.nchunk, part, iv, nq, nq, ldq);
   } else if (want_b) {
     if (want_d)
-      hipLaunchKernelGGL((rowpass_kernel<float, true, true>), grid, block, 0, st, S, p.n, p.m, p.lds, v, p.chunk, p.nchunk, part, iv);
+      hipLaunchKernelGGL((rowpass_kernel<float, true, true, 0>), grid, block, 0, st, S, p.n, p.m, p.lds, v, p.chunk, p.nchunk, part, iv, nq, nq, ldq);
     else
-      hipLaunchKernelGGL((rowpass_kernel<float, true, false>), grid, block, 0, st, S, p.n, p.m, p.lds, v, p.chunk, p.nchunk, part, iv);
+      hipLaunchKernelGGL((rowpass_kernel<float, true, false, 0>), grid, block, 0, st, S, p.n, p.m, p.lds, v, p.chunk, p.nchunk, part, iv, nq, nq, ldq);
   } else if (want_d) {
-    hipLaunchKernelGGL((rowpass_kernel<float, false, true>), grid, block, 0, st, S, p.n, p.m, p.lds, (const float*)nullptr, p.chunk, p.nchunk, part, iv);
+    hipLaunchKernelGGL((rowpass_kernel<float, false, true, 0>), grid, block, 0, st, S, p.n, p.m, p.lds, (const float*)nullptr, p.chunk, p.nchunk, part, iv, nq, nq, ldq);
   }
+  return hipGetLastError();
+}
+
+hipError_t rowpass_launch_split(const RowPassPlan& p, const float* S, const float* v, double* part, uint16_t* hi,
+                                uint16_t* lo, int64_t ldh, hipStream_t st) {
+  const bool vec = ((p.lds & 3) == 0) && aligned16(S);
+  const bool vecv = vec && (v ? aligned16(v) : true);
+  if (!vec || (ldh & 63) != 0 || ldh < p.m) return hipErrorInvalidValue;
+  const dim3 grid((unsigned)((p.n + RP_WAVES * RP_RPW - 1) / (RP_WAVES * RP_RPW)), (unsigned)p.nchunk);
+  const dim3 block(64 * RP_WAVES);
+  const int iv = 1 | (vecv ? 2 : 0);
+  uint8_t* qh = reinterpret_cast<uint8_t*>(hi);
+  uint8_t* ql = reinterpret_cast<uint8_t*>(lo);
+  if (v)
+    hipLaunchKernelGGL((rowpass_kernel<float, true, true, 2>), grid, block, 0, st, S, p.n, p.m, p.lds, v, p.chunk, p.nchunk, part, iv, qh, ql, ldh);
+  else
+    hipLaunchKernelGGL((rowpass_kernel<float, false, true, 2>), grid, block, 0, st, S, p.n, p.m, p.lds, (const float*)nullptr, p.chunk, p.nchunk, part, iv, qh, ql, ldh);
   return hipGetLastError();
 }
 

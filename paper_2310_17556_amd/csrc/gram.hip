@@ -128,6 +128,14 @@ __device__ __forceinline__ void store_bf16(__bf16* hi, __bf16* lo, const f32x4 (
   }
 }
 
+// Flip the sign bits of eight bf16 values when mask = 0x80008000 (identity for mask = 0).
+__device__ __forceinline__ bf16x8 flip_sign(bf16x8 v, uint32_t mask) {
+  typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+  u32x4 u = __builtin_bit_cast(u32x4, v);
+  u ^= mask;
+  return __builtin_bit_cast(bf16x8, u);
+}
+
 template <int PREC, bool VEC>
 __global__ void __launch_bounds__(NTHR, 1)
 gram_kernel(const float* __restrict__ S, int64_t n, int64_t lds, int64_t m, int64_t ntri,
@@ -141,6 +149,9 @@ gram_kernel(const float* __restrict__ S, int64_t n, int64_t lds, int64_t m, int6
   const int64_t q = local / ntri;
   const int64_t tile = local - q * ntri;
   const int64_t slice = xcd * (nslice >> 3) + q;
+  // odd slices negate A (see the alternating slice sign note of gram_kernel_v2)
+  const float sgn = (slice & 1) ? -1.f : 1.f;
+  const uint32_t bflip = (slice & 1) ? 0x80008000u : 0u;
 
   int64_t ti, tj;
   tri_index(tile, ti, tj);
@@ -213,7 +224,7 @@ gram_kernel(const float* __restrict__ S, int64_t n, int64_t lds, int64_t m, int6
           for (int i = 0; i < IM; ++i)
 #pragma unroll
             for (int j = 0; j < IN; ++j)
-              acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(fa[i][e >> 2][e & 3], fb[j][e >> 2][e & 3],
+              acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(sgn * fa[i][e >> 2][e & 3], fb[j][e >> 2][e & 3],
                                                                acc[i][j], 0, 0, 0);
       }
     } else {
@@ -227,8 +238,8 @@ gram_kernel(const float* __restrict__ S, int64_t n, int64_t lds, int64_t m, int6
 #pragma unroll
         for (int i = 0; i < IM; ++i) {
           const int oa = (wr * BMW + i * 32 + l32) * BF_STRIDE + half * 16 + kk;
-          ah[i] = *reinterpret_cast<const bf16x8*>(ph + oa);
-          al[i] = *reinterpret_cast<const bf16x8*>(pl + oa);
+          ah[i] = flip_sign(*reinterpret_cast<const bf16x8*>(ph + oa), bflip);
+          al[i] = flip_sign(*reinterpret_cast<const bf16x8*>(pl + oa), bflip);
         }
 #pragma unroll
         for (int j = 0; j < IN; ++j) {
@@ -259,15 +270,594 @@ gram_kernel(const float* __restrict__ S, int64_t n, int64_t lds, int64_t m, int6
       for (int r = 0; r < 16; ++r) {
         const int row = wr * BMW + i * 32 + 8 * (r >> 2) + 4 * half + (r & 3);
         const int col = wc * BNW + j * 32 + l32;
-        out[row * T + col] = active ? acc[i][j][r] : 0.f;
+        out[row * T + col] = active ? sgn * acc[i][j][r] : 0.f;
       }
 }
 
-// W_ij = sum over slices of the partial tiles (FP64, slice order) for i > j; W_ii = d_i + lambda.
+// ---------------------------------------------------------------------------------------------
+// Gram kernel v2 (16-byte aligned rows): asynchronous direct-to-LDS loads into a two-stage ring.
+//
+//   * Each k-step stages the FP32 columns [k, k+32) of the two 256-row panels with
+//     global_load_lds_dwordx4: every wave instruction moves 8 rows x 128 B straight from global
+//     memory to LDS (no register staging). Row r's eight 16-byte chunks are stored XOR-swizzled
+//     (LDS chunk p holds column chunk p ^ (r & 7)) so that fragment reads of 8 consecutive rows
+//     hit distinct banks.
+//   * Two LDS stages: the loads for step s+1 are in flight while step s is multiplied; one
+//     barrier per step.
+//   * 4 waves in a 2 x 2 layout, each owning a 128 x 128 sub-tile (4 x 4 blocks of 32 x 32
+//     accumulators). Split-BF16 fragments are formed when a wave reads its FP32 fragment from
+//     LDS: hi = bf16_rne(a), lo = bf16_rne(a - hi).
+//   * Rows beyond n load a valid row (their products only reach discarded outputs). The kernel
+//     covers columns [0, m4) with m4 = m rounded down to a multiple of 4; chunks past a slice end
+//     load zeros, and the FP64 reduction adds the products of the last m - m4 (< 4) columns.
+//   * Alternating slice sign: on odd k-slices the A operand is negated and the stored partial
+//     tile negated back. The bf16 matrix-core accumulation shows a small sign-independent bias
+//     (low-order bits of the aligned addends are dropped toward minus infinity); it is the same
+//     for +A and -A, so it cancels between even and odd slices instead of adding up coherently
+//     over all entries (which would shift W along directions where many entries add, such as
+//     the all-ones direction of a column-centered S).
+namespace v2 {
+
+constexpr int NW = 4;
+constexpr int NT = 64 * NW;
+constexpr int WT = 128;                 // wave sub-tile edge
+constexpr int NB = WT / 32;             // 4 blocks per edge
+constexpr int PANEL = T * KS;           // floats per panel per stage (32 KB)
+
+typedef __attribute__((address_space(3))) void lds_void;
+
+// Source of the zero chunks loaded past the end of a k-slice.
+__device__ __align__(16) float g_zero_chunk[4] = {0.f, 0.f, 0.f, 0.f};
+
+struct Stage {
+  float a[PANEL];
+  float b[PANEL];
+};
+
+// Issue the direct-to-LDS loads of one panel for one k-step. Wave w moves row groups
+// g = w, w + 4, ..., each of 8 rows.
+__device__ __forceinline__ void issue_panel(const float* __restrict__ S, int64_t lds, int64_t n, int64_t row0,
+                                            int64_t kcol, int64_t kend, float* panel) {
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int rsub = lane >> 3;        // row inside the 8-row group
+  const int p = lane & 7;            // LDS chunk position
+#pragma unroll
+  for (int i = 0; i < T / 8 / NW; ++i) {
+    const int g = wave + NW * i;
+    const int r = 8 * g + rsub;
+    const int c = p ^ (r & 7);       // column chunk this lane fetches
+    int64_t R = row0 + r;
+    if (R >= n) R = n - 1;
+    const int64_t col = kcol + 4 * c;
+    // kend is a multiple of 4 here: a chunk is either wholly inside the slice or wholly past it
+    const float* src = (col < kend) ? S + R * lds + col : g_zero_chunk;
+    __builtin_amdgcn_global_load_lds((const void*)src, (lds_void*)(panel + 8 * g * KS), 16, 0, 0);
+  }
+}
+
+// Read the 8 FP32 values of row r, step columns [c0, c0 + 8) (c0 a multiple of 8) from a
+// swizzled panel.
+__device__ __forceinline__ void read8(const float* panel, int r, int c0, float (&v)[8]) {
+  const int q0 = (c0 >> 2) ^ (r & 7);
+  const int q1 = ((c0 >> 2) + 1) ^ (r & 7);
+  const f32x4 x0 = *reinterpret_cast<const f32x4*>(panel + r * KS + 4 * q0);
+  const f32x4 x1 = *reinterpret_cast<const f32x4*>(panel + r * KS + 4 * q1);
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    v[e] = x0[e];
+    v[4 + e] = x1[e];
+  }
+}
+
+__device__ __forceinline__ void split8(const float (&v)[8], float sgn, bf16x8& hi, bf16x8& lo) {
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    const float a = v[e] * sgn;
+    const __bf16 h = (__bf16)a;
+    hi[e] = h;
+    lo[e] = (__bf16)(a - (float)h);
+  }
+}
+
+// One k-step of the wave's 128 x 128 sub-tile from the current LDS stage.
+template <int PREC>
+__device__ __forceinline__ void step_compute(const float* pa, const float* pb, int ra0, int rb0, int half, float sgn,
+                                             f32x16 (&acc)[NB][NB]) {
+  if constexpr (PREC == 1) {
+#pragma unroll
+    for (int kk = 0; kk < 16; kk += 8) {
+      // B fragments stay in registers for the substep; A fragments stream through, the next one
+      // read while the current one's products issue.
+      bf16x8 bh[NB], bl[NB];
+#pragma unroll
+      for (int j = 0; j < NB; ++j) {
+        float v[8];
+        read8(pb, rb0 + j * 32, half * 16 + kk, v);
+        split8(v, 1.f, bh[j], bl[j]);
+      }
+      float va[8];
+      read8(pa, ra0, half * 16 + kk, va);
+#pragma unroll
+      for (int i = 0; i < NB; ++i) {
+        bf16x8 ah, al;
+        split8(va, sgn, ah, al);
+        if (i + 1 < NB) read8(pa, ra0 + (i + 1) * 32, half * 16 + kk, va);
+#pragma unroll
+        for (int j = 0; j < NB; ++j) {
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh[j], acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl[j], acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh[j], acc[i][j], 0, 0, 0);
+        }
+      }
+    }
+  } else {
+#pragma unroll
+    for (int kk = 0; kk < 16; kk += 8) {
+      float fb[NB][8];
+#pragma unroll
+      for (int j = 0; j < NB; ++j) read8(pb, rb0 + j * 32, half * 16 + kk, fb[j]);
+      float fa[8];
+      read8(pa, ra0, half * 16 + kk, fa);
+#pragma unroll
+      for (int i = 0; i < NB; ++i) {
+        float a[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) a[e] = fa[e] * sgn;
+        if (i + 1 < NB) read8(pa, ra0 + (i + 1) * 32, half * 16 + kk, fa);
+#pragma unroll
+        for (int e = 0; e < 8; ++e)
+#pragma unroll
+          for (int j = 0; j < NB; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[e], fb[j][e], acc[i][j], 0, 0, 0);
+      }
+    }
+  }
+}
+
+template <int PREC>
+__global__ void __launch_bounds__(NT, 1)
+gram_kernel_v2(const float* __restrict__ S, int64_t n, int64_t lds, int64_t m, int64_t ntri, int64_t nslice,
+               int64_t kslice, float* __restrict__ part) {
+  __shared__ Stage st0;
+  __shared__ Stage st1;
+
+  const int64_t w = blockIdx.x;
+  const int64_t xcd = w & 7;
+  const int64_t local = w >> 3;
+  const int64_t q = local / ntri;
+  const int64_t tile = local - q * ntri;
+  const int64_t slice = xcd * (nslice >> 3) + q;
+  const float sgn = (slice & 1) ? -1.f : 1.f;
+
+  int64_t ti, tj;
+  tri_index(tile, ti, tj);
+  const bool diag = (ti == tj);
+  const int64_t rowA = ti * T, rowB = tj * T;
+  const int64_t k0 = slice * kslice;
+  const int64_t kend = min(m & ~(int64_t)3, k0 + kslice);   // columns [m4, m) go to the reduction
+  const int64_t nsteps = (kend > k0) ? (kend - k0 + KS - 1) / KS : 0;
+
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int wr = wave >> 1, wc = wave & 1;
+  const int half = lane >> 5;
+  const int l32 = lane & 31;
+  const bool active = !(diag && wr == 0 && wc == 1);
+
+  f32x16 acc[NB][NB];
+#pragma unroll
+  for (int i = 0; i < NB; ++i)
+#pragma unroll
+    for (int j = 0; j < NB; ++j)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) acc[i][j][e] = 0.f;
+
+  if (nsteps > 0) {
+    issue_panel(S, lds, n, rowA, k0, kend, st0.a);
+    if (!diag) issue_panel(S, lds, n, rowB, k0, kend, st0.b);
+  }
+  for (int64_t s = 0; s < nsteps; ++s) {
+    __builtin_amdgcn_s_waitcnt(0);  // this wave's loads for step s have landed
+    __syncthreads();                // ... and every wave's; stage (s+1)&1 is free again
+    const int64_t kc = k0 + s * KS;
+    if (s + 1 < nsteps) {
+      Stage& nx = ((s + 1) & 1) ? st1 : st0;
+      issue_panel(S, lds, n, rowA, kc + KS, kend, nx.a);
+      if (!diag) issue_panel(S, lds, n, rowB, kc + KS, kend, nx.b);
+    }
+    // (in diagonal tiles the wave above the diagonal computes too; its result is not stored:
+    // a divergent skip here makes the compiler shuffle every accumulator each step)
+    const Stage& cu = (s & 1) ? st1 : st0;
+    const float* pa = cu.a;
+    const float* pb = diag ? cu.a : cu.b;
+    step_compute<PREC>(pa, pb, wr * WT + l32, wc * WT + l32, half, sgn, acc);
+  }
+
+  float* out = part + (slice * ntri + tile) * (int64_t)(T * T);
+#pragma unroll
+  for (int i = 0; i < NB; ++i)
+#pragma unroll
+    for (int j = 0; j < NB; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int row = wr * WT + i * 32 + 8 * (r >> 2) + 4 * half + (r & 3);
+        const int col = wc * WT + j * 32 + l32;
+        out[row * T + col] = active ? sgn * acc[i][j][r] : 0.f;
+      }
+}
+
+}  // namespace v2
+
+// ---------------------------------------------------------------------------------------------
+// Gram kernel v3: scaled FP8. The operands are the block-scaled E4M3 codes written by the row
+// pass (codes q: n x ldq bytes; E8M0 scales: n x ldq/32 bytes, one per row and 32-column block).
+//   * k-step = 64 columns (two scale blocks). Codes move direct-to-LDS: each wave instruction
+//     carries 16 rows x 64 B; row r's four 16-byte chunks are XOR-swizzled by (r >> 2) & 3 so the
+//     fragment reads of 16 consecutive rows hit distinct banks. Scale bytes move direct-to-LDS as
+//     one aligned 4-byte word per row (four blocks, 128 columns; the step uses two of them), since
+//     the LDS side of these loads advances 4 bytes per lane. Needs ldq a multiple of 128.
+//   * Four LDS stages: loads run three steps ahead of the matrix cores. Every wave issues the same
+//     number of loads per step (diagonal tiles load their B panel as well), so waiting for a
+//     stage is a vmcnt wait on the count of loads issued after it, plus one barrier per step.
+//   * v_mfma_scale_f32_32x32x64_f8f6f4: lane l supplies row (l % 32), 16 codes from scale block 0
+//     and 16 from block 1 of the step (bytes [16h, 16h+16) and [32+16h, 32+16h+16) for h = l/32),
+//     and the E8M0 scale of block h of its row. A and B use the same byte arrangement, so every
+//     product pairs one column with itself.
+//   * Columns [m16, m) with m16 = m rounded down to 16 are left to the FP64 reduction.
+//   * Alternating slice sign as in v2: odd slices flip the sign bit of A's codes.
+namespace v3 {
+
+constexpr int NW = 4;
+constexpr int NT = 64 * NW;
+constexpr int WT = 128;
+constexpr int NB = WT / 32;
+constexpr int KS8 = 64;                  // codes (bytes) per row per step
+constexpr int PANEL = T * KS8;           // 16 KB
+constexpr int NS = 4;                    // LDS stages
+constexpr int LOADS_PER_STEP = 2 * (T / 16 / NW) + 2;   // codes A, B + scales A, B (per wave)
+
+typedef __attribute__((address_space(3))) void lds_void;
+typedef int i32x8 __attribute__((ext_vector_type(8)));
+typedef int i32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __align__(16) uint8_t g_zero_chunk8[16] = {0};
+
+struct Stage {
+  uint8_t a[PANEL];
+  uint8_t b[PANEL];
+  uint8_t sa[4 * T];   // scale word of row r at [4r, 4r + 4): blocks 4w .. 4w + 3, w = kcol / 128
+  uint8_t sb[4 * T];
+};
+
+__device__ __forceinline__ void issue_codes(const uint8_t* __restrict__ q, int64_t ldq, int64_t n, int64_t row0,
+                                            int64_t kcol, int64_t kend, uint8_t* panel) {
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int rsub = lane >> 2;          // row inside the 16-row group
+  const int p = lane & 3;              // LDS chunk position
+#pragma unroll
+  for (int i = 0; i < T / 16 / NW; ++i) {
+    const int g = wave + NW * i;
+    const int r = 16 * g + rsub;
+    const int c = p ^ ((r >> 2) & 3);
+    int64_t R = row0 + r;
+    if (R >= n) R = n - 1;
+    const int64_t col = kcol + 16 * c;
+    // Branch-free choice between the row chunk and the zero chunk: a divergent branch here would
+    // issue the load twice (once per path) and break the fixed per-step load count that the
+    // vmcnt waits rely on.
+    const uint64_t in = (uint64_t)0 - (uint64_t)(col < kend);
+    const uint64_t addr = ((uint64_t)(uintptr_t)(q + R * ldq + col) & in) |
+                          ((uint64_t)(uintptr_t)g_zero_chunk8 & ~in);
+    __builtin_amdgcn_global_load_lds((const void*)(uintptr_t)addr, (lds_void*)(panel + 16 * g * KS8), 16, 0, 0);
+  }
+}
+
+// Scale words of rows [row0, row0 + 256) for the step at column kcol: the 4-byte word holding blocks
+// 4 (kcol / 128) .. + 3 (aligned: ldq / 32 is a multiple of 4). Wave w moves rows 64w .. 64w + 63.
+__device__ __forceinline__ void issue_scales(const uint8_t* __restrict__ sc, int64_t ldsc, int64_t n, int64_t row0,
+                                             int64_t kcol, uint8_t* dst) {
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  int64_t R = row0 + 64 * wave + lane;
+  if (R >= n) R = n - 1;
+  const uint8_t* src = sc + R * ldsc + ((kcol >> 5) & ~(int64_t)3);
+  __builtin_amdgcn_global_load_lds((const void*)src, (lds_void*)(dst + 256 * wave), 4, 0, 0);
+}
+
+// Fragment of row r: chunks h and 2 + h (swizzled) -> 32 codes.
+__device__ __forceinline__ i32x8 read_frag(const uint8_t* panel, int r, int h) {
+  const int sw = (r >> 2) & 3;
+  const i32x4 x0 = *reinterpret_cast<const i32x4*>(panel + r * KS8 + 16 * (h ^ sw));
+  const i32x4 x1 = *reinterpret_cast<const i32x4*>(panel + r * KS8 + 16 * ((2 + h) ^ sw));
+  i32x8 v;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    v[e] = x0[e];
+    v[4 + e] = x1[e];
+  }
+  return v;
+}
+
+// vmcnt(N) with the other counters left alone (gfx9 encoding: vmcnt bits [3:0] and [15:14]).
+#define DFI_WAIT_VM(N) __builtin_amdgcn_s_waitcnt(((N) & 15) | (((N) >> 4) << 14) | (7 << 4) | (15 << 8))
+
+__global__ void __launch_bounds__(NT, 1)
+gram_kernel_fp8(const uint8_t* __restrict__ q, const uint8_t* __restrict__ sc, int64_t ldq, int64_t n, int64_t m16,
+                int64_t ntri, int64_t nslice, int64_t kslice, float* __restrict__ part) {
+  __shared__ Stage stg0, stg1, stg2, stg3;
+
+  const int64_t w = blockIdx.x;
+  const int64_t xcd = w & 7;
+  const int64_t local = w >> 3;
+  const int64_t qq = local / ntri;
+  const int64_t tile = local - qq * ntri;
+  const int64_t slice = xcd * (nslice >> 3) + qq;
+  const int flip = (slice & 1) ? (int)0x80808080 : 0;
+
+  int64_t ti, tj;
+  tri_index(tile, ti, tj);
+  const bool diag = (ti == tj);
+  const int64_t rowA = ti * T, rowB = tj * T;
+  const int64_t k0 = slice * kslice;
+  const int64_t kend = min(m16, k0 + kslice);
+  const int64_t nsteps = (kend > k0) ? (kend - k0 + KS8 - 1) / KS8 : 0;
+  const int64_t ldsc = ldq >> 5;
+
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int wr = wave >> 1, wc = wave & 1;
+  const int half = lane >> 5;
+  const int l32 = lane & 31;
+  const bool active = !(diag && wr == 0 && wc == 1);
+
+  f32x16 acc[NB][NB];
+#pragma unroll
+  for (int i = 0; i < NB; ++i)
+#pragma unroll
+    for (int j = 0; j < NB; ++j)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) acc[i][j][e] = 0.f;
+
+  auto stage_ptr = [&](int64_t idx) -> Stage* {
+    switch (idx & 3) {
+      case 0: return &stg0;
+      case 1: return &stg1;
+      case 2: return &stg2;
+      default: return &stg3;
+    }
+  };
+  auto issue_step = [&](int64_t step) {
+    Stage* st = stage_ptr(step);
+    const int64_t kc = k0 + step * KS8;
+    issue_codes(q, ldq, n, rowA, kc, kend, st->a);
+    issue_codes(q, ldq, n, rowB, kc, kend, st->b);   // diagonal tiles too: uniform load counts
+    issue_scales(sc, ldsc, n, rowA, kc, st->sa);
+    issue_scales(sc, ldsc, n, rowB, kc, st->sb);
+  };
+
+  for (int64_t st = 0; st < NS - 1 && st < nsteps; ++st) issue_step(st);
+  for (int64_t s = 0; s < nsteps; ++s) {
+    // loads issued after step s's: steps s+1 .. min(s + NS - 2, nsteps - 1)
+    const int64_t later = min<int64_t>(NS - 2, nsteps - 1 - s);
+    if (later >= 2) DFI_WAIT_VM(2 * LOADS_PER_STEP);
+    else if (later == 1) DFI_WAIT_VM(LOADS_PER_STEP);
+    else DFI_WAIT_VM(0);
+    // Every wave's loads for step s have landed and every wave has finished reading stage
+    // (s - 1) % NS. A bare barrier: __syncthreads() would also wait for the later stages' loads.
+    asm volatile("s_barrier" ::: "memory");
+    if (s + NS - 1 < nsteps) issue_step(s + NS - 1);
+    const Stage* cu = stage_ptr(s);
+    const int sbyte = (int)(((k0 + s * KS8) >> 5) & 3) + half;   // this step's block h in the scale word
+    i32x8 fb[NB];
+    int sbv[NB];
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      const int r = wc * WT + j * 32 + l32;
+      fb[j] = read_frag(cu->b, r, half);
+      sbv[j] = cu->sb[4 * r + sbyte];
+    }
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+      const int r = wr * WT + i * 32 + l32;
+      i32x8 fa = read_frag(cu->a, r, half);
+      const int sav = cu->sa[4 * r + sbyte];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) fa[e] ^= flip;
+#pragma unroll
+      for (int j = 0; j < NB; ++j)
+        acc[i][j] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(fa, fb[j], acc[i][j], 0, 0, 0, sav, 0, sbv[j]);
+    }
+  }
+
+  const float sgn = (slice & 1) ? -1.f : 1.f;
+  float* out = part + (slice * ntri + tile) * (int64_t)(T * T);
+#pragma unroll
+  for (int i = 0; i < NB; ++i)
+#pragma unroll
+    for (int j = 0; j < NB; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int row = wr * WT + i * 32 + 8 * (r >> 2) + 4 * half + (r & 3);
+        const int col = wc * WT + j * 32 + l32;
+        out[row * T + col] = active ? sgn * acc[i][j][r] : 0.f;
+      }
+}
+
+}  // namespace v3
+
+// ---------------------------------------------------------------------------------------------
+// Gram kernel v4: split-BF16 from pre-split planes. The row pass writes hi = bf16_rne(S) and
+// lo = bf16_rne(S - hi) as two n x ldh bf16 planes; the tile kernel is then a plain bf16
+// matrix-core product with three terms per pair of elements (lo.hi, hi.lo, hi.hi) and no
+// conversion work in its loop.
+//   * k-step = 16 columns: 32 bytes of each of the 256 rows of a panel, per plane. One wave
+//     instruction moves 32 rows straight to LDS (two 16-byte chunks per row); a row's chunks are
+//     swapped when (row >> 2) is odd, so the fragment reads of 8 consecutive rows cover all banks.
+//   * Four LDS stages of 32 KB (A hi, A lo, B hi, B lo); loads run three steps ahead of the
+//     matrix cores, with the same vmcnt-counted waits as v3 (every wave issues the same number of
+//     loads per step; diagonal tiles load their B panel too).
+//   * v_mfma_f32_32x32x16_bf16: lane l supplies row l % 32 and columns 8h .. 8h + 7 of the step
+//     (h = l / 32), for A and B alike.
+//   * Columns [m8, m), m8 = m rounded down to 8, are left to the FP64 reduction.
+//   * Alternating slice sign as in v1: odd slices flip the sign bits of A's fragments.
+namespace v4 {
+
+constexpr int NW = 4;
+constexpr int NT = 64 * NW;
+constexpr int WT = 128;
+constexpr int NB = WT / 32;
+constexpr int KSB = 16;                          // bf16 columns per step
+constexpr int ROWB = 2 * KSB;                    // 32 bytes per row and plane
+constexpr int PANEL = T * ROWB;                  // 8 KB
+constexpr int NS = 4;                            // LDS stages
+constexpr int INSTR = T / 32 / NW;               // load instructions per wave, panel and plane (2)
+constexpr int LOADS_PER_STEP = 4 * INSTR;        // A hi, A lo, B hi, B lo
+
+typedef __attribute__((address_space(3))) void lds_void;
+
+__device__ __align__(16) uint16_t g_zero_chunk16[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+
+struct Stage {
+  uint8_t ah[PANEL];
+  uint8_t al[PANEL];
+  uint8_t bh[PANEL];
+  uint8_t bl[PANEL];
+};
+
+// One plane of one 256-row panel for the step at column kcol. Wave instruction i moves rows
+// 32 g .. 32 g + 31 (g = wave + 4 i); lane l fills LDS row 32 g + l / 2, chunk slot l % 2, with
+// column chunk (l % 2) ^ ((row >> 2) & 1) of that row (or zeros past kend).
+__device__ __forceinline__ void issue_plane(const uint16_t* __restrict__ plane, int64_t ldh, int64_t n, int64_t row0,
+                                            int64_t kcol, int64_t kend, uint8_t* panel) {
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int i = 0; i < INSTR; ++i) {
+    const int g = wave + NW * i;
+    const int r = 32 * g + (lane >> 1);
+    const int c = (lane & 1) ^ ((r >> 2) & 1);
+    int64_t R = row0 + r;
+    if (R >= n) R = n - 1;
+    const int64_t col = kcol + 8 * c;
+    // branch-free choice of the source keeps the per-step load count fixed (see v3)
+    const uint64_t in = (uint64_t)0 - (uint64_t)(col < kend);
+    const uint64_t addr = ((uint64_t)(uintptr_t)(plane + R * ldh + col) & in) |
+                          ((uint64_t)(uintptr_t)g_zero_chunk16 & ~in);
+    __builtin_amdgcn_global_load_lds((const void*)(uintptr_t)addr, (lds_void*)(panel + 32 * g * ROWB), 16, 0, 0);
+  }
+}
+
+__device__ __forceinline__ bf16x8 read_bf(const uint8_t* panel, int r, int h) {
+  return *reinterpret_cast<const bf16x8*>(panel + r * ROWB + 16 * (h ^ ((r >> 2) & 1)));
+}
+
+__global__ void __launch_bounds__(NT, 1)
+gram_kernel_split(const uint16_t* __restrict__ hi, const uint16_t* __restrict__ lo, int64_t ldh, int64_t n,
+                  int64_t m8, int64_t ntri, int64_t nslice, int64_t kslice, float* __restrict__ part) {
+  __shared__ Stage stg0, stg1, stg2, stg3;
+
+  const int64_t w = blockIdx.x;
+  const int64_t xcd = w & 7;
+  const int64_t local = w >> 3;
+  const int64_t qq = local / ntri;
+  const int64_t tile = local - qq * ntri;
+  const int64_t slice = xcd * (nslice >> 3) + qq;
+  const uint32_t bflip = (slice & 1) ? 0x80008000u : 0u;
+
+  int64_t ti, tj;
+  tri_index(tile, ti, tj);
+  const bool diag = (ti == tj);
+  const int64_t rowA = ti * T, rowB = tj * T;
+  const int64_t k0 = slice * kslice;
+  const int64_t kend = min(m8, k0 + kslice);
+  const int64_t nsteps = (kend > k0) ? (kend - k0 + KSB - 1) / KSB : 0;
+
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int wr = wave >> 1, wc = wave & 1;
+  const int half = lane >> 5;
+  const int l32 = lane & 31;
+  const bool active = !(diag && wr == 0 && wc == 1);
+
+  f32x16 acc[NB][NB];
+#pragma unroll
+  for (int i = 0; i < NB; ++i)
+#pragma unroll
+    for (int j = 0; j < NB; ++j)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) acc[i][j][e] = 0.f;
+
+  auto stage_ptr = [&](int64_t idx) -> Stage* {
+    switch (idx & 3) {
+      case 0: return &stg0;
+      case 1: return &stg1;
+      case 2: return &stg2;
+      default: return &stg3;
+    }
+  };
+  auto issue_step = [&](int64_t step) {
+    Stage* sp = stage_ptr(step);
+    const int64_t kc = k0 + step * KSB;
+    issue_plane(hi, ldh, n, rowA, kc, kend, sp->ah);
+    issue_plane(lo, ldh, n, rowA, kc, kend, sp->al);
+    issue_plane(hi, ldh, n, rowB, kc, kend, sp->bh);
+    issue_plane(lo, ldh, n, rowB, kc, kend, sp->bl);
+  };
+
+  for (int64_t s0 = 0; s0 < NS - 1 && s0 < nsteps; ++s0) issue_step(s0);
+  for (int64_t s = 0; s < nsteps; ++s) {
+    const int64_t later = min<int64_t>(NS - 2, nsteps - 1 - s);
+    if (later >= 2) DFI_WAIT_VM(2 * LOADS_PER_STEP);
+    else if (later == 1) DFI_WAIT_VM(LOADS_PER_STEP);
+    else DFI_WAIT_VM(0);
+    asm volatile("s_barrier" ::: "memory");
+    if (s + NS - 1 < nsteps) issue_step(s + NS - 1);
+    const Stage* cu = stage_ptr(s);
+    bf16x8 bh[NB], bl[NB];
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      const int r = wc * WT + j * 32 + l32;
+      bh[j] = read_bf(cu->bh, r, half);
+      bl[j] = read_bf(cu->bl, r, half);
+    }
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+      const int r = wr * WT + i * 32 + l32;
+      const bf16x8 ah = flip_sign(read_bf(cu->ah, r, half), bflip);
+      const bf16x8 al = flip_sign(read_bf(cu->al, r, half), bflip);
+#pragma unroll
+      for (int j = 0; j < NB; ++j) {
+        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh[j], acc[i][j], 0, 0, 0);
+        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl[j], acc[i][j], 0, 0, 0);
+        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh[j], acc[i][j], 0, 0, 0);
+      }
+    }
+  }
+
+  const float sgn = (slice & 1) ? -1.f : 1.f;
+  float* out = part + (slice * ntri + tile) * (int64_t)(T * T);
+#pragma unroll
+  for (int i = 0; i < NB; ++i)
+#pragma unroll
+    for (int j = 0; j < NB; ++j)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int row = wr * WT + i * 32 + 8 * (r >> 2) + 4 * half + (r & 3);
+        const int col = wc * WT + j * 32 + l32;
+        out[row * T + col] = active ? sgn * acc[i][j][r] : 0.f;
+      }
+}
+
+}  // namespace v4
+
+// W_ij = sum over slices of the partial tiles (FP64, slice order) for i > j, plus the products of
+// columns [ktail, m) that the tile kernel left out (FP64); W_ii = d_i + lambda.
 // mirror != 0 also writes W_ji. One workgroup covers 256 consecutive columns j of one row i.
 __global__ void gram_reduce_kernel(const float* __restrict__ part, int64_t n, int64_t ntri, int64_t nslice,
                                    const double* __restrict__ d, double lambda, double* __restrict__ W,
-                                   int mirror) {
+                                   int mirror, const float* __restrict__ S, int64_t lds, int64_t ktail, int64_t m) {
   const int64_t nb = (n + 255) / 256;
   const int64_t i = (int64_t)blockIdx.x / nb;
   const int64_t j = ((int64_t)blockIdx.x - i * nb) * 256 + threadIdx.x;
@@ -281,6 +871,7 @@ __global__ void gram_reduce_kernel(const float* __restrict__ part, int64_t n, in
     const int64_t off = (i - ti * T) * T + (j - tj * T);
     s = 0.0;
     for (int64_t sl = 0; sl < nslice; ++sl) s += (double)part[(sl * ntri + tile) * (int64_t)(T * T) + off];
+    for (int64_t k = ktail; k < m; ++k) s += (double)S[i * lds + k] * (double)S[j * lds + k];
   }
   W[i * n + j] = s;
   if (mirror && i != j) W[j * n + i] = s;
@@ -288,7 +879,7 @@ __global__ void gram_reduce_kernel(const float* __restrict__ part, int64_t n, in
 
 }  // namespace
 
-GramPlan gram_plan(int64_t n, int64_t m, int64_t lds, int prec) {
+GramPlan gram_plan(int64_t n, int64_t m, int64_t lds, int prec, bool aligned16) {
   GramPlan p{};
   p.n = n;
   p.m = m;
@@ -314,37 +905,70 @@ GramPlan gram_plan(int64_t n, int64_t m, int64_t lds, int prec) {
     }
   }
   p.nslice = 8 * best_q;
+  const int64_t kstep = (prec == 2) ? 64 : KS;
   int64_t ks = (m + p.nslice - 1) / p.nslice;
-  ks = (ks + KS - 1) / KS * KS;
-  if (ks < KS) ks = KS;
+  ks = (ks + kstep - 1) / kstep * kstep;
+  if (ks < kstep) ks = kstep;
   p.kslice = ks;
+  p.ldh = (prec == 1 && aligned16) ? split_ldh(m) : 0;
   p.part_bytes = (size_t)p.nslice * (size_t)p.ntri * (size_t)(T * T) * sizeof(float);
   return p;
+}
+
+hipError_t gram_launch_fp8(const GramPlan& p, const uint8_t* q, const uint8_t* sc, int64_t ldq, float* part,
+                           hipStream_t st) {
+  const dim3 grid((unsigned)(p.nslice * p.ntri));
+  hipLaunchKernelGGL(v3::gram_kernel_fp8, grid, dim3(v3::NT), 0, st, q, sc, ldq, p.n, p.m & ~(int64_t)15, p.ntri,
+                     p.nslice, p.kslice, part);
+  return hipGetLastError();
+}
+
+hipError_t gram_launch_split(const GramPlan& p, const uint16_t* hi, const uint16_t* lo, float* part, hipStream_t st) {
+  if (p.prec != 1 || p.ldh <= 0 || (p.ldh & 63) != 0) return hipErrorInvalidValue;
+  const dim3 grid((unsigned)(p.nslice * p.ntri));
+  hipLaunchKernelGGL(v4::gram_kernel_split, grid, dim3(v4::NT), 0, st, hi, lo, p.ldh, p.n, p.m & ~(int64_t)7, p.ntri,
+                     p.nslice, p.kslice, part);
+  return hipGetLastError();
+}
+
+// Which tile kernel runs for an FP32 input S, and the first column it leaves to the reduction:
+//   * FP32 products, 16-byte aligned rows: v2 (direct-to-LDS), columns [0, m rounded down to 4);
+//   * split-BF16, or unaligned rows: v1 (register staging, conversion on the LDS store), all columns.
+// (For split-BF16 the register-staged kernel converts each element once per workgroup; v2 would
+// convert it once per reading wave, which measured slower.)
+static bool use_v2(const GramPlan& p, const float* S) {
+  const bool vec = ((p.lds & 3) == 0) && ((reinterpret_cast<uintptr_t>(S) & 15) == 0);
+  return vec && p.prec == 0;
+}
+
+static int64_t tail_start(const GramPlan& p, const float* S) {
+  if (p.prec == 2) return p.m & ~(int64_t)15;
+  if (p.prec == 1 && p.ldh > 0) return p.m & ~(int64_t)7;
+  return use_v2(p, S) ? (p.m & ~(int64_t)3) : p.m;
 }
 
 hipError_t gram_launch(const GramPlan& p, const float* S, float* part, hipStream_t st) {
   const bool vec = ((p.lds & 3) == 0) && ((reinterpret_cast<uintptr_t>(S) & 15) == 0);
   const dim3 grid((unsigned)(p.nslice * p.ntri));
-  const dim3 block(NTHR);
-  if (p.prec == 0) {
-    if (vec)
-      hipLaunchKernelGGL((gram_kernel<0, true>), grid, block, 0, st, S, p.n, p.lds, p.m, p.ntri, p.nslice, p.kslice, part);
-    else
-      hipLaunchKernelGGL((gram_kernel<0, false>), grid, block, 0, st, S, p.n, p.lds, p.m, p.ntri, p.nslice, p.kslice, part);
+  if (use_v2(p, S)) {
+    hipLaunchKernelGGL((v2::gram_kernel_v2<0>), grid, dim3(v2::NT), 0, st, S, p.n, p.lds, p.m, p.ntri, p.nslice, p.kslice, part);
+  } else if (p.prec == 0) {
+    hipLaunchKernelGGL((gram_kernel<0, false>), grid, dim3(NTHR), 0, st, S, p.n, p.lds, p.m, p.ntri, p.nslice, p.kslice, part);
+  } else if (vec) {
+    hipLaunchKernelGGL((gram_kernel<1, true>), grid, dim3(NTHR), 0, st, S, p.n, p.lds, p.m, p.ntri, p.nslice, p.kslice, part);
   } else {
-    if (vec)
-      hipLaunchKernelGGL((gram_kernel<1, true>), grid, block, 0, st, S, p.n, p.lds, p.m, p.ntri, p.nslice, p.kslice, part);
-    else
-      hipLaunchKernelGGL((gram_kernel<1, false>), grid, block, 0, st, S, p.n, p.lds, p.m, p.ntri, p.nslice, p.kslice, part);
+    hipLaunchKernelGGL((gram_kernel<1, false>), grid, dim3(NTHR), 0, st, S, p.n, p.lds, p.m, p.ntri, p.nslice, p.kslice, part);
   }
   return hipGetLastError();
 }
 
-hipError_t gram_reduce(const GramPlan& p, const float* part, const double* d, double lambda, double* W,
-                       int mirror, hipStream_t st) {
+hipError_t gram_reduce(const GramPlan& p, const float* S, const float* part, const double* d, double lambda,
+                       double* W, int mirror, hipStream_t st) {
+  const int64_t ktail = tail_start(p, S);   // first column the tile kernel left out
   const int64_t nb = (p.n + 255) / 256;
   const dim3 grid((unsigned)(nb * p.n));
-  hipLaunchKernelGGL(gram_reduce_kernel, grid, dim3(256), 0, st, part, p.n, p.ntri, p.nslice, d, lambda, W, mirror);
+  hipLaunchKernelGGL(gram_reduce_kernel, grid, dim3(256), 0, st, part, p.n, p.ntri, p.nslice, d, lambda, W, mirror,
+                     S, p.lds, ktail, p.m);
   return hipGetLastError();
 }
 

@@ -1,9 +1,12 @@
 // Blocked right-looking FP64 Cholesky W = L L^T (Algorithm 1 step 2), in place on a row-major
 // n x n matrix, lower triangle. Block size 64; per block column k:
 //   1. potf2   one wave factors the 64 x 64 diagonal block in LDS (left-looking: lane i owns
-//              row i and forms column j from dot products with the finished columns).
-//   2. trsm    rows below the block: A_ik <- A_ik L_kk^-T, one lane per row, L_kk in LDS.
-//   3. update  trailing lower triangle A_IJ -= A_Ik A_Jk^T in 64 x 64 tiles, panels in LDS.
+//              row i and forms column j from dot products with the finished columns), then forms
+//              the block's inverse L_kk^-1 (lane c solves for column c).
+//   2. trsm    rows below the block: A_ik <- A_ik L_kk^-T as a product with the stored inverse,
+//              64 rows per workgroup, every output independent.
+//   3. update  trailing lower triangle A_IJ -= A_Ik A_Jk^T in 64 x 64 tiles on the FP64 matrix
+//              cores (v_mfma_f64_16x16x4), panels staged in LDS.
 // A pivot d with !(d > 0) (NaN included) stores the 1-based global index in *info and raises
 // *flag; every later kernel sees the flag and returns at once, so the device work drains
 // without touching the matrix further.
@@ -12,11 +15,14 @@
 namespace dfi {
 namespace {
 
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
 constexpr int NB = 64;
 constexpr int LDP = NB + 1;  // padded LDS row (doubles)
 
 __global__ void __launch_bounds__(64)
-potf2_kernel(double* __restrict__ A, int64_t n, int64_t k, int64_t* __restrict__ info, int32_t* __restrict__ flag) {
+potf2_kernel(double* __restrict__ A, int64_t n, int64_t k, int64_t* __restrict__ info, int32_t* __restrict__ flag,
+             double* __restrict__ Dkk) {
   __shared__ double a[NB * LDP];
   if (*(volatile int32_t*)flag) return;
   const int lane = threadIdx.x;
@@ -54,35 +60,68 @@ potf2_kernel(double* __restrict__ A, int64_t n, int64_t k, int64_t* __restrict__
   for (int r = 0; r < nb; ++r) {
     if (lane <= r) A[(k + r) * n + k + lane] = a[r * LDP + lane];
   }
-}
-
-// Rows i in [k + NB, n): A[i][k .. k+NB) <- A[i][k .. k+NB) * L_kk^-T. One lane per row.
-__global__ void __launch_bounds__(64)
-trsm_kernel(double* __restrict__ A, int64_t n, int64_t k, const int32_t* __restrict__ flag) {
-  __shared__ double Lk[NB * LDP];
-  if (*(volatile const int32_t*)flag) return;
-  const int lane = threadIdx.x;
-  for (int r = 0; r < NB; ++r) Lk[r * LDP + lane] = (lane <= r) ? A[(k + r) * n + k + lane] : 0.0;
-  __syncthreads();
-  const int64_t i = k + NB + (int64_t)blockIdx.x * 64 + lane;
-  if (i >= n) return;
+  if (k + NB >= n) return;  // no rows below: the inverse is not needed
+  // Dkk = L_kk^-1; lane c forms column c (x_l = 0 for l < c).
+  const int c = lane;
   double x[NB];
-  double* row = A + i * n + k;
 #pragma unroll
-  for (int j = 0; j < NB; ++j) x[j] = row[j];
+  for (int r = 0; r < NB; ++r) {
+    double s = (r == c) ? 1.0 : 0.0;
 #pragma unroll
-  for (int j = 0; j < NB; ++j) {
-    double s = x[j];
-#pragma unroll
-    for (int l = 0; l < j; ++l) s -= x[l] * Lk[j * LDP + l];
-    x[j] = s / Lk[j * LDP + j];
+    for (int l = 0; l < r; ++l) s -= a[r * LDP + l] * x[l];
+    x[r] = (r >= c) ? s / a[r * LDP + r] : 0.0;
   }
 #pragma unroll
-  for (int j = 0; j < NB; ++j) row[j] = x[j];
+  for (int r = 0; r < NB; ++r) Dkk[r * NB + c] = x[r];
+}
+
+// Rows i in [k + NB, n): A[i][k .. k+NB) <- A[i][k .. k+NB) L_kk^-T, i.e. out_rc = sum_l A_rl D_cl.
+// 64 rows per workgroup, 256 threads with 4 x 4 outputs each.
+__global__ void __launch_bounds__(256)
+trsm_kernel(double* __restrict__ A, int64_t n, int64_t k, const int32_t* __restrict__ flag,
+            const double* __restrict__ Dkk) {
+  __shared__ double Ab[NB * LDP];
+  __shared__ double Db[NB * LDP];
+  if (*(volatile const int32_t*)flag) return;
+  const int tid = threadIdx.x;
+  const int64_t row0 = k + NB + (int64_t)blockIdx.x * NB;
+  for (int idx = tid; idx < NB * NB; idx += 256) {
+    const int r = idx / NB, c = idx % NB;
+    Ab[r * LDP + c] = (row0 + r < n) ? A[(row0 + r) * n + k + c] : 0.0;
+    Db[r * LDP + c] = Dkk[r * NB + c];
+  }
+  __syncthreads();
+  const int ty = tid / 16, tx = tid % 16;
+  double acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
+  for (int l = 0; l < NB; ++l) {
+    double av[4], dv[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) av[a] = Ab[(ty + 16 * a) * LDP + l];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) dv[b] = Db[(tx + 16 * b) * LDP + l];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) acc[a][b] = fma(av[a], dv[b], acc[a][b]);
+  }
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+    const int64_t gi = row0 + ty + 16 * a;
+    if (gi >= n) continue;
+#pragma unroll
+    for (int b = 0; b < 4; ++b) A[gi * n + k + tx + 16 * b] = acc[a][b];
+  }
 }
 
 // Trailing update of the lower triangle below/right of block column k: for tiles (I >= J) of the
-// trailing matrix, A_IJ -= P_I P_J^T with P = A[:, k .. k+NB). 256 threads, 4 x 4 outputs each.
+// trailing matrix, A_IJ -= P_I P_J^T with P = A[:, k .. k+NB). Four waves, each a 32 x 32 quarter
+// of the tile as 2 x 2 blocks of 16 x 16 FP64 MFMA accumulators; K = 64 in 16 steps of 4.
+// MFMA lane layout (16x16x4 f64): A lane l = (row l%16, k l/16), B lane l = (k l/16, col l%16),
+// D lane l register r = (row l/16 + 4r, col l%16).
 __global__ void __launch_bounds__(256)
 update_kernel(double* __restrict__ A, int64_t n, int64_t k, const int32_t* __restrict__ flag) {
   __shared__ double PI[NB * LDP];
@@ -102,34 +141,36 @@ update_kernel(double* __restrict__ A, int64_t n, int64_t k, const int32_t* __res
     PJ[r * LDP + c] = (rj + r < n) ? A[(rj + r) * n + k + c] : 0.0;
   }
   __syncthreads();
-  const int ty = tid / 16, tx = tid % 16;
-  double acc[4][4];
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wy = wave >> 1, wx = wave & 1;
+  const int l16 = lane & 15, kq = lane >> 4;
+  f64x4 acc[2][2];
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+  for (int a = 0; a < 2; ++a)
 #pragma unroll
-    for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
-  for (int l = 0; l < NB; ++l) {
-    double pi[4], pj[4];
+    for (int b = 0; b < 2; ++b) acc[a][b] = (f64x4){0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+  for (int k0 = 0; k0 < NB; k0 += 4) {
+    double av[2], bv[2];
 #pragma unroll
-    for (int a = 0; a < 4; ++a) pi[a] = PI[(ty + 16 * a) * LDP + l];
+    for (int a = 0; a < 2; ++a) av[a] = PI[(wy * 32 + a * 16 + l16) * LDP + k0 + kq];
 #pragma unroll
-    for (int b = 0; b < 4; ++b) pj[b] = PJ[(tx + 16 * b) * LDP + l];
+    for (int b = 0; b < 2; ++b) bv[b] = PJ[(wx * 32 + b * 16 + l16) * LDP + k0 + kq];
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
+    for (int a = 0; a < 2; ++a)
 #pragma unroll
-      for (int b = 0; b < 4; ++b) acc[a][b] = fma(pi[a], pj[b], acc[a][b]);
+      for (int b = 0; b < 2; ++b) acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
   }
 #pragma unroll
-  for (int a = 0; a < 4; ++a) {
-    const int64_t gi = ri + ty + 16 * a;
-    if (gi >= n) continue;
+  for (int a = 0; a < 2; ++a)
 #pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      const int64_t gj = rj + tx + 16 * b;
-      if (gj > gi || gj >= n) continue;
-      A[gi * n + gj] -= acc[a][b];
-    }
-  }
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t gi = ri + wy * 32 + a * 16 + kq + 4 * r;
+        const int64_t gj = rj + wx * 32 + b * 16 + l16;
+        if (gi < n && gj <= gi) A[gi * n + gj] -= acc[a][b][r];
+      }
 }
 
 __global__ void zero_upper_kernel(double* __restrict__ A, int64_t n) {
@@ -139,11 +180,15 @@ __global__ void zero_upper_kernel(double* __restrict__ A, int64_t n) {
   if (i < n && j < n && j > i) A[i * n + j] = 0.0;
 }
 
-__global__ void shift_copy_kernel(const double* __restrict__ src, double* __restrict__ dst, int64_t n, double tau) {
+// dst = src + (scale * dmax[0] + lam) I
+__global__ void shift_copy_kernel(const double* __restrict__ src, double* __restrict__ dst, int64_t n, double scale,
+                                  const double* __restrict__ dmax, double lam) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= n * n) return;
   const int64_t i = idx / n, j = idx - i * n;
-  dst[idx] = src[idx] + ((i == j) ? tau : 0.0);
+  double add = 0.0;
+  if (i == j) add = lam + ((scale != 0.0) ? scale * dmax[0] : 0.0);
+  dst[idx] = src[idx] + add;
 }
 
 __global__ void axpy_kernel(double* __restrict__ y, const double* __restrict__ d, int64_t n) {
@@ -174,14 +219,14 @@ __global__ void clear_status_kernel(int64_t* info, int32_t* flag) {
 
 }  // namespace
 
-hipError_t potrf_launch(double* A, int64_t n, int64_t* info_dev, int32_t* flag_dev, hipStream_t st) {
+hipError_t potrf_launch(double* A, int64_t n, int64_t* info_dev, int32_t* flag_dev, double* dkk, hipStream_t st) {
   hipLaunchKernelGGL(clear_status_kernel, dim3(1), dim3(1), 0, st, info_dev, flag_dev);
   for (int64_t k = 0; k < n; k += NB) {
-    hipLaunchKernelGGL(potf2_kernel, dim3(1), dim3(64), 0, st, A, n, k, info_dev, flag_dev);
+    hipLaunchKernelGGL(potf2_kernel, dim3(1), dim3(64), 0, st, A, n, k, info_dev, flag_dev, dkk);
     const int64_t rest = n - k - NB;
     if (rest > 0) {
       const int64_t rb = (rest + 63) / 64;
-      hipLaunchKernelGGL(trsm_kernel, dim3((unsigned)rb), dim3(64), 0, st, A, n, k, flag_dev);
+      hipLaunchKernelGGL(trsm_kernel, dim3((unsigned)rb), dim3(256), 0, st, A, n, k, flag_dev, (const double*)dkk);
       hipLaunchKernelGGL(update_kernel, dim3((unsigned)(rb * (rb + 1) / 2)), dim3(256), 0, st, A, n, k, flag_dev);
     }
   }
@@ -194,9 +239,17 @@ hipError_t zero_upper(double* A, int64_t n, hipStream_t st) {
   return hipGetLastError();
 }
 
-hipError_t shift_copy(const double* src, double* dst, int64_t n, double tau, hipStream_t st) {
+hipError_t shift_copy(const double* src, double* dst, int64_t n, double scale, const double* dmax, hipStream_t st) {
   const int64_t tot = n * n;
-  hipLaunchKernelGGL(shift_copy_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, src, dst, n, tau);
+  hipLaunchKernelGGL(shift_copy_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, src, dst, n, scale, dmax,
+                     0.0);
+  return hipGetLastError();
+}
+
+hipError_t add_diag_copy(const double* src, double* dst, int64_t n, double lam, hipStream_t st) {
+  const int64_t tot = n * n;
+  hipLaunchKernelGGL(shift_copy_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, src, dst, n, 0.0,
+                     (const double*)nullptr, lam);
   return hipGetLastError();
 }
 

@@ -1,13 +1,16 @@
 // Triangular solves with the Cholesky factor L (row-major n x n FP64, lower): the L^-1 and L^-T
 // applications of the right-to-left evaluation of S^T L^-T L^-1 S v (Section 2, after Algorithm 1).
 //
-// One workgroup of 1024 threads (16 waves) walks 64-row blocks. For each block:
-//   * the off-diagonal contribution is a dense product over the already solved part, spread over
-//     all 16 waves (forward: row dot products, lanes striding the row; backward: the rows below
-//     the block, each lane owning one column of the block);
-//   * the 64 x 64 diagonal triangle is solved by one wave with register broadcasts (__shfl),
-//     its coefficients staged in LDS.
-// The solution vector lives in LDS, so n is limited by LDS capacity (TRSV_MAX_N).
+// Blocked by 64-row blocks, in two parts:
+//   * diag_inv: the inverse of every 64 x 64 diagonal block D_k = L_kk^-1 (one workgroup per
+//     block, all blocks in parallel; lane c forms column c by forward substitution). For a
+//     factorisation this is computed once and reused by every solve.
+//   * one launch per block step. Forward step k: every workgroup forms z_k = D_k r_k (a 64 x 64
+//     matrix-vector product; r_k is final because all earlier steps have updated it), workgroup 0
+//     stores z_k, and each workgroup then updates its own 64-row block J > k of the right-hand
+//     side, r_J -= L_Jk z_k. Backward step k (from the last block): y_k = D_k^T r_k, then
+//     r_J -= L_kJ^T y_k for the blocks J < k, which read row block k of L (contiguous rows).
+// Every launch reads only the panel it needs; the whole solve reads the lower triangle once.
 #include "dfisher_internal.h"
 
 namespace dfi {
@@ -15,122 +18,143 @@ namespace {
 
 constexpr int NB = 64;
 constexpr int LDP = NB + 1;
-constexpr int NW = 16;  // waves
 
-__device__ __forceinline__ double wave_sum(double x) {
+// D_k = inverse of the lower-triangular 64 x 64 block L_kk (identity-padded past n).
+// One 64-lane workgroup per block; lane c computes column c: x_c = e_c, x_i = -(sum_{c<=l<i} L_il x_l)/L_ii.
+__global__ void __launch_bounds__(64)
+diag_inv_kernel(const double* __restrict__ L, int64_t n, double* __restrict__ Dinv) {
+  __shared__ double Lk[NB * LDP];
+  const int64_t k = blockIdx.x;
+  const int64_t r0 = k * NB;
+  const int c = threadIdx.x;
+  for (int r = 0; r < NB; ++r) {
+    double val = 0.0;
+    if (r0 + r < n && r0 + c < n) {
+      if (c <= r) val = L[(r0 + r) * n + r0 + c];
+    } else if (r == c) {
+      val = 1.0;
+    }
+    Lk[r * LDP + c] = val;
+  }
+  __syncthreads();
+  double x[NB];
 #pragma unroll
-  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
-  return x;
+  for (int i = 0; i < NB; ++i) {
+    double s = (i == c) ? 1.0 : 0.0;
+#pragma unroll
+    for (int l = 0; l < i; ++l) s -= Lk[i * LDP + l] * x[l];   // x_l = 0 for l < c
+    x[i] = (i >= c) ? s / Lk[i * LDP + i] : 0.0;
+  }
+  double* D = Dinv + k * NB * NB;
+#pragma unroll
+  for (int i = 0; i < NB; ++i) D[i * NB + c] = x[i];   // D[i][c] = (L_kk^-1)_ic
 }
 
-// y = L^-1 b
-__global__ void __launch_bounds__(64 * NW)
-trsv_fwd_kernel(const double* __restrict__ L, int64_t n, const double* b, double* y) {
-  extern __shared__ double sm[];
-  double* z = sm;               // n
-  double* rhs = z + n;          // NB
-  double* D = rhs + NB;         // NB * LDP
-  const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
-  const int64_t nblk = (n + NB - 1) / NB;
-  for (int64_t kb = 0; kb < nblk; ++kb) {
-    const int64_t r0 = kb * NB;
-    const int nb = (int)min<int64_t>(NB, n - r0);
-    // rhs_i = b_i - sum_{c < r0} L_ic z_c ; wave w takes rows w, w + 16, ...
-    for (int r = wave; r < nb; r += NW) {
-      const double* Lr = L + (r0 + r) * n;
-      double acc = 0.0;
-      for (int64_t c = lane; c < r0; c += 64) acc = fma(Lr[c], z[c], acc);
-      acc = wave_sum(acc);
-      if (lane == 0) rhs[r] = b[r0 + r] - acc;
-    }
-    // diagonal block into LDS
-    for (int idx = threadIdx.x; idx < NB * NB; idx += 64 * NW) {
-      const int r = idx / NB, c = idx % NB;
-      D[r * LDP + c] = (r < nb && c <= r) ? L[(r0 + r) * n + r0 + c] : 0.0;
-    }
-    __syncthreads();
-    if (wave == 0) {
-      double val = (lane < nb) ? rhs[lane] : 0.0;
-      double zi = 0.0;
-      for (int c = 0; c < nb; ++c) {
-        const double zc = __shfl(val / D[lane * LDP + lane], c, 64);
-        if (lane == c) zi = zc;
-        if (lane > c) val = fma(-D[lane * LDP + c], zc, val);
-      }
-      if (lane < nb) {
-        z[r0 + lane] = zi;
-      }
-    }
-    __syncthreads();
+// Forward step k. r: right-hand side being reduced in place (FP64, length n); z: output.
+// Grid: 1 + number of row blocks below k (at least 1). 256 threads.
+__global__ void __launch_bounds__(256)
+fwd_step_kernel(const double* __restrict__ L, int64_t n, const double* __restrict__ Dinv, int64_t k,
+                double* __restrict__ r, double* __restrict__ z) {
+  __shared__ double zk[NB];
+  __shared__ double part[4][NB];
+  const int tid = threadIdx.x;
+  const int64_t r0 = k * NB;
+  const int nb = (int)min<int64_t>(NB, n - r0);
+  // z_k = D_k r_k: 4 groups of 64 threads each take 16 columns of D_k
+  {
+    const int i = tid & 63, g = tid >> 6;
+    const double* D = Dinv + k * NB * NB;
+    double s = 0.0;
+    for (int c = g * 16; c < g * 16 + 16; ++c)
+      if (c < nb) s = fma(D[i * NB + c], r[r0 + c], s);
+    part[g][i] = s;
   }
-  for (int64_t i = threadIdx.x; i < n; i += 64 * NW) y[i] = z[i];
+  __syncthreads();
+  if (tid < NB) zk[tid] = part[0][tid] + part[1][tid] + part[2][tid] + part[3][tid];
+  __syncthreads();
+  if (blockIdx.x == 0) {
+    if (tid < nb) z[r0 + tid] = zk[tid];
+    return;
+  }
+  // r_J -= L_Jk z_k for row block J = k + blockIdx.x: 4 threads per row, 16 columns each
+  const int64_t row = (k + blockIdx.x) * NB + (tid >> 2);
+  if (row >= n) return;
+  const int q = tid & 3;
+  const double* Lr = L + row * n + r0;
+  double s = 0.0;
+#pragma unroll
+  for (int c = q * 16; c < q * 16 + 16; ++c)
+    if (c < nb) s = fma(Lr[c], zk[c], s);
+  s += __shfl_xor(s, 1, 64);
+  s += __shfl_xor(s, 2, 64);
+  if (q == 0) r[row] -= s;
 }
 
-// y = L^-T b : y_i = (b_i - sum_{k > i} L_ki y_k) / L_ii, blocks from the last to the first.
-__global__ void __launch_bounds__(64 * NW)
-trsv_bwd_kernel(const double* __restrict__ L, int64_t n, const double* b, double* y) {
-  extern __shared__ double sm[];
-  double* z = sm;               // n (solution)
-  double* part = z + n;         // NW * NB
-  double* D = part + NW * NB;   // NB * LDP
-  const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
-  const int64_t nblk = (n + NB - 1) / NB;
-  for (int64_t kb = nblk - 1; kb >= 0; --kb) {
-    const int64_t r0 = kb * NB;
-    const int nb = (int)min<int64_t>(NB, n - r0);
-    const int64_t rend = r0 + nb;
-    // part_w[j] = sum over rows k >= rend handled by wave w of L_k,(r0+j) z_k
-    double acc = 0.0;
-    if (lane < nb) {
-      for (int64_t k = rend + wave; k < n; k += NW) acc = fma(L[k * n + r0 + lane], z[k], acc);
-    }
-    part[wave * NB + lane] = acc;
-    for (int idx = threadIdx.x; idx < NB * NB; idx += 64 * NW) {
-      const int r = idx / NB, c = idx % NB;
-      D[r * LDP + c] = (r < nb && c <= r) ? L[(r0 + r) * n + r0 + c] : 0.0;
-    }
-    __syncthreads();
-    if (wave == 0) {
-      double s = 0.0;
-      for (int w = 0; w < NW; ++w) s += part[w * NB + lane];
-      double val = (lane < nb) ? b[r0 + lane] - s : 0.0;
-      double yi = 0.0;
-      for (int c = nb - 1; c >= 0; --c) {
-        const double yc = __shfl(val / D[lane * LDP + lane], c, 64);
-        if (lane == c) yi = yc;
-        if (lane < c) val = fma(-D[c * LDP + lane], yc, val);
-      }
-      if (lane < nb) z[r0 + lane] = yi;
-    }
-    __syncthreads();
+// Backward step k. Grid: 1 + k (block k itself and the blocks J < k). 256 threads.
+__global__ void __launch_bounds__(256)
+bwd_step_kernel(const double* __restrict__ L, int64_t n, const double* __restrict__ Dinv, int64_t k,
+                double* __restrict__ r, double* __restrict__ y) {
+  __shared__ double yk[NB];
+  __shared__ double part[4][NB];
+  const int tid = threadIdx.x;
+  const int64_t r0 = k * NB;
+  const int nb = (int)min<int64_t>(NB, n - r0);
+  // y_k = D_k^T r_k
+  {
+    const int i = tid & 63, g = tid >> 6;
+    const double* D = Dinv + k * NB * NB;
+    double s = 0.0;
+    for (int c = g * 16; c < g * 16 + 16; ++c)
+      if (c < nb) s = fma(D[c * NB + i], r[r0 + c], s);
+    part[g][i] = s;
   }
-  for (int64_t i = threadIdx.x; i < n; i += 64 * NW) y[i] = z[i];
+  __syncthreads();
+  if (tid < NB) yk[tid] = part[0][tid] + part[1][tid] + part[2][tid] + part[3][tid];
+  __syncthreads();
+  if (blockIdx.x == 0) {
+    if (tid < nb) y[r0 + tid] = yk[tid];
+    return;
+  }
+  // r_J -= L_kJ^T y_k for J = blockIdx.x - 1 < k: column c of block J gets sum_i L[r0+i][J*64+c] y_k[i]
+  const int64_t J = blockIdx.x - 1;
+  const int c = tid & 63, g = tid >> 6;
+  double s = 0.0;
+  for (int i = g * 16; i < g * 16 + 16; ++i)
+    if (i < nb) s = fma(L[(r0 + i) * n + J * NB + c], yk[i], s);
+  __syncthreads();
+  part[g][c] = s;
+  __syncthreads();
+  if (tid < NB) r[J * NB + tid] -= part[0][tid] + part[1][tid] + part[2][tid] + part[3][tid];
+}
+
+__global__ void copy_vec_kernel(const double* __restrict__ a, double* __restrict__ b, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) b[i] = a[i];
 }
 
 }  // namespace
 
-size_t trsv_lds_bytes(int64_t n, int trans) {
-  return (size_t)(n + (trans ? NW * NB : NB) + NB * LDP) * sizeof(double);
+size_t trsv_dinv_bytes(int64_t n) { return (size_t)((n + NB - 1) / NB) * NB * NB * sizeof(double); }
+
+hipError_t trsv_diag_inv(const double* L, int64_t n, double* Dinv, hipStream_t st) {
+  const int64_t nblk = (n + NB - 1) / NB;
+  hipLaunchKernelGGL(diag_inv_kernel, dim3((unsigned)nblk), dim3(64), 0, st, L, n, Dinv);
+  return hipGetLastError();
 }
 
-// The solves keep the solution vector in LDS; allow up to the full 160 KB of a CDNA4 CU.
-hipError_t trsv_prepare() {
-  const int bytes = 160 * 1024;
-  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&trsv_fwd_kernel),
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-  if (e != hipSuccess) return e;
-  return hipFuncSetAttribute(reinterpret_cast<const void*>(&trsv_bwd_kernel),
-                             hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
-}
-
-hipError_t trsv_launch(const double* L, int64_t n, int trans, const double* b, double* y, hipStream_t st) {
-  const size_t shm = trsv_lds_bytes(n, trans);
-  if (trans == 0)
-    hipLaunchKernelGGL(trsv_fwd_kernel, dim3(1), dim3(64 * NW), shm, st, L, n, b, y);
-  else
-    hipLaunchKernelGGL(trsv_bwd_kernel, dim3(1), dim3(64 * NW), shm, st, L, n, b, y);
+// y = L^-1 b (trans = 0) or L^-T b (trans = 1). work: n doubles (the reduced right-hand side).
+// b may alias y; work must not alias either.
+hipError_t trsv_launch(const double* L, const double* Dinv, int64_t n, int trans, const double* b, double* y,
+                       double* work, hipStream_t st) {
+  const int64_t nblk = (n + NB - 1) / NB;
+  hipLaunchKernelGGL(copy_vec_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, b, work, n);
+  if (trans == 0) {
+    for (int64_t k = 0; k < nblk; ++k)
+      hipLaunchKernelGGL(fwd_step_kernel, dim3((unsigned)(nblk - k)), dim3(256), 0, st, L, n, Dinv, k, work, y);
+  } else {
+    for (int64_t k = nblk - 1; k >= 0; --k)
+      hipLaunchKernelGGL(bwd_step_kernel, dim3((unsigned)(k + 1)), dim3(256), 0, st, L, n, Dinv, k, work, y);
+  }
   return hipGetLastError();
 }
 

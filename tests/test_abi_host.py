@@ -103,11 +103,6 @@ def test_invalid_arguments_rejected_on_host(dfl):
     assert "NULL" in dfl.dfisher_last_error() or dfl.dfisher_last_error() != ""
 
 
-def test_too_large_n_for_triangular_solves_is_unsupported(dfl):
-    st = ctypes.c_void_p(0)
-    assert dfl.lib.dfisher_trsv(FAKE_CTX, FAKE_DEV, 20000, 0, FAKE_DEV, FAKE_DEV, st) == dfl.DFISHER_E_UNSUPPORTED
-
-
 def test_context_on_missing_device(dfl):
     torch = pytest.importorskip("torch")
     if torch.cuda.is_available():

@@ -70,6 +70,7 @@ GRAM_SHAPES = [
     (513, 20001, 20004, "scaled"),  # 3 tile rows, ragged m and n
     (1, 777, 777, "iid"),           # single row
     (700, 3000, 3072, "iid"),       # 3 tile rows, padded stride
+    (257, 4099, 4100, "iid"),       # aligned rows, m mod 8 = 3 (tail left to the reduction), 1-row tile
 ]
 
 
@@ -97,6 +98,60 @@ def test_gram_bf16x3(dfl, ctx, oracle_mod, n, m, ld, kind):
     np.testing.assert_allclose(np.diag(W), np.diag(Wex), rtol=1e-13)
     assert scaled_err(W, W3) <= 2e-6            # same products as the split definition
     assert scaled_err(W, Wex) <= 3e-5           # within the split's 2^-16-level product error
+
+
+def decode_e4m3(codes):
+    """Values of OCP E4M3 codes (1 sign, 4 exponent bits with bias 7, 3 mantissa bits)."""
+    c = codes.astype(np.int64)
+    sign = np.where(c & 0x80, -1.0, 1.0)
+    ex = (c >> 3) & 0xF
+    mant = c & 7
+    val = np.where(ex == 0, mant * 2.0 ** -9, (1.0 + mant / 8.0) * 2.0 ** (ex - 7))
+    return sign * val
+
+
+MX_SHAPES = [(32, 1024), (300, 5000), (513, 20001), (7, 100), (257, 4160)]
+
+
+@pytest.mark.parametrize("n,m", MX_SHAPES)
+def test_quantize_mxfp8_bit_exact(dfl, ctx, oracle_mod, n, m):
+    """The device's E4M3 codes and block exponents equal the oracle's definition exactly."""
+    print(f"[quantize mxfp8] n={n} m={m}", flush=True)
+    S = synth.make_S(n, m, synth.seed(35, n), "scaled")
+    S[0, :5] = [0.0, 448.0 * 2.0 ** -20, -(2.0 ** -30), 1e-38, 3.0]   # ties, tiny and zero values
+    codes, scales, ldq = dfl.dfisher_quantize_mxfp8(ctx, dev_strided(S, (m + 3) // 4 * 4))
+    codes = codes.cpu().numpy()[:, :m]
+    e = scales.cpu().numpy().astype(np.int64)[:, :(m + 31) // 32] - 127
+    deq_ref, e_ref = oracle_mod.quant_mxfp8(S)
+    assert np.array_equal(e, e_ref)
+    deq = decode_e4m3(codes) * 2.0 ** np.repeat(e, 32, axis=1)[:, :m]
+    assert np.array_equal(deq.astype(np.float32), deq_ref)
+
+
+@pytest.mark.parametrize("n,m", MX_SHAPES)
+def test_gram_mxfp8(dfl, ctx, oracle_mod, n, m):
+    """Scaled-FP8 Gram = Gram of the dequantized S (FP32 accumulation error only); exact diagonal."""
+    print(f"[gram mxfp8] n={n} m={m}", flush=True)
+    S = synth.make_S(n, m, synth.seed(36, n), "iid")
+    W = dfl.dfisher_gram(ctx, dev_strided(S, (m + 3) // 4 * 4), dfl.DFISHER_GRAM_MXFP8, 0.0).cpu().numpy()
+    deq, _ = oracle_mod.quant_mxfp8(S)
+    m16 = m - m % 16
+    # the last m mod 16 columns are added exactly, not quantized
+    Sq = np.concatenate([deq[:, :m16], S[:, m16:]], axis=1).astype(np.float32)
+    Wq = oracle_mod.gram(Sq, 0.0)
+    Wex = oracle_mod.gram(S, 0.0)
+    np.fill_diagonal(Wq, np.diag(Wex))
+    np.testing.assert_allclose(np.diag(W), np.diag(Wex), rtol=1e-13)
+    # the FP8 matrix-core instruction sums its 64 products with ~2^-20 relative precision
+    assert scaled_err(W, Wq) <= 3e-5
+    assert scaled_err(W, Wex) <= 0.13       # the scaled-FP8 product error bound
+
+
+def test_mxfp8_rejects_unaligned_rows(dfl, ctx):
+    S = synth.make_S(8, 101, 38)
+    with pytest.raises(dfl.DfisherError) as ei:
+        dfl.dfisher_gram(ctx, dev(S), dfl.DFISHER_GRAM_MXFP8, 0.0)
+    assert ei.value.status == dfl.DFISHER_E_UNSUPPORTED
 
 
 @pytest.mark.parametrize("n", [1, 5, 64, 65, 130, 1000])
@@ -188,6 +243,9 @@ SOLVE_CASES = [
     (257, 30000, 1e-3, 0, 1, "scaled", 1e-6),   # row-space-heavy v (cancellation in v - S^T y)
     (257, 30000, 1e-3, 1, 2, "scaled", 1e-6),
     (600, 12000, 1e-4, 0, 2, "iid", 1e-6),
+    (300, 20000, 1e-2, 2, 2, "iid", 1e-6),      # scaled-FP8 Gram + refinement
+    (300, 20000, 1e-6, 2, 3, "iid", 1e-6),
+    (257, 30000, 1e-3, 2, 3, "iid", 1e-6),
 ]
 
 
@@ -197,13 +255,15 @@ def test_solve(dfl, ctx, oracle_mod, n, m, lam, prec, sweeps, kind, bound):
     S = synth.make_S(n, m, synth.seed(26, n), kind)
     v = synth.make_v(S, synth.seed(26, n), kind)
     xref = oracle_mod.solve(S, v, lam)
-    x, info = dfl.dfisher_solve(ctx, dev(S), dev(v), lam, gram_prec=prec, sweeps=sweeps, x_fp64=True)
+    policy = dfl.DFISHER_SHIFT_ALWAYS if prec == 2 else dfl.DFISHER_SHIFT_ON_FAILURE
+    x, info = dfl.dfisher_solve(ctx, dev(S), dev(v), lam, gram_prec=prec, sweeps=sweeps, shift_policy=policy,
+                                x_fp64=True)
     err = rel(x.cpu().numpy(), xref)
     print(f"    rel err {err:.3e}  info {info}", flush=True)
     assert info["sweeps_done"] == sweeps
     assert err <= bound
     # FP32 output: the same solution rounded once
-    x32, _ = dfl.dfisher_solve(ctx, dev(S), dev(v), lam, gram_prec=prec, sweeps=sweeps)
+    x32, _ = dfl.dfisher_solve(ctx, dev(S), dev(v), lam, gram_prec=prec, sweeps=sweeps, shift_policy=policy)
     assert rel(x32.cpu().numpy(), xref) <= bound + 2.0 ** -23
 
 
@@ -276,6 +336,21 @@ def test_uneven(dfl, ctx, oracle_mod):
         err = rel(xs[p].cpu().numpy(), oracle_mod.solve(S, v, lam))
         print(f"    problem {p} rel err {err:.3e}", flush=True)
         assert err <= 1e-6
+
+
+def test_shift_always_contracts(dfl, ctx, oracle_mod):
+    """With the up-front shift every sweep shrinks the error (the factored matrix dominates W)."""
+    S = synth.make_S(300, 20000, 37)
+    v = synth.make_v(S, 37)
+    xref = oracle_mod.solve(S, v, 1e-6)
+    errs = []
+    for sweeps in range(3):
+        x, info = dfl.dfisher_solve(ctx, dev(S), dev(v), 1e-6, gram_prec=2, sweeps=sweeps,
+                                    shift_policy=dfl.DFISHER_SHIFT_ALWAYS, x_fp64=True)
+        errs.append(rel(x.cpu().numpy(), xref))
+        assert info["shift"] > 0 and info["attempts"] == 1
+    print(f"    errors by sweep {errs}", flush=True)
+    assert errs[1] < errs[0] and errs[2] <= max(errs[1], 1e-12) * 1.01
 
 
 def test_nan_input_reports_not_spd(dfl, ctx):
