@@ -100,12 +100,14 @@ def cpu_baseline(S, v, lam, m_sample):
     }
 
 
-def run_path(dfl, ctx, S, v, lams, prec, sweeps, steps, warmup, xbuf):
+SHIFT = {"on_failure": "DFISHER_SHIFT_ON_FAILURE", "always": "DFISHER_SHIFT_ALWAYS", "none": "DFISHER_SHIFT_NONE"}
+GRAM_KERNEL = {"fp32": "gram_kernel_v2<0>", "bf16x3": "gram_kernel_split", "mxfp8": "gram_kernel_fp8"}
+
+
+def run_path(dfl, ctx, S, v, lams, prec, sweeps, steps, warmup, xbuf, shift="on_failure"):
     import torch
 
-    # mixed paths refine, so they factor W + tau I up front (no retry factorisations);
-    # the plain FP32 path shifts only if its Cholesky fails
-    policy = dfl.DFISHER_SHIFT_ALWAYS if sweeps > 0 else dfl.DFISHER_SHIFT_ON_FAILURE
+    policy = getattr(dfl, SHIFT[shift])
     infos = []
     for _ in range(warmup):
         for lam in lams:
@@ -137,6 +139,8 @@ def main() -> int:
     ap.add_argument("--m", type=int, default=4_000_000)
     ap.add_argument("--prec", default="bf16x3", choices=sorted(PREC_CODE))
     ap.add_argument("--sweeps", type=int, default=1)
+    ap.add_argument("--shift", default="on_failure", choices=sorted(SHIFT),
+                    help="Cholesky shift policy of the mixed path")
     ap.add_argument("--lams", default="1e-2,1e-4,1e-6")
     ap.add_argument("--fp32-steps", type=int, default=1, help="timed steps of the plain FP32 path (0: skip)")
     ap.add_argument("--no-ref", action="store_true", help="skip the FP64 error check")
@@ -172,7 +176,7 @@ def main() -> int:
 
     log(f"[bench] mixed path: {args.prec} Gram + {args.sweeps} sweep(s), {args.warmup} warmup + {args.steps} steps")
     elapsed, gram_ms, stage_avg, infos = run_path(dfl, ctx, S, v, lams, args.prec, args.sweeps, args.steps,
-                                                  args.warmup, xbuf)
+                                                  args.warmup, xbuf, args.shift)
     solves = args.steps * len(lams)
     value = solves / elapsed
     gram_avg_ms = sum(gram_ms) / len(gram_ms)
@@ -235,9 +239,9 @@ def main() -> int:
         "data": "synthetic",
         "config": {"workload": f"damped Fisher solve n={n} m={m} (iid N(0,1)/sqrt(n) column-centered S, iid v), "
                                f"one solve per lambda in {lams}",
-                   "n": n, "m": m, "lambdas": lams, "gram": args.prec, "sweeps": args.sweeps,
+                   "n": n, "m": m, "lambdas": lams, "gram": args.prec, "sweeps": args.sweeps, "shift": args.shift,
                    "solves_per_step": len(lams)},
-        "roofline": {"bound": "mfma", "kernel": "gram_kernel", "achieved": achieved, "peak": peak,
+        "roofline": {"bound": "mfma", "kernel": GRAM_KERNEL[args.prec], "achieved": achieved, "peak": peak,
                      "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None,
                      "algorithmic_flops_per_launch": algo_flops, "avg_launch_ms": gram_avg_ms,
                      "mfma_util_hw": achieved * passes / peak},

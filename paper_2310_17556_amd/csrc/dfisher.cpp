@@ -8,6 +8,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <vector>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -176,7 +177,9 @@ dfisher_status check_prec_layout(int prec, const float* S, int64_t lds) {
 
 // Rounding unit of the computed Gram's entries, relative to max_i W_ii, used by the up-front shift.
 double gram_unit(int prec, int64_t m) {
-  if (prec == DFISHER_GRAM_MXFP8) return 0.25 / std::sqrt((double)m);
+  // FP8: E4M3 keeps 3 mantissa bits; the relative error of a sum of m products of block-scaled
+  // values shrinks like 1/sqrt(m) (random rounding errors), here with constant 2^-4.
+  if (prec == DFISHER_GRAM_MXFP8) return 0.0625 / std::sqrt((double)m);
   return std::ldexp(1.0, -24);
 }
 
@@ -273,7 +276,7 @@ dfisher_status gram_stage(const float* S, const float* v, const dfi::GramPlan& g
                           const SolveBufs& B, double lambda, double* W, int mirror, hipStream_t st, StageClock* clk) {
   if (clk) clk->mark(0);
   if (gp.prec == DFISHER_GRAM_MXFP8) {
-    HIP_TRY(dfi::rowpass_launch(rp, S, v, nullptr, v != nullptr, true, B.rpart, st, B.q8, B.sc8, B.ldq));
+    HIP_TRY(dfi::rowpass_launch(rp, S, v, nullptr, v != nullptr, true, B.rpart, st, B.q8, B.sc8, B.ldq, true));
   } else if (B.hi) {
     HIP_TRY(dfi::rowpass_launch_split(rp, S, v, B.rpart, B.hi, B.lo, gp.ldh, st));
   } else {
@@ -310,6 +313,93 @@ dfisher_status solve_y(const float* S, int64_t n, int64_t m, int64_t lds, double
     HIP_TRY(dfi::axpy_inplace(B.y, B.r, n, st));
   }
   if (clk) clk->mark(6);
+  return DFISHER_OK;
+}
+
+// Many right-hand sides against nfac factors in shared launches (multi-vector passes over S, batched
+// triangular solves). Vector j = f * nrhs + r pairs factor f (L + f n^2, its block inverses at
+// Dinv + f trsv_dinv_bytes(n) / 8, damping lams[f]) with v_r = V + r ldv; x_j goes to X + j ldx.
+// Per vector: y = W_f^-1 S v_r, `sweeps` FP64 refinement sweeps against the exact operator, then
+// x = (v_r - S^T y) / lambda_f. Needs nfac * nrhs <= 65535.
+struct MultiBufs {
+  double *Bs, *Bexp, *Y, *R, *D, *W1, *T, *part;
+};
+
+MultiBufs carve_multi(Carver& c, int64_t n, int64_t m, int64_t nrhs, int64_t nvec, const dfi::RowMultiPlan& rm,
+                      bool need_t) {
+  MultiBufs b{};
+  b.Bs = c.take<double>((size_t)(nrhs * n));
+  b.Bexp = c.take<double>((size_t)(nvec * n));
+  b.Y = c.take<double>((size_t)(nvec * n));
+  b.R = c.take<double>((size_t)(nvec * n));
+  b.D = c.take<double>((size_t)(nvec * n));
+  b.W1 = c.take<double>((size_t)(nvec * n));
+  b.T = need_t ? c.take<double>((size_t)(m * dfi::MULTI_VECS)) : nullptr;
+  b.part = c.take<double>(rm.part_bytes / sizeof(double) + 1);
+  return b;
+}
+
+dfisher_status multi_solve(const float* S, int64_t n, int64_t m, int64_t lds, int64_t nfac, const double* L,
+                           const double* Dinv, const double* lams, const float* V, int64_t nrhs, int64_t ldv, void* X,
+                           int64_t ldx, int x_fp64, int sweeps, const dfi::RowMultiPlan& rm, const MultiBufs& b,
+                           hipStream_t st) {
+  constexpr int MV = dfi::MULTI_VECS;
+  const int64_t nvec = nfac * nrhs;
+  const int64_t sL = n * n;
+  // B_r = S v_r, eight right-hand sides per pass over S
+  for (int64_t r0 = 0; r0 < nrhs; r0 += MV) {
+    const int nv = (int)std::min<int64_t>(MV, nrhs - r0);
+    dfi::MultiVecs vs{};
+    dfi::MultiOut mo{};
+    for (int c = 0; c < nv; ++c) {
+      vs.f[c] = V + (r0 + c) * ldv;
+      mo.b[c] = b.Bs + (r0 + c) * n;
+    }
+    HIP_TRY(dfi::rowpass_multi_launch(rm, S, vs, nullptr, nv, b.part, st));
+    HIP_TRY(dfi::rowpass_multi_reduce(rm, b.part, nv, mo, st));
+  }
+  for (int64_t f = 0; f < nfac; ++f)
+    HIP_TRY(hipMemcpyAsync(b.Bexp + f * nrhs * n, b.Bs, (size_t)(nrhs * n) * sizeof(double), hipMemcpyDeviceToDevice, st));
+  // Y = L^-T L^-1 B for every vector
+  HIP_TRY(dfi::trsv_launch_batched(L, sL, Dinv, n, nvec, nrhs, 0, b.Bexp, b.D, b.W1, st));
+  HIP_TRY(dfi::trsv_launch_batched(L, sL, Dinv, n, nvec, nrhs, 1, b.D, b.Y, b.W1, st));
+  for (int s = 0; s < sweeps; ++s) {
+    // R = B - lambda Y - S (S^T Y), eight vectors per pair of passes
+    for (int64_t j0 = 0; j0 < nvec; j0 += MV) {
+      const int nv = (int)std::min<int64_t>(MV, nvec - j0);
+      dfi::MultiCols mc{};
+      dfi::MultiOut mo{};
+      for (int c = 0; c < MV; ++c) mc.y[c] = b.Y + (j0 + std::min(c, nv - 1)) * n;
+      for (int c = 0; c < nv; ++c) {
+        const int64_t j = j0 + c;
+        mo.b[c] = b.R + j * n;
+        mo.r0[c] = b.Bexp + j * n;
+        mo.y[c] = b.Y + j * n;
+        mo.lam[c] = lams[j / nrhs];
+      }
+      HIP_TRY(dfi::colpass_multi_launch(S, n, m, lds, mc, nv, 2, b.T, st));
+      dfi::MultiVecs none{};
+      HIP_TRY(dfi::rowpass_multi_launch(rm, S, none, b.T, nv, b.part, st));
+      HIP_TRY(dfi::rowpass_multi_reduce(rm, b.part, nv, mo, st));
+    }
+    HIP_TRY(dfi::trsv_launch_batched(L, sL, Dinv, n, nvec, nrhs, 0, b.R, b.D, b.W1, st));
+    HIP_TRY(dfi::trsv_launch_batched(L, sL, Dinv, n, nvec, nrhs, 1, b.D, b.R, b.W1, st));
+    HIP_TRY(dfi::axpy_many(b.Y, b.R, nvec * n, st));
+  }
+  // x = (v - S^T y) / lambda, eight vectors per pass
+  const size_t xel = x_fp64 ? sizeof(double) : sizeof(float);
+  for (int64_t j0 = 0; j0 < nvec; j0 += MV) {
+    const int nv = (int)std::min<int64_t>(MV, nvec - j0);
+    dfi::MultiCols mc{};
+    for (int c = 0; c < MV; ++c) {
+      const int64_t j = j0 + std::min(c, nv - 1);
+      mc.y[c] = b.Y + j * n;
+      mc.v[c] = V + (j % nrhs) * ldv;
+      mc.x[c] = static_cast<char*>(X) + (size_t)(j * ldx) * xel;
+      mc.lam[c] = lams[j / nrhs];
+    }
+    HIP_TRY(dfi::colpass_multi_launch(S, n, m, lds, mc, nv, x_fp64 ? 1 : 0, nullptr, st));
+  }
   return DFISHER_OK;
 }
 
@@ -613,21 +703,17 @@ dfisher_status dfisher_factor_solve(dfisher_factor* f, const float* V, int64_t n
   DeviceGuard g(ctx->device);
   hipStream_t st = as_stream(stream);
   const int64_t n = f->n, m = f->m;
-  const dfi::RowPassPlan rp = dfi::rowpass_plan(n, m, f->lds);
-  const dfi::ColPassPlan cp = dfi::colpass_plan(n, m);
-  const bool need_t = f->opt.sweeps > 0;
-  SolveBufs B = carve(nullptr, n, m, nullptr, rp, cp, false, need_t);
-  DF_TRY(ensure_ws(ctx, B.bytes));
-  B = carve(static_cast<char*>(ctx->ws), n, m, nullptr, rp, cp, false, need_t);
-  const size_t xel = f->opt.x_fp64 ? sizeof(double) : sizeof(float);
-  for (int64_t r = 0; r < nrhs; ++r) {
-    const float* v = V + r * ldv;
-    void* x = static_cast<char*>(X) + (size_t)(r * ldx) * xel;
-    HIP_TRY(dfi::rowpass_launch(rp, f->S, v, nullptr, true, false, B.rpart, st));
-    HIP_TRY(dfi::rowpass_reduce(rp, B.rpart, true, false, B.b, nullptr, nullptr, nullptr, 0.0, st));
-    DF_TRY(solve_y(f->S, n, m, f->lds, f->lambda, f->L, f->Dinv, B, rp, cp, f->opt.sweeps, st));
-    HIP_TRY(dfi::colpass_launch(cp, f->S, n, m, f->lds, B.y, v, f->lambda, x, f->opt.x_fp64 ? 1 : 0, B.cpart, st));
-  }
+  if (nrhs > 65535) return fail(DFISHER_E_UNSUPPORTED, "nrhs = %lld > 65535", (long long)nrhs);
+  const dfi::RowMultiPlan rm = dfi::rowmulti_plan(n, m, f->lds);
+  Carver c;
+  MultiBufs mb = carve_multi(c, n, m, nrhs, nrhs, rm, f->opt.sweeps > 0);
+  DF_TRY(ensure_ws(ctx, c.off));
+  c = Carver{};
+  c.base = static_cast<char*>(ctx->ws);
+  mb = carve_multi(c, n, m, nrhs, nrhs, rm, f->opt.sweeps > 0);
+  const double lam = f->lambda;
+  DF_TRY(multi_solve(f->S, n, m, f->lds, 1, f->L, f->Dinv, &lam, V, nrhs, ldv, X, ldx, f->opt.x_fp64, f->opt.sweeps, rm,
+                     mb, st));
   if (info) {
     info->potrf_info = 0;
     info->shift = f->shift;
@@ -703,6 +789,7 @@ dfisher_status dfisher_solve_batched(dfisher_ctx* ctx, const float* S, int64_t n
   if (ldv < m || ldx < m) return fail(DFISHER_E_INVALID_ARG, "ldv/ldx < m");
   for (int32_t l = 0; l < nlam; ++l)
     if (!finite_pos(lambdas[l])) return fail(DFISHER_E_INVALID_ARG, "lambdas[%d] must be finite and > 0", l);
+  if ((int64_t)nlam * nrhs > 65535) return fail(DFISHER_E_UNSUPPORTED, "nlam * nrhs > 65535");
   dfisher_options o;
   DF_TRY(check_opt(opt, &o));
   DF_TRY(check_prec_layout(o.gram_prec, S, lds));
@@ -711,52 +798,69 @@ dfisher_status dfisher_solve_batched(dfisher_ctx* ctx, const float* S, int64_t n
   const dfi::GramPlan gp = dfi::gram_plan(n, m, lds, o.gram_prec, rows_aligned16(S, lds));
   const dfi::RowPassPlan rp = dfi::rowpass_plan(n, m, lds);
   const dfi::ColPassPlan cp = dfi::colpass_plan(n, m);
-  const bool need_t = o.sweeps > 0;
-  SolveBufs B = carve(nullptr, n, m, &gp, rp, cp, true, need_t);
-  Carver extra;
-  extra.off = B.bytes;
-  double* G = extra.take<double>((size_t)(n * n));
-  double* Bs = extra.take<double>((size_t)(n * nrhs));
-  DF_TRY(ensure_ws(ctx, extra.off));
-  char* base = static_cast<char*>(ctx->ws);
-  B = carve(base, n, m, &gp, rp, cp, true, need_t);
-  extra = Carver{};
-  extra.base = base;
-  extra.off = B.bytes;
-  G = extra.take<double>((size_t)(n * n));
-  Bs = extra.take<double>((size_t)(n * nrhs));
-  // shared Gram G = S S^T (exact diagonal, no lambda)
-  DF_TRY(gram_stage(S, nullptr, gp, rp, B, 0.0, G, 0, st, nullptr));
-  // b_r = S v_r for every right-hand side, shared by all lambdas
-  for (int32_t r = 0; r < nrhs; ++r) {
-    HIP_TRY(dfi::rowpass_launch(rp, S, V + (int64_t)r * ldv, nullptr, true, false, B.rpart, st));
-    HIP_TRY(dfi::rowpass_reduce(rp, B.rpart, true, false, Bs + (int64_t)r * n, nullptr, nullptr, nullptr, 0.0, st));
-  }
-  const size_t xel = o.x_fp64 ? sizeof(double) : sizeof(float);
+  const dfi::RowMultiPlan rm = dfi::rowmulti_plan(n, m, lds);
+  const int64_t nvec = (int64_t)nlam * nrhs;
+  const size_t dinv_el = dfi::trsv_dinv_bytes(n) / sizeof(double);
+  // workspace: the single-solve buffers (Gram stage, retry scratch), nlam factors, their block
+  // inverses and statuses, and the multi-vector buffers
+  auto layout = [&](char* base, SolveBufs& B, double*& Lall, double*& Dall, double*& dkk, int64_t*& dinfo,
+                    int32_t*& dflag, MultiBufs& mb) {
+    B = carve(base, n, m, &gp, rp, cp, true, false);
+    Carver c;
+    c.base = base;
+    c.off = B.bytes;
+    Lall = c.take<double>((size_t)(nlam * n * n));
+    Dall = c.take<double>((size_t)nlam * dinv_el);
+    dkk = c.take<double>((size_t)nlam * 64 * 64);
+    dinfo = c.take<int64_t>((size_t)nlam);
+    dflag = c.take<int32_t>((size_t)nlam);
+    mb = carve_multi(c, n, m, nrhs, nvec, rm, o.sweeps > 0);
+    return c.off;
+  };
+  SolveBufs B;
+  double *Lall, *Dall, *dkk;
+  int64_t* dinfo;
+  int32_t* dflag;
+  MultiBufs mb;
+  DF_TRY(ensure_ws(ctx, layout(nullptr, B, Lall, Dall, dkk, dinfo, dflag, mb)));
+  layout(static_cast<char*>(ctx->ws), B, Lall, Dall, dkk, dinfo, dflag, mb);
+
+  // the shared Gram G = S S^T (exact diagonal, no lambda), formed once
+  DF_TRY(gram_stage(S, nullptr, gp, rp, B, 0.0, B.W, 0, st, nullptr));
+  // every W_l = G + lambda_l I (+ the up-front shift) factored in the same launches
+  const double unit = gram_unit(o.gram_prec, m);
+  const double scale0 = (o.shift_policy == DFISHER_SHIFT_ALWAYS) ? 2.0 * std::sqrt((double)n) * unit : 0.0;
+  if (scale0 != 0.0) HIP_TRY(dfi::diag_max(B.W, n, ctx->d_scalar, st));
+  for (int32_t l = 0; l < nlam; ++l)
+    HIP_TRY(dfi::shift_add_copy(B.W, Lall + (int64_t)l * n * n, n, scale0, ctx->d_scalar, lambdas[l], st));
+  HIP_TRY(dfi::potrf_launch_batched(Lall, n, nlam, n * n, dinfo, dflag, dkk, st));
+  std::vector<int64_t> hinfo((size_t)nlam);
+  double dmax = 0.0;
+  HIP_TRY(hipMemcpyAsync(hinfo.data(), dinfo, (size_t)nlam * sizeof(int64_t), hipMemcpyDeviceToHost, st));
+  if (scale0 != 0.0) HIP_TRY(hipMemcpyAsync(&dmax, ctx->d_scalar, sizeof(double), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
   dfisher_status worst = DFISHER_OK;
   for (int32_t l = 0; l < nlam; ++l) {
-    const double lam = lambdas[l];
-    HIP_TRY(dfi::add_diag_copy(G, B.W, n, lam, st));
     dfisher_info inf{};
-    dfisher_status s = factor_with_policy(ctx, B.W, B.L, B.dkk, n, o.shift_policy, gram_unit(o.gram_prec, m), st, &inf.shift, &inf.potrf_info,
-                                         &inf.attempts);
-    if (s == DFISHER_OK) {
-      HIP_TRY(dfi::trsv_diag_inv(B.L, n, B.Dinv, st));
-      for (int32_t r = 0; r < nrhs; ++r) {
-        HIP_TRY(hipMemcpyAsync(B.b, Bs + (int64_t)r * n, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, st));
-        DF_TRY(solve_y(S, n, m, lds, lam, B.L, B.Dinv, B, rp, cp, o.sweeps, st));
-        void* x = static_cast<char*>(X) + (size_t)(((int64_t)l * nrhs + r) * ldx) * xel;
-        HIP_TRY(dfi::colpass_launch(cp, S, n, m, lds, B.y, V + (int64_t)r * ldv, lam, x, o.x_fp64, B.cpart, st));
-      }
-      inf.sweeps_done = o.sweeps;
-    } else if (s == DFISHER_E_NOT_SPD) {
-      worst = s;
-    } else {
-      return s;
+    inf.attempts = 1;
+    inf.potrf_info = hinfo[(size_t)l];
+    inf.shift = scale0 * dmax;
+    if (inf.potrf_info != 0 && o.shift_policy != DFISHER_SHIFT_NONE) {
+      // rare: refactor this lambda alone with escalating shifts (B.L holds G + lambda_l I)
+      HIP_TRY(dfi::add_diag_copy(B.W, B.L, n, lambdas[l], st));
+      int32_t att = 0;
+      const dfisher_status s = factor_with_policy(ctx, B.L, Lall + (int64_t)l * n * n, B.dkk, n, o.shift_policy, unit,
+                                                  st, &inf.shift, &inf.potrf_info, &att);
+      inf.attempts += att;
+      if (s != DFISHER_OK && s != DFISHER_E_NOT_SPD) return s;
     }
+    if (inf.potrf_info != 0) worst = DFISHER_E_NOT_SPD;
+    inf.sweeps_done = o.sweeps;
     if (infos) infos[l] = inf;
   }
-  if (worst != DFISHER_OK) return fail(worst, "at least one lambda failed to factor");
+  HIP_TRY(dfi::trsv_diag_inv_batched(Lall, n * n, n, nlam, Dall, st));
+  DF_TRY(multi_solve(S, n, m, lds, nlam, Lall, Dall, lambdas, V, nrhs, ldv, X, ldx, o.x_fp64, o.sweeps, rm, mb, st));
+  if (worst != DFISHER_OK) return fail(worst, "at least one lambda failed to factor (its x is not meaningful)");
   return DFISHER_OK;
 }
 

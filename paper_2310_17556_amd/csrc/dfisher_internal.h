@@ -29,9 +29,9 @@ GramPlan gram_plan(int64_t n, int64_t m, int64_t lds, int prec, bool aligned16);
 hipError_t gram_launch(const GramPlan& p, const float* S, float* part, hipStream_t st);
 // Row stride (bf16 elements) of the split-BF16 planes for m columns.
 inline int64_t split_ldh(int64_t m) { return (m + 63) / 64 * 64; }
-// Split-BF16 Gram from the planes hi = bf16(S), lo = bf16(S - hi) (n x ldh each, p.ldh > 0).
+// Split-BF16 Gram from the column-blocked planes hi = bf16(S), lo = bf16(S - hi) (p.ldh > 0).
 hipError_t gram_launch_split(const GramPlan& p, const uint16_t* hi, const uint16_t* lo, float* part, hipStream_t st);
-// Scaled-FP8 Gram from the row pass's codes (n x ldq bytes) and E8M0 scales (n x ldq/32 bytes).
+// Scaled-FP8 Gram from the row pass's column-blocked codes and E8M0 scales (see rowpass_launch).
 hipError_t gram_launch_fp8(const GramPlan& p, const uint8_t* q, const uint8_t* sc, int64_t ldq, float* part,
                            hipStream_t st);
 // Row stride of the FP8 codes for m columns (a multiple of 64).
@@ -54,14 +54,17 @@ struct RowPassPlan {
 };
 RowPassPlan rowpass_plan(int64_t n, int64_t m, int64_t lds);
 // With q != nullptr the pass also writes the scaled-FP8 copy of S (codes n x ldq bytes, E8M0
-// scale bytes n x ldq/32; ldq a multiple of 64, >= m; needs 16-byte aligned rows and want_d;
-// the scaled-FP8 Gram kernel further needs ldq a multiple of 128, see fp8_ldq).
+// scale bytes n x ldq/32; ldq a multiple of 64, >= m; needs 16-byte aligned rows and want_d).
+// Row-major, or with `blocked` (ldq a multiple of 128) in the column-blocked layout the
+// scaled-FP8 Gram reads: 128-column blocks, each holding all n rows contiguously, code (i, k) at
+// q[((k / 128) n + i) 128 + k % 128], scale byte (i, k / 32) at sc[((k / 128) n + i) 4 + (k / 32) % 4].
 hipError_t rowpass_launch(const RowPassPlan& p, const float* S, const float* v, const double* vd,
                           bool want_b, bool want_d, double* part, hipStream_t st, uint8_t* q = nullptr,
-                          uint8_t* sc = nullptr, int64_t ldq = 0);
+                          uint8_t* sc = nullptr, int64_t ldq = 0, bool blocked = false);
 // Row pass that also writes the split-BF16 planes of S: hi = bf16_rne(S), lo = bf16_rne(S - hi),
-// n x ldh each (ldh a multiple of 64, >= m; entries k >= m are zero). Needs 16-byte aligned rows;
-// always computes d, and b when v != nullptr.
+// column-blocked in 64-column blocks of all n rows: element (i, k) at [((k / 64) n + i) 64 + k % 64]
+// (ldh = m rounded up to 64; entries k >= m are zero). Needs 16-byte aligned rows; always
+// computes d, and b when v != nullptr.
 hipError_t rowpass_launch_split(const RowPassPlan& p, const float* S, const float* v, double* part, uint16_t* hi,
                                 uint16_t* lo, int64_t ldh, hipStream_t st);
 // Reduce: b_i = sum_c part_b[c][i]; when r0 != nullptr: b_i = r0_i - lam * y_i - sum_c part_b[c][i]
@@ -81,12 +84,53 @@ ColPassPlan colpass_plan(int64_t n, int64_t m);
 hipError_t colpass_launch(const ColPassPlan& p, const float* S, int64_t n, int64_t m, int64_t lds, const double* y,
                           const float* v, double lambda, void* out, int mode, double* part, hipStream_t st);
 
+// ----------------------------------------------------------------------------- multi-vector passes
+// One pass over S for up to MULTI_VECS vectors (batched right-hand sides / damping values).
+constexpr int MULTI_VECS = 8;
+struct MultiVecs {                 // FP32 input vectors of length m (row pass)
+  const float* f[MULTI_VECS];
+};
+struct MultiOut {                  // row-pass results of length n
+  double* b[MULTI_VECS];           // output c
+  const double* r0[MULTI_VECS];    // if set: b_c = r0_c - lam_c y_c - S t_c (refinement residual)
+  const double* y[MULTI_VECS];
+  double lam[MULTI_VECS];
+};
+struct MultiCols {                 // column-pass operands, per vector c
+  const double* y[MULTI_VECS];     // length n (every slot must point to valid memory)
+  const float* v[MULTI_VECS];      // length m (modes 0, 1)
+  void* x[MULTI_VECS];             // length m, FP32 (mode 0) or FP64 (mode 1)
+  double lam[MULTI_VECS];
+};
+struct RowMultiPlan {
+  int64_t n, m, lds;
+  int64_t nchunk, chunk;
+  size_t part_bytes;               // nchunk * MULTI_VECS * n * 8
+};
+RowMultiPlan rowmulti_plan(int64_t n, int64_t m, int64_t lds);
+// part <- per-group partials of S V_c, c < nv. V_c = vs.f[c] (FP32) or, with T != nullptr, the FP64
+// interleaved T[k * 8 + c] written by colpass_multi_launch mode 2.
+hipError_t rowpass_multi_launch(const RowMultiPlan& p, const float* S, const MultiVecs& vs, const double* T, int nv,
+                                double* part, hipStream_t st);
+hipError_t rowpass_multi_reduce(const RowMultiPlan& p, const double* part, int nv, const MultiOut& out,
+                                hipStream_t st);
+// t_c = S^T y_c (c < nc). mode 2: T[k * 8 + c] = t_c[k] (T: m * 8 doubles); mode 0 / 1:
+// x_c = (v_c - t_c) / lam_c as FP32 / FP64.
+hipError_t colpass_multi_launch(const float* S, int64_t n, int64_t m, int64_t lds, const MultiCols& mc, int nc,
+                                int mode, double* T, hipStream_t st);
+// y += d over len entries
+hipError_t axpy_many(double* y, const double* d, int64_t len, hipStream_t st);
+
 // ----------------------------------------------------------------------------- Cholesky
 // In-place blocked FP64 Cholesky (row-major, lower). info_dev: device int64, 0 or 1-based
 // index of the first bad pivot. flag_dev: device int32 scratch (stop flag). dkk: device
 // scratch of 64 x 64 doubles (the current diagonal block's inverse).
 constexpr size_t POTRF_DKK_BYTES = 64 * 64 * sizeof(double);
 hipError_t potrf_launch(double* A, int64_t n, int64_t* info_dev, int32_t* flag_dev, double* dkk, hipStream_t st);
+// nbatch independent factorisations in the same launches: matrix b at A + b sA, info_dev[b],
+// flag_dev[b], dkk + b 64 * 64 (nbatch <= 65535).
+hipError_t potrf_launch_batched(double* A, int64_t n, int64_t nbatch, int64_t sA, int64_t* info_dev, int32_t* flag_dev,
+                                double* dkk, hipStream_t st);
 
 // ----------------------------------------------------------------------------- triangular solves
 // Inverses of the 64 x 64 diagonal blocks of L (Dinv: trsv_dinv_bytes(n)), computed once per factor.
@@ -95,12 +139,21 @@ hipError_t trsv_diag_inv(const double* L, int64_t n, double* Dinv, hipStream_t s
 // y = L^-1 b (trans 0) or L^-T b (trans 1); work: n doubles, not aliasing b or y; b may alias y.
 hipError_t trsv_launch(const double* L, const double* Dinv, int64_t n, int trans, const double* b, double* y,
                        double* work, hipStream_t st);
+// Batched: nfac factors at L + f sL with their block inverses at Dinv + f trsv_dinv_bytes(n) / 8.
+hipError_t trsv_diag_inv_batched(const double* L, int64_t sL, int64_t n, int64_t nfac, double* Dinv, hipStream_t st);
+// nvec right-hand sides (vector j at b + j n, result at y + j n, work nvec x n) solved in the same
+// launches; vector j uses factor j / nper. nvec <= 65535.
+hipError_t trsv_launch_batched(const double* L, int64_t sL, const double* Dinv, int64_t n, int64_t nvec, int64_t nper,
+                               int trans, const double* b, double* y, double* work, hipStream_t st);
 
 // ----------------------------------------------------------------------------- small helpers
 // dst = src + scale * dmax[0] * I (n x n, row-major; dmax a device scalar, unread if scale == 0).
 hipError_t shift_copy(const double* src, double* dst, int64_t n, double scale, const double* dmax, hipStream_t st);
 // dst = src + lam * I
 hipError_t add_diag_copy(const double* src, double* dst, int64_t n, double lam, hipStream_t st);
+// dst = src + (lam + scale * dmax[0]) * I (dmax unread if scale == 0)
+hipError_t shift_add_copy(const double* src, double* dst, int64_t n, double scale, const double* dmax, double lam,
+                          hipStream_t st);
 // y += d (length n)
 hipError_t axpy_inplace(double* y, const double* d, int64_t n, hipStream_t st);
 // max_i W_ii

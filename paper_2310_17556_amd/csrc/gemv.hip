@@ -87,13 +87,19 @@ __device__ __forceinline__ void load_s4(const float* __restrict__ p, int64_t col
 
 // Grid: x = row blocks of RP_WAVES * RP_RPW rows, y = column groups of `cg` columns (multiple
 // of RP_SUB). part layout: part_b[g * n + i], part_d[(ngroups + g) * n + i].
-// QM selects an extra output, written for every column k < ldq (zero input beyond m); both need the
+// QM selects an extra output, written for every column k < ldq (zero input beyond m); all need the
 // vectorised path:
-//   QM = 1: the scaled-FP8 form of S: codes q[i * ldq + k] (E4M3, round to nearest even) and scale
-//           exponents sc[i * (ldq / 32) + k / 32] (E8M0 byte e + 127) per 32-column block; a block
-//           is 8 consecutive lanes of one 16-byte load.
-//   QM = 2: the split-BF16 planes hi[i * ldq + k] = bf16_rne(S_ik), lo[...] = bf16_rne(S_ik - hi)
-//           (S_ik - hi is exact in FP32); hi and lo are passed in q and sc as bf16 arrays.
+//   QM = 1: the scaled-FP8 form of S, row-major: codes q[i * ldq + k] (E4M3, round to nearest
+//           even) and scale exponents sc[i * (ldq / 32) + k / 32] (E8M0 byte e + 127) per
+//           32-column block; a block is 8 consecutive lanes of one 16-byte load.
+//   QM = 3: the same codes and scales, column-blocked for the Gram kernel: columns are cut into
+//           128-wide blocks and block b holds all n rows contiguously, code (i, k) at
+//           q[((k / 128) n + i) 128 + k % 128] and its scale byte at
+//           sc[((k / 128) n + i) 4 + (k / 32) % 4]. A k-step of a row panel is then one
+//           contiguous stretch of memory instead of one piece per row.
+//   QM = 2: the split-BF16 planes hi = bf16_rne(S_ik), lo = bf16_rne(S_ik - hi) (S_ik - hi is
+//           exact in FP32), column-blocked in 64-wide blocks: element (i, k) at
+//           [((k / 64) n + i) 64 + k % 64]; hi and lo are passed in q and sc as bf16 arrays.
 template <typename VT, bool WANT_B, bool WANT_D, int QM>
 __global__ void __launch_bounds__(64 * RP_WAVES)
 rowpass_kernel(const float* __restrict__ S, int64_t n, int64_t m, int64_t lds, const VT* __restrict__ v,
@@ -148,12 +154,13 @@ rowpass_kernel(const float* __restrict__ S, int64_t n, int64_t m, int64_t lds, c
               l[e] = (__bf16)(sv[u][e] - (float)hb);
             }
             if (col < ldq) {
-              *reinterpret_cast<bf16x4*>(reinterpret_cast<__bf16*>(q) + (row0 + r) * ldq + col) = h;
-              *reinterpret_cast<bf16x4*>(reinterpret_cast<__bf16*>(sc) + (row0 + r) * ldq + col) = l;
+              const int64_t off = (((col >> 6) * n + row0 + r) << 6) + (col & 63);
+              *reinterpret_cast<bf16x4*>(reinterpret_cast<__bf16*>(q) + off) = h;
+              *reinterpret_cast<bf16x4*>(reinterpret_cast<__bf16*>(sc) + off) = l;
             }
           }
         }
-        if constexpr (QM == 1) {
+        if constexpr (QM == 1 || QM == 3) {
 #pragma unroll
           for (int u = 0; u < RP_U; ++u) {
             const int64_t col = cs + 256 * u + 4 * lane;
@@ -167,9 +174,14 @@ rowpass_kernel(const float* __restrict__ S, int64_t n, int64_t m, int64_t lds, c
             int packed = __builtin_amdgcn_cvt_pk_fp8_f32(sv[u][0] * inv, sv[u][1] * inv, 0, false);
             packed = __builtin_amdgcn_cvt_pk_fp8_f32(sv[u][2] * inv, sv[u][3] * inv, packed, true);
             if (col < ldq) {
-              uint8_t* rowq = q + (row0 + r) * ldq;
-              *reinterpret_cast<int*>(rowq + col) = packed;
-              if ((lane & 7) == 0) sc[(row0 + r) * (ldq >> 5) + (col >> 5)] = (uint8_t)(ex + 127);
+              if constexpr (QM == 1) {
+                *reinterpret_cast<int*>(q + (row0 + r) * ldq + col) = packed;
+                if ((lane & 7) == 0) sc[(row0 + r) * (ldq >> 5) + (col >> 5)] = (uint8_t)(ex + 127);
+              } else {
+                const int64_t blk = (col >> 7) * n + row0 + r;
+                *reinterpret_cast<int*>(q + (blk << 7) + (col & 127)) = packed;
+                if ((lane & 7) == 0) sc[(blk << 2) + ((col >> 5) & 3)] = (uint8_t)(ex + 127);
+              }
             }
           }
         }
@@ -326,7 +338,8 @@ RowPassPlan rowpass_plan(int64_t n, int64_t m, int64_t lds) {
 }
 
 hipError_t rowpass_launch(const RowPassPlan& p, const float* S, const float* v, const double* vd, bool want_b,
-                          bool want_d, double* part, hipStream_t st, uint8_t* q, uint8_t* sc, int64_t ldq) {
+                          bool want_d, double* part, hipStream_t st, uint8_t* q, uint8_t* sc, int64_t ldq,
+                          bool blocked) {
   // bit 0: rows of S are 16-byte aligned; bit 1: the vector is 16-byte aligned as well
   const bool vec = ((p.lds & 3) == 0) && aligned16(S);
   const bool vecv = vec && (v ? aligned16(v) : true) && (vd ? aligned16(vd) : true);
@@ -335,8 +348,13 @@ hipError_t rowpass_launch(const RowPassPlan& p, const float* S, const float* v, 
   const int iv = (vec ? 1 : 0) | (vecv ? 2 : 0);
   if (q) {
     // fused quantisation: b = S v (optional), row norms, and the scaled-FP8 copy of S
-    if (!vec || !want_d || vd || (ldq & 63) != 0) return hipErrorInvalidValue;
-    if (want_b)
+    if (!vec || !want_d || vd || (ldq & 63) != 0 || ldq < p.m) return hipErrorInvalidValue;
+    if (blocked && (ldq & 127) != 0) return hipErrorInvalidValue;
+    if (blocked && want_b)
+      hipLaunchKernelGGL((rowpass_kernel<float, true, true, 3>), grid, block, 0, st, S, p.n, p.m, p.lds, v, p.chunk, p.nchunk, part, iv, q, sc, ldq);
+    else if (blocked)
+      hipLaunchKernelGGL((rowpass_kernel<float, false, true, 3>), grid, block, 0, st, S, p.n, p.m, p.lds, (const float*)nullptr, p.chunk, p.nchunk, part, iv, q, sc, ldq);
+    else if (want_b)
       hipLaunchKernelGGL((rowpass_kernel<float, true, true, 1>), grid, block, 0, st, S, p.n, p.m, p.lds, v, p.chunk, p.nchunk, part, iv, q, sc, ldq);
     else
       hipLaunchKernelGGL((rowpass_kernel<float, false, true, 1>), grid, block, 0, st, S, p.n, p.m, p.lds, (const float*)nullptr, p.chunk, p.nchunk, part, iv, q, sc, ldq);

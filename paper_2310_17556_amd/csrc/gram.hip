@@ -491,12 +491,15 @@ gram_kernel_v2(const float* __restrict__ S, int64_t n, int64_t lds, int64_t m, i
 
 // ---------------------------------------------------------------------------------------------
 // Gram kernel v3: scaled FP8. The operands are the block-scaled E4M3 codes written by the row
-// pass (codes q: n x ldq bytes; E8M0 scales: n x ldq/32 bytes, one per row and 32-column block).
+// pass in its column-blocked layout: 128-column blocks, each holding all n rows contiguously
+// (code (i, k) at q[((k / 128) n + i) 128 + k % 128]; the four E8M0 scale bytes of row i and
+// block k / 128 form one aligned 4-byte word at sc[((k / 128) n + i) 4]). The 256 rows of a
+// panel are then adjacent in memory for every k-step (few pages per step instead of one per row).
 //   * k-step = 64 columns (two scale blocks). Codes move direct-to-LDS: each wave instruction
 //     carries 16 rows x 64 B; row r's four 16-byte chunks are XOR-swizzled by (r >> 2) & 3 so the
 //     fragment reads of 16 consecutive rows hit distinct banks. Scale bytes move direct-to-LDS as
-//     one aligned 4-byte word per row (four blocks, 128 columns; the step uses two of them), since
-//     the LDS side of these loads advances 4 bytes per lane. Needs ldq a multiple of 128.
+//     one 4-byte word per row (four blocks, 128 columns; the step uses two of them), since the LDS
+//     side of these loads advances 4 bytes per lane.
 //   * Four LDS stages: loads run three steps ahead of the matrix cores. Every wave issues the same
 //     number of loads per step (diagonal tiles load their B panel as well), so waiting for a
 //     stage is a vmcnt wait on the count of loads issued after it, plus one barrier per step.
@@ -530,8 +533,9 @@ struct Stage {
   uint8_t sb[4 * T];
 };
 
-__device__ __forceinline__ void issue_codes(const uint8_t* __restrict__ q, int64_t ldq, int64_t n, int64_t row0,
+__device__ __forceinline__ void issue_codes(const uint8_t* __restrict__ q, int64_t n, int64_t row0,
                                             int64_t kcol, int64_t kend, uint8_t* panel) {
+  const uint8_t* qb = q + ((kcol >> 7) * n << 7) + (kcol & 127);   // this step's 64 bytes of row 0
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int rsub = lane >> 2;          // row inside the 16-row group
@@ -548,21 +552,21 @@ __device__ __forceinline__ void issue_codes(const uint8_t* __restrict__ q, int64
     // issue the load twice (once per path) and break the fixed per-step load count that the
     // vmcnt waits rely on.
     const uint64_t in = (uint64_t)0 - (uint64_t)(col < kend);
-    const uint64_t addr = ((uint64_t)(uintptr_t)(q + R * ldq + col) & in) |
+    const uint64_t addr = ((uint64_t)(uintptr_t)(qb + (R << 7) + 16 * c) & in) |
                           ((uint64_t)(uintptr_t)g_zero_chunk8 & ~in);
     __builtin_amdgcn_global_load_lds((const void*)(uintptr_t)addr, (lds_void*)(panel + 16 * g * KS8), 16, 0, 0);
   }
 }
 
-// Scale words of rows [row0, row0 + 256) for the step at column kcol: the 4-byte word holding blocks
-// 4 (kcol / 128) .. + 3 (aligned: ldq / 32 is a multiple of 4). Wave w moves rows 64w .. 64w + 63.
-__device__ __forceinline__ void issue_scales(const uint8_t* __restrict__ sc, int64_t ldsc, int64_t n, int64_t row0,
+// Scale words of rows [row0, row0 + 256) for the step at column kcol: the 4-byte word holding the
+// scales of 32-column blocks 4 (kcol / 128) .. + 3. Wave w moves rows 64w .. 64w + 63.
+__device__ __forceinline__ void issue_scales(const uint8_t* __restrict__ sc, int64_t n, int64_t row0,
                                              int64_t kcol, uint8_t* dst) {
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   int64_t R = row0 + 64 * wave + lane;
   if (R >= n) R = n - 1;
-  const uint8_t* src = sc + R * ldsc + ((kcol >> 5) & ~(int64_t)3);
+  const uint8_t* src = sc + (((kcol >> 7) * n + R) << 2);
   __builtin_amdgcn_global_load_lds((const void*)src, (lds_void*)(dst + 256 * wave), 4, 0, 0);
 }
 
@@ -584,7 +588,7 @@ __device__ __forceinline__ i32x8 read_frag(const uint8_t* panel, int r, int h) {
 #define DFI_WAIT_VM(N) __builtin_amdgcn_s_waitcnt(((N) & 15) | (((N) >> 4) << 14) | (7 << 4) | (15 << 8))
 
 __global__ void __launch_bounds__(NT, 1)
-gram_kernel_fp8(const uint8_t* __restrict__ q, const uint8_t* __restrict__ sc, int64_t ldq, int64_t n, int64_t m16,
+gram_kernel_fp8(const uint8_t* __restrict__ q, const uint8_t* __restrict__ sc, int64_t n, int64_t m16,
                 int64_t ntri, int64_t nslice, int64_t kslice, float* __restrict__ part) {
   __shared__ Stage stg0, stg1, stg2, stg3;
 
@@ -603,7 +607,6 @@ gram_kernel_fp8(const uint8_t* __restrict__ q, const uint8_t* __restrict__ sc, i
   const int64_t k0 = slice * kslice;
   const int64_t kend = min(m16, k0 + kslice);
   const int64_t nsteps = (kend > k0) ? (kend - k0 + KS8 - 1) / KS8 : 0;
-  const int64_t ldsc = ldq >> 5;
 
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
@@ -631,10 +634,10 @@ gram_kernel_fp8(const uint8_t* __restrict__ q, const uint8_t* __restrict__ sc, i
   auto issue_step = [&](int64_t step) {
     Stage* st = stage_ptr(step);
     const int64_t kc = k0 + step * KS8;
-    issue_codes(q, ldq, n, rowA, kc, kend, st->a);
-    issue_codes(q, ldq, n, rowB, kc, kend, st->b);   // diagonal tiles too: uniform load counts
-    issue_scales(sc, ldsc, n, rowA, kc, st->sa);
-    issue_scales(sc, ldsc, n, rowB, kc, st->sb);
+    issue_codes(q, n, rowA, kc, kend, st->a);
+    issue_codes(q, n, rowB, kc, kend, st->b);   // diagonal tiles too: uniform load counts
+    issue_scales(sc, n, rowA, kc, st->sa);
+    issue_scales(sc, n, rowB, kc, st->sb);
   };
 
   for (int64_t st = 0; st < NS - 1 && st < nsteps; ++st) issue_step(st);
@@ -689,7 +692,8 @@ gram_kernel_fp8(const uint8_t* __restrict__ q, const uint8_t* __restrict__ sc, i
 
 // ---------------------------------------------------------------------------------------------
 // Gram kernel v4: split-BF16 from pre-split planes. The row pass writes hi = bf16_rne(S) and
-// lo = bf16_rne(S - hi) as two n x ldh bf16 planes; the tile kernel is then a plain bf16
+// lo = bf16_rne(S - hi) as two bf16 planes in its column-blocked layout (64-column blocks of all
+// n rows, element (i, k) at [((k / 64) n + i) 64 + k % 64]); the tile kernel is then a plain bf16
 // matrix-core product with three terms per pair of elements (lo.hi, hi.lo, hi.hi) and no
 // conversion work in its loop.
 //   * k-step = 16 columns: 32 bytes of each of the 256 rows of a panel, per plane. One wave
@@ -729,8 +733,9 @@ struct Stage {
 // One plane of one 256-row panel for the step at column kcol. Wave instruction i moves rows
 // 32 g .. 32 g + 31 (g = wave + 4 i); lane l fills LDS row 32 g + l / 2, chunk slot l % 2, with
 // column chunk (l % 2) ^ ((row >> 2) & 1) of that row (or zeros past kend).
-__device__ __forceinline__ void issue_plane(const uint16_t* __restrict__ plane, int64_t ldh, int64_t n, int64_t row0,
+__device__ __forceinline__ void issue_plane(const uint16_t* __restrict__ plane, int64_t n, int64_t row0,
                                             int64_t kcol, int64_t kend, uint8_t* panel) {
+  const uint16_t* pb = plane + ((kcol >> 6) * n << 6) + (kcol & 63);   // this step's 16 values of row 0
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
 #pragma unroll
@@ -743,7 +748,7 @@ __device__ __forceinline__ void issue_plane(const uint16_t* __restrict__ plane, 
     const int64_t col = kcol + 8 * c;
     // branch-free choice of the source keeps the per-step load count fixed (see v3)
     const uint64_t in = (uint64_t)0 - (uint64_t)(col < kend);
-    const uint64_t addr = ((uint64_t)(uintptr_t)(plane + R * ldh + col) & in) |
+    const uint64_t addr = ((uint64_t)(uintptr_t)(pb + (R << 6) + 8 * c) & in) |
                           ((uint64_t)(uintptr_t)g_zero_chunk16 & ~in);
     __builtin_amdgcn_global_load_lds((const void*)(uintptr_t)addr, (lds_void*)(panel + 32 * g * ROWB), 16, 0, 0);
   }
@@ -754,7 +759,7 @@ __device__ __forceinline__ bf16x8 read_bf(const uint8_t* panel, int r, int h) {
 }
 
 __global__ void __launch_bounds__(NT, 1)
-gram_kernel_split(const uint16_t* __restrict__ hi, const uint16_t* __restrict__ lo, int64_t ldh, int64_t n,
+gram_kernel_split(const uint16_t* __restrict__ hi, const uint16_t* __restrict__ lo, int64_t n,
                   int64_t m8, int64_t ntri, int64_t nslice, int64_t kslice, float* __restrict__ part) {
   __shared__ Stage stg0, stg1, stg2, stg3;
 
@@ -800,10 +805,10 @@ gram_kernel_split(const uint16_t* __restrict__ hi, const uint16_t* __restrict__ 
   auto issue_step = [&](int64_t step) {
     Stage* sp = stage_ptr(step);
     const int64_t kc = k0 + step * KSB;
-    issue_plane(hi, ldh, n, rowA, kc, kend, sp->ah);
-    issue_plane(lo, ldh, n, rowA, kc, kend, sp->al);
-    issue_plane(hi, ldh, n, rowB, kc, kend, sp->bh);
-    issue_plane(lo, ldh, n, rowB, kc, kend, sp->bl);
+    issue_plane(hi, n, rowA, kc, kend, sp->ah);
+    issue_plane(lo, n, rowA, kc, kend, sp->al);
+    issue_plane(hi, n, rowB, kc, kend, sp->bh);
+    issue_plane(lo, n, rowB, kc, kend, sp->bl);
   };
 
   for (int64_t s0 = 0; s0 < NS - 1 && s0 < nsteps; ++s0) issue_step(s0);
@@ -918,7 +923,8 @@ GramPlan gram_plan(int64_t n, int64_t m, int64_t lds, int prec, bool aligned16) 
 hipError_t gram_launch_fp8(const GramPlan& p, const uint8_t* q, const uint8_t* sc, int64_t ldq, float* part,
                            hipStream_t st) {
   const dim3 grid((unsigned)(p.nslice * p.ntri));
-  hipLaunchKernelGGL(v3::gram_kernel_fp8, grid, dim3(v3::NT), 0, st, q, sc, ldq, p.n, p.m & ~(int64_t)15, p.ntri,
+  if ((ldq & 127) != 0 || ldq < p.m) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(v3::gram_kernel_fp8, grid, dim3(v3::NT), 0, st, q, sc, p.n, p.m & ~(int64_t)15, p.ntri,
                      p.nslice, p.kslice, part);
   return hipGetLastError();
 }
@@ -926,7 +932,7 @@ hipError_t gram_launch_fp8(const GramPlan& p, const uint8_t* q, const uint8_t* s
 hipError_t gram_launch_split(const GramPlan& p, const uint16_t* hi, const uint16_t* lo, float* part, hipStream_t st) {
   if (p.prec != 1 || p.ldh <= 0 || (p.ldh & 63) != 0) return hipErrorInvalidValue;
   const dim3 grid((unsigned)(p.nslice * p.ntri));
-  hipLaunchKernelGGL(v4::gram_kernel_split, grid, dim3(v4::NT), 0, st, hi, lo, p.ldh, p.n, p.m & ~(int64_t)7, p.ntri,
+  hipLaunchKernelGGL(v4::gram_kernel_split, grid, dim3(v4::NT), 0, st, hi, lo, p.n, p.m & ~(int64_t)7, p.ntri,
                      p.nslice, p.kslice, part);
   return hipGetLastError();
 }

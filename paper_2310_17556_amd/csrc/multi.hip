@@ -1,0 +1,274 @@
+// Multi-vector streaming passes over S for many right-hand sides and damping values that share
+// one S: the batched form of the right-to-left evaluation x = (v - S^T L^-T L^-1 S v) / lambda
+// (Section 2), where one HBM pass over S serves up to MV = 8 vectors instead of one.
+//
+// Row pass  B_c = S V_c for c < nv. A wave owns 4 rows and a group of columns; per 256-column step
+//           each lane loads 4 columns of every vector once and reuses them for its 4 rows, with
+//           one FP64 accumulator per (row, vector). Vectors are FP32 (separate arrays, the
+//           caller's right-hand sides) or FP64 interleaved T[k * 8 + c] (the column pass output).
+//           FP64 partials per (column group, vector, row) are added in fixed order by a second
+//           kernel, which can also form refinement residuals r = b - lambda y - S t.
+// Column pass t_c = S^T y_c for c < nc. A workgroup owns 1024 consecutive columns (4 per lane)
+//           and walks all rows; y_c[i] is wave-uniform. Output either T[k * 8 + c] (FP64) or
+//           x_c = (v_c - t_c) / lambda_c (FP32 or FP64), each column with its own v, x, lambda.
+// Products of FP32 and FP64 values are formed and accumulated in FP64.
+#include "dfisher_internal.h"
+
+#include <algorithm>
+
+namespace dfi {
+namespace {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+
+constexpr int MV = MULTI_VECS;   // 8
+constexpr int RM_WAVES = 4;
+constexpr int RM_RPW = 4;        // rows per wave
+constexpr int RM_STEP = 256;     // columns per wave step (4 per lane)
+
+__device__ __forceinline__ double wave_sum(double x) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+  return x;
+}
+
+__device__ __forceinline__ void load_s4(const float* __restrict__ p, int64_t col, int64_t c1, bool vec, f32x4& out) {
+  if (vec && col + 4 <= c1) {
+    out = *reinterpret_cast<const f32x4*>(p);
+  } else {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) out[e] = (col + e < c1) ? p[e] : 0.f;
+  }
+}
+
+// Grid: x = row blocks of RM_WAVES * RM_RPW rows, y = column groups of cg columns.
+// IL = false: vector c is vs.f[c] (FP32, contiguous). IL = true: vector c is T[k * 8 + c] (FP64).
+// part[(g * MV + c) * n + i] = sum over group g of S_ik V_c[k].
+template <bool IL>
+__global__ void __launch_bounds__(64 * RM_WAVES)
+rowpass_multi_kernel(const float* __restrict__ S, int64_t n, int64_t m, int64_t lds, MultiVecs vs,
+                     const double* __restrict__ T, int nv, int64_t cg, double* __restrict__ part, int vec) {
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int64_t row0 = ((int64_t)blockIdx.x * RM_WAVES + wave) * RM_RPW;
+  const int64_t g = blockIdx.y;
+  const int64_t c0 = g * cg;
+  const int64_t c1 = min(m, c0 + cg);
+  if (row0 >= n) return;
+  const int nr = (int)min<int64_t>(RM_RPW, n - row0);
+
+  double acc[RM_RPW][MV];
+#pragma unroll
+  for (int r = 0; r < RM_RPW; ++r)
+#pragma unroll
+    for (int c = 0; c < MV; ++c) acc[r][c] = 0.0;
+
+  for (int64_t cs = c0; cs < c1; cs += RM_STEP) {
+    const int64_t col = cs + 4 * lane;
+    double vv[4][MV];
+    if constexpr (IL) {
+      // 4 columns x 8 vectors = 32 consecutive doubles
+      const double* tp = T + col * MV;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const bool in = col + e < c1;
+#pragma unroll
+        for (int c = 0; c < MV; c += 2) {
+          f64x2 t2 = {0.0, 0.0};
+          if (in) t2 = *reinterpret_cast<const f64x2*>(tp + e * MV + c);
+          vv[e][c] = t2[0];
+          vv[e][c + 1] = t2[1];
+        }
+      }
+    } else {
+#pragma unroll
+      for (int c = 0; c < MV; ++c) {
+        f32x4 t4 = {0.f, 0.f, 0.f, 0.f};
+        if (c < nv) load_s4(vs.f[c] + col, col, c1, (vec & 2) != 0, t4);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) vv[e][c] = (double)t4[e];
+      }
+    }
+    f32x4 sv[RM_RPW];
+#pragma unroll
+    for (int r = 0; r < RM_RPW; ++r) {
+      sv[r] = (f32x4){0.f, 0.f, 0.f, 0.f};
+      if (r < nr) load_s4(S + (row0 + r) * lds + col, col, c1, (vec & 1) != 0, sv[r]);
+    }
+#pragma unroll
+    for (int r = 0; r < RM_RPW; ++r)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const double s = (double)sv[r][e];
+#pragma unroll
+        for (int c = 0; c < MV; ++c) acc[r][c] = fma(s, vv[e][c], acc[r][c]);
+      }
+  }
+#pragma unroll
+  for (int r = 0; r < RM_RPW; ++r) {
+    if (r >= nr) continue;
+#pragma unroll
+    for (int c = 0; c < MV; ++c) {
+      const double t = wave_sum(acc[r][c]);
+      if (lane == 0 && c < nv) part[(g * MV + c) * n + row0 + r] = t;
+    }
+  }
+}
+
+// out.b[c][i] = sum_g part[(g * MV + c) * n + i]; with out.r0[c] set:
+// out.b[c][i] = (r0_c[i] - lam_c y_c[i]) - sum_g part[...] (refinement residual).
+__global__ void rowpass_multi_reduce_kernel(const double* __restrict__ part, int64_t n, int64_t ngroups, int nv,
+                                            MultiOut out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int c = blockIdx.y;
+  if (i >= n || c >= nv) return;
+  double s = 0.0;
+  for (int64_t g = 0; g < ngroups; ++g) s += part[(g * MV + c) * n + i];
+  const double* r0 = out.r0[c];
+  out.b[c][i] = r0 ? (r0[i] - out.lam[c] * out.y[c][i]) - s : s;
+}
+
+constexpr int CM_THREADS = 256;
+constexpr int CM_COLS = 4 * CM_THREADS;
+constexpr int CM_UNROLL = 4;
+
+// MODE 2: T[k * 8 + c] = t_c[k]; MODE 0 / 1: x_c[k] = (v_c[k] - t_c[k]) / lam_c as FP32 / FP64.
+// Vectors c >= nc are computed from y_0 and discarded.
+template <int MODE>
+__global__ void __launch_bounds__(CM_THREADS)
+colpass_multi_kernel(const float* __restrict__ S, int64_t n, int64_t m, int64_t lds, MultiCols mc, int nc,
+                     double* __restrict__ T, int vec) {
+  const int64_t col = (int64_t)blockIdx.x * CM_COLS + 4 * threadIdx.x;
+  if (col >= m) return;
+  const bool full = vec && (col + 4 <= m);
+  double t[4][MV];
+#pragma unroll
+  for (int e = 0; e < 4; ++e)
+#pragma unroll
+    for (int c = 0; c < MV; ++c) t[e][c] = 0.0;
+  int64_t i = 0;
+  for (; i < n; i += CM_UNROLL) {
+    f32x4 sv[CM_UNROLL];
+#pragma unroll
+    for (int u = 0; u < CM_UNROLL; ++u) {
+      sv[u] = (f32x4){0.f, 0.f, 0.f, 0.f};
+      if (i + u < n) {
+        const float* p = S + (i + u) * lds + col;
+        if (full) {
+          sv[u] = *reinterpret_cast<const f32x4*>(p);
+        } else {
+#pragma unroll
+          for (int e = 0; e < 4; ++e) sv[u][e] = (col + e < m) ? p[e] : 0.f;
+        }
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < CM_UNROLL; ++u) {
+      if (i + u >= n) break;
+#pragma unroll
+      for (int c = 0; c < MV; ++c) {
+        const double yc = mc.y[c][i + u];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) t[e][c] = fma((double)sv[u][e], yc, t[e][c]);
+      }
+    }
+  }
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const int64_t k = col + e;
+    if (k >= m) break;
+    if constexpr (MODE == 2) {
+#pragma unroll
+      for (int c = 0; c < MV; c += 2) *reinterpret_cast<f64x2*>(T + k * MV + c) = (f64x2){t[e][c], t[e][c + 1]};
+    } else {
+#pragma unroll
+      for (int c = 0; c < MV; ++c) {
+        if (c >= nc) break;
+        const double x = ((double)mc.v[c][k] - t[e][c]) / mc.lam[c];
+        if constexpr (MODE == 0) static_cast<float*>(mc.x[c])[k] = (float)x;
+        else static_cast<double*>(mc.x[c])[k] = x;
+      }
+    }
+  }
+}
+
+__global__ void axpy_many_kernel(double* __restrict__ y, const double* __restrict__ d, int64_t len) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < len) y[i] += d[i];
+}
+
+bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
+
+}  // namespace
+
+RowMultiPlan rowmulti_plan(int64_t n, int64_t m, int64_t lds) {
+  RowMultiPlan p{};
+  p.n = n;
+  p.m = m;
+  p.lds = lds;
+  const int64_t rowblocks = (n + RM_WAVES * RM_RPW - 1) / (RM_WAVES * RM_RPW);
+  const int64_t target = std::max<int64_t>(1, 4096 / rowblocks);       // ~4096 workgroups
+  const int64_t maxg = (m + 2047) / 2048;                                // >= 2048 columns per group
+  p.nchunk = std::max<int64_t>(1, std::min(target, maxg));
+  int64_t cg = (m + p.nchunk - 1) / p.nchunk;
+  cg = (cg + RM_STEP - 1) / RM_STEP * RM_STEP;
+  p.chunk = cg;
+  p.nchunk = (m + cg - 1) / cg;
+  p.part_bytes = (size_t)p.nchunk * MV * (size_t)n * sizeof(double);
+  return p;
+}
+
+hipError_t rowpass_multi_launch(const RowMultiPlan& p, const float* S, const MultiVecs& vs, const double* T, int nv,
+                                double* part, hipStream_t st) {
+  if (nv < 1 || nv > MV) return hipErrorInvalidValue;
+  const bool vec = ((p.lds & 3) == 0) && aligned16(S);
+  bool vecv = true;
+  if (!T)
+    for (int c = 0; c < nv; ++c) vecv = vecv && aligned16(vs.f[c]);
+  const int iv = (vec ? 1 : 0) | (vecv ? 2 : 0);
+  const dim3 grid((unsigned)((p.n + RM_WAVES * RM_RPW - 1) / (RM_WAVES * RM_RPW)), (unsigned)p.nchunk);
+  if (T)
+    hipLaunchKernelGGL((rowpass_multi_kernel<true>), grid, dim3(64 * RM_WAVES), 0, st, S, p.n, p.m, p.lds, vs, T, nv,
+                       p.chunk, part, iv);
+  else
+    hipLaunchKernelGGL((rowpass_multi_kernel<false>), grid, dim3(64 * RM_WAVES), 0, st, S, p.n, p.m, p.lds, vs, T, nv,
+                       p.chunk, part, iv);
+  return hipGetLastError();
+}
+
+hipError_t rowpass_multi_reduce(const RowMultiPlan& p, const double* part, int nv, const MultiOut& out,
+                                hipStream_t st) {
+  if (nv < 1 || nv > MV) return hipErrorInvalidValue;
+  const dim3 grid((unsigned)((p.n + 255) / 256), (unsigned)nv);
+  hipLaunchKernelGGL(rowpass_multi_reduce_kernel, grid, dim3(256), 0, st, part, p.n, p.nchunk, nv, out);
+  return hipGetLastError();
+}
+
+hipError_t colpass_multi_launch(const float* S, int64_t n, int64_t m, int64_t lds, const MultiCols& mc, int nc,
+                                int mode, double* T, hipStream_t st) {
+  if (nc < 1 || nc > MV) return hipErrorInvalidValue;
+  const bool vec = ((lds & 3) == 0) && aligned16(S);
+  const dim3 grid((unsigned)((m + CM_COLS - 1) / CM_COLS));
+  switch (mode) {
+    case 0:
+      hipLaunchKernelGGL((colpass_multi_kernel<0>), grid, dim3(CM_THREADS), 0, st, S, n, m, lds, mc, nc, T, vec ? 1 : 0);
+      break;
+    case 1:
+      hipLaunchKernelGGL((colpass_multi_kernel<1>), grid, dim3(CM_THREADS), 0, st, S, n, m, lds, mc, nc, T, vec ? 1 : 0);
+      break;
+    case 2:
+      hipLaunchKernelGGL((colpass_multi_kernel<2>), grid, dim3(CM_THREADS), 0, st, S, n, m, lds, mc, nc, T, vec ? 1 : 0);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t axpy_many(double* y, const double* d, int64_t len, hipStream_t st) {
+  hipLaunchKernelGGL(axpy_many_kernel, dim3((unsigned)((len + 255) / 256)), dim3(256), 0, st, y, d, len);
+  return hipGetLastError();
+}
+
+}  // namespace dfi

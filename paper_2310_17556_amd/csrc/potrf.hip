@@ -10,6 +10,8 @@
 // A pivot d with !(d > 0) (NaN included) stores the 1-based global index in *info and raises
 // *flag; every later kernel sees the flag and returns at once, so the device work drains
 // without touching the matrix further.
+// Batched form: grid dimension y indexes independent matrices (A + b sA, info[b], flag[b], Dkk
+// block b), which then share every launch; a breakdown stops only its own matrix.
 #include "dfisher_internal.h"
 
 namespace dfi {
@@ -22,8 +24,13 @@ constexpr int LDP = NB + 1;  // padded LDS row (doubles)
 
 __global__ void __launch_bounds__(64)
 potf2_kernel(double* __restrict__ A, int64_t n, int64_t k, int64_t* __restrict__ info, int32_t* __restrict__ flag,
-             double* __restrict__ Dkk) {
+             double* __restrict__ Dkk, int64_t sA) {
   __shared__ double a[NB * LDP];
+  const int64_t bb = blockIdx.y;
+  A += bb * sA;
+  info += bb;
+  flag += bb;
+  Dkk += bb * NB * NB;
   if (*(volatile int32_t*)flag) return;
   const int lane = threadIdx.x;
   const int64_t nb = min<int64_t>(NB, n - k);
@@ -79,9 +86,13 @@ potf2_kernel(double* __restrict__ A, int64_t n, int64_t k, int64_t* __restrict__
 // 64 rows per workgroup, 256 threads with 4 x 4 outputs each.
 __global__ void __launch_bounds__(256)
 trsm_kernel(double* __restrict__ A, int64_t n, int64_t k, const int32_t* __restrict__ flag,
-            const double* __restrict__ Dkk) {
+            const double* __restrict__ Dkk, int64_t sA) {
   __shared__ double Ab[NB * LDP];
   __shared__ double Db[NB * LDP];
+  const int64_t bb = blockIdx.y;
+  A += bb * sA;
+  flag += bb;
+  Dkk += bb * NB * NB;
   if (*(volatile const int32_t*)flag) return;
   const int tid = threadIdx.x;
   const int64_t row0 = k + NB + (int64_t)blockIdx.x * NB;
@@ -123,9 +134,11 @@ trsm_kernel(double* __restrict__ A, int64_t n, int64_t k, const int32_t* __restr
 // MFMA lane layout (16x16x4 f64): A lane l = (row l%16, k l/16), B lane l = (k l/16, col l%16),
 // D lane l register r = (row l/16 + 4r, col l%16).
 __global__ void __launch_bounds__(256)
-update_kernel(double* __restrict__ A, int64_t n, int64_t k, const int32_t* __restrict__ flag) {
+update_kernel(double* __restrict__ A, int64_t n, int64_t k, const int32_t* __restrict__ flag, int64_t sA) {
   __shared__ double PI[NB * LDP];
   __shared__ double PJ[NB * LDP];
+  A += (int64_t)blockIdx.y * sA;
+  flag += blockIdx.y;
   if (*(volatile const int32_t*)flag) return;
   const int64_t t = blockIdx.x;
   int64_t I = (int64_t)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
@@ -212,25 +225,36 @@ __global__ void diag_max_kernel(const double* __restrict__ W, int64_t n, double*
   if (threadIdx.x == 0) *out = red[0];
 }
 
-__global__ void clear_status_kernel(int64_t* info, int32_t* flag) {
-  *info = 0;
-  *flag = 0;
+__global__ void clear_status_kernel(int64_t* info, int32_t* flag, int64_t nbatch) {
+  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (b < nbatch) {
+    info[b] = 0;
+    flag[b] = 0;
+  }
 }
 
 }  // namespace
 
-hipError_t potrf_launch(double* A, int64_t n, int64_t* info_dev, int32_t* flag_dev, double* dkk, hipStream_t st) {
-  hipLaunchKernelGGL(clear_status_kernel, dim3(1), dim3(1), 0, st, info_dev, flag_dev);
+hipError_t potrf_launch_batched(double* A, int64_t n, int64_t nbatch, int64_t sA, int64_t* info_dev, int32_t* flag_dev,
+                                double* dkk, hipStream_t st) {
+  if (nbatch < 1 || nbatch > 65535) return hipErrorInvalidValue;
+  const unsigned nb = (unsigned)nbatch;
+  hipLaunchKernelGGL(clear_status_kernel, dim3((unsigned)((nbatch + 255) / 256)), dim3(256), 0, st, info_dev, flag_dev,
+                     nbatch);
   for (int64_t k = 0; k < n; k += NB) {
-    hipLaunchKernelGGL(potf2_kernel, dim3(1), dim3(64), 0, st, A, n, k, info_dev, flag_dev, dkk);
+    hipLaunchKernelGGL(potf2_kernel, dim3(1, nb), dim3(64), 0, st, A, n, k, info_dev, flag_dev, dkk, sA);
     const int64_t rest = n - k - NB;
     if (rest > 0) {
       const int64_t rb = (rest + 63) / 64;
-      hipLaunchKernelGGL(trsm_kernel, dim3((unsigned)rb), dim3(256), 0, st, A, n, k, flag_dev, (const double*)dkk);
-      hipLaunchKernelGGL(update_kernel, dim3((unsigned)(rb * (rb + 1) / 2)), dim3(256), 0, st, A, n, k, flag_dev);
+      hipLaunchKernelGGL(trsm_kernel, dim3((unsigned)rb, nb), dim3(256), 0, st, A, n, k, flag_dev, (const double*)dkk, sA);
+      hipLaunchKernelGGL(update_kernel, dim3((unsigned)(rb * (rb + 1) / 2), nb), dim3(256), 0, st, A, n, k, flag_dev, sA);
     }
   }
   return hipGetLastError();
+}
+
+hipError_t potrf_launch(double* A, int64_t n, int64_t* info_dev, int32_t* flag_dev, double* dkk, hipStream_t st) {
+  return potrf_launch_batched(A, n, 1, n * n, info_dev, flag_dev, dkk, st);
 }
 
 hipError_t zero_upper(double* A, int64_t n, hipStream_t st) {
@@ -250,6 +274,14 @@ hipError_t add_diag_copy(const double* src, double* dst, int64_t n, double lam, 
   const int64_t tot = n * n;
   hipLaunchKernelGGL(shift_copy_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, src, dst, n, 0.0,
                      (const double*)nullptr, lam);
+  return hipGetLastError();
+}
+
+hipError_t shift_add_copy(const double* src, double* dst, int64_t n, double scale, const double* dmax, double lam,
+                          hipStream_t st) {
+  const int64_t tot = n * n;
+  hipLaunchKernelGGL(shift_copy_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, src, dst, n, scale, dmax,
+                     lam);
   return hipGetLastError();
 }
 

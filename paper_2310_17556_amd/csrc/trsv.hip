@@ -11,6 +11,9 @@
 //     side, r_J -= L_Jk z_k. Backward step k (from the last block): y_k = D_k^T r_k, then
 //     r_J -= L_kJ^T y_k for the blocks J < k, which read row block k of L (contiguous rows).
 // Every launch reads only the panel it needs; the whole solve reads the lower triangle once.
+// Batched form: grid dimension y indexes right-hand sides (vector j at offset j n); vector j uses
+// factor j / nper (L + (j / nper) sL, Dinv + (j / nper) sD), so several right-hand sides of one
+// factor and several factors share every launch.
 #include "dfisher_internal.h"
 
 namespace dfi {
@@ -22,8 +25,10 @@ constexpr int LDP = NB + 1;
 // D_k = inverse of the lower-triangular 64 x 64 block L_kk (identity-padded past n).
 // One 64-lane workgroup per block; lane c computes column c: x_c = e_c, x_i = -(sum_{c<=l<i} L_il x_l)/L_ii.
 __global__ void __launch_bounds__(64)
-diag_inv_kernel(const double* __restrict__ L, int64_t n, double* __restrict__ Dinv) {
+diag_inv_kernel(const double* __restrict__ L, int64_t n, double* __restrict__ Dinv, int64_t sL, int64_t sD) {
   __shared__ double Lk[NB * LDP];
+  L += (int64_t)blockIdx.y * sL;
+  Dinv += (int64_t)blockIdx.y * sD;
   const int64_t k = blockIdx.x;
   const int64_t r0 = k * NB;
   const int c = threadIdx.x;
@@ -54,9 +59,16 @@ diag_inv_kernel(const double* __restrict__ L, int64_t n, double* __restrict__ Di
 // Grid: 1 + number of row blocks below k (at least 1). 256 threads.
 __global__ void __launch_bounds__(256)
 fwd_step_kernel(const double* __restrict__ L, int64_t n, const double* __restrict__ Dinv, int64_t k,
-                double* __restrict__ r, double* __restrict__ z) {
+                double* __restrict__ r, double* __restrict__ z, int64_t sL, int64_t sD, int64_t nper) {
   __shared__ double zk[NB];
   __shared__ double part[4][NB];
+  {
+    const int64_t j = blockIdx.y, f = j / nper;
+    L += f * sL;
+    Dinv += f * sD;
+    r += j * n;
+    z += j * n;
+  }
   const int tid = threadIdx.x;
   const int64_t r0 = k * NB;
   const int nb = (int)min<int64_t>(NB, n - r0);
@@ -93,9 +105,16 @@ fwd_step_kernel(const double* __restrict__ L, int64_t n, const double* __restric
 // Backward step k. Grid: 1 + k (block k itself and the blocks J < k). 256 threads.
 __global__ void __launch_bounds__(256)
 bwd_step_kernel(const double* __restrict__ L, int64_t n, const double* __restrict__ Dinv, int64_t k,
-                double* __restrict__ r, double* __restrict__ y) {
+                double* __restrict__ r, double* __restrict__ y, int64_t sL, int64_t sD, int64_t nper) {
   __shared__ double yk[NB];
   __shared__ double part[4][NB];
+  {
+    const int64_t j = blockIdx.y, f = j / nper;
+    L += f * sL;
+    Dinv += f * sD;
+    r += j * n;
+    y += j * n;
+  }
   const int tid = threadIdx.x;
   const int64_t r0 = k * NB;
   const int nb = (int)min<int64_t>(NB, n - r0);
@@ -136,9 +155,35 @@ __global__ void copy_vec_kernel(const double* __restrict__ a, double* __restrict
 
 size_t trsv_dinv_bytes(int64_t n) { return (size_t)((n + NB - 1) / NB) * NB * NB * sizeof(double); }
 
-hipError_t trsv_diag_inv(const double* L, int64_t n, double* Dinv, hipStream_t st) {
+hipError_t trsv_diag_inv_batched(const double* L, int64_t sL, int64_t n, int64_t nfac, double* Dinv, hipStream_t st) {
+  if (nfac < 1 || nfac > 65535) return hipErrorInvalidValue;
   const int64_t nblk = (n + NB - 1) / NB;
-  hipLaunchKernelGGL(diag_inv_kernel, dim3((unsigned)nblk), dim3(64), 0, st, L, n, Dinv);
+  hipLaunchKernelGGL(diag_inv_kernel, dim3((unsigned)nblk, (unsigned)nfac), dim3(64), 0, st, L, n, Dinv, sL,
+                     (int64_t)(trsv_dinv_bytes(n) / sizeof(double)));
+  return hipGetLastError();
+}
+
+hipError_t trsv_diag_inv(const double* L, int64_t n, double* Dinv, hipStream_t st) {
+  return trsv_diag_inv_batched(L, n * n, n, 1, Dinv, st);
+}
+
+hipError_t trsv_launch_batched(const double* L, int64_t sL, const double* Dinv, int64_t n, int64_t nvec, int64_t nper,
+                               int trans, const double* b, double* y, double* work, hipStream_t st) {
+  if (nvec < 1 || nvec > 65535 || nper < 1) return hipErrorInvalidValue;
+  const int64_t nblk = (n + NB - 1) / NB;
+  const int64_t sD = (int64_t)(trsv_dinv_bytes(n) / sizeof(double));
+  const unsigned nv = (unsigned)nvec;
+  const int64_t tot = n * nvec;
+  hipLaunchKernelGGL(copy_vec_kernel, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, b, work, tot);
+  if (trans == 0) {
+    for (int64_t k = 0; k < nblk; ++k)
+      hipLaunchKernelGGL(fwd_step_kernel, dim3((unsigned)(nblk - k), nv), dim3(256), 0, st, L, n, Dinv, k, work, y, sL,
+                         sD, nper);
+  } else {
+    for (int64_t k = nblk - 1; k >= 0; --k)
+      hipLaunchKernelGGL(bwd_step_kernel, dim3((unsigned)(k + 1), nv), dim3(256), 0, st, L, n, Dinv, k, work, y, sL,
+                         sD, nper);
+  }
   return hipGetLastError();
 }
 
@@ -146,16 +191,7 @@ hipError_t trsv_diag_inv(const double* L, int64_t n, double* Dinv, hipStream_t s
 // b may alias y; work must not alias either.
 hipError_t trsv_launch(const double* L, const double* Dinv, int64_t n, int trans, const double* b, double* y,
                        double* work, hipStream_t st) {
-  const int64_t nblk = (n + NB - 1) / NB;
-  hipLaunchKernelGGL(copy_vec_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, b, work, n);
-  if (trans == 0) {
-    for (int64_t k = 0; k < nblk; ++k)
-      hipLaunchKernelGGL(fwd_step_kernel, dim3((unsigned)(nblk - k)), dim3(256), 0, st, L, n, Dinv, k, work, y);
-  } else {
-    for (int64_t k = nblk - 1; k >= 0; --k)
-      hipLaunchKernelGGL(bwd_step_kernel, dim3((unsigned)(k + 1)), dim3(256), 0, st, L, n, Dinv, k, work, y);
-  }
-  return hipGetLastError();
+  return trsv_launch_batched(L, n * n, Dinv, n, 1, 1, trans, b, y, work, st);
 }
 
 }  // namespace dfi

@@ -243,7 +243,7 @@ SOLVE_CASES = [
     (257, 30000, 1e-3, 0, 1, "scaled", 1e-6),   # row-space-heavy v (cancellation in v - S^T y)
     (257, 30000, 1e-3, 1, 2, "scaled", 1e-6),
     (600, 12000, 1e-4, 0, 2, "iid", 1e-6),
-    (300, 20000, 1e-2, 2, 2, "iid", 1e-6),      # scaled-FP8 Gram + refinement
+    (300, 20000, 1e-2, 2, 4, "iid", 1e-6),      # scaled-FP8 Gram + refinement (m/n = 67: slow contraction)
     (300, 20000, 1e-6, 2, 3, "iid", 1e-6),
     (257, 30000, 1e-3, 2, 3, "iid", 1e-6),
 ]
@@ -265,6 +265,21 @@ def test_solve(dfl, ctx, oracle_mod, n, m, lam, prec, sweeps, kind, bound):
     # FP32 output: the same solution rounded once
     x32, _ = dfl.dfisher_solve(ctx, dev(S), dev(v), lam, gram_prec=prec, sweeps=sweeps, shift_policy=policy)
     assert rel(x32.cpu().numpy(), xref) <= bound + 2.0 ** -23
+
+
+@pytest.mark.parametrize("lam", [1e-2, 1e-6])
+def test_solve_fp8_unshifted(dfl, ctx, oracle_mod, lam):
+    """Scaled-FP8 Gram under the default policy (shift only on failure) at m/n = 1024, the aspect
+    ratio of the full-size workload: one refinement sweep reaches the 1e-6 target."""
+    n, m = 128, 131072
+    print(f"[solve fp8 on-failure] n={n} m={m} lam={lam}", flush=True)
+    S = synth.make_S(n, m, synth.seed(31, n), "iid")
+    v = synth.make_v(S, synth.seed(31, n), "iid")
+    xref = oracle_mod.solve(S, v, lam)
+    x, info = dfl.dfisher_solve(ctx, dev(S), dev(v), lam, gram_prec=dfl.DFISHER_GRAM_MXFP8, sweeps=1, x_fp64=True)
+    err = rel(x.cpu().numpy(), xref)
+    print(f"    rel err {err:.3e}  info {info}", flush=True)
+    assert err <= 1e-6
 
 
 def test_solve_deterministic(dfl, ctx):
@@ -324,6 +339,45 @@ def test_batched(dfl, ctx, oracle_mod):
             err = rel(X[li, r], Xref[li, r])
             print(f"    lam={lams[li]} rhs={r} rel err {err:.3e} info {infos[li]}", flush=True)
             assert err <= 1e-6
+
+
+@pytest.mark.parametrize("n,m,ld,nlam,nrhs,prec,sweeps,policy", [
+    (200, 12001, 12001, 5, 3, 1, 2, "on_failure"),   # 15 vectors: a full and a ragged group of 8; unaligned rows
+    (96, 8192, 8200, 2, 9, 0, 1, "on_failure"),      # 18 vectors, padded stride
+    (256, 65536, 65536, 3, 2, 2, 3, "always"),       # scaled-FP8 Gram with the up-front shift
+])
+def test_batched_groups(dfl, ctx, oracle_mod, n, m, ld, nlam, nrhs, prec, sweeps, policy):
+    """Every (lambda, rhs) pair of the multi-vector path matches Algorithm 1 run on its own."""
+    print(f"[batched] n={n} m={m} ld={ld} nlam={nlam} nrhs={nrhs} prec={prec} sweeps={sweeps} {policy}", flush=True)
+    S = synth.make_S(n, m, synth.seed(38, n), "iid")
+    V = synth.make_V(m, nrhs, synth.seed(38, n))
+    lams = list(np.logspace(-6, -1, nlam))
+    pol = dfl.DFISHER_SHIFT_ALWAYS if policy == "always" else dfl.DFISHER_SHIFT_ON_FAILURE
+    Vd = dev_strided(V, m + 5)                      # row stride of V not equal to m
+    X, infos = dfl.dfisher_solve_batched(ctx, dev_strided(S, ld), lams, Vd, gram_prec=prec, sweeps=sweeps,
+                                         shift_policy=pol, x_fp64=True)
+    Xref = oracle_mod.solve_batched(S, lams, V)
+    X = X.cpu().numpy()
+    for li in range(nlam):
+        assert infos[li]["potrf_info"] == 0 and infos[li]["sweeps_done"] == sweeps
+        for r in range(nrhs):
+            err = rel(X[li, r], Xref[li, r])
+            assert err <= 1e-6, (li, r, err, infos[li])
+    X32, _ = dfl.dfisher_solve_batched(ctx, dev_strided(S, ld), lams, Vd, gram_prec=prec, sweeps=sweeps,
+                                       shift_policy=pol)
+    assert rel(X32.cpu().numpy(), Xref) <= 1e-6 + 2.0 ** -23
+
+
+def test_factor_solve_many(dfl, ctx, oracle_mod):
+    """Factor reuse with 11 right-hand sides (two groups of the multi-vector passes)."""
+    n, m, lam = 160, 9000, 1e-4
+    S = synth.make_S(n, m, synth.seed(39, n))
+    V = synth.make_V(m, 11, synth.seed(39, n))
+    f, _ = dfl.dfisher_factor_create(ctx, dev(S), lam, gram_prec=1, sweeps=2, x_fp64=True)
+    X = dfl.dfisher_factor_solve(f, dev(V)).cpu().numpy()
+    dfl.dfisher_factor_destroy(f)
+    for r in range(11):
+        assert rel(X[r], oracle_mod.solve(S, V[r], lam)) <= 1e-6
 
 
 def test_uneven(dfl, ctx, oracle_mod):
