@@ -194,7 +194,12 @@ DFISHER_API dfisher_status dfisher_factor_destroy(dfisher_factor* f);
 /* Many damping values and right-hand sides sharing one Gram: for every lambda_l (nlam values,
  * host array) and every row v_r of V (nrhs x m FP32, stride ldv), X[(l * nrhs + r) * ldx + k]
  * holds x_{l,r} solving (S^T S + lambda_l I) x = v_r. infos (host, may be NULL) has nlam
- * entries. The Gram is formed once; each lambda_l gets its own Cholesky of G + lambda_l I. */
+ * entries. Algorithm 1 for every pair, with step 1 shared: the Gram G = S S^T is formed once,
+ * the nlam Cholesky factorisations of G + lambda_l I run in the same launches, and S V, the
+ * refinement residuals and x = (v - S^T y) / lambda run as passes over S that serve 8 vectors
+ * each. Needs nlam * nrhs <= 65535 (else DFISHER_E_UNSUPPORTED). A factorisation that fails
+ * under DFISHER_SHIFT_NONE makes the call return DFISHER_E_NOT_SPD; the x of that lambda is then
+ * unspecified. Synchronises the stream once to read the factorisation statuses. */
 DFISHER_API dfisher_status dfisher_solve_batched(dfisher_ctx* ctx, const float* S, int64_t n, int64_t m, int64_t lds,
                                      const double* lambdas, int32_t nlam, const float* V, int32_t nrhs,
                                      int64_t ldv, void* X, int64_t ldx, const dfisher_options* opt,
@@ -203,11 +208,22 @@ DFISHER_API dfisher_status dfisher_solve_batched(dfisher_ctx* ctx, const float* 
 /* Independent problems of different sizes (for example per-layer Fisher blocks): problem p
  * solves (S_p^T S_p + lambda_p I) x_p = v_p with S_p n[p] x m[p] (stride lds[p]). All arrays
  * of length nprob are HOST arrays of device pointers / sizes. infos (host, may be NULL) has
- * nprob entries. */
+ * nprob entries. Each problem follows Algorithm 1 as in dfisher_solve; the Cholesky
+ * factorisations and the triangular solves of all problems share launches, nothing waits for the
+ * host until the end, and the launch sequence is captured into a HIP graph and replayed on later
+ * calls with the same arguments (dfisher_ctx_enable_graphs). nprob <= 65535. A problem whose
+ * factorisation fails is then solved again on its own with the shift policy's escalation
+ * (DFISHER_SHIFT_ON_FAILURE / _ALWAYS; under _NONE the call returns DFISHER_E_NOT_SPD and that x
+ * is unspecified). Synchronises the stream once, plus once per problem solved again. */
 DFISHER_API dfisher_status dfisher_solve_uneven(dfisher_ctx* ctx, int32_t nprob, const float* const* S, const int64_t* n,
                                     const int64_t* m, const int64_t* lds, const float* const* v,
                                     const double* lambda, void* const* x, const dfisher_options* opt,
                                     void* stream, dfisher_info* infos);
+
+/* dfisher_solve_uneven captures its launch sequence into a HIP graph and replays it while the
+ * arguments (pointers, sizes, lambdas, options) and the context's buffers stay the same; enable = 0
+ * runs every call eagerly instead (and drops the cached graph). Default: enabled. */
+DFISHER_API dfisher_status dfisher_ctx_enable_graphs(dfisher_ctx* ctx, int32_t enable);
 
 /* Static text for a status code. */
 DFISHER_API const char* dfisher_status_string(dfisher_status s);

@@ -18,6 +18,7 @@ __all__ = [
     "DFISHER_E_UNSUPPORTED", "DFISHER_GRAM_FP32", "DFISHER_GRAM_BF16X3", "DFISHER_GRAM_MXFP8", "DFISHER_SHIFT_NONE",
     "DFISHER_SHIFT_ON_FAILURE", "DFISHER_SHIFT_ALWAYS",
     "dfisher_ctx_create", "dfisher_ctx_destroy", "dfisher_ctx_enable_timing", "dfisher_ctx_last_timing",
+    "dfisher_ctx_enable_graphs",
     "dfisher_gram", "dfisher_quantize_mxfp8", "dfisher_potrf", "dfisher_gemv",
     "dfisher_trsv", "dfisher_apply", "dfisher_solve", "dfisher_factor_create", "dfisher_factor_solve",
     "dfisher_factor_copy_L", "dfisher_factor_destroy", "dfisher_solve_batched", "dfisher_solve_uneven",
@@ -89,6 +90,7 @@ def _load():
         "dfisher_solve_uneven": ([P, I32, PP, ctypes.POINTER(I64), ctypes.POINTER(I64), ctypes.POINTER(I64), PP,
                                   ctypes.POINTER(D), PP, ctypes.POINTER(_Options), P, ctypes.POINTER(Info)], I32),
         "dfisher_ctx_enable_timing": ([P, I32], I32),
+        "dfisher_ctx_enable_graphs": ([P, I32], I32),
         "dfisher_ctx_last_timing": ([P, ctypes.POINTER(Timing)], I32),
         "dfisher_status_string": ([I32], ctypes.c_char_p),
         "dfisher_last_error": ([], ctypes.c_char_p),
@@ -217,6 +219,10 @@ def dfisher_ctx_destroy(ctx: _Handle) -> None:
 
 def dfisher_ctx_enable_timing(ctx, enable: bool = True) -> None:
     _check(_lib().dfisher_ctx_enable_timing(ctx.ptr, 1 if enable else 0), "dfisher_ctx_enable_timing")
+
+
+def dfisher_ctx_enable_graphs(ctx, enable: bool = True) -> None:
+    _check(_lib().dfisher_ctx_enable_graphs(ctx.ptr, 1 if enable else 0), "dfisher_ctx_enable_graphs")
 
 
 def dfisher_ctx_last_timing(ctx) -> dict:

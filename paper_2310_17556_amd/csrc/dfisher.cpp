@@ -65,6 +65,14 @@ struct dfisher_ctx {
   int64_t* d_info = nullptr;
   int32_t* d_flag = nullptr;
   double* d_scalar = nullptr;
+  // uneven batches: job tables (own buffer, never carved from ws) and the captured graph of the
+  // last call, replayed when the next call has the same arguments and buffers
+  bool graphs = true;
+  void* tbuf = nullptr;
+  size_t tbuf_bytes = 0;
+  hipStream_t cap_stream = nullptr;
+  hipGraphExec_t uneven_exec = nullptr;
+  std::vector<uint64_t> uneven_key;
 };
 
 struct dfisher_factor {
@@ -103,8 +111,11 @@ struct DeviceGuard {
   }
 };
 
+void drop_graph(dfisher_ctx* ctx);
+
 dfisher_status ensure_ws(dfisher_ctx* ctx, size_t bytes) {
   if (bytes <= ctx->ws_bytes) return DFISHER_OK;
+  drop_graph(ctx);   // a cached graph points into the old workspace
   if (ctx->ws) {
     HIP_TRY(hipDeviceSynchronize());
     HIP_TRY(hipFree(ctx->ws));
@@ -403,6 +414,292 @@ dfisher_status multi_solve(const float* S, int64_t n, int64_t m, int64_t lds, in
   return DFISHER_OK;
 }
 
+// ----------------------------------------------------------------------------- uneven batches
+// Independent problems of different sizes (per-layer Fisher blocks). Every problem runs the same
+// steps as dfisher_solve, but the latency-bound steps of all problems share launches: one grouped
+// Cholesky over all W_p, one grouped set of triangular solves per application of L^-1 / L^-T, and
+// one update of all y_p. The streaming passes and Gram kernels run per problem, largest first,
+// back to back on one stream with shared scratch. Nothing in between waits for the host, so the
+// whole sequence is captured once into a HIP graph and replayed while the arguments stay the same.
+// Factorisations are first tried with the policy's initial shift (none, or the up-front shift);
+// after the run, problems whose factorisation failed are solved again on their own by
+// dfisher_solve, which escalates the shift.
+
+void drop_graph(dfisher_ctx* ctx) {
+  if (ctx->uneven_exec) (void)hipGraphExecDestroy(ctx->uneven_exec);
+  ctx->uneven_exec = nullptr;
+  ctx->uneven_key.clear();
+}
+
+dfisher_status ensure_tbuf(dfisher_ctx* ctx, size_t bytes) {
+  if (bytes <= ctx->tbuf_bytes) return DFISHER_OK;
+  drop_graph(ctx);   // the cached graph points into the old buffer
+  if (ctx->tbuf) {
+    HIP_TRY(hipDeviceSynchronize());
+    HIP_TRY(hipFree(ctx->tbuf));
+    ctx->tbuf = nullptr;
+    ctx->tbuf_bytes = 0;
+  }
+  if (hipMalloc(&ctx->tbuf, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    ctx->tbuf = nullptr;
+    return fail(DFISHER_E_NO_MEMORY, "job table allocation failed");
+  }
+  ctx->tbuf_bytes = bytes;
+  return DFISHER_OK;
+}
+
+struct UnevenLayout {
+  std::vector<dfi::GramPlan> gp;
+  std::vector<dfi::RowPassPlan> rp;
+  std::vector<dfi::ColPassPlan> cp;
+  std::vector<int64_t> voff, woff, doff;   // offsets of problem p in the concatenated vectors / matrices
+  int64_t ntot = 0, nmax = 0, mmax = 0;
+  SolveBufs shared{};                      // scratch reused by every problem (largest sizes)
+  double *W = nullptr, *Dinv = nullptr, *dkk = nullptr, *dmax = nullptr;
+  double *b = nullptr, *d = nullptr, *y = nullptr, *z = nullptr, *r = nullptr, *wk = nullptr;
+  int64_t* info = nullptr;
+  int32_t* flag = nullptr;
+  size_t bytes = 0;
+};
+
+void uneven_layout(char* base, int32_t np, const float* const* S, const int64_t* n, const int64_t* m,
+                   const int64_t* lds, int prec, int sweeps, UnevenLayout& U) {
+  U.gp.clear();
+  U.rp.clear();
+  U.cp.clear();
+  U.voff.assign((size_t)np, 0);
+  U.woff.assign((size_t)np, 0);
+  U.doff.assign((size_t)np, 0);
+  U.ntot = U.nmax = U.mmax = 0;
+  int64_t wtot = 0, dtot = 0;
+  size_t gpart = 0, rpart = 0, cpart = 0, q8 = 0, sc8 = 0, planes = 0;
+  for (int32_t p = 0; p < np; ++p) {
+    U.gp.push_back(dfi::gram_plan(n[p], m[p], lds[p], prec, rows_aligned16(S[p], lds[p])));
+    U.rp.push_back(dfi::rowpass_plan(n[p], m[p], lds[p]));
+    U.cp.push_back(dfi::colpass_plan(n[p], m[p]));
+    U.voff[(size_t)p] = U.ntot;
+    U.woff[(size_t)p] = wtot;
+    U.doff[(size_t)p] = dtot;
+    U.ntot += n[p];
+    wtot += n[p] * n[p];
+    dtot += (int64_t)(dfi::trsv_dinv_bytes(n[p]) / sizeof(double));
+    U.nmax = std::max(U.nmax, n[p]);
+    U.mmax = std::max(U.mmax, m[p]);
+    gpart = std::max(gpart, U.gp.back().part_bytes);
+    rpart = std::max(rpart, U.rp.back().part_bytes);
+    cpart = std::max(cpart, U.cp.back().part_bytes);
+    const int64_t ldq = dfi::fp8_ldq(m[p]);
+    if (prec == DFISHER_GRAM_MXFP8) {
+      q8 = std::max(q8, (size_t)(n[p] * ldq));
+      sc8 = std::max(sc8, (size_t)(n[p] * (ldq / 32)));
+    }
+    if (U.gp.back().ldh > 0) planes = std::max(planes, (size_t)(n[p] * U.gp.back().ldh));
+  }
+  Carver c;
+  c.base = base;
+  SolveBufs& B = U.shared;
+  B = SolveBufs{};
+  B.gpart = c.take<float>(gpart / sizeof(float) + 1);
+  B.rpart = c.take<double>(rpart / sizeof(double) + 1);
+  B.cpart = c.take<double>(cpart / sizeof(double) + 1);
+  B.t = sweeps > 0 ? c.take<double>((size_t)U.mmax) : nullptr;
+  B.q8 = q8 ? c.take<uint8_t>(q8) : nullptr;
+  B.sc8 = sc8 ? c.take<uint8_t>(sc8) : nullptr;
+  B.hi = planes ? c.take<uint16_t>(planes) : nullptr;
+  B.lo = planes ? c.take<uint16_t>(planes) : nullptr;
+  U.W = c.take<double>((size_t)wtot);
+  U.Dinv = c.take<double>((size_t)dtot);
+  U.dkk = c.take<double>((size_t)np * 64 * 64);
+  U.dmax = c.take<double>((size_t)np);
+  U.b = c.take<double>((size_t)U.ntot);
+  U.d = c.take<double>((size_t)U.ntot);
+  U.y = c.take<double>((size_t)U.ntot);
+  U.z = c.take<double>((size_t)U.ntot);
+  U.r = c.take<double>((size_t)U.ntot);
+  U.wk = c.take<double>((size_t)U.ntot);
+  U.info = c.take<int64_t>((size_t)np);
+  U.flag = c.take<int32_t>((size_t)np);
+  U.bytes = c.off;
+}
+
+// Enqueues the whole uneven solve on st (no host synchronisation). fjobs / tjobs: device tables.
+dfisher_status uneven_enqueue(dfisher_ctx* ctx, int32_t np, const float* const* S, const int64_t* n, const int64_t* m,
+                              const int64_t* lds, const float* const* v, const double* lambda, void* const* x,
+                              const dfisher_options& o, const UnevenLayout& U, const std::vector<int32_t>& order,
+                              const dfi::FactorJob* fjobs, const dfi::TrsvJob* tj_fwd, const dfi::TrsvJob* tj_bwd,
+                              const dfi::TrsvJob* tj_bwd_r, hipStream_t st) {
+  (void)ctx;
+  // Gram stage per problem, largest first: b_p = S_p v_p, d_p, W_p = S_p S_p^T + lambda_p I
+  for (int32_t p : order) {
+    SolveBufs B = U.shared;
+    B.b = U.b + U.voff[(size_t)p];
+    B.d = U.d + U.voff[(size_t)p];
+    B.ldq = dfi::fp8_ldq(m[p]);
+    if (U.gp[(size_t)p].ldh == 0) B.hi = B.lo = nullptr;   // this problem splits inside the tile kernel
+    DF_TRY(gram_stage(S[p], v[p], U.gp[(size_t)p], U.rp[(size_t)p], B, lambda[p], U.W + U.woff[(size_t)p], 0, st,
+                      nullptr));
+    if (o.shift_policy == DFISHER_SHIFT_ALWAYS) {
+      double* Wp = U.W + U.woff[(size_t)p];
+      const double scale = 2.0 * std::sqrt((double)n[p]) * gram_unit(o.gram_prec, m[p]);
+      HIP_TRY(dfi::diag_max(Wp, n[p], U.dmax + p, st));
+      HIP_TRY(dfi::shift_add_copy(Wp, Wp, n[p], scale, U.dmax + p, 0.0, st));
+    }
+  }
+  // all Cholesky factorisations in the same launches (in place), then the diagonal-block inverses
+  HIP_TRY(dfi::potrf_launch_grouped(fjobs, np, U.nmax, st));
+  HIP_TRY(dfi::trsv_diag_inv_grouped(tj_fwd, np, U.nmax, st));
+  const size_t vb = (size_t)U.ntot * sizeof(double);
+  // y = L^-T L^-1 b for every problem (wk is each solve's reduced right-hand side)
+  HIP_TRY(hipMemcpyAsync(U.wk, U.b, vb, hipMemcpyDeviceToDevice, st));
+  HIP_TRY(dfi::trsv_launch_grouped(tj_fwd, np, U.nmax, 0, st));    // wk -> z
+  HIP_TRY(hipMemcpyAsync(U.wk, U.z, vb, hipMemcpyDeviceToDevice, st));
+  HIP_TRY(dfi::trsv_launch_grouped(tj_bwd, np, U.nmax, 1, st));    // wk -> y
+  for (int s = 0; s < o.sweeps; ++s) {
+    // r_p = b_p - lambda_p y_p - S_p (S_p^T y_p), per problem (FP64 accumulation)
+    for (int32_t p : order) {
+      const int64_t off = U.voff[(size_t)p];
+      HIP_TRY(dfi::colpass_launch(U.cp[(size_t)p], S[p], n[p], m[p], lds[p], U.y + off, nullptr, 1.0, U.shared.t, 2,
+                                  U.shared.cpart, st));
+      HIP_TRY(dfi::rowpass_launch(U.rp[(size_t)p], S[p], nullptr, U.shared.t, true, false, U.shared.rpart, st));
+      HIP_TRY(dfi::rowpass_reduce(U.rp[(size_t)p], U.shared.rpart, true, false, U.r + off, nullptr, U.b + off,
+                                  U.y + off, lambda[p], st));
+    }
+    // delta = L^-T L^-1 r for every problem, y += delta
+    HIP_TRY(hipMemcpyAsync(U.wk, U.r, vb, hipMemcpyDeviceToDevice, st));
+    HIP_TRY(dfi::trsv_launch_grouped(tj_fwd, np, U.nmax, 0, st));
+    HIP_TRY(hipMemcpyAsync(U.wk, U.z, vb, hipMemcpyDeviceToDevice, st));
+    HIP_TRY(dfi::trsv_launch_grouped(tj_bwd_r, np, U.nmax, 1, st));  // wk -> r
+    HIP_TRY(dfi::axpy_many(U.y, U.r, U.ntot, st));
+  }
+  // x_p = (v_p - S_p^T y_p) / lambda_p
+  for (int32_t p : order)
+    HIP_TRY(dfi::colpass_launch(U.cp[(size_t)p], S[p], n[p], m[p], lds[p], U.y + U.voff[(size_t)p], v[p], lambda[p],
+                                x[p], o.x_fp64, U.shared.cpart, st));
+  return DFISHER_OK;
+}
+
+dfisher_status uneven_solve(dfisher_ctx* ctx, int32_t np, const float* const* S, const int64_t* n, const int64_t* m,
+                            const int64_t* lds, const float* const* v, const double* lambda, void* const* x,
+                            const dfisher_options& o, hipStream_t st, dfisher_info* infos) {
+  UnevenLayout U;
+  uneven_layout(nullptr, np, S, n, m, lds, o.gram_prec, o.sweeps, U);
+  DF_TRY(ensure_ws(ctx, U.bytes));
+  uneven_layout(static_cast<char*>(ctx->ws), np, S, n, m, lds, o.gram_prec, o.sweeps, U);
+  // largest problems first (their Gram kernels fill the device; small ones follow)
+  std::vector<int32_t> order((size_t)np);
+  for (int32_t p = 0; p < np; ++p) order[(size_t)p] = p;
+  std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+    return (double)n[a] * (double)n[a] * (double)m[a] > (double)n[b] * (double)n[b] * (double)m[b];
+  });
+  // job tables: factor jobs, forward solves (wk -> z, the first entry set also drives diag_inv)
+  // and backward solves (wk -> y for the first solve, wk -> r inside sweeps: two tables)
+  std::vector<dfi::FactorJob> fj((size_t)np);
+  std::vector<dfi::TrsvJob> tf((size_t)np), tb((size_t)np), tr((size_t)np);
+  for (int32_t p = 0; p < np; ++p) {
+    const size_t q = (size_t)p;
+    double* Wp = U.W + U.woff[q];
+    fj[q] = dfi::FactorJob{Wp, n[p], U.info + p, U.flag + p, U.dkk + (int64_t)p * 64 * 64};
+    tf[q] = dfi::TrsvJob{Wp, U.Dinv + U.doff[q], n[p], U.wk + U.voff[q], U.z + U.voff[q]};
+    tb[q] = dfi::TrsvJob{Wp, U.Dinv + U.doff[q], n[p], U.wk + U.voff[q], U.y + U.voff[q]};
+    tr[q] = dfi::TrsvJob{Wp, U.Dinv + U.doff[q], n[p], U.wk + U.voff[q], U.r + U.voff[q]};
+  }
+  const size_t fbytes = align_up(fj.size() * sizeof(dfi::FactorJob));
+  const size_t tbytes = align_up(tf.size() * sizeof(dfi::TrsvJob));
+  DF_TRY(ensure_tbuf(ctx, fbytes + 3 * tbytes));
+  char* tb0 = static_cast<char*>(ctx->tbuf);
+  auto* d_fj = reinterpret_cast<dfi::FactorJob*>(tb0);
+  auto* d_tf = reinterpret_cast<dfi::TrsvJob*>(tb0 + fbytes);
+  auto* d_tb = reinterpret_cast<dfi::TrsvJob*>(tb0 + fbytes + tbytes);
+  auto* d_tr = reinterpret_cast<dfi::TrsvJob*>(tb0 + fbytes + 2 * tbytes);
+  HIP_TRY(hipMemcpyAsync(d_fj, fj.data(), fj.size() * sizeof(dfi::FactorJob), hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(d_tf, tf.data(), tf.size() * sizeof(dfi::TrsvJob), hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(d_tb, tb.data(), tb.size() * sizeof(dfi::TrsvJob), hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(d_tr, tr.data(), tr.size() * sizeof(dfi::TrsvJob), hipMemcpyHostToDevice, st));
+  HIP_TRY(hipStreamSynchronize(st));   // the host tables go out of scope; the graph reads the device copies
+
+  // the run: replay the captured graph if every argument and buffer is unchanged
+  std::vector<uint64_t> key;
+  auto put = [&](const void* pp, size_t nbytes) {
+    const auto* c = static_cast<const unsigned char*>(pp);
+    for (size_t i = 0; i < nbytes; i += 8) {
+      uint64_t w = 0;
+      std::memcpy(&w, c + i, std::min<size_t>(8, nbytes - i));
+      key.push_back(w);
+    }
+  };
+  put(&np, sizeof(np));
+  put(S, sizeof(void*) * (size_t)np);
+  put(n, sizeof(int64_t) * (size_t)np);
+  put(m, sizeof(int64_t) * (size_t)np);
+  put(lds, sizeof(int64_t) * (size_t)np);
+  put(v, sizeof(void*) * (size_t)np);
+  put(lambda, sizeof(double) * (size_t)np);
+  put(x, sizeof(void*) * (size_t)np);
+  put(&o, sizeof(o));
+  put(&ctx->ws, sizeof(void*));
+  put(&ctx->tbuf, sizeof(void*));
+  bool ran = false;
+  if (ctx->graphs) {
+    if (!ctx->uneven_exec || ctx->uneven_key != key) {
+      drop_graph(ctx);
+      if (!ctx->cap_stream && hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+        (void)hipGetLastError();
+        ctx->cap_stream = nullptr;
+      }
+      if (ctx->cap_stream) {
+        hipGraph_t graph = nullptr;
+        bool ok = hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal) == hipSuccess;
+        dfisher_status se = DFISHER_OK;
+        if (ok)
+          se = uneven_enqueue(ctx, np, S, n, m, lds, v, lambda, x, o, U, order, d_fj, d_tf, d_tb, d_tr, ctx->cap_stream);
+        if (ok) ok = hipStreamEndCapture(ctx->cap_stream, &graph) == hipSuccess && graph != nullptr;
+        if (ok && se == DFISHER_OK) {
+          hipGraphExec_t ex = nullptr;
+          if (hipGraphInstantiate(&ex, graph, nullptr, nullptr, 0) == hipSuccess) {
+            ctx->uneven_exec = ex;
+            ctx->uneven_key = key;
+          }
+        }
+        if (graph) (void)hipGraphDestroy(graph);
+        (void)hipGetLastError();   // a failed capture leaves the eager path below
+      }
+    }
+    if (ctx->uneven_exec) {
+      HIP_TRY(hipGraphLaunch(ctx->uneven_exec, st));
+      ran = true;
+    }
+  }
+  if (!ran) DF_TRY(uneven_enqueue(ctx, np, S, n, m, lds, v, lambda, x, o, U, order, d_fj, d_tf, d_tb, d_tr, st));
+  std::vector<int64_t> hinfo((size_t)np);
+  std::vector<double> hmax((size_t)np, 0.0);
+  HIP_TRY(hipMemcpyAsync(hinfo.data(), U.info, (size_t)np * sizeof(int64_t), hipMemcpyDeviceToHost, st));
+  if (o.shift_policy == DFISHER_SHIFT_ALWAYS)
+    HIP_TRY(hipMemcpyAsync(hmax.data(), U.dmax, (size_t)np * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  dfisher_status worst = DFISHER_OK;
+  for (int32_t p = 0; p < np; ++p) {
+    dfisher_info inf{};
+    inf.potrf_info = hinfo[(size_t)p];
+    inf.attempts = 1;
+    inf.sweeps_done = o.sweeps;
+    if (o.shift_policy == DFISHER_SHIFT_ALWAYS)
+      inf.shift = 2.0 * std::sqrt((double)n[p]) * gram_unit(o.gram_prec, m[p]) * hmax[(size_t)p];
+    if (inf.potrf_info != 0 && o.shift_policy != DFISHER_SHIFT_NONE) {
+      // solve this problem again on its own with the escalating shift (uses the workspace anew)
+      dfisher_info again{};
+      const dfisher_status s2 = dfisher_solve(ctx, S[p], n[p], m[p], lds[p], v[p], lambda[p], x[p], &o, st, &again);
+      again.attempts += 1;
+      inf = again;
+      if (s2 != DFISHER_OK && s2 != DFISHER_E_NOT_SPD) return s2;
+    }
+    if (inf.potrf_info != 0) worst = DFISHER_E_NOT_SPD;
+    if (infos) infos[p] = inf;
+  }
+  if (worst != DFISHER_OK) return fail(worst, "at least one problem failed to factor (its x is not meaningful)");
+  return DFISHER_OK;
+}
+
 // Per-device kernel set-up (called with the device current). Nothing to do at present.
 dfisher_status init_kernels() { return DFISHER_OK; }
 
@@ -473,6 +770,9 @@ dfisher_status dfisher_ctx_destroy(dfisher_ctx* ctx) {
   if (!ctx) return DFISHER_OK;
   DeviceGuard g(ctx->device);
   (void)hipDeviceSynchronize();
+  drop_graph(ctx);
+  if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
+  if (ctx->tbuf) (void)hipFree(ctx->tbuf);
   if (ctx->ws) (void)hipFree(ctx->ws);
   for (int i = 0; i < NEV; ++i)
     if (ctx->ev[i]) (void)hipEventDestroy(ctx->ev[i]);
@@ -869,6 +1169,7 @@ dfisher_status dfisher_solve_uneven(dfisher_ctx* ctx, int32_t nprob, const float
                                     void* const* x, const dfisher_options* opt, void* stream, dfisher_info* infos) {
   DF_TRY(check_ctx(ctx));
   if (nprob < 1) return fail(DFISHER_E_INVALID_ARG, "nprob = %d < 1", nprob);
+  if (nprob > 65535) return fail(DFISHER_E_UNSUPPORTED, "nprob = %d > 65535", nprob);
   if (!S || !n || !m || !lds || !v || !lambda || !x) return fail(DFISHER_E_INVALID_ARG, "NULL array argument");
   dfisher_options o;
   DF_TRY(check_opt(opt, &o));
@@ -877,16 +1178,18 @@ dfisher_status dfisher_solve_uneven(dfisher_ctx* ctx, int32_t nprob, const float
     if (s != DFISHER_OK) return fail(s, "problem %d: %s", p, g_last_error.c_str());
     if (!v[p] || !x[p]) return fail(DFISHER_E_INVALID_ARG, "problem %d: v or x is NULL", p);
     if (!finite_pos(lambda[p])) return fail(DFISHER_E_INVALID_ARG, "problem %d: lambda must be finite and > 0", p);
+    s = check_prec_layout(o.gram_prec, S[p], lds[p]);
+    if (s != DFISHER_OK) return fail(s, "problem %d: %s", p, g_last_error.c_str());
   }
-  dfisher_status worst = DFISHER_OK;
-  for (int32_t p = 0; p < nprob; ++p) {
-    dfisher_info inf{};
-    dfisher_status s = dfisher_solve(ctx, S[p], n[p], m[p], lds[p], v[p], lambda[p], x[p], &o, stream, &inf);
-    if (infos) infos[p] = inf;
-    if (s == DFISHER_E_NOT_SPD) worst = s;
-    else if (s != DFISHER_OK) return s;
-  }
-  if (worst != DFISHER_OK) return fail(worst, "at least one problem failed to factor");
+  DeviceGuard g(ctx->device);
+  hipStream_t st = as_stream(stream);
+  return uneven_solve(ctx, nprob, S, n, m, lds, v, lambda, x, o, st, infos);
+}
+
+dfisher_status dfisher_ctx_enable_graphs(dfisher_ctx* ctx, int32_t enable) {
+  DF_TRY(check_ctx(ctx));
+  ctx->graphs = enable != 0;
+  if (!ctx->graphs) drop_graph(ctx);
   return DFISHER_OK;
 }
 

@@ -27,6 +27,19 @@ struct GramPlan {
 // split-BF16 on aligned rows the plan uses planes hi/lo written by the row pass (ldh > 0).
 GramPlan gram_plan(int64_t n, int64_t m, int64_t lds, int prec, bool aligned16);
 hipError_t gram_launch(const GramPlan& p, const float* S, float* part, hipStream_t st);
+// One problem of a grouped Gram launch (several independent Grams in one launch). a, b: the FP8
+// codes and scales (prec 2) or the hi and lo planes (prec 1) in the row pass's column-blocked
+// layout; kcap: m rounded down to 16 (prec 2) or 8 (prec 1); part: that problem's partial tiles;
+// wg_begin: its first workgroup (sorted ascending, each job's count nslice * ntri a multiple of 8).
+struct GramJob {
+  const void* a;
+  const void* b;
+  float* part;
+  int64_t n, kcap, ntri, nslice, kslice, wg_begin;
+};
+hipError_t gram_launch_grouped(int prec, const GramJob* jobs_dev, int njobs, int64_t total_wg, hipStream_t st);
+// The first column the tile kernel of plan p leaves to gram_reduce.
+int64_t gram_tail_start(const GramPlan& p, const float* S);
 // Row stride (bf16 elements) of the split-BF16 planes for m columns.
 inline int64_t split_ldh(int64_t m) { return (m + 63) / 64 * 64; }
 // Split-BF16 Gram from the column-blocked planes hi = bf16(S), lo = bf16(S - hi) (p.ldh > 0).
@@ -131,6 +144,16 @@ hipError_t potrf_launch(double* A, int64_t n, int64_t* info_dev, int32_t* flag_d
 // flag_dev[b], dkk + b 64 * 64 (nbatch <= 65535).
 hipError_t potrf_launch_batched(double* A, int64_t n, int64_t nbatch, int64_t sA, int64_t* info_dev, int32_t* flag_dev,
                                 double* dkk, hipStream_t st);
+// Matrices of different sizes in the same launches: one job per matrix (device table, njobs <= 65535),
+// nmax = the largest n. Each job's info / flag are cleared first.
+struct FactorJob {
+  double* A;         // n x n, factored in place
+  int64_t n;
+  int64_t* info;     // 0 or the 1-based index of the first bad pivot
+  int32_t* flag;     // stop flag
+  double* dkk;       // 64 x 64 scratch
+};
+hipError_t potrf_launch_grouped(const FactorJob* jobs_dev, int64_t njobs, int64_t nmax, hipStream_t st);
 
 // ----------------------------------------------------------------------------- triangular solves
 // Inverses of the 64 x 64 diagonal blocks of L (Dinv: trsv_dinv_bytes(n)), computed once per factor.
@@ -145,6 +168,18 @@ hipError_t trsv_diag_inv_batched(const double* L, int64_t sL, int64_t n, int64_t
 // launches; vector j uses factor j / nper. nvec <= 65535.
 hipError_t trsv_launch_batched(const double* L, int64_t sL, const double* Dinv, int64_t n, int64_t nvec, int64_t nper,
                                int trans, const double* b, double* y, double* work, hipStream_t st);
+// Systems of different sizes in the same launches (device job table, njobs <= 65535; nmax = the
+// largest n). diag_inv: Dinv of each L. Solve: r holds the right-hand side on entry and is reduced
+// in place (it is the work vector); the solution goes to out (not aliasing r).
+struct TrsvJob {
+  const double* L;
+  double* Dinv;
+  int64_t n;
+  double* r;
+  double* out;
+};
+hipError_t trsv_diag_inv_grouped(const TrsvJob* jobs_dev, int64_t njobs, int64_t nmax, hipStream_t st);
+hipError_t trsv_launch_grouped(const TrsvJob* jobs_dev, int64_t njobs, int64_t nmax, int trans, hipStream_t st);
 
 // ----------------------------------------------------------------------------- small helpers
 // dst = src + scale * dmax[0] * I (n x n, row-major; dmax a device scalar, unread if scale == 0).

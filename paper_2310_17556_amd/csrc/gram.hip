@@ -55,6 +55,19 @@ __device__ __forceinline__ void tri_index(int64_t t, int64_t& ti, int64_t& tj) {
   tj = t - r * (r + 1) / 2;
 }
 
+// Grouped launches: workgroup w belongs to the job with the largest wg_begin <= w (binary search
+// over the sorted table; the result is uniform across the workgroup). Every job's workgroup count
+// is a multiple of 8, so w - wg_begin keeps the XCD assignment w mod 8.
+__device__ __forceinline__ int find_job(const GramJob* __restrict__ jobs, int njobs, int64_t w) {
+  int lo = 0, hi = njobs - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (jobs[mid].wg_begin <= w) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
 // Global -> register staging for one 256-row panel and one k-step.
 // Thread t loads rows (t / 8) + 64 i, columns 4 (t % 8) .. +3 of the step.
 template <bool VEC>
@@ -587,12 +600,27 @@ __device__ __forceinline__ i32x8 read_frag(const uint8_t* panel, int r, int h) {
 // vmcnt(N) with the other counters left alone (gfx9 encoding: vmcnt bits [3:0] and [15:14]).
 #define DFI_WAIT_VM(N) __builtin_amdgcn_s_waitcnt(((N) & 15) | (((N) >> 4) << 14) | (7 << 4) | (15 << 8))
 
+// G = true: a grouped launch over jobs[0 .. njobs) (the scalar arguments are then ignored).
+template <bool G>
 __global__ void __launch_bounds__(NT, 1)
 gram_kernel_fp8(const uint8_t* __restrict__ q, const uint8_t* __restrict__ sc, int64_t n, int64_t m16,
-                int64_t ntri, int64_t nslice, int64_t kslice, float* __restrict__ part) {
+                int64_t ntri, int64_t nslice, int64_t kslice, float* __restrict__ part, const GramJob* __restrict__ jobs,
+                int njobs) {
   __shared__ Stage stg0, stg1, stg2, stg3;
 
-  const int64_t w = blockIdx.x;
+  int64_t w = blockIdx.x;
+  if constexpr (G) {
+    const GramJob& jb = jobs[find_job(jobs, njobs, w)];
+    q = static_cast<const uint8_t*>(jb.a);
+    sc = static_cast<const uint8_t*>(jb.b);
+    n = jb.n;
+    m16 = jb.kcap;
+    ntri = jb.ntri;
+    nslice = jb.nslice;
+    kslice = jb.kslice;
+    part = jb.part;
+    w -= jb.wg_begin;
+  }
   const int64_t xcd = w & 7;
   const int64_t local = w >> 3;
   const int64_t qq = local / ntri;
@@ -758,12 +786,27 @@ __device__ __forceinline__ bf16x8 read_bf(const uint8_t* panel, int r, int h) {
   return *reinterpret_cast<const bf16x8*>(panel + r * ROWB + 16 * (h ^ ((r >> 2) & 1)));
 }
 
+// G = true: a grouped launch over jobs[0 .. njobs) (the scalar arguments are then ignored).
+template <bool G>
 __global__ void __launch_bounds__(NT, 1)
 gram_kernel_split(const uint16_t* __restrict__ hi, const uint16_t* __restrict__ lo, int64_t n,
-                  int64_t m8, int64_t ntri, int64_t nslice, int64_t kslice, float* __restrict__ part) {
+                  int64_t m8, int64_t ntri, int64_t nslice, int64_t kslice, float* __restrict__ part,
+                  const GramJob* __restrict__ jobs, int njobs) {
   __shared__ Stage stg0, stg1, stg2, stg3;
 
-  const int64_t w = blockIdx.x;
+  int64_t w = blockIdx.x;
+  if constexpr (G) {
+    const GramJob& jb = jobs[find_job(jobs, njobs, w)];
+    hi = static_cast<const uint16_t*>(jb.a);
+    lo = static_cast<const uint16_t*>(jb.b);
+    n = jb.n;
+    m8 = jb.kcap;
+    ntri = jb.ntri;
+    nslice = jb.nslice;
+    kslice = jb.kslice;
+    part = jb.part;
+    w -= jb.wg_begin;
+  }
   const int64_t xcd = w & 7;
   const int64_t local = w >> 3;
   const int64_t qq = local / ntri;
@@ -924,16 +967,30 @@ hipError_t gram_launch_fp8(const GramPlan& p, const uint8_t* q, const uint8_t* s
                            hipStream_t st) {
   const dim3 grid((unsigned)(p.nslice * p.ntri));
   if ((ldq & 127) != 0 || ldq < p.m) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(v3::gram_kernel_fp8, grid, dim3(v3::NT), 0, st, q, sc, p.n, p.m & ~(int64_t)15, p.ntri,
-                     p.nslice, p.kslice, part);
+  hipLaunchKernelGGL(v3::gram_kernel_fp8<false>, grid, dim3(v3::NT), 0, st, q, sc, p.n, p.m & ~(int64_t)15, p.ntri,
+                     p.nslice, p.kslice, part, (const GramJob*)nullptr, 0);
   return hipGetLastError();
 }
 
 hipError_t gram_launch_split(const GramPlan& p, const uint16_t* hi, const uint16_t* lo, float* part, hipStream_t st) {
   if (p.prec != 1 || p.ldh <= 0 || (p.ldh & 63) != 0) return hipErrorInvalidValue;
   const dim3 grid((unsigned)(p.nslice * p.ntri));
-  hipLaunchKernelGGL(v4::gram_kernel_split, grid, dim3(v4::NT), 0, st, hi, lo, p.n, p.m & ~(int64_t)7, p.ntri,
-                     p.nslice, p.kslice, part);
+  hipLaunchKernelGGL(v4::gram_kernel_split<false>, grid, dim3(v4::NT), 0, st, hi, lo, p.n, p.m & ~(int64_t)7, p.ntri,
+                     p.nslice, p.kslice, part, (const GramJob*)nullptr, 0);
+  return hipGetLastError();
+}
+
+hipError_t gram_launch_grouped(int prec, const GramJob* jobs_dev, int njobs, int64_t total_wg, hipStream_t st) {
+  if (njobs < 1 || total_wg < 1 || (total_wg & 7) != 0 || total_wg > 0x7fffffff) return hipErrorInvalidValue;
+  const dim3 grid((unsigned)total_wg);
+  if (prec == 2)
+    hipLaunchKernelGGL(v3::gram_kernel_fp8<true>, grid, dim3(v3::NT), 0, st, (const uint8_t*)nullptr,
+                       (const uint8_t*)nullptr, 0, 0, 0, 0, 0, (float*)nullptr, jobs_dev, njobs);
+  else if (prec == 1)
+    hipLaunchKernelGGL(v4::gram_kernel_split<true>, grid, dim3(v4::NT), 0, st, (const uint16_t*)nullptr,
+                       (const uint16_t*)nullptr, 0, 0, 0, 0, 0, (float*)nullptr, jobs_dev, njobs);
+  else
+    return hipErrorInvalidValue;
   return hipGetLastError();
 }
 
@@ -952,6 +1009,8 @@ static int64_t tail_start(const GramPlan& p, const float* S) {
   if (p.prec == 1 && p.ldh > 0) return p.m & ~(int64_t)7;
   return use_v2(p, S) ? (p.m & ~(int64_t)3) : p.m;
 }
+
+int64_t gram_tail_start(const GramPlan& p, const float* S) { return tail_start(p, S); }
 
 hipError_t gram_launch(const GramPlan& p, const float* S, float* part, hipStream_t st) {
   const bool vec = ((p.lds & 3) == 0) && ((reinterpret_cast<uintptr_t>(S) & 15) == 0);

@@ -24,13 +24,23 @@ constexpr int LDP = NB + 1;  // padded LDS row (doubles)
 
 __global__ void __launch_bounds__(64)
 potf2_kernel(double* __restrict__ A, int64_t n, int64_t k, int64_t* __restrict__ info, int32_t* __restrict__ flag,
-             double* __restrict__ Dkk, int64_t sA) {
+             double* __restrict__ Dkk, int64_t sA, const FactorJob* __restrict__ jobs) {
   __shared__ double a[NB * LDP];
   const int64_t bb = blockIdx.y;
-  A += bb * sA;
-  info += bb;
-  flag += bb;
-  Dkk += bb * NB * NB;
+  if (jobs) {
+    const FactorJob& j = jobs[bb];
+    A = j.A;
+    n = j.n;
+    info = j.info;
+    flag = j.flag;
+    Dkk = j.dkk;
+    if (k >= n) return;
+  } else {
+    A += bb * sA;
+    info += bb;
+    flag += bb;
+    Dkk += bb * NB * NB;
+  }
   if (*(volatile int32_t*)flag) return;
   const int lane = threadIdx.x;
   const int64_t nb = min<int64_t>(NB, n - k);
@@ -86,16 +96,25 @@ potf2_kernel(double* __restrict__ A, int64_t n, int64_t k, int64_t* __restrict__
 // 64 rows per workgroup, 256 threads with 4 x 4 outputs each.
 __global__ void __launch_bounds__(256)
 trsm_kernel(double* __restrict__ A, int64_t n, int64_t k, const int32_t* __restrict__ flag,
-            const double* __restrict__ Dkk, int64_t sA) {
+            const double* __restrict__ Dkk, int64_t sA, const FactorJob* __restrict__ jobs) {
   __shared__ double Ab[NB * LDP];
   __shared__ double Db[NB * LDP];
   const int64_t bb = blockIdx.y;
-  A += bb * sA;
-  flag += bb;
-  Dkk += bb * NB * NB;
-  if (*(volatile const int32_t*)flag) return;
+  if (jobs) {
+    const FactorJob& j = jobs[bb];
+    A = j.A;
+    n = j.n;
+    flag = j.flag;
+    Dkk = j.dkk;
+  } else {
+    A += bb * sA;
+    flag += bb;
+    Dkk += bb * NB * NB;
+  }
   const int tid = threadIdx.x;
   const int64_t row0 = k + NB + (int64_t)blockIdx.x * NB;
+  if (row0 >= n) return;   // grouped launches size the grid for the largest matrix
+  if (*(volatile const int32_t*)flag) return;
   for (int idx = tid; idx < NB * NB; idx += 256) {
     const int r = idx / NB, c = idx % NB;
     Ab[r * LDP + c] = (row0 + r < n) ? A[(row0 + r) * n + k + c] : 0.0;
@@ -134,11 +153,25 @@ trsm_kernel(double* __restrict__ A, int64_t n, int64_t k, const int32_t* __restr
 // MFMA lane layout (16x16x4 f64): A lane l = (row l%16, k l/16), B lane l = (k l/16, col l%16),
 // D lane l register r = (row l/16 + 4r, col l%16).
 __global__ void __launch_bounds__(256)
-update_kernel(double* __restrict__ A, int64_t n, int64_t k, const int32_t* __restrict__ flag, int64_t sA) {
+update_kernel(double* __restrict__ A, int64_t n, int64_t k, const int32_t* __restrict__ flag, int64_t sA,
+              const FactorJob* __restrict__ jobs) {
   __shared__ double PI[NB * LDP];
   __shared__ double PJ[NB * LDP];
-  A += (int64_t)blockIdx.y * sA;
-  flag += blockIdx.y;
+  if (jobs) {
+    const FactorJob& j = jobs[blockIdx.y];
+    A = j.A;
+    n = j.n;
+    flag = j.flag;
+  } else {
+    A += (int64_t)blockIdx.y * sA;
+    flag += blockIdx.y;
+  }
+  if (k + NB >= n) return;
+  {
+    // tiles of this matrix's trailing triangle: rb (rb + 1) / 2 of the grid's
+    const int64_t rb = (n - k - NB + NB - 1) / NB;
+    if ((int64_t)blockIdx.x >= rb * (rb + 1) / 2) return;
+  }
   if (*(volatile const int32_t*)flag) return;
   const int64_t t = blockIdx.x;
   int64_t I = (int64_t)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
@@ -241,13 +274,43 @@ hipError_t potrf_launch_batched(double* A, int64_t n, int64_t nbatch, int64_t sA
   const unsigned nb = (unsigned)nbatch;
   hipLaunchKernelGGL(clear_status_kernel, dim3((unsigned)((nbatch + 255) / 256)), dim3(256), 0, st, info_dev, flag_dev,
                      nbatch);
+  const FactorJob* nj = nullptr;
   for (int64_t k = 0; k < n; k += NB) {
-    hipLaunchKernelGGL(potf2_kernel, dim3(1, nb), dim3(64), 0, st, A, n, k, info_dev, flag_dev, dkk, sA);
+    hipLaunchKernelGGL(potf2_kernel, dim3(1, nb), dim3(64), 0, st, A, n, k, info_dev, flag_dev, dkk, sA, nj);
     const int64_t rest = n - k - NB;
     if (rest > 0) {
       const int64_t rb = (rest + 63) / 64;
-      hipLaunchKernelGGL(trsm_kernel, dim3((unsigned)rb, nb), dim3(256), 0, st, A, n, k, flag_dev, (const double*)dkk, sA);
-      hipLaunchKernelGGL(update_kernel, dim3((unsigned)(rb * (rb + 1) / 2), nb), dim3(256), 0, st, A, n, k, flag_dev, sA);
+      hipLaunchKernelGGL(trsm_kernel, dim3((unsigned)rb, nb), dim3(256), 0, st, A, n, k, flag_dev, (const double*)dkk, sA,
+                         nj);
+      hipLaunchKernelGGL(update_kernel, dim3((unsigned)(rb * (rb + 1) / 2), nb), dim3(256), 0, st, A, n, k, flag_dev, sA,
+                         nj);
+    }
+  }
+  return hipGetLastError();
+}
+
+__global__ void clear_jobs_kernel(const FactorJob* __restrict__ jobs, int64_t njobs) {
+  const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (b < njobs) {
+    *jobs[b].info = 0;
+    *jobs[b].flag = 0;
+  }
+}
+
+hipError_t potrf_launch_grouped(const FactorJob* jobs_dev, int64_t njobs, int64_t nmax, hipStream_t st) {
+  if (njobs < 1 || njobs > 65535) return hipErrorInvalidValue;
+  const unsigned nb = (unsigned)njobs;
+  hipLaunchKernelGGL(clear_jobs_kernel, dim3((unsigned)((njobs + 255) / 256)), dim3(256), 0, st, jobs_dev, njobs);
+  for (int64_t k = 0; k < nmax; k += NB) {
+    hipLaunchKernelGGL(potf2_kernel, dim3(1, nb), dim3(64), 0, st, (double*)nullptr, (int64_t)0, k, (int64_t*)nullptr,
+                       (int32_t*)nullptr, (double*)nullptr, (int64_t)0, jobs_dev);
+    const int64_t rest = nmax - k - NB;
+    if (rest > 0) {
+      const int64_t rb = (rest + 63) / 64;
+      hipLaunchKernelGGL(trsm_kernel, dim3((unsigned)rb, nb), dim3(256), 0, st, (double*)nullptr, (int64_t)0, k,
+                         (const int32_t*)nullptr, (const double*)nullptr, (int64_t)0, jobs_dev);
+      hipLaunchKernelGGL(update_kernel, dim3((unsigned)(rb * (rb + 1) / 2), nb), dim3(256), 0, st, (double*)nullptr,
+                         (int64_t)0, k, (const int32_t*)nullptr, (int64_t)0, jobs_dev);
     }
   }
   return hipGetLastError();

@@ -25,10 +25,19 @@ constexpr int LDP = NB + 1;
 // D_k = inverse of the lower-triangular 64 x 64 block L_kk (identity-padded past n).
 // One 64-lane workgroup per block; lane c computes column c: x_c = e_c, x_i = -(sum_{c<=l<i} L_il x_l)/L_ii.
 __global__ void __launch_bounds__(64)
-diag_inv_kernel(const double* __restrict__ L, int64_t n, double* __restrict__ Dinv, int64_t sL, int64_t sD) {
+diag_inv_kernel(const double* __restrict__ L, int64_t n, double* __restrict__ Dinv, int64_t sL, int64_t sD,
+                const TrsvJob* __restrict__ jobs) {
   __shared__ double Lk[NB * LDP];
-  L += (int64_t)blockIdx.y * sL;
-  Dinv += (int64_t)blockIdx.y * sD;
+  if (jobs) {
+    const TrsvJob& j = jobs[blockIdx.y];
+    L = j.L;
+    Dinv = j.Dinv;
+    n = j.n;
+    if ((int64_t)blockIdx.x * NB >= n) return;
+  } else {
+    L += (int64_t)blockIdx.y * sL;
+    Dinv += (int64_t)blockIdx.y * sD;
+  }
   const int64_t k = blockIdx.x;
   const int64_t r0 = k * NB;
   const int c = threadIdx.x;
@@ -59,10 +68,20 @@ diag_inv_kernel(const double* __restrict__ L, int64_t n, double* __restrict__ Di
 // Grid: 1 + number of row blocks below k (at least 1). 256 threads.
 __global__ void __launch_bounds__(256)
 fwd_step_kernel(const double* __restrict__ L, int64_t n, const double* __restrict__ Dinv, int64_t k,
-                double* __restrict__ r, double* __restrict__ z, int64_t sL, int64_t sD, int64_t nper) {
+                double* __restrict__ r, double* __restrict__ z, int64_t sL, int64_t sD, int64_t nper,
+                const TrsvJob* __restrict__ jobs) {
   __shared__ double zk[NB];
   __shared__ double part[4][NB];
-  {
+  if (jobs) {
+    const TrsvJob& j = jobs[blockIdx.y];
+    L = j.L;
+    Dinv = j.Dinv;
+    n = j.n;
+    r = j.r;
+    z = j.out;
+    const int64_t nblk = (n + NB - 1) / NB;
+    if (k >= nblk || (int64_t)blockIdx.x >= nblk - k) return;   // grid sized for the largest system
+  } else {
     const int64_t j = blockIdx.y, f = j / nper;
     L += f * sL;
     Dinv += f * sD;
@@ -105,10 +124,19 @@ fwd_step_kernel(const double* __restrict__ L, int64_t n, const double* __restric
 // Backward step k. Grid: 1 + k (block k itself and the blocks J < k). 256 threads.
 __global__ void __launch_bounds__(256)
 bwd_step_kernel(const double* __restrict__ L, int64_t n, const double* __restrict__ Dinv, int64_t k,
-                double* __restrict__ r, double* __restrict__ y, int64_t sL, int64_t sD, int64_t nper) {
+                double* __restrict__ r, double* __restrict__ y, int64_t sL, int64_t sD, int64_t nper,
+                const TrsvJob* __restrict__ jobs) {
   __shared__ double yk[NB];
   __shared__ double part[4][NB];
-  {
+  if (jobs) {
+    const TrsvJob& j = jobs[blockIdx.y];
+    L = j.L;
+    Dinv = j.Dinv;
+    n = j.n;
+    r = j.r;
+    y = j.out;
+    if (k >= (n + NB - 1) / NB) return;   // this system's backward sweep starts at its own last block
+  } else {
     const int64_t j = blockIdx.y, f = j / nper;
     L += f * sL;
     Dinv += f * sD;
@@ -159,7 +187,7 @@ hipError_t trsv_diag_inv_batched(const double* L, int64_t sL, int64_t n, int64_t
   if (nfac < 1 || nfac > 65535) return hipErrorInvalidValue;
   const int64_t nblk = (n + NB - 1) / NB;
   hipLaunchKernelGGL(diag_inv_kernel, dim3((unsigned)nblk, (unsigned)nfac), dim3(64), 0, st, L, n, Dinv, sL,
-                     (int64_t)(trsv_dinv_bytes(n) / sizeof(double)));
+                     (int64_t)(trsv_dinv_bytes(n) / sizeof(double)), (const TrsvJob*)nullptr);
   return hipGetLastError();
 }
 
@@ -178,11 +206,37 @@ hipError_t trsv_launch_batched(const double* L, int64_t sL, const double* Dinv, 
   if (trans == 0) {
     for (int64_t k = 0; k < nblk; ++k)
       hipLaunchKernelGGL(fwd_step_kernel, dim3((unsigned)(nblk - k), nv), dim3(256), 0, st, L, n, Dinv, k, work, y, sL,
-                         sD, nper);
+                         sD, nper, (const TrsvJob*)nullptr);
   } else {
     for (int64_t k = nblk - 1; k >= 0; --k)
       hipLaunchKernelGGL(bwd_step_kernel, dim3((unsigned)(k + 1), nv), dim3(256), 0, st, L, n, Dinv, k, work, y, sL,
-                         sD, nper);
+                         sD, nper, (const TrsvJob*)nullptr);
+  }
+  return hipGetLastError();
+}
+
+hipError_t trsv_diag_inv_grouped(const TrsvJob* jobs_dev, int64_t njobs, int64_t nmax, hipStream_t st) {
+  if (njobs < 1 || njobs > 65535) return hipErrorInvalidValue;
+  const int64_t nblk = (nmax + NB - 1) / NB;
+  hipLaunchKernelGGL(diag_inv_kernel, dim3((unsigned)nblk, (unsigned)njobs), dim3(64), 0, st, (const double*)nullptr,
+                     (int64_t)0, (double*)nullptr, (int64_t)0, (int64_t)0, jobs_dev);
+  return hipGetLastError();
+}
+
+hipError_t trsv_launch_grouped(const TrsvJob* jobs_dev, int64_t njobs, int64_t nmax, int trans, hipStream_t st) {
+  if (njobs < 1 || njobs > 65535) return hipErrorInvalidValue;
+  const int64_t nblk = (nmax + NB - 1) / NB;
+  const unsigned nj = (unsigned)njobs;
+  if (trans == 0) {
+    for (int64_t k = 0; k < nblk; ++k)
+      hipLaunchKernelGGL(fwd_step_kernel, dim3((unsigned)(nblk - k), nj), dim3(256), 0, st, (const double*)nullptr,
+                         (int64_t)0, (const double*)nullptr, k, (double*)nullptr, (double*)nullptr, (int64_t)0,
+                         (int64_t)0, (int64_t)1, jobs_dev);
+  } else {
+    for (int64_t k = nblk - 1; k >= 0; --k)
+      hipLaunchKernelGGL(bwd_step_kernel, dim3((unsigned)(k + 1), nj), dim3(256), 0, st, (const double*)nullptr,
+                         (int64_t)0, (const double*)nullptr, k, (double*)nullptr, (double*)nullptr, (int64_t)0,
+                         (int64_t)0, (int64_t)1, jobs_dev);
   }
   return hipGetLastError();
 }
