@@ -225,6 +225,23 @@ DFISHER_API dfisher_status dfisher_solve_uneven(dfisher_ctx* ctx, int32_t nprob,
  * runs every call eagerly instead (and drops the cached graph). Default: enabled. */
 DFISHER_API dfisher_status dfisher_ctx_enable_graphs(dfisher_ctx* ctx, int32_t enable);
 
+/* Gram autotuning. The split-K factor of the Gram kernels (how many k-slices the m columns are
+ * cut into, which sets the number of workgroups and the partial-tile traffic) and, for
+ * split-BF16 on 16-byte aligned rows, whether the row pass pre-splits S into bf16 planes, are
+ * chosen per size class (precision, ceil(n / 256), floor(log2 m), row alignment).
+ * dfisher_autotune_gram times every candidate on the given S (Gram stage only: row pass, tile
+ * kernel, reduction; one untimed and two timed runs each, HIP events on the stream, synchronous)
+ * and stores the fastest in the context; later calls with that size class use it. With
+ * dfisher_ctx_enable_autotune(ctx, 1), dfisher_gram / _solve / _factor_create / _solve_batched /
+ * _solve_uneven tune every size class they have not seen before on first use. The table can be
+ * saved to and loaded from a text file ("prec tiles log2m aligned q mode" per line); loading
+ * merges into the context's table and rejects malformed files with DFISHER_E_INVALID_ARG. */
+DFISHER_API dfisher_status dfisher_autotune_gram(dfisher_ctx* ctx, const float* S, int64_t n, int64_t m, int64_t lds,
+                                     int32_t prec, void* stream);
+DFISHER_API dfisher_status dfisher_ctx_enable_autotune(dfisher_ctx* ctx, int32_t enable);
+DFISHER_API dfisher_status dfisher_ctx_save_tuning(const dfisher_ctx* ctx, const char* path);
+DFISHER_API dfisher_status dfisher_ctx_load_tuning(dfisher_ctx* ctx, const char* path);
+
 /* Static text for a status code. */
 DFISHER_API const char* dfisher_status_string(dfisher_status s);
 /* Message describing the last failure on the calling thread ("" if none). */

@@ -18,7 +18,8 @@ __all__ = [
     "DFISHER_E_UNSUPPORTED", "DFISHER_GRAM_FP32", "DFISHER_GRAM_BF16X3", "DFISHER_GRAM_MXFP8", "DFISHER_SHIFT_NONE",
     "DFISHER_SHIFT_ON_FAILURE", "DFISHER_SHIFT_ALWAYS",
     "dfisher_ctx_create", "dfisher_ctx_destroy", "dfisher_ctx_enable_timing", "dfisher_ctx_last_timing",
-    "dfisher_ctx_enable_graphs",
+    "dfisher_ctx_enable_graphs", "dfisher_ctx_enable_autotune", "dfisher_autotune_gram", "dfisher_ctx_save_tuning",
+    "dfisher_ctx_load_tuning",
     "dfisher_gram", "dfisher_quantize_mxfp8", "dfisher_potrf", "dfisher_gemv",
     "dfisher_trsv", "dfisher_apply", "dfisher_solve", "dfisher_factor_create", "dfisher_factor_solve",
     "dfisher_factor_copy_L", "dfisher_factor_destroy", "dfisher_solve_batched", "dfisher_solve_uneven",
@@ -91,6 +92,10 @@ def _load():
                                   ctypes.POINTER(D), PP, ctypes.POINTER(_Options), P, ctypes.POINTER(Info)], I32),
         "dfisher_ctx_enable_timing": ([P, I32], I32),
         "dfisher_ctx_enable_graphs": ([P, I32], I32),
+        "dfisher_ctx_enable_autotune": ([P, I32], I32),
+        "dfisher_autotune_gram": ([P, P, I64, I64, I64, I32, P], I32),
+        "dfisher_ctx_save_tuning": ([P, ctypes.c_char_p], I32),
+        "dfisher_ctx_load_tuning": ([P, ctypes.c_char_p], I32),
         "dfisher_ctx_last_timing": ([P, ctypes.POINTER(Timing)], I32),
         "dfisher_status_string": ([I32], ctypes.c_char_p),
         "dfisher_last_error": ([], ctypes.c_char_p),
@@ -223,6 +228,25 @@ def dfisher_ctx_enable_timing(ctx, enable: bool = True) -> None:
 
 def dfisher_ctx_enable_graphs(ctx, enable: bool = True) -> None:
     _check(_lib().dfisher_ctx_enable_graphs(ctx.ptr, 1 if enable else 0), "dfisher_ctx_enable_graphs")
+
+
+def dfisher_ctx_enable_autotune(ctx, enable: bool = True) -> None:
+    _check(_lib().dfisher_ctx_enable_autotune(ctx.ptr, 1 if enable else 0), "dfisher_ctx_enable_autotune")
+
+
+def dfisher_autotune_gram(ctx, S, prec: int, stream=None) -> None:
+    """Time the Gram stage's split-K candidates on S and keep the fastest for S's size class."""
+    n, m, lds = _S_args(S)
+    _check(_lib().dfisher_autotune_gram(ctx.ptr, _ptr(S), n, m, lds, int(prec), _stream(stream)),
+           "dfisher_autotune_gram")
+
+
+def dfisher_ctx_save_tuning(ctx, path: str) -> None:
+    _check(_lib().dfisher_ctx_save_tuning(ctx.ptr, os.fsencode(path)), "dfisher_ctx_save_tuning")
+
+
+def dfisher_ctx_load_tuning(ctx, path: str) -> None:
+    _check(_lib().dfisher_ctx_load_tuning(ctx.ptr, os.fsencode(path)), "dfisher_ctx_load_tuning")
 
 
 def dfisher_ctx_last_timing(ctx) -> dict:

@@ -9,6 +9,8 @@
 #include <algorithm>
 #include <cmath>
 #include <vector>
+#include <map>
+#include <tuple>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -73,6 +75,9 @@ struct dfisher_ctx {
   hipStream_t cap_stream = nullptr;
   hipGraphExec_t uneven_exec = nullptr;
   std::vector<uint64_t> uneven_key;
+  // Gram autotuning: (precision, tiles per edge, floor(log2 m), aligned rows) -> (q, split mode)
+  bool autotune = false;
+  std::map<std::tuple<int, int64_t, int, int>, std::pair<int, int>> tune;
 };
 
 struct dfisher_factor {
@@ -192,6 +197,21 @@ double gram_unit(int prec, int64_t m) {
   // values shrinks like 1/sqrt(m) (random rounding errors), here with constant 2^-4.
   if (prec == DFISHER_GRAM_MXFP8) return 0.0625 / std::sqrt((double)m);
   return std::ldexp(1.0, -24);
+}
+
+std::tuple<int, int64_t, int, int> tune_key(int prec, int64_t n, int64_t m, bool aligned) {
+  int lg = 0;
+  while (lg < 62 && ((int64_t)1 << (lg + 1)) <= m) ++lg;
+  return std::make_tuple(prec, (n + dfi::GRAM_TILE - 1) / dfi::GRAM_TILE, lg, aligned ? 1 : 0);
+}
+
+// The Gram plan for a shape: the tuned split-K factor / split mode of its size class if the
+// context has one, else the built-in choice.
+dfi::GramPlan make_gram_plan(const dfisher_ctx* ctx, const float* S, int64_t n, int64_t m, int64_t lds, int prec) {
+  const bool al = rows_aligned16(S, lds);
+  auto it = ctx->tune.find(tune_key(prec, n, m, al));
+  if (it != ctx->tune.end()) return dfi::gram_plan(n, m, lds, prec, al, it->second.first, it->second.second);
+  return dfi::gram_plan(n, m, lds, prec, al);
 }
 
 // Everything one factorisation + solve needs, carved from the workspace.
@@ -414,6 +434,73 @@ dfisher_status multi_solve(const float* S, int64_t n, int64_t m, int64_t lds, in
   return DFISHER_OK;
 }
 
+// ----------------------------------------------------------------------------- autotuning
+// For one size class, times the Gram stage (row pass + tile kernel + reduction) on the caller's
+// S for every split-K factor q from dfi::gram_q_candidates (and, for split-BF16 on aligned rows,
+// with and without the pre-split planes), keeps the fastest in ctx->tune. Each candidate runs once
+// untimed and twice timed (HIP events on the stream; the minimum counts).
+constexpr size_t TUNE_MAX_PART_BYTES = (size_t)4 << 30;
+
+dfisher_status tune_gram(dfisher_ctx* ctx, const float* S, int64_t n, int64_t m, int64_t lds, int prec,
+                         hipStream_t st) {
+  const bool al = rows_aligned16(S, lds);
+  int qs[16];
+  int nq = 0;
+  dfi::gram_q_candidates(n, m, TUNE_MAX_PART_BYTES, qs, &nq, 16);
+  std::vector<int> modes = {-1};
+  if (prec == DFISHER_GRAM_BF16X3 && al) modes = {1, 0};
+  const dfi::RowPassPlan rp = dfi::rowpass_plan(n, m, lds);
+  const dfi::ColPassPlan cp = dfi::colpass_plan(n, m);
+  size_t need = 0;
+  for (int mode : modes)
+    for (int i = 0; i < nq; ++i) {
+      const dfi::GramPlan gp = dfi::gram_plan(n, m, lds, prec, al, qs[i], mode);
+      need = std::max(need, carve(nullptr, n, m, &gp, rp, cp, false, false).bytes);
+    }
+  DF_TRY(ensure_ws(ctx, need));
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    (void)hipGetLastError();
+    if (e0) (void)hipEventDestroy(e0);
+    return fail(DFISHER_E_DEVICE, "event creation failed");
+  }
+  float best = 0.f;
+  int best_q = 0, best_mode = -1;
+  dfisher_status rs = DFISHER_OK;
+  for (int mode : modes) {
+    for (int i = 0; i < nq && rs == DFISHER_OK; ++i) {
+      const dfi::GramPlan gp = dfi::gram_plan(n, m, lds, prec, al, qs[i], mode);
+      const SolveBufs B = carve(static_cast<char*>(ctx->ws), n, m, &gp, rp, cp, false, false);
+      float tmin = 0.f;
+      for (int rep = 0; rep < 3 && rs == DFISHER_OK; ++rep) {
+        if (hipEventRecord(e0, st) != hipSuccess) rs = fail(DFISHER_E_DEVICE, "event record failed");
+        if (rs == DFISHER_OK) rs = gram_stage(S, nullptr, gp, rp, B, 0.0, B.W, 0, st, nullptr);
+        if (rs == DFISHER_OK && (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess))
+          rs = fail(DFISHER_E_DEVICE, "event wait failed");
+        float ms = 0.f;
+        if (rs == DFISHER_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) rs = fail(DFISHER_E_DEVICE, "timing");
+        if (rep > 0 && (tmin == 0.f || ms < tmin)) tmin = ms;
+      }
+      if (rs == DFISHER_OK && (best_q == 0 || tmin < best)) {
+        best = tmin;
+        best_q = qs[i];
+        best_mode = mode;
+      }
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rs != DFISHER_OK) return rs;
+  ctx->tune[tune_key(prec, n, m, al)] = std::make_pair(best_q, best_mode);
+  return DFISHER_OK;
+}
+
+dfisher_status tune_if_new(dfisher_ctx* ctx, const float* S, int64_t n, int64_t m, int64_t lds, int prec,
+                           hipStream_t st) {
+  if (ctx->tune.count(tune_key(prec, n, m, rows_aligned16(S, lds)))) return DFISHER_OK;
+  return tune_gram(ctx, S, n, m, lds, prec, st);
+}
+
 // ----------------------------------------------------------------------------- uneven batches
 // Independent problems of different sizes (per-layer Fisher blocks). Every problem runs the same
 // steps as dfisher_solve, but the latency-bound steps of all problems share launches: one grouped
@@ -463,8 +550,8 @@ struct UnevenLayout {
   size_t bytes = 0;
 };
 
-void uneven_layout(char* base, int32_t np, const float* const* S, const int64_t* n, const int64_t* m,
-                   const int64_t* lds, int prec, int sweeps, UnevenLayout& U) {
+void uneven_layout(const dfisher_ctx* ctx, char* base, int32_t np, const float* const* S, const int64_t* n,
+                   const int64_t* m, const int64_t* lds, int prec, int sweeps, UnevenLayout& U) {
   U.gp.clear();
   U.rp.clear();
   U.cp.clear();
@@ -475,7 +562,7 @@ void uneven_layout(char* base, int32_t np, const float* const* S, const int64_t*
   int64_t wtot = 0, dtot = 0;
   size_t gpart = 0, rpart = 0, cpart = 0, q8 = 0, sc8 = 0, planes = 0;
   for (int32_t p = 0; p < np; ++p) {
-    U.gp.push_back(dfi::gram_plan(n[p], m[p], lds[p], prec, rows_aligned16(S[p], lds[p])));
+    U.gp.push_back(make_gram_plan(ctx, S[p], n[p], m[p], lds[p], prec));
     U.rp.push_back(dfi::rowpass_plan(n[p], m[p], lds[p]));
     U.cp.push_back(dfi::colpass_plan(n[p], m[p]));
     U.voff[(size_t)p] = U.ntot;
@@ -582,10 +669,12 @@ dfisher_status uneven_enqueue(dfisher_ctx* ctx, int32_t np, const float* const* 
 dfisher_status uneven_solve(dfisher_ctx* ctx, int32_t np, const float* const* S, const int64_t* n, const int64_t* m,
                             const int64_t* lds, const float* const* v, const double* lambda, void* const* x,
                             const dfisher_options& o, hipStream_t st, dfisher_info* infos) {
+  if (ctx->autotune)
+    for (int32_t p = 0; p < np; ++p) DF_TRY(tune_if_new(ctx, S[p], n[p], m[p], lds[p], o.gram_prec, st));
   UnevenLayout U;
-  uneven_layout(nullptr, np, S, n, m, lds, o.gram_prec, o.sweeps, U);
+  uneven_layout(ctx, nullptr, np, S, n, m, lds, o.gram_prec, o.sweeps, U);
   DF_TRY(ensure_ws(ctx, U.bytes));
-  uneven_layout(static_cast<char*>(ctx->ws), np, S, n, m, lds, o.gram_prec, o.sweeps, U);
+  uneven_layout(ctx, static_cast<char*>(ctx->ws), np, S, n, m, lds, o.gram_prec, o.sweeps, U);
   // largest problems first (their Gram kernels fill the device; small ones follow)
   std::vector<int32_t> order((size_t)np);
   for (int32_t p = 0; p < np; ++p) order[(size_t)p] = p;
@@ -840,7 +929,8 @@ dfisher_status dfisher_gram(dfisher_ctx* ctx, const float* S, int64_t n, int64_t
   DF_TRY(check_prec_layout(prec, S, lds));
   DeviceGuard g(ctx->device);
   hipStream_t st = as_stream(stream);
-  const dfi::GramPlan gp = dfi::gram_plan(n, m, lds, prec, rows_aligned16(S, lds));
+  if (ctx->autotune) DF_TRY(tune_if_new(ctx, S, n, m, lds, prec, st));
+  const dfi::GramPlan gp = make_gram_plan(ctx, S, n, m, lds, prec);
   const dfi::RowPassPlan rp = dfi::rowpass_plan(n, m, lds);
   const dfi::ColPassPlan cp = dfi::colpass_plan(n, m);
   SolveBufs B = carve(nullptr, n, m, &gp, rp, cp, false, false);
@@ -950,7 +1040,8 @@ dfisher_status dfisher_factor_create(dfisher_ctx* ctx, const float* S, int64_t n
   DF_TRY(check_prec_layout(o.gram_prec, S, lds));
   DeviceGuard g(ctx->device);
   hipStream_t st = as_stream(stream);
-  const dfi::GramPlan gp = dfi::gram_plan(n, m, lds, o.gram_prec, rows_aligned16(S, lds));
+  if (ctx->autotune) DF_TRY(tune_if_new(ctx, S, n, m, lds, o.gram_prec, st));
+  const dfi::GramPlan gp = make_gram_plan(ctx, S, n, m, lds, o.gram_prec);
   const dfi::RowPassPlan rp = dfi::rowpass_plan(n, m, lds);
   const dfi::ColPassPlan cp = dfi::colpass_plan(n, m);
   SolveBufs B = carve(nullptr, n, m, &gp, rp, cp, false, false);
@@ -1052,7 +1143,8 @@ dfisher_status dfisher_solve(dfisher_ctx* ctx, const float* S, int64_t n, int64_
   DF_TRY(check_prec_layout(o.gram_prec, S, lds));
   DeviceGuard g(ctx->device);
   hipStream_t st = as_stream(stream);
-  const dfi::GramPlan gp = dfi::gram_plan(n, m, lds, o.gram_prec, rows_aligned16(S, lds));
+  if (ctx->autotune) DF_TRY(tune_if_new(ctx, S, n, m, lds, o.gram_prec, st));
+  const dfi::GramPlan gp = make_gram_plan(ctx, S, n, m, lds, o.gram_prec);
   const dfi::RowPassPlan rp = dfi::rowpass_plan(n, m, lds);
   const dfi::ColPassPlan cp = dfi::colpass_plan(n, m);
   const bool need_t = o.sweeps > 0;
@@ -1095,7 +1187,8 @@ dfisher_status dfisher_solve_batched(dfisher_ctx* ctx, const float* S, int64_t n
   DF_TRY(check_prec_layout(o.gram_prec, S, lds));
   DeviceGuard g(ctx->device);
   hipStream_t st = as_stream(stream);
-  const dfi::GramPlan gp = dfi::gram_plan(n, m, lds, o.gram_prec, rows_aligned16(S, lds));
+  if (ctx->autotune) DF_TRY(tune_if_new(ctx, S, n, m, lds, o.gram_prec, st));
+  const dfi::GramPlan gp = make_gram_plan(ctx, S, n, m, lds, o.gram_prec);
   const dfi::RowPassPlan rp = dfi::rowpass_plan(n, m, lds);
   const dfi::ColPassPlan cp = dfi::colpass_plan(n, m);
   const dfi::RowMultiPlan rm = dfi::rowmulti_plan(n, m, lds);
@@ -1184,6 +1277,62 @@ dfisher_status dfisher_solve_uneven(dfisher_ctx* ctx, int32_t nprob, const float
   DeviceGuard g(ctx->device);
   hipStream_t st = as_stream(stream);
   return uneven_solve(ctx, nprob, S, n, m, lds, v, lambda, x, o, st, infos);
+}
+
+dfisher_status dfisher_ctx_enable_autotune(dfisher_ctx* ctx, int32_t enable) {
+  DF_TRY(check_ctx(ctx));
+  ctx->autotune = enable != 0;
+  return DFISHER_OK;
+}
+
+dfisher_status dfisher_autotune_gram(dfisher_ctx* ctx, const float* S, int64_t n, int64_t m, int64_t lds, int32_t prec,
+                                     void* stream) {
+  DF_TRY(check_ctx(ctx));
+  DF_TRY(check_S(S, n, m, lds));
+  if (prec != DFISHER_GRAM_FP32 && prec != DFISHER_GRAM_BF16X3 && prec != DFISHER_GRAM_MXFP8)
+    return fail(DFISHER_E_INVALID_ARG, "unknown gram_prec %d", prec);
+  DF_TRY(check_prec_layout(prec, S, lds));
+  DeviceGuard g(ctx->device);
+  return tune_gram(ctx, S, n, m, lds, prec, as_stream(stream));
+}
+
+// Text format, one size class per line: "prec tiles log2m aligned q mode".
+dfisher_status dfisher_ctx_save_tuning(const dfisher_ctx* ctx, const char* path) {
+  if (!ctx || !path) return fail(DFISHER_E_INVALID_ARG, "ctx or path is NULL");
+  FILE* f = std::fopen(path, "w");
+  if (!f) return fail(DFISHER_E_INVALID_ARG, "cannot open %s for writing", path);
+  std::fprintf(f, "# dfisher gram tuning: prec tiles log2m aligned q mode\n");
+  for (const auto& kv : ctx->tune)
+    std::fprintf(f, "%d %lld %d %d %d %d\n", std::get<0>(kv.first), (long long)std::get<1>(kv.first),
+                 std::get<2>(kv.first), std::get<3>(kv.first), kv.second.first, kv.second.second);
+  const bool ok = std::fclose(f) == 0;
+  return ok ? DFISHER_OK : fail(DFISHER_E_INVALID_ARG, "write to %s failed", path);
+}
+
+dfisher_status dfisher_ctx_load_tuning(dfisher_ctx* ctx, const char* path) {
+  if (!ctx || !path) return fail(DFISHER_E_INVALID_ARG, "ctx or path is NULL");
+  FILE* f = std::fopen(path, "r");
+  if (!f) return fail(DFISHER_E_INVALID_ARG, "cannot open %s", path);
+  std::map<std::tuple<int, int64_t, int, int>, std::pair<int, int>> t;
+  char line[256];
+  int lineno = 0;
+  dfisher_status st = DFISHER_OK;
+  while (std::fgets(line, sizeof line, f)) {
+    ++lineno;
+    if (line[0] == '#' || line[0] == '\n') continue;
+    int prec, lg, al, q, mode;
+    long long tiles;
+    if (std::sscanf(line, "%d %lld %d %d %d %d", &prec, &tiles, &lg, &al, &q, &mode) != 6 || prec < 0 || prec > 2 ||
+        tiles < 1 || lg < 0 || lg > 62 || (al != 0 && al != 1) || q < 1 || q > 64 || mode < -1 || mode > 1) {
+      st = fail(DFISHER_E_INVALID_ARG, "%s:%d: malformed tuning entry", path, lineno);
+      break;
+    }
+    t[std::make_tuple(prec, (int64_t)tiles, lg, al)] = std::make_pair(q, mode);
+  }
+  std::fclose(f);
+  if (st != DFISHER_OK) return st;
+  for (const auto& kv : t) ctx->tune[kv.first] = kv.second;
+  return DFISHER_OK;
 }
 
 dfisher_status dfisher_ctx_enable_graphs(dfisher_ctx* ctx, int32_t enable) {

@@ -25,7 +25,13 @@ struct GramPlan {
 
 // aligned16: rows of S start on 16-byte boundaries (lds % 4 == 0 and S 16-byte aligned). For
 // split-BF16 on aligned rows the plan uses planes hi/lo written by the row pass (ldh > 0).
-GramPlan gram_plan(int64_t n, int64_t m, int64_t lds, int prec, bool aligned16);
+// q_override > 0 fixes the split-K factor (nslice = 8 q); split_mode 0 keeps split-BF16 inside the
+// tile kernel even on aligned rows (-1: planes whenever possible).
+GramPlan gram_plan(int64_t n, int64_t m, int64_t lds, int prec, bool aligned16, int q_override = 0,
+                   int split_mode = -1);
+// The split-K factors q (nslice = 8 q) worth trying for a shape: every q from 1 up to the largest
+// that keeps >= 2048 columns per slice and the partial tiles within max_part_bytes.
+void gram_q_candidates(int64_t n, int64_t m, size_t max_part_bytes, int* out, int* count, int cap);
 hipError_t gram_launch(const GramPlan& p, const float* S, float* part, hipStream_t st);
 // One problem of a grouped Gram launch (several independent Grams in one launch). a, b: the FP8
 // codes and scales (prec 2) or the hi and lo planes (prec 1) in the row pass's column-blocked

@@ -927,7 +927,7 @@ __global__ void gram_reduce_kernel(const float* __restrict__ part, int64_t n, in
 
 }  // namespace
 
-GramPlan gram_plan(int64_t n, int64_t m, int64_t lds, int prec, bool aligned16) {
+GramPlan gram_plan(int64_t n, int64_t m, int64_t lds, int prec, bool aligned16, int q_override, int split_mode) {
   GramPlan p{};
   p.n = n;
   p.m = m;
@@ -952,15 +952,30 @@ GramPlan gram_plan(int64_t n, int64_t m, int64_t lds, int prec, bool aligned16) 
       best_q = q;
     }
   }
+  if (q_override > 0) best_q = q_override;
   p.nslice = 8 * best_q;
   const int64_t kstep = (prec == 2) ? 64 : KS;
   int64_t ks = (m + p.nslice - 1) / p.nslice;
   ks = (ks + kstep - 1) / kstep * kstep;
   if (ks < kstep) ks = kstep;
   p.kslice = ks;
-  p.ldh = (prec == 1 && aligned16) ? split_ldh(m) : 0;
+  p.ldh = (prec == 1 && aligned16 && split_mode != 0) ? split_ldh(m) : 0;
   p.part_bytes = (size_t)p.nslice * (size_t)p.ntri * (size_t)(T * T) * sizeof(float);
   return p;
+}
+
+void gram_q_candidates(int64_t n, int64_t m, size_t max_part_bytes, int* out, int* count, int cap) {
+  const int64_t ntile = (n + T - 1) / T;
+  const int64_t ntri = ntile * (ntile + 1) / 2;
+  const int64_t maxq = std::max<int64_t>(1, m / (8 * 2048));
+  static const int qs[] = {1, 2, 3, 4, 6, 8, 12, 16, 24, 32, 48, 64};
+  int c = 0;
+  for (int q : qs) {
+    if (q > 1 && q > maxq) break;
+    if (q > 1 && (size_t)8 * q * ntri * T * T * sizeof(float) > max_part_bytes) break;
+    if (c < cap) out[c++] = q;
+  }
+  *count = c;
 }
 
 hipError_t gram_launch_fp8(const GramPlan& p, const uint8_t* q, const uint8_t* sc, int64_t ldq, float* part,

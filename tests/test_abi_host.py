@@ -101,6 +101,17 @@ def test_invalid_arguments_rejected_on_host(dfl):
     assert lib.dfisher_solve_batched(FAKE_CTX, P, 4, 8, 8, lams, 1, P, 1, 7, P, 8, None, st, None) == E
     assert lib.dfisher_solve_uneven(FAKE_CTX, 0, None, None, None, None, None, None, None, None, st, None) == E
     assert "NULL" in dfl.dfisher_last_error() or dfl.dfisher_last_error() != ""
+    # context switches and the tuning table
+    assert lib.dfisher_ctx_enable_graphs(None, 1) == E
+    assert lib.dfisher_ctx_enable_autotune(None, 1) == E
+    assert lib.dfisher_autotune_gram(None, P, 4, 8, 8, 1, st) == E
+    assert lib.dfisher_autotune_gram(FAKE_CTX, P, 4, 8, 8, 7, st) == E
+    assert lib.dfisher_autotune_gram(FAKE_CTX, P, 4, 8, 7, 1, st) == E
+    assert lib.dfisher_ctx_save_tuning(None, b"/tmp/x") == E
+    assert lib.dfisher_ctx_load_tuning(None, b"/tmp/x") == E
+    assert lib.dfisher_ctx_load_tuning(FAKE_CTX, None) == E
+    # a nonexistent file is rejected before the context is touched
+    assert lib.dfisher_ctx_load_tuning(FAKE_CTX, b"/nonexistent/dir/tune.txt") == E
 
 
 def test_context_on_missing_device(dfl):

@@ -445,6 +445,40 @@ def test_uneven_graph_replays_match_eager(dfl, ctx):
         torch.cuda.synchronize()
 
 
+def test_autotune_save_load(dfl, oracle_mod, tmp_path):
+    """Tuning a size class records a valid (q, mode); a saved table loads into a fresh context,
+    whose solves stay within the bound; automatic tuning adds unseen classes; bad files fail."""
+    n, m, lam = 300, 40000, 1e-3
+    S = synth.make_S(n, m, synth.seed(46, n))
+    v = synth.make_v(S, synth.seed(46, n))
+    Sd, vd = dev(S), dev(v)
+    c1 = dfl.dfisher_ctx_create(0)
+    dfl.dfisher_autotune_gram(c1, Sd, dfl.DFISHER_GRAM_BF16X3)
+    path = str(tmp_path / "tune.txt")
+    dfl.dfisher_ctx_save_tuning(c1, path)
+    rows = [l.split() for l in open(path) if not l.startswith("#")]
+    assert len(rows) == 1
+    prec, tiles, lg, al, q, mode = map(int, rows[0])
+    assert (prec, tiles, lg, al) == (1, 2, 15, 1) and 1 <= q <= 64 and mode in (0, 1)
+    c2 = dfl.dfisher_ctx_create(0)
+    dfl.dfisher_ctx_load_tuning(c2, path)
+    x, _ = dfl.dfisher_solve(c2, Sd, vd, lam, gram_prec=1, sweeps=1, x_fp64=True)
+    assert rel(x.cpu().numpy(), oracle_mod.solve(S, v, lam)) <= 1e-6
+    dfl.dfisher_ctx_enable_autotune(c2, True)
+    S2 = synth.make_S(64, 8192, synth.seed(46, 64))
+    v2 = synth.make_v(S2, synth.seed(46, 64))
+    x2, _ = dfl.dfisher_solve(c2, dev(S2), dev(v2), 1e-2, gram_prec=2, sweeps=2, x_fp64=True)
+    assert rel(x2.cpu().numpy(), oracle_mod.solve(S2, v2, 1e-2)) <= 1e-6
+    dfl.dfisher_ctx_save_tuning(c2, path)
+    assert len([l for l in open(path) if not l.startswith("#")]) == 2
+    bad = tmp_path / "bad.txt"
+    bad.write_text("1 2 15 1 99 0\n")
+    with pytest.raises(dfl.DfisherError):
+        dfl.dfisher_ctx_load_tuning(c2, str(bad))
+    dfl.dfisher_ctx_destroy(c1)
+    dfl.dfisher_ctx_destroy(c2)
+
+
 def test_shift_always_contracts(dfl, ctx, oracle_mod):
     """With the up-front shift every sweep shrinks the error (the factored matrix dominates W)."""
     S = synth.make_S(300, 20000, 37)
