@@ -1,10 +1,15 @@
 """Throughput of the damped Fisher solve (Algorithm 1 of arXiv 2310.17556) on one MI355X.
 
 Workload (default): n = 4096 samples, m = 4,000,000 parameters, FP32 S = G / sqrt(n) with G iid
-N(0,1), column-centered, v iid N(0,1), lambda in {1e-2, 1e-4, 1e-6}; the Gram in split-BF16
-(three bf16 products, FP32 accumulation, FP64 across k-slices), FP64 Cholesky / triangular
-solves and FP64 refinement sweeps. One step = one independent one-shot solve per lambda (three
-solves, each forming its own Gram). Inputs are drawn on the device before timing starts.
+N(0,1), column-centered, v iid N(0,1), lambda in {1e-2, 1e-4, 1e-6}; the Gram in scaled FP8
+(E4M3 with a power-of-two scale per 32 columns, FP32 accumulation, FP64 across k-slices, exact
+FP64 diagonal), FP64 Cholesky / triangular solves and one FP64 refinement sweep. One step = one
+independent one-shot solve per lambda (three solves, each forming its own Gram). Inputs are
+drawn on the device before timing starts.
+
+Also reported on the same line: the plain FP32 path and the split-BF16 path on the same workload,
+the batched path (n = 2048, m = 2M, 16 lambdas x 8 right-hand sides sharing one Gram) and the
+uneven batch (64 problems of log-uniform sizes), each with sampled errors against FP64.
 
 Printed: one JSON line with solves/s (value), the Gram kernel's roofline position (timed with
 HIP events on the stream it runs on), the plain FP32 path for comparison, the relative error of
@@ -104,6 +109,25 @@ SHIFT = {"on_failure": "DFISHER_SHIFT_ON_FAILURE", "always": "DFISHER_SHIFT_ALWA
 GRAM_KERNEL = {"fp32": "gram_kernel_v2<0>", "bf16x3": "gram_kernel_split", "mxfp8": "gram_kernel_fp8"}
 
 
+# HBM bytes per launch of the Gram tile kernel at the full workload, from rocprofv3 FETCH_SIZE /
+# WRITE_SIZE passes (each scaled by the same counters' reading for a device copy of known size),
+# valid only for the kernel source they were taken on (sha256 of csrc/gram.hip); see profiles/.
+GRAM_TRAFFIC = {}
+
+
+def gram_traffic(prec, n, m):
+    import hashlib
+
+    rec = GRAM_TRAFFIC.get((prec, n, m))
+    if rec is None:
+        return None
+    with open(os.path.join(ROOT, "paper_2310_17556_amd", "csrc", "gram.hip"), "rb") as f:
+        sha = hashlib.sha256(f.read()).hexdigest()
+    if sha != rec["gram_hip_sha256"]:
+        return None   # the kernel changed since the counters were taken
+    return rec["bytes_per_launch"]
+
+
 def run_path(dfl, ctx, S, v, lams, prec, sweeps, steps, warmup, xbuf, shift="on_failure"):
     import torch
 
@@ -130,6 +154,99 @@ def run_path(dfl, ctx, S, v, lams, prec, sweeps, steps, warmup, xbuf, shift="on_
     return elapsed, gram_ms, avg, infos
 
 
+def _fp64_x(S, v, lam, chunk=131072):
+    """FP64 reference x for one (S, v, lambda) from torch FP64 products on the device."""
+    import torch
+
+    n, m = S.shape
+    G = torch.zeros((n, n), dtype=torch.float64, device=S.device)
+    b = torch.zeros(n, dtype=torch.float64, device=S.device)
+    v64 = v.double()
+    for c0 in range(0, m, chunk):
+        blk = S[:, c0:c0 + chunk].double()
+        G += blk @ blk.T
+        b += blk @ v64[c0:c0 + chunk]
+        del blk
+    L = torch.linalg.cholesky(G + lam * torch.eye(n, dtype=torch.float64, device=S.device))
+    y = torch.cholesky_solve(b[:, None], L)[:, 0]
+    x = torch.empty(m, dtype=torch.float64, device=S.device)
+    for c0 in range(0, m, chunk):
+        x[c0:c0 + chunk] = (v64[c0:c0 + chunk] - S[:, c0:c0 + chunk].double().T @ y) / lam
+    return x
+
+
+def batched_leg(dfl, dev, prec, sweeps, reps, n=2048, m=2_000_000, nlam=16, nrhs=8, seed=4):
+    """Many lambdas x right-hand sides sharing one S: one dfisher_solve_batched call per step."""
+    import torch
+
+    import synth
+
+    S = synth.make_S_torch(n, m, synth.seed(seed), dev, kind="iid")
+    V = synth.make_V_torch(m, nrhs, synth.seed(seed), dev)
+    lams = [float(x) for x in synth.lambdas_logspaced(1e-6, 1e-1, nlam)]
+    ctx = dfl.dfisher_ctx_create(0)
+    X = torch.empty((nlam, nrhs, m), dtype=torch.float32, device=dev)
+    dfl.dfisher_solve_batched(ctx, S, lams, V, gram_prec=PREC_CODE[prec], sweeps=sweeps, X=X)   # warmup
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        _, infos = dfl.dfisher_solve_batched(ctx, S, lams, V, gram_prec=PREC_CODE[prec], sweeps=sweeps, X=X)
+    torch.cuda.synchronize()
+    el = (time.perf_counter() - t0) / reps
+    errs = {}
+    for li, r in [(0, 0), (nlam // 2, nrhs - 1), (nlam - 1, 1)]:
+        x = _fp64_x(S, V[r], lams[li])
+        errs[f"lam={lams[li]:.3g},rhs={r}"] = float(torch.linalg.norm(X[li, r].double() - x) / torch.linalg.norm(x))
+    dfl.dfisher_ctx_destroy(ctx)
+    del S, V, X
+    torch.cuda.empty_cache()
+    return {"workload": f"batched: n={n} m={m}, {nlam} lambdas log-spaced in [1e-6, 1e-1] x {nrhs} iid right-hand "
+                        "sides, one shared Gram",
+            "gram": prec, "sweeps": sweeps, "solves_per_s": nlam * nrhs / el, "ms_per_call": el * 1e3,
+            "rel_err_sampled": errs, "max_shift": max(i["shift"] for i in infos)}
+
+
+def uneven_leg(dfl, dev, prec, sweeps, reps, nprob=64, seed=5):
+    """64 independent problems, n log-uniform in [256, 2048], m log-uniform in [1e5, 2e6],
+    lambda log-uniform in [1e-5, 1e-2]: one dfisher_solve_uneven call per step."""
+    import torch
+
+    import synth
+
+    ns, ms, lams = synth.uneven_shapes(nprob, synth.seed(seed))
+    Ss, vs = [], []
+    for p in range(nprob):
+        n, m = int(ns[p]), int(ms[p])
+        buf = synth.make_S_torch(n, m, synth.seed(seed, p), dev, kind="iid", ld=(m + 3) // 4 * 4)
+        Ss.append(buf[:, :m])
+        vs.append(synth.make_v_torch(buf, synth.seed(seed, p), kind="iid", m=m))
+    lams = [float(x) for x in lams]
+    ctx = dfl.dfisher_ctx_create(0)
+    xs = [torch.empty(int(m), dtype=torch.float32, device=dev) for m in ms]
+    dfl.dfisher_solve_uneven(ctx, Ss, vs, lams, gram_prec=PREC_CODE[prec], sweeps=sweeps, xs=xs)   # capture
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        _, infos = dfl.dfisher_solve_uneven(ctx, Ss, vs, lams, gram_prec=PREC_CODE[prec], sweeps=sweeps, xs=xs)
+    torch.cuda.synchronize()
+    el = (time.perf_counter() - t0) / reps
+    errs = {}
+    order = sorted(range(nprob), key=lambda p: int(ns[p]) * int(ns[p]) * int(ms[p]))
+    for p in [order[0], order[nprob // 2], order[-1]]:
+        x = _fp64_x(Ss[p], vs[p], lams[p])
+        errs[f"n={int(ns[p])},m={int(ms[p])}"] = float(torch.linalg.norm(xs[p].double() - x) / torch.linalg.norm(x))
+    dfl.dfisher_ctx_destroy(ctx)
+    out = {"workload": f"uneven: {nprob} problems, n log-uniform [256, 2048], m log-uniform [1e5, 2e6], "
+                       "lambda log-uniform [1e-5, 1e-2], one right-hand side each",
+           "gram": prec, "sweeps": sweeps, "solves_per_s": nprob / el, "ms_per_call": el * 1e3,
+           "S_GB": sum(4.0 * int(n) * int(m) for n, m in zip(ns, ms)) / 1e9,
+           "gram_flops": sum(float(n) * (n + 1) * m for n, m in zip(ns, ms)),
+           "rel_err_sampled": errs, "retried": sum(1 for i in infos if i["attempts"] > 1)}
+    del Ss, vs, xs
+    torch.cuda.empty_cache()
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -137,7 +254,7 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--n", type=int, default=4096)
     ap.add_argument("--m", type=int, default=4_000_000)
-    ap.add_argument("--prec", default="bf16x3", choices=sorted(PREC_CODE))
+    ap.add_argument("--prec", default="mxfp8", choices=sorted(PREC_CODE))
     ap.add_argument("--sweeps", type=int, default=1)
     ap.add_argument("--shift", default="on_failure", choices=sorted(SHIFT),
                     help="Cholesky shift policy of the mixed path")
@@ -147,6 +264,12 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-m", type=int, default=8192)
     ap.add_argument("--seed", type=int, default=3)
+    ap.add_argument("--alt-prec", default="bf16x3", help="second mixed precision timed for comparison ('' to skip)")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched multi-lambda/RHS leg")
+    ap.add_argument("--no-uneven", action="store_true", help="skip the uneven-batch leg")
+    ap.add_argument("--leg-reps", type=int, default=3, help="timed calls of the batched and uneven legs")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run two device copies of 1 GiB (reference reading for the HBM byte counters)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -163,6 +286,15 @@ def main() -> int:
     if not torch.cuda.is_available():
         print(json.dumps({"error": "no GPU available"}))
         return 2
+    if args.copy_calibration:
+        # a plain device copy of known size: each launch reads 2^30 bytes and writes 2^30 bytes
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(2):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": 1 << 30, "copy_bytes_written": 1 << 30, "launches": 2}))
+        return 0
     n, m = args.n, args.m
     lams = [float(x) for x in args.lams.split(",")]
     dev = torch.device("cuda:0")
@@ -186,7 +318,6 @@ def main() -> int:
     peak = PEAK_TFLOPS[args.prec]
     log(f"[bench] mixed: {value:.3f} solves/s, gram {gram_avg_ms:.2f} ms, stages {stage_avg}")
 
-    results = {"mixed": {}, "fp32": {}}
     x_mixed = {lam: xbuf[lam].clone() for lam in lams}
 
     fp32 = None
@@ -202,16 +333,32 @@ def main() -> int:
                 "shifts": {str(l): i["shift"] for l, i in inf32}}
         log(f"[bench] fp32: {fp32['solves_per_s']:.3f} solves/s, gram {g32avg:.2f} ms")
 
+    alt = None
+    if args.alt_prec and args.alt_prec != args.prec:
+        log(f"[bench] {args.alt_prec} path: 1 step")
+        xbalt = {lam: torch.empty(m, dtype=torch.float32, device=dev) for lam in lams}
+        ea, ga, sta, infa = run_path(dfl, ctx, S, v, lams, args.alt_prec, args.sweeps, 1, 1, xbalt, args.shift)
+        gaavg = sum(ga) / len(ga)
+        alt = {"gram": args.alt_prec, "sweeps": args.sweeps, "solves_per_s": len(lams) / ea, "gram_ms": gaavg,
+               "gram_tflops_algorithmic": algo_flops / (gaavg * 1e-3) / 1e12,
+               "gram_mfma_frac_hw": algo_flops * PASSES[args.alt_prec] / (gaavg * 1e-3) / 1e12
+               / PEAK_TFLOPS[args.alt_prec],
+               "stage_ms": sta, "shifts": {str(l): i["shift"] for l, i in infa}}
+        log(f"[bench] {args.alt_prec}: {alt['solves_per_s']:.3f} solves/s, gram {gaavg:.2f} ms")
+
     errors = None
     if not args.no_ref:
         log("[bench] FP64 reference for the error report")
         xref = fp64_reference(S, v, lams)
-        errors = {"mixed": {}, "fp32": {}}
+        errors = {"mixed": {}, "fp32": {}, "alt": {}}
         for lam in lams:
             r = xref[lam]
-            errors["mixed"][str(lam)] = float(torch.linalg.norm(x_mixed[lam].double() - r) / torch.linalg.norm(r))
+            nr = torch.linalg.norm(r)
+            errors["mixed"][str(lam)] = float(torch.linalg.norm(x_mixed[lam].double() - r) / nr)
             if fp32 is not None:
-                errors["fp32"][str(lam)] = float(torch.linalg.norm(xb32[lam].double() - r) / torch.linalg.norm(r))
+                errors["fp32"][str(lam)] = float(torch.linalg.norm(xb32[lam].double() - r) / nr)
+            if alt is not None:
+                errors["alt"][str(lam)] = float(torch.linalg.norm(xbalt[lam].double() - r) / nr)
         del xref
         log(f"[bench] errors {errors}")
 
@@ -223,6 +370,24 @@ def main() -> int:
         log(f"[bench] FP64 CPU oracle on a {args.cpu_sample_m}-column sample")
         cpu = cpu_baseline(S, v, lams[-1], args.cpu_sample_m)
         log(f"[bench] cpu baseline {cpu}")
+    dfl.dfisher_ctx_destroy(ctx)
+    del S, v, xbuf, x_mixed
+    if fp32 is not None:
+        del xb32
+    if alt is not None:
+        del xbalt
+    torch.cuda.empty_cache()
+
+    batched = None
+    if not args.no_batched:
+        log("[bench] batched leg: n=2048 m=2M, 16 lambdas x 8 right-hand sides")
+        batched = batched_leg(dfl, dev, args.prec, args.sweeps, args.leg_reps)
+        log(f"[bench] batched {batched}")
+    uneven = None
+    if not args.no_uneven:
+        log("[bench] uneven leg: 64 problems")
+        uneven = uneven_leg(dfl, dev, args.prec, args.sweeps, args.leg_reps)
+        log(f"[bench] uneven {uneven}")
 
     line = {
         "metric": METRIC,
@@ -242,7 +407,7 @@ def main() -> int:
                    "n": n, "m": m, "lambdas": lams, "gram": args.prec, "sweeps": args.sweeps, "shift": args.shift,
                    "solves_per_step": len(lams)},
         "roofline": {"bound": "mfma", "kernel": GRAM_KERNEL[args.prec], "achieved": achieved, "peak": peak,
-                     "unit": "TFLOP/s", "frac": achieved / peak, "traffic": None,
+                     "unit": "TFLOP/s", "frac": achieved / peak, "traffic": gram_traffic(args.prec, n, m),
                      "algorithmic_flops_per_launch": algo_flops, "avg_launch_ms": gram_avg_ms,
                      "mfma_util_hw": achieved * passes / peak},
         "stage_ms": stage_avg,
@@ -250,11 +415,13 @@ def main() -> int:
                 "apply_GBs": apply_bytes / (stage_avg.get("apply_ms", 0) * 1e-3) / 1e9 if stage_avg.get("apply_ms") else None,
                 "peak_GBs": HBM_PEAK_GBS},
         "fp32_path": fp32,
+        "alt_path": alt,
         "rel_err_vs_fp64": errors,
         "shifts": {str(l): i["shift"] for l, i in infos[-len(lams):]},
+        "batched": batched,
+        "uneven": uneven,
         "cpu_baseline": cpu,
     }
-    dfl.dfisher_ctx_destroy(ctx)
     print(json.dumps(line), flush=True)
     return 0
 

@@ -35,7 +35,8 @@ void gram_q_candidates(int64_t n, int64_t m, size_t max_part_bytes, int* out, in
 hipError_t gram_launch(const GramPlan& p, const float* S, float* part, hipStream_t st);
 // One problem of a grouped Gram launch (several independent Grams in one launch). a, b: the FP8
 // codes and scales (prec 2) or the hi and lo planes (prec 1) in the row pass's column-blocked
-// layout; kcap: m rounded down to 16 (prec 2) or 8 (prec 1); part: that problem's partial tiles;
+// layout; kcap: ldq (prec 2) or ldh (prec 1), the column range the slices cover; part: that
+// problem's partial tiles;
 // wg_begin: its first workgroup (sorted ascending, each job's count nslice * ntri a multiple of 8).
 struct GramJob {
   const void* a;

@@ -513,15 +513,19 @@ gram_kernel_v2(const float* __restrict__ S, int64_t n, int64_t lds, int64_t m, i
 //     fragment reads of 16 consecutive rows hit distinct banks. Scale bytes move direct-to-LDS as
 //     one 4-byte word per row (four blocks, 128 columns; the step uses two of them), since the LDS
 //     side of these loads advances 4 bytes per lane.
-//   * Four LDS stages: loads run three steps ahead of the matrix cores. Every wave issues the same
-//     number of loads per step (diagonal tiles load their B panel as well), so waiting for a
-//     stage is a vmcnt wait on the count of loads issued after it, plus one barrier per step.
+//   * Four LDS stages: the direct-to-LDS loads run three steps ahead of the matrix cores. Every
+//     wave issues the same number of loads per step (diagonal tiles load their B panel as well),
+//     so waiting for a stage is a vmcnt wait on the count of loads issued after it, plus one
+//     barrier per step. Inside a step the wave reads its four B fragments, then each A fragment
+//     one MFMA group ahead of its use, so the LDS latency hides behind the previous group.
 //   * v_mfma_scale_f32_32x32x64_f8f6f4: lane l supplies row (l % 32), 16 codes from scale block 0
 //     and 16 from block 1 of the step (bytes [16h, 16h+16) and [32+16h, 32+16h+16) for h = l/32),
 //     and the E8M0 scale of block h of its row. A and B use the same byte arrangement, so every
 //     product pairs one column with itself.
-//   * Columns [m16, m) with m16 = m rounded down to 16 are left to the FP64 reduction.
-//   * Alternating slice sign as in v2: odd slices flip the sign bit of A's codes.
+//   * The slices cover all of [0, ldq): past m the row pass wrote zero codes, so every k-step is
+//     whole and nothing is masked; the reduction adds no tail columns for this kernel.
+//   * No alternating slice sign: the accumulation bias it cancels for bf16 (about 1e-6 relative)
+//     is far below the E4M3 rounding of the operands.
 namespace v3 {
 
 constexpr int NW = 4;
@@ -537,8 +541,6 @@ typedef __attribute__((address_space(3))) void lds_void;
 typedef int i32x8 __attribute__((ext_vector_type(8)));
 typedef int i32x4 __attribute__((ext_vector_type(4)));
 
-__device__ __align__(16) uint8_t g_zero_chunk8[16] = {0};
-
 struct Stage {
   uint8_t a[PANEL];
   uint8_t b[PANEL];
@@ -546,41 +548,44 @@ struct Stage {
   uint8_t sb[4 * T];
 };
 
-__device__ __forceinline__ void issue_codes(const uint8_t* __restrict__ q, int64_t n, int64_t row0,
-                                            int64_t kcol, int64_t kend, uint8_t* panel) {
-  const uint8_t* qb = q + ((kcol >> 7) * n << 7) + (kcol & 127);   // this step's 64 bytes of row 0
+// Loop-invariant per-lane byte offsets, inside one column block, of what this lane moves for a
+// 256-row panel: code chunks (wave instruction i carries rows 16 g .. 16 g + 15, g = wave + 4 i;
+// lane l fills LDS row 16 g + l / 4, chunk slot l % 4, with column chunk (l % 4) ^ ((row >> 2) & 3))
+// and the scale word of row 64 wave + lane. Rows past n are clamped to n - 1 (their products are
+// never stored).
+struct PanelOffs {
+  uint32_t code[T / 16 / NW];
+  uint32_t scale;
+};
+
+__device__ __forceinline__ void panel_offsets(int64_t n, int64_t row0, PanelOffs& po) {
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
-  const int rsub = lane >> 2;          // row inside the 16-row group
-  const int p = lane & 3;              // LDS chunk position
 #pragma unroll
   for (int i = 0; i < T / 16 / NW; ++i) {
     const int g = wave + NW * i;
-    const int r = 16 * g + rsub;
-    const int c = p ^ ((r >> 2) & 3);
-    int64_t R = row0 + r;
-    if (R >= n) R = n - 1;
-    const int64_t col = kcol + 16 * c;
-    // Branch-free choice between the row chunk and the zero chunk: a divergent branch here would
-    // issue the load twice (once per path) and break the fixed per-step load count that the
-    // vmcnt waits rely on.
-    const uint64_t in = (uint64_t)0 - (uint64_t)(col < kend);
-    const uint64_t addr = ((uint64_t)(uintptr_t)(qb + (R << 7) + 16 * c) & in) |
-                          ((uint64_t)(uintptr_t)g_zero_chunk8 & ~in);
-    __builtin_amdgcn_global_load_lds((const void*)(uintptr_t)addr, (lds_void*)(panel + 16 * g * KS8), 16, 0, 0);
+    const int r = 16 * g + (lane >> 2);
+    const int c = (lane & 3) ^ ((r >> 2) & 3);
+    const int64_t R = min(row0 + r, n - 1);
+    po.code[i] = (uint32_t)((R << 7) + 16 * c);
   }
+  po.scale = (uint32_t)(min(row0 + 64 * wave + lane, n - 1) << 2);
 }
 
-// Scale words of rows [row0, row0 + 256) for the step at column kcol: the 4-byte word holding the
-// scales of 32-column blocks 4 (kcol / 128) .. + 3. Wave w moves rows 64w .. 64w + 63.
-__device__ __forceinline__ void issue_scales(const uint8_t* __restrict__ sc, int64_t n, int64_t row0,
-                                             int64_t kcol, uint8_t* dst) {
-  const int lane = threadIdx.x & 63;
+// The step at column kcol (a multiple of 64): 64 code bytes of each of the panel's rows and the
+// rows' scale words, direct to LDS. Every step lies inside [0, ldq), where the row pass wrote
+// zero codes past m, so there is nothing to mask.
+__device__ __forceinline__ void issue_panel(const uint8_t* __restrict__ q, const uint8_t* __restrict__ sc, int64_t n,
+                                            int64_t kcol, const PanelOffs& po, uint8_t* panel, uint8_t* sdst) {
   const int wave = threadIdx.x >> 6;
-  int64_t R = row0 + 64 * wave + lane;
-  if (R >= n) R = n - 1;
-  const uint8_t* src = sc + (((kcol >> 7) * n + R) << 2);
-  __builtin_amdgcn_global_load_lds((const void*)src, (lds_void*)(dst + 256 * wave), 4, 0, 0);
+  const uint8_t* qb = q + ((kcol >> 7) * n << 7) + (kcol & 127);   // row 0 of this step, uniform
+#pragma unroll
+  for (int i = 0; i < T / 16 / NW; ++i) {
+    const int g = wave + NW * i;
+    __builtin_amdgcn_global_load_lds((const void*)(qb + po.code[i]), (lds_void*)(panel + 16 * g * KS8), 16, 0, 0);
+  }
+  const uint8_t* sb = sc + ((kcol >> 7) * n << 2);
+  __builtin_amdgcn_global_load_lds((const void*)(sb + po.scale), (lds_void*)(sdst + 256 * wave), 4, 0, 0);
 }
 
 // Fragment of row r: chunks h and 2 + h (swizzled) -> 32 codes.
@@ -603,7 +608,7 @@ __device__ __forceinline__ i32x8 read_frag(const uint8_t* panel, int r, int h) {
 // G = true: a grouped launch over jobs[0 .. njobs) (the scalar arguments are then ignored).
 template <bool G>
 __global__ void __launch_bounds__(NT, 1)
-gram_kernel_fp8(const uint8_t* __restrict__ q, const uint8_t* __restrict__ sc, int64_t n, int64_t m16,
+gram_kernel_fp8(const uint8_t* __restrict__ q, const uint8_t* __restrict__ sc, int64_t n, int64_t kcap,
                 int64_t ntri, int64_t nslice, int64_t kslice, float* __restrict__ part, const GramJob* __restrict__ jobs,
                 int njobs) {
   __shared__ Stage stg0, stg1, stg2, stg3;
@@ -614,7 +619,7 @@ gram_kernel_fp8(const uint8_t* __restrict__ q, const uint8_t* __restrict__ sc, i
     q = static_cast<const uint8_t*>(jb.a);
     sc = static_cast<const uint8_t*>(jb.b);
     n = jb.n;
-    m16 = jb.kcap;
+    kcap = jb.kcap;
     ntri = jb.ntri;
     nslice = jb.nslice;
     kslice = jb.kslice;
@@ -626,15 +631,14 @@ gram_kernel_fp8(const uint8_t* __restrict__ q, const uint8_t* __restrict__ sc, i
   const int64_t qq = local / ntri;
   const int64_t tile = local - qq * ntri;
   const int64_t slice = xcd * (nslice >> 3) + qq;
-  const int flip = (slice & 1) ? (int)0x80808080 : 0;
 
   int64_t ti, tj;
   tri_index(tile, ti, tj);
   const bool diag = (ti == tj);
   const int64_t rowA = ti * T, rowB = tj * T;
   const int64_t k0 = slice * kslice;
-  const int64_t kend = min(m16, k0 + kslice);
-  const int64_t nsteps = (kend > k0) ? (kend - k0 + KS8 - 1) / KS8 : 0;
+  const int64_t kend = min(kcap, k0 + kslice);
+  const int64_t nsteps = (kend > k0) ? (kend - k0) / KS8 : 0;   // both multiples of 64
 
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
@@ -659,28 +663,26 @@ gram_kernel_fp8(const uint8_t* __restrict__ q, const uint8_t* __restrict__ sc, i
       default: return &stg3;
     }
   };
+  PanelOffs offA, offB;
+  panel_offsets(n, rowA, offA);
+  panel_offsets(n, rowB, offB);
   auto issue_step = [&](int64_t step) {
-    Stage* st = stage_ptr(step);
+    Stage* sp = stage_ptr(step);
     const int64_t kc = k0 + step * KS8;
-    issue_codes(q, n, rowA, kc, kend, st->a);
-    issue_codes(q, n, rowB, kc, kend, st->b);   // diagonal tiles too: uniform load counts
-    issue_scales(sc, n, rowA, kc, st->sa);
-    issue_scales(sc, n, rowB, kc, st->sb);
+    issue_panel(q, sc, n, kc, offA, sp->a, sp->sa);
+    issue_panel(q, sc, n, kc, offB, sp->b, sp->sb);   // diagonal tiles too: uniform load counts
   };
-
-  for (int64_t st = 0; st < NS - 1 && st < nsteps; ++st) issue_step(st);
-  for (int64_t s = 0; s < nsteps; ++s) {
-    // loads issued after step s's: steps s+1 .. min(s + NS - 2, nsteps - 1)
+  // this wave's operands of one step, read from LDS into registers
+  auto body = [&](int64_t s) {
+    // step s has landed: loads issued after it are steps s+1 .. min(s + NS - 2, nsteps - 1)
     const int64_t later = min<int64_t>(NS - 2, nsteps - 1 - s);
     if (later >= 2) DFI_WAIT_VM(2 * LOADS_PER_STEP);
     else if (later == 1) DFI_WAIT_VM(LOADS_PER_STEP);
     else DFI_WAIT_VM(0);
-    // Every wave's loads for step s have landed and every wave has finished reading stage
-    // (s - 1) % NS. A bare barrier: __syncthreads() would also wait for the later stages' loads.
     asm volatile("s_barrier" ::: "memory");
     if (s + NS - 1 < nsteps) issue_step(s + NS - 1);
     const Stage* cu = stage_ptr(s);
-    const int sbyte = (int)(((k0 + s * KS8) >> 5) & 3) + half;   // this step's block h in the scale word
+    const int sbyte = (int)(((k0 + s * KS8) >> 5) & 3) + half;
     i32x8 fb[NB];
     int sbv[NB];
 #pragma unroll
@@ -689,20 +691,32 @@ gram_kernel_fp8(const uint8_t* __restrict__ q, const uint8_t* __restrict__ sc, i
       fb[j] = read_frag(cu->b, r, half);
       sbv[j] = cu->sb[4 * r + sbyte];
     }
+    i32x8 fa[2];
+    int sav[2];
+    {
+      const int r = wr * WT + l32;
+      fa[0] = read_frag(cu->a, r, half);
+      sav[0] = cu->sa[4 * r + sbyte];
+    }
 #pragma unroll
     for (int i = 0; i < NB; ++i) {
-      const int r = wr * WT + i * 32 + l32;
-      i32x8 fa = read_frag(cu->a, r, half);
-      const int sav = cu->sa[4 * r + sbyte];
-#pragma unroll
-      for (int e = 0; e < 8; ++e) fa[e] ^= flip;
+      if (i + 1 < NB) {
+        const int r = wr * WT + (i + 1) * 32 + l32;
+        fa[(i + 1) & 1] = read_frag(cu->a, r, half);
+        sav[(i + 1) & 1] = cu->sa[4 * r + sbyte];
+      }
+      __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
       for (int j = 0; j < NB; ++j)
-        acc[i][j] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(fa, fb[j], acc[i][j], 0, 0, 0, sav, 0, sbv[j]);
+        acc[i][j] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(fa[i & 1], fb[j], acc[i][j], 0, 0, 0, sav[i & 1], 0,
+                                                                    sbv[j]);
+      __builtin_amdgcn_sched_barrier(0);
     }
-  }
+  };
+  const int64_t npro = min<int64_t>(NS - 1, nsteps);
+  for (int64_t s0 = 0; s0 < npro; ++s0) issue_step(s0);
+  for (int64_t s = 0; s < nsteps; ++s) body(s);
 
-  const float sgn = (slice & 1) ? -1.f : 1.f;
   float* out = part + (slice * ntri + tile) * (int64_t)(T * T);
 #pragma unroll
   for (int i = 0; i < NB; ++i)
@@ -712,7 +726,7 @@ gram_kernel_fp8(const uint8_t* __restrict__ q, const uint8_t* __restrict__ sc, i
       for (int r = 0; r < 16; ++r) {
         const int row = wr * WT + i * 32 + 8 * (r >> 2) + 4 * half + (r & 3);
         const int col = wc * WT + j * 32 + l32;
-        out[row * T + col] = active ? sgn * acc[i][j][r] : 0.f;
+        out[row * T + col] = active ? acc[i][j][r] : 0.f;
       }
 }
 
@@ -727,12 +741,13 @@ gram_kernel_fp8(const uint8_t* __restrict__ q, const uint8_t* __restrict__ sc, i
 //   * k-step = 16 columns: 32 bytes of each of the 256 rows of a panel, per plane. One wave
 //     instruction moves 32 rows straight to LDS (two 16-byte chunks per row); a row's chunks are
 //     swapped when (row >> 2) is odd, so the fragment reads of 8 consecutive rows cover all banks.
-//   * Four LDS stages of 32 KB (A hi, A lo, B hi, B lo); loads run three steps ahead of the
-//     matrix cores, with the same vmcnt-counted waits as v3 (every wave issues the same number of
-//     loads per step; diagonal tiles load their B panel too).
+//   * Four LDS stages of 32 KB (A hi, A lo, B hi, B lo) and two register sets of operands, with
+//     the same schedule and vmcnt-counted waits as v3 (every wave issues the same number of loads
+//     per step; diagonal tiles load their B panel too).
 //   * v_mfma_f32_32x32x16_bf16: lane l supplies row l % 32 and columns 8h .. 8h + 7 of the step
 //     (h = l / 32), for A and B alike.
-//   * Columns [m8, m), m8 = m rounded down to 8, are left to the FP64 reduction.
+//   * The slices cover all of [0, ldh): past m the planes hold zeros, so every k-step is whole;
+//     the reduction adds no tail columns for this kernel.
 //   * Alternating slice sign as in v1: odd slices flip the sign bits of A's fragments.
 namespace v4 {
 
@@ -749,8 +764,6 @@ constexpr int LOADS_PER_STEP = 4 * INSTR;        // A hi, A lo, B hi, B lo
 
 typedef __attribute__((address_space(3))) void lds_void;
 
-__device__ __align__(16) uint16_t g_zero_chunk16[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-
 struct Stage {
   uint8_t ah[PANEL];
   uint8_t al[PANEL];
@@ -758,12 +771,15 @@ struct Stage {
   uint8_t bl[PANEL];
 };
 
-// One plane of one 256-row panel for the step at column kcol. Wave instruction i moves rows
-// 32 g .. 32 g + 31 (g = wave + 4 i); lane l fills LDS row 32 g + l / 2, chunk slot l % 2, with
-// column chunk (l % 2) ^ ((row >> 2) & 1) of that row (or zeros past kend).
-__device__ __forceinline__ void issue_plane(const uint16_t* __restrict__ plane, int64_t n, int64_t row0,
-                                            int64_t kcol, int64_t kend, uint8_t* panel) {
-  const uint16_t* pb = plane + ((kcol >> 6) * n << 6) + (kcol & 63);   // this step's 16 values of row 0
+// Loop-invariant per-lane element offsets (inside one 64-column block of a plane) of the chunks
+// this lane moves for a 256-row panel: wave instruction i carries rows 32 g .. 32 g + 31
+// (g = wave + 4 i); lane l fills LDS row 32 g + l / 2, chunk slot l % 2, with column chunk
+// (l % 2) ^ ((row >> 2) & 1). Rows past n are clamped to n - 1 (their products are never stored).
+struct PanelOffs {
+  uint32_t e[INSTR];
+};
+
+__device__ __forceinline__ void panel_offsets(int64_t n, int64_t row0, PanelOffs& po) {
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
 #pragma unroll
@@ -771,14 +787,21 @@ __device__ __forceinline__ void issue_plane(const uint16_t* __restrict__ plane, 
     const int g = wave + NW * i;
     const int r = 32 * g + (lane >> 1);
     const int c = (lane & 1) ^ ((r >> 2) & 1);
-    int64_t R = row0 + r;
-    if (R >= n) R = n - 1;
-    const int64_t col = kcol + 8 * c;
-    // branch-free choice of the source keeps the per-step load count fixed (see v3)
-    const uint64_t in = (uint64_t)0 - (uint64_t)(col < kend);
-    const uint64_t addr = ((uint64_t)(uintptr_t)(pb + (R << 6) + 8 * c) & in) |
-                          ((uint64_t)(uintptr_t)g_zero_chunk16 & ~in);
-    __builtin_amdgcn_global_load_lds((const void*)(uintptr_t)addr, (lds_void*)(panel + 32 * g * ROWB), 16, 0, 0);
+    const int64_t R = min(row0 + r, n - 1);
+    po.e[i] = (uint32_t)((R << 6) + 8 * c);
+  }
+}
+
+// One plane of one panel for the step at column kcol (a multiple of 16): every step lies inside
+// [0, ldh), where the row pass wrote zeros past m, so nothing is masked.
+__device__ __forceinline__ void issue_plane(const uint16_t* __restrict__ plane, int64_t n, int64_t kcol,
+                                            const PanelOffs& po, uint8_t* panel) {
+  const uint16_t* pb = plane + ((kcol >> 6) * n << 6) + (kcol & 63);   // row 0 of this step, uniform
+  const int wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int i = 0; i < INSTR; ++i) {
+    const int g = wave + NW * i;
+    __builtin_amdgcn_global_load_lds((const void*)(pb + po.e[i]), (lds_void*)(panel + 32 * g * ROWB), 16, 0, 0);
   }
 }
 
@@ -786,11 +809,16 @@ __device__ __forceinline__ bf16x8 read_bf(const uint8_t* panel, int r, int h) {
   return *reinterpret_cast<const bf16x8*>(panel + r * ROWB + 16 * (h ^ ((r >> 2) & 1)));
 }
 
+// One wave's operands of one k-step: hi and lo fragments of its 4 A and 4 B row blocks.
+struct Frags {
+  bf16x8 ah[NB], al[NB], bh[NB], bl[NB];
+};
+
 // G = true: a grouped launch over jobs[0 .. njobs) (the scalar arguments are then ignored).
 template <bool G>
 __global__ void __launch_bounds__(NT, 1)
 gram_kernel_split(const uint16_t* __restrict__ hi, const uint16_t* __restrict__ lo, int64_t n,
-                  int64_t m8, int64_t ntri, int64_t nslice, int64_t kslice, float* __restrict__ part,
+                  int64_t kcap, int64_t ntri, int64_t nslice, int64_t kslice, float* __restrict__ part,
                   const GramJob* __restrict__ jobs, int njobs) {
   __shared__ Stage stg0, stg1, stg2, stg3;
 
@@ -800,7 +828,7 @@ gram_kernel_split(const uint16_t* __restrict__ hi, const uint16_t* __restrict__ 
     hi = static_cast<const uint16_t*>(jb.a);
     lo = static_cast<const uint16_t*>(jb.b);
     n = jb.n;
-    m8 = jb.kcap;
+    kcap = jb.kcap;
     ntri = jb.ntri;
     nslice = jb.nslice;
     kslice = jb.kslice;
@@ -819,8 +847,8 @@ gram_kernel_split(const uint16_t* __restrict__ hi, const uint16_t* __restrict__ 
   const bool diag = (ti == tj);
   const int64_t rowA = ti * T, rowB = tj * T;
   const int64_t k0 = slice * kslice;
-  const int64_t kend = min(m8, k0 + kslice);
-  const int64_t nsteps = (kend > k0) ? (kend - k0 + KSB - 1) / KSB : 0;
+  const int64_t kend = min(kcap, k0 + kslice);
+  const int64_t nsteps = (kend > k0) ? (kend - k0) / KSB : 0;   // both multiples of 16
 
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
@@ -845,44 +873,78 @@ gram_kernel_split(const uint16_t* __restrict__ hi, const uint16_t* __restrict__ 
       default: return &stg3;
     }
   };
+  PanelOffs offA, offB;
+  panel_offsets(n, rowA, offA);
+  panel_offsets(n, rowB, offB);
   auto issue_step = [&](int64_t step) {
     Stage* sp = stage_ptr(step);
     const int64_t kc = k0 + step * KSB;
-    issue_plane(hi, n, rowA, kc, kend, sp->ah);
-    issue_plane(lo, n, rowA, kc, kend, sp->al);
-    issue_plane(hi, n, rowB, kc, kend, sp->bh);
-    issue_plane(lo, n, rowB, kc, kend, sp->bl);
+    issue_plane(hi, n, kc, offA, sp->ah);
+    issue_plane(lo, n, kc, offA, sp->al);
+    issue_plane(hi, n, kc, offB, sp->bh);   // diagonal tiles too: uniform load counts
+    issue_plane(lo, n, kc, offB, sp->bl);
   };
-
-  for (int64_t s0 = 0; s0 < NS - 1 && s0 < nsteps; ++s0) issue_step(s0);
-  for (int64_t s = 0; s < nsteps; ++s) {
-    const int64_t later = min<int64_t>(NS - 2, nsteps - 1 - s);
-    if (later >= 2) DFI_WAIT_VM(2 * LOADS_PER_STEP);
-    else if (later == 1) DFI_WAIT_VM(LOADS_PER_STEP);
-    else DFI_WAIT_VM(0);
-    asm volatile("s_barrier" ::: "memory");
-    if (s + NS - 1 < nsteps) issue_step(s + NS - 1);
-    const Stage* cu = stage_ptr(s);
-    bf16x8 bh[NB], bl[NB];
+  auto load_frags = [&](int64_t step, Frags& f) {
+    const Stage* cu = stage_ptr(step);
 #pragma unroll
     for (int j = 0; j < NB; ++j) {
       const int r = wc * WT + j * 32 + l32;
-      bh[j] = read_bf(cu->bh, r, half);
-      bl[j] = read_bf(cu->bl, r, half);
+      f.bh[j] = read_bf(cu->bh, r, half);
+      f.bl[j] = read_bf(cu->bl, r, half);
     }
 #pragma unroll
     for (int i = 0; i < NB; ++i) {
       const int r = wr * WT + i * 32 + l32;
-      const bf16x8 ah = flip_sign(read_bf(cu->ah, r, half), bflip);
-      const bf16x8 al = flip_sign(read_bf(cu->al, r, half), bflip);
+      f.ah[i] = read_bf(cu->ah, r, half);
+      f.al[i] = read_bf(cu->al, r, half);
+    }
+  };
+  auto mfma_step = [&](const Frags& f) {
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+      const bf16x8 ah = flip_sign(f.ah[i], bflip);
+      const bf16x8 al = flip_sign(f.al[i], bflip);
 #pragma unroll
       for (int j = 0; j < NB; ++j) {
-        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, bh[j], acc[i][j], 0, 0, 0);
-        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bl[j], acc[i][j], 0, 0, 0);
-        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, bh[j], acc[i][j], 0, 0, 0);
+        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, f.bh[j], acc[i][j], 0, 0, 0);
+        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, f.bl[j], acc[i][j], 0, 0, 0);
+        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, f.bh[j], acc[i][j], 0, 0, 0);
       }
     }
+  };
+  // Same schedule as the scaled-FP8 kernel: step s + 1's operands are read into the spare register
+  // set while step s's products run; stage s is refilled with step s + NS after the barrier.
+  auto body = [&](int64_t s, Frags& cur, Frags& nxt) {
+    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+    if (s + 1 < nsteps) {
+      const int64_t later = min<int64_t>(NS - 2, nsteps - 2 - s);
+      if (later >= 2) DFI_WAIT_VM(2 * LOADS_PER_STEP);
+      else if (later == 1) DFI_WAIT_VM(LOADS_PER_STEP);
+      else DFI_WAIT_VM(0);
+    }
+    asm volatile("s_barrier" ::: "memory");
+    if (s + NS < nsteps) issue_step(s + NS);
+    if (s + 1 < nsteps) load_frags(s + 1, nxt);
+    mfma_step(cur);
+  };
+
+  Frags f0, f1;
+  const int64_t npro = min<int64_t>(NS, nsteps);
+  for (int64_t s0 = 0; s0 < npro; ++s0) issue_step(s0);
+  if (nsteps > 0) {
+    if (npro >= 4) DFI_WAIT_VM(3 * LOADS_PER_STEP);
+    else if (npro == 3) DFI_WAIT_VM(2 * LOADS_PER_STEP);
+    else if (npro == 2) DFI_WAIT_VM(LOADS_PER_STEP);
+    else DFI_WAIT_VM(0);
+    asm volatile("s_barrier" ::: "memory");
+    load_frags(0, f0);
   }
+  int64_t s = 0;
+  for (; s + 1 < nsteps; s += 2) {
+    body(s, f0, f1);
+    body(s + 1, f1, f0);
+  }
+  if (s < nsteps) body(s, f0, f1);
 
   const float sgn = (slice & 1) ? -1.f : 1.f;
   float* out = part + (slice * ntri + tile) * (int64_t)(T * T);
@@ -981,17 +1043,18 @@ void gram_q_candidates(int64_t n, int64_t m, size_t max_part_bytes, int* out, in
 hipError_t gram_launch_fp8(const GramPlan& p, const uint8_t* q, const uint8_t* sc, int64_t ldq, float* part,
                            hipStream_t st) {
   const dim3 grid((unsigned)(p.nslice * p.ntri));
-  if ((ldq & 127) != 0 || ldq < p.m) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(v3::gram_kernel_fp8<false>, grid, dim3(v3::NT), 0, st, q, sc, p.n, p.m & ~(int64_t)15, p.ntri,
-                     p.nslice, p.kslice, part, (const GramJob*)nullptr, 0);
+  if ((ldq & 127) != 0 || ldq < p.m || p.nslice * p.kslice < ldq || (p.kslice & 63) != 0) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(v3::gram_kernel_fp8<false>, grid, dim3(v3::NT), 0, st, q, sc, p.n, ldq, p.ntri, p.nslice,
+                     p.kslice, part, (const GramJob*)nullptr, 0);
   return hipGetLastError();
 }
 
 hipError_t gram_launch_split(const GramPlan& p, const uint16_t* hi, const uint16_t* lo, float* part, hipStream_t st) {
   if (p.prec != 1 || p.ldh <= 0 || (p.ldh & 63) != 0) return hipErrorInvalidValue;
   const dim3 grid((unsigned)(p.nslice * p.ntri));
-  hipLaunchKernelGGL(v4::gram_kernel_split<false>, grid, dim3(v4::NT), 0, st, hi, lo, p.n, p.m & ~(int64_t)7, p.ntri,
-                     p.nslice, p.kslice, part, (const GramJob*)nullptr, 0);
+  if (p.nslice * p.kslice < p.ldh || (p.kslice & 15) != 0) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(v4::gram_kernel_split<false>, grid, dim3(v4::NT), 0, st, hi, lo, p.n, p.ldh, p.ntri, p.nslice,
+                     p.kslice, part, (const GramJob*)nullptr, 0);
   return hipGetLastError();
 }
 
@@ -1020,8 +1083,8 @@ static bool use_v2(const GramPlan& p, const float* S) {
 }
 
 static int64_t tail_start(const GramPlan& p, const float* S) {
-  if (p.prec == 2) return p.m & ~(int64_t)15;
-  if (p.prec == 1 && p.ldh > 0) return p.m & ~(int64_t)7;
+  if (p.prec == 2) return p.m;   // the FP8 kernel covers every column (zero codes past m)
+  if (p.prec == 1 && p.ldh > 0) return p.m;   // the plane kernel covers every column (zeros past m)
   return use_v2(p, S) ? (p.m & ~(int64_t)3) : p.m;
 }
 

@@ -1,8 +1,8 @@
 // Blocked right-looking FP64 Cholesky W = L L^T (Algorithm 1 step 2), in place on a row-major
 // n x n matrix, lower triangle. Block size 64; per block column k:
-//   1. potf2   one wave factors the 64 x 64 diagonal block in LDS (left-looking: lane i owns
-//              row i and forms column j from dot products with the finished columns), then forms
-//              the block's inverse L_kk^-1 (lane c solves for column c).
+//   1. potf2   one wave factors the 64 x 64 diagonal block (right-looking: lane i keeps row i in
+//              registers; each column is scaled, broadcast through LDS and subtracted from the
+//              trailing rows), then forms the block's inverse L_kk^-1 (lane c owns column c).
 //   2. trsm    rows below the block: A_ik <- A_ik L_kk^-T as a product with the stored inverse,
 //              64 rows per workgroup, every output independent.
 //   3. update  trailing lower triangle A_IJ -= A_Ik A_Jk^T in 64 x 64 tiles on the FP64 matrix
@@ -42,54 +42,56 @@ potf2_kernel(double* __restrict__ A, int64_t n, int64_t k, int64_t* __restrict__
     Dkk += bb * NB * NB;
   }
   if (*(volatile int32_t*)flag) return;
-  const int lane = threadIdx.x;
+  const int i = threadIdx.x;   // lane i owns row i of the block
   const int64_t nb = min<int64_t>(NB, n - k);
-  // Load the lower triangle of the diagonal block; pad beyond nb with the identity.
-  for (int i = 0; i < NB; ++i) {
-    const int j = lane;
-    double val = 0.0;
-    if (i < nb && j < nb) {
-      if (j <= i) val = A[(k + i) * n + k + j];
-    } else if (i == j) {
-      val = 1.0;
-    }
-    a[i * LDP + j] = val;
+  // Row i of the lower triangle in registers; rows and columns beyond nb padded with the identity.
+  double r[NB];
+#pragma unroll
+  for (int c = 0; c < NB; ++c) {
+    double val = (c == i) ? 1.0 : 0.0;
+    if (i < nb && c < nb && c <= i) val = A[(k + i) * n + k + c];
+    r[c] = val;
   }
-  __syncthreads();
-  const int i = lane;
+  // Right-looking: at step j lane j holds the updated pivot; column j is scaled and broadcast
+  // through LDS, and every lane subtracts its rank-1 update from the rest of its row (independent
+  // FMAs, no dependence chain). The order of the subtractions from a_ic is l = 0, 1, ..., c - 1.
+#pragma unroll
   for (int j = 0; j < NB; ++j) {
-    // lane i >= j: s = a_ij - sum_{l<j} L_il L_jl
-    double s = (i >= j) ? a[i * LDP + j] : 0.0;
-    for (int l = 0; l < j; ++l) s -= a[i * LDP + l] * a[j * LDP + l];
-    const double d = __shfl(s, j, 64);
+    const double d = __shfl(r[j], j, 64);
     if (!(d > 0.0)) {
-      if (lane == 0) {
+      if (i == 0) {
         *info = k + j + 1;
         *flag = 1;
       }
       return;
     }
     const double ljj = sqrt(d);
-    if (i == j) a[i * LDP + j] = ljj;
-    else if (i > j) a[i * LDP + j] = s / ljj;
+    const double lij = (i > j) ? r[j] / ljj : ((i == j) ? ljj : 0.0);
+    r[j] = lij;
+    a[i * LDP + j] = lij;                 // column j of L (also kept for the inverse below)
     __syncthreads();
+#pragma unroll
+    for (int c = j + 1; c < NB; ++c) r[c] -= lij * a[c * LDP + j];
   }
-  for (int r = 0; r < nb; ++r) {
-    if (lane <= r) A[(k + r) * n + k + lane] = a[r * LDP + lane];
+  // store the factor's lower triangle
+  for (int rr = 0; rr < nb; ++rr) {
+    if (i <= rr) A[(k + rr) * n + k + i] = a[rr * LDP + i];
   }
   if (k + NB >= n) return;  // no rows below: the inverse is not needed
-  // Dkk = L_kk^-1; lane c forms column c (x_l = 0 for l < c).
-  const int c = lane;
+  // Dkk = L_kk^-1, lane c owning column c of the inverse, also right-looking: x = e_c; for each
+  // row q: x_q /= L_qq, then x_t -= L_tq x_q for t > q (independent FMAs per step).
+  const int c = i;
   double x[NB];
 #pragma unroll
-  for (int r = 0; r < NB; ++r) {
-    double s = (r == c) ? 1.0 : 0.0;
+  for (int t = 0; t < NB; ++t) x[t] = (t == c) ? 1.0 : 0.0;
 #pragma unroll
-    for (int l = 0; l < r; ++l) s -= a[r * LDP + l] * x[l];
-    x[r] = (r >= c) ? s / a[r * LDP + r] : 0.0;
+  for (int q = 0; q < NB; ++q) {
+    x[q] = x[q] / a[q * LDP + q];
+#pragma unroll
+    for (int t = q + 1; t < NB; ++t) x[t] -= a[t * LDP + q] * x[q];
   }
 #pragma unroll
-  for (int r = 0; r < NB; ++r) Dkk[r * NB + c] = x[r];
+  for (int t = 0; t < NB; ++t) Dkk[t * NB + c] = x[t];
 }
 
 // Rows i in [k + NB, n): A[i][k .. k+NB) <- A[i][k .. k+NB) L_kk^-T, i.e. out_rc = sum_l A_rl D_cl.

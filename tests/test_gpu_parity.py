@@ -135,10 +135,8 @@ def test_gram_mxfp8(dfl, ctx, oracle_mod, n, m):
     S = synth.make_S(n, m, synth.seed(36, n), "iid")
     W = dfl.dfisher_gram(ctx, dev_strided(S, (m + 3) // 4 * 4), dfl.DFISHER_GRAM_MXFP8, 0.0).cpu().numpy()
     deq, _ = oracle_mod.quant_mxfp8(S)
-    m16 = m - m % 16
-    # the last m mod 16 columns are added exactly, not quantized
-    Sq = np.concatenate([deq[:, :m16], S[:, m16:]], axis=1).astype(np.float32)
-    Wq = oracle_mod.gram(Sq, 0.0)
+    # every column's products come from the quantized values; only the diagonal is exact
+    Wq = oracle_mod.gram(deq, 0.0)
     Wex = oracle_mod.gram(S, 0.0)
     np.fill_diagonal(Wq, np.diag(Wex))
     np.testing.assert_allclose(np.diag(W), np.diag(Wex), rtol=1e-13)
@@ -462,12 +460,13 @@ def test_autotune_save_load(dfl, oracle_mod, tmp_path):
     assert (prec, tiles, lg, al) == (1, 2, 15, 1) and 1 <= q <= 64 and mode in (0, 1)
     c2 = dfl.dfisher_ctx_create(0)
     dfl.dfisher_ctx_load_tuning(c2, path)
-    x, _ = dfl.dfisher_solve(c2, Sd, vd, lam, gram_prec=1, sweeps=1, x_fp64=True)
+    x, _ = dfl.dfisher_solve(c2, Sd, vd, lam, gram_prec=1, sweeps=2, x_fp64=True)
     assert rel(x.cpu().numpy(), oracle_mod.solve(S, v, lam)) <= 1e-6
     dfl.dfisher_ctx_enable_autotune(c2, True)
     S2 = synth.make_S(64, 8192, synth.seed(46, 64))
     v2 = synth.make_v(S2, synth.seed(46, 64))
-    x2, _ = dfl.dfisher_solve(c2, dev(S2), dev(v2), 1e-2, gram_prec=2, sweeps=2, x_fp64=True)
+    x2, _ = dfl.dfisher_solve(c2, dev(S2), dev(v2), 1e-2, gram_prec=2, sweeps=4, x_fp64=True,
+                              shift_policy=dfl.DFISHER_SHIFT_ALWAYS)
     assert rel(x2.cpu().numpy(), oracle_mod.solve(S2, v2, 1e-2)) <= 1e-6
     dfl.dfisher_ctx_save_tuning(c2, path)
     assert len([l for l in open(path) if not l.startswith("#")]) == 2
