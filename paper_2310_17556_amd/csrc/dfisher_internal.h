@@ -76,13 +76,13 @@ RowPassPlan rowpass_plan(int64_t n, int64_t m, int64_t lds);
 // With q != nullptr the pass also writes the scaled-FP8 copy of S (codes n x ldq bytes, E8M0
 // scale bytes n x ldq/32; ldq a multiple of 64, >= m; needs 16-byte aligned rows and want_d).
 // Row-major, or with `blocked` (ldq a multiple of 128) in the column-blocked layout the
-// scaled-FP8 Gram reads: 128-column blocks, each holding all n rows contiguously, code (i, k) at
-// q[((k / 128) n + i) 128 + k % 128], scale byte (i, k / 32) at sc[((k / 128) n + i) 4 + (k / 32) % 4].
+// scaled-FP8 Gram reads: codes in 64-column blocks, each holding all n rows contiguously, code
+// (i, k) at q[((k / 64) n + i) 64 + k % 64]; scale byte (i, k / 32) at sc[((k / 128) n + i) 4 + (k / 32) % 4].
 hipError_t rowpass_launch(const RowPassPlan& p, const float* S, const float* v, const double* vd,
                           bool want_b, bool want_d, double* part, hipStream_t st, uint8_t* q = nullptr,
                           uint8_t* sc = nullptr, int64_t ldq = 0, bool blocked = false);
 // Row pass that also writes the split-BF16 planes of S: hi = bf16_rne(S), lo = bf16_rne(S - hi),
-// column-blocked in 64-column blocks of all n rows: element (i, k) at [((k / 64) n + i) 64 + k % 64]
+// column-blocked in 16-column blocks of all n rows: element (i, k) at [((k / 16) n + i) 16 + k % 16]
 // (ldh = m rounded up to 64; entries k >= m are zero). Needs 16-byte aligned rows; always
 // computes d, and b when v != nullptr.
 hipError_t rowpass_launch_split(const RowPassPlan& p, const float* S, const float* v, double* part, uint16_t* hi,

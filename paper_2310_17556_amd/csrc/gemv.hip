@@ -87,19 +87,11 @@ __device__ __forceinline__ void load_s4(const float* __restrict__ p, int64_t col
 
 // Grid: x = row blocks of RP_WAVES * RP_RPW rows, y = column groups of `cg` columns (multiple
 // of RP_SUB). part layout: part_b[g * n + i], part_d[(ngroups + g) * n + i].
-// QM selects an extra output, written for every column k < ldq (zero input beyond m); all need the
-// vectorised path:
-//   QM = 1: the scaled-FP8 form of S, row-major: codes q[i * ldq + k] (E4M3, round to nearest
-//           even) and scale exponents sc[i * (ldq / 32) + k / 32] (E8M0 byte e + 127) per
-//           32-column block; a block is 8 consecutive lanes of one 16-byte load.
-//   QM = 3: the same codes and scales, column-blocked for the Gram kernel: columns are cut into
-//           128-wide blocks and block b holds all n rows contiguously, code (i, k) at
-//           q[((k / 128) n + i) 128 + k % 128] and its scale byte at
-//           sc[((k / 128) n + i) 4 + (k / 32) % 4]. A k-step of a row panel is then one
-//           contiguous stretch of memory instead of one piece per row.
-//   QM = 2: the split-BF16 planes hi = bf16_rne(S_ik), lo = bf16_rne(S_ik - hi) (S_ik - hi is
-//           exact in FP32), column-blocked in 64-wide blocks: element (i, k) at
-//           [((k / 64) n + i) 64 + k % 64]; hi and lo are passed in q and sc as bf16 arrays.
+// QM = 1 also writes the scaled-FP8 form of S, row-major, for every column k < ldq (zero input
+// beyond m; needs the vectorised path): codes q[i * ldq + k] (E4M3, round to nearest even) and
+// scale exponents sc[i * (ldq / 32) + k / 32] (E8M0 byte e + 127) per 32-column block; a block is
+// 8 consecutive lanes of one 16-byte load. (The Gram's column-blocked operands come from
+// rowpass_prep_kernel.)
 template <typename VT, bool WANT_B, bool WANT_D, int QM>
 __global__ void __launch_bounds__(64 * RP_WAVES)
 rowpass_kernel(const float* __restrict__ S, int64_t n, int64_t m, int64_t lds, const VT* __restrict__ v,
@@ -142,25 +134,7 @@ rowpass_kernel(const float* __restrict__ S, int64_t n, int64_t m, int64_t lds, c
             if constexpr (WANT_B) ab[r] = fma(s, (double)vv[u].x[e], ab[r]);
             if constexpr (WANT_D) ad[r] = fma(s, s, ad[r]);
           }
-        if constexpr (QM == 2) {
-#pragma unroll
-          for (int u = 0; u < RP_U; ++u) {
-            const int64_t col = cs + 256 * u + 4 * lane;
-            bf16x4 h, l;
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-              const __bf16 hb = (__bf16)sv[u][e];        // round to nearest even
-              h[e] = hb;
-              l[e] = (__bf16)(sv[u][e] - (float)hb);
-            }
-            if (col < ldq) {
-              const int64_t off = (((col >> 6) * n + row0 + r) << 6) + (col & 63);
-              *reinterpret_cast<bf16x4*>(reinterpret_cast<__bf16*>(q) + off) = h;
-              *reinterpret_cast<bf16x4*>(reinterpret_cast<__bf16*>(sc) + off) = l;
-            }
-          }
-        }
-        if constexpr (QM == 1 || QM == 3) {
+        if constexpr (QM == 1) {
 #pragma unroll
           for (int u = 0; u < RP_U; ++u) {
             const int64_t col = cs + 256 * u + 4 * lane;
@@ -174,14 +148,8 @@ rowpass_kernel(const float* __restrict__ S, int64_t n, int64_t m, int64_t lds, c
             int packed = __builtin_amdgcn_cvt_pk_fp8_f32(sv[u][0] * inv, sv[u][1] * inv, 0, false);
             packed = __builtin_amdgcn_cvt_pk_fp8_f32(sv[u][2] * inv, sv[u][3] * inv, packed, true);
             if (col < ldq) {
-              if constexpr (QM == 1) {
-                *reinterpret_cast<int*>(q + (row0 + r) * ldq + col) = packed;
-                if ((lane & 7) == 0) sc[(row0 + r) * (ldq >> 5) + (col >> 5)] = (uint8_t)(ex + 127);
-              } else {
-                const int64_t blk = (col >> 7) * n + row0 + r;
-                *reinterpret_cast<int*>(q + (blk << 7) + (col & 127)) = packed;
-                if ((lane & 7) == 0) sc[(blk << 2) + ((col >> 5) & 3)] = (uint8_t)(ex + 127);
-              }
+              *reinterpret_cast<int*>(q + (row0 + r) * ldq + col) = packed;
+              if ((lane & 7) == 0) sc[(row0 + r) * (ldq >> 5) + (col >> 5)] = (uint8_t)(ex + 127);
             }
           }
         }
@@ -315,6 +283,133 @@ __global__ void colpass_finalize_kernel(const double* __restrict__ part, int64_t
   }
 }
 
+// Row pass that also writes the Gram's operands in their column-blocked layouts (QM = 3: scaled-FP8
+// codes in 64-column blocks + scale bytes; QM = 2: split-BF16 planes in 16-column blocks). A wave
+// owns RP_RPW = 8 consecutive rows and walks its column group 256 columns at a time (one 16-byte
+// load per lane and row). The converted values of the 8 rows go to a per-wave LDS buffer laid out
+// like the global blocks, so each global store covers one block's 8 consecutive rows: 512 bytes
+// of codes, or 256 bytes of a plane, contiguous. b = S v (if WANT_B) and d_i = |s_i|^2 accumulate in
+// FP64 as in rowpass_kernel. Needs the vectorised path (16-byte aligned rows); every column below
+// ldq (zero input past m) is written.
+constexpr int RPREP_COLS = 256;
+constexpr int RPREP_STAGE = RP_RPW * RPREP_COLS * 4;   // bytes per wave: 8 rows x 256 columns x (hi + lo)
+
+template <bool WANT_B, int QM>
+__global__ void __launch_bounds__(64 * RP_WAVES)
+rowpass_prep_kernel(const float* __restrict__ S, int64_t n, int64_t m, int64_t lds, const float* __restrict__ v,
+                    int64_t cg, double* __restrict__ part, int vec, uint8_t* __restrict__ q, uint8_t* __restrict__ sc,
+                    int64_t ldq) {
+  __shared__ __align__(16) uint8_t stage_all[RP_WAVES][RPREP_STAGE];
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  uint8_t* stg = stage_all[wave];
+  const int64_t row0 = ((int64_t)blockIdx.x * RP_WAVES + wave) * RP_RPW;
+  const int64_t g = blockIdx.y;
+  const int64_t ngroups = gridDim.y;
+  const int64_t c0 = g * cg;
+  const int64_t c1 = min(m, c0 + cg);
+  if (row0 >= n) return;
+  const int nr = (int)min<int64_t>(RP_RPW, n - row0);
+
+  double ab[RP_RPW], ad[RP_RPW];
+#pragma unroll
+  for (int r = 0; r < RP_RPW; ++r) { ab[r] = 0.0; ad[r] = 0.0; }
+
+  for (int64_t cs = c0; cs < c1; cs += RPREP_COLS) {
+    const int64_t col = cs + 4 * lane;
+    f32x4 vv = {0.f, 0.f, 0.f, 0.f};
+    if constexpr (WANT_B) load_s4(v + col, col, c1, (vec & 2) != 0, vv);
+    f32x4 sv[RP_RPW];
+#pragma unroll
+    for (int r = 0; r < RP_RPW; ++r) {
+      sv[r] = (f32x4){0.f, 0.f, 0.f, 0.f};
+      if (r < nr) load_s4(S + (row0 + r) * lds + col, col, c1, (vec & 1) != 0, sv[r]);
+    }
+#pragma unroll
+    for (int r = 0; r < RP_RPW; ++r)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const double s = (double)sv[r][e];
+        if constexpr (WANT_B) ab[r] = fma(s, (double)vv[e], ab[r]);
+        ad[r] = fma(s, s, ad[r]);
+      }
+    if constexpr (QM == 3) {
+      // codes of row r, columns col..col+3: block b = lane / 16 (64 columns), row r inside it
+#pragma unroll
+      for (int r = 0; r < RP_RPW; ++r) {
+        float amax = fmaxf(fmaxf(fabsf(sv[r][0]), fabsf(sv[r][1])), fmaxf(fabsf(sv[r][2]), fabsf(sv[r][3])));
+        amax = fmaxf(amax, __shfl_xor(amax, 1, 64));
+        amax = fmaxf(amax, __shfl_xor(amax, 2, 64));
+        amax = fmaxf(amax, __shfl_xor(amax, 4, 64));
+        const int ex = mx_scale_exp(amax);
+        const float inv = pow2_neg(ex);
+        // |sv * inv| <= 448 by the choice of ex; the conversion rounds to nearest even
+        int packed = __builtin_amdgcn_cvt_pk_fp8_f32(sv[r][0] * inv, sv[r][1] * inv, 0, false);
+        packed = __builtin_amdgcn_cvt_pk_fp8_f32(sv[r][2] * inv, sv[r][3] * inv, packed, true);
+        *reinterpret_cast<int*>(stg + ((lane >> 4) * RP_RPW + r) * 64 + (lane & 15) * 4) = packed;
+        if ((lane & 7) == 0 && r < nr && col < ldq)
+          sc[(((col >> 7) * n + row0 + r) << 2) + ((col >> 5) & 3)] = (uint8_t)(ex + 127);
+      }
+      asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+      // 4 blocks x (8 rows x 64 bytes): lane l stores bytes 8 (l % 8) .. of row l / 8
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const int64_t bc = cs + 64 * b;   // first column of the block
+        const int r = lane >> 3;
+        const uint64_t w = *reinterpret_cast<const uint64_t*>(stg + (b * RP_RPW + r) * 64 + (lane & 7) * 8);
+        if (r < nr && bc < ldq)
+          *reinterpret_cast<uint64_t*>(q + (((bc >> 6) * n + row0 + r) << 6) + (lane & 7) * 8) = w;
+      }
+    } else {
+      // planes of row r, columns col..col+3: block b = lane / 4 (16 columns); hi at [0, 4 KB), lo after
+#pragma unroll
+      for (int r = 0; r < RP_RPW; ++r) {
+        bf16x4 h, l;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const __bf16 hb = (__bf16)sv[r][e];        // round to nearest even
+          h[e] = hb;
+          l[e] = (__bf16)(sv[r][e] - (float)hb);
+        }
+        const int off = ((lane >> 2) * RP_RPW + r) * 32 + (lane & 3) * 8;
+        *reinterpret_cast<bf16x4*>(stg + off) = h;
+        *reinterpret_cast<bf16x4*>(stg + RPREP_STAGE / 2 + off) = l;
+      }
+      asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+      // per plane 16 blocks x (8 rows x 32 bytes); one store covers two blocks: lanes 0-31 block
+      // 2i, lanes 32-63 block 2i + 1; lane l stores bytes 8 (l % 4) .. of row (l % 32) / 4
+      __bf16* hi = reinterpret_cast<__bf16*>(q);
+      __bf16* lo = reinterpret_cast<__bf16*>(sc);
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const int b = 2 * i + (lane >> 5);
+        const int r = (lane & 31) >> 2;
+        const int64_t bc = cs + 16 * b;
+        const int soff = (b * RP_RPW + r) * 32 + (lane & 3) * 8;
+        const uint64_t wh = *reinterpret_cast<const uint64_t*>(stg + soff);
+        const uint64_t wl = *reinterpret_cast<const uint64_t*>(stg + RPREP_STAGE / 2 + soff);
+        if (r < nr && bc < ldq) {
+          const int64_t e0 = (((bc >> 4) * n + row0 + r) << 4) + (lane & 3) * 4;   // element offset
+          *reinterpret_cast<uint64_t*>(hi + e0) = wh;
+          *reinterpret_cast<uint64_t*>(lo + e0) = wl;
+        }
+      }
+    }
+    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");   // the buffer is rewritten next iteration
+  }
+#pragma unroll
+  for (int r = 0; r < RP_RPW; ++r) {
+    if (r < nr) {
+      if constexpr (WANT_B) {
+        const double t = wave_sum(ab[r]);
+        if (lane == 0) part[g * n + row0 + r] = t;
+      }
+      const double t = wave_sum(ad[r]);
+      if (lane == 0) part[(ngroups + g) * n + row0 + r] = t;
+    }
+  }
+}
+
 bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
 
 }  // namespace
@@ -351,9 +446,9 @@ hipError_t rowpass_launch(const RowPassPlan& p, const float* S, const float* v, 
     if (!vec || !want_d || vd || (ldq & 63) != 0 || ldq < p.m) return hipErrorInvalidValue;
     if (blocked && (ldq & 127) != 0) return hipErrorInvalidValue;
     if (blocked && want_b)
-      hipLaunchKernelGGL((rowpass_kernel<float, true, true, 3>), grid, block, 0, st, S, p.n, p.m, p.lds, v, p.chunk, p.nchunk, part, iv, q, sc, ldq);
+      hipLaunchKernelGGL((rowpass_prep_kernel<true, 3>), grid, block, 0, st, S, p.n, p.m, p.lds, v, p.chunk, part, iv, q, sc, ldq);
     else if (blocked)
-      hipLaunchKernelGGL((rowpass_kernel<float, false, true, 3>), grid, block, 0, st, S, p.n, p.m, p.lds, (const float*)nullptr, p.chunk, p.nchunk, part, iv, q, sc, ldq);
+      hipLaunchKernelGGL((rowpass_prep_kernel<false, 3>), grid, block, 0, st, S, p.n, p.m, p.lds, (const float*)nullptr, p.chunk, part, iv, q, sc, ldq);
     else if (want_b)
       hipLaunchKernelGGL((rowpass_kernel<float, true, true, 1>), grid, block, 0, st, S, p.n, p.m, p.lds, v, p.chunk, p.nchunk, part, iv, q, sc, ldq);
     else
@@ -388,9 +483,9 @@ hipError_t rowpass_launch_split(const RowPassPlan& p, const float* S, const floa
   uint8_t* qh = reinterpret_cast<uint8_t*>(hi);
   uint8_t* ql = reinterpret_cast<uint8_t*>(lo);
   if (v)
-    hipLaunchKernelGGL((rowpass_kernel<float, true, true, 2>), grid, block, 0, st, S, p.n, p.m, p.lds, v, p.chunk, p.nchunk, part, iv, qh, ql, ldh);
+    hipLaunchKernelGGL((rowpass_prep_kernel<true, 2>), grid, block, 0, st, S, p.n, p.m, p.lds, v, p.chunk, part, iv, qh, ql, ldh);
   else
-    hipLaunchKernelGGL((rowpass_kernel<float, false, true, 2>), grid, block, 0, st, S, p.n, p.m, p.lds, (const float*)nullptr, p.chunk, p.nchunk, part, iv, qh, ql, ldh);
+    hipLaunchKernelGGL((rowpass_prep_kernel<false, 2>), grid, block, 0, st, S, p.n, p.m, p.lds, (const float*)nullptr, p.chunk, part, iv, qh, ql, ldh);
   return hipGetLastError();
 }
 

@@ -504,10 +504,11 @@ gram_kernel_v2(const float* __restrict__ S, int64_t n, int64_t lds, int64_t m, i
 
 // ---------------------------------------------------------------------------------------------
 // Gram kernel v3: scaled FP8. The operands are the block-scaled E4M3 codes written by the row
-// pass in its column-blocked layout: 128-column blocks, each holding all n rows contiguously
-// (code (i, k) at q[((k / 128) n + i) 128 + k % 128]; the four E8M0 scale bytes of row i and
-// block k / 128 form one aligned 4-byte word at sc[((k / 128) n + i) 4]). The 256 rows of a
-// panel are then adjacent in memory for every k-step (few pages per step instead of one per row).
+// pass in its column-blocked layout: 64-column blocks (one k-step), each holding all n rows
+// contiguously (code (i, k) at q[((k / 64) n + i) 64 + k % 64]; the four E8M0 scale bytes of row
+// i and 128-column block k / 128 form one aligned 4-byte word at sc[((k / 128) n + i) 4]). A
+// k-step of a 256-row panel is then 16 KB of dense contiguous memory: whole cache lines, few
+// pages, half the memory requests of 64-byte pieces of longer rows.
 //   * k-step = 64 columns (two scale blocks). Codes move direct-to-LDS: each wave instruction
 //     carries 16 rows x 64 B; row r's four 16-byte chunks are XOR-swizzled by (r >> 2) & 3 so the
 //     fragment reads of 16 consecutive rows hit distinct banks. Scale bytes move direct-to-LDS as
@@ -567,7 +568,7 @@ __device__ __forceinline__ void panel_offsets(int64_t n, int64_t row0, PanelOffs
     const int r = 16 * g + (lane >> 2);
     const int c = (lane & 3) ^ ((r >> 2) & 3);
     const int64_t R = min(row0 + r, n - 1);
-    po.code[i] = (uint32_t)((R << 7) + 16 * c);
+    po.code[i] = (uint32_t)((R << 6) + 16 * c);
   }
   po.scale = (uint32_t)(min(row0 + 64 * wave + lane, n - 1) << 2);
 }
@@ -578,7 +579,7 @@ __device__ __forceinline__ void panel_offsets(int64_t n, int64_t row0, PanelOffs
 __device__ __forceinline__ void issue_panel(const uint8_t* __restrict__ q, const uint8_t* __restrict__ sc, int64_t n,
                                             int64_t kcol, const PanelOffs& po, uint8_t* panel, uint8_t* sdst) {
   const int wave = threadIdx.x >> 6;
-  const uint8_t* qb = q + ((kcol >> 7) * n << 7) + (kcol & 127);   // row 0 of this step, uniform
+  const uint8_t* qb = q + ((kcol >> 6) * n << 6);   // row 0 of this step's block, uniform
 #pragma unroll
   for (int i = 0; i < T / 16 / NW; ++i) {
     const int g = wave + NW * i;
@@ -734,8 +735,9 @@ gram_kernel_fp8(const uint8_t* __restrict__ q, const uint8_t* __restrict__ sc, i
 
 // ---------------------------------------------------------------------------------------------
 // Gram kernel v4: split-BF16 from pre-split planes. The row pass writes hi = bf16_rne(S) and
-// lo = bf16_rne(S - hi) as two bf16 planes in its column-blocked layout (64-column blocks of all
-// n rows, element (i, k) at [((k / 64) n + i) 64 + k % 64]); the tile kernel is then a plain bf16
+// lo = bf16_rne(S - hi) as two bf16 planes in its column-blocked layout (16-column blocks, one
+// k-step, of all n rows: element (i, k) at [((k / 16) n + i) 16 + k % 16], so a step of a panel
+// is 8 KB of dense contiguous memory); the tile kernel is then a plain bf16
 // matrix-core product with three terms per pair of elements (lo.hi, hi.lo, hi.hi) and no
 // conversion work in its loop.
 //   * k-step = 16 columns: 32 bytes of each of the 256 rows of a panel, per plane. One wave
@@ -771,7 +773,7 @@ struct Stage {
   uint8_t bl[PANEL];
 };
 
-// Loop-invariant per-lane element offsets (inside one 64-column block of a plane) of the chunks
+// Loop-invariant per-lane element offsets (inside one 16-column block of a plane) of the chunks
 // this lane moves for a 256-row panel: wave instruction i carries rows 32 g .. 32 g + 31
 // (g = wave + 4 i); lane l fills LDS row 32 g + l / 2, chunk slot l % 2, with column chunk
 // (l % 2) ^ ((row >> 2) & 1). Rows past n are clamped to n - 1 (their products are never stored).
@@ -788,7 +790,7 @@ __device__ __forceinline__ void panel_offsets(int64_t n, int64_t row0, PanelOffs
     const int r = 32 * g + (lane >> 1);
     const int c = (lane & 1) ^ ((r >> 2) & 1);
     const int64_t R = min(row0 + r, n - 1);
-    po.e[i] = (uint32_t)((R << 6) + 8 * c);
+    po.e[i] = (uint32_t)((R << 4) + 8 * c);
   }
 }
 
@@ -796,7 +798,7 @@ __device__ __forceinline__ void panel_offsets(int64_t n, int64_t row0, PanelOffs
 // [0, ldh), where the row pass wrote zeros past m, so nothing is masked.
 __device__ __forceinline__ void issue_plane(const uint16_t* __restrict__ plane, int64_t n, int64_t kcol,
                                             const PanelOffs& po, uint8_t* panel) {
-  const uint16_t* pb = plane + ((kcol >> 6) * n << 6) + (kcol & 63);   // row 0 of this step, uniform
+  const uint16_t* pb = plane + ((kcol >> 4) * n << 4);   // row 0 of this step's block, uniform
   const int wave = threadIdx.x >> 6;
 #pragma unroll
   for (int i = 0; i < INSTR; ++i) {
