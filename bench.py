@@ -112,7 +112,12 @@ GRAM_KERNEL = {"fp32": "gram_kernel_v2<0>", "bf16x3": "gram_kernel_split", "mxfp
 # HBM bytes per launch of the Gram tile kernel at the full workload, from rocprofv3 FETCH_SIZE /
 # WRITE_SIZE passes (each scaled by the same counters' reading for a device copy of known size),
 # valid only for the kernel source they were taken on (sha256 of csrc/gram.hip); see profiles/.
-GRAM_TRAFFIC = {}
+GRAM_TRAFFIC = {
+    ("mxfp8", 4096, 4_000_000): {
+        "gram_hip_sha256": "d8749722c10d04bf2d10fac7323d903ea8238d991ee987e911e793c561e83493",
+        "bytes_per_launch": 62.96e9 + 1.14e9,   # FETCH_SIZE x 2 + WRITE_SIZE x 1 (KiB -> bytes)
+    },
+}
 
 
 def gram_traffic(prec, n, m):
@@ -264,7 +269,8 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-m", type=int, default=8192)
     ap.add_argument("--seed", type=int, default=3)
-    ap.add_argument("--alt-prec", default="bf16x3", help="second mixed precision timed for comparison ('' to skip)")
+    ap.add_argument("--alt-prec", default="bf16x3", choices=sorted(PREC_CODE) + ["none"],
+                    help="second mixed precision timed for comparison (none: skip)")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched multi-lambda/RHS leg")
     ap.add_argument("--no-uneven", action="store_true", help="skip the uneven-batch leg")
     ap.add_argument("--leg-reps", type=int, default=3, help="timed calls of the batched and uneven legs")
@@ -334,7 +340,7 @@ def main() -> int:
         log(f"[bench] fp32: {fp32['solves_per_s']:.3f} solves/s, gram {g32avg:.2f} ms")
 
     alt = None
-    if args.alt_prec and args.alt_prec != args.prec:
+    if args.alt_prec != "none" and args.alt_prec != args.prec:
         log(f"[bench] {args.alt_prec} path: 1 step")
         xbalt = {lam: torch.empty(m, dtype=torch.float32, device=dev) for lam in lams}
         ea, ga, sta, infa = run_path(dfl, ctx, S, v, lams, args.alt_prec, args.sweeps, 1, 1, xbalt, args.shift)

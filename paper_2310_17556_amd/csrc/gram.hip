@@ -514,11 +514,12 @@ gram_kernel_v2(const float* __restrict__ S, int64_t n, int64_t lds, int64_t m, i
 //     fragment reads of 16 consecutive rows hit distinct banks. Scale bytes move direct-to-LDS as
 //     one 4-byte word per row (four blocks, 128 columns; the step uses two of them), since the LDS
 //     side of these loads advances 4 bytes per lane.
-//   * Four LDS stages: the direct-to-LDS loads run three steps ahead of the matrix cores. Every
-//     wave issues the same number of loads per step (diagonal tiles load their B panel as well),
-//     so waiting for a stage is a vmcnt wait on the count of loads issued after it, plus one
-//     barrier per step. Inside a step the wave reads its four B fragments, then each A fragment
-//     one MFMA group ahead of its use, so the LDS latency hides behind the previous group.
+//   * Four LDS stages: the direct-to-LDS loads run up to four steps ahead of the matrix cores.
+//     Every wave issues the same number of loads per step (diagonal tiles load their B panel as
+//     well), so waiting for a stage is a vmcnt wait on the count of loads issued after it, plus
+//     one barrier per step. Inside a step each A fragment is read one MFMA group ahead of its use;
+//     the step's barrier sits before its last group, so the next step's B fragments and first A
+//     fragment are read while that group's products run.
 //   * v_mfma_scale_f32_32x32x64_f8f6f4: lane l supplies row (l % 32), 16 codes from scale block 0
 //     and 16 from block 1 of the step (bytes [16h, 16h+16) and [32+16h, 32+16h+16) for h = l/32),
 //     and the E8M0 scale of block h of its row. A and B use the same byte arrangement, so every
@@ -674,31 +675,35 @@ gram_kernel_fp8(const uint8_t* __restrict__ q, const uint8_t* __restrict__ sc, i
     issue_panel(q, sc, n, kc, offB, sp->b, sp->sb);   // diagonal tiles too: uniform load counts
   };
   // this wave's operands of one step, read from LDS into registers
-  auto body = [&](int64_t s) {
-    // step s has landed: loads issued after it are steps s+1 .. min(s + NS - 2, nsteps - 1)
-    const int64_t later = min<int64_t>(NS - 2, nsteps - 1 - s);
-    if (later >= 2) DFI_WAIT_VM(2 * LOADS_PER_STEP);
-    else if (later == 1) DFI_WAIT_VM(LOADS_PER_STEP);
-    else DFI_WAIT_VM(0);
-    asm volatile("s_barrier" ::: "memory");
-    if (s + NS - 1 < nsteps) issue_step(s + NS - 1);
-    const Stage* cu = stage_ptr(s);
-    const int sbyte = (int)(((k0 + s * KS8) >> 5) & 3) + half;
+  // head of a step: the four B fragments with their scales and the first A fragment
+  struct Head {
     i32x8 fb[NB];
     int sbv[NB];
+    i32x8 fa0;
+    int sa0;
+  };
+  auto load_head = [&](int64_t step, Head& h) {
+    const Stage* cu = stage_ptr(step);
+    const int sbyte = (int)(((k0 + step * KS8) >> 5) & 3) + half;
 #pragma unroll
     for (int j = 0; j < NB; ++j) {
       const int r = wc * WT + j * 32 + l32;
-      fb[j] = read_frag(cu->b, r, half);
-      sbv[j] = cu->sb[4 * r + sbyte];
+      h.fb[j] = read_frag(cu->b, r, half);
+      h.sbv[j] = cu->sb[4 * r + sbyte];
     }
+    const int r = wr * WT + l32;
+    h.fa0 = read_frag(cu->a, r, half);
+    h.sa0 = cu->sa[4 * r + sbyte];
+  };
+  // Step s from head h (already in registers): A fragments 1..3 are read one group ahead; after
+  // the third group every LDS read of step s is done, so the wave waits for step s + 1's loads,
+  // meets the others at the barrier, refills stage s with step s + NS and reads step s + 1's head
+  // into hn while the last group of matrix-core products runs.
+  auto body = [&](int64_t s, Head& h, Head& hn) {
+    const Stage* cu = stage_ptr(s);
+    const int sbyte = (int)(((k0 + s * KS8) >> 5) & 3) + half;
     i32x8 fa[2];
     int sav[2];
-    {
-      const int r = wr * WT + l32;
-      fa[0] = read_frag(cu->a, r, half);
-      sav[0] = cu->sa[4 * r + sbyte];
-    }
 #pragma unroll
     for (int i = 0; i < NB; ++i) {
       if (i + 1 < NB) {
@@ -706,17 +711,44 @@ gram_kernel_fp8(const uint8_t* __restrict__ q, const uint8_t* __restrict__ sc, i
         fa[(i + 1) & 1] = read_frag(cu->a, r, half);
         sav[(i + 1) & 1] = cu->sa[4 * r + sbyte];
       }
+      if (i == NB - 1) {
+        asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+        if (s + 1 < nsteps) {
+          const int64_t later = min<int64_t>(NS - 2, nsteps - 2 - s);
+          if (later >= 2) DFI_WAIT_VM(2 * LOADS_PER_STEP);
+          else if (later == 1) DFI_WAIT_VM(LOADS_PER_STEP);
+          else DFI_WAIT_VM(0);
+        }
+        asm volatile("s_barrier" ::: "memory");
+        if (s + NS < nsteps) issue_step(s + NS);
+        if (s + 1 < nsteps) load_head(s + 1, hn);
+      }
       __builtin_amdgcn_sched_barrier(0);
+      const i32x8 a = (i == 0) ? h.fa0 : fa[i & 1];
+      const int sa = (i == 0) ? h.sa0 : sav[i & 1];
 #pragma unroll
       for (int j = 0; j < NB; ++j)
-        acc[i][j] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(fa[i & 1], fb[j], acc[i][j], 0, 0, 0, sav[i & 1], 0,
-                                                                    sbv[j]);
+        acc[i][j] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a, h.fb[j], acc[i][j], 0, 0, 0, sa, 0, h.sbv[j]);
       __builtin_amdgcn_sched_barrier(0);
     }
   };
-  const int64_t npro = min<int64_t>(NS - 1, nsteps);
+  Head h0, h1;
+  const int64_t npro = min<int64_t>(NS, nsteps);
   for (int64_t s0 = 0; s0 < npro; ++s0) issue_step(s0);
-  for (int64_t s = 0; s < nsteps; ++s) body(s);
+  if (nsteps > 0) {
+    if (npro >= 4) DFI_WAIT_VM(3 * LOADS_PER_STEP);
+    else if (npro == 3) DFI_WAIT_VM(2 * LOADS_PER_STEP);
+    else if (npro == 2) DFI_WAIT_VM(LOADS_PER_STEP);
+    else DFI_WAIT_VM(0);
+    asm volatile("s_barrier" ::: "memory");
+    load_head(0, h0);
+  }
+  int64_t s = 0;
+  for (; s + 1 < nsteps; s += 2) {
+    body(s, h0, h1);
+    body(s + 1, h1, h0);
+  }
+  if (s < nsteps) body(s, h0, h1);
 
   float* out = part + (slice * ntri + tile) * (int64_t)(T * T);
 #pragma unroll
