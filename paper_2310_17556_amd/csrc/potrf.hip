@@ -1,8 +1,9 @@
 // Blocked right-looking FP64 Cholesky W = L L^T (Algorithm 1 step 2), in place on a row-major
 // n x n matrix, lower triangle. Block size 64; per block column k:
-//   1. potf2   one wave factors the 64 x 64 diagonal block (right-looking: lane i keeps row i in
-//              registers; each column is scaled, broadcast through LDS and subtracted from the
-//              trailing rows), then forms the block's inverse L_kk^-1 (lane c owns column c).
+//   1. potf2   four waves factor the 64 x 64 diagonal block (right-looking: lane i keeps row i
+//              in registers, each wave a quarter of its columns; each column is scaled, broadcast
+//              through LDS and subtracted from the trailing columns), then form the block's
+//              inverse L_kk^-1 the same way (lane c owns column c).
 //   2. trsm    rows below the block: A_ik <- A_ik L_kk^-T as a product with the stored inverse,
 //              64 rows per workgroup, every output independent.
 //   3. update  trailing lower triangle A_IJ -= A_Ik A_Jk^T in 64 x 64 tiles on the FP64 matrix
@@ -22,18 +23,37 @@ typedef double f64x4 __attribute__((ext_vector_type(4)));
 constexpr int NB = 64;
 constexpr int LDP = NB + 1;  // padded LDS row (doubles)
 
-__global__ void __launch_bounds__(64)
+constexpr int PW = 4;          // waves of the diagonal-block kernel
+constexpr int PC = NB / PW;    // 16 columns (factor) or rows of the inverse per wave
+
+// Diagonal block: L_kk = chol(A_kk) and Dkk = L_kk^-1, with 4 waves. Lane i holds row i of the
+// block, wave w its columns 16 w .. 16 w + 15, in registers. Right-looking: at step j the wave
+// owning column j scales it by the pivot's square root and publishes it in LDS (column-major, so
+// a wave reads the 16 entries l_cj it needs as 8 two-double broadcasts); after a barrier every
+// wave subtracts l_ij l_cj from its columns c > j (independent FMAs, no dependence chain). The
+// subtractions from a_ic come in the order l = 0, 1, ..., c - 1. A pivot that is not > 0 stops
+// all four waves together (LDS flag) and is reported as its 1-based global index.
+// Inverse, also right-looking: lane c holds column c of L_kk^-1, wave w its rows 16 w .. + 15;
+// x = e_c; for each q: x_q /= l_qq (owning wave, published in LDS), then x_t -= l_tq x_q, t > q.
+// The step loops run over the four column (row) groups without unrolling and unroll the 16 steps
+// inside a group, so the owner's register index is a constant and the code stays a few thousand
+// instructions (a fully unrolled 64-step body overflows the instruction cache).
+constexpr int LDT = NB + 1;   // padded column stride of the LDS copy of L_kk (doubles)
+
+__global__ void __launch_bounds__(64 * PW)
 potf2_kernel(double* __restrict__ A, int64_t n, int64_t k, int64_t* __restrict__ info, int32_t* __restrict__ flag,
              double* __restrict__ Dkk, int64_t sA, const FactorJob* __restrict__ jobs) {
-  __shared__ double a[NB * LDP];
+  __shared__ double lt[NB * LDT];   // l_ij at lt[j * LDT + i], filled column by column
+  __shared__ double xs[2][NB];      // the inverse's pivot row, double-buffered
+  __shared__ int failed;
   const int64_t bb = blockIdx.y;
   if (jobs) {
-    const FactorJob& j = jobs[bb];
-    A = j.A;
-    n = j.n;
-    info = j.info;
-    flag = j.flag;
-    Dkk = j.dkk;
+    const FactorJob& jb = jobs[bb];
+    A = jb.A;
+    n = jb.n;
+    info = jb.info;
+    flag = jb.flag;
+    Dkk = jb.dkk;
     if (k >= n) return;
   } else {
     A += bb * sA;
@@ -42,56 +62,86 @@ potf2_kernel(double* __restrict__ A, int64_t n, int64_t k, int64_t* __restrict__
     Dkk += bb * NB * NB;
   }
   if (*(volatile int32_t*)flag) return;
-  const int i = threadIdx.x;   // lane i owns row i of the block
+  const int i = threadIdx.x & 63;      // row of the block
+  const int w = threadIdx.x >> 6;
+  const int c0 = w * PC;               // this wave's first column
   const int64_t nb = min<int64_t>(NB, n - k);
-  // Row i of the lower triangle in registers; rows and columns beyond nb padded with the identity.
-  double r[NB];
+  if (threadIdx.x == 0) failed = 0;
+  double r[PC];
 #pragma unroll
-  for (int c = 0; c < NB; ++c) {
-    double val = (c == i) ? 1.0 : 0.0;
+  for (int u = 0; u < PC; ++u) {
+    const int c = c0 + u;
+    double val = (c == i) ? 1.0 : 0.0;   // identity padding past nb
     if (i < nb && c < nb && c <= i) val = A[(k + i) * n + k + c];
-    r[c] = val;
+    r[u] = val;
   }
-  // Right-looking: at step j lane j holds the updated pivot; column j is scaled and broadcast
-  // through LDS, and every lane subtracts its rank-1 update from the rest of its row (independent
-  // FMAs, no dependence chain). The order of the subtractions from a_ic is l = 0, 1, ..., c - 1.
+  __syncthreads();
+#pragma unroll 1
+  for (int jb = 0; jb < PW; ++jb) {
 #pragma unroll
-  for (int j = 0; j < NB; ++j) {
-    const double d = __shfl(r[j], j, 64);
-    if (!(d > 0.0)) {
-      if (i == 0) {
-        *info = k + j + 1;
-        *flag = 1;
+    for (int jj = 0; jj < PC; ++jj) {
+      const int j = jb * PC + jj;
+      if (w == jb) {   // wave-uniform: the owner of column j
+        const double d = __shfl(r[jj], j, 64);
+        if (!(d > 0.0)) {
+          if (i == 0) {
+            *info = k + j + 1;
+            *flag = 1;
+            failed = 1;
+          }
+        } else {
+          const double ljj = sqrt(d);
+          const double lij = (i > j) ? r[jj] / ljj : ((i == j) ? ljj : 0.0);
+          r[jj] = lij;
+          lt[j * LDT + i] = lij;
+        }
       }
-      return;
+      __syncthreads();
+      if (failed) return;   // uniform: every thread sees the flag after the barrier
+      const double* col = lt + j * LDT + c0;   // l_cj for this wave's columns c = c0 + u
+      if (w > jb) {
+        const double lij = lt[j * LDT + i];
+#pragma unroll
+        for (int u = 0; u < PC; ++u) r[u] -= lij * col[u];
+      } else if (w == jb) {
+        const double lij = r[jj];
+#pragma unroll
+        for (int u = jj + 1; u < PC; ++u) r[u] -= lij * col[u];
+      }
     }
-    const double ljj = sqrt(d);
-    const double lij = (i > j) ? r[j] / ljj : ((i == j) ? ljj : 0.0);
-    r[j] = lij;
-    a[i * LDP + j] = lij;                 // column j of L (also kept for the inverse below)
-    __syncthreads();
-#pragma unroll
-    for (int c = j + 1; c < NB; ++c) r[c] -= lij * a[c * LDP + j];
   }
-  // store the factor's lower triangle
-  for (int rr = 0; rr < nb; ++rr) {
-    if (i <= rr) A[(k + rr) * n + k + i] = a[rr * LDP + i];
-  }
+  // the factor's lower triangle: wave w stores rows w, w + 4, ..., lane c column c
+  for (int rr = w; rr < nb; rr += PW)
+    if (i <= rr) A[(k + rr) * n + k + i] = lt[i * LDT + rr];
   if (k + NB >= n) return;  // no rows below: the inverse is not needed
-  // Dkk = L_kk^-1, lane c owning column c of the inverse, also right-looking: x = e_c; for each
-  // row q: x_q /= L_qq, then x_t -= L_tq x_q for t > q (independent FMAs per step).
-  const int c = i;
-  double x[NB];
+  const int cc = i;   // column of the inverse
+  double x[PC];
 #pragma unroll
-  for (int t = 0; t < NB; ++t) x[t] = (t == c) ? 1.0 : 0.0;
+  for (int u = 0; u < PC; ++u) x[u] = (c0 + u == cc) ? 1.0 : 0.0;
+#pragma unroll 1
+  for (int qb = 0; qb < PW; ++qb) {
 #pragma unroll
-  for (int q = 0; q < NB; ++q) {
-    x[q] = x[q] / a[q * LDP + q];
+    for (int qq = 0; qq < PC; ++qq) {
+      const int q = qb * PC + qq;
+      if (w == qb) {
+        x[qq] = x[qq] / lt[q * LDT + q];
+        xs[q & 1][cc] = x[qq];
+      }
+      __syncthreads();
+      const double* col = lt + q * LDT + c0;   // l_tq for this wave's rows t = c0 + u
+      if (w > qb) {
+        const double xq = xs[q & 1][cc];
 #pragma unroll
-    for (int t = q + 1; t < NB; ++t) x[t] -= a[t * LDP + q] * x[q];
+        for (int u = 0; u < PC; ++u) x[u] -= col[u] * xq;
+      } else if (w == qb) {
+        const double xq = x[qq];
+#pragma unroll
+        for (int u = qq + 1; u < PC; ++u) x[u] -= col[u] * xq;
+      }
+    }
   }
 #pragma unroll
-  for (int t = 0; t < NB; ++t) Dkk[t * NB + c] = x[t];
+  for (int u = 0; u < PC; ++u) Dkk[(c0 + u) * NB + cc] = x[u];   // D[t][c] = (L_kk^-1)_tc
 }
 
 // Rows i in [k + NB, n): A[i][k .. k+NB) <- A[i][k .. k+NB) L_kk^-T, i.e. out_rc = sum_l A_rl D_cl.
@@ -278,7 +328,7 @@ hipError_t potrf_launch_batched(double* A, int64_t n, int64_t nbatch, int64_t sA
                      nbatch);
   const FactorJob* nj = nullptr;
   for (int64_t k = 0; k < n; k += NB) {
-    hipLaunchKernelGGL(potf2_kernel, dim3(1, nb), dim3(64), 0, st, A, n, k, info_dev, flag_dev, dkk, sA, nj);
+    hipLaunchKernelGGL(potf2_kernel, dim3(1, nb), dim3(64 * PW), 0, st, A, n, k, info_dev, flag_dev, dkk, sA, nj);
     const int64_t rest = n - k - NB;
     if (rest > 0) {
       const int64_t rb = (rest + 63) / 64;
@@ -304,7 +354,7 @@ hipError_t potrf_launch_grouped(const FactorJob* jobs_dev, int64_t njobs, int64_
   const unsigned nb = (unsigned)njobs;
   hipLaunchKernelGGL(clear_jobs_kernel, dim3((unsigned)((njobs + 255) / 256)), dim3(256), 0, st, jobs_dev, njobs);
   for (int64_t k = 0; k < nmax; k += NB) {
-    hipLaunchKernelGGL(potf2_kernel, dim3(1, nb), dim3(64), 0, st, (double*)nullptr, (int64_t)0, k, (int64_t*)nullptr,
+    hipLaunchKernelGGL(potf2_kernel, dim3(1, nb), dim3(64 * PW), 0, st, (double*)nullptr, (int64_t)0, k, (int64_t*)nullptr,
                        (int32_t*)nullptr, (double*)nullptr, (int64_t)0, jobs_dev);
     const int64_t rest = nmax - k - NB;
     if (rest > 0) {
