@@ -239,14 +239,14 @@ struct SolveBufs {
 };
 
 SolveBufs carve(char* base, int64_t n, int64_t m, const dfi::GramPlan* gp, const dfi::RowPassPlan& rp,
-                const dfi::ColPassPlan& cp, bool need_L, bool need_t) {
+                const dfi::ColPassPlan& cp, bool need_L, bool need_t, const dfi::RefinePassPlan* fp = nullptr) {
   Carver c;
   c.base = base;
   SolveBufs s{};
   s.W = gp ? c.take<double>((size_t)(n * n)) : nullptr;
   s.L = need_L ? c.take<double>((size_t)(n * n)) : nullptr;
   s.gpart = gp ? c.take<float>(gp->part_bytes / sizeof(float)) : nullptr;
-  s.rpart = c.take<double>(rp.part_bytes / sizeof(double) + 1);
+  s.rpart = c.take<double>(std::max(rp.part_bytes, fp ? fp->part_bytes : 0) / sizeof(double) + 1);
   s.cpart = c.take<double>(cp.part_bytes / sizeof(double) + 1);
   s.b = c.take<double>((size_t)n);
   s.d = c.take<double>((size_t)n);
@@ -328,17 +328,25 @@ dfisher_status gram_stage(const float* S, const float* v, const dfi::GramPlan& g
 }
 
 // y = W^-1 b through the factor, then `sweeps` refinement sweeps against the exact operator
-// W = S S^T + lambda I: r = b - lambda y - S (S^T y) (FP64 accumulation), y += L^-T L^-1 r.
+// W = S S^T + lambda I: r = b - lambda y - S (S^T y) (FP64 accumulation), y += L^-T L^-1 r. The
+// product S (S^T y) takes one read of S through the fused pass when `fp` allows it, else a column
+// pass (t = S^T y into B.t) and a row pass.
 dfisher_status solve_y(const float* S, int64_t n, int64_t m, int64_t lds, double lambda, const double* L,
                        const double* Dinv, const SolveBufs& B, const dfi::RowPassPlan& rp, const dfi::ColPassPlan& cp,
-                       int sweeps, hipStream_t st, StageClock* clk = nullptr) {
+                       int sweeps, hipStream_t st, StageClock* clk = nullptr, const dfi::RefinePassPlan* fp = nullptr) {
   HIP_TRY(dfi::trsv_launch(L, Dinv, n, 0, B.b, B.z, B.tw, st));
   HIP_TRY(dfi::trsv_launch(L, Dinv, n, 1, B.z, B.y, B.tw, st));
   if (clk) clk->mark(5);
+  const bool fused = fp && fp->usable;
   for (int s = 0; s < sweeps; ++s) {
-    HIP_TRY(dfi::colpass_launch(cp, S, n, m, lds, B.y, nullptr, 1.0, B.t, 2, B.cpart, st));
-    HIP_TRY(dfi::rowpass_launch(rp, S, nullptr, B.t, true, false, B.rpart, st));
-    HIP_TRY(dfi::rowpass_reduce(rp, B.rpart, true, false, B.r, nullptr, B.b, B.y, lambda, st));
+    if (fused) {
+      HIP_TRY(dfi::refine_pass_launch(*fp, S, n, m, lds, B.y, B.rpart, st));
+      HIP_TRY(dfi::refine_pass_reduce(*fp, B.rpart, B.r, B.b, B.y, lambda, st));
+    } else {
+      HIP_TRY(dfi::colpass_launch(cp, S, n, m, lds, B.y, nullptr, 1.0, B.t, 2, B.cpart, st));
+      HIP_TRY(dfi::rowpass_launch(rp, S, nullptr, B.t, true, false, B.rpart, st));
+      HIP_TRY(dfi::rowpass_reduce(rp, B.rpart, true, false, B.r, nullptr, B.b, B.y, lambda, st));
+    }
     HIP_TRY(dfi::trsv_launch(L, Dinv, n, 0, B.r, B.z, B.tw, st));
     HIP_TRY(dfi::trsv_launch(L, Dinv, n, 1, B.z, B.r, B.tw, st));
     HIP_TRY(dfi::axpy_inplace(B.y, B.r, n, st));
@@ -540,6 +548,7 @@ struct UnevenLayout {
   std::vector<dfi::GramPlan> gp;
   std::vector<dfi::RowPassPlan> rp;
   std::vector<dfi::ColPassPlan> cp;
+  std::vector<dfi::RefinePassPlan> fp;   // fused refinement product, where usable
   std::vector<int64_t> voff, woff, doff;   // offsets of problem p in the concatenated vectors / matrices
   int64_t ntot = 0, nmax = 0, mmax = 0;
   SolveBufs shared{};                      // scratch reused by every problem (largest sizes)
@@ -555,6 +564,7 @@ void uneven_layout(const dfisher_ctx* ctx, char* base, int32_t np, const float* 
   U.gp.clear();
   U.rp.clear();
   U.cp.clear();
+  U.fp.clear();
   U.voff.assign((size_t)np, 0);
   U.woff.assign((size_t)np, 0);
   U.doff.assign((size_t)np, 0);
@@ -565,6 +575,7 @@ void uneven_layout(const dfisher_ctx* ctx, char* base, int32_t np, const float* 
     U.gp.push_back(make_gram_plan(ctx, S[p], n[p], m[p], lds[p], prec));
     U.rp.push_back(dfi::rowpass_plan(n[p], m[p], lds[p]));
     U.cp.push_back(dfi::colpass_plan(n[p], m[p]));
+    U.fp.push_back(dfi::refine_pass_plan(n[p], m[p], lds[p], S[p]));
     U.voff[(size_t)p] = U.ntot;
     U.woff[(size_t)p] = wtot;
     U.doff[(size_t)p] = dtot;
@@ -574,7 +585,7 @@ void uneven_layout(const dfisher_ctx* ctx, char* base, int32_t np, const float* 
     U.nmax = std::max(U.nmax, n[p]);
     U.mmax = std::max(U.mmax, m[p]);
     gpart = std::max(gpart, U.gp.back().part_bytes);
-    rpart = std::max(rpart, U.rp.back().part_bytes);
+    rpart = std::max(rpart, std::max(U.rp.back().part_bytes, U.fp.back().part_bytes));
     cpart = std::max(cpart, U.cp.back().part_bytes);
     const int64_t ldq = dfi::fp8_ldq(m[p]);
     if (prec == DFISHER_GRAM_MXFP8) {
@@ -646,6 +657,12 @@ dfisher_status uneven_enqueue(dfisher_ctx* ctx, int32_t np, const float* const* 
     // r_p = b_p - lambda_p y_p - S_p (S_p^T y_p), per problem (FP64 accumulation)
     for (int32_t p : order) {
       const int64_t off = U.voff[(size_t)p];
+      if (U.fp[(size_t)p].usable) {   // one read of S_p
+        HIP_TRY(dfi::refine_pass_launch(U.fp[(size_t)p], S[p], n[p], m[p], lds[p], U.y + off, U.shared.rpart, st));
+        HIP_TRY(dfi::refine_pass_reduce(U.fp[(size_t)p], U.shared.rpart, U.r + off, U.b + off, U.y + off, lambda[p],
+                                        st));
+        continue;
+      }
       HIP_TRY(dfi::colpass_launch(U.cp[(size_t)p], S[p], n[p], m[p], lds[p], U.y + off, nullptr, 1.0, U.shared.t, 2,
                                   U.shared.cpart, st));
       HIP_TRY(dfi::rowpass_launch(U.rp[(size_t)p], S[p], nullptr, U.shared.t, true, false, U.shared.rpart, st));
@@ -1147,10 +1164,11 @@ dfisher_status dfisher_solve(dfisher_ctx* ctx, const float* S, int64_t n, int64_
   const dfi::GramPlan gp = make_gram_plan(ctx, S, n, m, lds, o.gram_prec);
   const dfi::RowPassPlan rp = dfi::rowpass_plan(n, m, lds);
   const dfi::ColPassPlan cp = dfi::colpass_plan(n, m);
-  const bool need_t = o.sweeps > 0;
-  SolveBufs B = carve(nullptr, n, m, &gp, rp, cp, true, need_t);
+  const dfi::RefinePassPlan fp = dfi::refine_pass_plan(n, m, lds, S);
+  const bool need_t = o.sweeps > 0 && !fp.usable;
+  SolveBufs B = carve(nullptr, n, m, &gp, rp, cp, true, need_t, &fp);
   DF_TRY(ensure_ws(ctx, B.bytes));
-  B = carve(static_cast<char*>(ctx->ws), n, m, &gp, rp, cp, true, need_t);
+  B = carve(static_cast<char*>(ctx->ws), n, m, &gp, rp, cp, true, need_t, &fp);
   StageClock clk(ctx, st);
   // one pass over S (b = S v, the exact diagonal |s_i|^2, the FP8 codes if used), then step 1
   DF_TRY(gram_stage(S, v, gp, rp, B, lambda, B.W, 0, st, &clk));
@@ -1162,7 +1180,7 @@ dfisher_status dfisher_solve(dfisher_ctx* ctx, const float* S, int64_t n, int64_
   HIP_TRY(dfi::trsv_diag_inv(B.L, n, B.Dinv, st));
   // steps 3-4 inlined: y = W^-1 S v (+ refinement), x = (v - S^T y) / lambda
   clk.mark(4);
-  DF_TRY(solve_y(S, n, m, lds, lambda, B.L, B.Dinv, B, rp, cp, o.sweeps, st, &clk));
+  DF_TRY(solve_y(S, n, m, lds, lambda, B.L, B.Dinv, B, rp, cp, o.sweeps, st, &clk, &fp));
   HIP_TRY(dfi::colpass_launch(cp, S, n, m, lds, B.y, v, lambda, x, o.x_fp64, B.cpart, st));
   clk.mark(7);
   inf.sweeps_done = o.sweeps;

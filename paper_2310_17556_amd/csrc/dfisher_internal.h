@@ -104,6 +104,24 @@ ColPassPlan colpass_plan(int64_t n, int64_t m);
 hipError_t colpass_launch(const ColPassPlan& p, const float* S, int64_t n, int64_t m, int64_t lds, const double* y,
                           const float* v, double lambda, void* out, int mode, double* part, hipStream_t st);
 
+// Fused refinement pass: part[g][i] = per-workgroup partials of (S S^T y)_i with one read of S
+// (n <= 4096 and a multiple of 16, m >= 16, 16-byte aligned rows; `usable` is false otherwise and
+// the caller takes the column pass + row pass). The last m % 16 columns add one more group.
+// refine_pass_reduce: r_i = b_i - lam y_i - sum_g part[g][i] in fixed order.
+struct RefinePassPlan {
+  int64_t n;
+  int nch;            // 16-byte loads per lane and block (8, 16 or 32)
+  bool usable;
+  int64_t ngroups;    // workgroups (one per compute unit)
+  bool tail;          // m % 16 != 0: one more partial group for the last columns
+  size_t part_bytes;  // (ngroups + tail) * n * 8
+};
+RefinePassPlan refine_pass_plan(int64_t n, int64_t m, int64_t lds, const float* S);
+hipError_t refine_pass_launch(const RefinePassPlan& p, const float* S, int64_t n, int64_t m, int64_t lds,
+                              const double* y, double* part, hipStream_t st);
+hipError_t refine_pass_reduce(const RefinePassPlan& p, const double* part, double* r, const double* b,
+                              const double* y, double lam, hipStream_t st);
+
 // ----------------------------------------------------------------------------- multi-vector passes
 // One pass over S for up to MULTI_VECS vectors (batched right-hand sides / damping values).
 constexpr int MULTI_VECS = 8;

@@ -410,6 +410,184 @@ rowpass_prep_kernel(const float* __restrict__ S, int64_t n, int64_t m, int64_t l
   }
 }
 
+// ---------------------------------------------------------------------------- fused refinement pass
+// u = S (S^T y) with one read of S: the product of the exact S S^T with y that the refinement
+// residual needs, without forming t = S^T y in memory. A workgroup of FR_WAVES waves holds a block
+// of FR_COLS = 16 columns over all n rows in registers (one 16-byte load per lane; a wave covers 16
+// rows per load, lane 4 r + q holding columns 4 q .. 4 q + 3 of row r), forms t_c = sum_i S_ic y_i
+// for the block's columns (FP64 products and sums, reduced over the 16 lanes of a column and then
+// over the waves in fixed order through LDS), and adds S_ic t_c to per-lane FP64 row accumulators.
+// In each round the grid takes the next ngroups consecutive blocks; with ngroups a multiple of 8,
+// the workgroups of one XCD (w mod 8, in dispatch order) take a contiguous run of them, so the two
+// halves of each 128-byte line of a row are read through the same L2 at about the same time. At
+// the end each row's accumulators are reduced over its 4 lanes and stored as one partial per
+// workgroup, part[g * n + i], which refine_reduce_kernel adds in fixed order. NCH loads per lane
+// cover n <= 16 FR_WAVES NCH rows; n is a multiple of 16, so a wave's rows of one load are all
+// valid or all past the end. Only whole 16-column blocks are streamed here.
+constexpr int FR_COLS = 16;
+constexpr int FR_WAVES = 8;    // 2 waves per SIMD: 256 registers per lane for 32 loads in flight
+
+template <int NCH>
+__global__ void __launch_bounds__(64 * FR_WAVES)
+refine_pass_kernel(const float* __restrict__ S, int64_t n, int64_t m, int64_t lds, const double* __restrict__ y,
+                   double* __restrict__ part) {
+  constexpr int ROWS = 16 * FR_WAVES;   // rows per load step of the workgroup
+  __shared__ double ys[ROWS * NCH];
+  // Per-wave partials of t and t itself. Single buffers suffice: a block's partials are read
+  // before its second barrier, which every wave passes before writing the next block's.
+  __shared__ double tp[FR_WAVES][FR_COLS];
+  __shared__ double tf[FR_COLS];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int q = lane & 3;
+  const int rbase = wave * 16 + (lane >> 2);
+  for (int idx = tid; idx < ROWS * NCH; idx += 64 * FR_WAVES) ys[idx] = idx < n ? y[idx] : 0.0;
+  __syncthreads();
+  double acc[NCH];
+#pragma unroll
+  for (int c = 0; c < NCH; ++c) acc[c] = 0.0;
+  const int64_t nblk = m / FR_COLS;   // full blocks; the m % 16 last columns go to refine_tail_kernel
+  // addresses: wave-uniform base + a 32-bit lane offset (the plan checks 16 lds * 4 < 2^31)
+  const uint32_t loff = (uint32_t)(((lane >> 2) * lds + 4 * q) * 4);
+  // Block of this workgroup in round s: s G + x (G / 8) + l for workgroup w = 8 l + x (G = grid).
+  const int64_t G = gridDim.x;
+  const int64_t slot = (G & 7) == 0 ? (int64_t)(blockIdx.x & 7) * (G >> 3) + (blockIdx.x >> 3) : (int64_t)blockIdx.x;
+  auto block_of = [&](int64_t s) { return s * G + slot; };
+  // Load c of a block: rows c ROWS + 16 wave .. + 15, as a buffer load from a wave-uniform base
+  // (the block's first column in row c ROWS + 16 wave) with the 32-bit lane offset; for a wave
+  // whose rows of this load lie past n, or with !any (no next block), the buffer has no records:
+  // the load returns zeros without touching memory, and the loop needs no branch around it.
+  auto load = [&](int64_t blk, int c, bool any) -> f32x4 {
+    const int64_t r0 = (int64_t)c * ROWS + wave * 16;
+    const bool in = any && r0 < n;   // uniform
+    const float* base = S + (in ? r0 : 0) * lds + blk * FR_COLS;
+    const __amdgpu_buffer_rsrc_t rs =
+        __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(base), 0, in ? (int)(16 * lds * 4) : 0, 0x00020000);
+    return __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(rs, (int)loff, 0, 0));
+  };
+  // Software pipeline without extra registers: the loads of block s + 1 are issued during the
+  // second product of block s, each into the register its block-s data has just left, so HBM
+  // streams while the matrix of one block is reduced and applied.
+  f32x4 sv[NCH];
+  int64_t s = 0;
+  bool more = block_of(0) < nblk;   // uniform
+  if (more) {
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) sv[c] = load(block_of(0), c, true);
+  }
+  // a do-while with the test at the bottom: no copies of the loop-carried accumulators
+  if (more) do {
+    const int64_t nxt = block_of(s + 1);
+    more = nxt < nblk;
+    double tq[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) {
+      const double yr = ys[c * ROWS + rbase];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) tq[e] = fma((double)sv[c][e], yr, tq[e]);
+    }
+#pragma unroll
+    for (int o = 4; o < 64; o <<= 1)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) tq[e] += __shfl_xor(tq[e], o, 64);
+    if ((lane >> 2) == 0) {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) tp[wave][4 * q + e] = tq[e];
+    }
+    __syncthreads();
+    // wave 0 adds the waves' partials in fixed order: lane (col, g) sums waves 2 g and 2 g + 1,
+    // then the four groups are combined pairwise (commutative adds: every lane gets the same bits)
+    static_assert(FR_WAVES == 8, "the partial sum below takes 4 groups of 2 waves");
+    if (wave == 0) {
+      const int col = lane & 15, g = lane >> 4;
+      double sg = tp[2 * g][col] + tp[2 * g + 1][col];
+      sg += __shfl_xor(sg, 16, 64);
+      sg += __shfl_xor(sg, 32, 64);
+      if (lane < FR_COLS) tf[lane] = sg;
+    }
+    __syncthreads();
+    double t[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) t[e] = tf[4 * q + e];
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) {
+      asm volatile("" : "+v"(sv[c]));   // convert again rather than keep 2 NCH FP64 copies live
+#pragma unroll
+      for (int e = 0; e < 4; ++e) acc[c] = fma((double)sv[c][e], t[e], acc[c]);
+      sv[c] = load(more ? nxt : 0, c, more);
+      __builtin_amdgcn_sched_barrier(0);   // keep the load behind the products that free its register
+    }
+    ++s;
+  } while (more);
+#pragma unroll
+  for (int c = 0; c < NCH; ++c) {
+    double v = acc[c];
+    v += __shfl_xor(v, 1, 64);
+    v += __shfl_xor(v, 2, 64);
+    const int64_t row = (int64_t)c * ROWS + rbase;
+    if (q == 0 && row < n) part[(int64_t)blockIdx.x * n + row] = v;
+  }
+}
+
+// r_i = b_i - lam y_i - sum_g part[g][i] over the fused pass's ngroups partials, with 16 rows and
+// 16 group lanes per 256-thread workgroup: lane s adds groups s, s + 16, ... in order, and the 16
+// lane sums are combined by a fixed pairwise tree in LDS.
+__global__ void __launch_bounds__(256)
+refine_reduce_kernel(const double* __restrict__ part, int64_t n, int64_t ngroups, double* __restrict__ r,
+                     const double* __restrict__ b, const double* __restrict__ y, double lam) {
+  __shared__ double red[16][17];
+  const int tid = threadIdx.x;
+  const int ri = tid & 15, sl = tid >> 4;
+  const int64_t i = (int64_t)blockIdx.x * 16 + ri;
+  double acc = 0.0;
+  if (i < n)
+    for (int64_t g = sl; g < ngroups; g += 16) acc += part[g * n + i];
+  red[sl][ri] = acc;
+  __syncthreads();
+#pragma unroll
+  for (int w = 8; w > 0; w >>= 1) {
+    if (sl < w) red[sl][ri] += red[sl + w][ri];
+    __syncthreads();
+  }
+  if (sl == 0 && i < n) r[i] = (b[i] - lam * y[i]) - red[0][ri];
+}
+
+// The last m % 16 (< 16) columns of the fused pass, as one more group of partials: t_c = sum_i
+// S_ic y_i for those columns (per-thread FP64 partials over rows tid, tid + 256, ..., then added in
+// fixed order through LDS), then part[i] = sum_c S_ic t_c. One workgroup of 256 threads.
+__global__ void __launch_bounds__(256)
+refine_tail_kernel(const float* __restrict__ S, int64_t n, int64_t m, int64_t lds, const double* __restrict__ y,
+                   int64_t c0, double* __restrict__ part) {
+  __shared__ double red[256][FR_COLS];
+  __shared__ double tc[FR_COLS];
+  const int tid = threadIdx.x;
+  const int nt = (int)(m - c0);   // 1 .. 15
+  double p[FR_COLS];
+#pragma unroll
+  for (int c = 0; c < FR_COLS; ++c) p[c] = 0.0;
+  for (int64_t i = tid; i < n; i += 256) {
+    const double yi = y[i];
+#pragma unroll
+    for (int c = 0; c < FR_COLS; ++c)
+      if (c < nt) p[c] = fma((double)S[i * lds + c0 + c], yi, p[c]);
+  }
+#pragma unroll
+  for (int c = 0; c < FR_COLS; ++c) red[tid][c] = p[c];
+  __syncthreads();
+  if (tid < FR_COLS) {
+    double sum = 0.0;
+    for (int k = 0; k < 256; ++k) sum += red[k][tid];
+    tc[tid] = sum;
+  }
+  __syncthreads();
+  for (int64_t i = tid; i < n; i += 256) {
+    double u = 0.0;
+    for (int c = 0; c < nt; ++c) u = fma((double)S[i * lds + c0 + c], tc[c], u);
+    part[i] = u;
+  }
+}
+
 bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
 
 }  // namespace
@@ -529,6 +707,45 @@ hipError_t colpass_launch(const ColPassPlan& p, const float* S, int64_t n, int64
     case 1: hipLaunchKernelGGL(colpass_finalize_kernel<1>, g2, dim3(256), 0, st, part, p.nsplit, m, v, lambda, out); break;
     default: hipLaunchKernelGGL(colpass_finalize_kernel<2>, g2, dim3(256), 0, st, part, p.nsplit, m, v, lambda, out); break;
   }
+  return hipGetLastError();
+}
+
+RefinePassPlan refine_pass_plan(int64_t n, int64_t m, int64_t lds, const float* S) {
+  RefinePassPlan p{};
+  p.n = n;
+  const int64_t rows = 16 * FR_WAVES;
+  p.nch = n <= 8 * rows ? 8 : (n <= 16 * rows ? 16 : (n <= 32 * rows ? 32 : 0));
+  const int64_t nfull = m / FR_COLS;
+  p.usable = p.nch > 0 && n % 16 == 0 && nfull > 0 && ((lds & 3) == 0) && aligned16(S) &&
+             16 * lds * 4 < ((int64_t)1 << 31);
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+    cus = 256;
+  p.ngroups = std::max<int64_t>(1, std::min<int64_t>(cus, nfull));
+  p.tail = (m % FR_COLS) != 0;
+  p.part_bytes = p.usable ? (size_t)(p.ngroups + (p.tail ? 1 : 0)) * (size_t)n * sizeof(double) : 0;
+  return p;
+}
+
+hipError_t refine_pass_launch(const RefinePassPlan& p, const float* S, int64_t n, int64_t m, int64_t lds,
+                              const double* y, double* part, hipStream_t st) {
+  if (!p.usable || p.n != n) return hipErrorInvalidValue;
+  const dim3 grid((unsigned)p.ngroups), block(64 * FR_WAVES);
+  switch (p.nch) {
+    case 8: hipLaunchKernelGGL(refine_pass_kernel<8>, grid, block, 0, st, S, n, m, lds, y, part); break;
+    case 16: hipLaunchKernelGGL(refine_pass_kernel<16>, grid, block, 0, st, S, n, m, lds, y, part); break;
+    default: hipLaunchKernelGGL(refine_pass_kernel<32>, grid, block, 0, st, S, n, m, lds, y, part); break;
+  }
+  if (p.tail)
+    hipLaunchKernelGGL(refine_tail_kernel, dim3(1), dim3(256), 0, st, S, n, m, lds, y, m / FR_COLS * FR_COLS,
+                       part + p.ngroups * n);
+  return hipGetLastError();
+}
+
+hipError_t refine_pass_reduce(const RefinePassPlan& p, const double* part, double* r, const double* b,
+                              const double* y, double lam, hipStream_t st) {
+  hipLaunchKernelGGL(refine_reduce_kernel, dim3((unsigned)((p.n + 15) / 16)), dim3(256), 0, st, part, p.n,
+                     p.ngroups + (p.tail ? 1 : 0), r, b, y, lam);
   return hipGetLastError();
 }
 

@@ -244,6 +244,13 @@ SOLVE_CASES = [
     (300, 20000, 1e-2, 2, 4, "iid", 1e-6),      # scaled-FP8 Gram + refinement (m/n = 67: slow contraction)
     (300, 20000, 1e-6, 2, 3, "iid", 1e-6),
     (257, 30000, 1e-3, 2, 3, "iid", 1e-6),
+    # n a multiple of 16 and 16-byte aligned rows: the refinement product S S^T y takes the fused
+    # one-read pass
+    (320, 20004, 1e-2, 2, 4, "iid", 1e-6),      # m % 16 = 4: the last columns in the tail group
+    (320, 20016, 1e-6, 2, 3, "iid", 1e-6),      # whole 16-column blocks only
+    (320, 20008, 1e-3, 0, 1, "scaled", 1e-6),
+    (1040, 9000, 1e-3, 1, 2, "iid", 1e-6),      # 8 loads per lane and block
+    (2064, 5004, 1e-3, 1, 2, "iid", 1e-6),      # 16 loads per lane, rows past n in the last load
 ]
 
 
@@ -280,8 +287,9 @@ def test_solve_fp8_unshifted(dfl, ctx, oracle_mod, lam):
     assert err <= 1e-6
 
 
-def test_solve_deterministic(dfl, ctx):
-    S = synth.make_S(300, 20001, 27)
+@pytest.mark.parametrize("n", [300, 320])   # two-pass and fused refinement products
+def test_solve_deterministic(dfl, ctx, n):
+    S = synth.make_S(n, 20004, 27)
     v = synth.make_v(S, 27)
     Sd, vd = dev(S), dev(v)
     x1, _ = dfl.dfisher_solve(ctx, Sd, vd, 1e-3, gram_prec=1, sweeps=1)
@@ -298,11 +306,12 @@ def test_solve_x_aliases_v(dfl, ctx, oracle_mod):
     assert rel(vd.cpu().numpy(), xref) <= 1e-6
 
 
-def test_solve_strided_S(dfl, ctx, oracle_mod):
-    S = synth.make_S(200, 9999, 29)
+@pytest.mark.parametrize("n,ld", [(200, 10001), (208, 10004)])   # two-pass / fused refinement product
+def test_solve_strided_S(dfl, ctx, oracle_mod, n, ld):
+    S = synth.make_S(n, 9999, 29)
     v = synth.make_v(S, 29)
     xref = oracle_mod.solve(S, v, 1e-3)
-    x, _ = dfl.dfisher_solve(ctx, dev_strided(S, 10001), dev(v), 1e-3, sweeps=1, x_fp64=True)
+    x, _ = dfl.dfisher_solve(ctx, dev_strided(S, ld), dev(v), 1e-3, sweeps=1, x_fp64=True)
     assert rel(x.cpu().numpy(), xref) <= 1e-6
 
 
@@ -393,7 +402,7 @@ def test_uneven(dfl, ctx, oracle_mod):
 
 
 UNEVEN_SHAPES = [(256, 20000, 1e-3), (40, 3000, 1e-2), (700, 30001, 1e-5), (1, 512, 1e-2), (129, 7777, 3e-4),
-                 (512, 16384, 1e-4)]
+                 (512, 16384, 1e-4), (48, 1000, 1e-2)]
 
 
 def _uneven_inputs(shapes, seed_base, aligned):
