@@ -2,8 +2,8 @@
 // n x n matrix, lower triangle. Block size 64; per block column k:
 //   1. potf2   four waves factor the 64 x 64 diagonal block (right-looking: lane i keeps row i
 //              in registers, each wave a quarter of its columns; each column is scaled, broadcast
-//              through LDS and subtracted from the trailing columns), then form the block's
-//              inverse L_kk^-1 the same way (lane c owns column c).
+//              through LDS and subtracted from the trailing columns) and form the block's inverse
+//              L_kk^-1 the same way one step behind (lane c owns column c).
 //   2. trsm    rows below the block: A_ik <- A_ik L_kk^-T as a product with the stored inverse,
 //              64 rows per workgroup, every output independent.
 //   3. update  trailing lower triangle A_IJ -= A_Ik A_Jk^T in 64 x 64 tiles on the FP64 matrix
@@ -28,22 +28,46 @@ constexpr int PC = NB / PW;    // 16 columns (factor) or rows of the inverse per
 
 // Diagonal block: L_kk = chol(A_kk) and Dkk = L_kk^-1, with 4 waves. Lane i holds row i of the
 // block, wave w its columns 16 w .. 16 w + 15, in registers. Right-looking: at step j the wave
-// owning column j scales it by the pivot's square root and publishes it in LDS (column-major, so
-// a wave reads the 16 entries l_cj it needs as 8 two-double broadcasts); after a barrier every
-// wave subtracts l_ij l_cj from its columns c > j (independent FMAs, no dependence chain). The
-// subtractions from a_ic come in the order l = 0, 1, ..., c - 1. A pivot that is not > 0 stops
-// all four waves together (LDS flag) and is reported as its 1-based global index.
-// Inverse, also right-looking: lane c holds column c of L_kk^-1, wave w its rows 16 w .. + 15;
-// x = e_c; for each q: x_q /= l_qq (owning wave, published in LDS), then x_t -= l_tq x_q, t > q.
-// The step loops run over the four column (row) groups without unrolling and unroll the 16 steps
-// inside a group, so the owner's register index is a constant and the code stays a few thousand
-// instructions (a fully unrolled 64-step body overflows the instruction cache).
+// owning column j scales it by the reciprocal square root of the pivot and publishes it in LDS
+// (column-major, so a wave reads the 16 entries l_cj it needs as 8 two-double broadcasts); after a
+// barrier every wave subtracts l_ij l_cj from its columns c > j (independent FMAs, no dependence
+// chain). The subtractions from a_ic come in the order l = 0, 1, ..., c - 1. The first pivot that
+// is not > 0 is reported as its 1-based global index (LDS flag); the block is then not stored.
+// The inverse runs one step behind in the same loop, sharing its barriers: lane c holds column c
+// of L_kk^-1, wave w its rows 16 w .. + 15; x = e_c; at step j, row q = j - 1 (whose column of L
+// and reciprocal pivot are now published) is scaled, x_q *= 1 / l_qq (owning wave, published in
+// LDS), and x_t -= l_tq x_q for t > q.
+// The step loops run over the four column groups without unrolling and unroll the 16 steps
+// inside a group, so the owners' register indices are constants and the code stays a few
+// thousand instructions (a fully unrolled 64-step body overflows the instruction cache).
 constexpr int LDT = NB + 1;   // padded column stride of the LDS copy of L_kk (doubles)
+
+// Lane j's value of a double (j wave-uniform): two v_readlane, no LDS round trip.
+__device__ __forceinline__ double lane_read(double v, int j) {
+  const uint64_t b = __double_as_longlong(v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, j);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), j);
+  return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
+// 1 / sqrt(d) for a normal d > 0: the hardware estimate refined by two Newton steps
+// y <- y + y (1 - d y^2) / 2 (each roughly doubles the correct bits; the result is within a few
+// units in the last place, the pivot then being l_jj = d y).
+__device__ __forceinline__ double rsqrt_f64(double d) {
+  double y = __builtin_amdgcn_rsq(d);
+#pragma unroll
+  for (int it = 0; it < 2; ++it) {
+    const double e = fma(-d * y, y, 1.0);
+    y = fma(0.5 * y, e, y);
+  }
+  return y;
+}
 
 __global__ void __launch_bounds__(64 * PW)
 potf2_kernel(double* __restrict__ A, int64_t n, int64_t k, int64_t* __restrict__ info, int32_t* __restrict__ flag,
              double* __restrict__ Dkk, int64_t sA, const FactorJob* __restrict__ jobs) {
   __shared__ double lt[NB * LDT];   // l_ij at lt[j * LDT + i], filled column by column
+  __shared__ double rp[NB];         // 1 / l_jj
   __shared__ double xs[2][NB];      // the inverse's pivot row, double-buffered
   __shared__ int failed;
   const int64_t bb = blockIdx.y;
@@ -62,18 +86,19 @@ potf2_kernel(double* __restrict__ A, int64_t n, int64_t k, int64_t* __restrict__
     Dkk += bb * NB * NB;
   }
   if (*(volatile int32_t*)flag) return;
-  const int i = threadIdx.x & 63;      // row of the block
-  const int w = threadIdx.x >> 6;
-  const int c0 = w * PC;               // this wave's first column
+  const int i = threadIdx.x & 63;      // row of the block (factor), column of the inverse
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform: scalar branches
+  const int c0 = w * PC;               // this wave's first column (factor) / row (inverse)
   const int64_t nb = min<int64_t>(NB, n - k);
   if (threadIdx.x == 0) failed = 0;
-  double r[PC];
+  double r[PC], x[PC];
 #pragma unroll
   for (int u = 0; u < PC; ++u) {
     const int c = c0 + u;
     double val = (c == i) ? 1.0 : 0.0;   // identity padding past nb
     if (i < nb && c < nb && c <= i) val = A[(k + i) * n + k + c];
     r[u] = val;
+    x[u] = (c == i) ? 1.0 : 0.0;
   }
   __syncthreads();
 #pragma unroll 1
@@ -81,23 +106,34 @@ potf2_kernel(double* __restrict__ A, int64_t n, int64_t k, int64_t* __restrict__
 #pragma unroll
     for (int jj = 0; jj < PC; ++jj) {
       const int j = jb * PC + jj;
+      // inverse row q = j - 1: owner wave qb, register qq (uniform)
+      const int qb = (jj > 0) ? jb : jb - 1;
+      constexpr int QQ_WRAP = PC - 1;
+      const int qq = (jj > 0) ? jj - 1 : QQ_WRAP;
       if (w == jb) {   // wave-uniform: the owner of column j
-        const double d = __shfl(r[jj], j, 64);
+        const double d = lane_read(r[jj], j);
         if (!(d > 0.0)) {
-          if (i == 0) {
+          // the first breakdown is reported; later pivots are then garbage and are ignored
+          if (i == 0 && failed == 0) {
             *info = k + j + 1;
             *flag = 1;
             failed = 1;
           }
         } else {
-          const double ljj = sqrt(d);
-          const double lij = (i > j) ? r[jj] / ljj : ((i == j) ? ljj : 0.0);
+          const double rinv = rsqrt_f64(d);
+          const double ljj = d * rinv;
+          const double lij = (i > j) ? r[jj] * rinv : ((i == j) ? ljj : 0.0);
           r[jj] = lij;
           lt[j * LDT + i] = lij;
+          if (i == j) rp[j] = rinv;
         }
       }
+      if (j > 0 && w == qb) {
+        const double xq = x[(jj > 0) ? jj - 1 : QQ_WRAP] * rp[j - 1];
+        x[(jj > 0) ? jj - 1 : QQ_WRAP] = xq;
+        xs[(j - 1) & 1][i] = xq;
+      }
       __syncthreads();
-      if (failed) return;   // uniform: every thread sees the flag after the barrier
       const double* col = lt + j * LDT + c0;   // l_cj for this wave's columns c = c0 + u
       if (w > jb) {
         const double lij = lt[j * LDT + i];
@@ -108,40 +144,32 @@ potf2_kernel(double* __restrict__ A, int64_t n, int64_t k, int64_t* __restrict__
 #pragma unroll
         for (int u = jj + 1; u < PC; ++u) r[u] -= lij * col[u];
       }
+      if (j > 0) {
+        const double* colq = lt + (j - 1) * LDT + c0;   // l_tq for this wave's rows t = c0 + u
+        if (w > qb) {
+          const double xq = xs[(j - 1) & 1][i];
+#pragma unroll
+          for (int u = 0; u < PC; ++u) x[u] -= colq[u] * xq;
+        } else if (w == qb) {
+          const double xq = x[qq];
+#pragma unroll
+          for (int u = 0; u < PC; ++u)
+            if (u > qq) x[u] -= colq[u] * xq;
+        }
+      }
     }
   }
+  // After a breakdown the remaining steps ran on garbage (finite or not, all indices in range);
+  // nothing of this block is stored. Every thread sees the flag (set before a barrier).
+  if (failed) return;
+  // the last row of the inverse has no later rows to update
+  if (w == PW - 1) x[PC - 1] *= rp[NB - 1];
   // the factor's lower triangle: wave w stores rows w, w + 4, ..., lane c column c
   for (int rr = w; rr < nb; rr += PW)
     if (i <= rr) A[(k + rr) * n + k + i] = lt[i * LDT + rr];
   if (k + NB >= n) return;  // no rows below: the inverse is not needed
-  const int cc = i;   // column of the inverse
-  double x[PC];
 #pragma unroll
-  for (int u = 0; u < PC; ++u) x[u] = (c0 + u == cc) ? 1.0 : 0.0;
-#pragma unroll 1
-  for (int qb = 0; qb < PW; ++qb) {
-#pragma unroll
-    for (int qq = 0; qq < PC; ++qq) {
-      const int q = qb * PC + qq;
-      if (w == qb) {
-        x[qq] = x[qq] / lt[q * LDT + q];
-        xs[q & 1][cc] = x[qq];
-      }
-      __syncthreads();
-      const double* col = lt + q * LDT + c0;   // l_tq for this wave's rows t = c0 + u
-      if (w > qb) {
-        const double xq = xs[q & 1][cc];
-#pragma unroll
-        for (int u = 0; u < PC; ++u) x[u] -= col[u] * xq;
-      } else if (w == qb) {
-        const double xq = x[qq];
-#pragma unroll
-        for (int u = qq + 1; u < PC; ++u) x[u] -= col[u] * xq;
-      }
-    }
-  }
-#pragma unroll
-  for (int u = 0; u < PC; ++u) Dkk[(c0 + u) * NB + cc] = x[u];   // D[t][c] = (L_kk^-1)_tc
+  for (int u = 0; u < PC; ++u) Dkk[(c0 + u) * NB + i] = x[u];   // D[t][c] = (L_kk^-1)_tc
 }
 
 // Rows i in [k + NB, n): A[i][k .. k+NB) <- A[i][k .. k+NB) L_kk^-T, i.e. out_rc = sum_l A_rl D_cl.

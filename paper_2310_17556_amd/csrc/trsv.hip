@@ -91,6 +91,14 @@ fwd_step_kernel(const double* __restrict__ L, int64_t n, const double* __restric
   const int tid = threadIdx.x;
   const int64_t r0 = k * NB;
   const int nb = (int)min<int64_t>(NB, n - r0);
+  // This workgroup's piece of the panel L_Jk (row block J = k + blockIdx.x; 4 threads per row,
+  // 16 columns each) is loaded first: it does not depend on z_k, so its latency overlaps z_k's.
+  const int64_t row = (k + blockIdx.x) * NB + (tid >> 2);
+  const int q = tid & 3;
+  const bool upd = blockIdx.x > 0 && row < n;
+  double lv[16];
+#pragma unroll
+  for (int u = 0; u < 16; ++u) lv[u] = (upd && q * 16 + u < nb) ? L[row * n + r0 + q * 16 + u] : 0.0;
   // z_k = D_k r_k: 4 groups of 64 threads each take 16 columns of D_k
   {
     const int i = tid & 63, g = tid >> 6;
@@ -107,15 +115,11 @@ fwd_step_kernel(const double* __restrict__ L, int64_t n, const double* __restric
     if (tid < nb) z[r0 + tid] = zk[tid];
     return;
   }
-  // r_J -= L_Jk z_k for row block J = k + blockIdx.x: 4 threads per row, 16 columns each
-  const int64_t row = (k + blockIdx.x) * NB + (tid >> 2);
+  // r_J -= L_Jk z_k
   if (row >= n) return;
-  const int q = tid & 3;
-  const double* Lr = L + row * n + r0;
   double s = 0.0;
 #pragma unroll
-  for (int c = q * 16; c < q * 16 + 16; ++c)
-    if (c < nb) s = fma(Lr[c], zk[c], s);
+  for (int u = 0; u < 16; ++u) s = fma(lv[u], zk[q * 16 + u], s);
   s += __shfl_xor(s, 1, 64);
   s += __shfl_xor(s, 2, 64);
   if (q == 0) r[row] -= s;
@@ -146,6 +150,13 @@ bwd_step_kernel(const double* __restrict__ L, int64_t n, const double* __restric
   const int tid = threadIdx.x;
   const int64_t r0 = k * NB;
   const int nb = (int)min<int64_t>(NB, n - r0);
+  // This workgroup's piece of row block k of L (columns of block J = blockIdx.x - 1; thread (c, g)
+  // takes rows 16 g .. 16 g + 15 of column c), loaded before y_k so the two latencies overlap.
+  const int64_t J = (int64_t)blockIdx.x - 1;
+  const int cc = tid & 63, gg = tid >> 6;
+  double lv[16];
+#pragma unroll
+  for (int u = 0; u < 16; ++u) lv[u] = (J >= 0 && gg * 16 + u < nb) ? L[(r0 + gg * 16 + u) * n + J * NB + cc] : 0.0;
   // y_k = D_k^T r_k
   {
     const int i = tid & 63, g = tid >> 6;
@@ -163,13 +174,11 @@ bwd_step_kernel(const double* __restrict__ L, int64_t n, const double* __restric
     return;
   }
   // r_J -= L_kJ^T y_k for J = blockIdx.x - 1 < k: column c of block J gets sum_i L[r0+i][J*64+c] y_k[i]
-  const int64_t J = blockIdx.x - 1;
-  const int c = tid & 63, g = tid >> 6;
   double s = 0.0;
-  for (int i = g * 16; i < g * 16 + 16; ++i)
-    if (i < nb) s = fma(L[(r0 + i) * n + J * NB + c], yk[i], s);
+#pragma unroll
+  for (int u = 0; u < 16; ++u) s = fma(lv[u], yk[gg * 16 + u], s);
   __syncthreads();
-  part[g][c] = s;
+  part[gg][cc] = s;
   __syncthreads();
   if (tid < NB) r[J * NB + tid] -= part[0][tid] + part[1][tid] + part[2][tid] + part[3][tid];
 }
