@@ -51,7 +51,9 @@ typedef enum dfisher_status {
   DFISHER_E_NOT_SPD = 2,       /* Cholesky met a pivot that is not > 0 (info says where) */
   DFISHER_E_NO_MEMORY = 3,     /* workspace allocation failed                            */
   DFISHER_E_DEVICE = 4,        /* no usable device, or a HIP runtime error               */
-  DFISHER_E_UNSUPPORTED = 5    /* valid request this build does not implement            */
+  DFISHER_E_UNSUPPORTED = 5,   /* valid request this build does not implement            */
+  DFISHER_E_NOT_CONVERGED = 6  /* a tolerance was set and no measured refinement residual
+                                  met it within opt->sweeps sweeps; x is still written    */
 } dfisher_status;
 
 /* Arithmetic of the Gram S S^T (Algorithm 1 step 1, the O(n^2 m) term of Section 2).
@@ -87,10 +89,16 @@ typedef struct dfisher_options {
                             adds L^-T L^-1 r to y                                            */
   int32_t shift_policy;  /* dfisher_shift_policy                                            */
   int32_t x_fp64;        /* 0: x (and X) are float*, 1: double*                             */
+  double tol;            /* 0: run exactly `sweeps` sweeps. > 0 (dfisher_solve only; other
+                            entry points return DFISHER_E_UNSUPPORTED): after forming sweep k's
+                            residual r_k = S v - lambda y_k - S (S^T y_k), read
+                            rho_k = |r_k|_2 / |S v|_2 (one stream synchronisation per sweep),
+                            apply that sweep's correction, and stop once rho_k <= tol; with
+                            `sweeps` as the cap. Finite and >= 0.                             */
 } dfisher_options;
 
-/* Defaults: FP32 Gram, 0 sweeps, shift on failure, FP32 output. */
-#define DFISHER_OPTIONS_DEFAULT {DFISHER_GRAM_FP32, 0, DFISHER_SHIFT_ON_FAILURE, 0}
+/* Defaults: FP32 Gram, 0 sweeps, shift on failure, FP32 output, no tolerance. */
+#define DFISHER_OPTIONS_DEFAULT {DFISHER_GRAM_FP32, 0, DFISHER_SHIFT_ON_FAILURE, 0, 0.0}
 
 typedef struct dfisher_info {
   int64_t potrf_info;    /* 0, or the 1-based index of the first pivot that is not > 0 in the
@@ -98,6 +106,10 @@ typedef struct dfisher_info {
   double shift;          /* tau added to W's diagonal by the successful factorisation (0: none) */
   int32_t attempts;      /* number of factorisations run                                      */
   int32_t sweeps_done;   /* refinement sweeps applied                                         */
+  double resid;          /* with opt->tol > 0: rho of the last sweep (the relative residual of
+                            the iterate that sweep corrected, measured before the correction;
+                            the returned iterate's is smaller by about the contraction factor);
+                            -1 when not measured (tol == 0 or no sweep)                         */
 } dfisher_info;
 
 typedef struct dfisher_ctx dfisher_ctx;        /* device id, workspace, pinned status buffer  */
@@ -172,7 +184,9 @@ DFISHER_API dfisher_status dfisher_apply(dfisher_ctx* ctx, const float* S, int64
                              void* stream);
 
 /* Algorithm 1 end to end: x solving (S^T S + lambda I) x = v. v is FP32 (length m); x is FP32
- * or FP64 per opt->x_fp64 and may alias v when FP32. opt NULL = defaults; info may be NULL. */
+ * or FP64 per opt->x_fp64 and may alias v when FP32. opt NULL = defaults; info may be NULL.
+ * With opt->tol > 0 the sweeps stop at the tolerance (see dfisher_options) and the call returns
+ * DFISHER_E_NOT_CONVERGED, with x and info written, if no measured residual met it. */
 DFISHER_API dfisher_status dfisher_solve(dfisher_ctx* ctx, const float* S, int64_t n, int64_t m, int64_t lds,
                              const float* v, double lambda, void* x, const dfisher_options* opt,
                              void* stream, dfisher_info* info);

@@ -15,7 +15,7 @@ import os
 __all__ = [
     "DfisherError", "Info", "Timing", "lib",
     "DFISHER_OK", "DFISHER_E_INVALID_ARG", "DFISHER_E_NOT_SPD", "DFISHER_E_NO_MEMORY", "DFISHER_E_DEVICE",
-    "DFISHER_E_UNSUPPORTED", "DFISHER_GRAM_FP32", "DFISHER_GRAM_BF16X3", "DFISHER_GRAM_MXFP8", "DFISHER_SHIFT_NONE",
+    "DFISHER_E_UNSUPPORTED", "DFISHER_E_NOT_CONVERGED", "DFISHER_GRAM_FP32", "DFISHER_GRAM_BF16X3", "DFISHER_GRAM_MXFP8", "DFISHER_SHIFT_NONE",
     "DFISHER_SHIFT_ON_FAILURE", "DFISHER_SHIFT_ALWAYS",
     "dfisher_ctx_create", "dfisher_ctx_destroy", "dfisher_ctx_enable_timing", "dfisher_ctx_last_timing",
     "dfisher_ctx_enable_graphs", "dfisher_ctx_enable_autotune", "dfisher_autotune_gram", "dfisher_ctx_save_tuning",
@@ -32,6 +32,7 @@ DFISHER_E_NOT_SPD = 2
 DFISHER_E_NO_MEMORY = 3
 DFISHER_E_DEVICE = 4
 DFISHER_E_UNSUPPORTED = 5
+DFISHER_E_NOT_CONVERGED = 6
 DFISHER_GRAM_FP32 = 0
 DFISHER_GRAM_BF16X3 = 1
 DFISHER_GRAM_MXFP8 = 2
@@ -45,16 +46,16 @@ LIB_PATH = os.path.join(_HERE, "libdfisher.so")
 
 class _Options(ctypes.Structure):
     _fields_ = [("gram_prec", ctypes.c_int32), ("sweeps", ctypes.c_int32),
-                ("shift_policy", ctypes.c_int32), ("x_fp64", ctypes.c_int32)]
+                ("shift_policy", ctypes.c_int32), ("x_fp64", ctypes.c_int32), ("tol", ctypes.c_double)]
 
 
 class Info(ctypes.Structure):
     _fields_ = [("potrf_info", ctypes.c_int64), ("shift", ctypes.c_double),
-                ("attempts", ctypes.c_int32), ("sweeps_done", ctypes.c_int32)]
+                ("attempts", ctypes.c_int32), ("sweeps_done", ctypes.c_int32), ("resid", ctypes.c_double)]
 
     def as_dict(self):
         return {"potrf_info": self.potrf_info, "shift": self.shift, "attempts": self.attempts,
-                "sweeps_done": self.sweeps_done}
+                "sweeps_done": self.sweeps_done, "resid": self.resid}
 
 
 class Timing(ctypes.Structure):
@@ -331,8 +332,11 @@ def dfisher_apply(ctx, S, v, y, lam: float, x=None, x_fp64: bool = False, stream
 
 
 def dfisher_solve(ctx, S, v, lam: float, gram_prec: int = DFISHER_GRAM_FP32, sweeps: int = 0,
-                  shift_policy: int = DFISHER_SHIFT_ON_FAILURE, x_fp64: bool = False, x=None, stream=None):
-    """x solving (S^T S + lam I) x = v. Returns (x, info_dict)."""
+                  shift_policy: int = DFISHER_SHIFT_ON_FAILURE, x_fp64: bool = False, x=None, stream=None,
+                  tol: float = 0.0):
+    """x solving (S^T S + lam I) x = v. Returns (x, info_dict). With tol > 0 the refinement stops at
+    the tolerance (sweeps is the cap); info_dict["converged"] is False (and x is still the result)
+    when the library returns DFISHER_E_NOT_CONVERGED."""
     torch = _torch()
     n, m, lds = _S_args(S)
     _vec(v, m, torch.float32, "v")
@@ -341,10 +345,15 @@ def dfisher_solve(ctx, S, v, lam: float, gram_prec: int = DFISHER_GRAM_FP32, swe
         x = torch.empty(m, dtype=dt, device=S.device)
     _vec(x, m, dt, "x")
     opt = _options(gram_prec, sweeps, shift_policy, x_fp64)
+    opt.tol = float(tol)
     info = Info()
-    _check(_lib().dfisher_solve(ctx.ptr, _ptr(S), n, m, lds, _ptr(v), float(lam), _ptr(x), ctypes.byref(opt),
-                             _stream(stream), ctypes.byref(info)), "dfisher_solve")
-    return x, info.as_dict()
+    st = _lib().dfisher_solve(ctx.ptr, _ptr(S), n, m, lds, _ptr(v), float(lam), _ptr(x), ctypes.byref(opt),
+                              _stream(stream), ctypes.byref(info))
+    if st != DFISHER_E_NOT_CONVERGED:
+        _check(st, "dfisher_solve")
+    d = info.as_dict()
+    d["converged"] = st == DFISHER_OK
+    return x, d
 
 
 def dfisher_factor_create(ctx, S, lam: float, gram_prec: int = DFISHER_GRAM_FP32, sweeps: int = 0,

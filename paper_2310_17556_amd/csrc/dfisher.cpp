@@ -175,7 +175,14 @@ dfisher_status check_opt(const dfisher_options* opt, dfisher_options* out) {
       d.shift_policy != DFISHER_SHIFT_ALWAYS)
     return fail(DFISHER_E_INVALID_ARG, "unknown shift_policy %d", d.shift_policy);
   if (d.x_fp64 != 0 && d.x_fp64 != 1) return fail(DFISHER_E_INVALID_ARG, "x_fp64 must be 0 or 1");
+  if (!std::isfinite(d.tol) || d.tol < 0.0) return fail(DFISHER_E_INVALID_ARG, "tol must be finite and >= 0");
   *out = d;
+  return DFISHER_OK;
+}
+
+// Entry points that run a fixed number of sweeps reject a tolerance.
+dfisher_status check_no_tol(const dfisher_options& o) {
+  if (o.tol != 0.0) return fail(DFISHER_E_UNSUPPORTED, "tol is honoured by dfisher_solve only");
   return DFISHER_OK;
 }
 
@@ -330,14 +337,21 @@ dfisher_status gram_stage(const float* S, const float* v, const dfi::GramPlan& g
 // y = W^-1 b through the factor, then `sweeps` refinement sweeps against the exact operator
 // W = S S^T + lambda I: r = b - lambda y - S (S^T y) (FP64 accumulation), y += L^-T L^-1 r. The
 // product S (S^T y) takes one read of S through the fused pass when `fp` allows it, else a column
-// pass (t = S^T y into B.t) and a row pass.
+// pass (t = S^T y into B.t) and a row pass. With tol > 0 (ctx given): after each residual, read
+// rho = |r| / |b| (one synchronisation), apply the correction, stop once rho <= tol. *done and
+// *resid report the sweeps applied and the last rho (-1 if none was measured).
 dfisher_status solve_y(const float* S, int64_t n, int64_t m, int64_t lds, double lambda, const double* L,
                        const double* Dinv, const SolveBufs& B, const dfi::RowPassPlan& rp, const dfi::ColPassPlan& cp,
-                       int sweeps, hipStream_t st, StageClock* clk = nullptr, const dfi::RefinePassPlan* fp = nullptr) {
+                       int sweeps, hipStream_t st, StageClock* clk = nullptr, const dfi::RefinePassPlan* fp = nullptr,
+                       dfisher_ctx* ctx = nullptr, double tol = 0.0, int* done = nullptr, double* resid = nullptr) {
   HIP_TRY(dfi::trsv_launch(L, Dinv, n, 0, B.b, B.z, B.tw, st));
   HIP_TRY(dfi::trsv_launch(L, Dinv, n, 1, B.z, B.y, B.tw, st));
   if (clk) clk->mark(5);
   const bool fused = fp && fp->usable;
+  const bool measure = ctx && tol > 0.0;
+  if (done) *done = 0;
+  if (resid) *resid = -1.0;
+  if (measure) HIP_TRY(dfi::sumsq(B.b, n, ctx->d_scalar + 2, st));
   for (int s = 0; s < sweeps; ++s) {
     if (fused) {
       HIP_TRY(dfi::refine_pass_launch(*fp, S, n, m, lds, B.y, B.rpart, st));
@@ -347,9 +361,20 @@ dfisher_status solve_y(const float* S, int64_t n, int64_t m, int64_t lds, double
       HIP_TRY(dfi::rowpass_launch(rp, S, nullptr, B.t, true, false, B.rpart, st));
       HIP_TRY(dfi::rowpass_reduce(rp, B.rpart, true, false, B.r, nullptr, B.b, B.y, lambda, st));
     }
+    double rho = -1.0;
+    if (measure) {
+      HIP_TRY(dfi::sumsq(B.r, n, ctx->d_scalar + 3, st));
+      HIP_TRY(hipMemcpyAsync(ctx->h_scalar + 2, ctx->d_scalar + 2, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+      HIP_TRY(hipStreamSynchronize(st));
+      const double bb = ctx->h_scalar[2], rr = ctx->h_scalar[3];
+      rho = bb > 0.0 ? std::sqrt(rr / bb) : (rr > 0.0 ? INFINITY : 0.0);
+      if (resid) *resid = rho;
+    }
     HIP_TRY(dfi::trsv_launch(L, Dinv, n, 0, B.r, B.z, B.tw, st));
     HIP_TRY(dfi::trsv_launch(L, Dinv, n, 1, B.z, B.r, B.tw, st));
     HIP_TRY(dfi::axpy_inplace(B.y, B.r, n, st));
+    if (done) *done = s + 1;
+    if (measure && rho <= tol) break;
   }
   if (clk) clk->mark(6);
   return DFISHER_OK;
@@ -786,6 +811,7 @@ dfisher_status uneven_solve(dfisher_ctx* ctx, int32_t np, const float* const* S,
   dfisher_status worst = DFISHER_OK;
   for (int32_t p = 0; p < np; ++p) {
     dfisher_info inf{};
+    inf.resid = -1.0;
     inf.potrf_info = hinfo[(size_t)p];
     inf.attempts = 1;
     inf.sweeps_done = o.sweeps;
@@ -821,6 +847,7 @@ const char* dfisher_status_string(dfisher_status s) {
     case DFISHER_E_NO_MEMORY: return "out of device memory";
     case DFISHER_E_DEVICE: return "device or HIP runtime error";
     case DFISHER_E_UNSUPPORTED: return "unsupported request";
+    case DFISHER_E_NOT_CONVERGED: return "refinement tolerance not met";
   }
   return "unknown status";
 }
@@ -1054,6 +1081,7 @@ dfisher_status dfisher_factor_create(dfisher_ctx* ctx, const float* S, int64_t n
   if (!finite_pos(lambda)) return fail(DFISHER_E_INVALID_ARG, "lambda must be finite and > 0");
   dfisher_options o;
   DF_TRY(check_opt(opt, &o));
+  DF_TRY(check_no_tol(o));
   DF_TRY(check_prec_layout(o.gram_prec, S, lds));
   DeviceGuard g(ctx->device);
   hipStream_t st = as_stream(stream);
@@ -1090,6 +1118,7 @@ dfisher_status dfisher_factor_create(dfisher_ctx* ctx, const float* S, int64_t n
     if (sg != DFISHER_OK) return cleanup(sg);
   }
   dfisher_info inf{};
+  inf.resid = -1.0;
   dfisher_status s = factor_with_policy(ctx, B.W, f->L, B.dkk, n, o.shift_policy, gram_unit(o.gram_prec, m), st, &inf.shift, &inf.potrf_info,
                                        &inf.attempts);
   if (info) *info = inf;
@@ -1127,6 +1156,7 @@ dfisher_status dfisher_factor_solve(dfisher_factor* f, const float* V, int64_t n
     info->shift = f->shift;
     info->attempts = 0;
     info->sweeps_done = f->opt.sweeps;
+    info->resid = -1.0;
   }
   return DFISHER_OK;
 }
@@ -1175,16 +1205,22 @@ dfisher_status dfisher_solve(dfisher_ctx* ctx, const float* S, int64_t n, int64_
   // step 2 (with the shift policy)
   clk.mark(3);
   dfisher_info inf{};
+  inf.resid = -1.0;
   DF_TRY(factor_with_policy(ctx, B.W, B.L, B.dkk, n, o.shift_policy, gram_unit(o.gram_prec, m), st, &inf.shift, &inf.potrf_info,
                             &inf.attempts));
   HIP_TRY(dfi::trsv_diag_inv(B.L, n, B.Dinv, st));
   // steps 3-4 inlined: y = W^-1 S v (+ refinement), x = (v - S^T y) / lambda
   clk.mark(4);
-  DF_TRY(solve_y(S, n, m, lds, lambda, B.L, B.Dinv, B, rp, cp, o.sweeps, st, &clk, &fp));
+  int done = 0;
+  double resid = -1.0;
+  DF_TRY(solve_y(S, n, m, lds, lambda, B.L, B.Dinv, B, rp, cp, o.sweeps, st, &clk, &fp, ctx, o.tol, &done, &resid));
   HIP_TRY(dfi::colpass_launch(cp, S, n, m, lds, B.y, v, lambda, x, o.x_fp64, B.cpart, st));
   clk.mark(7);
-  inf.sweeps_done = o.sweeps;
+  inf.sweeps_done = done;
+  inf.resid = resid;
   if (info) *info = inf;
+  if (o.tol > 0.0 && !(resid >= 0.0 && resid <= o.tol))
+    return fail(DFISHER_E_NOT_CONVERGED, "relative residual %.3g above tol %.3g after %d sweep(s)", resid, o.tol, done);
   return DFISHER_OK;
 }
 
@@ -1202,6 +1238,7 @@ dfisher_status dfisher_solve_batched(dfisher_ctx* ctx, const float* S, int64_t n
   if ((int64_t)nlam * nrhs > 65535) return fail(DFISHER_E_UNSUPPORTED, "nlam * nrhs > 65535");
   dfisher_options o;
   DF_TRY(check_opt(opt, &o));
+  DF_TRY(check_no_tol(o));
   DF_TRY(check_prec_layout(o.gram_prec, S, lds));
   DeviceGuard g(ctx->device);
   hipStream_t st = as_stream(stream);
@@ -1253,6 +1290,7 @@ dfisher_status dfisher_solve_batched(dfisher_ctx* ctx, const float* S, int64_t n
   dfisher_status worst = DFISHER_OK;
   for (int32_t l = 0; l < nlam; ++l) {
     dfisher_info inf{};
+    inf.resid = -1.0;
     inf.attempts = 1;
     inf.potrf_info = hinfo[(size_t)l];
     inf.shift = scale0 * dmax;
@@ -1284,6 +1322,7 @@ dfisher_status dfisher_solve_uneven(dfisher_ctx* ctx, int32_t nprob, const float
   if (!S || !n || !m || !lds || !v || !lambda || !x) return fail(DFISHER_E_INVALID_ARG, "NULL array argument");
   dfisher_options o;
   DF_TRY(check_opt(opt, &o));
+  DF_TRY(check_no_tol(o));
   for (int32_t p = 0; p < nprob; ++p) {
     dfisher_status s = check_S(S[p], n[p], m[p], lds[p]);
     if (s != DFISHER_OK) return fail(s, "problem %d: %s", p, g_last_error.c_str());

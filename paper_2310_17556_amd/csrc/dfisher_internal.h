@@ -218,6 +218,8 @@ hipError_t shift_add_copy(const double* src, double* dst, int64_t n, double scal
 hipError_t axpy_inplace(double* y, const double* d, int64_t n, hipStream_t st);
 // max_i W_ii
 hipError_t diag_max(const double* W, int64_t n, double* out_dev, hipStream_t st);
+// *out_dev = sum_i x_i^2 (FP64, deterministic)
+hipError_t sumsq(const double* x, int64_t n, double* out_dev, hipStream_t st);
 // zero the strict upper triangle
 hipError_t zero_upper(double* A, int64_t n, hipStream_t st);
 

@@ -338,6 +338,20 @@ __global__ void diag_max_kernel(const double* __restrict__ W, int64_t n, double*
   if (threadIdx.x == 0) *out = red[0];
 }
 
+// *out = sum_i x_i^2 (FP64, one workgroup, fixed order: strided per-thread sums, then a tree).
+__global__ void sumsq_kernel(const double* __restrict__ x, int64_t n, double* __restrict__ out) {
+  __shared__ double red[256];
+  double acc = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += 256) acc = fma(x[i], x[i], acc);
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = red[0];
+}
+
 __global__ void clear_status_kernel(int64_t* info, int32_t* flag, int64_t nbatch) {
   const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (b < nbatch) {
@@ -435,6 +449,11 @@ hipError_t axpy_inplace(double* y, const double* d, int64_t n, hipStream_t st) {
 
 hipError_t diag_max(const double* W, int64_t n, double* out_dev, hipStream_t st) {
   hipLaunchKernelGGL(diag_max_kernel, dim3(1), dim3(256), 0, st, W, n, out_dev);
+  return hipGetLastError();
+}
+
+hipError_t sumsq(const double* x, int64_t n, double* out_dev, hipStream_t st) {
+  hipLaunchKernelGGL(sumsq_kernel, dim3(1), dim3(256), 0, st, x, n, out_dev);
   return hipGetLastError();
 }
 

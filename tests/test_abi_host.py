@@ -45,7 +45,7 @@ def test_binding_names_match_abi(dfl):
 
 
 def test_status_strings(dfl):
-    for code in range(6):
+    for code in range(7):
         assert dfl.dfisher_status_string(code) != "unknown status"
     assert dfl.dfisher_status_string(99) == "unknown status"
 
@@ -54,8 +54,8 @@ FAKE_CTX = ctypes.c_void_p(0x1000)   # never dereferenced: every call below fail
 FAKE_DEV = ctypes.c_void_p(0x2000)
 
 
-def _opts(dfl, prec=0, sweeps=0, shift=1, x64=0):
-    return dfl._Options(prec, sweeps, shift, x64)
+def _opts(dfl, prec=0, sweeps=0, shift=1, x64=0, tol=0.0):
+    return dfl._Options(prec, sweeps, shift, x64, tol)
 
 
 def test_invalid_arguments_rejected_on_host(dfl):
@@ -78,7 +78,7 @@ def test_invalid_arguments_rejected_on_host(dfl):
     for lam in [0.0, -1e-3, float("inf"), float("nan")]:
         assert lib.dfisher_solve(FAKE_CTX, P, 4, 8, 8, P, lam, P, None, st, ctypes.byref(info)) == E
     for o in [_opts(dfl, prec=5), _opts(dfl, sweeps=-1), _opts(dfl, sweeps=17), _opts(dfl, shift=3),
-              _opts(dfl, x64=2)]:
+              _opts(dfl, x64=2), _opts(dfl, tol=-1e-9), _opts(dfl, tol=float("nan")), _opts(dfl, tol=float("inf"))]:
         assert lib.dfisher_solve(FAKE_CTX, P, 4, 8, 8, P, 1.0, P, ctypes.byref(o), st, None) == E
     assert lib.dfisher_solve(FAKE_CTX, P, 4, 8, 8, None, 1.0, P, None, st, None) == E
     assert lib.dfisher_solve(FAKE_CTX, P, 4, 8, 8, P, 1.0, None, None, st, None) == E
@@ -100,6 +100,16 @@ def test_invalid_arguments_rejected_on_host(dfl):
     assert lib.dfisher_solve_batched(FAKE_CTX, P, 4, 8, 8, lams, 0, P, 1, 8, P, 8, None, st, None) == E
     assert lib.dfisher_solve_batched(FAKE_CTX, P, 4, 8, 8, lams, 1, P, 1, 7, P, 8, None, st, None) == E
     assert lib.dfisher_solve_uneven(FAKE_CTX, 0, None, None, None, None, None, None, None, None, st, None) == E
+    # a tolerance is honoured by dfisher_solve only; the fixed-sweep entry points refuse it
+    U = dfl.DFISHER_E_UNSUPPORTED
+    otol = _opts(dfl, sweeps=2, tol=1e-9)
+    assert lib.dfisher_solve_batched(FAKE_CTX, P, 4, 8, 8, lams, 1, P, 1, 8, P, 8, ctypes.byref(otol), st, None) == U
+    assert lib.dfisher_factor_create(FAKE_CTX, P, 4, 8, 8, 1.0, ctypes.byref(otol), st, ctypes.byref(out), None) == U
+    arrp = (ctypes.c_void_p * 1)(P.value)
+    arr64 = (ctypes.c_int64 * 1)(8)
+    arrn = (ctypes.c_int64 * 1)(4)
+    assert lib.dfisher_solve_uneven(FAKE_CTX, 1, arrp, arrn, arr64, arr64, arrp, lams, arrp, ctypes.byref(otol), st,
+                                    None) == U
     assert "NULL" in dfl.dfisher_last_error() or dfl.dfisher_last_error() != ""
     # context switches and the tuning table
     assert lib.dfisher_ctx_enable_graphs(None, 1) == E

@@ -287,6 +287,37 @@ def test_solve_fp8_unshifted(dfl, ctx, oracle_mod, lam):
     assert err <= 1e-6
 
 
+def test_solve_tolerance(dfl, ctx, oracle_mod):
+    """opt.tol: the sweeps stop once a measured relative residual |b - W y| / |b| meets tol (sweeps
+    is the cap); an unreachable tol returns DFISHER_E_NOT_CONVERGED with x still written. Split-BF16
+    Gram (each sweep contracts the residual by orders of magnitude, down to the FP64 floor)."""
+    n, m, lam = 320, 20016, 1e-2
+    print(f"[solve tol] n={n} m={m} lam={lam}", flush=True)
+    S = synth.make_S(n, m, synth.seed(34, n))
+    v = synth.make_v(S, synth.seed(34, n))
+    xref = oracle_mod.solve(S, v, lam)
+    Sd, vd = dev(S), dev(v)
+    x, info = dfl.dfisher_solve(ctx, Sd, vd, lam, gram_prec=1, sweeps=16, x_fp64=True, tol=1e-12)
+    print(f"    tol 1e-12: {info}", flush=True)
+    assert info["converged"] and 1 <= info["sweeps_done"] <= 16 and 0.0 <= info["resid"] <= 1e-12
+    assert rel(x.cpu().numpy(), xref) <= 1e-6
+    # a loose tolerance stops after the first measured residual
+    _, infl = dfl.dfisher_solve(ctx, Sd, vd, lam, gram_prec=1, sweeps=16, tol=1.0)
+    assert infl["converged"] and infl["sweeps_done"] == 1
+    # fixed sweeps measure nothing
+    _, info0 = dfl.dfisher_solve(ctx, Sd, vd, lam, gram_prec=1, sweeps=2)
+    assert info0["resid"] == -1.0 and info0["converged"] and info0["sweeps_done"] == 2
+    # unreachable tolerance: every allowed sweep runs, the result equals the fixed-sweep one
+    x1, info1 = dfl.dfisher_solve(ctx, Sd, vd, lam, gram_prec=1, sweeps=1, x_fp64=True, tol=1e-30)
+    assert not info1["converged"] and info1["sweeps_done"] == 1 and info1["resid"] > 1e-30
+    x1b, _ = dfl.dfisher_solve(ctx, Sd, vd, lam, gram_prec=1, sweeps=1, x_fp64=True)
+    assert torch.equal(x1, x1b)
+    # the residual contracts from sweep to sweep
+    _, info3 = dfl.dfisher_solve(ctx, Sd, vd, lam, gram_prec=1, sweeps=3, tol=1e-30)
+    print(f"    rho after 1 and 3 sweeps: {info1['resid']:.3e} {info3['resid']:.3e}", flush=True)
+    assert info3["sweeps_done"] == 3 and info3["resid"] < info1["resid"]
+
+
 @pytest.mark.parametrize("n", [300, 320])   # two-pass and fused refinement products
 def test_solve_deterministic(dfl, ctx, n):
     S = synth.make_S(n, 20004, 27)
