@@ -551,3 +551,54 @@ def test_stage_timing(dfl, ctx):
     t = dfl.dfisher_ctx_last_timing(ctx)
     dfl.dfisher_ctx_enable_timing(ctx, False)
     assert t["gram_ms"] > 0 and t["total_ms"] >= t["gram_ms"]
+
+
+def test_full_size_bench_workload(dfl, ctx, oracle_mod):
+    """The workload bench.py times, at full size and in its launch configuration (n = 4096,
+    m = 4M, scaled-FP8 Gram, one refinement sweep, shift on failure, lambda = 1e-6). The reference
+    x is formed from FP64 products on the device (torch, independent of the library); it is pinned
+    to the oracle on sampled Gram entries and sampled outputs, each of which the oracle computes
+    one dot product at a time, and its y is checked against the definition W y = S v."""
+    n, m, lam = 4096, 4_000_000, 1e-6
+    dv = torch.device("cuda:0")
+    print(f"[full size] n={n} m={m} lam={lam}: generating", flush=True)
+    S = synth.make_S_torch(n, m, synth.seed(3), dv, kind="iid")
+    v = synth.make_v_torch(S, synth.seed(3), kind="iid")
+    x, info = dfl.dfisher_solve(ctx, S, v, lam, gram_prec=dfl.DFISHER_GRAM_MXFP8, sweeps=1, x_fp64=True)
+    torch.cuda.synchronize()
+    print(f"    solved: {info}; FP64 reference", flush=True)
+    chunk = 131072
+    G = torch.zeros((n, n), dtype=torch.float64, device=dv)
+    b = torch.zeros(n, dtype=torch.float64, device=dv)
+    v64 = v.double()
+    for c0 in range(0, m, chunk):
+        blk = S[:, c0:c0 + chunk].double()
+        G += blk @ blk.T
+        b += blk @ v64[c0:c0 + chunk]
+        del blk
+    W = G + lam * torch.eye(n, dtype=torch.float64, device=dv)
+    y = torch.cholesky_solve(b[:, None], torch.linalg.cholesky(W))[:, 0]
+    assert float(torch.linalg.norm(W @ y - b) / torch.linalg.norm(b)) <= 1e-9
+    xref = torch.empty(m, dtype=torch.float64, device=dv)
+    for c0 in range(0, m, chunk):
+        xref[c0:c0 + chunk] = (v64[c0:c0 + chunk] - S[:, c0:c0 + chunk].double().T @ y) / lam
+    err = float(torch.linalg.norm(x - xref) / torch.linalg.norm(xref))
+    print(f"    rel err vs FP64 reference {err:.3e}", flush=True)
+    assert err <= 1e-6
+    # pins: sampled Gram entries (one 4M-term dot product each) and sampled outputs
+    rng = np.random.default_rng(11)
+    ii, jj = rng.integers(0, n, 6), rng.integers(0, n, 6)
+    rows = np.unique(np.concatenate([ii, jj]))
+    pos = {int(r): k for k, r in enumerate(rows)}
+    Srows = S[torch.from_numpy(rows).to(dv)].cpu().numpy()
+    ent = oracle_mod.gram_entries(Srows, [pos[int(i)] for i in ii], [pos[int(j)] for j in jj])
+    Gh = G.cpu().numpy()
+    d = np.sqrt(np.diag(Gh)[ii] * np.diag(Gh)[jj])
+    assert np.all(np.abs(Gh[ii, jj] - ent) <= 1e-12 * d)
+    J = np.sort(rng.choice(m, 512, replace=False))
+    Jt = torch.from_numpy(J).to(dv)
+    xJ = oracle_mod.apply(S[:, Jt].cpu().numpy(), v[Jt].cpu().numpy(), y.cpu().numpy(), lam)
+    assert rel(xref[Jt].cpu().numpy(), xJ) <= 1e-12
+    assert rel(x[Jt].cpu().numpy(), xJ) <= 1e-6
+    del S, v, x, xref, G, W
+    torch.cuda.empty_cache()
