@@ -7,7 +7,8 @@
 //           one FP64 accumulator per (row, vector). Vectors are FP32 (separate arrays, the
 //           caller's right-hand sides) or FP64 interleaved T[k * 8 + c] (the column pass output).
 //           FP64 partials per (column group, vector, row) are added in fixed order by a second
-//           kernel, which can also form refinement residuals r = b - lambda y - S t.
+//           kernel, which can also form refinement residuals r = b - lambda y - S t. With the
+//           FP64 vectors T the 8 waves of a workgroup share each step of T through LDS.
 // Column pass t_c = S^T y_c for c < nc. A workgroup owns 1024 consecutive columns (4 per lane)
 //           and walks all rows; y_c[i] is wave-uniform. Output either T[k * 8 + c] (FP64) or
 //           x_c = (v_c - t_c) / lambda_c (FP32 or FP64), each column with its own v, x, lambda.
@@ -42,13 +43,11 @@ __device__ __forceinline__ void load_s4(const float* __restrict__ p, int64_t col
   }
 }
 
-// Grid: x = row blocks of RM_WAVES * RM_RPW rows, y = column groups of cg columns.
-// IL = false: vector c is vs.f[c] (FP32, contiguous). IL = true: vector c is T[k * 8 + c] (FP64).
-// part[(g * MV + c) * n + i] = sum over group g of S_ik V_c[k].
-template <bool IL>
+// Grid: x = row blocks of RM_WAVES * RM_RPW rows, y = column groups of cg columns. Vector c is
+// vs.f[c] (FP32, contiguous). part[(g * MV + c) * n + i] = sum over group g of S_ik V_c[k].
 __global__ void __launch_bounds__(64 * RM_WAVES)
-rowpass_multi_kernel(const float* __restrict__ S, int64_t n, int64_t m, int64_t lds, MultiVecs vs,
-                     const double* __restrict__ T, int nv, int64_t cg, double* __restrict__ part, int vec) {
+rowpass_multi_kernel(const float* __restrict__ S, int64_t n, int64_t m, int64_t lds, MultiVecs vs, int nv,
+                     int64_t cg, double* __restrict__ part, int vec) {
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int64_t row0 = ((int64_t)blockIdx.x * RM_WAVES + wave) * RM_RPW;
@@ -67,28 +66,12 @@ rowpass_multi_kernel(const float* __restrict__ S, int64_t n, int64_t m, int64_t 
   for (int64_t cs = c0; cs < c1; cs += RM_STEP) {
     const int64_t col = cs + 4 * lane;
     double vv[4][MV];
-    if constexpr (IL) {
-      // 4 columns x 8 vectors = 32 consecutive doubles
-      const double* tp = T + col * MV;
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const bool in = col + e < c1;
+    for (int c = 0; c < MV; ++c) {
+      f32x4 t4 = {0.f, 0.f, 0.f, 0.f};
+      if (c < nv) load_s4(vs.f[c] + col, col, c1, (vec & 2) != 0, t4);
 #pragma unroll
-        for (int c = 0; c < MV; c += 2) {
-          f64x2 t2 = {0.0, 0.0};
-          if (in) t2 = *reinterpret_cast<const f64x2*>(tp + e * MV + c);
-          vv[e][c] = t2[0];
-          vv[e][c + 1] = t2[1];
-        }
-      }
-    } else {
-#pragma unroll
-      for (int c = 0; c < MV; ++c) {
-        f32x4 t4 = {0.f, 0.f, 0.f, 0.f};
-        if (c < nv) load_s4(vs.f[c] + col, col, c1, (vec & 2) != 0, t4);
-#pragma unroll
-        for (int e = 0; e < 4; ++e) vv[e][c] = (double)t4[e];
-      }
+      for (int e = 0; e < 4; ++e) vv[e][c] = (double)t4[e];
     }
     f32x4 sv[RM_RPW];
 #pragma unroll
@@ -103,6 +86,84 @@ rowpass_multi_kernel(const float* __restrict__ S, int64_t n, int64_t m, int64_t 
         const double s = (double)sv[r][e];
 #pragma unroll
         for (int c = 0; c < MV; ++c) acc[r][c] = fma(s, vv[e][c], acc[r][c]);
+      }
+  }
+#pragma unroll
+  for (int r = 0; r < RM_RPW; ++r) {
+    if (r >= nr) continue;
+#pragma unroll
+    for (int c = 0; c < MV; ++c) {
+      const double t = wave_sum(acc[r][c]);
+      if (lane == 0 && c < nv) part[(g * MV + c) * n + row0 + r] = t;
+    }
+  }
+}
+
+// Row pass with the FP64 interleaved vectors T[k * 8 + c] (the refinement's S t_c): the same
+// products and partials as rowpass_multi_kernel with T[k * 8 + c] as vector c, but the workgroup's
+// RT_WAVES waves (32 rows) share each 256-column step of T through LDS (16 KB, double-buffered), so
+// T is read from memory once per 32 rows of S instead of once per 4. In LDS each lane's 4 columns x 8 vectors (256 bytes)
+// are padded by 16 bytes, so the 16-byte fragment reads of 16 consecutive lanes cover all banks.
+constexpr int RT_WAVES = 8;
+constexpr int RT_ROWS = RT_WAVES * RM_RPW;   // 32 rows per workgroup
+constexpr int RT_GROUP = 4 * MV + 2;         // doubles per lane group (4 columns x 8 vectors + pad)
+
+__global__ void __launch_bounds__(64 * RT_WAVES)
+rowpass_multi_t_kernel(const float* __restrict__ S, int64_t n, int64_t m, int64_t lds, const double* __restrict__ T,
+                       int nv, int64_t cg, double* __restrict__ part, int vec) {
+  __shared__ __attribute__((aligned(16))) double tl[2][64 * RT_GROUP];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int64_t row0 = (int64_t)blockIdx.x * RT_ROWS + wave * RM_RPW;
+  const int64_t g = blockIdx.y;
+  const int64_t c0 = g * cg;
+  const int64_t c1 = min(m, c0 + cg);
+  // waves whose rows lie past n still load their share of T and meet the barriers
+  const int nr = (int)max<int64_t>(0, min<int64_t>(RM_RPW, n - row0));
+
+  double acc[RM_RPW][MV];
+#pragma unroll
+  for (int r = 0; r < RM_RPW; ++r)
+#pragma unroll
+    for (int c = 0; c < MV; ++c) acc[r][c] = 0.0;
+
+  int buf = 0;
+  for (int64_t cs = c0; cs < c1; cs += RM_STEP, buf ^= 1) {
+    // T[cs .. cs + 256) x 8 vectors: 2048 doubles, two 16-byte pieces per thread (zero past c1)
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int idx = 2 * (h * 64 * RT_WAVES + tid);   // double index in the step: column idx / 8, vector idx % 8
+      const int cl = idx / MV;
+      f64x2 t2 = {0.0, 0.0};
+      if (cs + cl < c1) t2 = *reinterpret_cast<const f64x2*>(T + cs * MV + idx);
+      *reinterpret_cast<f64x2*>(&tl[buf][(cl >> 2) * RT_GROUP + (cl & 3) * MV + (idx % MV)]) = t2;
+    }
+    __syncthreads();   // the other buffer is rewritten only after the next step's barrier
+    const int64_t col = cs + 4 * lane;
+    f32x4 sv[RM_RPW];
+#pragma unroll
+    for (int r = 0; r < RM_RPW; ++r) {
+      sv[r] = (f32x4){0.f, 0.f, 0.f, 0.f};
+      if (r < nr) load_s4(S + (row0 + r) * lds + col, col, c1, (vec & 1) != 0, sv[r]);
+    }
+    double vv[4][MV];
+    const double* tg = &tl[buf][lane * RT_GROUP];
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+#pragma unroll
+      for (int c = 0; c < MV; c += 2) {
+        const f64x2 t2 = *reinterpret_cast<const f64x2*>(tg + e * MV + c);
+        vv[e][c] = t2[0];
+        vv[e][c + 1] = t2[1];
+      }
+#pragma unroll
+    for (int r = 0; r < RM_RPW; ++r)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const double sd = (double)sv[r][e];
+#pragma unroll
+        for (int c = 0; c < MV; ++c) acc[r][c] = fma(sd, vv[e][c], acc[r][c]);
       }
   }
 #pragma unroll
@@ -228,12 +289,13 @@ hipError_t rowpass_multi_launch(const RowMultiPlan& p, const float* S, const Mul
     for (int c = 0; c < nv; ++c) vecv = vecv && aligned16(vs.f[c]);
   const int iv = (vec ? 1 : 0) | (vecv ? 2 : 0);
   const dim3 grid((unsigned)((p.n + RM_WAVES * RM_RPW - 1) / (RM_WAVES * RM_RPW)), (unsigned)p.nchunk);
-  if (T)
-    hipLaunchKernelGGL((rowpass_multi_kernel<true>), grid, dim3(64 * RM_WAVES), 0, st, S, p.n, p.m, p.lds, vs, T, nv,
-                       p.chunk, part, iv);
-  else
-    hipLaunchKernelGGL((rowpass_multi_kernel<false>), grid, dim3(64 * RM_WAVES), 0, st, S, p.n, p.m, p.lds, vs, T, nv,
-                       p.chunk, part, iv);
+  if (T) {
+    const dim3 gridt((unsigned)((p.n + RT_ROWS - 1) / RT_ROWS), (unsigned)p.nchunk);
+    hipLaunchKernelGGL(rowpass_multi_t_kernel, gridt, dim3(64 * RT_WAVES), 0, st, S, p.n, p.m, p.lds, T, nv, p.chunk,
+                       part, iv);
+  } else
+    hipLaunchKernelGGL(rowpass_multi_kernel, grid, dim3(64 * RM_WAVES), 0, st, S, p.n, p.m, p.lds, vs, nv, p.chunk,
+                       part, iv);
   return hipGetLastError();
 }
 
