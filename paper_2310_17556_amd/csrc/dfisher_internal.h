@@ -105,7 +105,7 @@ hipError_t colpass_launch(const ColPassPlan& p, const float* S, int64_t n, int64
                           const float* v, double lambda, void* out, int mode, double* part, hipStream_t st);
 
 // Fused refinement pass: part[g][i] = per-workgroup partials of (S S^T y)_i with one read of S
-// (n <= 4096 and a multiple of 16, m >= 16, 16-byte aligned rows; `usable` is false otherwise and
+// (n <= 4096, m >= 16, 16-byte aligned rows; `usable` is false otherwise and
 // the caller takes the column pass + row pass). The last m % 16 columns add one more group.
 // refine_pass_reduce: r_i = b_i - lam y_i - sum_g part[g][i] in fixed order.
 struct RefinePassPlan {

@@ -422,8 +422,7 @@ rowpass_prep_kernel(const float* __restrict__ S, int64_t n, int64_t m, int64_t l
 // halves of each 128-byte line of a row are read through the same L2 at about the same time. At
 // the end each row's accumulators are reduced over its 4 lanes and stored as one partial per
 // workgroup, part[g * n + i], which refine_reduce_kernel adds in fixed order. NCH loads per lane
-// cover n <= 16 FR_WAVES NCH rows; n is a multiple of 16, so a wave's rows of one load are all
-// valid or all past the end. Only whole 16-column blocks are streamed here.
+// cover n <= 16 FR_WAVES NCH rows. Only whole 16-column blocks are streamed here.
 constexpr int FR_COLS = 16;
 constexpr int FR_WAVES = 8;    // 2 waves per SIMD: 256 registers per lane for 32 loads in flight
 
@@ -455,15 +454,18 @@ refine_pass_kernel(const float* __restrict__ S, int64_t n, int64_t m, int64_t ld
   const int64_t slot = (G & 7) == 0 ? (int64_t)(blockIdx.x & 7) * (G >> 3) + (blockIdx.x >> 3) : (int64_t)blockIdx.x;
   auto block_of = [&](int64_t s) { return s * G + slot; };
   // Load c of a block: rows c ROWS + 16 wave .. + 15, as a buffer load from a wave-uniform base
-  // (the block's first column in row c ROWS + 16 wave) with the 32-bit lane offset; for a wave
-  // whose rows of this load lie past n, or with !any (no next block), the buffer has no records:
-  // the load returns zeros without touching memory, and the loop needs no branch around it.
+  // (the block's first column in row c ROWS + 16 wave) with the 32-bit lane offset. The buffer's
+  // records end at row n, so rows past n read zeros; for a wave whose rows of this load all lie
+  // past n, or with !any (no next block), it has no records at all and the load touches no
+  // memory. The loop needs no branch around a load.
   auto load = [&](int64_t blk, int c, bool any) -> f32x4 {
     const int64_t r0 = (int64_t)c * ROWS + wave * 16;
-    const bool in = any && r0 < n;   // uniform
+    const int64_t rin = any ? min<int64_t>(16, n - r0) : 0;   // rows of this load below n (uniform)
+    const bool in = rin > 0;
     const float* base = S + (in ? r0 : 0) * lds + blk * FR_COLS;
+    // records end at row r0 + rin: lanes of rows past n read zeros (their offsets start there)
     const __amdgpu_buffer_rsrc_t rs =
-        __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(base), 0, in ? (int)(16 * lds * 4) : 0, 0x00020000);
+        __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(base), 0, in ? (int)(rin * lds * 4) : 0, 0x00020000);
     return __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(rs, (int)loff, 0, 0));
   };
   // Software pipeline without extra registers: the loads of block s + 1 are issued during the
@@ -716,7 +718,7 @@ RefinePassPlan refine_pass_plan(int64_t n, int64_t m, int64_t lds, const float* 
   const int64_t rows = 16 * FR_WAVES;
   p.nch = n <= 8 * rows ? 8 : (n <= 16 * rows ? 16 : (n <= 32 * rows ? 32 : 0));
   const int64_t nfull = m / FR_COLS;
-  p.usable = p.nch > 0 && n % 16 == 0 && nfull > 0 && ((lds & 3) == 0) && aligned16(S) &&
+  p.usable = p.nch > 0 && nfull > 0 && ((lds & 3) == 0) && aligned16(S) &&
              16 * lds * 4 < ((int64_t)1 << 31);
   int dev = 0, cus = 0;
   if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)

@@ -244,8 +244,8 @@ SOLVE_CASES = [
     (300, 20000, 1e-2, 2, 4, "iid", 1e-6),      # scaled-FP8 Gram + refinement (m/n = 67: slow contraction)
     (300, 20000, 1e-6, 2, 3, "iid", 1e-6),
     (257, 30000, 1e-3, 2, 3, "iid", 1e-6),
-    # n a multiple of 16 and 16-byte aligned rows: the refinement product S S^T y takes the fused
-    # one-read pass
+    # 16-byte aligned rows: the refinement product S S^T y takes the fused one-read pass (also in
+    # the aligned cases above, n = 300 and 257 with a partial last row group)
     (320, 20004, 1e-2, 2, 4, "iid", 1e-6),      # m % 16 = 4: the last columns in the tail group
     (320, 20016, 1e-6, 2, 3, "iid", 1e-6),      # whole 16-column blocks only
     (320, 20008, 1e-3, 0, 1, "scaled", 1e-6),
