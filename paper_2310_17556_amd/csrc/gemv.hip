@@ -172,20 +172,37 @@ rowpass_kernel(const float* __restrict__ S, int64_t n, int64_t m, int64_t lds, c
 }
 
 // b_i = sum_g part_b[g][i] (or r0_i - lam y_i - sum_g part_b[g][i]); d_i = sum_g part_d[g][i].
-__global__ void rowpass_reduce_kernel(const double* __restrict__ part, int64_t n, int64_t ngroups, int want_b,
-                                      int want_d, double* __restrict__ b, double* __restrict__ d,
-                                      const double* __restrict__ r0, const double* __restrict__ y, double lam) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  if (want_b) {
-    double s = 0.0;
-    for (int64_t g = 0; g < ngroups; ++g) s += part[g * n + i];
-    b[i] = r0 ? (r0[i] - lam * y[i]) - s : s;
+// 16 rows and 16 group lanes per 256-thread workgroup: lane s adds groups s, s + 16, ... in order,
+// and the 16 lane sums are combined by a fixed pairwise tree in LDS (many groups at small n).
+__global__ void __launch_bounds__(256)
+rowpass_reduce_kernel(const double* __restrict__ part, int64_t n, int64_t ngroups, int want_b, int want_d,
+                      double* __restrict__ b, double* __restrict__ d, const double* __restrict__ r0,
+                      const double* __restrict__ y, double lam) {
+  __shared__ double red[2][16][17];
+  const int tid = threadIdx.x;
+  const int ri = tid & 15, sl = tid >> 4;
+  const int64_t i = (int64_t)blockIdx.x * 16 + ri;
+  double sb = 0.0, sd = 0.0;
+  if (i < n) {
+    for (int64_t g = sl; g < ngroups; g += 16) {
+      if (want_b) sb += part[g * n + i];
+      if (want_d) sd += part[(ngroups + g) * n + i];
+    }
   }
-  if (want_d) {
-    double s = 0.0;
-    for (int64_t g = 0; g < ngroups; ++g) s += part[(ngroups + g) * n + i];
-    d[i] = s;
+  red[0][sl][ri] = sb;
+  red[1][sl][ri] = sd;
+  __syncthreads();
+#pragma unroll
+  for (int w = 8; w > 0; w >>= 1) {
+    if (sl < w) {
+      red[0][sl][ri] += red[0][sl + w][ri];
+      red[1][sl][ri] += red[1][sl + w][ri];
+    }
+    __syncthreads();
+  }
+  if (sl == 0 && i < n) {
+    if (want_b) b[i] = r0 ? (r0[i] - lam * y[i]) - red[0][0][ri] : red[0][0][ri];
+    if (want_d) d[i] = red[1][0][ri];
   }
 }
 
@@ -421,7 +438,7 @@ rowpass_prep_kernel(const float* __restrict__ S, int64_t n, int64_t m, int64_t l
 // the workgroups of one XCD (w mod 8, in dispatch order) take a contiguous run of them, so the two
 // halves of each 128-byte line of a row are read through the same L2 at about the same time. At
 // the end each row's accumulators are reduced over its 4 lanes and stored as one partial per
-// workgroup, part[g * n + i], which refine_reduce_kernel adds in fixed order. NCH loads per lane
+// workgroup, part[g * n + i], which rowpass_reduce_kernel adds in fixed order. NCH loads per lane
 // cover n <= 16 FR_WAVES NCH rows. Only whole 16-column blocks are streamed here.
 constexpr int FR_COLS = 16;
 constexpr int FR_WAVES = 8;    // 2 waves per SIMD: 256 registers per lane for 32 loads in flight
@@ -530,29 +547,6 @@ refine_pass_kernel(const float* __restrict__ S, int64_t n, int64_t m, int64_t ld
     const int64_t row = (int64_t)c * ROWS + rbase;
     if (q == 0 && row < n) part[(int64_t)blockIdx.x * n + row] = v;
   }
-}
-
-// r_i = b_i - lam y_i - sum_g part[g][i] over the fused pass's ngroups partials, with 16 rows and
-// 16 group lanes per 256-thread workgroup: lane s adds groups s, s + 16, ... in order, and the 16
-// lane sums are combined by a fixed pairwise tree in LDS.
-__global__ void __launch_bounds__(256)
-refine_reduce_kernel(const double* __restrict__ part, int64_t n, int64_t ngroups, double* __restrict__ r,
-                     const double* __restrict__ b, const double* __restrict__ y, double lam) {
-  __shared__ double red[16][17];
-  const int tid = threadIdx.x;
-  const int ri = tid & 15, sl = tid >> 4;
-  const int64_t i = (int64_t)blockIdx.x * 16 + ri;
-  double acc = 0.0;
-  if (i < n)
-    for (int64_t g = sl; g < ngroups; g += 16) acc += part[g * n + i];
-  red[sl][ri] = acc;
-  __syncthreads();
-#pragma unroll
-  for (int w = 8; w > 0; w >>= 1) {
-    if (sl < w) red[sl][ri] += red[sl + w][ri];
-    __syncthreads();
-  }
-  if (sl == 0 && i < n) r[i] = (b[i] - lam * y[i]) - red[0][ri];
 }
 
 // The last m % 16 (< 16) columns of the fused pass, as one more group of partials: t_c = sum_i
@@ -671,7 +665,7 @@ hipError_t rowpass_launch_split(const RowPassPlan& p, const float* S, const floa
 
 hipError_t rowpass_reduce(const RowPassPlan& p, const double* part, bool want_b, bool want_d, double* b, double* d,
                           const double* r0, const double* y, double lam, hipStream_t st) {
-  const dim3 grid((unsigned)((p.n + 255) / 256));
+  const dim3 grid((unsigned)((p.n + 15) / 16));
   hipLaunchKernelGGL(rowpass_reduce_kernel, grid, dim3(256), 0, st, part, p.n, p.nchunk, want_b ? 1 : 0,
                      want_d ? 1 : 0, b, d, r0, y, lam);
   return hipGetLastError();
@@ -746,8 +740,8 @@ hipError_t refine_pass_launch(const RefinePassPlan& p, const float* S, int64_t n
 
 hipError_t refine_pass_reduce(const RefinePassPlan& p, const double* part, double* r, const double* b,
                               const double* y, double lam, hipStream_t st) {
-  hipLaunchKernelGGL(refine_reduce_kernel, dim3((unsigned)((p.n + 15) / 16)), dim3(256), 0, st, part, p.n,
-                     p.ngroups + (p.tail ? 1 : 0), r, b, y, lam);
+  hipLaunchKernelGGL(rowpass_reduce_kernel, dim3((unsigned)((p.n + 15) / 16)), dim3(256), 0, st, part, p.n,
+                     p.ngroups + (p.tail ? 1 : 0), 1, 0, r, (double*)nullptr, b, y, lam);
   return hipGetLastError();
 }
 
