@@ -1014,7 +1014,18 @@ __global__ void gram_reduce_kernel(const float* __restrict__ part, int64_t n, in
     const int64_t tile = ti * (ti + 1) / 2 + tj;
     const int64_t off = (i - ti * T) * T + (j - tj * T);
     s = 0.0;
-    for (int64_t sl = 0; sl < nslice; ++sl) s += (double)part[(sl * ntri + tile) * (int64_t)(T * T) + off];
+    // slices added in order; unrolled so that several slices' loads are in flight at once
+    const float* pp = part + tile * (int64_t)(T * T) + off;
+    const int64_t sstride = ntri * (int64_t)(T * T);
+    int64_t sl = 0;
+    for (; sl + 8 <= nslice; sl += 8) {
+      float v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = pp[(sl + u) * sstride];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) s += (double)v[u];
+    }
+    for (; sl < nslice; ++sl) s += (double)pp[sl * sstride];
     for (int64_t k = ktail; k < m; ++k) s += (double)S[i * lds + k] * (double)S[j * lds + k];
   }
   W[i * n + j] = s;
