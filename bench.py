@@ -114,8 +114,8 @@ GRAM_KERNEL = {"fp32": "gram_kernel_v2<0>", "bf16x3": "gram_kernel_split", "mxfp
 # valid only for the kernel source they were taken on (sha256 of csrc/gram.hip); see profiles/.
 GRAM_TRAFFIC = {
     ("mxfp8", 4096, 4_000_000): {
-        "gram_hip_sha256": "d8749722c10d04bf2d10fac7323d903ea8238d991ee987e911e793c561e83493",
-        "bytes_per_launch": 62.96e9 + 1.14e9,   # FETCH_SIZE x 2 + WRITE_SIZE x 1 (KiB -> bytes)
+        "gram_hip_sha256": "baf84ddbe4cc2ef3aa8ad6bc7dce39e34a85f4ef8da9e3ea7dd59f43b35e08d8",
+        "bytes_per_launch": 62.99e9 + 1.14e9,   # FETCH_SIZE x 2 + WRITE_SIZE x 1 (KiB -> bytes)
     },
 }
 
