@@ -101,11 +101,12 @@ rowpass_multi_kernel(const float* __restrict__ S, int64_t n, int64_t m, int64_t 
 
 // Row pass with the FP64 interleaved vectors T[k * 8 + c] (the refinement's S t_c): the same
 // products and partials as rowpass_multi_kernel with T[k * 8 + c] as vector c, but the workgroup's
-// RT_WAVES waves (32 rows) share each 256-column step of T through LDS (16 KB, double-buffered), so
-// T is read from memory once per 32 rows of S instead of once per 4. In LDS each lane's 4 columns x 8 vectors (256 bytes)
+// RT_WAVES waves (64 rows) share each 256-column step of T through LDS (16 KB, double-buffered), so
+// T is read from memory once per 64 rows of S instead of once per 4. In LDS each lane's 4 columns x 8 vectors (256 bytes)
 // are padded by 16 bytes, so the 16-byte fragment reads of 16 consecutive lanes cover all banks.
 constexpr int RT_WAVES = 8;
-constexpr int RT_ROWS = RT_WAVES * RM_RPW;   // 32 rows per workgroup
+constexpr int RT_RPW = 8;                    // rows per wave
+constexpr int RT_ROWS = RT_WAVES * RT_RPW;   // 64 rows per workgroup
 constexpr int RT_GROUP = 4 * MV + 2;         // doubles per lane group (4 columns x 8 vectors + pad)
 
 __global__ void __launch_bounds__(64 * RT_WAVES)
@@ -115,16 +116,16 @@ rowpass_multi_t_kernel(const float* __restrict__ S, int64_t n, int64_t m, int64_
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
-  const int64_t row0 = (int64_t)blockIdx.x * RT_ROWS + wave * RM_RPW;
+  const int64_t row0 = (int64_t)blockIdx.x * RT_ROWS + wave * RT_RPW;
   const int64_t g = blockIdx.y;
   const int64_t c0 = g * cg;
   const int64_t c1 = min(m, c0 + cg);
   // waves whose rows lie past n still load their share of T and meet the barriers
-  const int nr = (int)max<int64_t>(0, min<int64_t>(RM_RPW, n - row0));
+  const int nr = (int)max<int64_t>(0, min<int64_t>(RT_RPW, n - row0));
 
-  double acc[RM_RPW][MV];
+  double acc[RT_RPW][MV];
 #pragma unroll
-  for (int r = 0; r < RM_RPW; ++r)
+  for (int r = 0; r < RT_RPW; ++r)
 #pragma unroll
     for (int c = 0; c < MV; ++c) acc[r][c] = 0.0;
 
@@ -141,9 +142,9 @@ rowpass_multi_t_kernel(const float* __restrict__ S, int64_t n, int64_t m, int64_
     }
     __syncthreads();   // the other buffer is rewritten only after the next step's barrier
     const int64_t col = cs + 4 * lane;
-    f32x4 sv[RM_RPW];
+    f32x4 sv[RT_RPW];
 #pragma unroll
-    for (int r = 0; r < RM_RPW; ++r) {
+    for (int r = 0; r < RT_RPW; ++r) {
       sv[r] = (f32x4){0.f, 0.f, 0.f, 0.f};
       if (r < nr) load_s4(S + (row0 + r) * lds + col, col, c1, (vec & 1) != 0, sv[r]);
     }
@@ -158,7 +159,7 @@ rowpass_multi_t_kernel(const float* __restrict__ S, int64_t n, int64_t m, int64_
         vv[e][c + 1] = t2[1];
       }
 #pragma unroll
-    for (int r = 0; r < RM_RPW; ++r)
+    for (int r = 0; r < RT_RPW; ++r)
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
         const double sd = (double)sv[r][e];
@@ -167,7 +168,7 @@ rowpass_multi_t_kernel(const float* __restrict__ S, int64_t n, int64_t m, int64_
       }
   }
 #pragma unroll
-  for (int r = 0; r < RM_RPW; ++r) {
+  for (int r = 0; r < RT_RPW; ++r) {
     if (r >= nr) continue;
 #pragma unroll
     for (int c = 0; c < MV; ++c) {
