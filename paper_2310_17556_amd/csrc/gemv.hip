@@ -475,14 +475,19 @@ refine_pass_kernel(const float* __restrict__ S, int64_t n, int64_t m, int64_t ld
   // records end at row n, so rows past n read zeros; for a wave whose rows of this load all lie
   // past n, or with !any (no next block), it has no records at all and the load touches no
   // memory. The loop needs no branch around a load.
+  // n, re-declared opaque every block (see the loop): each load's record count is formed where it
+  // is used instead of NCH of them being kept in scalar registers
+  // 32-bit scalars (n <= 4096, 16 lds * 4 < 2^31): few scalar registers per load
+  int nrows = (int)n;
+  const int rowbytes = (int)(lds * 4);
   auto load = [&](int64_t blk, int c, bool any) -> f32x4 {
-    const int64_t r0 = (int64_t)c * ROWS + wave * 16;
-    const int64_t rin = any ? min<int64_t>(16, n - r0) : 0;   // rows of this load below n (uniform)
+    const int r0 = c * ROWS + wave * 16;
+    const int rin = any ? min(16, nrows - r0) : 0;   // rows of this load below n (uniform)
     const bool in = rin > 0;
-    const float* base = S + (in ? r0 : 0) * lds + blk * FR_COLS;
+    const float* base = S + (in ? (int64_t)r0 : 0) * lds + blk * FR_COLS;
     // records end at row r0 + rin: lanes of rows past n read zeros (their offsets start there)
     const __amdgpu_buffer_rsrc_t rs =
-        __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(base), 0, in ? (int)(rin * lds * 4) : 0, 0x00020000);
+        __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(base), 0, in ? rin * rowbytes : 0, 0x00020000);
     return __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(rs, (int)loff, 0, 0));
   };
   // Software pipeline without extra registers: the loads of block s + 1 are issued during the
@@ -499,6 +504,7 @@ refine_pass_kernel(const float* __restrict__ S, int64_t n, int64_t m, int64_t ld
   if (more) do {
     const int64_t nxt = block_of(s + 1);
     more = nxt < nblk;
+    asm volatile("" : "+s"(nrows));
     double tq[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int c = 0; c < NCH; ++c) {
