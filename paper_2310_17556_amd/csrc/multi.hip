@@ -148,24 +148,25 @@ rowpass_multi_t_kernel(const float* __restrict__ S, int64_t n, int64_t m, int64_
       sv[r] = (f32x4){0.f, 0.f, 0.f, 0.f};
       if (r < nr) load_s4(S + (row0 + r) * lds + col, col, c1, (vec & 1) != 0, sv[r]);
     }
-    double vv[4][MV];
     const double* tg = &tl[buf][lane * RT_GROUP];
+    // one column at a time: its 8 vector entries are live only while its products are formed
 #pragma unroll
-    for (int e = 0; e < 4; ++e)
+    for (int e = 0; e < 4; ++e) {
+      double vv[MV];
 #pragma unroll
       for (int c = 0; c < MV; c += 2) {
         const f64x2 t2 = *reinterpret_cast<const f64x2*>(tg + e * MV + c);
-        vv[e][c] = t2[0];
-        vv[e][c + 1] = t2[1];
+        vv[c] = t2[0];
+        vv[c + 1] = t2[1];
       }
 #pragma unroll
-    for (int r = 0; r < RT_RPW; ++r)
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
+      for (int r = 0; r < RT_RPW; ++r) {
         const double sd = (double)sv[r][e];
 #pragma unroll
-        for (int c = 0; c < MV; ++c) acc[r][c] = fma(sd, vv[e][c], acc[r][c]);
+        for (int c = 0; c < MV; ++c) acc[r][c] = fma(sd, vv[c], acc[r][c]);
       }
+      __builtin_amdgcn_sched_barrier(0);
+    }
   }
 #pragma unroll
   for (int r = 0; r < RT_RPW; ++r) {
