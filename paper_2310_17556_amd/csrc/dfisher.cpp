@@ -8,6 +8,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <functional>
 #include <vector>
 #include <map>
 #include <tuple>
@@ -276,9 +277,13 @@ SolveBufs carve(char* base, int64_t n, int64_t m, const dfi::GramPlan* gp, const
 }
 
 // Cholesky of W (+ tau I) into L following the shift policy. Synchronises once per attempt.
+// `spec`, if given, is enqueued right after the first attempt's factorisation and before the wait
+// for its status (work that depends on L, started speculatively so that the host enqueues it while
+// the device is still busy); *spec_ok tells whether that work saw the final factor.
 dfisher_status factor_with_policy(dfisher_ctx* ctx, const double* W, double* L, double* dkk, int64_t n, int policy,
                                   double unit, hipStream_t st, double* shift_out, int64_t* info_out,
-                                  int32_t* attempts_out) {
+                                  int32_t* attempts_out, const std::function<dfisher_status()>& spec = {},
+                                  bool* spec_ok = nullptr) {
   // base shift: about sqrt(n) times the rounding unit of a computed Gram entry
   const double base_scale = std::sqrt((double)n) * unit;
   double scale = 0.0;  // tau = scale * max_i W_ii, evaluated on the device
@@ -289,6 +294,7 @@ dfisher_status factor_with_policy(dfisher_ctx* ctx, const double* W, double* L, 
   for (;;) {
     HIP_TRY(dfi::shift_copy(W, L, n, scale, ctx->d_scalar, st));
     HIP_TRY(dfi::potrf_launch(L, n, ctx->d_info, ctx->d_flag, dkk, st));
+    if (attempts == 0 && spec) DF_TRY(spec());
     HIP_TRY(hipMemcpyAsync(ctx->h_status, ctx->d_info, sizeof(int64_t), hipMemcpyDeviceToHost, st));
     if (policy != DFISHER_SHIFT_NONE)
       HIP_TRY(hipMemcpyAsync(ctx->h_scalar, ctx->d_scalar, sizeof(double), hipMemcpyDeviceToHost, st));
@@ -300,6 +306,7 @@ dfisher_status factor_with_policy(dfisher_ctx* ctx, const double* W, double* L, 
     scale = (scale == 0.0) ? base_scale : 8.0 * scale;
   }
   HIP_TRY(dfi::zero_upper(L, n, st));
+  if (spec_ok) *spec_ok = attempts == 1 && info == 0;
   *shift_out = (info == 0 && policy != DFISHER_SHIFT_NONE) ? scale * ctx->h_scalar[0] : 0.0;
   *info_out = info;
   *attempts_out = attempts;
@@ -343,10 +350,13 @@ dfisher_status gram_stage(const float* S, const float* v, const dfi::GramPlan& g
 dfisher_status solve_y(const float* S, int64_t n, int64_t m, int64_t lds, double lambda, const double* L,
                        const double* Dinv, const SolveBufs& B, const dfi::RowPassPlan& rp, const dfi::ColPassPlan& cp,
                        int sweeps, hipStream_t st, StageClock* clk = nullptr, const dfi::RefinePassPlan* fp = nullptr,
-                       dfisher_ctx* ctx = nullptr, double tol = 0.0, int* done = nullptr, double* resid = nullptr) {
-  HIP_TRY(dfi::trsv_launch(L, Dinv, n, 0, B.b, B.z, B.tw, st));
-  HIP_TRY(dfi::trsv_launch(L, Dinv, n, 1, B.z, B.y, B.tw, st));
-  if (clk) clk->mark(5);
+                       dfisher_ctx* ctx = nullptr, double tol = 0.0, int* done = nullptr, double* resid = nullptr,
+                       bool initial = true) {
+  if (initial) {   // (else the caller has formed y = L^-T L^-1 b already)
+    HIP_TRY(dfi::trsv_launch(L, Dinv, n, 0, B.b, B.z, B.tw, st));
+    HIP_TRY(dfi::trsv_launch(L, Dinv, n, 1, B.z, B.y, B.tw, st));
+    if (clk) clk->mark(5);
+  }
   const bool fused = fp && fp->usable;
   const bool measure = ctx && tol > 0.0;
   if (done) *done = 0;
@@ -1206,14 +1216,25 @@ dfisher_status dfisher_solve(dfisher_ctx* ctx, const float* S, int64_t n, int64_
   clk.mark(3);
   dfisher_info inf{};
   inf.resid = -1.0;
-  DF_TRY(factor_with_policy(ctx, B.W, B.L, B.dkk, n, o.shift_policy, gram_unit(o.gram_prec, m), st, &inf.shift, &inf.potrf_info,
-                            &inf.attempts));
-  HIP_TRY(dfi::trsv_diag_inv(B.L, n, B.Dinv, st));
-  // steps 3-4 inlined: y = W^-1 S v (+ refinement), x = (v - S^T y) / lambda
-  clk.mark(4);
+  // steps 3-4 inlined: y = W^-1 S v (+ refinement), x = (v - S^T y) / lambda. The first
+  // application of L^-1 and L^-T is enqueued right behind the first factorisation attempt, before
+  // the host waits for its status, and repeated only if that attempt was not the final one.
+  auto first_solve = [&]() -> dfisher_status {
+    clk.mark(4);
+    HIP_TRY(dfi::trsv_diag_inv(B.L, n, B.Dinv, st));
+    HIP_TRY(dfi::trsv_launch(B.L, B.Dinv, n, 0, B.b, B.z, B.tw, st));
+    HIP_TRY(dfi::trsv_launch(B.L, B.Dinv, n, 1, B.z, B.y, B.tw, st));
+    clk.mark(5);
+    return DFISHER_OK;
+  };
+  bool spec_ok = false;
+  DF_TRY(factor_with_policy(ctx, B.W, B.L, B.dkk, n, o.shift_policy, gram_unit(o.gram_prec, m), st, &inf.shift,
+                            &inf.potrf_info, &inf.attempts, first_solve, &spec_ok));
+  if (!spec_ok) DF_TRY(first_solve());
   int done = 0;
   double resid = -1.0;
-  DF_TRY(solve_y(S, n, m, lds, lambda, B.L, B.Dinv, B, rp, cp, o.sweeps, st, &clk, &fp, ctx, o.tol, &done, &resid));
+  DF_TRY(solve_y(S, n, m, lds, lambda, B.L, B.Dinv, B, rp, cp, o.sweeps, st, &clk, &fp, ctx, o.tol, &done, &resid,
+                 false));
   HIP_TRY(dfi::colpass_launch(cp, S, n, m, lds, B.y, v, lambda, x, o.x_fp64, B.cpart, st));
   clk.mark(7);
   inf.sweeps_done = done;
