@@ -23,6 +23,7 @@
 #include "dfisher_internal.h"
 
 #include <algorithm>
+#include <type_traits>
 
 namespace dfi {
 namespace {
@@ -53,6 +54,15 @@ __device__ __forceinline__ void tri_index(int64_t t, int64_t& ti, int64_t& tj) {
   while (r * (r + 1) / 2 > t) --r;
   ti = r;
   tj = t - r * (r + 1) / 2;
+}
+
+// A value the whole wave agrees on, moved to scalar registers. 64-bit division and the square
+// root in tri_index expand to vector code, and without this everything derived from their
+// results (column ranges, step counts, load addresses) would be computed per lane in the loops.
+__device__ __forceinline__ int64_t uni64(int64_t x) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)x);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)((uint64_t)x >> 32));
+  return (int64_t)(((uint64_t)hi << 32) | lo);
 }
 
 // Grouped launches: workgroup w belongs to the job with the largest wg_begin <= w (binary search
@@ -577,8 +587,8 @@ __device__ __forceinline__ void panel_offsets(int64_t n, int64_t row0, PanelOffs
 // The step at column kcol (a multiple of 64): 64 code bytes of each of the panel's rows and the
 // rows' scale words, direct to LDS. Every step lies inside [0, ldq), where the row pass wrote
 // zero codes past m, so there is nothing to mask.
-__device__ __forceinline__ void issue_panel(const uint8_t* __restrict__ q, const uint8_t* __restrict__ sc, int64_t n,
-                                            int64_t kcol, const PanelOffs& po, uint8_t* panel, uint8_t* sdst) {
+__device__ __forceinline__ void issue_panel(const uint8_t* q, const uint8_t* sc, int64_t n, int64_t kcol,
+                                            const PanelOffs& po, uint8_t* panel, uint8_t* sdst) {
   const int wave = threadIdx.x >> 6;
   const uint8_t* qb = q + ((kcol >> 6) * n << 6);   // row 0 of this step's block, uniform
 #pragma unroll
@@ -606,6 +616,8 @@ __device__ __forceinline__ i32x8 read_frag(const uint8_t* panel, int r, int h) {
 
 // vmcnt(N) with the other counters left alone (gfx9 encoding: vmcnt bits [3:0] and [15:14]).
 #define DFI_WAIT_VM(N) __builtin_amdgcn_s_waitcnt(((N) & 15) | (((N) >> 4) << 14) | (7 << 4) | (15 << 8))
+// lgkmcnt(0) with the other counters left alone (lgkmcnt bits [11:8]).
+#define DFI_WAIT_LGKM0() __builtin_amdgcn_s_waitcnt(15 | (3 << 14) | (7 << 4))
 
 // G = true: a grouped launch over jobs[0 .. njobs) (the scalar arguments are then ignored).
 template <bool G>
@@ -630,17 +642,19 @@ gram_kernel_fp8(const uint8_t* __restrict__ q, const uint8_t* __restrict__ sc, i
   }
   const int64_t xcd = w & 7;
   const int64_t local = w >> 3;
-  const int64_t qq = local / ntri;
+  const int64_t qq = uni64(local / ntri);
   const int64_t tile = local - qq * ntri;
   const int64_t slice = xcd * (nslice >> 3) + qq;
 
   int64_t ti, tj;
   tri_index(tile, ti, tj);
+  ti = uni64(ti);
+  tj = uni64(tj);
   const bool diag = (ti == tj);
   const int64_t rowA = ti * T, rowB = tj * T;
-  const int64_t k0 = slice * kslice;
+  const int64_t k0 = uni64(slice * kslice);
   const int64_t kend = min(kcap, k0 + kslice);
-  const int64_t nsteps = (kend > k0) ? (kend - k0) / KS8 : 0;   // both multiples of 64
+  const int64_t nsteps = uni64((kend > k0) ? (kend - k0) / KS8 : 0);   // both multiples of 64
 
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
@@ -657,22 +671,28 @@ gram_kernel_fp8(const uint8_t* __restrict__ q, const uint8_t* __restrict__ sc, i
 #pragma unroll
       for (int e = 0; e < 16; ++e) acc[i][j][e] = 0.f;
 
-  auto stage_ptr = [&](int64_t idx) -> Stage* {
-    switch (idx & 3) {
-      case 0: return &stg0;
-      case 1: return &stg1;
-      case 2: return &stg2;
-      default: return &stg3;
-    }
+  // Stage k of the ring, k a compile-time constant: the step loop is unrolled by NS so that every
+  // LDS access names its stage object. The compiler's tracking of direct-to-LDS loads can then
+  // tell the stages apart; with a stage picked at run time it cannot, and it inserts a wait for
+  // every load in flight (the three steps ahead included) before the first operand read of a step.
+  auto stage = [&](auto k) -> Stage& {
+    constexpr int K = decltype(k)::value;
+    if constexpr (K == 0) return stg0;
+    else if constexpr (K == 1) return stg1;
+    else if constexpr (K == 2) return stg2;
+    else return stg3;
   };
   PanelOffs offA, offB;
   panel_offsets(n, rowA, offA);
   panel_offsets(n, rowB, offB);
-  auto issue_step = [&](int64_t step) {
-    Stage* sp = stage_ptr(step);
-    const int64_t kc = k0 + step * KS8;
-    issue_panel(q, sc, n, kc, offA, sp->a, sp->sa);
-    issue_panel(q, sc, n, kc, offB, sp->b, sp->sb);   // diagonal tiles too: uniform load counts
+  // Refill stage k with `step` (k = step mod NS). Steps past the slice's end load the slice's
+  // last step again (never read as operands): every step then issues the same loads and waits
+  // for the same count, with no branch in the loop.
+  auto issue_step = [&](auto k, int64_t step) {
+    Stage& sp = stage(k);
+    const int64_t kc = k0 + min(step, nsteps - 1) * KS8;
+    issue_panel(q, sc, n, kc, offA, sp.a, sp.sa);
+    issue_panel(q, sc, n, kc, offB, sp.b, sp.sb);   // diagonal tiles too: uniform load counts
   };
   // this wave's operands of one step, read from LDS into registers
   // head of a step: the four B fragments with their scales and the first A fragment
@@ -682,46 +702,78 @@ gram_kernel_fp8(const uint8_t* __restrict__ q, const uint8_t* __restrict__ sc, i
     i32x8 fa0;
     int sa0;
   };
-  auto load_head = [&](int64_t step, Head& h) {
-    const Stage* cu = stage_ptr(step);
-    const int sbyte = (int)(((k0 + step * KS8) >> 5) & 3) + half;
+  // Per-lane LDS byte offsets inside a stage. Fragment i of the wave's A rows is row
+  // wr WT + 32 i + l32; its swizzle (row >> 2) & 3 depends on l32 only, so fragment i sits at the
+  // fragment-0 offsets + 32 i KS8 and its scale byte at + 128 i.
+  struct LaneOffs {
+    int a0, a1, b0, b1, sa, sb;
+  };
+  LaneOffs lo0;
+  {
+    const int sw = (l32 >> 2) & 3;
+    const int ra = wr * WT + l32, rb = wc * WT + l32;
+    lo0.a0 = ra * KS8 + 16 * (half ^ sw);
+    lo0.a1 = ra * KS8 + 16 * ((2 + half) ^ sw);
+    lo0.b0 = rb * KS8 + 16 * (half ^ sw);
+    lo0.b1 = rb * KS8 + 16 * ((2 + half) ^ sw);
+    lo0.sa = 4 * ra + half;
+    lo0.sb = 4 * rb + half;
+  }
+  auto frag = [](const uint8_t* p0, const uint8_t* p1) {
+    const i32x4 x0 = *reinterpret_cast<const i32x4*>(p0);
+    const i32x4 x1 = *reinterpret_cast<const i32x4*>(p1);
+    i32x8 v;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      v[e] = x0[e];
+      v[4 + e] = x1[e];
+    }
+    return v;
+  };
+  auto load_head = [&](auto k, int64_t step, Head& h, const LaneOffs& lo) {
+    const Stage& cu = stage(k);
+    const int sbyte = (int)(((k0 + step * KS8) >> 5) & 3);
 #pragma unroll
     for (int j = 0; j < NB; ++j) {
-      const int r = wc * WT + j * 32 + l32;
-      h.fb[j] = read_frag(cu->b, r, half);
-      h.sbv[j] = cu->sb[4 * r + sbyte];
+      h.fb[j] = frag(cu.b + lo.b0 + 32 * KS8 * j, cu.b + lo.b1 + 32 * KS8 * j);
+      h.sbv[j] = cu.sb[lo.sb + 128 * j + sbyte];
     }
-    const int r = wr * WT + l32;
-    h.fa0 = read_frag(cu->a, r, half);
-    h.sa0 = cu->sa[4 * r + sbyte];
+    h.fa0 = frag(cu.a + lo.a0, cu.a + lo.a1);
+    h.sa0 = cu.sa[lo.sa + sbyte];
   };
-  // Step s from head h (already in registers): A fragments 1..3 are read one group ahead; after
-  // the third group every LDS read of step s is done, so the wave waits for step s + 1's loads,
-  // meets the others at the barrier, refills stage s with step s + NS and reads step s + 1's head
-  // into hn while the last group of matrix-core products runs.
-  auto body = [&](int64_t s, Head& h, Head& hn) {
-    const Stage* cu = stage_ptr(s);
-    const int sbyte = (int)(((k0 + s * KS8) >> 5) & 3) + half;
+  // Step s (in stage k) from head h (already in registers): A fragments 1..3 are read one group
+  // ahead; after the third group every LDS read of step s is done, so the wave waits for step
+  // s + 1's loads (two steps' loads issued later may stay in flight), meets the others at the
+  // barrier, refills stage k with step s + NS and reads step s + 1's head into hn while the last
+  // group of matrix-core products runs. The step has no branch: the scheduling fences below only
+  // hold inside one basic block, and with branches in the step the compiler sinks its products
+  // below the waits and the barrier, leaving the matrix cores idle through them. At the last step
+  // the head read is of a stage that holds no later step; it is never used. The lane offsets are
+  // made opaque once per step, so that the compiler forms each address next to its read instead
+  // of keeping every stage's addresses live (which spills).
+  auto body = [&](auto k, int64_t s, Head& h, Head& hn) {
+    constexpr int K = decltype(k)::value;
+    const Stage& cu = stage(k);
+    LaneOffs lo = lo0;
+    asm volatile("" : "+v"(lo.a0), "+v"(lo.a1), "+v"(lo.b0), "+v"(lo.b1), "+v"(lo.sa), "+v"(lo.sb));
+    const int sbyte = (int)(((k0 + s * KS8) >> 5) & 3);
     i32x8 fa[2];
     int sav[2];
 #pragma unroll
     for (int i = 0; i < NB; ++i) {
+      // Group i's operands were requested a whole group earlier and have arrived; waiting for
+      // them here, before fragment i + 1 is requested, keeps the wait off the newer reads.
+      DFI_WAIT_LGKM0();
       if (i + 1 < NB) {
-        const int r = wr * WT + (i + 1) * 32 + l32;
-        fa[(i + 1) & 1] = read_frag(cu->a, r, half);
-        sav[(i + 1) & 1] = cu->sa[4 * r + sbyte];
+        fa[(i + 1) & 1] = frag(cu.a + lo.a0 + 32 * KS8 * (i + 1), cu.a + lo.a1 + 32 * KS8 * (i + 1));
+        sav[(i + 1) & 1] = cu.sa[lo.sa + 128 * (i + 1) + sbyte];
       }
       if (i == NB - 1) {
         asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
-        if (s + 1 < nsteps) {
-          const int64_t later = min<int64_t>(NS - 2, nsteps - 2 - s);
-          if (later >= 2) DFI_WAIT_VM(2 * LOADS_PER_STEP);
-          else if (later == 1) DFI_WAIT_VM(LOADS_PER_STEP);
-          else DFI_WAIT_VM(0);
-        }
+        DFI_WAIT_VM(2 * LOADS_PER_STEP);
         asm volatile("s_barrier" ::: "memory");
-        if (s + NS < nsteps) issue_step(s + NS);
-        if (s + 1 < nsteps) load_head(s + 1, hn);
+        issue_step(k, s + NS);
+        load_head(std::integral_constant<int, (K + 1) % NS>{}, s + 1, hn, lo);
       }
       __builtin_amdgcn_sched_barrier(0);
       const i32x8 a = (i == 0) ? h.fa0 : fa[i & 1];
@@ -732,23 +784,32 @@ gram_kernel_fp8(const uint8_t* __restrict__ q, const uint8_t* __restrict__ sc, i
       __builtin_amdgcn_sched_barrier(0);
     }
   };
+  using K0 = std::integral_constant<int, 0>;
+  using K1 = std::integral_constant<int, 1>;
+  using K2 = std::integral_constant<int, 2>;
+  using K3 = std::integral_constant<int, 3>;
+  static_assert(NS == 4, "the step loop is unrolled by the stage count");
   Head h0, h1;
-  const int64_t npro = min<int64_t>(NS, nsteps);
-  for (int64_t s0 = 0; s0 < npro; ++s0) issue_step(s0);
   if (nsteps > 0) {
-    if (npro >= 4) DFI_WAIT_VM(3 * LOADS_PER_STEP);
-    else if (npro == 3) DFI_WAIT_VM(2 * LOADS_PER_STEP);
-    else if (npro == 2) DFI_WAIT_VM(LOADS_PER_STEP);
-    else DFI_WAIT_VM(0);
+    issue_step(K0{}, 0);
+    issue_step(K1{}, 1);
+    issue_step(K2{}, 2);
+    issue_step(K3{}, 3);
+    DFI_WAIT_VM(3 * LOADS_PER_STEP);
     asm volatile("s_barrier" ::: "memory");
-    load_head(0, h0);
+    load_head(K0{}, 0, h0, lo0);
+    int64_t s = 0;
+    for (; s + 3 < nsteps; s += 4) {
+      body(K0{}, s, h0, h1);
+      body(K1{}, s + 1, h1, h0);
+      body(K2{}, s + 2, h0, h1);
+      body(K3{}, s + 3, h1, h0);
+    }
+    if (s < nsteps) body(K0{}, s, h0, h1);
+    if (s + 1 < nsteps) body(K1{}, s + 1, h1, h0);
+    if (s + 2 < nsteps) body(K2{}, s + 2, h0, h1);
+    DFI_WAIT_VM(0);   // the trailing refills land in LDS before the workgroup ends
   }
-  int64_t s = 0;
-  for (; s + 1 < nsteps; s += 2) {
-    body(s, h0, h1);
-    body(s + 1, h1, h0);
-  }
-  if (s < nsteps) body(s, h0, h1);
 
   float* out = part + (slice * ntri + tile) * (int64_t)(T * T);
 #pragma unroll
