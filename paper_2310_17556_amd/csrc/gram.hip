@@ -586,16 +586,18 @@ __device__ __forceinline__ void panel_offsets(int64_t n, int64_t row0, PanelOffs
 
 // The step at column kcol (a multiple of 64): 64 code bytes of each of the panel's rows and the
 // rows' scale words, direct to LDS. Every step lies inside [0, ldq), where the row pass wrote
-// zero codes past m, so there is nothing to mask.
-__device__ __forceinline__ void issue_panel(const uint8_t* q, const uint8_t* sc, int64_t n, int64_t kcol,
-                                            const PanelOffs& po, uint8_t* panel, uint8_t* sdst) {
-  const int wave = threadIdx.x >> 6;
+// zero codes past m, so there is nothing to mask. issue_codes moves the rows of wave instruction
+// i (16 rows x 64 B), issue_scales the scale words; a whole panel is i = 0 .. T / 16 / NW - 1
+// plus the scales.
+__device__ __forceinline__ void issue_codes(const uint8_t* q, int64_t n, int64_t kcol, const PanelOffs& po,
+                                            uint8_t* panel, int i) {
+  const int g = (int)(threadIdx.x >> 6) + NW * i;
   const uint8_t* qb = q + ((kcol >> 6) * n << 6);   // row 0 of this step's block, uniform
-#pragma unroll
-  for (int i = 0; i < T / 16 / NW; ++i) {
-    const int g = wave + NW * i;
-    __builtin_amdgcn_global_load_lds((const void*)(qb + po.code[i]), (lds_void*)(panel + 16 * g * KS8), 16, 0, 0);
-  }
+  __builtin_amdgcn_global_load_lds((const void*)(qb + po.code[i]), (lds_void*)(panel + 16 * g * KS8), 16, 0, 0);
+}
+__device__ __forceinline__ void issue_scales(const uint8_t* sc, int64_t n, int64_t kcol, const PanelOffs& po,
+                                             uint8_t* sdst) {
+  const int wave = threadIdx.x >> 6;
   const uint8_t* sb = sc + ((kcol >> 7) * n << 2);
   __builtin_amdgcn_global_load_lds((const void*)(sb + po.scale), (lds_void*)(sdst + 256 * wave), 4, 0, 0);
 }
@@ -688,11 +690,22 @@ gram_kernel_fp8(const uint8_t* __restrict__ q, const uint8_t* __restrict__ sc, i
   // Refill stage k with `step` (k = step mod NS). Steps past the slice's end load the slice's
   // last step again (never read as operands): every step then issues the same loads and waits
   // for the same count, with no branch in the loop.
-  auto issue_step = [&](auto k, int64_t step) {
+  // Piece p (0 .. NB - 1) of the refill: code instruction p of both panels, and with the last
+  // piece both panels' scale words. Diagonal tiles load their B panel too: uniform load counts.
+  static_assert(T / 16 / NW == NB, "one refill piece per product of a group");
+  auto issue_piece = [&](auto k, int64_t step, int p) {
     Stage& sp = stage(k);
     const int64_t kc = k0 + min(step, nsteps - 1) * KS8;
-    issue_panel(q, sc, n, kc, offA, sp.a, sp.sa);
-    issue_panel(q, sc, n, kc, offB, sp.b, sp.sb);   // diagonal tiles too: uniform load counts
+    issue_codes(q, n, kc, offA, sp.a, p);
+    issue_codes(q, n, kc, offB, sp.b, p);
+    if (p == NB - 1) {
+      issue_scales(sc, n, kc, offA, sp.sa);
+      issue_scales(sc, n, kc, offB, sp.sb);
+    }
+  };
+  auto issue_step = [&](auto k, int64_t step) {
+#pragma unroll
+    for (int p = 0; p < NB; ++p) issue_piece(k, step, p);
   };
   // this wave's operands of one step, read from LDS into registers
   // head of a step: the four B fragments with their scales and the first A fragment
@@ -744,7 +757,7 @@ gram_kernel_fp8(const uint8_t* __restrict__ q, const uint8_t* __restrict__ sc, i
   // Step s (in stage k) from head h (already in registers): A fragments 1..3 are read one group
   // ahead; after the third group every LDS read of step s is done, so the wave waits for step
   // s + 1's loads (two steps' loads issued later may stay in flight), meets the others at the
-  // barrier, refills stage k with step s + NS and reads step s + 1's head into hn while the last
+  // barrier, reads step s + 1's head into hn and refills stage k with step s + NS while the last
   // group of matrix-core products runs. The step has no branch: the scheduling fences below only
   // hold inside one basic block, and with branches in the step the compiler sinks its products
   // below the waits and the barrier, leaving the matrix cores idle through them. At the last step
@@ -772,15 +785,22 @@ gram_kernel_fp8(const uint8_t* __restrict__ q, const uint8_t* __restrict__ sc, i
         asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
         DFI_WAIT_VM(2 * LOADS_PER_STEP);
         asm volatile("s_barrier" ::: "memory");
-        issue_step(k, s + NS);
         load_head(std::integral_constant<int, (K + 1) % NS>{}, s + 1, hn, lo);
       }
       __builtin_amdgcn_sched_barrier(0);
       const i32x8 a = (i == 0) ? h.fa0 : fa[i & 1];
       const int sa = (i == 0) ? h.sa0 : sav[i & 1];
 #pragma unroll
-      for (int j = 0; j < NB; ++j)
+      for (int j = 0; j < NB; ++j) {
         acc[i][j] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(a, h.fb[j], acc[i][j], 0, 0, 0, sa, 0, h.sbv[j]);
+        if (i == NB - 1) {
+          // the refill of stage k goes out in pieces between the last group's products, whose
+          // execution hides the issue of its loads and their address arithmetic
+          __builtin_amdgcn_sched_barrier(0);
+          issue_piece(k, s + NS, j);
+          __builtin_amdgcn_sched_barrier(0);
+        }
+      }
       __builtin_amdgcn_sched_barrier(0);
     }
   };
@@ -889,8 +909,8 @@ __device__ __forceinline__ void panel_offsets(int64_t n, int64_t row0, PanelOffs
 
 // One plane of one panel for the step at column kcol (a multiple of 16): every step lies inside
 // [0, ldh), where the row pass wrote zeros past m, so nothing is masked.
-__device__ __forceinline__ void issue_plane(const uint16_t* __restrict__ plane, int64_t n, int64_t kcol,
-                                            const PanelOffs& po, uint8_t* panel) {
+__device__ __forceinline__ void issue_plane(const uint16_t* plane, int64_t n, int64_t kcol, const PanelOffs& po,
+                                            uint8_t* panel) {
   const uint16_t* pb = plane + ((kcol >> 4) * n << 4);   // row 0 of this step's block, uniform
   const int wave = threadIdx.x >> 6;
 #pragma unroll
@@ -898,10 +918,6 @@ __device__ __forceinline__ void issue_plane(const uint16_t* __restrict__ plane, 
     const int g = wave + NW * i;
     __builtin_amdgcn_global_load_lds((const void*)(pb + po.e[i]), (lds_void*)(panel + 32 * g * ROWB), 16, 0, 0);
   }
-}
-
-__device__ __forceinline__ bf16x8 read_bf(const uint8_t* panel, int r, int h) {
-  return *reinterpret_cast<const bf16x8*>(panel + r * ROWB + 16 * (h ^ ((r >> 2) & 1)));
 }
 
 // One wave's operands of one k-step: hi and lo fragments of its 4 A and 4 B row blocks.
@@ -932,18 +948,20 @@ gram_kernel_split(const uint16_t* __restrict__ hi, const uint16_t* __restrict__ 
   }
   const int64_t xcd = w & 7;
   const int64_t local = w >> 3;
-  const int64_t qq = local / ntri;
+  const int64_t qq = uni64(local / ntri);
   const int64_t tile = local - qq * ntri;
   const int64_t slice = xcd * (nslice >> 3) + qq;
   const uint32_t bflip = (slice & 1) ? 0x80008000u : 0u;
 
   int64_t ti, tj;
   tri_index(tile, ti, tj);
+  ti = uni64(ti);
+  tj = uni64(tj);
   const bool diag = (ti == tj);
   const int64_t rowA = ti * T, rowB = tj * T;
-  const int64_t k0 = slice * kslice;
+  const int64_t k0 = uni64(slice * kslice);
   const int64_t kend = min(kcap, k0 + kslice);
-  const int64_t nsteps = (kend > k0) ? (kend - k0) / KSB : 0;   // both multiples of 16
+  const int64_t nsteps = uni64((kend > k0) ? (kend - k0) / KSB : 0);   // both multiples of 16
 
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
@@ -960,86 +978,121 @@ gram_kernel_split(const uint16_t* __restrict__ hi, const uint16_t* __restrict__ 
 #pragma unroll
       for (int e = 0; e < 16; ++e) acc[i][j][e] = 0.f;
 
-  auto stage_ptr = [&](int64_t idx) -> Stage* {
-    switch (idx & 3) {
-      case 0: return &stg0;
-      case 1: return &stg1;
-      case 2: return &stg2;
-      default: return &stg3;
-    }
+  // Stage k of the ring, k a compile-time constant (see the scaled-FP8 kernel: the loop is unrolled
+  // by NS so that every LDS access names its stage object).
+  auto stage = [&](auto k) -> Stage& {
+    constexpr int K = decltype(k)::value;
+    if constexpr (K == 0) return stg0;
+    else if constexpr (K == 1) return stg1;
+    else if constexpr (K == 2) return stg2;
+    else return stg3;
   };
   PanelOffs offA, offB;
   panel_offsets(n, rowA, offA);
   panel_offsets(n, rowB, offB);
-  auto issue_step = [&](int64_t step) {
-    Stage* sp = stage_ptr(step);
-    const int64_t kc = k0 + step * KSB;
-    issue_plane(hi, n, kc, offA, sp->ah);
-    issue_plane(lo, n, kc, offA, sp->al);
-    issue_plane(hi, n, kc, offB, sp->bh);   // diagonal tiles too: uniform load counts
-    issue_plane(lo, n, kc, offB, sp->bl);
+  // Piece p of the refill of stage k with `step` (k = step mod NS): plane p of the four (A hi, A lo,
+  // B hi, B lo; diagonal tiles load B too: uniform load counts). Steps past the slice's end load
+  // the slice's last step again (never read as operands), so every step issues the same loads.
+  auto issue_piece = [&](auto k, int64_t step, int p) {
+    Stage& sp = stage(k);
+    const int64_t kc = k0 + min(step, nsteps - 1) * KSB;
+    if (p == 0) issue_plane(hi, n, kc, offA, sp.ah);
+    else if (p == 1) issue_plane(lo, n, kc, offA, sp.al);
+    else if (p == 2) issue_plane(hi, n, kc, offB, sp.bh);
+    else issue_plane(lo, n, kc, offB, sp.bl);
   };
-  auto load_frags = [&](int64_t step, Frags& f) {
-    const Stage* cu = stage_ptr(step);
+  auto issue_step = [&](auto k, int64_t step) {
+#pragma unroll
+    for (int p = 0; p < 4; ++p) issue_piece(k, step, p);
+  };
+  // Per-lane LDS byte offsets of fragment 0 of the wave's A and B rows inside a plane; fragment i
+  // is 32 rows further on (+ 32 i ROWB), with the same swizzle ((row >> 2) & 1 depends on l32 only).
+  int oA0, oB0;
+  {
+    const int sw = (l32 >> 2) & 1;
+    oA0 = (wr * WT + l32) * ROWB + 16 * (half ^ sw);
+    oB0 = (wc * WT + l32) * ROWB + 16 * (half ^ sw);
+  }
+  auto rd = [](const uint8_t* p) { return *reinterpret_cast<const bf16x8*>(p); };
+  auto load_frags = [&](auto k, Frags& f, int oA, int oB) {
+    const Stage& cu = stage(k);
 #pragma unroll
     for (int j = 0; j < NB; ++j) {
-      const int r = wc * WT + j * 32 + l32;
-      f.bh[j] = read_bf(cu->bh, r, half);
-      f.bl[j] = read_bf(cu->bl, r, half);
+      f.bh[j] = rd(cu.bh + oB + 32 * ROWB * j);
+      f.bl[j] = rd(cu.bl + oB + 32 * ROWB * j);
     }
 #pragma unroll
     for (int i = 0; i < NB; ++i) {
-      const int r = wr * WT + i * 32 + l32;
-      f.ah[i] = read_bf(cu->ah, r, half);
-      f.al[i] = read_bf(cu->al, r, half);
+      f.ah[i] = rd(cu.ah + oA + 32 * ROWB * i);
+      f.al[i] = rd(cu.al + oA + 32 * ROWB * i);
     }
   };
-  auto mfma_step = [&](const Frags& f) {
-#pragma unroll
-    for (int i = 0; i < NB; ++i) {
-      const bf16x8 ah = flip_sign(f.ah[i], bflip);
-      const bf16x8 al = flip_sign(f.al[i], bflip);
-#pragma unroll
-      for (int j = 0; j < NB; ++j) {
-        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, f.bh[j], acc[i][j], 0, 0, 0);
-        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, f.bl[j], acc[i][j], 0, 0, 0);
-        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, f.bh[j], acc[i][j], 0, 0, 0);
-      }
-    }
+  // term t of the product of A row block i with B row block j: lo.hi, hi.lo, hi.hi in that order
+  auto mfma_term = [&](const Frags& f, int i, int j, int t) {
+    const bf16x8 a = flip_sign(t == 0 ? f.al[i] : f.ah[i], bflip);
+    const bf16x8 b = t == 1 ? f.bl[j] : f.bh[j];
+    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc[i][j], 0, 0, 0);
   };
-  // Same schedule as the scaled-FP8 kernel: step s + 1's operands are read into the spare register
-  // set while step s's products run; stage s is refilled with step s + NS after the barrier.
-  auto body = [&](int64_t s, Frags& cur, Frags& nxt) {
+  // Step s (stage k) from operands cur (already in registers): the products of A row blocks
+  // 0 .. NB - 2 run first; then the wave waits for step s + 1's loads (two later steps' loads may
+  // stay in flight), meets the others at the barrier (every wave has read stage k, which it did
+  // into cur one step earlier), reads step s + 1's operands into nxt and refills stage k with step
+  // s + NS between the last row block's products. The step has no branch, so the
+  // scheduling fences hold and the products overlap the waits.
+  auto body = [&](auto k, Frags& cur, Frags& nxt, int64_t s) {
+    constexpr int K = decltype(k)::value;
+    int oA = oA0, oB = oB0;
+    asm volatile("" : "+v"(oA), "+v"(oB));
+#pragma unroll
+    for (int i = 0; i < NB - 1; ++i)
+#pragma unroll
+      for (int j = 0; j < NB; ++j)
+#pragma unroll
+        for (int t = 0; t < 3; ++t) mfma_term(cur, i, j, t);
+    __builtin_amdgcn_sched_barrier(0);
     asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
-    if (s + 1 < nsteps) {
-      const int64_t later = min<int64_t>(NS - 2, nsteps - 2 - s);
-      if (later >= 2) DFI_WAIT_VM(2 * LOADS_PER_STEP);
-      else if (later == 1) DFI_WAIT_VM(LOADS_PER_STEP);
-      else DFI_WAIT_VM(0);
+    DFI_WAIT_VM(2 * LOADS_PER_STEP);
+    asm volatile("s_barrier" ::: "memory");
+    load_frags(std::integral_constant<int, (K + 1) % NS>{}, nxt, oA, oB);
+    __builtin_amdgcn_sched_barrier(0);
+    // the last row block term by term (four independent accumulators between fences), with the
+    // refill's planes 0 and 1, 2, 3 after the three terms
+#pragma unroll
+    for (int t = 0; t < 3; ++t) {
+#pragma unroll
+      for (int j = 0; j < NB; ++j) mfma_term(cur, NB - 1, j, t);
+      __builtin_amdgcn_sched_barrier(0);
+      if (t == 0) issue_piece(k, s + NS, 0);
+      issue_piece(k, s + NS, t + 1);
+      __builtin_amdgcn_sched_barrier(0);
     }
-    asm volatile("s_barrier" ::: "memory");
-    if (s + NS < nsteps) issue_step(s + NS);
-    if (s + 1 < nsteps) load_frags(s + 1, nxt);
-    mfma_step(cur);
   };
-
+  using K0 = std::integral_constant<int, 0>;
+  using K1 = std::integral_constant<int, 1>;
+  using K2 = std::integral_constant<int, 2>;
+  using K3 = std::integral_constant<int, 3>;
+  static_assert(NS == 4 && NB == 4, "the step loop is unrolled by the stage count");
   Frags f0, f1;
-  const int64_t npro = min<int64_t>(NS, nsteps);
-  for (int64_t s0 = 0; s0 < npro; ++s0) issue_step(s0);
   if (nsteps > 0) {
-    if (npro >= 4) DFI_WAIT_VM(3 * LOADS_PER_STEP);
-    else if (npro == 3) DFI_WAIT_VM(2 * LOADS_PER_STEP);
-    else if (npro == 2) DFI_WAIT_VM(LOADS_PER_STEP);
-    else DFI_WAIT_VM(0);
+    issue_step(K0{}, 0);
+    issue_step(K1{}, 1);
+    issue_step(K2{}, 2);
+    issue_step(K3{}, 3);
+    DFI_WAIT_VM(3 * LOADS_PER_STEP);
     asm volatile("s_barrier" ::: "memory");
-    load_frags(0, f0);
+    load_frags(K0{}, f0, oA0, oB0);
+    int64_t s = 0;
+    for (; s + 3 < nsteps; s += 4) {
+      body(K0{}, f0, f1, s);
+      body(K1{}, f1, f0, s + 1);
+      body(K2{}, f0, f1, s + 2);
+      body(K3{}, f1, f0, s + 3);
+    }
+    if (s < nsteps) body(K0{}, f0, f1, s);
+    if (s + 1 < nsteps) body(K1{}, f1, f0, s + 1);
+    if (s + 2 < nsteps) body(K2{}, f0, f1, s + 2);
+    DFI_WAIT_VM(0);   // the trailing refills land in LDS before the workgroup ends
   }
-  int64_t s = 0;
-  for (; s + 1 < nsteps; s += 2) {
-    body(s, f0, f1);
-    body(s + 1, f1, f0);
-  }
-  if (s < nsteps) body(s, f0, f1);
 
   const float sgn = (slice & 1) ? -1.f : 1.f;
   float* out = part + (slice * ntri + tile) * (int64_t)(T * T);
