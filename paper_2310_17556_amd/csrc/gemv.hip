@@ -434,9 +434,9 @@ rowpass_prep_kernel(const float* __restrict__ S, int64_t n, int64_t m, int64_t l
 // rows per load, lane 4 r + q holding columns 4 q .. 4 q + 3 of row r), forms t_c = sum_i S_ic y_i
 // for the block's columns (FP64 products and sums, reduced over the 16 lanes of a column and then
 // over the waves in fixed order through LDS), and adds S_ic t_c to per-lane FP64 row accumulators.
-// In each round the grid takes the next ngroups consecutive blocks; with ngroups a multiple of 8,
-// the workgroups of one XCD (w mod 8, in dispatch order) take a contiguous run of them, so the two
-// halves of each 128-byte line of a row are read through the same L2 at about the same time. At
+// Two workgroups of one XCD (w mod 8, in dispatch order) walk a contiguous region of blocks side
+// by side, so the two halves of each 128-byte line of a row are read through the same L2 at about
+// the same time, and the regions of the pairs spread the reads in flight over the row. At
 // the end each row's accumulators are reduced over its 4 lanes and stored as one partial per
 // workgroup, part[g * n + i], which rowpass_reduce_kernel adds in fixed order. NCH loads per lane
 // cover n <= 16 FR_WAVES NCH rows. Only whole 16-column blocks are streamed here.
@@ -466,10 +466,20 @@ refine_pass_kernel(const float* __restrict__ S, int64_t n, int64_t m, int64_t ld
   const int64_t nblk = m / FR_COLS;   // full blocks; the m % 16 last columns go to refine_tail_kernel
   // addresses: wave-uniform base + a 32-bit lane offset (the plan checks 16 lds * 4 < 2^31)
   const uint32_t loff = (uint32_t)(((lane >> 2) * lds + 4 * q) * 4);
-  // Block of this workgroup in round s: s G + x (G / 8) + l for workgroup w = 8 l + x (G = grid).
+  // Block of this workgroup in round s. Workgroup w = 8 l + x (x = its XCD, G = grid) has slot
+  // x (G / 8) + l; slots 2 p and 2 p + 1 (one XCD when G / 8 is even) form pair p, which walks its
+  // own contiguous region of R blocks two at a time: the two halves of each 128-byte line go
+  // through one L2 at about the same time, and the pairs' regions spread the reads in flight over
+  // the whole row. (With every workgroup on consecutive blocks, the reads in flight would all lie
+  // in one 16 KB window of columns, rows a large power of two apart in the usual layout: the same
+  // low address bits everywhere, which is hard on the HBM channel interleave.) Other grids take
+  // blocks s G + slot.
   const int64_t G = gridDim.x;
   const int64_t slot = (G & 7) == 0 ? (int64_t)(blockIdx.x & 7) * (G >> 3) + (blockIdx.x >> 3) : (int64_t)blockIdx.x;
-  auto block_of = [&](int64_t s) { return s * G + slot; };
+  const bool paired = (G & 15) == 0;
+  const int64_t R = paired ? 2 * ((nblk + G - 1) / G) : 0;
+  auto block_of = [&](int64_t s) { return paired ? (slot >> 1) * R + 2 * s + (slot & 1) : s * G + slot; };
+  auto valid = [&](int64_t s) { return (!paired || 2 * s + (slot & 1) < R) && block_of(s) < nblk; };
   // Load c of a block: rows c ROWS + 16 wave .. + 15, as a buffer load from a wave-uniform base
   // (the block's first column in row c ROWS + 16 wave) with the 32-bit lane offset. The buffer's
   // records end at row n, so rows past n read zeros; for a wave whose rows of this load all lie
@@ -495,7 +505,7 @@ refine_pass_kernel(const float* __restrict__ S, int64_t n, int64_t m, int64_t ld
   // streams while the matrix of one block is reduced and applied.
   f32x4 sv[NCH];
   int64_t s = 0;
-  bool more = block_of(0) < nblk;   // uniform
+  bool more = valid(0);   // uniform
   if (more) {
 #pragma unroll
     for (int c = 0; c < NCH; ++c) sv[c] = load(block_of(0), c, true);
@@ -503,7 +513,7 @@ refine_pass_kernel(const float* __restrict__ S, int64_t n, int64_t m, int64_t ld
   // a do-while with the test at the bottom: no copies of the loop-carried accumulators
   if (more) do {
     const int64_t nxt = block_of(s + 1);
-    more = nxt < nblk;
+    more = valid(s + 1);
     asm volatile("" : "+s"(nrows));
     double tq[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
