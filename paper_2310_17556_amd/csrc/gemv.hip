@@ -442,6 +442,7 @@ rowpass_prep_kernel(const float* __restrict__ S, int64_t n, int64_t m, int64_t l
 // cover n <= 16 FR_WAVES NCH rows. Only whole 16-column blocks are streamed here.
 constexpr int FR_COLS = 16;
 constexpr int FR_WAVES = 8;    // 2 waves per SIMD: 256 registers per lane for 32 loads in flight
+constexpr int FR_GROUP = 2;    // workgroups (of one XCD) walking adjacent blocks side by side
 
 template <int NCH>
 __global__ void __launch_bounds__(64 * FR_WAVES)
@@ -476,10 +477,11 @@ refine_pass_kernel(const float* __restrict__ S, int64_t n, int64_t m, int64_t ld
   // blocks s G + slot.
   const int64_t G = gridDim.x;
   const int64_t slot = (G & 7) == 0 ? (int64_t)(blockIdx.x & 7) * (G >> 3) + (blockIdx.x >> 3) : (int64_t)blockIdx.x;
-  const bool paired = (G & 15) == 0;
-  const int64_t R = paired ? 2 * ((nblk + G - 1) / G) : 0;
-  auto block_of = [&](int64_t s) { return paired ? (slot >> 1) * R + 2 * s + (slot & 1) : s * G + slot; };
-  auto valid = [&](int64_t s) { return (!paired || 2 * s + (slot & 1) < R) && block_of(s) < nblk; };
+  const bool grouped = (G % (8 * FR_GROUP)) == 0;
+  const int64_t R = grouped ? FR_GROUP * ((nblk + G - 1) / G) : 0;
+  const int64_t grp = slot / FR_GROUP, mem = slot % FR_GROUP;
+  auto block_of = [&](int64_t s) { return grouped ? grp * R + FR_GROUP * s + mem : s * G + slot; };
+  auto valid = [&](int64_t s) { return (!grouped || FR_GROUP * s + mem < R) && block_of(s) < nblk; };
   // Load c of a block: rows c ROWS + 16 wave .. + 15, as a buffer load from a wave-uniform base
   // (the block's first column in row c ROWS + 16 wave) with the 32-bit lane offset. The buffer's
   // records end at row n, so rows past n read zeros; for a wave whose rows of this load all lie
