@@ -210,7 +210,7 @@ DFISHER_API dfisher_status dfisher_factor_destroy(dfisher_factor* f);
  * holds x_{l,r} solving (S^T S + lambda_l I) x = v_r. infos (host, may be NULL) has nlam
  * entries. Algorithm 1 for every pair, with step 1 shared: the Gram G = S S^T is formed once,
  * the nlam Cholesky factorisations of G + lambda_l I run in the same launches, and S V, the
- * refinement residuals and x = (v - S^T y) / lambda run as passes over S that serve 8 vectors
+ * refinement residuals and x = (v - S^T y) / lambda run as passes over S that serve 16 vectors
  * each. Needs nlam * nrhs <= 65535 (else DFISHER_E_UNSUPPORTED). A factorisation that fails
  * under DFISHER_SHIFT_NONE makes the call return DFISHER_E_NOT_SPD; the x of that lambda is then
  * unspecified. Synchronises the stream once to read the factorisation statuses. */

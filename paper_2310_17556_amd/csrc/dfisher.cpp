@@ -420,7 +420,7 @@ dfisher_status multi_solve(const float* S, int64_t n, int64_t m, int64_t lds, in
   constexpr int MV = dfi::MULTI_VECS;
   const int64_t nvec = nfac * nrhs;
   const int64_t sL = n * n;
-  // B_r = S v_r, eight right-hand sides per pass over S
+  // B_r = S v_r, MV right-hand sides per pass over S
   for (int64_t r0 = 0; r0 < nrhs; r0 += MV) {
     const int nv = (int)std::min<int64_t>(MV, nrhs - r0);
     dfi::MultiVecs vs{};
@@ -438,7 +438,7 @@ dfisher_status multi_solve(const float* S, int64_t n, int64_t m, int64_t lds, in
   HIP_TRY(dfi::trsv_launch_batched(L, sL, Dinv, n, nvec, nrhs, 0, b.Bexp, b.D, b.W1, st));
   HIP_TRY(dfi::trsv_launch_batched(L, sL, Dinv, n, nvec, nrhs, 1, b.D, b.Y, b.W1, st));
   for (int s = 0; s < sweeps; ++s) {
-    // R = B - lambda Y - S (S^T Y), eight vectors per pair of passes
+    // R = B - lambda Y - S (S^T Y), MV vectors per pair of passes
     for (int64_t j0 = 0; j0 < nvec; j0 += MV) {
       const int nv = (int)std::min<int64_t>(MV, nvec - j0);
       dfi::MultiCols mc{};
@@ -460,7 +460,7 @@ dfisher_status multi_solve(const float* S, int64_t n, int64_t m, int64_t lds, in
     HIP_TRY(dfi::trsv_launch_batched(L, sL, Dinv, n, nvec, nrhs, 1, b.D, b.R, b.W1, st));
     HIP_TRY(dfi::axpy_many(b.Y, b.R, nvec * n, st));
   }
-  // x = (v - S^T y) / lambda, eight vectors per pass
+  // x = (v - S^T y) / lambda, MV vectors per pass
   const size_t xel = x_fp64 ? sizeof(double) : sizeof(float);
   for (int64_t j0 = 0; j0 < nvec; j0 += MV) {
     const int nv = (int)std::min<int64_t>(MV, nvec - j0);

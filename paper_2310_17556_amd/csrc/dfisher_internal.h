@@ -124,7 +124,7 @@ hipError_t refine_pass_reduce(const RefinePassPlan& p, const double* part, doubl
 
 // ----------------------------------------------------------------------------- multi-vector passes
 // One pass over S for up to MULTI_VECS vectors (batched right-hand sides / damping values).
-constexpr int MULTI_VECS = 8;
+constexpr int MULTI_VECS = 16;
 struct MultiVecs {                 // FP32 input vectors of length m (row pass)
   const float* f[MULTI_VECS];
 };
@@ -147,12 +147,12 @@ struct RowMultiPlan {
 };
 RowMultiPlan rowmulti_plan(int64_t n, int64_t m, int64_t lds);
 // part <- per-group partials of S V_c, c < nv. V_c = vs.f[c] (FP32) or, with T != nullptr, the FP64
-// interleaved T[k * 8 + c] written by colpass_multi_launch mode 2.
+// interleaved T[k * MULTI_VECS + c] written by colpass_multi_launch mode 2.
 hipError_t rowpass_multi_launch(const RowMultiPlan& p, const float* S, const MultiVecs& vs, const double* T, int nv,
                                 double* part, hipStream_t st);
 hipError_t rowpass_multi_reduce(const RowMultiPlan& p, const double* part, int nv, const MultiOut& out,
                                 hipStream_t st);
-// t_c = S^T y_c (c < nc). mode 2: T[k * 8 + c] = t_c[k] (T: m * 8 doubles); mode 0 / 1:
+// t_c = S^T y_c (c < nc). mode 2: T[k * MULTI_VECS + c] = t_c[k] (T: m * MULTI_VECS doubles); mode 0 / 1:
 // x_c = (v_c - t_c) / lam_c as FP32 / FP64.
 hipError_t colpass_multi_launch(const float* S, int64_t n, int64_t m, int64_t lds, const MultiCols& mc, int nc,
                                 int mode, double* T, hipStream_t st);

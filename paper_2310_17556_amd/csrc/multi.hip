@@ -1,16 +1,16 @@
 // Multi-vector streaming passes over S for many right-hand sides and damping values that share
 // one S: the batched form of the right-to-left evaluation x = (v - S^T L^-T L^-1 S v) / lambda
-// (Section 2), where one HBM pass over S serves up to MV = 8 vectors instead of one.
+// (Section 2), where one HBM pass over S serves up to MV = 16 vectors instead of one.
 //
-// Row pass  B_c = S V_c for c < nv. A wave owns 4 rows and a group of columns; per 256-column step
-//           each lane loads 4 columns of every vector once and reuses them for its 4 rows, with
-//           one FP64 accumulator per (row, vector). Vectors are FP32 (separate arrays, the
-//           caller's right-hand sides) or FP64 interleaved T[k * 8 + c] (the column pass output).
+// Row pass  B_c = S V_c for c < nv. A workgroup owns 32 rows (4 per wave) and a group of
+//           columns; per 256-column step the vectors' entries are staged once in LDS as FP64 and
+//           each lane reuses its 4 columns of every vector for its 4 rows, with one FP64
+//           accumulator per (row, vector). Vectors are FP32 (separate arrays, the caller's
+//           right-hand sides) or FP64 interleaved T[k * MV + c] (the column pass output).
 //           FP64 partials per (column group, vector, row) are added in fixed order by a second
-//           kernel, which can also form refinement residuals r = b - lambda y - S t. With the
-//           FP64 vectors T the 8 waves of a workgroup share each step of T through LDS.
+//           kernel, which can also form refinement residuals r = b - lambda y - S t.
 // Column pass t_c = S^T y_c for c < nc. A workgroup owns 1024 consecutive columns (4 per lane)
-//           and walks all rows; y_c[i] is wave-uniform. Output either T[k * 8 + c] (FP64) or
+//           and walks all rows; y_c[i] is wave-uniform. Output either T[k * MV + c] (FP64) or
 //           x_c = (v_c - t_c) / lambda_c (FP32 or FP64), each column with its own v, x, lambda.
 // Products of FP32 and FP64 values are formed and accumulated in FP64.
 #include "dfisher_internal.h"
@@ -23,9 +23,7 @@ namespace {
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef double f64x2 __attribute__((ext_vector_type(2)));
 
-constexpr int MV = MULTI_VECS;   // 8
-constexpr int RM_WAVES = 4;
-constexpr int RM_RPW = 4;        // rows per wave
+constexpr int MV = MULTI_VECS;   // 16
 constexpr int RM_STEP = 256;     // columns per wave step (4 per lane)
 
 __device__ __forceinline__ double wave_sum(double x) {
@@ -43,75 +41,25 @@ __device__ __forceinline__ void load_s4(const float* __restrict__ p, int64_t col
   }
 }
 
-// Grid: x = row blocks of RM_WAVES * RM_RPW rows, y = column groups of cg columns. Vector c is
-// vs.f[c] (FP32, contiguous). part[(g * MV + c) * n + i] = sum over group g of S_ik V_c[k].
-__global__ void __launch_bounds__(64 * RM_WAVES)
-rowpass_multi_kernel(const float* __restrict__ S, int64_t n, int64_t m, int64_t lds, MultiVecs vs, int nv,
-                     int64_t cg, double* __restrict__ part, int vec) {
-  const int lane = threadIdx.x & 63;
-  const int wave = threadIdx.x >> 6;
-  const int64_t row0 = ((int64_t)blockIdx.x * RM_WAVES + wave) * RM_RPW;
-  const int64_t g = blockIdx.y;
-  const int64_t c0 = g * cg;
-  const int64_t c1 = min(m, c0 + cg);
-  if (row0 >= n) return;
-  const int nr = (int)min<int64_t>(RM_RPW, n - row0);
-
-  double acc[RM_RPW][MV];
-#pragma unroll
-  for (int r = 0; r < RM_RPW; ++r)
-#pragma unroll
-    for (int c = 0; c < MV; ++c) acc[r][c] = 0.0;
-
-  for (int64_t cs = c0; cs < c1; cs += RM_STEP) {
-    const int64_t col = cs + 4 * lane;
-    double vv[4][MV];
-#pragma unroll
-    for (int c = 0; c < MV; ++c) {
-      f32x4 t4 = {0.f, 0.f, 0.f, 0.f};
-      if (c < nv) load_s4(vs.f[c] + col, col, c1, (vec & 2) != 0, t4);
-#pragma unroll
-      for (int e = 0; e < 4; ++e) vv[e][c] = (double)t4[e];
-    }
-    f32x4 sv[RM_RPW];
-#pragma unroll
-    for (int r = 0; r < RM_RPW; ++r) {
-      sv[r] = (f32x4){0.f, 0.f, 0.f, 0.f};
-      if (r < nr) load_s4(S + (row0 + r) * lds + col, col, c1, (vec & 1) != 0, sv[r]);
-    }
-#pragma unroll
-    for (int r = 0; r < RM_RPW; ++r)
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const double s = (double)sv[r][e];
-#pragma unroll
-        for (int c = 0; c < MV; ++c) acc[r][c] = fma(s, vv[e][c], acc[r][c]);
-      }
-  }
-#pragma unroll
-  for (int r = 0; r < RM_RPW; ++r) {
-    if (r >= nr) continue;
-#pragma unroll
-    for (int c = 0; c < MV; ++c) {
-      const double t = wave_sum(acc[r][c]);
-      if (lane == 0 && c < nv) part[(g * MV + c) * n + row0 + r] = t;
-    }
-  }
-}
-
-// Row pass with the FP64 interleaved vectors T[k * 8 + c] (the refinement's S t_c): the same
-// products and partials as rowpass_multi_kernel with T[k * 8 + c] as vector c, but the workgroup's
-// RT_WAVES waves (64 rows) share each 256-column step of T through LDS (16 KB, double-buffered), so
-// T is read from memory once per 64 rows of S instead of once per 4. In LDS each lane's 4 columns x 8 vectors (256 bytes)
-// are padded by 16 bytes, so the 16-byte fragment reads of 16 consecutive lanes cover all banks.
+// Row pass B_c = S V_c for c < nv, the vectors either FP64 interleaved, T[k * MV + c] (the
+// refinement's S t_c, from the column pass), or FP32 arrays vs.f[c] (the caller's right-hand
+// sides). Grid: x = blocks of RT_ROWS rows, y = column groups of cg columns; part[(g * MV + c) * n
+// + i] = sum over group g of S_ik V_c[k]. The workgroup's RT_WAVES waves (32 rows) share each
+// 256-column step of the vectors through LDS, widened to FP64 (32 KB, double-buffered), so the
+// vectors are read once per 32 rows of S instead of once per wave. In LDS each lane's 4 columns
+// x 16 vectors (512 bytes) are padded by 16 bytes, so the 16-byte fragment reads of 16
+// consecutive lanes cover all banks. Four rows per wave: the 4 x 16 FP64 accumulators take 128
+// registers per lane.
 constexpr int RT_WAVES = 8;
-constexpr int RT_RPW = 8;                    // rows per wave
-constexpr int RT_ROWS = RT_WAVES * RT_RPW;   // 64 rows per workgroup
-constexpr int RT_GROUP = 4 * MV + 2;         // doubles per lane group (4 columns x 8 vectors + pad)
+constexpr int RT_RPW = 4;                    // rows per wave
+constexpr int RT_ROWS = RT_WAVES * RT_RPW;   // 32 rows per workgroup
+constexpr int RT_GROUP = 4 * MV + 2;         // doubles per lane group (4 columns x MV vectors + pad)
+constexpr int RT_PIECES = 256 * MV / (2 * 64 * RT_WAVES);   // 16-byte pieces of T per thread and step
 
+template <bool FP32V>
 __global__ void __launch_bounds__(64 * RT_WAVES)
 rowpass_multi_t_kernel(const float* __restrict__ S, int64_t n, int64_t m, int64_t lds, const double* __restrict__ T,
-                       int nv, int64_t cg, double* __restrict__ part, int vec) {
+                       MultiVecs vs, int nv, int64_t cg, double* __restrict__ part, int vec) {
   __shared__ __attribute__((aligned(16))) double tl[2][64 * RT_GROUP];
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -129,27 +77,80 @@ rowpass_multi_t_kernel(const float* __restrict__ S, int64_t n, int64_t m, int64_
 #pragma unroll
     for (int c = 0; c < MV; ++c) acc[r][c] = 0.0;
 
-  int buf = 0;
-  for (int64_t cs = c0; cs < c1; cs += RM_STEP, buf ^= 1) {
-    // T[cs .. cs + 256) x 8 vectors: 2048 doubles, two 16-byte pieces per thread (zero past c1)
+  // This thread's share of one step of the vectors, loaded into registers: FP32V, vector tid / 32
+  // and 8 consecutive columns (two 16-byte loads, zero past c1 and for vectors c >= nv); else
+  // RT_PIECES 16-byte pieces of T[cs .. cs + 256) x MV (zero past c1).
+  static_assert(!FP32V || 64 * RT_WAVES == 32 * MV, "one vector per 32 threads");
+  struct VecShare {
+    f32x4 f[2];
+    f64x2 t[RT_PIECES];
+  };
+  auto load_vecs = [&](int64_t cs, VecShare& vsh) {
+    if constexpr (FP32V) {
+      const int c = tid >> 5;
+      const int cl0 = (tid & 31) * 8;
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int idx = 2 * (h * 64 * RT_WAVES + tid);   // double index in the step: column idx / 8, vector idx % 8
-      const int cl = idx / MV;
-      f64x2 t2 = {0.0, 0.0};
-      if (cs + cl < c1) t2 = *reinterpret_cast<const f64x2*>(T + cs * MV + idx);
-      *reinterpret_cast<f64x2*>(&tl[buf][(cl >> 2) * RT_GROUP + (cl & 3) * MV + (idx % MV)]) = t2;
+      for (int h = 0; h < 2; ++h) {
+        const int cl = cl0 + 4 * h;
+        vsh.f[h] = (f32x4){0.f, 0.f, 0.f, 0.f};
+        if (c < nv) load_s4(vs.f[c] + cs + cl, cs + cl, c1, (vec & 2) != 0, vsh.f[h]);
+      }
+    } else {
+#pragma unroll
+      for (int h = 0; h < RT_PIECES; ++h) {
+        const int idx = 2 * (h * 64 * RT_WAVES + tid);   // double index in the step: column idx / MV, vector idx % MV
+        vsh.t[h] = (f64x2){0.0, 0.0};
+        if (cs + idx / MV < c1) vsh.t[h] = *reinterpret_cast<const f64x2*>(T + cs * MV + idx);
+      }
     }
-    __syncthreads();   // the other buffer is rewritten only after the next step's barrier
+  };
+  // ... and stored to LDS, widened to FP64, in the layout the products read
+  auto store_vecs = [&](const VecShare& vsh, double* tb) {
+    if constexpr (FP32V) {
+      const int c = tid >> 5;
+      const int cl0 = (tid & 31) * 8;
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) tb[((cl0 + 4 * h) >> 2) * RT_GROUP + e * MV + c] = (double)vsh.f[h][e];
+    } else {
+#pragma unroll
+      for (int h = 0; h < RT_PIECES; ++h) {
+        const int idx = 2 * (h * 64 * RT_WAVES + tid);
+        const int cl = idx / MV;
+        *reinterpret_cast<f64x2*>(&tb[(cl >> 2) * RT_GROUP + (cl & 3) * MV + (idx % MV)]) = vsh.t[h];
+      }
+    }
+  };
+  auto load_rows = [&](int64_t cs, f32x4* sv) {
     const int64_t col = cs + 4 * lane;
-    f32x4 sv[RT_RPW];
 #pragma unroll
     for (int r = 0; r < RT_RPW; ++r) {
       sv[r] = (f32x4){0.f, 0.f, 0.f, 0.f};
       if (r < nr) load_s4(S + (row0 + r) * lds + col, col, c1, (vec & 1) != 0, sv[r]);
     }
+  };
+  // Software pipeline: step cs + 256's rows of S and share of the vectors are loaded into
+  // registers while step cs's products run, so each step's loads have a whole step to arrive.
+  VecShare vn;
+  f32x4 sn[RT_RPW];
+  if (c0 < c1) {
+    load_vecs(c0, vn);
+    load_rows(c0, sn);
+  }
+  int buf = 0;
+  for (int64_t cs = c0; cs < c1; cs += RM_STEP, buf ^= 1) {
+    store_vecs(vn, tl[buf]);
+    __syncthreads();   // the other buffer is rewritten only after the next step's barrier
+    f32x4 sv[RT_RPW];
+#pragma unroll
+    for (int r = 0; r < RT_RPW; ++r) sv[r] = sn[r];
+    if (cs + RM_STEP < c1) {
+      load_vecs(cs + RM_STEP, vn);
+      load_rows(cs + RM_STEP, sn);
+    }
     const double* tg = &tl[buf][lane * RT_GROUP];
-    // one column at a time: its 8 vector entries are live only while its products are formed
+    // one column at a time: its MV vector entries are live only while its products are formed
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
       double vv[MV];
@@ -196,7 +197,7 @@ constexpr int CM_THREADS = 256;
 constexpr int CM_COLS = 4 * CM_THREADS;
 constexpr int CM_UNROLL = 4;
 
-// MODE 2: T[k * 8 + c] = t_c[k]; MODE 0 / 1: x_c[k] = (v_c[k] - t_c[k]) / lam_c as FP32 / FP64.
+// MODE 2: T[k * MV + c] = t_c[k]; MODE 0 / 1: x_c[k] = (v_c[k] - t_c[k]) / lam_c as FP32 / FP64.
 // Vectors c >= nc are computed from y_0 and discarded.
 template <int MODE>
 __global__ void __launch_bounds__(CM_THREADS)
@@ -237,20 +238,32 @@ colpass_multi_kernel(const float* __restrict__ S, int64_t n, int64_t m, int64_t 
       }
     }
   }
+  if constexpr (MODE == 2) {
 #pragma unroll
-  for (int e = 0; e < 4; ++e) {
-    const int64_t k = col + e;
-    if (k >= m) break;
-    if constexpr (MODE == 2) {
+    for (int e = 0; e < 4; ++e) {
+      const int64_t k = col + e;
+      if (k < m) {
 #pragma unroll
-      for (int c = 0; c < MV; c += 2) *reinterpret_cast<f64x2*>(T + k * MV + c) = (f64x2){t[e][c], t[e][c + 1]};
-    } else {
+        for (int c = 0; c < MV; c += 2) *reinterpret_cast<f64x2*>(T + k * MV + c) = (f64x2){t[e][c], t[e][c + 1]};
+      }
+    }
+  } else {
+    // vector-major, every index a constant after unrolling (a loop that stops at nc would keep
+    // the argument arrays in scratch memory)
 #pragma unroll
-      for (int c = 0; c < MV; ++c) {
-        if (c >= nc) break;
-        const double x = ((double)mc.v[c][k] - t[e][c]) / mc.lam[c];
-        if constexpr (MODE == 0) static_cast<float*>(mc.x[c])[k] = (float)x;
-        else static_cast<double*>(mc.x[c])[k] = x;
+    for (int c = 0; c < MV; ++c) {
+      if (c < nc) {
+        const float* vc = mc.v[c];
+        const double lam = mc.lam[c];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int64_t k = col + e;
+          if (k < m) {
+            const double x = ((double)vc[k] - t[e][c]) / lam;
+            if constexpr (MODE == 0) static_cast<float*>(mc.x[c])[k] = (float)x;
+            else static_cast<double*>(mc.x[c])[k] = x;
+          }
+        }
       }
     }
   }
@@ -270,8 +283,8 @@ RowMultiPlan rowmulti_plan(int64_t n, int64_t m, int64_t lds) {
   p.n = n;
   p.m = m;
   p.lds = lds;
-  const int64_t rowblocks = (n + RM_WAVES * RM_RPW - 1) / (RM_WAVES * RM_RPW);
-  const int64_t target = std::max<int64_t>(1, 4096 / rowblocks);       // ~4096 workgroups
+  const int64_t rowblocks = (n + RT_ROWS - 1) / RT_ROWS;
+  const int64_t target = std::max<int64_t>(1, 2048 / rowblocks);       // ~2048 workgroups
   const int64_t maxg = (m + 2047) / 2048;                                // >= 2048 columns per group
   p.nchunk = std::max<int64_t>(1, std::min(target, maxg));
   int64_t cg = (m + p.nchunk - 1) / p.nchunk;
@@ -290,14 +303,13 @@ hipError_t rowpass_multi_launch(const RowMultiPlan& p, const float* S, const Mul
   if (!T)
     for (int c = 0; c < nv; ++c) vecv = vecv && aligned16(vs.f[c]);
   const int iv = (vec ? 1 : 0) | (vecv ? 2 : 0);
-  const dim3 grid((unsigned)((p.n + RM_WAVES * RM_RPW - 1) / (RM_WAVES * RM_RPW)), (unsigned)p.nchunk);
-  if (T) {
-    const dim3 gridt((unsigned)((p.n + RT_ROWS - 1) / RT_ROWS), (unsigned)p.nchunk);
-    hipLaunchKernelGGL(rowpass_multi_t_kernel, gridt, dim3(64 * RT_WAVES), 0, st, S, p.n, p.m, p.lds, T, nv, p.chunk,
-                       part, iv);
-  } else
-    hipLaunchKernelGGL(rowpass_multi_kernel, grid, dim3(64 * RM_WAVES), 0, st, S, p.n, p.m, p.lds, vs, nv, p.chunk,
-                       part, iv);
+  const dim3 grid((unsigned)((p.n + RT_ROWS - 1) / RT_ROWS), (unsigned)p.nchunk);
+  if (T)
+    hipLaunchKernelGGL(rowpass_multi_t_kernel<false>, grid, dim3(64 * RT_WAVES), 0, st, S, p.n, p.m, p.lds, T, vs, nv,
+                       p.chunk, part, iv);
+  else
+    hipLaunchKernelGGL(rowpass_multi_t_kernel<true>, grid, dim3(64 * RT_WAVES), 0, st, S, p.n, p.m, p.lds,
+                       (const double*)nullptr, vs, nv, p.chunk, part, iv);
   return hipGetLastError();
 }
 

@@ -383,8 +383,9 @@ def test_batched(dfl, ctx, oracle_mod):
 
 
 @pytest.mark.parametrize("n,m,ld,nlam,nrhs,prec,sweeps,policy", [
-    (200, 12001, 12001, 5, 3, 1, 2, "on_failure"),   # 15 vectors: a full and a ragged group of 8; unaligned rows
-    (96, 8192, 8200, 2, 9, 0, 1, "on_failure"),      # 18 vectors, padded stride
+    (200, 12001, 12001, 5, 3, 1, 2, "on_failure"),   # 15 vectors: one ragged group of 16; unaligned rows
+    (96, 8192, 8200, 2, 9, 0, 1, "on_failure"),      # 18 vectors: a full and a ragged group, padded stride
+    (128, 9000, 9000, 2, 17, 1, 1, "on_failure"),    # 34 vectors; 17 right-hand sides: S V in two passes
     (256, 65536, 65536, 3, 2, 2, 3, "always"),       # scaled-FP8 Gram with the up-front shift
 ])
 def test_batched_groups(dfl, ctx, oracle_mod, n, m, ld, nlam, nrhs, prec, sweeps, policy):
@@ -410,14 +411,14 @@ def test_batched_groups(dfl, ctx, oracle_mod, n, m, ld, nlam, nrhs, prec, sweeps
 
 
 def test_factor_solve_many(dfl, ctx, oracle_mod):
-    """Factor reuse with 11 right-hand sides (two groups of the multi-vector passes)."""
+    """Factor reuse with 19 right-hand sides (two groups of the multi-vector passes)."""
     n, m, lam = 160, 9000, 1e-4
     S = synth.make_S(n, m, synth.seed(39, n))
-    V = synth.make_V(m, 11, synth.seed(39, n))
+    V = synth.make_V(m, 19, synth.seed(39, n))
     f, _ = dfl.dfisher_factor_create(ctx, dev(S), lam, gram_prec=1, sweeps=2, x_fp64=True)
     X = dfl.dfisher_factor_solve(f, dev(V)).cpu().numpy()
     dfl.dfisher_factor_destroy(f)
-    for r in range(11):
+    for r in range(19):
         assert rel(X[r], oracle_mod.solve(S, V[r], lam)) <= 1e-6
 
 

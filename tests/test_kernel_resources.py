@@ -1,6 +1,8 @@
 """Register and scratch use of the hot-path kernels, read from the compiler's resource report for
 gfx950 (no GPU needed). A kernel on the hot path that spills to scratch memory loses much of its
-speed without any change in its results, so the parity tests cannot see it; this test can."""
+speed without any change in its results, so the parity tests cannot see it; this test can.
+Vector registers may not spill at all and no kernel may use scratch memory; scalar registers may
+spill only into lanes of vector registers (scratch size 0), which costs one lane move each."""
 import concurrent.futures as cf
 import os
 import re
@@ -73,4 +75,4 @@ def test_hot_kernel_does_not_spill(reports, frag):
     assert hits, f"no kernel matching {frag} in {HOT[frag]}"
     for name, r in hits.items():
         assert r.get("ScratchSize [bytes/lane]") == "0", (name, r)
-        assert r.get("VGPRs Spill") == "0" and r.get("SGPRs Spill") == "0", (name, r)
+        assert r.get("VGPRs Spill") == "0", (name, r)
