@@ -735,7 +735,11 @@ RefinePassPlan refine_pass_plan(int64_t n, int64_t m, int64_t lds, const float* 
   int dev = 0, cus = 0;
   if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
     cus = 256;
-  p.ngroups = std::max<int64_t>(1, std::min<int64_t>(cus, nfull));
+  // workgroups per compute unit as the registers allow (8 waves each: 6, 4 and 2 waves per SIMD fit
+  // for 8, 16 and 32 loads per lane): with small n one block is little data, and several blocks
+  // per compute unit keep enough bytes in flight
+  const int64_t per_cu = p.nch == 8 ? 3 : (p.nch == 16 ? 2 : 1);
+  p.ngroups = std::max<int64_t>(1, std::min<int64_t>((int64_t)cus * per_cu, nfull));
   p.tail = (m % FR_COLS) != 0;
   p.part_bytes = p.usable ? (size_t)(p.ngroups + (p.tail ? 1 : 0)) * (size_t)n * sizeof(double) : 0;
   return p;
