@@ -396,7 +396,7 @@ dfisher_status solve_y(const float* S, int64_t n, int64_t m, int64_t lds, double
 // Per vector: y = W_f^-1 S v_r, `sweeps` FP64 refinement sweeps against the exact operator, then
 // x = (v_r - S^T y) / lambda_f. Needs nfac * nrhs <= 65535.
 struct MultiBufs {
-  double *Bs, *Bexp, *Y, *R, *D, *W1, *T, *part;
+  double *Bs, *Bexp, *Y, *R, *D, *W1, *T, *Yi, *part;
 };
 
 MultiBufs carve_multi(Carver& c, int64_t n, int64_t m, int64_t nrhs, int64_t nvec, const dfi::RowMultiPlan& rm,
@@ -409,6 +409,7 @@ MultiBufs carve_multi(Carver& c, int64_t n, int64_t m, int64_t nrhs, int64_t nve
   b.D = c.take<double>((size_t)(nvec * n));
   b.W1 = c.take<double>((size_t)(nvec * n));
   b.T = need_t ? c.take<double>((size_t)(m * dfi::MULTI_VECS)) : nullptr;
+  b.Yi = c.take<double>((size_t)(n * dfi::MULTI_VECS));
   b.part = c.take<double>(rm.part_bytes / sizeof(double) + 1);
   return b;
 }
@@ -451,7 +452,7 @@ dfisher_status multi_solve(const float* S, int64_t n, int64_t m, int64_t lds, in
         mo.y[c] = b.Y + j * n;
         mo.lam[c] = lams[j / nrhs];
       }
-      HIP_TRY(dfi::colpass_multi_launch(S, n, m, lds, mc, nv, 2, b.T, st));
+      HIP_TRY(dfi::colpass_multi_launch(S, n, m, lds, mc, nv, 2, b.T, b.Yi, st));
       dfi::MultiVecs none{};
       HIP_TRY(dfi::rowpass_multi_launch(rm, S, none, b.T, nv, b.part, st));
       HIP_TRY(dfi::rowpass_multi_reduce(rm, b.part, nv, mo, st));
@@ -472,7 +473,7 @@ dfisher_status multi_solve(const float* S, int64_t n, int64_t m, int64_t lds, in
       mc.x[c] = static_cast<char*>(X) + (size_t)(j * ldx) * xel;
       mc.lam[c] = lams[j / nrhs];
     }
-    HIP_TRY(dfi::colpass_multi_launch(S, n, m, lds, mc, nv, x_fp64 ? 1 : 0, nullptr, st));
+    HIP_TRY(dfi::colpass_multi_launch(S, n, m, lds, mc, nv, x_fp64 ? 1 : 0, nullptr, b.Yi, st));
   }
   return DFISHER_OK;
 }

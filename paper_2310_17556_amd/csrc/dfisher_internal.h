@@ -153,9 +153,10 @@ hipError_t rowpass_multi_launch(const RowMultiPlan& p, const float* S, const Mul
 hipError_t rowpass_multi_reduce(const RowMultiPlan& p, const double* part, int nv, const MultiOut& out,
                                 hipStream_t st);
 // t_c = S^T y_c (c < nc). mode 2: T[k * MULTI_VECS + c] = t_c[k] (T: m * MULTI_VECS doubles); mode 0 / 1:
-// x_c = (v_c - t_c) / lam_c as FP32 / FP64.
+// x_c = (v_c - t_c) / lam_c as FP32 / FP64. Yi: scratch of n * MULTI_VECS doubles (the y_c
+// interleaved by row).
 hipError_t colpass_multi_launch(const float* S, int64_t n, int64_t m, int64_t lds, const MultiCols& mc, int nc,
-                                int mode, double* T, hipStream_t st);
+                                int mode, double* T, double* Yi, hipStream_t st);
 // y += d over len entries
 hipError_t axpy_many(double* y, const double* d, int64_t len, hipStream_t st);
 

@@ -9,8 +9,9 @@
 //           right-hand sides) or FP64 interleaved T[k * MV + c] (the column pass output).
 //           FP64 partials per (column group, vector, row) are added in fixed order by a second
 //           kernel, which can also form refinement residuals r = b - lambda y - S t.
-// Column pass t_c = S^T y_c for c < nc. A workgroup owns 1024 consecutive columns (4 per lane)
-//           and walks all rows; y_c[i] is wave-uniform. Output either T[k * MV + c] (FP64) or
+// Column pass t_c = S^T y_c for c < nc on the FP64 matrix cores. A wave owns 64 consecutive
+//           columns and walks all rows, 4 at a time per product, with the y_c copied out
+//           interleaved by row first. Output either T[k * MV + c] (FP64) or
 //           x_c = (v_c - t_c) / lambda_c (FP32 or FP64), each column with its own v, x, lambda.
 // Products of FP32 and FP64 values are formed and accumulated in FP64.
 #include "dfisher_internal.h"
@@ -22,6 +23,7 @@ namespace {
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef double f64x2 __attribute__((ext_vector_type(2)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
 
 constexpr int MV = MULTI_VECS;   // 16
 constexpr int RM_STEP = 256;     // columns per wave step (4 per lane)
@@ -193,73 +195,87 @@ __global__ void rowpass_multi_reduce_kernel(const double* __restrict__ part, int
   out.b[c][i] = r0 ? (r0[i] - out.lam[c] * out.y[c][i]) - s : s;
 }
 
-constexpr int CM_THREADS = 256;
-constexpr int CM_COLS = 4 * CM_THREADS;
-constexpr int CM_UNROLL = 4;
+// Yi[i * MV + c] = mc.y[c][i] for i < n, c < MV: the y vectors interleaved by row.
+__global__ void interleave_y_kernel(MultiCols mc, int64_t n, double* __restrict__ Yi) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= n * MV) return;
+  Yi[idx] = mc.y[idx % MV][idx / MV];
+}
 
-// MODE 2: T[k * MV + c] = t_c[k]; MODE 0 / 1: x_c[k] = (v_c[k] - t_c[k]) / lam_c as FP32 / FP64.
-// Vectors c >= nc are computed from y_0 and discarded.
+// The column pass on the FP64 matrix cores: per wave 64 consecutive columns, D_j(16 vectors x 16
+// columns) += Y(4 rows x 16 vectors)^T S(4 rows x 16 columns) with v_mfma_f64_16x16x4f64. Lane l
+// = 16 kr + q loads row i + kr, columns col .. col + 3 (col = c0 + 4 q) of S with one 16-byte load
+// and supplies element j to product j (columns col + j: D_j covers columns c0 + 4 n + j); its A
+// operand is Yi[(i + kr) MV + q], one 8-byte load. Lane l holds D_j[vector kr + 4 r][n = q] in
+// register r. Each product adds 4 rows (its k = 4) in FP64; rows past n and columns past m read
+// as zero. The accumulators take 32 registers per lane, so many waves keep loads in flight.
+constexpr int CF_WAVES = 4;
+constexpr int CF_COLS = 64;    // columns per wave
+constexpr int CF_GROUPS = 4;   // 4-row groups per loop step
+static_assert(MV == 16, "one MFMA dimension holds the vectors");
+
 template <int MODE>
-__global__ void __launch_bounds__(CM_THREADS)
-colpass_multi_kernel(const float* __restrict__ S, int64_t n, int64_t m, int64_t lds, MultiCols mc, int nc,
-                     double* __restrict__ T, int vec) {
-  const int64_t col = (int64_t)blockIdx.x * CM_COLS + 4 * threadIdx.x;
-  if (col >= m) return;
+__global__ void __launch_bounds__(64 * CF_WAVES)
+colpass_multi_mfma_kernel(const float* __restrict__ S, int64_t n, int64_t m, int64_t lds, MultiCols mc, int nc,
+                          const double* __restrict__ Yi, double* __restrict__ T, int vec) {
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int64_t c0 = ((int64_t)blockIdx.x * CF_WAVES + wave) * CF_COLS;
+  if (c0 >= m) return;   // the whole wave
+  const int q = lane & 15, kr = lane >> 4;
+  const int64_t col = c0 + 4 * q;
   const bool full = vec && (col + 4 <= m);
-  double t[4][MV];
+  auto load_s = [&](int64_t row) {
+    f32x4 v = {0.f, 0.f, 0.f, 0.f};
+    if (row < n) {
+      const float* p = S + row * lds + col;
+      if (full) {
+        v = *reinterpret_cast<const f32x4*>(p);
+      } else {
 #pragma unroll
-  for (int e = 0; e < 4; ++e)
-#pragma unroll
-    for (int c = 0; c < MV; ++c) t[e][c] = 0.0;
-  int64_t i = 0;
-  for (; i < n; i += CM_UNROLL) {
-    f32x4 sv[CM_UNROLL];
-#pragma unroll
-    for (int u = 0; u < CM_UNROLL; ++u) {
-      sv[u] = (f32x4){0.f, 0.f, 0.f, 0.f};
-      if (i + u < n) {
-        const float* p = S + (i + u) * lds + col;
-        if (full) {
-          sv[u] = *reinterpret_cast<const f32x4*>(p);
-        } else {
-#pragma unroll
-          for (int e = 0; e < 4; ++e) sv[u][e] = (col + e < m) ? p[e] : 0.f;
-        }
+        for (int e = 0; e < 4; ++e) v[e] = (col + e < m) ? p[e] : 0.f;
       }
     }
+    return v;
+  };
+  auto load_y = [&](int64_t row) { return row < n ? Yi[row * MV + q] : 0.0; };
+  f64x4 acc[4];
 #pragma unroll
-    for (int u = 0; u < CM_UNROLL; ++u) {
-      if (i + u >= n) break;
+  for (int j = 0; j < 4; ++j) acc[j] = (f64x4){0.0, 0.0, 0.0, 0.0};
+  for (int64_t i = 0; i < n; i += 4 * CF_GROUPS) {
+    f32x4 sv[CF_GROUPS];
+    double ya[CF_GROUPS];
 #pragma unroll
-      for (int c = 0; c < MV; ++c) {
-        const double yc = mc.y[c][i + u];
-#pragma unroll
-        for (int e = 0; e < 4; ++e) t[e][c] = fma((double)sv[u][e], yc, t[e][c]);
-      }
+    for (int g = 0; g < CF_GROUPS; ++g) {
+      sv[g] = load_s(i + 4 * g + kr);
+      ya[g] = load_y(i + 4 * g + kr);
     }
+#pragma unroll
+    for (int g = 0; g < CF_GROUPS; ++g)
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        acc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ya[g], (double)sv[g][j], acc[j], 0, 0, 0);
   }
   if constexpr (MODE == 2) {
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      const int64_t k = col + e;
-      if (k < m) {
+    for (int j = 0; j < 4; ++j) {
+      if (col + j >= m) continue;
 #pragma unroll
-        for (int c = 0; c < MV; c += 2) *reinterpret_cast<f64x2*>(T + k * MV + c) = (f64x2){t[e][c], t[e][c + 1]};
-      }
+      for (int r = 0; r < 4; ++r) T[(col + j) * MV + kr + 4 * r] = acc[j][r];
     }
   } else {
-    // vector-major, every index a constant after unrolling (a loop that stops at nc would keep
-    // the argument arrays in scratch memory)
+    // vector by vector with a uniform index into the argument arrays: vector c lives in register
+    // c / 4 of the lanes with kr = c % 4
 #pragma unroll
     for (int c = 0; c < MV; ++c) {
-      if (c < nc) {
+      if (c < nc && kr == (c & 3)) {
         const float* vc = mc.v[c];
         const double lam = mc.lam[c];
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const int64_t k = col + e;
+        for (int j = 0; j < 4; ++j) {
+          const int64_t k = col + j;
           if (k < m) {
-            const double x = ((double)vc[k] - t[e][c]) / lam;
+            const double x = ((double)vc[k] - acc[j][c >> 2]) / lam;
             if constexpr (MODE == 0) static_cast<float*>(mc.x[c])[k] = (float)x;
             else static_cast<double*>(mc.x[c])[k] = x;
           }
@@ -322,19 +338,22 @@ hipError_t rowpass_multi_reduce(const RowMultiPlan& p, const double* part, int n
 }
 
 hipError_t colpass_multi_launch(const float* S, int64_t n, int64_t m, int64_t lds, const MultiCols& mc, int nc,
-                                int mode, double* T, hipStream_t st) {
-  if (nc < 1 || nc > MV) return hipErrorInvalidValue;
+                                int mode, double* T, double* Yi, hipStream_t st) {
+  if (nc < 1 || nc > MV || !Yi) return hipErrorInvalidValue;
   const bool vec = ((lds & 3) == 0) && aligned16(S);
-  const dim3 grid((unsigned)((m + CM_COLS - 1) / CM_COLS));
+  hipLaunchKernelGGL(interleave_y_kernel, dim3((unsigned)((n * MV + 255) / 256)), dim3(256), 0, st, mc, n, Yi);
+  const dim3 grid((unsigned)((m + CF_WAVES * CF_COLS - 1) / (CF_WAVES * CF_COLS)));
+  const dim3 block(64 * CF_WAVES);
+  const double* yi = Yi;
   switch (mode) {
     case 0:
-      hipLaunchKernelGGL((colpass_multi_kernel<0>), grid, dim3(CM_THREADS), 0, st, S, n, m, lds, mc, nc, T, vec ? 1 : 0);
+      hipLaunchKernelGGL((colpass_multi_mfma_kernel<0>), grid, block, 0, st, S, n, m, lds, mc, nc, yi, T, vec ? 1 : 0);
       break;
     case 1:
-      hipLaunchKernelGGL((colpass_multi_kernel<1>), grid, dim3(CM_THREADS), 0, st, S, n, m, lds, mc, nc, T, vec ? 1 : 0);
+      hipLaunchKernelGGL((colpass_multi_mfma_kernel<1>), grid, block, 0, st, S, n, m, lds, mc, nc, yi, T, vec ? 1 : 0);
       break;
     case 2:
-      hipLaunchKernelGGL((colpass_multi_kernel<2>), grid, dim3(CM_THREADS), 0, st, S, n, m, lds, mc, nc, T, vec ? 1 : 0);
+      hipLaunchKernelGGL((colpass_multi_mfma_kernel<2>), grid, block, 0, st, S, n, m, lds, mc, nc, yi, T, vec ? 1 : 0);
       break;
     default:
       return hipErrorInvalidValue;
