@@ -182,6 +182,104 @@ rowpass_multi_t_kernel(const float* __restrict__ S, int64_t n, int64_t m, int64_
   }
 }
 
+// The row pass with the FP64 vectors T on the FP64 matrix cores. A wave owns 16 rows; a
+// workgroup of RG_WAVES waves (64 rows) walks its column group 256 columns at a time, with that
+// step of T staged in LDS (double-buffered, each group of 4 columns' 64 values padded to 80 so that
+// a product's B-operand read touches each bank at most twice). Per step each lane = 16 kr + q loads
+// row r0 + q, columns 16 u + 4 kr .. + 3 for u < 16 (16 loads of 16 bytes: the wave reads 1 KB of
+// each of its rows), and product (u, j) takes element j of load u as its A operand (row q, column
+// 16 u + 4 kr + j) and T[16 u + 4 kr + j][q] from LDS as its B operand: D(16 rows x 16 vectors) +=
+// S(16 x 4) T(4 x 16) with v_mfma_f64_16x16x4f64. Lane l then holds D[row kr + 4 r][vector q] in
+// register r, the partial this wave stores for the group. Rows past n and columns past c1 read
+// as zero.
+constexpr int RG_WAVES = 4;
+constexpr int RG_ROWS = 16 * RG_WAVES;
+constexpr int RG_STEP = 256;
+constexpr int RG_GSTRIDE = 80;                        // doubles per 4-column group in LDS (64 used)
+constexpr int RG_BUF = (RG_STEP / 4) * RG_GSTRIDE;   // doubles per LDS buffer (40 KB)
+constexpr int RG_PIECES = RG_STEP * MV / 2 / (64 * RG_WAVES);   // 16-byte pieces of T per thread and step
+
+__global__ void __launch_bounds__(64 * RG_WAVES, 2)
+rowpass_multi_tm_kernel(const float* __restrict__ S, int64_t n, int64_t m, int64_t lds, const double* __restrict__ T,
+                        int nv, int64_t cg, double* __restrict__ part, int vec) {
+  __shared__ __attribute__((aligned(16))) double tl[2][RG_BUF];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int q = lane & 15, kr = lane >> 4;
+  const int64_t rbase = (int64_t)blockIdx.x * RG_ROWS + wave * 16;
+  const int64_t g = blockIdx.y;
+  const int64_t c0 = g * cg;
+  const int64_t c1 = min(m, c0 + cg);
+  // waves whose rows lie past n still stage their share of T and meet the barriers
+  auto load_t = [&](int64_t cs, f64x2* tv) {
+#pragma unroll
+    for (int h = 0; h < RG_PIECES; ++h) {
+      const int idx = 2 * (h * 64 * RG_WAVES + tid);   // double index in the step: column idx / MV, vector idx % MV
+      tv[h] = (f64x2){0.0, 0.0};
+      if (cs + idx / MV < c1) tv[h] = *reinterpret_cast<const f64x2*>(T + cs * MV + idx);
+    }
+  };
+  auto store_t = [&](const f64x2* tv, double* tb) {
+#pragma unroll
+    for (int h = 0; h < RG_PIECES; ++h) {
+      const int idx = 2 * (h * 64 * RG_WAVES + tid);
+      const int cl = idx / MV;
+      *reinterpret_cast<f64x2*>(&tb[(cl >> 2) * RG_GSTRIDE + (cl & 3) * MV + (idx % MV)]) = tv[h];
+    }
+  };
+  // The wave's 16 rows of S as one buffer from a wave-uniform base (row rbase, column c0) with a
+  // 32-bit lane offset (the launcher checks 16 lds * 4 < 2^31): the records end at row n, so lanes
+  // of rows past n read zeros, and a wave with no rows below n has no records and touches no memory.
+  const int rin = (int)max<int64_t>(0, min<int64_t>(16, n - rbase));
+  const float* sbase = S + (rin > 0 ? rbase : 0) * lds + c0;
+  const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+      const_cast<float*>(sbase), 0, rin > 0 ? (int)((int64_t)rin * lds * 4) : 0, 0x00020000);
+  const uint32_t qoff = (uint32_t)((int64_t)q * lds * 4);
+  f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+  f64x2 tv[RG_PIECES];
+  if (c0 < c1) {
+    load_t(c0, tv);
+    store_t(tv, tl[0]);
+  }
+  __syncthreads();
+  int buf = 0;
+  for (int64_t cs = c0; cs < c1; cs += RG_STEP, buf ^= 1) {
+    const bool more = cs + RG_STEP < c1;
+    if (more) load_t(cs + RG_STEP, tv);   // the next step's T, stored after this step's products
+    f32x4 sv[16];
+    const int kc = (int)(cs - c0);
+#pragma unroll
+    for (int u = 0; u < 16; ++u)
+      sv[u] = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(
+                                            rs, (int)(qoff + 4u * (uint32_t)(kc + 16 * u + 4 * kr)), 0, 0));
+    // columns past c1 (in the group's last step only) count as zero: a select, no branch
+    const int lim = (int)min<int64_t>(c1 - cs, RG_STEP);
+#pragma unroll
+    for (int u = 0; u < 16; ++u)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) sv[u][e] = (16 * u + 4 * kr + e < lim) ? sv[u][e] : 0.f;
+    const double* tb = tl[buf];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const double b = tb[(4 * u + kr) * RG_GSTRIDE + j * MV + q];
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64((double)sv[u][j], b, acc, 0, 0, 0);
+      }
+      __builtin_amdgcn_sched_barrier(0);   // widen load u's values only where its products use them
+    }
+    if (more) store_t(tv, tl[buf ^ 1]);   // the other buffer was last read before the previous barrier
+    __syncthreads();
+  }
+  if (q >= nv) return;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int64_t rr = rbase + kr + 4 * r;
+    if (rr < n) part[(g * MV + q) * n + rr] = acc[r];
+  }
+}
+
 // out.b[c][i] = sum_g part[(g * MV + c) * n + i]; with out.r0[c] set:
 // out.b[c][i] = (r0_c[i] - lam_c y_c[i]) - sum_g part[...] (refinement residual).
 __global__ void rowpass_multi_reduce_kernel(const double* __restrict__ part, int64_t n, int64_t ngroups, int nv,
@@ -320,7 +418,10 @@ hipError_t rowpass_multi_launch(const RowMultiPlan& p, const float* S, const Mul
     for (int c = 0; c < nv; ++c) vecv = vecv && aligned16(vs.f[c]);
   const int iv = (vec ? 1 : 0) | (vecv ? 2 : 0);
   const dim3 grid((unsigned)((p.n + RT_ROWS - 1) / RT_ROWS), (unsigned)p.nchunk);
-  if (T)
+  if (T && 16 * p.lds * 4 < ((int64_t)1 << 31) && p.chunk < ((int64_t)1 << 28))
+    hipLaunchKernelGGL(rowpass_multi_tm_kernel, dim3((unsigned)((p.n + RG_ROWS - 1) / RG_ROWS), (unsigned)p.nchunk),
+                       dim3(64 * RG_WAVES), 0, st, S, p.n, p.m, p.lds, T, nv, p.chunk, part, iv);
+  else if (T)
     hipLaunchKernelGGL(rowpass_multi_t_kernel<false>, grid, dim3(64 * RT_WAVES), 0, st, S, p.n, p.m, p.lds, T, vs, nv,
                        p.chunk, part, iv);
   else

@@ -25,6 +25,7 @@ HOT = {
     "rowpass_prep_kernelILb1ELi3": "gemv.hip",
     "colpass_kernelILi0": "gemv.hip",
     "rowpass_multi_t_kernel": "multi.hip",
+    "rowpass_multi_tm_kernel": "multi.hip",
     "colpass_multi_mfma_kernel": "multi.hip",
     "potf2_kernel": "potrf.hip",
     "update_kernel": "potrf.hip",
