@@ -33,18 +33,6 @@ GramPlan gram_plan(int64_t n, int64_t m, int64_t lds, int prec, bool aligned16, 
 // that keeps >= 2048 columns per slice and the partial tiles within max_part_bytes.
 void gram_q_candidates(int64_t n, int64_t m, size_t max_part_bytes, int* out, int* count, int cap);
 hipError_t gram_launch(const GramPlan& p, const float* S, float* part, hipStream_t st);
-// One problem of a grouped Gram launch (several independent Grams in one launch). a, b: the FP8
-// codes and scales (prec 2) or the hi and lo planes (prec 1) in the row pass's column-blocked
-// layout; kcap: ldq (prec 2) or ldh (prec 1), the column range the slices cover; part: that
-// problem's partial tiles;
-// wg_begin: its first workgroup (sorted ascending, each job's count nslice * ntri a multiple of 8).
-struct GramJob {
-  const void* a;
-  const void* b;
-  float* part;
-  int64_t n, kcap, ntri, nslice, kslice, wg_begin;
-};
-hipError_t gram_launch_grouped(int prec, const GramJob* jobs_dev, int njobs, int64_t total_wg, hipStream_t st);
 // The first column the tile kernel of plan p leaves to gram_reduce.
 int64_t gram_tail_start(const GramPlan& p, const float* S);
 // Row stride (bf16 elements) of the split-BF16 planes for m columns.

@@ -65,19 +65,6 @@ __device__ __forceinline__ int64_t uni64(int64_t x) {
   return (int64_t)(((uint64_t)hi << 32) | lo);
 }
 
-// Grouped launches: workgroup w belongs to the job with the largest wg_begin <= w (binary search
-// over the sorted table; the result is uniform across the workgroup). Every job's workgroup count
-// is a multiple of 8, so w - wg_begin keeps the XCD assignment w mod 8.
-__device__ __forceinline__ int find_job(const GramJob* __restrict__ jobs, int njobs, int64_t w) {
-  int lo = 0, hi = njobs - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (jobs[mid].wg_begin <= w) lo = mid;
-    else hi = mid - 1;
-  }
-  return lo;
-}
-
 // Global -> register staging for one 256-row panel and one k-step.
 // Thread t loads rows (t / 8) + 64 i, columns 4 (t % 8) .. +3 of the step.
 template <bool VEC>
@@ -621,27 +608,12 @@ __device__ __forceinline__ i32x8 read_frag(const uint8_t* panel, int r, int h) {
 // lgkmcnt(0) with the other counters left alone (lgkmcnt bits [11:8]).
 #define DFI_WAIT_LGKM0() __builtin_amdgcn_s_waitcnt(15 | (3 << 14) | (7 << 4))
 
-// G = true: a grouped launch over jobs[0 .. njobs) (the scalar arguments are then ignored).
-template <bool G>
 __global__ void __launch_bounds__(NT, 1)
 gram_kernel_fp8(const uint8_t* __restrict__ q, const uint8_t* __restrict__ sc, int64_t n, int64_t kcap,
-                int64_t ntri, int64_t nslice, int64_t kslice, float* __restrict__ part, const GramJob* __restrict__ jobs,
-                int njobs) {
+                int64_t ntri, int64_t nslice, int64_t kslice, float* __restrict__ part) {
   __shared__ Stage stg0, stg1, stg2, stg3;
 
-  int64_t w = blockIdx.x;
-  if constexpr (G) {
-    const GramJob& jb = jobs[find_job(jobs, njobs, w)];
-    q = static_cast<const uint8_t*>(jb.a);
-    sc = static_cast<const uint8_t*>(jb.b);
-    n = jb.n;
-    kcap = jb.kcap;
-    ntri = jb.ntri;
-    nslice = jb.nslice;
-    kslice = jb.kslice;
-    part = jb.part;
-    w -= jb.wg_begin;
-  }
+  const int64_t w = blockIdx.x;
   const int64_t xcd = w & 7;
   const int64_t local = w >> 3;
   const int64_t qq = uni64(local / ntri);
@@ -925,27 +897,12 @@ struct Frags {
   bf16x8 ah[NB], al[NB], bh[NB], bl[NB];
 };
 
-// G = true: a grouped launch over jobs[0 .. njobs) (the scalar arguments are then ignored).
-template <bool G>
 __global__ void __launch_bounds__(NT, 1)
 gram_kernel_split(const uint16_t* __restrict__ hi, const uint16_t* __restrict__ lo, int64_t n,
-                  int64_t kcap, int64_t ntri, int64_t nslice, int64_t kslice, float* __restrict__ part,
-                  const GramJob* __restrict__ jobs, int njobs) {
+                  int64_t kcap, int64_t ntri, int64_t nslice, int64_t kslice, float* __restrict__ part) {
   __shared__ Stage stg0, stg1, stg2, stg3;
 
-  int64_t w = blockIdx.x;
-  if constexpr (G) {
-    const GramJob& jb = jobs[find_job(jobs, njobs, w)];
-    hi = static_cast<const uint16_t*>(jb.a);
-    lo = static_cast<const uint16_t*>(jb.b);
-    n = jb.n;
-    kcap = jb.kcap;
-    ntri = jb.ntri;
-    nslice = jb.nslice;
-    kslice = jb.kslice;
-    part = jb.part;
-    w -= jb.wg_begin;
-  }
+  const int64_t w = blockIdx.x;
   const int64_t xcd = w & 7;
   const int64_t local = w >> 3;
   const int64_t qq = uni64(local / ntri);
@@ -1203,8 +1160,8 @@ hipError_t gram_launch_fp8(const GramPlan& p, const uint8_t* q, const uint8_t* s
                            hipStream_t st) {
   const dim3 grid((unsigned)(p.nslice * p.ntri));
   if ((ldq & 127) != 0 || ldq < p.m || p.nslice * p.kslice < ldq || (p.kslice & 63) != 0) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(v3::gram_kernel_fp8<false>, grid, dim3(v3::NT), 0, st, q, sc, p.n, ldq, p.ntri, p.nslice,
-                     p.kslice, part, (const GramJob*)nullptr, 0);
+  hipLaunchKernelGGL(v3::gram_kernel_fp8, grid, dim3(v3::NT), 0, st, q, sc, p.n, ldq, p.ntri, p.nslice, p.kslice,
+                     part);
   return hipGetLastError();
 }
 
@@ -1212,22 +1169,8 @@ hipError_t gram_launch_split(const GramPlan& p, const uint16_t* hi, const uint16
   if (p.prec != 1 || p.ldh <= 0 || (p.ldh & 63) != 0) return hipErrorInvalidValue;
   const dim3 grid((unsigned)(p.nslice * p.ntri));
   if (p.nslice * p.kslice < p.ldh || (p.kslice & 15) != 0) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(v4::gram_kernel_split<false>, grid, dim3(v4::NT), 0, st, hi, lo, p.n, p.ldh, p.ntri, p.nslice,
-                     p.kslice, part, (const GramJob*)nullptr, 0);
-  return hipGetLastError();
-}
-
-hipError_t gram_launch_grouped(int prec, const GramJob* jobs_dev, int njobs, int64_t total_wg, hipStream_t st) {
-  if (njobs < 1 || total_wg < 1 || (total_wg & 7) != 0 || total_wg > 0x7fffffff) return hipErrorInvalidValue;
-  const dim3 grid((unsigned)total_wg);
-  if (prec == 2)
-    hipLaunchKernelGGL(v3::gram_kernel_fp8<true>, grid, dim3(v3::NT), 0, st, (const uint8_t*)nullptr,
-                       (const uint8_t*)nullptr, 0, 0, 0, 0, 0, (float*)nullptr, jobs_dev, njobs);
-  else if (prec == 1)
-    hipLaunchKernelGGL(v4::gram_kernel_split<true>, grid, dim3(v4::NT), 0, st, (const uint16_t*)nullptr,
-                       (const uint16_t*)nullptr, 0, 0, 0, 0, 0, (float*)nullptr, jobs_dev, njobs);
-  else
-    return hipErrorInvalidValue;
+  hipLaunchKernelGGL(v4::gram_kernel_split, grid, dim3(v4::NT), 0, st, hi, lo, p.n, p.ldh, p.ntri, p.nslice,
+                     p.kslice, part);
   return hipGetLastError();
 }
 

@@ -16,7 +16,7 @@ CSRC = os.path.join(ROOT, "paper_2310_17556_amd", "csrc")
 
 # kernel (demangled-name fragment as it appears in the mangled symbol) -> source file
 HOT = {
-    "gram_kernel_fp8ILb0": "gram.hip",
+    "gram_kernel_fp8": "gram.hip",
     "gram_kernel_split": "gram.hip",
     "gram_reduce_kernel": "gram.hip",
     "refine_pass_kernelILi32": "gemv.hip",
