@@ -410,6 +410,28 @@ def test_batched_groups(dfl, ctx, oracle_mod, n, m, ld, nlam, nrhs, prec, sweeps
     assert rel(X32.cpu().numpy(), Xref) <= 1e-6 + 2.0 ** -23
 
 
+def test_batched_huge_row_stride(dfl, ctx, oracle_mod):
+    """A row stride beyond 2^25 floats (padding NaN): the multi-vector row pass over T takes its
+    vector-ALU form (16 row strides do not fit a 32-bit buffer offset) and the refinement runs as a
+    column pass plus a row pass instead of the fused one; every (lambda, rhs) pair still matches
+    Algorithm 1 run on its own."""
+    n, m, ld = 40, 3000, (1 << 25) + 64
+    print(f"[batched huge stride] n={n} m={m} ld={ld}", flush=True)
+    S = synth.make_S(n, m, synth.seed(40, n), "iid")
+    V = synth.make_V(m, 3, synth.seed(40, n))
+    lams = [1e-5, 1e-2]
+    Sd = dev_strided(S, ld)
+    X, infos = dfl.dfisher_solve_batched(ctx, Sd, lams, dev(V), gram_prec=1, sweeps=2, x_fp64=True)
+    Xref = oracle_mod.solve_batched(S, lams, V)
+    X = X.cpu().numpy()
+    for li in range(len(lams)):
+        assert infos[li]["potrf_info"] == 0
+        for r in range(3):
+            assert rel(X[li, r], Xref[li, r]) <= 1e-6, (li, r)
+    del Sd
+    torch.cuda.empty_cache()
+
+
 def test_factor_solve_many(dfl, ctx, oracle_mod):
     """Factor reuse with 19 right-hand sides (two groups of the multi-vector passes)."""
     n, m, lam = 160, 9000, 1e-4
