@@ -72,6 +72,7 @@ fwd_step_kernel(const double* __restrict__ L, int64_t n, const double* __restric
                 const TrsvJob* __restrict__ jobs) {
   __shared__ double zk[NB];
   __shared__ double part[4][NB];
+  __shared__ double lp[NB * LDP];   // this workgroup's piece of the panel, lp[i * LDP + c] = L[J NB + i][k NB + c]
   if (jobs) {
     const TrsvJob& j = jobs[blockIdx.y];
     L = j.L;
@@ -91,15 +92,19 @@ fwd_step_kernel(const double* __restrict__ L, int64_t n, const double* __restric
   const int tid = threadIdx.x;
   const int64_t r0 = k * NB;
   const int nb = (int)min<int64_t>(NB, n - r0);
-  // This workgroup's piece of the panel L_Jk (row block J = k + blockIdx.x; 4 threads per row,
-  // 16 columns each) is loaded first: it does not depend on z_k, so its latency overlaps z_k's.
-  const int64_t row = (k + blockIdx.x) * NB + (tid >> 2);
-  const int q = tid & 3;
-  const bool upd = blockIdx.x > 0 && row < n;
+  // This workgroup's piece of the panel L_Jk (row block J = k + blockIdx.x) is loaded first: it does
+  // not depend on z_k, so its latency overlaps z_k's. Thread (c, g) loads column c of rows
+  // 16 g .. 16 g + 15, so each load instruction reads 512 contiguous bytes of one row; the piece
+  // goes through LDS to the row-wise products below.
+  const int64_t rowJ = (k + blockIdx.x) * NB;
+  const int lc = tid & 63, lg = tid >> 6;
   double lv[16];
 #pragma unroll
-  for (int u = 0; u < 16; ++u) lv[u] = (upd && q * 16 + u < nb) ? L[row * n + r0 + q * 16 + u] : 0.0;
-  // z_k = D_k r_k: 4 groups of 64 threads each take 16 columns of D_k
+  for (int u = 0; u < 16; ++u) {
+    const int64_t rw = rowJ + lg * 16 + u;
+    lv[u] = (blockIdx.x > 0 && rw < n && lc < nb) ? L[rw * n + r0 + lc] : 0.0;
+  }
+  // z_k = D_k r_k: 4 groups of 64 threads each take 16 columns of D_k (read from its transpose)
   {
     const int i = tid & 63, g = tid >> 6;
     const double* D = Dinv + k * NB * NB;
@@ -115,14 +120,19 @@ fwd_step_kernel(const double* __restrict__ L, int64_t n, const double* __restric
     if (tid < nb) z[r0 + tid] = zk[tid];
     return;
   }
-  // r_J -= L_Jk z_k
-  if (row >= n) return;
+#pragma unroll
+  for (int u = 0; u < 16; ++u) lp[(lg * 16 + u) * LDP + lc] = lv[u];
+  __syncthreads();
+  // r_J -= L_Jk z_k: 4 threads per row, 16 columns each
+  const int64_t row = rowJ + (tid >> 2);
+  const int q = tid & 3;
+  const double* lr = &lp[(tid >> 2) * LDP + q * 16];
   double s = 0.0;
 #pragma unroll
-  for (int u = 0; u < 16; ++u) s = fma(lv[u], zk[q * 16 + u], s);
+  for (int u = 0; u < 16; ++u) s = fma(lr[u], zk[q * 16 + u], s);
   s += __shfl_xor(s, 1, 64);
   s += __shfl_xor(s, 2, 64);
-  if (q == 0) r[row] -= s;
+  if (q == 0 && row < n) r[row] -= s;
 }
 
 // Backward step k. Grid: 1 + k (block k itself and the blocks J < k). 256 threads.
