@@ -51,7 +51,9 @@ __device__ __forceinline__ void load_s4(const float* __restrict__ p, int64_t col
 // vectors are read once per 32 rows of S instead of once per wave. In LDS each lane's 4 columns
 // x 16 vectors (512 bytes) are padded by 16 bytes, so the 16-byte fragment reads of 16
 // consecutive lanes cover all banks. Four rows per wave: the 4 x 16 FP64 accumulators take 128
-// registers per lane.
+// registers per lane. The next step's rows of S and share of the vectors are loaded while the
+// current step's products run. This form serves the caller's FP32 right-hand sides, and T when
+// 16 row strides do not fit a 32-bit buffer offset; otherwise rowpass_multi_tm_kernel takes T.
 constexpr int RT_WAVES = 8;
 constexpr int RT_RPW = 4;                    // rows per wave
 constexpr int RT_ROWS = RT_WAVES * RT_RPW;   // 32 rows per workgroup
