@@ -19,6 +19,7 @@ namespace dfi {
 namespace {
 
 typedef double f64x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 
 constexpr int NB = 64;
 constexpr int LDP = NB + 1;  // padded LDS row (doubles)
@@ -195,10 +196,21 @@ trsm_kernel(double* __restrict__ A, int64_t n, int64_t k, const int32_t* __restr
   const int64_t row0 = k + NB + (int64_t)blockIdx.x * NB;
   if (row0 >= n) return;   // grouped launches size the grid for the largest matrix
   if (*(volatile const int32_t*)flag) return;
-  for (int idx = tid; idx < NB * NB; idx += 256) {
-    const int r = idx / NB, c = idx % NB;
-    Ab[r * LDP + c] = (row0 + r < n) ? A[(row0 + r) * n + k + c] : 0.0;
-    Db[r * LDP + c] = Dkk[r * NB + c];
+  // All 32 loads in flight before the first LDS store (a loop of load, wait, store pays the memory
+  // latency 16 times). A row past n loads row n - 1 of the same block instead and is zeroed.
+  constexpr int PER = NB * NB / 256;
+  double ag[PER], dg[PER];
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int r = (tid + 256 * u) / NB, c = (tid + 256 * u) % NB;
+    ag[u] = A[min<int64_t>(row0 + r, n - 1) * n + k + c];
+    dg[u] = Dkk[r * NB + c];
+  }
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int r = (tid + 256 * u) / NB, c = (tid + 256 * u) % NB;
+    Ab[r * LDP + c] = (row0 + r < n) ? ag[u] : 0.0;
+    Db[r * LDP + c] = dg[u];
   }
   __syncthreads();
   const int ty = tid / 16, tx = tid % 16;
@@ -261,10 +273,21 @@ update_kernel(double* __restrict__ A, int64_t n, int64_t k, const int32_t* __res
   const int64_t base = k + NB;
   const int64_t ri = base + I * NB, rj = base + J * NB;
   const int tid = threadIdx.x;
-  for (int idx = tid; idx < NB * NB; idx += 256) {
-    const int r = idx / NB, c = idx % NB;
-    PI[r * LDP + c] = (ri + r < n) ? A[(ri + r) * n + k + c] : 0.0;
-    PJ[r * LDP + c] = (rj + r < n) ? A[(rj + r) * n + k + c] : 0.0;
+  // All 32 loads in flight before the first LDS store; a row past n loads row n - 1 of the same
+  // block instead and is zeroed.
+  constexpr int PER = NB * NB / 256;
+  double pi[PER], pj[PER];
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int r = (tid + 256 * u) / NB, c = (tid + 256 * u) % NB;
+    pi[u] = A[min<int64_t>(ri + r, n - 1) * n + k + c];
+    pj[u] = A[min<int64_t>(rj + r, n - 1) * n + k + c];
+  }
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int r = (tid + 256 * u) / NB, c = (tid + 256 * u) % NB;
+    PI[r * LDP + c] = (ri + r < n) ? pi[u] : 0.0;
+    PJ[r * LDP + c] = (rj + r < n) ? pj[u] : 0.0;
   }
   __syncthreads();
   const int lane = tid & 63, wave = tid >> 6;
@@ -287,6 +310,13 @@ update_kernel(double* __restrict__ A, int64_t n, int64_t k, const int32_t* __res
 #pragma unroll
       for (int b = 0; b < 2; ++b) acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
   }
+  // The 16 old values are read together (indices clamped into the tile's own rows and columns,
+  // so every read is in bounds), then written back through a buffer resource based at the tile's
+  // origin: an entry that must not be written (past n, or above the diagonal of a diagonal tile)
+  // gets an offset past the record count and the hardware drops that store, so the stores need
+  // no branch and no wait between them. Offsets stay below 64 n * 8 bytes, far under 2^31 for
+  // any n whose n x n FP64 matrix fits in device memory.
+  double old[2][2][4];
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
@@ -295,7 +325,21 @@ update_kernel(double* __restrict__ A, int64_t n, int64_t k, const int32_t* __res
       for (int r = 0; r < 4; ++r) {
         const int64_t gi = ri + wy * 32 + a * 16 + kq + 4 * r;
         const int64_t gj = rj + wx * 32 + b * 16 + l16;
-        if (gi < n && gj <= gi) A[gi * n + gj] -= acc[a][b][r];
+        old[a][b][r] = A[min<int64_t>(gi, n - 1) * n + min<int64_t>(gj, n - 1)];
+      }
+  constexpr int OOB = 0x7FFFFFF0;
+  const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(A + ri * n + rj, 0, OOB, 0x00020000);
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int li = wy * 32 + a * 16 + kq + 4 * r, lj = wx * 32 + b * 16 + l16;
+        const bool keep = ri + li < n && rj + lj <= ri + li;
+        const int off = keep ? (int)((li * n + lj) * 8) : OOB;
+        const double v = old[a][b][r] - acc[a][b][r];
+        __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), rs, off, 0, 0);
       }
 }
 
