@@ -109,8 +109,17 @@ fwd_step_kernel(const double* __restrict__ L, int64_t n, const double* __restric
     const int i = tid & 63, g = tid >> 6;
     const double* D = Dinv + k * NB * NB;
     double s = 0.0;
-    for (int c = g * 16; c < g * 16 + 16; ++c)
-      if (c < nb) s = fma(D[i * NB + c], r[r0 + c], s);
+    // the 32 loads first (columns past nb read column 0 of r and are skipped), then the sum in
+    // column order
+    const int c0 = g * 16;
+    double dv[16], rv[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      dv[u] = D[i * NB + c0 + u];
+      rv[u] = r[r0 + (c0 + u < nb ? c0 + u : 0)];
+    }
+#pragma unroll
+    for (int u = 0; u < 16; ++u) s = (c0 + u < nb) ? fma(dv[u], rv[u], s) : s;
     part[g][i] = s;
   }
   __syncthreads();
@@ -172,8 +181,17 @@ bwd_step_kernel(const double* __restrict__ L, int64_t n, const double* __restric
     const int i = tid & 63, g = tid >> 6;
     const double* D = Dinv + k * NB * NB;
     double s = 0.0;
-    for (int c = g * 16; c < g * 16 + 16; ++c)
-      if (c < nb) s = fma(D[c * NB + i], r[r0 + c], s);
+    // the 32 loads first (columns past nb read column 0 of r and are skipped), then the sum in
+    // column order
+    const int c0 = g * 16;
+    double dv[16], rv[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      dv[u] = D[(c0 + u) * NB + i];
+      rv[u] = r[r0 + (c0 + u < nb ? c0 + u : 0)];
+    }
+#pragma unroll
+    for (int u = 0; u < 16; ++u) s = (c0 + u < nb) ? fma(dv[u], rv[u], s) : s;
     part[g][i] = s;
   }
   __syncthreads();
