@@ -3,17 +3,19 @@
 Workload (default): n = 4096 samples, m = 4,000,000 parameters, FP32 S = G / sqrt(n) with G iid
 N(0,1), column-centered, v iid N(0,1), lambda in {1e-2, 1e-4, 1e-6}; the Gram in scaled FP8
 (E4M3 with a power-of-two scale per 32 columns, FP32 accumulation, FP64 across k-slices, exact
-FP64 diagonal), FP64 Cholesky / triangular solves and one FP64 refinement sweep. One step = one
-independent one-shot solve per lambda (three solves, each forming its own Gram). Inputs are
-drawn on the device before timing starts.
+FP64 diagonal), FP64 Cholesky / triangular solves and the library's automatic refinement sweep
+count (two FP64 sweeps at this shape). One step = one independent one-shot solve per lambda
+(three solves, each forming its own Gram). Inputs are drawn on the device before timing starts.
 
-Also reported on the same line: the plain FP32 path and the split-BF16 path on the same workload,
-the batched path (n = 2048, m = 2M, 16 lambdas x 8 right-hand sides sharing one Gram) and the
-uneven batch (64 problems of log-uniform sizes), each with sampled errors against FP64.
+Also reported on the same line: the plain FP32 path and the split-BF16 path on the same workload;
+an error table over Gram precision x sweeps x lambda (relative error of x, eps_Sy =
+|S^T (y - y*)| / |S^T y*| and the final W-residual, all against FP64); the paper-scale plain FP32
+workload (n = 1024, m = 1M, column-scaled S, v in the row space, lambda = 1e-3); the batched path
+(n = 2048, m = 2M, 16 lambdas x 8 right-hand sides sharing one Gram) and the uneven batch
+(64 problems of log-uniform sizes), each with the errors of every solve against FP64.
 
 Printed: one JSON line with solves/s (value), the Gram kernel's roofline position (timed with
-HIP events on the stream it runs on), the plain FP32 path for comparison, the relative error of
-each solve against an FP64 reference, and the FP64 CPU oracle's throughput on a bounded sample.
+HIP events on the stream it runs on), and the FP64 CPU oracle's throughput on a bounded sample.
 """
 from __future__ import annotations
 
@@ -67,6 +69,56 @@ def fp64_reference(S, v, lams, chunk=131072):
     return xs
 
 
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+_ONE_CORE = r"""
+import json, sys, time
+sys.path.insert(0, sys.argv[1])
+import numpy as np
+import oracle, synth
+out = {"threads": oracle.num_threads()}
+# smallest workload: n = 32, m = 1024, lambda = 1e-2, the whole solve
+S = synth.make_S(32, 1024, synth.seed(1), "iid"); v = synth.make_v(S, synth.seed(1), "iid")
+t0 = time.perf_counter(); reps = 0
+while time.perf_counter() - t0 < 1.0:
+    oracle.solve(S, v, 1e-2); reps += 1
+out["c1_solves_per_s"] = reps / (time.perf_counter() - t0)
+# paper-scale workload n = 1024, m = 1M: Gram, S v and the apply on a column sample (scaled by
+# m / sample), the Cholesky and the triangular solves at full n
+ms = int(sys.argv[2])
+S = synth.make_S(1024, ms, synth.seed(2), "scaled"); v = synth.make_v(S, synth.seed(2), "scaled")
+t0 = time.perf_counter(); W = oracle.gram(S, 1e-3); b = oracle.gemv(S, v); t1 = time.perf_counter()
+L, info = oracle.cholesky(W); y = oracle.backward(L, oracle.forward(L, b)); t2 = time.perf_counter()
+oracle.apply(S, v, y, 1e-3); t3 = time.perf_counter()
+out["c2_seconds_estimate"] = (t1 - t0 + t3 - t2) * (1_000_000 / ms) + (t2 - t1)
+out["c2_solves_per_s"] = 1.0 / out["c2_seconds_estimate"]
+out["c2_sample_columns"] = ms
+print(json.dumps(out))
+"""
+
+
+def cpu_one_core(m_sample=8192):
+    """The oracle on one host core (OMP_NUM_THREADS=1, a child process that touches no GPU) for the
+    smallest workload (whole solves) and the paper-scale workload (column sample, scaled)."""
+    import subprocess
+
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    r = subprocess.run([sys.executable, "-c", _ONE_CORE, ROOT, str(m_sample)], env=env, capture_output=True,
+                       text=True, timeout=600)
+    if r.returncode != 0:
+        return {"error": r.stderr[-500:]}
+    return json.loads(r.stdout.strip().splitlines()[-1])
+
+
 def cpu_baseline(S, v, lam, m_sample):
     """The FP64 oracle on the host on a column sample of the same workload: the Gram, S v and the
     final apply run on m_sample columns and are scaled by m / m_sample (they are linear in m); the
@@ -96,6 +148,7 @@ def cpu_baseline(S, v, lam, m_sample):
         "value": 1.0 / t_full,
         "unit": "solves/s",
         "cores": oracle.num_threads(),
+        "cpu_model": _cpu_model(),
         "kind": "oracle",
         "sample": (f"n={n}, first {m_sample} of m={m} columns: Gram+Sv+apply timed on the sample and "
                    f"scaled x{scale:.0f}; Cholesky and triangular solves timed at full n; lambda={lam}"),
@@ -159,6 +212,37 @@ def run_path(dfl, ctx, S, v, lams, prec, sweeps, steps, warmup, xbuf, shift="on_
     return elapsed, gram_ms, avg, infos
 
 
+def _errs(x, xref, v, lam):
+    """(|x - x*| / |x*|, eps_Sy) for one solve. S^T y = v - lambda x, so
+    eps_Sy = |S^T (y - y*)| / |S^T y*| = lambda |x - x*| / |v - lambda x*| (meaningful for FP64 x)."""
+    import torch
+
+    d = torch.linalg.norm(x.double() - xref)
+    return float(d / torch.linalg.norm(xref)), float(lam * d / torch.linalg.norm(v.double() - lam * xref))
+
+
+def error_table(dfl, ctx, S, v, lams, xref, table, shift="on_failure"):
+    """Untimed FP64-output solves for each (Gram precision, sweep count) and lambda: relative error of
+    x, eps_Sy and the final residual |S v - lambda y - S S^T y| / |S v| (measured by the library)."""
+    import torch
+
+    policy = getattr(dfl, SHIFT[shift])
+    x64 = torch.empty(S.shape[1], dtype=torch.float64, device=S.device)
+    out = {}
+    for prec, sweep_list in table:
+        for sw in sweep_list:
+            row = {}
+            for lam in lams:
+                _, info = dfl.dfisher_solve(ctx, S, v, lam, gram_prec=PREC_CODE[prec], sweeps=sw, shift_policy=policy,
+                                            x=x64, x_fp64=True, final_resid=True)
+                rel, esy = _errs(x64, xref[lam], v, lam)
+                row[str(lam)] = {"rel_err": rel, "eps_Sy": esy, "w_resid": info["w_resid"],
+                                 "sweeps": info["sweeps_done"], "shift": info["shift"]}
+            out[f"{prec}/{'auto' if sw < 0 else sw}"] = row
+    del x64
+    return out
+
+
 def _fp64_x(S, v, lam, chunk=131072):
     """FP64 reference x for one (S, v, lambda) from torch FP64 products on the device."""
     import torch
@@ -180,8 +264,70 @@ def _fp64_x(S, v, lam, chunk=131072):
     return x
 
 
+def _summ(vals):
+    vals = sorted(vals)
+    return {"max": vals[-1], "median": vals[len(vals) // 2], "count": len(vals)}
+
+
+def paper_scale_leg(dfl, dev, reps, n=1024, m=1_000_000, lam=1e-3, seed=2):
+    """The paper-scale plain FP32 workload: column-scaled S (scales log-uniform in [1e-3, 1]), v in
+    the row space of S plus N(0, 1e-6) noise, lambda = 1e-3; the plain FP32 path (no sweeps) and the
+    mixed paths with their automatic sweep counts."""
+    import torch
+
+    import synth
+
+    S = synth.make_S_torch(n, m, synth.seed(seed), dev, kind="scaled")
+    v = synth.make_v_torch(S, synth.seed(seed), kind="scaled")
+    ctx = dfl.dfisher_ctx_create(0)
+    xref = _fp64_x(S, v, lam)
+    out = {"workload": f"n={n} m={m}, column-scaled S, v = S^T u + N(0, 1e-6), lambda={lam}", "paths": {}}
+    x = torch.empty(m, dtype=torch.float32, device=dev)
+    x64 = torch.empty(m, dtype=torch.float64, device=dev)
+    for prec, sw in [("fp32", 0), ("fp32", 1), ("mxfp8", -1), ("bf16x3", -1)]:
+        dfl.dfisher_solve(ctx, S, v, lam, gram_prec=PREC_CODE[prec], sweeps=sw, x=x)   # warmup
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            _, info = dfl.dfisher_solve(ctx, S, v, lam, gram_prec=PREC_CODE[prec], sweeps=sw, x=x)
+        torch.cuda.synchronize()
+        el = (time.perf_counter() - t0) / reps
+        rel32, _ = _errs(x, xref, v, lam)
+        _, i64 = dfl.dfisher_solve(ctx, S, v, lam, gram_prec=PREC_CODE[prec], sweeps=sw, x=x64, x_fp64=True,
+                                   final_resid=True)
+        rel64, esy = _errs(x64, xref, v, lam)
+        out["paths"][f"{prec}/{'auto' if sw < 0 else sw}"] = {
+            "solves_per_s": 1.0 / el, "ms_per_solve": el * 1e3, "sweeps": info["sweeps_done"],
+            "shift": info["shift"], "rel_err_fp32_out": rel32, "rel_err": rel64, "eps_Sy": esy,
+            "w_resid": i64["w_resid"]}
+    dfl.dfisher_ctx_destroy(ctx)
+    del S, v, x, x64, xref
+    torch.cuda.empty_cache()
+    return out
+
+
+def _batched_ref(S, V, lams, chunk=131072):
+    """FP64 x for every (lambda, rhs) pair: one FP64 Gram, B = S V^T, one Cholesky per lambda."""
+    import torch
+
+    n, m = S.shape
+    G = torch.zeros((n, n), dtype=torch.float64, device=S.device)
+    B = torch.zeros((n, V.shape[0]), dtype=torch.float64, device=S.device)
+    for c0 in range(0, m, chunk):
+        blk = S[:, c0:c0 + chunk].double()
+        G += blk @ blk.T
+        B += blk @ V[:, c0:c0 + chunk].double().T.contiguous()
+        del blk
+    Ys = []
+    for lam in lams:
+        L = torch.linalg.cholesky(G + lam * torch.eye(n, dtype=torch.float64, device=S.device))
+        Ys.append(torch.cholesky_solve(B, L))   # n x nrhs
+    return Ys
+
+
 def batched_leg(dfl, dev, prec, sweeps, reps, n=2048, m=2_000_000, nlam=16, nrhs=8, seed=4):
-    """Many lambdas x right-hand sides sharing one S: one dfisher_solve_batched call per step."""
+    """Many lambdas x right-hand sides sharing one S: one dfisher_solve_batched call per step. The
+    errors of all nlam x nrhs solves are measured against FP64 (x and eps_Sy from an FP64-output call)."""
     import torch
 
     import synth
@@ -198,22 +344,39 @@ def batched_leg(dfl, dev, prec, sweeps, reps, n=2048, m=2_000_000, nlam=16, nrhs
         _, infos = dfl.dfisher_solve_batched(ctx, S, lams, V, gram_prec=PREC_CODE[prec], sweeps=sweeps, X=X)
     torch.cuda.synchronize()
     el = (time.perf_counter() - t0) / reps
-    errs = {}
-    for li, r in [(0, 0), (nlam // 2, nrhs - 1), (nlam - 1, 1)]:
-        x = _fp64_x(S, V[r], lams[li])
-        errs[f"lam={lams[li]:.3g},rhs={r}"] = float(torch.linalg.norm(X[li, r].double() - x) / torch.linalg.norm(x))
+    X64 = torch.empty((nlam, nrhs, m), dtype=torch.float64, device=dev)
+    dfl.dfisher_solve_batched(ctx, S, lams, V, gram_prec=PREC_CODE[prec], sweeps=sweeps, X=X64, x_fp64=True)
+    Ys = _batched_ref(S, V, lams)
+    Yall = torch.stack([Y for Y in Ys], dim=1).reshape(n, nlam * nrhs)   # column l * nrhs + r
+    lamv = torch.tensor(lams, dtype=torch.float64, device=dev)[:, None, None]
+    acc = {k: torch.zeros((nlam, nrhs), dtype=torch.float64, device=dev) for k in ("d32", "d64", "x", "sty")}
+    for c0 in range(0, m, 131072):
+        c1 = min(m, c0 + 131072)
+        T = (S[:, c0:c1].double().T @ Yall).T.reshape(nlam, nrhs, c1 - c0)   # S^T y* for every pair
+        Xr = (V[:, c0:c1].double()[None] - T) / lamv
+        acc["d32"] += ((X[:, :, c0:c1].double() - Xr) ** 2).sum(-1)
+        acc["d64"] += ((X64[:, :, c0:c1] - Xr) ** 2).sum(-1)
+        acc["x"] += (Xr ** 2).sum(-1)
+        acc["sty"] += (T ** 2).sum(-1)
+        del T, Xr
+    rel32 = (acc["d32"].sqrt() / acc["x"].sqrt()).flatten().tolist()
+    rel64 = (acc["d64"].sqrt() / acc["x"].sqrt()).flatten().tolist()
+    esy = (lamv[:, :, 0] * acc["d64"].sqrt() / acc["sty"].sqrt()).flatten().tolist()
     dfl.dfisher_ctx_destroy(ctx)
-    del S, V, X
+    del S, V, X, X64, Ys
     torch.cuda.empty_cache()
     return {"workload": f"batched: n={n} m={m}, {nlam} lambdas log-spaced in [1e-6, 1e-1] x {nrhs} iid right-hand "
                         "sides, one shared Gram",
-            "gram": prec, "sweeps": sweeps, "solves_per_s": nlam * nrhs / el, "ms_per_call": el * 1e3,
-            "rel_err_sampled": errs, "max_shift": max(i["shift"] for i in infos)}
+            "gram": prec, "sweeps": infos[0]["sweeps_done"], "solves_per_s": nlam * nrhs / el, "ms_per_call": el * 1e3,
+            "rel_err_fp32_out": _summ(rel32), "rel_err": _summ(rel64), "eps_Sy": _summ(esy),
+            "max_shift": max(i["shift"] for i in infos)}
 
 
 def uneven_leg(dfl, dev, prec, sweeps, reps, nprob=64, seed=5):
     """64 independent problems, n log-uniform in [256, 2048], m log-uniform in [1e5, 2e6],
-    lambda log-uniform in [1e-5, 1e-2]: one dfisher_solve_uneven call per step."""
+    lambda log-uniform in [1e-5, 1e-2]: one dfisher_solve_uneven call per step. Every problem's
+    error is measured against FP64 (x and eps_Sy from an FP64-output call that also reports the
+    final residual)."""
     import torch
 
     import synth
@@ -235,21 +398,40 @@ def uneven_leg(dfl, dev, prec, sweeps, reps, nprob=64, seed=5):
         _, infos = dfl.dfisher_solve_uneven(ctx, Ss, vs, lams, gram_prec=PREC_CODE[prec], sweeps=sweeps, xs=xs)
     torch.cuda.synchronize()
     el = (time.perf_counter() - t0) / reps
-    errs = {}
-    order = sorted(range(nprob), key=lambda p: int(ns[p]) * int(ns[p]) * int(ms[p]))
-    for p in [order[0], order[nprob // 2], order[-1]]:
-        x = _fp64_x(Ss[p], vs[p], lams[p])
-        errs[f"n={int(ns[p])},m={int(ms[p])}"] = float(torch.linalg.norm(xs[p].double() - x) / torch.linalg.norm(x))
+    x64s = [torch.empty(int(m), dtype=torch.float64, device=dev) for m in ms]
+    _, inf64 = dfl.dfisher_solve_uneven(ctx, Ss, vs, lams, gram_prec=PREC_CODE[prec], sweeps=sweeps, xs=x64s,
+                                        x_fp64=True, final_resid=True)
+    rel32, rel64, esy, per = [], [], [], []
+    for p in range(nprob):
+        xr = _fp64_x(Ss[p], vs[p], lams[p])
+        r32, _ = _errs(xs[p], xr, vs[p], lams[p])
+        r64, e = _errs(x64s[p], xr, vs[p], lams[p])
+        rel32.append(r32)
+        rel64.append(r64)
+        esy.append(e)
+        per.append([int(ns[p]), int(ms[p]), lams[p], infos[p]["sweeps_done"], r32, e, inf64[p]["w_resid"]])
+        del xr
+    worst = max(range(nprob), key=lambda q: esy[q])
     dfl.dfisher_ctx_destroy(ctx)
     out = {"workload": f"uneven: {nprob} problems, n log-uniform [256, 2048], m log-uniform [1e5, 2e6], "
                        "lambda log-uniform [1e-5, 1e-2], one right-hand side each",
-           "gram": prec, "sweeps": sweeps, "solves_per_s": nprob / el, "ms_per_call": el * 1e3,
+           "gram": prec, "sweeps": "auto" if sweeps < 0 else sweeps,
+           "sweeps_per_problem": _summ([i["sweeps_done"] for i in infos]),
+           "solves_per_s": nprob / el, "ms_per_call": el * 1e3,
            "S_GB": sum(4.0 * int(n) * int(m) for n, m in zip(ns, ms)) / 1e9,
-           "gram_flops": sum(float(n) * (n + 1) * m for n, m in zip(ns, ms)),
-           "rel_err_sampled": errs, "retried": sum(1 for i in infos if i["attempts"] > 1)}
-    del Ss, vs, xs
+           "gram_flops": float(sum(float(n) * (n + 1) * m for n, m in zip(ns, ms))),
+           "rel_err_fp32_out": _summ(rel32), "rel_err": _summ(rel64), "eps_Sy": _summ(esy),
+           "w_resid": _summ([i["w_resid"] for i in inf64]),
+           "worst_problem": dict(zip(["n", "m", "lambda", "sweeps", "rel_err_fp32_out", "eps_Sy", "w_resid"],
+                                     per[worst])),
+           "retried": sum(1 for i in infos if i["attempts"] > 1)}
+    del Ss, vs, xs, x64s
     torch.cuda.empty_cache()
     return out
+
+
+def _sweeps_arg(s):
+    return -1 if s == "auto" else int(s)
 
 
 def main() -> int:
@@ -260,17 +442,19 @@ def main() -> int:
     ap.add_argument("--n", type=int, default=4096)
     ap.add_argument("--m", type=int, default=4_000_000)
     ap.add_argument("--prec", default="mxfp8", choices=sorted(PREC_CODE))
-    ap.add_argument("--sweeps", type=int, default=1)
+    ap.add_argument("--sweeps", type=_sweeps_arg, default=-1, help="refinement sweeps, or 'auto' (the default)")
     ap.add_argument("--shift", default="on_failure", choices=sorted(SHIFT),
                     help="Cholesky shift policy of the mixed path")
     ap.add_argument("--lams", default="1e-2,1e-4,1e-6")
     ap.add_argument("--fp32-steps", type=int, default=1, help="timed steps of the plain FP32 path (0: skip)")
     ap.add_argument("--no-ref", action="store_true", help="skip the FP64 error check")
+    ap.add_argument("--no-table", action="store_true", help="skip the precision x sweeps error table")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-m", type=int, default=8192)
     ap.add_argument("--seed", type=int, default=3)
     ap.add_argument("--alt-prec", default="bf16x3", choices=sorted(PREC_CODE) + ["none"],
                     help="second mixed precision timed for comparison (none: skip)")
+    ap.add_argument("--no-paper-scale", action="store_true", help="skip the n=1024, m=1M plain FP32 workload")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched multi-lambda/RHS leg")
     ap.add_argument("--no-uneven", action="store_true", help="skip the uneven-batch leg")
     ap.add_argument("--leg-reps", type=int, default=3, help="timed calls of the batched and uneven legs")
@@ -311,8 +495,10 @@ def main() -> int:
     ctx = dfl.dfisher_ctx_create(0)
     dfl.dfisher_ctx_enable_timing(ctx, True)
     xbuf = {lam: torch.empty(m, dtype=torch.float32, device=dev) for lam in lams}
+    sweeps_resolved = dfl.dfisher_auto_sweeps(PREC_CODE[args.prec], n, m) if args.sweeps < 0 else args.sweeps
 
-    log(f"[bench] mixed path: {args.prec} Gram + {args.sweeps} sweep(s), {args.warmup} warmup + {args.steps} steps")
+    log(f"[bench] mixed path: {args.prec} Gram + {args.sweeps} sweep(s) (resolved {sweeps_resolved}), "
+        f"{args.warmup} warmup + {args.steps} steps")
     elapsed, gram_ms, stage_avg, infos = run_path(dfl, ctx, S, v, lams, args.prec, args.sweeps, args.steps,
                                                   args.warmup, xbuf, args.shift)
     solves = args.steps * len(lams)
@@ -345,36 +531,50 @@ def main() -> int:
         xbalt = {lam: torch.empty(m, dtype=torch.float32, device=dev) for lam in lams}
         ea, ga, sta, infa = run_path(dfl, ctx, S, v, lams, args.alt_prec, args.sweeps, 1, 1, xbalt, args.shift)
         gaavg = sum(ga) / len(ga)
-        alt = {"gram": args.alt_prec, "sweeps": args.sweeps, "solves_per_s": len(lams) / ea, "gram_ms": gaavg,
-               "gram_tflops_algorithmic": algo_flops / (gaavg * 1e-3) / 1e12,
+        alt = {"gram": args.alt_prec, "sweeps": infa[0][1]["sweeps_done"], "solves_per_s": len(lams) / ea,
+               "gram_ms": gaavg, "gram_tflops_algorithmic": algo_flops / (gaavg * 1e-3) / 1e12,
                "gram_mfma_frac_hw": algo_flops * PASSES[args.alt_prec] / (gaavg * 1e-3) / 1e12
                / PEAK_TFLOPS[args.alt_prec],
                "stage_ms": sta, "shifts": {str(l): i["shift"] for l, i in infa}}
         log(f"[bench] {args.alt_prec}: {alt['solves_per_s']:.3f} solves/s, gram {gaavg:.2f} ms")
 
     errors = None
+    table = None
     if not args.no_ref:
         log("[bench] FP64 reference for the error report")
         xref = fp64_reference(S, v, lams)
         errors = {"mixed": {}, "fp32": {}, "alt": {}}
         for lam in lams:
-            r = xref[lam]
-            nr = torch.linalg.norm(r)
-            errors["mixed"][str(lam)] = float(torch.linalg.norm(x_mixed[lam].double() - r) / nr)
+            errors["mixed"][str(lam)] = _errs(x_mixed[lam], xref[lam], v, lam)[0]
             if fp32 is not None:
-                errors["fp32"][str(lam)] = float(torch.linalg.norm(xb32[lam].double() - r) / nr)
+                errors["fp32"][str(lam)] = _errs(xb32[lam], xref[lam], v, lam)[0]
             if alt is not None:
-                errors["alt"][str(lam)] = float(torch.linalg.norm(xbalt[lam].double() - r) / nr)
+                errors["alt"][str(lam)] = _errs(xbalt[lam], xref[lam], v, lam)[0]
+        log(f"[bench] errors (FP32 x) {errors}")
+        if not args.no_table:
+            log("[bench] error table: precision x sweeps x lambda, FP64 x")
+            table = error_table(dfl, ctx, S, v, lams, xref,
+                                [("mxfp8", [0, 1, 2, 3]), ("bf16x3", [0, 1, 2, 3]), ("fp32", [0, 1])], args.shift)
+            log(f"[bench] table {json.dumps(table)}")
         del xref
-        log(f"[bench] errors {errors}")
 
-    # stage bandwidths (algorithmic bytes)
-    rowpass_bytes = 4.0 * n * m + 4.0 * m + 16.0 * n
+    # stage bandwidths (algorithmic bytes): the prep pass reads S (+ v) and, for the scaled-FP8 Gram,
+    # writes the codes and their scales; each refinement sweep reads S once (fused pass)
+    ldq = (m + 127) // 128 * 128
+    prep_write = {"mxfp8": n * ldq * (1 + 1 / 32), "bf16x3": 4.0 * n * ((m + 63) // 64 * 64), "fp32": 0.0}
+    rowpass_bytes = 4.0 * n * m + 4.0 * m + 16.0 * n + prep_write[args.prec]
     apply_bytes = 4.0 * n * m + 8.0 * n + 8.0 * m
+    refine_bytes = sweeps_resolved * (4.0 * n * m + 8.0 * n)
+
+    def gbs(b, ms):
+        return b / (ms * 1e-3) / 1e9 if ms else None
+
     cpu = None
     if not args.no_cpu_baseline:
         log(f"[bench] FP64 CPU oracle on a {args.cpu_sample_m}-column sample")
         cpu = cpu_baseline(S, v, lams[-1], args.cpu_sample_m)
+        log("[bench] FP64 CPU oracle on one core (smallest and paper-scale workloads)")
+        cpu["one_core"] = cpu_one_core()
         log(f"[bench] cpu baseline {cpu}")
     dfl.dfisher_ctx_destroy(ctx)
     del S, v, xbuf, x_mixed
@@ -384,6 +584,11 @@ def main() -> int:
         del xbalt
     torch.cuda.empty_cache()
 
+    paper = None
+    if not args.no_paper_scale:
+        log("[bench] paper-scale workload: n=1024 m=1M, column-scaled S, row-space v, lambda=1e-3")
+        paper = paper_scale_leg(dfl, dev, args.leg_reps)
+        log(f"[bench] paper scale {paper}")
     batched = None
     if not args.no_batched:
         log("[bench] batched leg: n=2048 m=2M, 16 lambdas x 8 right-hand sides")
@@ -410,20 +615,26 @@ def main() -> int:
         "data": "synthetic",
         "config": {"workload": f"damped Fisher solve n={n} m={m} (iid N(0,1)/sqrt(n) column-centered S, iid v), "
                                f"one solve per lambda in {lams}",
-                   "n": n, "m": m, "lambdas": lams, "gram": args.prec, "sweeps": args.sweeps, "shift": args.shift,
-                   "solves_per_step": len(lams)},
+                   "n": n, "m": m, "lambdas": lams, "gram": args.prec,
+                   "sweeps": "auto" if args.sweeps < 0 else args.sweeps, "sweeps_resolved": sweeps_resolved,
+                   "shift": args.shift, "solves_per_step": len(lams)},
         "roofline": {"bound": "mfma", "kernel": GRAM_KERNEL[args.prec], "achieved": achieved, "peak": peak,
                      "unit": "TFLOP/s", "frac": achieved / peak, "traffic": gram_traffic(args.prec, n, m),
                      "algorithmic_flops_per_launch": algo_flops, "avg_launch_ms": gram_avg_ms,
                      "mfma_util_hw": achieved * passes / peak},
         "stage_ms": stage_avg,
-        "hbm": {"rowpass_GBs": rowpass_bytes / (stage_avg.get("rowpass_ms", 0) * 1e-3) / 1e9 if stage_avg.get("rowpass_ms") else None,
-                "apply_GBs": apply_bytes / (stage_avg.get("apply_ms", 0) * 1e-3) / 1e9 if stage_avg.get("apply_ms") else None,
+        "hbm": {"rowpass_GBs": gbs(rowpass_bytes, stage_avg.get("rowpass_ms")),
+                "rowpass_bytes": rowpass_bytes,
+                "apply_GBs": gbs(apply_bytes, stage_avg.get("apply_ms")),
+                "refine_GBs": gbs(refine_bytes, stage_avg.get("refine_ms")),
+                "refine_note": "refine_ms includes the triangular solves of every sweep",
                 "peak_GBs": HBM_PEAK_GBS},
         "fp32_path": fp32,
         "alt_path": alt,
         "rel_err_vs_fp64": errors,
+        "error_table": table,
         "shifts": {str(l): i["shift"] for l, i in infos[-len(lams):]},
+        "paper_scale": paper,
         "batched": batched,
         "uneven": uneven,
         "cpu_baseline": cpu,

@@ -51,9 +51,9 @@ typedef enum dfisher_status {
   DFISHER_E_NOT_SPD = 2,       /* Cholesky met a pivot that is not > 0 (info says where) */
   DFISHER_E_NO_MEMORY = 3,     /* workspace allocation failed                            */
   DFISHER_E_DEVICE = 4,        /* no usable device, or a HIP runtime error               */
-  DFISHER_E_UNSUPPORTED = 5,   /* valid request this build does not implement            */
-  DFISHER_E_NOT_CONVERGED = 6  /* a tolerance was set and no measured refinement residual
+  DFISHER_E_NOT_CONVERGED = 5, /* a tolerance was set and no measured refinement residual
                                   met it within opt->sweeps sweeps; x is still written    */
+  DFISHER_E_UNSUPPORTED = 6    /* valid request this build does not implement            */
 } dfisher_status;
 
 /* Arithmetic of the Gram S S^T (Algorithm 1 step 1, the O(n^2 m) term of Section 2).
@@ -84,9 +84,9 @@ typedef enum dfisher_shift_policy {
 
 typedef struct dfisher_options {
   int32_t gram_prec;     /* dfisher_gram_prec                                               */
-  int32_t sweeps;        /* FP64 iterative-refinement sweeps on W y = S v, 0..16: each sweep
-                            forms r = S v - lambda y - S (S^T y) with FP64 accumulation and
-                            adds L^-T L^-1 r to y                                            */
+  int32_t sweeps;        /* FP64 iterative-refinement sweeps on W y = S v, 0..16 or
+                            DFISHER_SWEEPS_AUTO: each sweep forms r = S v - lambda y - S (S^T y)
+                            with FP64 accumulation and adds L^-T L^-1 r to y                  */
   int32_t shift_policy;  /* dfisher_shift_policy                                            */
   int32_t x_fp64;        /* 0: x (and X) are float*, 1: double*                             */
   double tol;            /* 0: run exactly `sweeps` sweeps. > 0 (dfisher_solve only; other
@@ -95,10 +95,27 @@ typedef struct dfisher_options {
                             rho_k = |r_k|_2 / |S v|_2 (one stream synchronisation per sweep),
                             apply that sweep's correction, and stop once rho_k <= tol; with
                             `sweeps` as the cap. Finite and >= 0.                             */
+  int32_t final_resid;   /* 1: after the last sweep, measure the relative residual of the
+                            returned iterate, w_resid = |S v - lambda y - S (S^T y)|_2 / |S v|_2
+                            (FP64 accumulation, one more pass over S, not applied) and report
+                            it in info->w_resid. dfisher_solve and dfisher_solve_uneven only
+                            (other entry points return DFISHER_E_UNSUPPORTED). 0 or 1.        */
+  int32_t reserved;      /* must be 0                                                       */
 } dfisher_options;
 
-/* Defaults: FP32 Gram, 0 sweeps, shift on failure, FP32 output, no tolerance. */
-#define DFISHER_OPTIONS_DEFAULT {DFISHER_GRAM_FP32, 0, DFISHER_SHIFT_ON_FAILURE, 0, 0.0}
+/* opt->sweeps = DFISHER_SWEEPS_AUTO lets the library choose the sweep count.
+ *   dfisher_solve: measured. After each sweep's residual rho_k = |r_k| / |S v| (one stream
+ *     synchronisation per sweep) the correction is applied, and the sweeps stop once the
+ *     residual expected of the corrected iterate, rho_k * min(1, rho_k / rho_{k-1}) with
+ *     rho_{-1} = 1, is <= opt->tol (1e-7 when opt->tol is 0); at most 16 sweeps, else
+ *     DFISHER_E_NOT_CONVERGED with x written. info->resid is the last rho_k.
+ *   dfisher_factor_create, dfisher_solve_batched, dfisher_solve_uneven (no host round trip per
+ *     sweep): the a-priori count of dfisher_auto_sweeps for each problem's shape, raised where
+ *     the factorisation was shifted (the batched call uses the largest count of its lambdas). */
+#define DFISHER_SWEEPS_AUTO (-1)
+
+/* Defaults: FP32 Gram, 0 sweeps, shift on failure, FP32 output, no tolerance, no final residual. */
+#define DFISHER_OPTIONS_DEFAULT {DFISHER_GRAM_FP32, 0, DFISHER_SHIFT_ON_FAILURE, 0, 0.0, 0, 0}
 
 typedef struct dfisher_info {
   int64_t potrf_info;    /* 0, or the 1-based index of the first pivot that is not > 0 in the
@@ -110,6 +127,8 @@ typedef struct dfisher_info {
                             the iterate that sweep corrected, measured before the correction;
                             the returned iterate's is smaller by about the contraction factor);
                             -1 when not measured (tol == 0 or no sweep)                         */
+  double w_resid;        /* with opt->final_resid = 1: |S v - lambda y - S (S^T y)|_2 / |S v|_2 of the
+                            returned y (FP64); -1 when not measured                             */
 } dfisher_info;
 
 typedef struct dfisher_ctx dfisher_ctx;        /* device id, workspace, pinned status buffer  */
@@ -255,6 +274,17 @@ DFISHER_API dfisher_status dfisher_autotune_gram(dfisher_ctx* ctx, const float* 
 DFISHER_API dfisher_status dfisher_ctx_enable_autotune(dfisher_ctx* ctx, int32_t enable);
 DFISHER_API dfisher_status dfisher_ctx_save_tuning(const dfisher_ctx* ctx, const char* path);
 DFISHER_API dfisher_status dfisher_ctx_load_tuning(dfisher_ctx* ctx, const char* path);
+
+/* The refinement sweep count that DFISHER_SWEEPS_AUTO picks for one problem of n samples and m
+ * parameters with the Gram in `prec` and no factored shift (a shift can only raise it; the
+ * solves re-evaluate it once the factorisation's shift is known). One y-level sweep multiplies
+ * the error of y = W^-1 S v by about c = |W~^-1 E| (E: error of the computed Gram, whose
+ * diagonal is exact); the model c = C / (sqrt(m/n) (1 - sqrt(n/m))^2) with C = 0.1 (scaled FP8),
+ * 1e-4 (split-BF16), 1e-5 (FP32) bounds the contraction of a Gram of rows with many independent
+ * entries, and the count is the smallest k with c^(k+1) <= 1e-7 (at most 16). It is a heuristic:
+ * for a guaranteed residual use opt->tol with dfisher_solve. Returns -1 for an unknown prec or
+ * n, m < 1. */
+DFISHER_API int32_t dfisher_auto_sweeps(int32_t prec, int64_t n, int64_t m);
 
 /* Static text for a status code. */
 DFISHER_API const char* dfisher_status_string(dfisher_status s);

@@ -23,7 +23,7 @@ __all__ = [
     "dfisher_gram", "dfisher_quantize_mxfp8", "dfisher_potrf", "dfisher_gemv",
     "dfisher_trsv", "dfisher_apply", "dfisher_solve", "dfisher_factor_create", "dfisher_factor_solve",
     "dfisher_factor_copy_L", "dfisher_factor_destroy", "dfisher_solve_batched", "dfisher_solve_uneven",
-    "dfisher_status_string", "dfisher_last_error",
+    "dfisher_status_string", "dfisher_last_error", "dfisher_auto_sweeps", "DFISHER_SWEEPS_AUTO",
 ]
 
 DFISHER_OK = 0
@@ -31,8 +31,9 @@ DFISHER_E_INVALID_ARG = 1
 DFISHER_E_NOT_SPD = 2
 DFISHER_E_NO_MEMORY = 3
 DFISHER_E_DEVICE = 4
-DFISHER_E_UNSUPPORTED = 5
-DFISHER_E_NOT_CONVERGED = 6
+DFISHER_E_NOT_CONVERGED = 5
+DFISHER_SWEEPS_AUTO = -1
+DFISHER_E_UNSUPPORTED = 6
 DFISHER_GRAM_FP32 = 0
 DFISHER_GRAM_BF16X3 = 1
 DFISHER_GRAM_MXFP8 = 2
@@ -46,16 +47,18 @@ LIB_PATH = os.path.join(_HERE, "libdfisher.so")
 
 class _Options(ctypes.Structure):
     _fields_ = [("gram_prec", ctypes.c_int32), ("sweeps", ctypes.c_int32),
-                ("shift_policy", ctypes.c_int32), ("x_fp64", ctypes.c_int32), ("tol", ctypes.c_double)]
+                ("shift_policy", ctypes.c_int32), ("x_fp64", ctypes.c_int32), ("tol", ctypes.c_double),
+                ("final_resid", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class Info(ctypes.Structure):
     _fields_ = [("potrf_info", ctypes.c_int64), ("shift", ctypes.c_double),
-                ("attempts", ctypes.c_int32), ("sweeps_done", ctypes.c_int32), ("resid", ctypes.c_double)]
+                ("attempts", ctypes.c_int32), ("sweeps_done", ctypes.c_int32), ("resid", ctypes.c_double),
+                ("w_resid", ctypes.c_double)]
 
     def as_dict(self):
         return {"potrf_info": self.potrf_info, "shift": self.shift, "attempts": self.attempts,
-                "sweeps_done": self.sweeps_done, "resid": self.resid}
+                "sweeps_done": self.sweeps_done, "resid": self.resid, "w_resid": self.w_resid}
 
 
 class Timing(ctypes.Structure):
@@ -98,6 +101,7 @@ def _load():
         "dfisher_ctx_save_tuning": ([P, ctypes.c_char_p], I32),
         "dfisher_ctx_load_tuning": ([P, ctypes.c_char_p], I32),
         "dfisher_ctx_last_timing": ([P, ctypes.POINTER(Timing)], I32),
+        "dfisher_auto_sweeps": ([I32, I64, I64], I32),
         "dfisher_status_string": ([I32], ctypes.c_char_p),
         "dfisher_last_error": ([], ctypes.c_char_p),
     }
@@ -181,8 +185,15 @@ def _vec(t, length, dtype, name):
         raise ValueError(f"{name} must be contiguous with {length} elements")
 
 
-def _options(gram_prec, sweeps, shift_policy, x_fp64):
-    return _Options(int(gram_prec), int(sweeps), int(shift_policy), 1 if x_fp64 else 0)
+def _options(gram_prec, sweeps, shift_policy, x_fp64, final_resid=False):
+    o = _Options(int(gram_prec), int(sweeps), int(shift_policy), 1 if x_fp64 else 0)
+    o.final_resid = 1 if final_resid else 0
+    return o
+
+
+def dfisher_auto_sweeps(gram_prec: int, n: int, m: int) -> int:
+    """The sweep count DFISHER_SWEEPS_AUTO picks for an n x m problem (no shift); -1 for bad input."""
+    return int(_lib().dfisher_auto_sweeps(int(gram_prec), int(n), int(m)))
 
 
 class _Handle:
@@ -333,7 +344,7 @@ def dfisher_apply(ctx, S, v, y, lam: float, x=None, x_fp64: bool = False, stream
 
 def dfisher_solve(ctx, S, v, lam: float, gram_prec: int = DFISHER_GRAM_FP32, sweeps: int = 0,
                   shift_policy: int = DFISHER_SHIFT_ON_FAILURE, x_fp64: bool = False, x=None, stream=None,
-                  tol: float = 0.0):
+                  tol: float = 0.0, final_resid: bool = False):
     """x solving (S^T S + lam I) x = v. Returns (x, info_dict). With tol > 0 the refinement stops at
     the tolerance (sweeps is the cap); info_dict["converged"] is False (and x is still the result)
     when the library returns DFISHER_E_NOT_CONVERGED."""
@@ -344,7 +355,7 @@ def dfisher_solve(ctx, S, v, lam: float, gram_prec: int = DFISHER_GRAM_FP32, swe
     if x is None:
         x = torch.empty(m, dtype=dt, device=S.device)
     _vec(x, m, dt, "x")
-    opt = _options(gram_prec, sweeps, shift_policy, x_fp64)
+    opt = _options(gram_prec, sweeps, shift_policy, x_fp64, final_resid)
     opt.tol = float(tol)
     info = Info()
     st = _lib().dfisher_solve(ctx.ptr, _ptr(S), n, m, lds, _ptr(v), float(lam), _ptr(x), ctypes.byref(opt),
@@ -428,7 +439,8 @@ def dfisher_solve_batched(ctx, S, lams, V, gram_prec: int = DFISHER_GRAM_FP32, s
 
 
 def dfisher_solve_uneven(ctx, Ss, vs, lams, gram_prec: int = DFISHER_GRAM_FP32, sweeps: int = 0,
-                         shift_policy: int = DFISHER_SHIFT_ON_FAILURE, x_fp64: bool = False, xs=None, stream=None):
+                         shift_policy: int = DFISHER_SHIFT_ON_FAILURE, x_fp64: bool = False, xs=None, stream=None,
+                         final_resid: bool = False):
     """Independent problems of different shapes. Returns (list of x, infos)."""
     torch = _torch()
     k = len(Ss)
@@ -449,7 +461,7 @@ def dfisher_solve_uneven(ctx, Ss, vs, lams, gram_prec: int = DFISHER_GRAM_FP32, 
     m_arr = I64Arr(*[d[1] for d in dims])
     l_arr = I64Arr(*[d[2] for d in dims])
     lam_arr = (ctypes.c_double * k)(*[float(a) for a in lams])
-    opt = _options(gram_prec, sweeps, shift_policy, x_fp64)
+    opt = _options(gram_prec, sweeps, shift_policy, x_fp64, final_resid)
     infos = (Info * k)()
     _check(_lib().dfisher_solve_uneven(ctx.ptr, k, s_arr, n_arr, m_arr, l_arr, v_arr, lam_arr, x_arr, ctypes.byref(opt),
                                     _stream(stream), infos), "dfisher_solve_uneven")

@@ -48,6 +48,7 @@ dfisher_status fail(dfisher_status s, const char* fmt, ...) {
   } while (0)
 
 constexpr int MAX_SWEEPS = 16;
+constexpr double AUTO_TOL = 1e-7;   // the residual DFISHER_SWEEPS_AUTO aims for in dfisher_solve
 constexpr int MAX_SHIFT_ATTEMPTS = 10;
 
 size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -170,15 +171,48 @@ dfisher_status check_opt(const dfisher_options* opt, dfisher_options* out) {
   if (opt) d = *opt;
   if (d.gram_prec != DFISHER_GRAM_FP32 && d.gram_prec != DFISHER_GRAM_BF16X3 && d.gram_prec != DFISHER_GRAM_MXFP8)
     return fail(DFISHER_E_INVALID_ARG, "unknown gram_prec %d", d.gram_prec);
-  if (d.sweeps < 0 || d.sweeps > MAX_SWEEPS)
-    return fail(DFISHER_E_INVALID_ARG, "sweeps = %d outside 0..%d", d.sweeps, MAX_SWEEPS);
+  if ((d.sweeps < 0 && d.sweeps != DFISHER_SWEEPS_AUTO) || d.sweeps > MAX_SWEEPS)
+    return fail(DFISHER_E_INVALID_ARG, "sweeps = %d outside 0..%d (or DFISHER_SWEEPS_AUTO)", d.sweeps, MAX_SWEEPS);
   if (d.shift_policy != DFISHER_SHIFT_NONE && d.shift_policy != DFISHER_SHIFT_ON_FAILURE &&
       d.shift_policy != DFISHER_SHIFT_ALWAYS)
     return fail(DFISHER_E_INVALID_ARG, "unknown shift_policy %d", d.shift_policy);
   if (d.x_fp64 != 0 && d.x_fp64 != 1) return fail(DFISHER_E_INVALID_ARG, "x_fp64 must be 0 or 1");
   if (!std::isfinite(d.tol) || d.tol < 0.0) return fail(DFISHER_E_INVALID_ARG, "tol must be finite and >= 0");
+  if (d.final_resid != 0 && d.final_resid != 1) return fail(DFISHER_E_INVALID_ARG, "final_resid must be 0 or 1");
+  if (d.reserved != 0) return fail(DFISHER_E_INVALID_ARG, "reserved must be 0");
   *out = d;
   return DFISHER_OK;
+}
+
+// Entry points that do not measure the final residual reject the request.
+dfisher_status check_no_final(const dfisher_options& o) {
+  if (o.final_resid != 0)
+    return fail(DFISHER_E_UNSUPPORTED, "final_resid is honoured by dfisher_solve and dfisher_solve_uneven only");
+  return DFISHER_OK;
+}
+
+// Sweep count of DFISHER_SWEEPS_AUTO. One y-level sweep multiplies the error of y by about
+// c = |W~^-1 E|, E the error of the computed Gram (its diagonal is exact). For rows of m
+// roughly independent entries, |E| ~ C_prec |s|^2 / sqrt(m/n) (C_prec ~ 2 sqrt(2) times the
+// relative rounding error of one product: E4M3 about 3e-2, the split-BF16 dropped term
+// 2^-16, FP32 accumulation within a slice) and the smallest bulk eigenvalue of S S^T is
+// about |s|^2 (1 - sqrt(n/m))^2, so c ~ C_prec / (sqrt(m/n) (1 - sqrt(n/m))^2). A factored
+// shift tau adds tau / (|s|^2 (1 - sqrt(n/m))^2) (tau_rel = tau / max_i W_ii). The count is the
+// smallest k with c^(k+1) <= 1e-7, ten times below the 1e-6 error target; capped at 16.
+int auto_sweeps(int prec, int64_t n, int64_t m, double tau_rel) {
+  const double a = (double)m / (double)n;
+  const double C = prec == DFISHER_GRAM_MXFP8 ? 0.1 : (prec == DFISHER_GRAM_BF16X3 ? 1e-4 : 1e-5);
+  const double gap = a > 4.0 ? (1.0 - 1.0 / std::sqrt(a)) * (1.0 - 1.0 / std::sqrt(a)) : 0.25;
+  double c = C / (std::sqrt(std::max(a, 1.0)) * gap);
+  if (tau_rel > 0.0) c = std::max(c, tau_rel / gap);
+  if (!(c < 0.5)) return MAX_SWEEPS;
+  int k = 0;
+  double e = c;
+  while (e > 1e-7 && k < MAX_SWEEPS) {
+    e *= c;
+    ++k;
+  }
+  return k;
 }
 
 // Entry points that run a fixed number of sweeps reject a tolerance.
@@ -347,11 +381,14 @@ dfisher_status gram_stage(const float* S, const float* v, const dfi::GramPlan& g
 // pass (t = S^T y into B.t) and a row pass. With tol > 0 (ctx given): after each residual, read
 // rho = |r| / |b| (one synchronisation), apply the correction, stop once rho <= tol. *done and
 // *resid report the sweeps applied and the last rho (-1 if none was measured).
+// With `predict` the stop test is on the residual the corrected iterate is expected to have:
+// rho_k times the contraction measured over the last sweep, rho_k / rho_{k-1} (rho_{-1} = 1, the
+// residual of y = 0), so that the sweep that brings the residual under tol is the last one.
 dfisher_status solve_y(const float* S, int64_t n, int64_t m, int64_t lds, double lambda, const double* L,
                        const double* Dinv, const SolveBufs& B, const dfi::RowPassPlan& rp, const dfi::ColPassPlan& cp,
                        int sweeps, hipStream_t st, StageClock* clk = nullptr, const dfi::RefinePassPlan* fp = nullptr,
                        dfisher_ctx* ctx = nullptr, double tol = 0.0, int* done = nullptr, double* resid = nullptr,
-                       bool initial = true) {
+                       bool initial = true, bool predict = false, bool* met = nullptr) {
   if (initial) {   // (else the caller has formed y = L^-T L^-1 b already)
     HIP_TRY(dfi::trsv_launch(L, Dinv, n, 0, B.b, B.z, B.tw, st));
     HIP_TRY(dfi::trsv_launch(L, Dinv, n, 1, B.z, B.y, B.tw, st));
@@ -361,6 +398,8 @@ dfisher_status solve_y(const float* S, int64_t n, int64_t m, int64_t lds, double
   const bool measure = ctx && tol > 0.0;
   if (done) *done = 0;
   if (resid) *resid = -1.0;
+  if (met) *met = false;
+  double prev = 1.0;
   if (measure) HIP_TRY(dfi::sumsq(B.b, n, ctx->d_scalar + 2, st));
   for (int s = 0; s < sweeps; ++s) {
     if (fused) {
@@ -384,9 +423,38 @@ dfisher_status solve_y(const float* S, int64_t n, int64_t m, int64_t lds, double
     HIP_TRY(dfi::trsv_launch(L, Dinv, n, 1, B.z, B.r, B.tw, st));
     HIP_TRY(dfi::axpy_inplace(B.y, B.r, n, st));
     if (done) *done = s + 1;
-    if (measure && rho <= tol) break;
+    if (measure) {
+      const double expect = predict ? rho * std::min(1.0, prev > 0.0 ? rho / prev : 0.0) : rho;
+      prev = rho;
+      if (expect <= tol) {
+        if (met) *met = true;
+        break;
+      }
+    }
   }
   if (clk) clk->mark(6);
+  return DFISHER_OK;
+}
+
+// r = b - lambda y - S (S^T y) for the current y (FP64), then w = |r| / |b| read back to the host
+// (one synchronisation). The residual is not applied.
+dfisher_status final_residual(dfisher_ctx* ctx, const float* S, int64_t n, int64_t m, int64_t lds, double lambda,
+                              const SolveBufs& B, const dfi::RowPassPlan& rp, const dfi::ColPassPlan& cp,
+                              const dfi::RefinePassPlan& fp, hipStream_t st, double* w) {
+  if (fp.usable) {
+    HIP_TRY(dfi::refine_pass_launch(fp, S, n, m, lds, B.y, B.rpart, st));
+    HIP_TRY(dfi::refine_pass_reduce(fp, B.rpart, B.r, B.b, B.y, lambda, st));
+  } else {
+    HIP_TRY(dfi::colpass_launch(cp, S, n, m, lds, B.y, nullptr, 1.0, B.t, 2, B.cpart, st));
+    HIP_TRY(dfi::rowpass_launch(rp, S, nullptr, B.t, true, false, B.rpart, st));
+    HIP_TRY(dfi::rowpass_reduce(rp, B.rpart, true, false, B.r, nullptr, B.b, B.y, lambda, st));
+  }
+  HIP_TRY(dfi::sumsq(B.b, n, ctx->d_scalar + 2, st));
+  HIP_TRY(dfi::sumsq(B.r, n, ctx->d_scalar + 3, st));
+  HIP_TRY(hipMemcpyAsync(ctx->h_scalar + 2, ctx->d_scalar + 2, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  const double bb = ctx->h_scalar[2], rr = ctx->h_scalar[3];
+  *w = bb > 0.0 ? std::sqrt(rr / bb) : (rr > 0.0 ? INFINITY : 0.0);
   return DFISHER_OK;
 }
 
@@ -536,6 +604,7 @@ dfisher_status tune_gram(dfisher_ctx* ctx, const float* S, int64_t n, int64_t m,
   (void)hipEventDestroy(e1);
   if (rs != DFISHER_OK) return rs;
   ctx->tune[tune_key(prec, n, m, al)] = std::make_pair(best_q, best_mode);
+  drop_graph(ctx);   // a captured uneven graph may have been laid out with the old plan
   return DFISHER_OK;
 }
 
@@ -592,6 +661,7 @@ struct UnevenLayout {
   double *b = nullptr, *d = nullptr, *y = nullptr, *z = nullptr, *r = nullptr, *wk = nullptr;
   int64_t* info = nullptr;
   int32_t* flag = nullptr;
+  double* res = nullptr;                   // final residuals: |b_p|^2, |r_p|^2 per problem
   size_t bytes = 0;
 };
 
@@ -654,13 +724,17 @@ void uneven_layout(const dfisher_ctx* ctx, char* base, int32_t np, const float* 
   U.wk = c.take<double>((size_t)U.ntot);
   U.info = c.take<int64_t>((size_t)np);
   U.flag = c.take<int32_t>((size_t)np);
+  U.res = c.take<double>((size_t)(2 * np));
   U.bytes = c.off;
 }
 
 // Enqueues the whole uneven solve on st (no host synchronisation). fjobs / tjobs: device tables.
+// sw[p]: problem p's sweep count. The job tables list the problems by decreasing sweep count, so
+// the problems still refining in sweep s are the first nactive[s] entries of each table.
 dfisher_status uneven_enqueue(dfisher_ctx* ctx, int32_t np, const float* const* S, const int64_t* n, const int64_t* m,
                               const int64_t* lds, const float* const* v, const double* lambda, void* const* x,
                               const dfisher_options& o, const UnevenLayout& U, const std::vector<int32_t>& order,
+                              const std::vector<int>& sw, const std::vector<int64_t>& nactive,
                               const dfi::FactorJob* fjobs, const dfi::TrsvJob* tj_fwd, const dfi::TrsvJob* tj_bwd,
                               const dfi::TrsvJob* tj_bwd_r, hipStream_t st) {
   (void)ctx;
@@ -689,28 +763,44 @@ dfisher_status uneven_enqueue(dfisher_ctx* ctx, int32_t np, const float* const* 
   HIP_TRY(dfi::trsv_launch_grouped(tj_fwd, np, U.nmax, 0, st));    // wk -> z
   HIP_TRY(hipMemcpyAsync(U.wk, U.z, vb, hipMemcpyDeviceToDevice, st));
   HIP_TRY(dfi::trsv_launch_grouped(tj_bwd, np, U.nmax, 1, st));    // wk -> y
-  for (int s = 0; s < o.sweeps; ++s) {
-    // r_p = b_p - lambda_p y_p - S_p (S_p^T y_p), per problem (FP64 accumulation)
-    for (int32_t p : order) {
-      const int64_t off = U.voff[(size_t)p];
-      if (U.fp[(size_t)p].usable) {   // one read of S_p
-        HIP_TRY(dfi::refine_pass_launch(U.fp[(size_t)p], S[p], n[p], m[p], lds[p], U.y + off, U.shared.rpart, st));
-        HIP_TRY(dfi::refine_pass_reduce(U.fp[(size_t)p], U.shared.rpart, U.r + off, U.b + off, U.y + off, lambda[p],
-                                        st));
-        continue;
-      }
-      HIP_TRY(dfi::colpass_launch(U.cp[(size_t)p], S[p], n[p], m[p], lds[p], U.y + off, nullptr, 1.0, U.shared.t, 2,
-                                  U.shared.cpart, st));
-      HIP_TRY(dfi::rowpass_launch(U.rp[(size_t)p], S[p], nullptr, U.shared.t, true, false, U.shared.rpart, st));
-      HIP_TRY(dfi::rowpass_reduce(U.rp[(size_t)p], U.shared.rpart, true, false, U.r + off, nullptr, U.b + off,
-                                  U.y + off, lambda[p], st));
+  // r_p = b_p - lambda_p y_p - S_p (S_p^T y_p) (FP64 accumulation)
+  auto residual = [&](int32_t p) -> dfisher_status {
+    const int64_t off = U.voff[(size_t)p];
+    if (U.fp[(size_t)p].usable) {   // one read of S_p
+      HIP_TRY(dfi::refine_pass_launch(U.fp[(size_t)p], S[p], n[p], m[p], lds[p], U.y + off, U.shared.rpart, st));
+      HIP_TRY(dfi::refine_pass_reduce(U.fp[(size_t)p], U.shared.rpart, U.r + off, U.b + off, U.y + off, lambda[p], st));
+      return DFISHER_OK;
     }
-    // delta = L^-T L^-1 r for every problem, y += delta
+    HIP_TRY(dfi::colpass_launch(U.cp[(size_t)p], S[p], n[p], m[p], lds[p], U.y + off, nullptr, 1.0, U.shared.t, 2,
+                                U.shared.cpart, st));
+    HIP_TRY(dfi::rowpass_launch(U.rp[(size_t)p], S[p], nullptr, U.shared.t, true, false, U.shared.rpart, st));
+    HIP_TRY(dfi::rowpass_reduce(U.rp[(size_t)p], U.shared.rpart, true, false, U.r + off, nullptr, U.b + off, U.y + off,
+                                lambda[p], st));
+    return DFISHER_OK;
+  };
+  const int max_sw = nactive.empty() ? 0 : (int)nactive.size();
+  for (int s = 0; s < max_sw; ++s) {
+    for (int32_t p : order) {
+      if (sw[(size_t)p] > s) {
+        DF_TRY(residual(p));
+      } else if (sw[(size_t)p] == s) {
+        // done refining: a zero correction from here on (the solves below skip it, y += 0)
+        HIP_TRY(dfi::fill_zero(U.r + U.voff[(size_t)p], n[p], st));
+      }
+    }
+    // delta = L^-T L^-1 r for the problems still refining, y += delta for all
     HIP_TRY(hipMemcpyAsync(U.wk, U.r, vb, hipMemcpyDeviceToDevice, st));
-    HIP_TRY(dfi::trsv_launch_grouped(tj_fwd, np, U.nmax, 0, st));
+    HIP_TRY(dfi::trsv_launch_grouped(tj_fwd, nactive[(size_t)s], U.nmax, 0, st));
     HIP_TRY(hipMemcpyAsync(U.wk, U.z, vb, hipMemcpyDeviceToDevice, st));
-    HIP_TRY(dfi::trsv_launch_grouped(tj_bwd_r, np, U.nmax, 1, st));  // wk -> r
+    HIP_TRY(dfi::trsv_launch_grouped(tj_bwd_r, nactive[(size_t)s], U.nmax, 1, st));  // wk -> r
     HIP_TRY(dfi::axpy_many(U.y, U.r, U.ntot, st));
+  }
+  if (o.final_resid) {   // the returned iterate's residual, per problem (not applied)
+    for (int32_t p : order) {
+      DF_TRY(residual(p));
+      HIP_TRY(dfi::sumsq(U.b + U.voff[(size_t)p], n[p], U.res + 2 * p, st));
+      HIP_TRY(dfi::sumsq(U.r + U.voff[(size_t)p], n[p], U.res + 2 * p + 1, st));
+    }
   }
   // x_p = (v_p - S_p^T y_p) / lambda_p
   for (int32_t p : order)
@@ -724,10 +814,22 @@ dfisher_status uneven_solve(dfisher_ctx* ctx, int32_t np, const float* const* S,
                             const dfisher_options& o, hipStream_t st, dfisher_info* infos) {
   if (ctx->autotune)
     for (int32_t p = 0; p < np; ++p) DF_TRY(tune_if_new(ctx, S[p], n[p], m[p], lds[p], o.gram_prec, st));
+  // sweep count per problem (DFISHER_SWEEPS_AUTO: from its precision, shape and up-front shift)
+  std::vector<int> sw((size_t)np, o.sweeps);
+  int max_sw = 0;
+  for (int32_t p = 0; p < np; ++p) {
+    if (o.sweeps == DFISHER_SWEEPS_AUTO) {
+      const double tau_rel = o.shift_policy == DFISHER_SHIFT_ALWAYS
+                                 ? 2.0 * std::sqrt((double)n[p]) * gram_unit(o.gram_prec, m[p]) : 0.0;
+      sw[(size_t)p] = auto_sweeps(o.gram_prec, n[p], m[p], tau_rel);
+    }
+    max_sw = std::max(max_sw, sw[(size_t)p]);
+  }
   UnevenLayout U;
-  uneven_layout(ctx, nullptr, np, S, n, m, lds, o.gram_prec, o.sweeps, U);
+  const int need_t = (max_sw > 0 || o.final_resid) ? 1 : 0;
+  uneven_layout(ctx, nullptr, np, S, n, m, lds, o.gram_prec, need_t, U);
   DF_TRY(ensure_ws(ctx, U.bytes));
-  uneven_layout(ctx, static_cast<char*>(ctx->ws), np, S, n, m, lds, o.gram_prec, o.sweeps, U);
+  uneven_layout(ctx, static_cast<char*>(ctx->ws), np, S, n, m, lds, o.gram_prec, need_t, U);
   // largest problems first (their Gram kernels fill the device; small ones follow)
   std::vector<int32_t> order((size_t)np);
   for (int32_t p = 0; p < np; ++p) order[(size_t)p] = p;
@@ -736,15 +838,24 @@ dfisher_status uneven_solve(dfisher_ctx* ctx, int32_t np, const float* const* S,
   });
   // job tables: factor jobs, forward solves (wk -> z, the first entry set also drives diag_inv)
   // and backward solves (wk -> y for the first solve, wk -> r inside sweeps: two tables)
+  // table entry j holds problem jord[j]: decreasing sweep count, so that the problems still
+  // refining in sweep s are a prefix of the tables (nactive[s] entries)
+  std::vector<int32_t> jord((size_t)np);
+  for (int32_t p = 0; p < np; ++p) jord[(size_t)p] = p;
+  std::stable_sort(jord.begin(), jord.end(), [&](int32_t a, int32_t b) { return sw[(size_t)a] > sw[(size_t)b]; });
+  std::vector<int64_t> nactive((size_t)max_sw, 0);
+  for (int s = 0; s < max_sw; ++s)
+    for (int32_t p = 0; p < np; ++p) nactive[(size_t)s] += sw[(size_t)p] > s ? 1 : 0;
   std::vector<dfi::FactorJob> fj((size_t)np);
   std::vector<dfi::TrsvJob> tf((size_t)np), tb((size_t)np), tr((size_t)np);
-  for (int32_t p = 0; p < np; ++p) {
+  for (int32_t j = 0; j < np; ++j) {
+    const int32_t p = jord[(size_t)j];
     const size_t q = (size_t)p;
     double* Wp = U.W + U.woff[q];
-    fj[q] = dfi::FactorJob{Wp, n[p], U.info + p, U.flag + p, U.dkk + (int64_t)p * 64 * 64};
-    tf[q] = dfi::TrsvJob{Wp, U.Dinv + U.doff[q], n[p], U.wk + U.voff[q], U.z + U.voff[q]};
-    tb[q] = dfi::TrsvJob{Wp, U.Dinv + U.doff[q], n[p], U.wk + U.voff[q], U.y + U.voff[q]};
-    tr[q] = dfi::TrsvJob{Wp, U.Dinv + U.doff[q], n[p], U.wk + U.voff[q], U.r + U.voff[q]};
+    fj[(size_t)j] = dfi::FactorJob{Wp, n[p], U.info + p, U.flag + p, U.dkk + (int64_t)p * 64 * 64};
+    tf[(size_t)j] = dfi::TrsvJob{Wp, U.Dinv + U.doff[q], n[p], U.wk + U.voff[q], U.z + U.voff[q]};
+    tb[(size_t)j] = dfi::TrsvJob{Wp, U.Dinv + U.doff[q], n[p], U.wk + U.voff[q], U.y + U.voff[q]};
+    tr[(size_t)j] = dfi::TrsvJob{Wp, U.Dinv + U.doff[q], n[p], U.wk + U.voff[q], U.r + U.voff[q]};
   }
   const size_t fbytes = align_up(fj.size() * sizeof(dfi::FactorJob));
   const size_t tbytes = align_up(tf.size() * sizeof(dfi::TrsvJob));
@@ -781,6 +892,14 @@ dfisher_status uneven_solve(dfisher_ctx* ctx, int32_t np, const float* const* S,
   put(&o, sizeof(o));
   put(&ctx->ws, sizeof(void*));
   put(&ctx->tbuf, sizeof(void*));
+  // the layout moves with the Gram plans (a tuning change alters a problem's partial-tile bytes
+  // and with them every later offset), so the plans and the layout size are part of the key
+  put(&U.bytes, sizeof(U.bytes));
+  for (int32_t p = 0; p < np; ++p) {
+    const dfi::GramPlan& g = U.gp[(size_t)p];
+    const int64_t pk[4] = {g.nslice, g.kslice, g.ldh, (int64_t)g.part_bytes};
+    put(pk, sizeof(pk));
+  }
   bool ran = false;
   if (ctx->graphs) {
     if (!ctx->uneven_exec || ctx->uneven_key != key) {
@@ -794,7 +913,8 @@ dfisher_status uneven_solve(dfisher_ctx* ctx, int32_t np, const float* const* S,
         bool ok = hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal) == hipSuccess;
         dfisher_status se = DFISHER_OK;
         if (ok)
-          se = uneven_enqueue(ctx, np, S, n, m, lds, v, lambda, x, o, U, order, d_fj, d_tf, d_tb, d_tr, ctx->cap_stream);
+          se = uneven_enqueue(ctx, np, S, n, m, lds, v, lambda, x, o, U, order, sw, nactive, d_fj, d_tf, d_tb, d_tr,
+                              ctx->cap_stream);
         if (ok) ok = hipStreamEndCapture(ctx->cap_stream, &graph) == hipSuccess && graph != nullptr;
         if (ok && se == DFISHER_OK) {
           hipGraphExec_t ex = nullptr;
@@ -812,12 +932,15 @@ dfisher_status uneven_solve(dfisher_ctx* ctx, int32_t np, const float* const* S,
       ran = true;
     }
   }
-  if (!ran) DF_TRY(uneven_enqueue(ctx, np, S, n, m, lds, v, lambda, x, o, U, order, d_fj, d_tf, d_tb, d_tr, st));
+  if (!ran)
+    DF_TRY(uneven_enqueue(ctx, np, S, n, m, lds, v, lambda, x, o, U, order, sw, nactive, d_fj, d_tf, d_tb, d_tr, st));
   std::vector<int64_t> hinfo((size_t)np);
-  std::vector<double> hmax((size_t)np, 0.0);
+  std::vector<double> hmax((size_t)np, 0.0), hres((size_t)(2 * np), -1.0);
   HIP_TRY(hipMemcpyAsync(hinfo.data(), U.info, (size_t)np * sizeof(int64_t), hipMemcpyDeviceToHost, st));
   if (o.shift_policy == DFISHER_SHIFT_ALWAYS)
     HIP_TRY(hipMemcpyAsync(hmax.data(), U.dmax, (size_t)np * sizeof(double), hipMemcpyDeviceToHost, st));
+  if (o.final_resid)
+    HIP_TRY(hipMemcpyAsync(hres.data(), U.res, (size_t)(2 * np) * sizeof(double), hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
   dfisher_status worst = DFISHER_OK;
   for (int32_t p = 0; p < np; ++p) {
@@ -825,7 +948,12 @@ dfisher_status uneven_solve(dfisher_ctx* ctx, int32_t np, const float* const* S,
     inf.resid = -1.0;
     inf.potrf_info = hinfo[(size_t)p];
     inf.attempts = 1;
-    inf.sweeps_done = o.sweeps;
+    inf.sweeps_done = sw[(size_t)p];
+    inf.w_resid = -1.0;
+    if (o.final_resid) {
+      const double bb = hres[(size_t)(2 * p)], rr = hres[(size_t)(2 * p + 1)];
+      inf.w_resid = bb > 0.0 ? std::sqrt(rr / bb) : (rr > 0.0 ? INFINITY : 0.0);
+    }
     if (o.shift_policy == DFISHER_SHIFT_ALWAYS)
       inf.shift = 2.0 * std::sqrt((double)n[p]) * gram_unit(o.gram_prec, m[p]) * hmax[(size_t)p];
     if (inf.potrf_info != 0 && o.shift_policy != DFISHER_SHIFT_NONE) {
@@ -1093,6 +1221,7 @@ dfisher_status dfisher_factor_create(dfisher_ctx* ctx, const float* S, int64_t n
   dfisher_options o;
   DF_TRY(check_opt(opt, &o));
   DF_TRY(check_no_tol(o));
+  DF_TRY(check_no_final(o));
   DF_TRY(check_prec_layout(o.gram_prec, S, lds));
   DeviceGuard g(ctx->device);
   hipStream_t st = as_stream(stream);
@@ -1130,8 +1259,14 @@ dfisher_status dfisher_factor_create(dfisher_ctx* ctx, const float* S, int64_t n
   }
   dfisher_info inf{};
   inf.resid = -1.0;
+  inf.w_resid = -1.0;
   dfisher_status s = factor_with_policy(ctx, B.W, f->L, B.dkk, n, o.shift_policy, gram_unit(o.gram_prec, m), st, &inf.shift, &inf.potrf_info,
                                        &inf.attempts);
+  if (o.sweeps == DFISHER_SWEEPS_AUTO) {   // resolved once, with the factored shift known
+    const double wmax = (o.shift_policy != DFISHER_SHIFT_NONE) ? ctx->h_scalar[0] : 0.0;
+    f->opt.sweeps = auto_sweeps(o.gram_prec, n, m, (inf.shift > 0.0 && wmax > 0.0) ? inf.shift / wmax : 0.0);
+  }
+  inf.sweeps_done = f->opt.sweeps;
   if (info) *info = inf;
   if (s != DFISHER_OK) return cleanup(s);
   if (dfi::trsv_diag_inv(f->L, n, f->Dinv, st) != hipSuccess)
@@ -1168,6 +1303,7 @@ dfisher_status dfisher_factor_solve(dfisher_factor* f, const float* V, int64_t n
     info->attempts = 0;
     info->sweeps_done = f->opt.sweeps;
     info->resid = -1.0;
+    info->w_resid = -1.0;
   }
   return DFISHER_OK;
 }
@@ -1206,7 +1342,7 @@ dfisher_status dfisher_solve(dfisher_ctx* ctx, const float* S, int64_t n, int64_
   const dfi::RowPassPlan rp = dfi::rowpass_plan(n, m, lds);
   const dfi::ColPassPlan cp = dfi::colpass_plan(n, m);
   const dfi::RefinePassPlan fp = dfi::refine_pass_plan(n, m, lds, S);
-  const bool need_t = o.sweeps > 0 && !fp.usable;
+  const bool need_t = (o.sweeps != 0 || o.final_resid) && !fp.usable;
   SolveBufs B = carve(nullptr, n, m, &gp, rp, cp, true, need_t, &fp);
   DF_TRY(ensure_ws(ctx, B.bytes));
   B = carve(static_cast<char*>(ctx->ws), n, m, &gp, rp, cp, true, need_t, &fp);
@@ -1232,17 +1368,24 @@ dfisher_status dfisher_solve(dfisher_ctx* ctx, const float* S, int64_t n, int64_
   DF_TRY(factor_with_policy(ctx, B.W, B.L, B.dkk, n, o.shift_policy, gram_unit(o.gram_prec, m), st, &inf.shift,
                             &inf.potrf_info, &inf.attempts, first_solve, &spec_ok));
   if (!spec_ok) DF_TRY(first_solve());
+  // DFISHER_SWEEPS_AUTO: measured, predictive stop at tol (default 1e-7), at most MAX_SWEEPS
+  const bool autos = o.sweeps == DFISHER_SWEEPS_AUTO;
+  const int sweeps = autos ? MAX_SWEEPS : o.sweeps;
+  const double tol = autos && !(o.tol > 0.0) ? AUTO_TOL : o.tol;
   int done = 0;
   double resid = -1.0;
-  DF_TRY(solve_y(S, n, m, lds, lambda, B.L, B.Dinv, B, rp, cp, o.sweeps, st, &clk, &fp, ctx, o.tol, &done, &resid,
-                 false));
+  bool met = false;
+  DF_TRY(solve_y(S, n, m, lds, lambda, B.L, B.Dinv, B, rp, cp, sweeps, st, &clk, &fp, ctx, tol, &done, &resid,
+                 false, autos, &met));
+  inf.w_resid = -1.0;
+  if (o.final_resid) DF_TRY(final_residual(ctx, S, n, m, lds, lambda, B, rp, cp, fp, st, &inf.w_resid));
   HIP_TRY(dfi::colpass_launch(cp, S, n, m, lds, B.y, v, lambda, x, o.x_fp64, B.cpart, st));
   clk.mark(7);
   inf.sweeps_done = done;
   inf.resid = resid;
   if (info) *info = inf;
-  if (o.tol > 0.0 && !(resid >= 0.0 && resid <= o.tol))
-    return fail(DFISHER_E_NOT_CONVERGED, "relative residual %.3g above tol %.3g after %d sweep(s)", resid, o.tol, done);
+  if (tol > 0.0 && !met)
+    return fail(DFISHER_E_NOT_CONVERGED, "relative residual %.3g above tol %.3g after %d sweep(s)", resid, tol, done);
   return DFISHER_OK;
 }
 
@@ -1261,6 +1404,7 @@ dfisher_status dfisher_solve_batched(dfisher_ctx* ctx, const float* S, int64_t n
   dfisher_options o;
   DF_TRY(check_opt(opt, &o));
   DF_TRY(check_no_tol(o));
+  DF_TRY(check_no_final(o));
   DF_TRY(check_prec_layout(o.gram_prec, S, lds));
   DeviceGuard g(ctx->device);
   hipStream_t st = as_stream(stream);
@@ -1284,7 +1428,7 @@ dfisher_status dfisher_solve_batched(dfisher_ctx* ctx, const float* S, int64_t n
     dkk = c.take<double>((size_t)nlam * 64 * 64);
     dinfo = c.take<int64_t>((size_t)nlam);
     dflag = c.take<int32_t>((size_t)nlam);
-    mb = carve_multi(c, n, m, nrhs, nvec, rm, o.sweeps > 0);
+    mb = carve_multi(c, n, m, nrhs, nvec, rm, o.sweeps != 0);
     return c.off;
   };
   SolveBufs B;
@@ -1310,12 +1454,16 @@ dfisher_status dfisher_solve_batched(dfisher_ctx* ctx, const float* S, int64_t n
   if (scale0 != 0.0) HIP_TRY(hipMemcpyAsync(&dmax, ctx->d_scalar, sizeof(double), hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
   dfisher_status worst = DFISHER_OK;
+  std::vector<dfisher_info> linf((size_t)nlam);
+  int sweeps = o.sweeps == DFISHER_SWEEPS_AUTO ? 0 : o.sweeps;   // AUTO: the largest count any lambda needs
   for (int32_t l = 0; l < nlam; ++l) {
     dfisher_info inf{};
     inf.resid = -1.0;
+    inf.w_resid = -1.0;
     inf.attempts = 1;
     inf.potrf_info = hinfo[(size_t)l];
     inf.shift = scale0 * dmax;
+    double tau_rel = scale0;
     if (inf.potrf_info != 0 && o.shift_policy != DFISHER_SHIFT_NONE) {
       // rare: refactor this lambda alone with escalating shifts (B.L holds G + lambda_l I)
       HIP_TRY(dfi::add_diag_copy(B.W, B.L, n, lambdas[l], st));
@@ -1324,13 +1472,18 @@ dfisher_status dfisher_solve_batched(dfisher_ctx* ctx, const float* S, int64_t n
                                                   st, &inf.shift, &inf.potrf_info, &att);
       inf.attempts += att;
       if (s != DFISHER_OK && s != DFISHER_E_NOT_SPD) return s;
+      tau_rel = ctx->h_scalar[0] > 0.0 ? inf.shift / ctx->h_scalar[0] : 0.0;
     }
     if (inf.potrf_info != 0) worst = DFISHER_E_NOT_SPD;
-    inf.sweeps_done = o.sweeps;
-    if (infos) infos[l] = inf;
+    if (o.sweeps == DFISHER_SWEEPS_AUTO) sweeps = std::max(sweeps, auto_sweeps(o.gram_prec, n, m, tau_rel));
+    linf[(size_t)l] = inf;
+  }
+  for (int32_t l = 0; l < nlam; ++l) {
+    linf[(size_t)l].sweeps_done = sweeps;
+    if (infos) infos[l] = linf[(size_t)l];
   }
   HIP_TRY(dfi::trsv_diag_inv_batched(Lall, n * n, n, nlam, Dall, st));
-  DF_TRY(multi_solve(S, n, m, lds, nlam, Lall, Dall, lambdas, V, nrhs, ldv, X, ldx, o.x_fp64, o.sweeps, rm, mb, st));
+  DF_TRY(multi_solve(S, n, m, lds, nlam, Lall, Dall, lambdas, V, nrhs, ldv, X, ldx, o.x_fp64, sweeps, rm, mb, st));
   if (worst != DFISHER_OK) return fail(worst, "at least one lambda failed to factor (its x is not meaningful)");
   return DFISHER_OK;
 }
@@ -1356,6 +1509,12 @@ dfisher_status dfisher_solve_uneven(dfisher_ctx* ctx, int32_t nprob, const float
   DeviceGuard g(ctx->device);
   hipStream_t st = as_stream(stream);
   return uneven_solve(ctx, nprob, S, n, m, lds, v, lambda, x, o, st, infos);
+}
+
+int32_t dfisher_auto_sweeps(int32_t prec, int64_t n, int64_t m) {
+  if (prec != DFISHER_GRAM_FP32 && prec != DFISHER_GRAM_BF16X3 && prec != DFISHER_GRAM_MXFP8) return -1;
+  if (n < 1 || m < 1) return -1;
+  return auto_sweeps(prec, n, m, 0.0);
 }
 
 dfisher_status dfisher_ctx_enable_autotune(dfisher_ctx* ctx, int32_t enable) {
@@ -1411,6 +1570,7 @@ dfisher_status dfisher_ctx_load_tuning(dfisher_ctx* ctx, const char* path) {
   std::fclose(f);
   if (st != DFISHER_OK) return st;
   for (const auto& kv : t) ctx->tune[kv.first] = kv.second;
+  drop_graph(ctx);   // a captured uneven graph may have been laid out with the old plans
   return DFISHER_OK;
 }
 

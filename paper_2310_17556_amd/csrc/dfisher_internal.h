@@ -205,6 +205,8 @@ hipError_t shift_add_copy(const double* src, double* dst, int64_t n, double scal
                           hipStream_t st);
 // y += d (length n)
 hipError_t axpy_inplace(double* y, const double* d, int64_t n, hipStream_t st);
+// y = 0 (length n; a kernel, not a memset, so that it may sit in a captured graph)
+hipError_t fill_zero(double* y, int64_t n, hipStream_t st);
 // max_i W_ii
 hipError_t diag_max(const double* W, int64_t n, double* out_dev, hipStream_t st);
 // *out_dev = sum_i x_i^2 (FP64, deterministic)

@@ -366,6 +366,11 @@ __global__ void axpy_kernel(double* __restrict__ y, const double* __restrict__ d
   if (i < n) y[i] += d[i];
 }
 
+__global__ void fill_zero_kernel(double* __restrict__ y, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = 0.0;
+}
+
 __global__ void diag_max_kernel(const double* __restrict__ W, int64_t n, double* __restrict__ out) {
   __shared__ double red[256];
   double mx = 0.0;
@@ -488,6 +493,12 @@ hipError_t shift_add_copy(const double* src, double* dst, int64_t n, double scal
 
 hipError_t axpy_inplace(double* y, const double* d, int64_t n, hipStream_t st) {
   hipLaunchKernelGGL(axpy_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, y, d, n);
+  return hipGetLastError();
+}
+
+hipError_t fill_zero(double* y, int64_t n, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(fill_zero_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, y, n);
   return hipGetLastError();
 }
 

@@ -54,8 +54,8 @@ FAKE_CTX = ctypes.c_void_p(0x1000)   # never dereferenced: every call below fail
 FAKE_DEV = ctypes.c_void_p(0x2000)
 
 
-def _opts(dfl, prec=0, sweeps=0, shift=1, x64=0, tol=0.0):
-    return dfl._Options(prec, sweeps, shift, x64, tol)
+def _opts(dfl, prec=0, sweeps=0, shift=1, x64=0, tol=0.0, final=0, reserved=0):
+    return dfl._Options(prec, sweeps, shift, x64, tol, final, reserved)
 
 
 def test_invalid_arguments_rejected_on_host(dfl):
@@ -77,8 +77,9 @@ def test_invalid_arguments_rejected_on_host(dfl):
     info = dfl.Info()
     for lam in [0.0, -1e-3, float("inf"), float("nan")]:
         assert lib.dfisher_solve(FAKE_CTX, P, 4, 8, 8, P, lam, P, None, st, ctypes.byref(info)) == E
-    for o in [_opts(dfl, prec=5), _opts(dfl, sweeps=-1), _opts(dfl, sweeps=17), _opts(dfl, shift=3),
-              _opts(dfl, x64=2), _opts(dfl, tol=-1e-9), _opts(dfl, tol=float("nan")), _opts(dfl, tol=float("inf"))]:
+    for o in [_opts(dfl, prec=5), _opts(dfl, sweeps=-2), _opts(dfl, sweeps=17), _opts(dfl, shift=3),
+              _opts(dfl, x64=2), _opts(dfl, tol=-1e-9), _opts(dfl, tol=float("nan")), _opts(dfl, tol=float("inf")),
+              _opts(dfl, final=2), _opts(dfl, reserved=1)]:
         assert lib.dfisher_solve(FAKE_CTX, P, 4, 8, 8, P, 1.0, P, ctypes.byref(o), st, None) == E
     assert lib.dfisher_solve(FAKE_CTX, P, 4, 8, 8, None, 1.0, P, None, st, None) == E
     assert lib.dfisher_solve(FAKE_CTX, P, 4, 8, 8, P, 1.0, None, None, st, None) == E
@@ -110,6 +111,10 @@ def test_invalid_arguments_rejected_on_host(dfl):
     arrn = (ctypes.c_int64 * 1)(4)
     assert lib.dfisher_solve_uneven(FAKE_CTX, 1, arrp, arrn, arr64, arr64, arrp, lams, arrp, ctypes.byref(otol), st,
                                     None) == U
+    # the final-residual measurement is offered by dfisher_solve and dfisher_solve_uneven only
+    ofin = _opts(dfl, sweeps=1, final=1)
+    assert lib.dfisher_solve_batched(FAKE_CTX, P, 4, 8, 8, lams, 1, P, 1, 8, P, 8, ctypes.byref(ofin), st, None) == U
+    assert lib.dfisher_factor_create(FAKE_CTX, P, 4, 8, 8, 1.0, ctypes.byref(ofin), st, ctypes.byref(out), None) == U
     assert "NULL" in dfl.dfisher_last_error() or dfl.dfisher_last_error() != ""
     # context switches and the tuning table
     assert lib.dfisher_ctx_enable_graphs(None, 1) == E
@@ -137,3 +142,28 @@ def test_context_on_missing_device(dfl):
         dfl.dfisher_ctx_create(0)
     assert ei.value.status == dfl.DFISHER_E_DEVICE
     assert dfl.lib.dfisher_ctx_destroy(None) == dfl.DFISHER_OK
+
+
+def test_auto_sweeps_rule(dfl):
+    """DFISHER_SWEEPS_AUTO's count: c = C / (sqrt(a) (1 - 1/sqrt(a))^2), a = m / n, and the smallest k
+    with c^(k+1) <= 1e-7 (C = 0.1 scaled FP8, 1e-4 split-BF16, 1e-5 FP32; a <= 4 uses (1/2)^2)."""
+    def rule(prec, n, m):
+        a = m / n
+        C = {0: 1e-5, 1: 1e-4, 2: 0.1}[prec]
+        gap = (1 - a ** -0.5) ** 2 if a > 4 else 0.25
+        c = C / (max(a, 1.0) ** 0.5 * gap)
+        if not c < 0.5:
+            return 16
+        k, e = 0, c
+        while e > 1e-7 and k < 16:
+            e *= c
+            k += 1
+        return k
+    for prec in (0, 1, 2):
+        for n, m in [(4096, 4_000_000), (2048, 2_000_000), (300, 20000), (1241, 119782), (32, 1024),
+                     (1000, 1000), (64, 100), (1, 777)]:
+            assert dfl.dfisher_auto_sweeps(prec, n, m) == rule(prec, n, m), (prec, n, m)
+    # the headline shape needs two sweeps of the scaled-FP8 Gram and one of the others
+    assert dfl.dfisher_auto_sweeps(2, 4096, 4_000_000) == 2
+    assert dfl.dfisher_auto_sweeps(1, 4096, 4_000_000) == 1
+    assert dfl.dfisher_auto_sweeps(3, 10, 10) == -1 and dfl.dfisher_auto_sweeps(0, 0, 10) == -1

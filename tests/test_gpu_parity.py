@@ -509,6 +509,32 @@ def test_uneven_graph_replays_match_eager(dfl, ctx):
         torch.cuda.synchronize()
 
 
+def test_uneven_graph_after_tuning_change(dfl, oracle_mod, tmp_path):
+    """Loading a tuning table that changes a problem's split-K factor moves the uneven layout; the
+    next call with the same arguments must not replay the graph captured with the old layout."""
+    shapes = [(300, 40000, 1e-3), (129, 7777, 3e-4), (40, 3000, 1e-2)]
+    Ss, vs, Sd, vd = _uneven_inputs(shapes, 47, aligned=True)
+    lams = [s[2] for s in shapes]
+    c = dfl.dfisher_ctx_create(0)
+    dfl.dfisher_ctx_enable_graphs(c, True)
+    path = tmp_path / "tune.txt"
+    try:
+        xs = [torch.empty(S.shape[1], dtype=torch.float64, device="cuda") for S in Ss]
+        for q in (2, 1, 2):   # the (split-BF16, 2 tile rows, m in [2^15, 2^16), aligned) class
+            path.write_text(f"1 2 15 1 {q} 1\n")
+            dfl.dfisher_ctx_load_tuning(c, str(path))
+            for x in xs:
+                x.fill_(float("nan"))
+            dfl.dfisher_solve_uneven(c, Sd, vd, lams, gram_prec=1, sweeps=2, x_fp64=True, xs=xs)
+            torch.cuda.synchronize()
+            for p, (S, v, lam) in enumerate(zip(Ss, vs, lams)):
+                err = rel(xs[p].cpu().numpy(), oracle_mod.solve(S, v, lam))
+                print(f"    q={q} problem {p} rel err {err:.3e}", flush=True)
+                assert err <= 1e-6
+    finally:
+        dfl.dfisher_ctx_destroy(c)
+
+
 def test_autotune_save_load(dfl, oracle_mod, tmp_path):
     """Tuning a size class records a valid (q, mode); a saved table loads into a fresh context,
     whose solves stay within the bound; automatic tuning adds unseen classes; bad files fail."""

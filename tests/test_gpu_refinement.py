@@ -1,0 +1,195 @@
+"""GPU checks of the refinement controls against the FP64 CPU oracle, through the C ABI: the
+automatic sweep count, the final-residual measurement, the error of the part of x the method
+computes (eps_Sy), the scaled-FP8 Gram on right-hand sides that lie in the row space of S, and the
+triangular solves on the ill-conditioned factor of a column-centered S.
+
+eps_Sy = |S^T (y - y*)| / |S^T y*|: since x = (v - S^T y) / lambda, it equals
+lambda |x - x*| / |v - lambda x*| for an FP64 x. For an iid v the norm-wise error |x - x*| / |x*| is
+dominated by the null-space part v / lambda, which the method does not compute, so eps_Sy is the
+sharper measure; both must meet 1e-6.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def dfl():
+    import paper_2310_17556_amd as dfl
+    return dfl
+
+
+@pytest.fixture(scope="module")
+def ctx(dfl):
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = dfl.dfisher_ctx_create(0)
+    yield c
+    c.close()
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def dev_aligned(S):
+    """S in a buffer whose row stride is a multiple of 4 floats (16-byte aligned rows)."""
+    n, m = S.shape
+    ld = (m + 3) // 4 * 4
+    buf = torch.zeros((n, ld), dtype=torch.float32, device="cuda")
+    buf[:, :m] = torch.from_numpy(S).cuda()
+    return buf[:, :m]
+
+
+def errs(x, xref, v, lam):
+    x = np.asarray(x, dtype=np.float64)
+    d = np.linalg.norm(x - xref)
+    return d / np.linalg.norm(xref), lam * d / np.linalg.norm(v.astype(np.float64) - lam * xref)
+
+
+AUTO_CASES = [
+    # n, m, lam, prec, kind
+    (256, 65536, 1e-2, 2, "iid"),
+    (256, 65536, 1e-6, 2, "iid"),
+    (256, 65536, 1e-3, 2, "scaled"),     # v in the row space: the error shows at full weight in x
+    (200, 20000, 1e-4, 2, "scaled"),     # m / n = 100, the slow end of the uneven workload
+    (128, 131072, 1e-6, 2, "scaled"),    # m / n = 1024, the aspect ratio of the headline workload
+    (300, 20001, 1e-6, 1, "iid"),
+    (257, 30000, 1e-3, 1, "scaled"),
+    (320, 20008, 1e-3, 0, "scaled"),
+]
+
+
+@pytest.mark.parametrize("n,m,lam,prec,kind", AUTO_CASES)
+def test_auto_sweeps_meet_target(dfl, ctx, oracle_mod, n, m, lam, prec, kind):
+    """DFISHER_SWEEPS_AUTO in dfisher_solve (measured residuals, predictive stop at 1e-7): the call
+    converges, both |x - x*| / |x*| and eps_Sy meet 1e-6 against the oracle, and the final
+    residual, measured separately, meets the 1e-7 aim within the contraction's spread."""
+    print(f"[auto sweeps] n={n} m={m} lam={lam} prec={prec} kind={kind}", flush=True)
+    S = synth.make_S(n, m, synth.seed(50, n), kind)
+    v = synth.make_v(S, synth.seed(50, n), kind)
+    xref = oracle_mod.solve(S, v, lam)
+    Sd = dev_aligned(S) if prec == 2 else dev(S)
+    x, info = dfl.dfisher_solve(ctx, Sd, dev(v), lam, gram_prec=prec, sweeps=dfl.DFISHER_SWEEPS_AUTO, x_fp64=True,
+                                final_resid=True)
+    rel, esy = errs(x.cpu().numpy(), xref, v, lam)
+    rule = dfl.dfisher_auto_sweeps(prec, n, m)
+    print(f"    sweeps {info['sweeps_done']} (a-priori rule {rule}) rel {rel:.3e} eps_Sy {esy:.3e} "
+          f"rho {info['resid']:.3e} w_resid {info['w_resid']:.3e} shift {info['shift']:.3e}", flush=True)
+    assert info["converged"] and 1 <= info["sweeps_done"] <= 16
+    assert rel <= 1e-6 and esy <= 1e-6
+    assert 0.0 <= info["w_resid"] <= 1e-6
+
+
+@pytest.mark.parametrize("prec,sweeps", [(2, 1), (1, 0), (1, 1)])
+def test_final_resid_is_next_sweeps_rho(dfl, ctx, prec, sweeps):
+    """The final residual of a k-sweep solve is the residual that sweep k + 1 measures before its
+    correction (tolerance mode, same kernels in the same order): the two must agree bit for bit.
+    With sweeps = 0 it is the residual of the unrefined solve."""
+    n, m, lam = 320, 20016, 1e-3
+    S = synth.make_S(n, m, synth.seed(51, n))
+    v = synth.make_v(S, synth.seed(51, n))
+    Sd, vd = dev(S), dev(v)
+    _, a = dfl.dfisher_solve(ctx, Sd, vd, lam, gram_prec=prec, sweeps=sweeps, final_resid=True)
+    _, b = dfl.dfisher_solve(ctx, Sd, vd, lam, gram_prec=prec, sweeps=sweeps + 1, tol=1e-300)
+    print(f"    w_resid {a['w_resid']:.6e} rho {b['resid']:.6e}", flush=True)
+    assert a["w_resid"] > 0.0 and a["w_resid"] == b["resid"]
+    assert a["resid"] == -1.0   # no tolerance: no per-sweep measurement
+    _, c = dfl.dfisher_solve(ctx, Sd, vd, lam, gram_prec=prec, sweeps=sweeps + 1, final_resid=True)
+    assert c["w_resid"] < a["w_resid"]
+
+
+@pytest.mark.parametrize("sweeps,bound", [(3, 1e-6), (-1, 1e-6)])
+def test_fp8_row_space_rhs(dfl, ctx, oracle_mod, sweeps, bound):
+    """The scaled-FP8 Gram on a right-hand side in the row space of a column-scaled S (the
+    paper-scale generator: v = S^T u + N(0, 1e-6), so x = v / lambda - S^T y / lambda cancels to
+    about lambda / sigma^2 and the Gram error reaches x at full weight), default shift policy."""
+    n, m, lam = 192, 49152, 1e-3
+    S = synth.make_S(n, m, synth.seed(52, n), "scaled")
+    v = synth.make_v(S, synth.seed(52, n), "scaled")
+    xref = oracle_mod.solve(S, v, lam)
+    x, info = dfl.dfisher_solve(ctx, dev(S), dev(v), lam, gram_prec=dfl.DFISHER_GRAM_MXFP8, sweeps=sweeps,
+                                x_fp64=True)
+    rel, esy = errs(x.cpu().numpy(), xref, v, lam)
+    print(f"    sweeps {info['sweeps_done']} rel {rel:.3e} eps_Sy {esy:.3e} info {info}", flush=True)
+    assert rel <= bound and esy <= bound
+    # with no sweep the scaled-FP8 Gram alone is far from the target on this right-hand side
+    x0, _ = dfl.dfisher_solve(ctx, dev(S), dev(v), lam, gram_prec=dfl.DFISHER_GRAM_MXFP8, sweeps=0, x_fp64=True)
+    assert errs(x0.cpu().numpy(), xref, v, lam)[0] > 1e-5
+
+
+@pytest.mark.parametrize("n,m", [(300, 20000), (700, 30000)])
+def test_trsv_centered_ill_conditioned(dfl, ctx, oracle_mod, n, m):
+    """Triangular solves with the factor of W = S S^T + 1e-6 I for a column-centered S (W has an
+    eigenvalue near lambda along the all-ones direction: cond(W) ~ (m / n) / lambda). The block
+    inverses make the forward error grow with cond(L); the bound is 1e-13 cond(L) against the
+    oracle's substitutions, and the backward error |L z - b| / (|L| |z|) stays at rounding level."""
+    S = synth.make_S(n, m, synth.seed(53, n), "iid")
+    L, info = oracle_mod.cholesky(oracle_mod.gram(S, 1e-6))
+    assert info == 0
+    condL = np.linalg.cond(L)
+    print(f"[trsv ill-conditioned] n={n} cond(L) = {condL:.3e}", flush=True)
+    assert condL > 1e3
+    rng = np.random.default_rng(n)
+    Ld = dev(L)
+    for b in (rng.standard_normal(n), np.ones(n)):   # a random and the near-null direction
+        z = dfl.dfisher_trsv(ctx, Ld, dev(b), 0).cpu().numpy()
+        y = dfl.dfisher_trsv(ctx, Ld, dev(b), 1).cpu().numpy()
+        zr, yr = oracle_mod.forward(L, b), oracle_mod.backward(L, b)
+        ez = np.linalg.norm(z - zr) / np.linalg.norm(zr)
+        ey = np.linalg.norm(y - yr) / np.linalg.norm(yr)
+        bz = np.linalg.norm(L @ z - b) / (np.linalg.norm(L, 2) * np.linalg.norm(z))
+        by = np.linalg.norm(L.T @ y - b) / (np.linalg.norm(L, 2) * np.linalg.norm(y))
+        print(f"    forward {ez:.3e} backward {ey:.3e}  backward errors {bz:.3e} {by:.3e}", flush=True)
+        assert ez <= 1e-13 * condL and ey <= 1e-13 * condL
+        assert bz <= 1e-12 and by <= 1e-12
+
+
+def test_uneven_auto_sweeps(dfl, ctx, oracle_mod):
+    """Uneven batch with DFISHER_SWEEPS_AUTO: each problem runs its own sweep count (the rule for
+    its shape), and each problem's x, eps_Sy and final residual meet 1e-6. Graph capture replays the
+    per-problem counts (second call)."""
+    shapes = [(256, 20000, 1e-3), (64, 30000, 1e-5), (300, 9000, 1e-4), (128, 60000, 1e-2), (40, 3000, 1e-2)]
+    Ss = [synth.make_S(n, m, synth.seed(54, p)) for p, (n, m, _) in enumerate(shapes)]
+    vs = [synth.make_v(S, synth.seed(54, p)) for p, S in enumerate(Ss)]
+    lams = [s[2] for s in shapes]
+    Sd = [dev_aligned(S) for S in Ss]
+    vd = [dev(v) for v in vs]
+    for call in range(2):
+        xs, infos = dfl.dfisher_solve_uneven(ctx, Sd, vd, lams, gram_prec=dfl.DFISHER_GRAM_MXFP8,
+                                             sweeps=dfl.DFISHER_SWEEPS_AUTO, x_fp64=True, final_resid=True)
+        for p, (S, v, lam) in enumerate(zip(Ss, vs, lams)):
+            n, m = S.shape
+            rel, esy = errs(xs[p].cpu().numpy(), oracle_mod.solve(S, v, lam), v, lam)
+            print(f"    call {call} problem {p} ({n}x{m}) sweeps {infos[p]['sweeps_done']} rel {rel:.3e} "
+                  f"eps_Sy {esy:.3e} w_resid {infos[p]['w_resid']:.3e}", flush=True)
+            if infos[p]["attempts"] == 1:
+                assert infos[p]["sweeps_done"] == dfl.dfisher_auto_sweeps(2, n, m)
+            assert rel <= 1e-6 and esy <= 1e-6
+            assert 0.0 <= infos[p]["w_resid"] <= 1e-6
+
+
+def test_batched_auto_sweeps(dfl, ctx, oracle_mod):
+    """Batched lambdas x right-hand sides with DFISHER_SWEEPS_AUTO: one count for the call, at least
+    the rule for the shape; every pair meets 1e-6 in x and in eps_Sy."""
+    n, m = 160, 40000
+    S = synth.make_S(n, m, synth.seed(55, n))
+    V = synth.make_V(m, 3, synth.seed(55, n))
+    lams = [1e-6, 1e-3, 1e-1]
+    X, infos = dfl.dfisher_solve_batched(ctx, dev(S), lams, dev(V), gram_prec=dfl.DFISHER_GRAM_MXFP8,
+                                         sweeps=dfl.DFISHER_SWEEPS_AUTO, x_fp64=True)
+    Xref = oracle_mod.solve_batched(S, lams, V)
+    X = X.cpu().numpy()
+    rule = dfl.dfisher_auto_sweeps(2, n, m)
+    for li, lam in enumerate(lams):
+        assert infos[li]["sweeps_done"] >= rule
+        for r in range(3):
+            rel, esy = errs(X[li, r], Xref[li, r], V[r], lam)
+            assert rel <= 1e-6 and esy <= 1e-6, (li, r, rel, esy)
