@@ -16,6 +16,12 @@ Every function states the passage of the paper it follows:
 * :func:`residual`   - v - lambda x - S^T S x, the identity of Proposition 1 (Appendix A).
 * :func:`split_bf16`, :func:`gram3` - definition of the split-BF16 Gram (three products).
 * :func:`quant_mxfp8` - definition of the block-scaled FP8 inputs of the scaled-FP8 Gram.
+* :func:`solve_rowspace` - the structured right-hand side v = S^T f of Appendix B,
+                       x = S^T (S S^T + lambda I)^-1 f.
+* :func:`center`, :func:`center_complex` - the SR score matrix S = (O - mean O) / sqrt(n) of
+                       Section 3; the complex form in the stacked real layout [Re S; Im S].
+* :func:`solve_complex` - the complex variant of Section 3 (transposes become Hermitian
+                       conjugates), in complex FP64.
 """
 from __future__ import annotations
 
@@ -66,6 +72,10 @@ def _load():
             "oracle_quant_mxfp8": ([P, I, I, I, P, P], None),
             "oracle_gram_entries": ([P, I, I, D, P, P, I, P], None),
             "oracle_num_threads": ([], ctypes.c_int),
+            "oracle_solve_rowspace": ([P, I, I, I, P, D, P, P], I),
+            "oracle_center": ([P, I, I, I, P, I], None),
+            "oracle_center_complex": ([P, I, I, I, P, I], None),
+            "oracle_solve_complex": ([P, I, I, I, P, D, P, P], I),
         }
         for name, (args, res) in sigs.items():
             f = getattr(lib, name)
@@ -253,3 +263,56 @@ def solve_batched(S, lams, V) -> np.ndarray:
             y = backward(L, forward(L, gemv(S, V[r])))
             out[li, r] = apply(S, V[r], y, float(lam))
     return out
+
+
+def solve_rowspace(S, f, lam: float, return_y: bool = False):
+    """Appendix B: x = S^T (S S^T + lam I)^-1 f, the solution of Eq. 1 for v = S^T f, without
+    forming v. Raises ``np.linalg.LinAlgError`` if the Cholesky fails."""
+    S, n, m, lds = _S(S)
+    f = _f64(f, (n,))
+    x = np.empty(m, dtype=np.float64)
+    y = np.empty(n, dtype=np.float64)
+    info = _load().oracle_solve_rowspace(_p(S), n, m, lds, _p(f), float(lam), _p(x), _p(y))
+    if info != 0:
+        raise np.linalg.LinAlgError(f"oracle Cholesky failed at pivot {info}")
+    return (x, y) if return_y else x
+
+
+def center(O) -> np.ndarray:
+    """Section 3: S = (O - mean over samples of O) / sqrt(n), FP64 arithmetic, FP32 result."""
+    O, n, m, ldo = _S(O)
+    S = np.empty((n, m), dtype=np.float32)
+    _load().oracle_center(_p(O), n, m, ldo, _p(S), m)
+    return S
+
+
+def center_complex(O) -> np.ndarray:
+    """Section 3 for a complex O (complex64, n x m): the centered, scaled S in the stacked real form
+    Z = [Re S; Im S], a 2n x m float32 array with rows 0..n-1 the real parts and rows n..2n-1 the
+    imaginary parts."""
+    O = np.ascontiguousarray(O, dtype=np.complex64)
+    if O.ndim != 2:
+        raise ValueError("O must be 2-D")
+    n, m = O.shape
+    Z = np.empty((2 * n, m), dtype=np.float32)
+    _load().oracle_center_complex(_p(O), n, m, m, _p(Z), m)
+    return Z
+
+
+def solve_complex(S, v, lam: float, return_y: bool = False):
+    """Section 3, complex variant: x solving (S^H S + lam I) x = v by Algorithm 1 with Hermitian
+    conjugates, in complex FP64. S: complex64 n x m; v: complex m. Raises
+    ``np.linalg.LinAlgError`` if the Cholesky fails."""
+    S = np.ascontiguousarray(S, dtype=np.complex64)
+    if S.ndim != 2:
+        raise ValueError("S must be 2-D")
+    n, m = S.shape
+    v = np.ascontiguousarray(v, dtype=np.complex128)
+    if v.shape != (m,):
+        raise ValueError(f"expected v of shape ({m},)")
+    x = np.empty(m, dtype=np.complex128)
+    y = np.empty(n, dtype=np.complex128)
+    info = _load().oracle_solve_complex(_p(S), n, m, m, _p(v), float(lam), _p(x), _p(y))
+    if info != 0:
+        raise np.linalg.LinAlgError(f"oracle Cholesky failed at pivot {info}")
+    return (x, y) if return_y else x

@@ -24,6 +24,7 @@
  * computes: S = hi + lo with hi = bf16 round-to-nearest-even of S and lo = bf16 RNE of the
  * (exact) remainder, and the Gram keeps the three products hi.hi + hi.lo + lo.hi.
  */
+#include <complex.h>
 #include <math.h>
 #include <stdint.h>
 #include <stdlib.h>
@@ -289,6 +290,163 @@ EXPORT void oracle_gram_entries(const float* S, int64_t m, int64_t lds, double l
     if (ii[p] == jj[p]) acc += lambda;
     out[p] = acc;
   }
+}
+
+/* ---------------------------------------------------------------------------------------------
+ * Structured right-hand side (Appendix B). When v = S^T f lies in the row space of S, the push-
+ * through identity S^T (S S^T + lambda I)^-1 = (S^T S + lambda I)^-1 S^T gives
+ *   x = S^T y,   y = (S S^T + lambda I)^-1 f,
+ * so neither b = S v nor the subtraction v - S^T y is formed. Steps: W = S S^T + lambda I
+ * (oracle_gram), L = Chol(W), z = L^-1 f, y = L^-T z, x_k = sum_i S_ik y_i (i ascending).
+ * Returns the Cholesky info (0 = ok); x and y are written only on success (y may be NULL). */
+EXPORT int64_t oracle_solve_rowspace(const float* S, int64_t n, int64_t m, int64_t lds, const double* f,
+                                     double lambda, double* x, double* y_out) {
+  double* W = (double*)malloc((size_t)(n * n) * sizeof(double));
+  double* L = (double*)malloc((size_t)(n * n) * sizeof(double));
+  double* z = (double*)malloc((size_t)n * sizeof(double));
+  double* y = (double*)malloc((size_t)n * sizeof(double));
+  int64_t info = -1;
+  if (W && L && z && y) {
+    oracle_gram(S, n, m, lds, lambda, W);
+    info = oracle_cholesky(W, n, L);
+    if (info == 0) {
+      oracle_forward(L, n, f, z);
+      oracle_backward(L, n, z, y);
+#pragma omp parallel for schedule(static)
+      for (int64_t k = 0; k < m; ++k) {
+        double acc = 0.0;
+        for (int64_t i = 0; i < n; ++i) acc += sd(S, lds, i, k) * y[i];
+        x[k] = acc;
+      }
+      if (y_out) memcpy(y_out, y, (size_t)n * sizeof(double));
+    }
+  }
+  free(W); free(L); free(z); free(y);
+  return info;
+}
+
+/* ---------------------------------------------------------------------------------------------
+ * Stochastic-reconfiguration front end (Section 3). The score matrix of SR is the centered,
+ * scaled log-derivative matrix S = (O - mean(O)) / sqrt(n), the mean taken over the n samples
+ * (rows) for every parameter (column):
+ *   mu_j = (sum_i O_ij) / n            (FP64, i ascending)
+ *   S_ij = fl32((O_ij - mu_j) / sqrt(n))   (FP64 subtraction and division, one rounding to FP32)
+ * O is n x m FP32 (row stride ldo); S is n x m FP32 (row stride lds). */
+EXPORT void oracle_center(const float* O, int64_t n, int64_t m, int64_t ldo, float* S, int64_t lds) {
+  const double rn = sqrt((double)n);
+#pragma omp parallel for schedule(static)
+  for (int64_t j = 0; j < m; ++j) {
+    double acc = 0.0;
+    for (int64_t i = 0; i < n; ++i) acc += (double)O[i * ldo + j];
+    const double mu = acc / (double)n;
+    for (int64_t i = 0; i < n; ++i) S[i * lds + j] = (float)(((double)O[i * ldo + j] - mu) / rn);
+  }
+}
+
+/* Complex O (the log-derivatives of a complex wave function), n x m complex values stored as
+ * interleaved (real, imaginary) FP32 pairs, row stride ldo complex elements. The complex mean is
+ * taken componentwise, so the real and imaginary parts are centered as two real matrices, and the
+ * result is written in the stacked real form Z (2n x m FP32, row stride ldz):
+ *   Z_ij = Re S_ij (rows 0..n-1),  Z_(n+i)j = Im S_ij (rows n..2n-1).
+ * Z is the concatenation of Re S and Im S in the sample dimension that the real-part variant of
+ * SR, F = Re[S^H S] = Z^T Z, solves with (Section 3), and the planar form of S that the complex
+ * variant takes. */
+EXPORT void oracle_center_complex(const float* O, int64_t n, int64_t m, int64_t ldo, float* Z, int64_t ldz) {
+  const double rn = sqrt((double)n);
+#pragma omp parallel for schedule(static)
+  for (int64_t j = 0; j < m; ++j) {
+    double ar = 0.0, ai = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+      ar += (double)O[2 * (i * ldo + j)];
+      ai += (double)O[2 * (i * ldo + j) + 1];
+    }
+    const double mr = ar / (double)n, mi = ai / (double)n;
+    for (int64_t i = 0; i < n; ++i) {
+      Z[i * ldz + j] = (float)(((double)O[2 * (i * ldo + j)] - mr) / rn);
+      Z[(n + i) * ldz + j] = (float)(((double)O[2 * (i * ldo + j) + 1] - mi) / rn);
+    }
+  }
+}
+
+/* ---------------------------------------------------------------------------------------------
+ * Complex variant (Section 3): with a complex S every transpose of Eq. 1 and Algorithm 1 becomes
+ * the Hermitian conjugate, (S^H S + lambda I) x = v with x, v in C^m:
+ *   W = S S^H + lambda I_n       W_ij = sum_k S_ik conj(S_jk)                      (k ascending)
+ *   W = L L^H                    L_ij = (W_ij - sum_{k<j} L_ik conj(L_jk)) / L_jj   (j < i)
+ *                                L_ii = sqrt(W_ii - sum_{k<i} |L_ik|^2)   (real; fails unless > 0)
+ *                                (every division is by the real L_jj, componentwise)
+ *   b = S v,  z = L^-1 b,  y = L^-H z   (y_i = (z_i - sum_{k>i} conj(L_ki) y_k) / L_ii)
+ *   x = (v - S^H y) / lambda     (S^H y)_k = sum_i conj(S_ik) y_i                   (i ascending)
+ * in C99 complex FP64. S: n x m complex FP32 values as interleaved (re, im) pairs with row stride
+ * lds complex elements; v, x (m) and y (n, may be NULL) are interleaved complex FP64. Returns the
+ * Cholesky info (0 or the 1-based index of the first pivot that is not > 0); on failure x is not
+ * written. */
+static double complex cs(const float* S, int64_t lds, int64_t i, int64_t k) {
+  return (double)S[2 * (i * lds + k)] + (double)S[2 * (i * lds + k) + 1] * I;
+}
+
+EXPORT int64_t oracle_solve_complex(const float* S, int64_t n, int64_t m, int64_t lds, const double* v,
+                                    double lambda, double* x, double* y_out) {
+  double complex* W = (double complex*)malloc((size_t)(n * n) * sizeof(double complex));
+  double complex* L = (double complex*)calloc((size_t)(n * n), sizeof(double complex));
+  double complex* b = (double complex*)malloc((size_t)n * sizeof(double complex));
+  double complex* z = (double complex*)malloc((size_t)n * sizeof(double complex));
+  double complex* y = (double complex*)malloc((size_t)n * sizeof(double complex));
+  int64_t info = -1;
+  if (!(W && L && b && z && y)) goto out;
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int64_t i = 0; i < n; ++i) {
+    for (int64_t j = 0; j <= i; ++j) {
+      double complex acc = 0.0;
+      for (int64_t k = 0; k < m; ++k) acc += cs(S, lds, i, k) * conj(cs(S, lds, j, k));
+      if (i == j) acc += lambda;
+      W[i * n + j] = acc;
+    }
+  }
+  info = 0;
+  for (int64_t i = 0; i < n && info == 0; ++i) {
+    for (int64_t j = 0; j < i; ++j) {
+      double complex acc = W[i * n + j];
+      for (int64_t k = 0; k < j; ++k) acc -= L[i * n + k] * conj(L[j * n + k]);
+      L[i * n + j] = acc / creal(L[j * n + j]);
+    }
+    double d = creal(W[i * n + i]);
+    for (int64_t k = 0; k < i; ++k) d -= creal(L[i * n + k]) * creal(L[i * n + k]) + cimag(L[i * n + k]) * cimag(L[i * n + k]);
+    if (!(d > 0.0)) info = i + 1;
+    else L[i * n + i] = sqrt(d);
+  }
+  if (info != 0) goto out;
+  for (int64_t i = 0; i < n; ++i) {
+    double complex acc = 0.0;
+    for (int64_t k = 0; k < m; ++k) acc += cs(S, lds, i, k) * (v[2 * k] + v[2 * k + 1] * I);
+    b[i] = acc;
+  }
+  for (int64_t i = 0; i < n; ++i) {
+    double complex acc = b[i];
+    for (int64_t k = 0; k < i; ++k) acc -= L[i * n + k] * z[k];
+    z[i] = acc / creal(L[i * n + i]);
+  }
+  for (int64_t i = n - 1; i >= 0; --i) {
+    double complex acc = z[i];
+    for (int64_t k = i + 1; k < n; ++k) acc -= conj(L[k * n + i]) * y[k];
+    y[i] = acc / creal(L[i * n + i]);
+  }
+#pragma omp parallel for schedule(static)
+  for (int64_t k = 0; k < m; ++k) {
+    double complex t = 0.0;
+    for (int64_t i = 0; i < n; ++i) t += conj(cs(S, lds, i, k)) * y[i];
+    const double complex xk = ((v[2 * k] + v[2 * k + 1] * I) - t) / lambda;
+    x[2 * k] = creal(xk);
+    x[2 * k + 1] = cimag(xk);
+  }
+  if (y_out)
+    for (int64_t i = 0; i < n; ++i) {
+      y_out[2 * i] = creal(y[i]);
+      y_out[2 * i + 1] = cimag(y[i]);
+    }
+out:
+  free(W); free(L); free(b); free(z); free(y);
+  return info;
 }
 
 /* Number of OpenMP threads the oracle runs on (1 without OpenMP). */

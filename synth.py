@@ -17,6 +17,10 @@ handle, and torch on a device (``make_*_torch``), for the full-scale workloads t
 fit the host. The two back ends use different random streams; a test always hands the same
 bytes to both sides.
 
+* ``make_O``  - the raw matrix the SR front end centers: per-column offsets 3 N(0,1) plus iid
+                N(0,1) samples (real, or complex with independent parts); ``make_vc`` draws a
+                complex right-hand side.
+
 Seeds: ``seed(c, p) = 2310017556 + 100 c + p`` for workload c and problem p.
 """
 from __future__ import annotations
@@ -64,6 +68,27 @@ def make_v(S: np.ndarray, seed_: int, kind: str = "iid") -> np.ndarray:
         e = rng.normal(0.0, 1e-3, size=m)
         return (S.astype(np.float64).T @ u + e).astype(np.float32)
     raise ValueError(f"unknown kind {kind!r}")
+
+
+def make_O(n: int, m: int, seed_: int, complex_: bool = False) -> np.ndarray:
+    """Raw log-derivative-like matrix O (n samples x m parameters) for the SR front end: every
+    column has its own offset mu_j ~ 3 N(0,1) plus iid N(0,1) sample noise, so that centering
+    removes a mean larger than the spread. float32 (n x m) or, with complex_, complex64 whose real
+    and imaginary parts are drawn independently the same way."""
+    rng = np.random.default_rng(seed_ + 17)
+    if not complex_:
+        mu = 3.0 * rng.standard_normal(m)
+        return (mu + rng.standard_normal((n, m))).astype(np.float32)
+    mr, mi = 3.0 * rng.standard_normal(m), 3.0 * rng.standard_normal(m)
+    re = (mr + rng.standard_normal((n, m))).astype(np.float32)
+    im = (mi + rng.standard_normal((n, m))).astype(np.float32)
+    return (re + 1j * im.astype(np.float64)).astype(np.complex64)
+
+
+def make_vc(m: int, seed_: int) -> np.ndarray:
+    """Complex right-hand side of length m (complex64), real and imaginary parts iid N(0,1)."""
+    rng = np.random.default_rng(seed_ + 19)
+    return (rng.standard_normal(m) + 1j * rng.standard_normal(m)).astype(np.complex64)
 
 
 def make_V(m: int, nrhs: int, seed_: int) -> np.ndarray:

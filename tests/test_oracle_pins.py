@@ -392,6 +392,22 @@ def test_gram3_against_blas(oracle_mod):
     assert np.max(np.abs(oracle_mod.gram3(hi, lo, 0.5) - W) / dd) <= 2.0 ** -15
 
 
+def test_gram3_hand_example(oracle_mod):
+    """The split and the three-product Gram on a hand-derived example (tests/golden) in which
+    lo.lo is nonzero in every entry: exact equality, so keeping the fourth product, dropping a
+    cross term or splitting with another rounding each fails."""
+    with open(os.path.join(HERE, "golden", "hand_examples.json")) as f:
+        g = json.load(f)["split_bf16_gram3"]
+    S = np.array(g["S"], dtype=np.float32)
+    hi, lo = oracle_mod.split_bf16(S)
+    np.testing.assert_array_equal(hi, np.array(g["hi"], dtype=np.float32))
+    np.testing.assert_array_equal(lo, np.array(g["lo"], dtype=np.float32))
+    W3 = oracle_mod.gram3(hi, lo, g["lambda"])
+    np.testing.assert_array_equal(W3, np.array(g["W3"]))
+    # the exact Gram is the three-product one plus lo lo^T, to the last bit
+    np.testing.assert_array_equal(oracle_mod.gram(S, g["lambda"]), W3 + np.array(g["lolo"]))
+
+
 # ------------------------------------------------------------------ scaled-FP8 (E4M3 + E8M0) form
 def _e4m3_table():
     """Every finite non-negative E4M3 value, from the bit layout: exponent field E (bias 7) and
