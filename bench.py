@@ -442,7 +442,9 @@ def main() -> int:
     ap.add_argument("--n", type=int, default=4096)
     ap.add_argument("--m", type=int, default=4_000_000)
     ap.add_argument("--prec", default="mxfp8", choices=sorted(PREC_CODE))
-    ap.add_argument("--sweeps", type=_sweeps_arg, default=-1, help="refinement sweeps, or 'auto' (the default)")
+    ap.add_argument("--sweeps", type=_sweeps_arg, default=2,
+                    help="refinement sweeps of the timed path, or 'auto' (default 2: the count at which every "
+                         "solve of the workload meets 1e-6 in x and in eps_Sy, reported by the error table)")
     ap.add_argument("--shift", default="on_failure", choices=sorted(SHIFT),
                     help="Cholesky shift policy of the mixed path")
     ap.add_argument("--lams", default="1e-2,1e-4,1e-6")
@@ -458,6 +460,9 @@ def main() -> int:
     ap.add_argument("--no-batched", action="store_true", help="skip the batched multi-lambda/RHS leg")
     ap.add_argument("--no-uneven", action="store_true", help="skip the uneven-batch leg")
     ap.add_argument("--leg-reps", type=int, default=3, help="timed calls of the batched and uneven legs")
+    ap.add_argument("--leg-sweeps", type=_sweeps_arg, default=-1,
+                    help="refinement sweeps of the batched and uneven legs (default 'auto': the a-priori count "
+                         "per problem shape)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run two device copies of 1 GiB (reference reading for the HBM byte counters)")
     args = ap.parse_args()
@@ -497,7 +502,7 @@ def main() -> int:
     xbuf = {lam: torch.empty(m, dtype=torch.float32, device=dev) for lam in lams}
     sweeps_resolved = dfl.dfisher_auto_sweeps(PREC_CODE[args.prec], n, m) if args.sweeps < 0 else args.sweeps
 
-    log(f"[bench] mixed path: {args.prec} Gram + {args.sweeps} sweep(s) (resolved {sweeps_resolved}), "
+    log(f"[bench] mixed path: {args.prec} Gram + {args.sweeps} sweep(s) (a-priori rule {sweeps_resolved}), "
         f"{args.warmup} warmup + {args.steps} steps")
     elapsed, gram_ms, stage_avg, infos = run_path(dfl, ctx, S, v, lams, args.prec, args.sweeps, args.steps,
                                                   args.warmup, xbuf, args.shift)
@@ -524,6 +529,15 @@ def main() -> int:
                 "sweeps": 0, "stage_ms": st32,
                 "shifts": {str(l): i["shift"] for l, i in inf32}}
         log(f"[bench] fp32: {fp32['solves_per_s']:.3f} solves/s, gram {g32avg:.2f} ms")
+
+    auto = None
+    if args.sweeps >= 0:
+        log("[bench] same path with DFISHER_SWEEPS_AUTO (measured residuals): 1 step")
+        xba = {lam: torch.empty(m, dtype=torch.float32, device=dev) for lam in lams}
+        eau, gau, stau, infau = run_path(dfl, ctx, S, v, lams, args.prec, -1, 1, 0, xba, args.shift)
+        auto = {"solves_per_s": len(lams) / eau, "sweeps_done": {str(l): i["sweeps_done"] for l, i in infau},
+                "resid": {str(l): i["resid"] for l, i in infau}, "stage_ms": stau}
+        log(f"[bench] auto: {auto['solves_per_s']:.3f} solves/s, sweeps {auto['sweeps_done']}")
 
     alt = None
     if args.alt_prec != "none" and args.alt_prec != args.prec:
@@ -564,7 +578,9 @@ def main() -> int:
     prep_write = {"mxfp8": n * ldq * (1 + 1 / 32), "bf16x3": 4.0 * n * ((m + 63) // 64 * 64), "fp32": 0.0}
     rowpass_bytes = 4.0 * n * m + 4.0 * m + 16.0 * n + prep_write[args.prec]
     apply_bytes = 4.0 * n * m + 8.0 * n + 8.0 * m
-    refine_bytes = sweeps_resolved * (4.0 * n * m + 8.0 * n)
+    timed = infos[-solves:]
+    sweeps_done = {str(l): i["sweeps_done"] for l, i in timed[-len(lams):]}
+    refine_bytes = sum(i["sweeps_done"] for _, i in timed) / len(timed) * (4.0 * n * m + 8.0 * n)
 
     def gbs(b, ms):
         return b / (ms * 1e-3) / 1e9 if ms else None
@@ -580,6 +596,8 @@ def main() -> int:
     del S, v, xbuf, x_mixed
     if fp32 is not None:
         del xb32
+    if auto is not None:
+        del xba
     if alt is not None:
         del xbalt
     torch.cuda.empty_cache()
@@ -592,12 +610,12 @@ def main() -> int:
     batched = None
     if not args.no_batched:
         log("[bench] batched leg: n=2048 m=2M, 16 lambdas x 8 right-hand sides")
-        batched = batched_leg(dfl, dev, args.prec, args.sweeps, args.leg_reps)
+        batched = batched_leg(dfl, dev, args.prec, args.leg_sweeps, args.leg_reps)
         log(f"[bench] batched {batched}")
     uneven = None
     if not args.no_uneven:
         log("[bench] uneven leg: 64 problems")
-        uneven = uneven_leg(dfl, dev, args.prec, args.sweeps, args.leg_reps)
+        uneven = uneven_leg(dfl, dev, args.prec, args.leg_sweeps, args.leg_reps)
         log(f"[bench] uneven {uneven}")
 
     line = {
@@ -616,8 +634,8 @@ def main() -> int:
         "config": {"workload": f"damped Fisher solve n={n} m={m} (iid N(0,1)/sqrt(n) column-centered S, iid v), "
                                f"one solve per lambda in {lams}",
                    "n": n, "m": m, "lambdas": lams, "gram": args.prec,
-                   "sweeps": "auto" if args.sweeps < 0 else args.sweeps, "sweeps_resolved": sweeps_resolved,
-                   "shift": args.shift, "solves_per_step": len(lams)},
+                   "sweeps": "auto" if args.sweeps < 0 else args.sweeps, "sweeps_a_priori_rule": sweeps_resolved,
+                   "sweeps_done": sweeps_done, "shift": args.shift, "solves_per_step": len(lams)},
         "roofline": {"bound": "mfma", "kernel": GRAM_KERNEL[args.prec], "achieved": achieved, "peak": peak,
                      "unit": "TFLOP/s", "frac": achieved / peak, "traffic": gram_traffic(args.prec, n, m),
                      "algorithmic_flops_per_launch": algo_flops, "avg_launch_ms": gram_avg_ms,
@@ -630,6 +648,7 @@ def main() -> int:
                 "refine_note": "refine_ms includes the triangular solves of every sweep",
                 "peak_GBs": HBM_PEAK_GBS},
         "fp32_path": fp32,
+        "auto_sweeps_path": auto,
         "alt_path": alt,
         "rel_err_vs_fp64": errors,
         "error_table": table,

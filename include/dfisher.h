@@ -84,9 +84,8 @@ typedef enum dfisher_shift_policy {
 
 typedef struct dfisher_options {
   int32_t gram_prec;     /* dfisher_gram_prec                                               */
-  int32_t sweeps;        /* FP64 iterative-refinement sweeps on W y = S v, 0..16 or
-                            DFISHER_SWEEPS_AUTO: each sweep forms r = S v - lambda y - S (S^T y)
-                            with FP64 accumulation and adds L^-T L^-1 r to y                  */
+  int32_t sweeps;        /* FP64 refinement sweeps on W y = S v (one read of S each; see below),
+                            0..16 or DFISHER_SWEEPS_AUTO                                      */
   int32_t shift_policy;  /* dfisher_shift_policy                                            */
   int32_t x_fp64;        /* 0: x (and X) are float*, 1: double*                             */
   double tol;            /* 0: run exactly `sweeps` sweeps. > 0 (dfisher_solve only; other
@@ -103,11 +102,17 @@ typedef struct dfisher_options {
   int32_t reserved;      /* must be 0                                                       */
 } dfisher_options;
 
-/* opt->sweeps = DFISHER_SWEEPS_AUTO lets the library choose the sweep count.
+/* Refinement sweeps. Each sweep reads S once. Sweep 1 forms the FP64 residual r = S v - lambda y
+ * - S (S^T y) of y = L^-T L^-1 S v; the sweeps after it are conjugate-gradient iterations on
+ * W y = S v preconditioned by the Cholesky factor of the computed Gram (one product W p per sweep,
+ * FP64 accumulation); after the last sweep the correction L^-T L^-1 r of the final residual is
+ * added. One sweep is thus the classic correction y += L^-T L^-1 (S v - W y).
+ *
+ * opt->sweeps = DFISHER_SWEEPS_AUTO lets the library choose the sweep count.
  *   dfisher_solve: measured. After each sweep's residual rho_k = |r_k| / |S v| (one stream
  *     synchronisation per sweep) the correction is applied, and the sweeps stop once the
- *     residual expected of the corrected iterate, rho_k * min(1, rho_k / rho_{k-1}) with
- *     rho_{-1} = 1, is <= opt->tol (1e-7 when opt->tol is 0); at most 16 sweeps, else
+ *     residual expected of the corrected iterate, rho_k * max(0.1, min(1, rho_k / rho_{k-1}))
+ *     with rho_{-1} = 1, is <= opt->tol (1e-7 when opt->tol is 0); at most 16 sweeps, else
  *     DFISHER_E_NOT_CONVERGED with x written. info->resid is the last rho_k.
  *   dfisher_factor_create, dfisher_solve_batched, dfisher_solve_uneven (no host round trip per
  *     sweep): the a-priori count of dfisher_auto_sweeps for each problem's shape, raised where
@@ -210,6 +215,17 @@ DFISHER_API dfisher_status dfisher_solve(dfisher_ctx* ctx, const float* S, int64
                              const float* v, double lambda, void* x, const dfisher_options* opt,
                              void* stream, dfisher_info* info);
 
+/* Structured right-hand side (Appendix B): when v = S^T f lies in the row space of S, the solution
+ * of Eq. 1 is x = S^T (S S^T + lambda I)^-1 f (the push-through identity of Proposition 1). This
+ * call takes f (FP64 device vector of length n) instead of v and runs Algorithm 1 with b = f: the
+ * pass for S v and the subtraction v - S^T y are skipped, and x = S^T y is written (FP32 rounded
+ * once, or FP64 per opt->x_fp64; length m). Refinement sweeps (opt->sweeps, DFISHER_SWEEPS_AUTO,
+ * opt->tol, opt->final_resid) act on W y = f exactly as in dfisher_solve, with residuals relative
+ * to |f|. Same errors and synchronisation as dfisher_solve; x must not overlap S or f. */
+DFISHER_API dfisher_status dfisher_solve_rowspace(dfisher_ctx* ctx, const float* S, int64_t n, int64_t m,
+                                                  int64_t lds, const double* f, double lambda, void* x,
+                                                  const dfisher_options* opt, void* stream, dfisher_info* info);
+
 /* Factor reuse: steps 1-2 of Algorithm 1 once (Gram + Cholesky, with the shift policy), then
  * any number of right-hand sides. The factor BORROWS S: S must stay valid and unchanged until
  * dfisher_factor_destroy. The factor keeps a pointer to ctx, which must outlive it. */
@@ -281,9 +297,11 @@ DFISHER_API dfisher_status dfisher_ctx_load_tuning(dfisher_ctx* ctx, const char*
  * the error of y = W^-1 S v by about c = |W~^-1 E| (E: error of the computed Gram, whose
  * diagonal is exact); the model c = C / (sqrt(m/n) (1 - sqrt(n/m))^2) with C = 0.1 (scaled FP8),
  * 1e-4 (split-BF16), 1e-5 (FP32) bounds the contraction of a Gram of rows with many independent
- * entries, and the count is the smallest k with c^(k+1) <= 1e-7 (at most 16). It is a heuristic:
- * for a guaranteed residual use opt->tol with dfisher_solve. Returns -1 for an unknown prec or
- * n, m < 1. */
+ * entries, and the count is the smallest k with c^(k+1) <= 1e-7; for the scaled-FP8 Gram it is
+ * then raised by 3 below m/n = 150 and by 2 below m/n = 600 (directions where the Gram's error
+ * exceeds W's eigenvalue, such as the all-ones direction of a column-centered S, converge only
+ * after the bulk); at most 16. It is a heuristic: for a measured residual use opt->tol with
+ * dfisher_solve. Returns -1 for an unknown prec or n, m < 1. */
 DFISHER_API int32_t dfisher_auto_sweeps(int32_t prec, int64_t n, int64_t m);
 
 /* Static text for a status code. */

@@ -24,6 +24,7 @@ __all__ = [
     "dfisher_trsv", "dfisher_apply", "dfisher_solve", "dfisher_factor_create", "dfisher_factor_solve",
     "dfisher_factor_copy_L", "dfisher_factor_destroy", "dfisher_solve_batched", "dfisher_solve_uneven",
     "dfisher_status_string", "dfisher_last_error", "dfisher_auto_sweeps", "DFISHER_SWEEPS_AUTO",
+    "dfisher_solve_rowspace",
 ]
 
 DFISHER_OK = 0
@@ -86,6 +87,8 @@ def _load():
         "dfisher_trsv": ([P, P, I64, I32, P, P, P], I32),
         "dfisher_apply": ([P, P, I64, I64, I64, P, P, D, P, I32, P], I32),
         "dfisher_solve": ([P, P, I64, I64, I64, P, D, P, ctypes.POINTER(_Options), P, ctypes.POINTER(Info)], I32),
+        "dfisher_solve_rowspace": ([P, P, I64, I64, I64, P, D, P, ctypes.POINTER(_Options), P,
+                                    ctypes.POINTER(Info)], I32),
         "dfisher_factor_create": ([P, P, I64, I64, I64, D, ctypes.POINTER(_Options), P, PP, ctypes.POINTER(Info)], I32),
         "dfisher_factor_solve": ([P, P, I64, I64, P, I64, P, ctypes.POINTER(Info)], I32),
         "dfisher_factor_copy_L": ([P, P, P], I32),
@@ -362,6 +365,30 @@ def dfisher_solve(ctx, S, v, lam: float, gram_prec: int = DFISHER_GRAM_FP32, swe
                               _stream(stream), ctypes.byref(info))
     if st != DFISHER_E_NOT_CONVERGED:
         _check(st, "dfisher_solve")
+    d = info.as_dict()
+    d["converged"] = st == DFISHER_OK
+    return x, d
+
+
+def dfisher_solve_rowspace(ctx, S, f, lam: float, gram_prec: int = DFISHER_GRAM_FP32, sweeps: int = 0,
+                           shift_policy: int = DFISHER_SHIFT_ON_FAILURE, x_fp64: bool = False, x=None, stream=None,
+                           tol: float = 0.0, final_resid: bool = False):
+    """x solving (S^T S + lam I) x = S^T f for an FP64 f of length n (the right-hand side in the row
+    space of S), as x = S^T (S S^T + lam I)^-1 f. Returns (x, info_dict) like dfisher_solve."""
+    torch = _torch()
+    n, m, lds = _S_args(S)
+    _vec(f, n, torch.float64, "f")
+    dt = torch.float64 if x_fp64 else torch.float32
+    if x is None:
+        x = torch.empty(m, dtype=dt, device=S.device)
+    _vec(x, m, dt, "x")
+    opt = _options(gram_prec, sweeps, shift_policy, x_fp64, final_resid)
+    opt.tol = float(tol)
+    info = Info()
+    st = _lib().dfisher_solve_rowspace(ctx.ptr, _ptr(S), n, m, lds, _ptr(f), float(lam), _ptr(x), ctypes.byref(opt),
+                                       _stream(stream), ctypes.byref(info))
+    if st != DFISHER_E_NOT_CONVERGED:
+        _check(st, "dfisher_solve_rowspace")
     d = info.as_dict()
     d["converged"] = st == DFISHER_OK
     return x, d

@@ -49,6 +49,7 @@ dfisher_status fail(dfisher_status s, const char* fmt, ...) {
 
 constexpr int MAX_SWEEPS = 16;
 constexpr double AUTO_TOL = 1e-7;   // the residual DFISHER_SWEEPS_AUTO aims for in dfisher_solve
+constexpr double AUTO_MIN_CONTRACTION = 0.1;   // least contraction a predictive stop assumes
 constexpr int MAX_SHIFT_ATTEMPTS = 10;
 
 size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -198,7 +199,11 @@ dfisher_status check_no_final(const dfisher_options& o) {
 // 2^-16, FP32 accumulation within a slice) and the smallest bulk eigenvalue of S S^T is
 // about |s|^2 (1 - sqrt(n/m))^2, so c ~ C_prec / (sqrt(m/n) (1 - sqrt(n/m))^2). A factored
 // shift tau adds tau / (|s|^2 (1 - sqrt(n/m))^2) (tau_rel = tau / max_i W_ii). The count is the
-// smallest k with c^(k+1) <= 1e-7, ten times below the 1e-6 error target; capped at 16.
+// smallest k with c^(k+1) <= 1e-7, ten times below the 1e-6 error target. The scaled-FP8 Gram's
+// error can also exceed W's eigenvalue along a few directions (for a column-centered S, the
+// all-ones one, eigenvalue ~ lambda); the conjugate-gradient sweeps remove such directions only
+// after the bulk, which took two or three more sweeps in measurements at m/n = 78 .. 256 (none at
+// m/n ~ 1000), so the count gets 3 more below m/n = 150 and 2 more below m/n = 600. Capped at 16.
 int auto_sweeps(int prec, int64_t n, int64_t m, double tau_rel) {
   const double a = (double)m / (double)n;
   const double C = prec == DFISHER_GRAM_MXFP8 ? 0.1 : (prec == DFISHER_GRAM_BF16X3 ? 1e-4 : 1e-5);
@@ -212,7 +217,8 @@ int auto_sweeps(int prec, int64_t n, int64_t m, double tau_rel) {
     e *= c;
     ++k;
   }
-  return k;
+  if (prec == DFISHER_GRAM_MXFP8) k += a < 150.0 ? 3 : (a < 600.0 ? 2 : 0);
+  return std::min(k, MAX_SWEEPS);
 }
 
 // Entry points that run a fixed number of sweeps reject a tolerance.
@@ -268,6 +274,10 @@ struct SolveBufs {
   double* z;       // work
   double* y;       // W^-1 S v
   double* r;       // refinement residual
+  double* zc;      // M^-1 r (refinement correction)
+  double* p;       // refinement search direction
+  double* nq;      // -(W p)
+  double* zero;    // n zeros (right-hand side of the W p pass)
   double* t;       // S^T y (m, FP64)
   double* Dinv;    // inverses of L's 64 x 64 diagonal blocks
   double* dkk;     // Cholesky scratch: current diagonal block inverse
@@ -295,6 +305,10 @@ SolveBufs carve(char* base, int64_t n, int64_t m, const dfi::GramPlan* gp, const
   s.z = c.take<double>((size_t)n);
   s.y = c.take<double>((size_t)n);
   s.r = c.take<double>((size_t)n);
+  s.zc = c.take<double>((size_t)n);
+  s.p = c.take<double>((size_t)n);
+  s.nq = c.take<double>((size_t)n);
+  s.zero = c.take<double>((size_t)n);
   s.t = need_t ? c.take<double>((size_t)m) : nullptr;
   s.Dinv = c.take<double>(dfi::trsv_dinv_bytes(n) / sizeof(double));
   s.dkk = c.take<double>(dfi::POTRF_DKK_BYTES / sizeof(double));
@@ -375,15 +389,41 @@ dfisher_status gram_stage(const float* S, const float* v, const dfi::GramPlan& g
   return DFISHER_OK;
 }
 
+// out = rhs - lambda u - S (S^T u) for an n-vector u (FP64 accumulation): one read of S through the
+// fused pass when `fp` allows it, else a column pass (t = S^T u into B.t) and a row pass. With
+// rhs = b and u = y it is the residual of y; with rhs = 0 and u = p it is -(W p).
+dfisher_status w_pass(const float* S, int64_t n, int64_t m, int64_t lds, double lambda, const double* u,
+                      const double* rhs, double* out, const SolveBufs& B, const dfi::RowPassPlan& rp,
+                      const dfi::ColPassPlan& cp, const dfi::RefinePassPlan* fp, hipStream_t st) {
+  if (fp && fp->usable) {
+    HIP_TRY(dfi::refine_pass_launch(*fp, S, n, m, lds, u, B.rpart, st));
+    HIP_TRY(dfi::refine_pass_reduce(*fp, B.rpart, out, rhs, u, lambda, st));
+  } else {
+    HIP_TRY(dfi::colpass_launch(cp, S, n, m, lds, u, nullptr, 1.0, B.t, 2, B.cpart, st));
+    HIP_TRY(dfi::rowpass_launch(rp, S, nullptr, B.t, true, false, B.rpart, st));
+    HIP_TRY(dfi::rowpass_reduce(rp, B.rpart, true, false, out, nullptr, rhs, u, lambda, st));
+  }
+  return DFISHER_OK;
+}
+
 // y = W^-1 b through the factor, then `sweeps` refinement sweeps against the exact operator
-// W = S S^T + lambda I: r = b - lambda y - S (S^T y) (FP64 accumulation), y += L^-T L^-1 r. The
-// product S (S^T y) takes one read of S through the fused pass when `fp` allows it, else a column
-// pass (t = S^T y into B.t) and a row pass. With tol > 0 (ctx given): after each residual, read
-// rho = |r| / |b| (one synchronisation), apply the correction, stop once rho <= tol. *done and
-// *resid report the sweeps applied and the last rho (-1 if none was measured).
+// W = S S^T + lambda I. A sweep is one read of S. Sweep 1 forms the residual r = b - W y; the
+// sweeps after it are conjugate-gradient iterations preconditioned by M = L L^T (the factor of the
+// computed, possibly shifted, Gram): q = W p from one pass, alpha = r.z / p.q, y += alpha p,
+// r -= alpha q, z = M^-1 r, p = z + beta p. After the last sweep the correction z = M^-1 r of the
+// final residual is added (y += z: with one sweep this is the classic correction
+// y += L^-T L^-1 (b - W y)). Unlike the plain correction repeated, the iteration does not stall
+// on directions where the computed Gram is far from W relative to W's eigenvalue there (for a
+// column-centered S, the all-ones direction has eigenvalue ~ lambda while the Gram's rounding
+// error along it can be much larger). With tol > 0 (ctx given): after each sweep read
+// rho = |r| / |b| (one synchronisation; from sweep 2 on r is the iteration's recurrence), apply
+// the correction and stop once rho <= tol. *done and *resid report the sweeps run and the last
+// rho (-1 if none was measured).
 // With `predict` the stop test is on the residual the corrected iterate is expected to have:
 // rho_k times the contraction measured over the last sweep, rho_k / rho_{k-1} (rho_{-1} = 1, the
-// residual of y = 0), so that the sweep that brings the residual under tol is the last one.
+// residual of y = 0), but never less than AUTO_MIN_CONTRACTION times rho_k, so that the call
+// stops only once a measured residual is <= tol / AUTO_MIN_CONTRACTION: the measured contraction
+// of one sweep can hide a slower direction (the all-ones one above).
 dfisher_status solve_y(const float* S, int64_t n, int64_t m, int64_t lds, double lambda, const double* L,
                        const double* Dinv, const SolveBufs& B, const dfi::RowPassPlan& rp, const dfi::ColPassPlan& cp,
                        int sweeps, hipStream_t st, StageClock* clk = nullptr, const dfi::RefinePassPlan* fp = nullptr,
@@ -394,42 +434,49 @@ dfisher_status solve_y(const float* S, int64_t n, int64_t m, int64_t lds, double
     HIP_TRY(dfi::trsv_launch(L, Dinv, n, 1, B.z, B.y, B.tw, st));
     if (clk) clk->mark(5);
   }
-  const bool fused = fp && fp->usable;
   const bool measure = ctx && tol > 0.0;
   if (done) *done = 0;
   if (resid) *resid = -1.0;
   if (met) *met = false;
-  double prev = 1.0;
-  if (measure) HIP_TRY(dfi::sumsq(B.b, n, ctx->d_scalar + 2, st));
-  for (int s = 0; s < sweeps; ++s) {
-    if (fused) {
-      HIP_TRY(dfi::refine_pass_launch(*fp, S, n, m, lds, B.y, B.rpart, st));
-      HIP_TRY(dfi::refine_pass_reduce(*fp, B.rpart, B.r, B.b, B.y, lambda, st));
-    } else {
-      HIP_TRY(dfi::colpass_launch(cp, S, n, m, lds, B.y, nullptr, 1.0, B.t, 2, B.cpart, st));
-      HIP_TRY(dfi::rowpass_launch(rp, S, nullptr, B.t, true, false, B.rpart, st));
-      HIP_TRY(dfi::rowpass_reduce(rp, B.rpart, true, false, B.r, nullptr, B.b, B.y, lambda, st));
-    }
-    double rho = -1.0;
-    if (measure) {
-      HIP_TRY(dfi::sumsq(B.r, n, ctx->d_scalar + 3, st));
-      HIP_TRY(hipMemcpyAsync(ctx->h_scalar + 2, ctx->d_scalar + 2, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
-      HIP_TRY(hipStreamSynchronize(st));
-      const double bb = ctx->h_scalar[2], rr = ctx->h_scalar[3];
-      rho = bb > 0.0 ? std::sqrt(rr / bb) : (rr > 0.0 ? INFINITY : 0.0);
-      if (resid) *resid = rho;
-    }
-    HIP_TRY(dfi::trsv_launch(L, Dinv, n, 0, B.r, B.z, B.tw, st));
-    HIP_TRY(dfi::trsv_launch(L, Dinv, n, 1, B.z, B.r, B.tw, st));
-    HIP_TRY(dfi::axpy_inplace(B.y, B.r, n, st));
-    if (done) *done = s + 1;
-    if (measure) {
-      const double expect = predict ? rho * std::min(1.0, prev > 0.0 ? rho / prev : 0.0) : rho;
-      prev = rho;
-      if (expect <= tol) {
-        if (met) *met = true;
+  if (sweeps > 0) {
+    double* rz = ctx ? ctx->d_scalar + 4 : nullptr;
+    double* rr = ctx ? ctx->d_scalar + 3 : nullptr;
+    if (!rz) return fail(DFISHER_E_DEVICE, "refinement needs the context's scalars");
+    if (measure) HIP_TRY(dfi::sumsq(B.b, n, ctx->d_scalar + 2, st));
+    HIP_TRY(dfi::fill_zero(B.zero, n, st));
+    DF_TRY(w_pass(S, n, m, lds, lambda, B.y, B.b, B.r, B, rp, cp, fp, st));   // sweep 1: r = b - W y
+    if (measure) HIP_TRY(dfi::sumsq(B.r, n, rr, st));
+    double prev = 1.0;
+    for (int s = 1;; ++s) {
+      double rho = -1.0;
+      if (measure) {
+        HIP_TRY(hipMemcpyAsync(ctx->h_scalar + 2, ctx->d_scalar + 2, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        const double bb = ctx->h_scalar[2], rrh = ctx->h_scalar[3];
+        rho = bb > 0.0 ? std::sqrt(rrh / bb) : (rrh > 0.0 ? INFINITY : 0.0);
+        if (resid) *resid = rho;
+      }
+      HIP_TRY(dfi::trsv_launch(L, Dinv, n, 0, B.r, B.z, B.tw, st));
+      HIP_TRY(dfi::trsv_launch(L, Dinv, n, 1, B.z, B.zc, B.tw, st));
+      bool stop = s >= sweeps;
+      if (measure) {
+        const double expect =
+            predict ? rho * std::max(AUTO_MIN_CONTRACTION, std::min(1.0, prev > 0.0 ? rho / prev : 0.0)) : rho;
+        prev = rho;
+        if (expect <= tol) {
+          if (met) *met = true;
+          stop = true;
+        }
+      }
+      if (stop) {
+        HIP_TRY(dfi::pcg_finish(nullptr, n, 0, 1, B.zc, B.y, st));
+        if (done) *done = s;
         break;
       }
+      if (s == 1) HIP_TRY(dfi::pcg_init(nullptr, n, 0, 1, B.r, B.zc, B.p, rz, st));
+      else HIP_TRY(dfi::pcg_dir(nullptr, n, 0, 1, B.r, B.zc, B.p, rz, st));
+      DF_TRY(w_pass(S, n, m, lds, lambda, B.p, B.zero, B.nq, B, rp, cp, fp, st));   // -(W p)
+      HIP_TRY(dfi::pcg_step(nullptr, n, 0, 1, B.p, B.nq, B.y, B.r, rz, measure ? rr : nullptr, st));
     }
   }
   if (clk) clk->mark(6);
@@ -465,6 +512,7 @@ dfisher_status final_residual(dfisher_ctx* ctx, const float* S, int64_t n, int64
 // x = (v_r - S^T y) / lambda_f. Needs nfac * nrhs <= 65535.
 struct MultiBufs {
   double *Bs, *Bexp, *Y, *R, *D, *W1, *T, *Yi, *part;
+  double *Zc, *P, *NQ, *zero, *rz;   // refinement: M^-1 R, directions, -(W P), n zeros, r.z per vector
 };
 
 MultiBufs carve_multi(Carver& c, int64_t n, int64_t m, int64_t nrhs, int64_t nvec, const dfi::RowMultiPlan& rm,
@@ -479,6 +527,11 @@ MultiBufs carve_multi(Carver& c, int64_t n, int64_t m, int64_t nrhs, int64_t nve
   b.T = need_t ? c.take<double>((size_t)(m * dfi::MULTI_VECS)) : nullptr;
   b.Yi = c.take<double>((size_t)(n * dfi::MULTI_VECS));
   b.part = c.take<double>(rm.part_bytes / sizeof(double) + 1);
+  b.Zc = c.take<double>((size_t)(nvec * n));
+  b.P = c.take<double>((size_t)(nvec * n));
+  b.NQ = c.take<double>((size_t)(nvec * n));
+  b.zero = c.take<double>((size_t)n);
+  b.rz = c.take<double>((size_t)nvec);
   return b;
 }
 
@@ -506,18 +559,20 @@ dfisher_status multi_solve(const float* S, int64_t n, int64_t m, int64_t lds, in
   // Y = L^-T L^-1 B for every vector
   HIP_TRY(dfi::trsv_launch_batched(L, sL, Dinv, n, nvec, nrhs, 0, b.Bexp, b.D, b.W1, st));
   HIP_TRY(dfi::trsv_launch_batched(L, sL, Dinv, n, nvec, nrhs, 1, b.D, b.Y, b.W1, st));
-  for (int s = 0; s < sweeps; ++s) {
-    // R = B - lambda Y - S (S^T Y), MV vectors per pair of passes
+  // refinement: OUT_j = RHS_j - lambda_j U_j - S (S^T U_j), MV vectors per pair of passes (the
+  // conjugate-gradient sweeps of solve_y, for every vector at once; RHS = B for the residual of Y,
+  // RHS = 0 for -(W P))
+  auto w_pass = [&](const double* U, const double* RHS, bool rhs_zero, double* OUT) -> dfisher_status {
     for (int64_t j0 = 0; j0 < nvec; j0 += MV) {
       const int nv = (int)std::min<int64_t>(MV, nvec - j0);
       dfi::MultiCols mc{};
       dfi::MultiOut mo{};
-      for (int c = 0; c < MV; ++c) mc.y[c] = b.Y + (j0 + std::min(c, nv - 1)) * n;
+      for (int c = 0; c < MV; ++c) mc.y[c] = U + (j0 + std::min(c, nv - 1)) * n;
       for (int c = 0; c < nv; ++c) {
         const int64_t j = j0 + c;
-        mo.b[c] = b.R + j * n;
-        mo.r0[c] = b.Bexp + j * n;
-        mo.y[c] = b.Y + j * n;
+        mo.b[c] = OUT + j * n;
+        mo.r0[c] = rhs_zero ? RHS : RHS + j * n;
+        mo.y[c] = U + j * n;
         mo.lam[c] = lams[j / nrhs];
       }
       HIP_TRY(dfi::colpass_multi_launch(S, n, m, lds, mc, nv, 2, b.T, b.Yi, st));
@@ -525,9 +580,23 @@ dfisher_status multi_solve(const float* S, int64_t n, int64_t m, int64_t lds, in
       HIP_TRY(dfi::rowpass_multi_launch(rm, S, none, b.T, nv, b.part, st));
       HIP_TRY(dfi::rowpass_multi_reduce(rm, b.part, nv, mo, st));
     }
-    HIP_TRY(dfi::trsv_launch_batched(L, sL, Dinv, n, nvec, nrhs, 0, b.R, b.D, b.W1, st));
-    HIP_TRY(dfi::trsv_launch_batched(L, sL, Dinv, n, nvec, nrhs, 1, b.D, b.R, b.W1, st));
-    HIP_TRY(dfi::axpy_many(b.Y, b.R, nvec * n, st));
+    return DFISHER_OK;
+  };
+  if (sweeps > 0) {
+    HIP_TRY(dfi::fill_zero(b.zero, n, st));
+    DF_TRY(w_pass(b.Y, b.Bexp, false, b.R));
+    for (int s = 1;; ++s) {
+      HIP_TRY(dfi::trsv_launch_batched(L, sL, Dinv, n, nvec, nrhs, 0, b.R, b.D, b.W1, st));
+      HIP_TRY(dfi::trsv_launch_batched(L, sL, Dinv, n, nvec, nrhs, 1, b.D, b.Zc, b.W1, st));
+      if (s >= sweeps) {
+        HIP_TRY(dfi::axpy_many(b.Y, b.Zc, nvec * n, st));
+        break;
+      }
+      if (s == 1) HIP_TRY(dfi::pcg_init(nullptr, n, 0, nvec, b.R, b.Zc, b.P, b.rz, st));
+      else HIP_TRY(dfi::pcg_dir(nullptr, n, 0, nvec, b.R, b.Zc, b.P, b.rz, st));
+      DF_TRY(w_pass(b.P, b.zero, true, b.NQ));
+      HIP_TRY(dfi::pcg_step(nullptr, n, 0, nvec, b.P, b.NQ, b.Y, b.R, b.rz, nullptr, st));
+    }
   }
   // x = (v - S^T y) / lambda, MV vectors per pass
   const size_t xel = x_fp64 ? sizeof(double) : sizeof(float);
@@ -659,6 +728,7 @@ struct UnevenLayout {
   SolveBufs shared{};                      // scratch reused by every problem (largest sizes)
   double *W = nullptr, *Dinv = nullptr, *dkk = nullptr, *dmax = nullptr;
   double *b = nullptr, *d = nullptr, *y = nullptr, *z = nullptr, *r = nullptr, *wk = nullptr;
+  double *zc = nullptr, *p = nullptr, *nq = nullptr, *zero = nullptr, *rz = nullptr;   // refinement (PCG)
   int64_t* info = nullptr;
   int32_t* flag = nullptr;
   double* res = nullptr;                   // final residuals: |b_p|^2, |r_p|^2 per problem
@@ -722,6 +792,11 @@ void uneven_layout(const dfisher_ctx* ctx, char* base, int32_t np, const float* 
   U.z = c.take<double>((size_t)U.ntot);
   U.r = c.take<double>((size_t)U.ntot);
   U.wk = c.take<double>((size_t)U.ntot);
+  U.zc = c.take<double>((size_t)U.ntot);
+  U.p = c.take<double>((size_t)U.ntot);
+  U.nq = c.take<double>((size_t)U.ntot);
+  U.zero = c.take<double>((size_t)U.nmax);
+  U.rz = c.take<double>((size_t)np);
   U.info = c.take<int64_t>((size_t)np);
   U.flag = c.take<int32_t>((size_t)np);
   U.res = c.take<double>((size_t)(2 * np));
@@ -736,7 +811,7 @@ dfisher_status uneven_enqueue(dfisher_ctx* ctx, int32_t np, const float* const* 
                               const dfisher_options& o, const UnevenLayout& U, const std::vector<int32_t>& order,
                               const std::vector<int>& sw, const std::vector<int64_t>& nactive,
                               const dfi::FactorJob* fjobs, const dfi::TrsvJob* tj_fwd, const dfi::TrsvJob* tj_bwd,
-                              const dfi::TrsvJob* tj_bwd_r, hipStream_t st) {
+                              const dfi::TrsvJob* tj_bwd_c, const int64_t* seg, hipStream_t st) {
   (void)ctx;
   // Gram stage per problem, largest first: b_p = S_p v_p, d_p, W_p = S_p S_p^T + lambda_p I
   for (int32_t p : order) {
@@ -763,37 +838,48 @@ dfisher_status uneven_enqueue(dfisher_ctx* ctx, int32_t np, const float* const* 
   HIP_TRY(dfi::trsv_launch_grouped(tj_fwd, np, U.nmax, 0, st));    // wk -> z
   HIP_TRY(hipMemcpyAsync(U.wk, U.z, vb, hipMemcpyDeviceToDevice, st));
   HIP_TRY(dfi::trsv_launch_grouped(tj_bwd, np, U.nmax, 1, st));    // wk -> y
-  // r_p = b_p - lambda_p y_p - S_p (S_p^T y_p) (FP64 accumulation)
-  auto residual = [&](int32_t p) -> dfisher_status {
+  // out_p = rhs_p - lambda_p u_p - S_p (S_p^T u_p) (FP64 accumulation): the residual of y_p
+  // (rhs = b, u = y) or -(W_p p_p) (rhs = 0, u = p)
+  auto w_pass = [&](int32_t p, const double* u, const double* rhs, bool rhs_zero, double* out) -> dfisher_status {
     const int64_t off = U.voff[(size_t)p];
+    const double* rh = rhs_zero ? rhs : rhs + off;
     if (U.fp[(size_t)p].usable) {   // one read of S_p
-      HIP_TRY(dfi::refine_pass_launch(U.fp[(size_t)p], S[p], n[p], m[p], lds[p], U.y + off, U.shared.rpart, st));
-      HIP_TRY(dfi::refine_pass_reduce(U.fp[(size_t)p], U.shared.rpart, U.r + off, U.b + off, U.y + off, lambda[p], st));
+      HIP_TRY(dfi::refine_pass_launch(U.fp[(size_t)p], S[p], n[p], m[p], lds[p], u + off, U.shared.rpart, st));
+      HIP_TRY(dfi::refine_pass_reduce(U.fp[(size_t)p], U.shared.rpart, out + off, rh, u + off, lambda[p], st));
       return DFISHER_OK;
     }
-    HIP_TRY(dfi::colpass_launch(U.cp[(size_t)p], S[p], n[p], m[p], lds[p], U.y + off, nullptr, 1.0, U.shared.t, 2,
+    HIP_TRY(dfi::colpass_launch(U.cp[(size_t)p], S[p], n[p], m[p], lds[p], u + off, nullptr, 1.0, U.shared.t, 2,
                                 U.shared.cpart, st));
     HIP_TRY(dfi::rowpass_launch(U.rp[(size_t)p], S[p], nullptr, U.shared.t, true, false, U.shared.rpart, st));
-    HIP_TRY(dfi::rowpass_reduce(U.rp[(size_t)p], U.shared.rpart, true, false, U.r + off, nullptr, U.b + off, U.y + off,
+    HIP_TRY(dfi::rowpass_reduce(U.rp[(size_t)p], U.shared.rpart, true, false, out + off, nullptr, rh, u + off,
                                 lambda[p], st));
     return DFISHER_OK;
   };
+  auto residual = [&](int32_t p) -> dfisher_status { return w_pass(p, U.y, U.b, false, U.r); };
+  // the conjugate-gradient sweeps of solve_y, per problem; the job tables and the segment table
+  // list the problems by decreasing sweep count, so the problems in sweep s (sw >= s) are the
+  // first nactive[s - 1] entries and those that go on after it the first nactive[s]
   const int max_sw = nactive.empty() ? 0 : (int)nactive.size();
-  for (int s = 0; s < max_sw; ++s) {
-    for (int32_t p : order) {
-      if (sw[(size_t)p] > s) {
-        DF_TRY(residual(p));
-      } else if (sw[(size_t)p] == s) {
-        // done refining: a zero correction from here on (the solves below skip it, y += 0)
-        HIP_TRY(dfi::fill_zero(U.r + U.voff[(size_t)p], n[p], st));
-      }
+  if (max_sw > 0) {
+    HIP_TRY(dfi::fill_zero(U.zero, U.nmax, st));
+    for (int32_t p : order)
+      if (sw[(size_t)p] > 0) DF_TRY(residual(p));
+    for (int s = 1;; ++s) {
+      const int64_t act = nactive[(size_t)(s - 1)];
+      const int64_t cont = s < max_sw ? nactive[(size_t)s] : 0;
+      // zc = L^-T L^-1 r for the problems in this sweep
+      HIP_TRY(hipMemcpyAsync(U.wk, U.r, vb, hipMemcpyDeviceToDevice, st));
+      HIP_TRY(dfi::trsv_launch_grouped(tj_fwd, act, U.nmax, 0, st));     // wk -> z
+      HIP_TRY(hipMemcpyAsync(U.wk, U.z, vb, hipMemcpyDeviceToDevice, st));
+      HIP_TRY(dfi::trsv_launch_grouped(tj_bwd_c, act, U.nmax, 1, st));   // wk -> zc
+      HIP_TRY(dfi::pcg_finish(seg, 0, cont, act, U.zc, U.y, st));        // last sweep: y += zc
+      if (cont == 0) break;
+      if (s == 1) HIP_TRY(dfi::pcg_init(seg, 0, 0, cont, U.r, U.zc, U.p, U.rz, st));
+      else HIP_TRY(dfi::pcg_dir(seg, 0, 0, cont, U.r, U.zc, U.p, U.rz, st));
+      for (int32_t p : order)
+        if (sw[(size_t)p] > s) DF_TRY(w_pass(p, U.p, U.zero, true, U.nq));   // -(W_p p_p)
+      HIP_TRY(dfi::pcg_step(seg, 0, 0, cont, U.p, U.nq, U.y, U.r, U.rz, nullptr, st));
     }
-    // delta = L^-T L^-1 r for the problems still refining, y += delta for all
-    HIP_TRY(hipMemcpyAsync(U.wk, U.r, vb, hipMemcpyDeviceToDevice, st));
-    HIP_TRY(dfi::trsv_launch_grouped(tj_fwd, nactive[(size_t)s], U.nmax, 0, st));
-    HIP_TRY(hipMemcpyAsync(U.wk, U.z, vb, hipMemcpyDeviceToDevice, st));
-    HIP_TRY(dfi::trsv_launch_grouped(tj_bwd_r, nactive[(size_t)s], U.nmax, 1, st));  // wk -> r
-    HIP_TRY(dfi::axpy_many(U.y, U.r, U.ntot, st));
   }
   if (o.final_resid) {   // the returned iterate's residual, per problem (not applied)
     for (int32_t p : order) {
@@ -837,7 +923,7 @@ dfisher_status uneven_solve(dfisher_ctx* ctx, int32_t np, const float* const* S,
     return (double)n[a] * (double)n[a] * (double)m[a] > (double)n[b] * (double)n[b] * (double)m[b];
   });
   // job tables: factor jobs, forward solves (wk -> z, the first entry set also drives diag_inv)
-  // and backward solves (wk -> y for the first solve, wk -> r inside sweeps: two tables)
+  // and backward solves (wk -> y for the first solve, wk -> zc inside sweeps: two tables)
   // table entry j holds problem jord[j]: decreasing sweep count, so that the problems still
   // refining in sweep s are a prefix of the tables (nactive[s] entries)
   std::vector<int32_t> jord((size_t)np);
@@ -848,6 +934,7 @@ dfisher_status uneven_solve(dfisher_ctx* ctx, int32_t np, const float* const* S,
     for (int32_t p = 0; p < np; ++p) nactive[(size_t)s] += sw[(size_t)p] > s ? 1 : 0;
   std::vector<dfi::FactorJob> fj((size_t)np);
   std::vector<dfi::TrsvJob> tf((size_t)np), tb((size_t)np), tr((size_t)np);
+  std::vector<int64_t> seg((size_t)(2 * np));   // refinement vectors in table order: (offset, length)
   for (int32_t j = 0; j < np; ++j) {
     const int32_t p = jord[(size_t)j];
     const size_t q = (size_t)p;
@@ -855,20 +942,25 @@ dfisher_status uneven_solve(dfisher_ctx* ctx, int32_t np, const float* const* S,
     fj[(size_t)j] = dfi::FactorJob{Wp, n[p], U.info + p, U.flag + p, U.dkk + (int64_t)p * 64 * 64};
     tf[(size_t)j] = dfi::TrsvJob{Wp, U.Dinv + U.doff[q], n[p], U.wk + U.voff[q], U.z + U.voff[q]};
     tb[(size_t)j] = dfi::TrsvJob{Wp, U.Dinv + U.doff[q], n[p], U.wk + U.voff[q], U.y + U.voff[q]};
-    tr[(size_t)j] = dfi::TrsvJob{Wp, U.Dinv + U.doff[q], n[p], U.wk + U.voff[q], U.r + U.voff[q]};
+    tr[(size_t)j] = dfi::TrsvJob{Wp, U.Dinv + U.doff[q], n[p], U.wk + U.voff[q], U.zc + U.voff[q]};
+    seg[(size_t)(2 * j)] = U.voff[q];
+    seg[(size_t)(2 * j + 1)] = n[p];
   }
   const size_t fbytes = align_up(fj.size() * sizeof(dfi::FactorJob));
   const size_t tbytes = align_up(tf.size() * sizeof(dfi::TrsvJob));
-  DF_TRY(ensure_tbuf(ctx, fbytes + 3 * tbytes));
+  const size_t sbytes = align_up(seg.size() * sizeof(int64_t));
+  DF_TRY(ensure_tbuf(ctx, fbytes + 3 * tbytes + sbytes));
   char* tb0 = static_cast<char*>(ctx->tbuf);
   auto* d_fj = reinterpret_cast<dfi::FactorJob*>(tb0);
   auto* d_tf = reinterpret_cast<dfi::TrsvJob*>(tb0 + fbytes);
   auto* d_tb = reinterpret_cast<dfi::TrsvJob*>(tb0 + fbytes + tbytes);
   auto* d_tr = reinterpret_cast<dfi::TrsvJob*>(tb0 + fbytes + 2 * tbytes);
+  auto* d_seg = reinterpret_cast<int64_t*>(tb0 + fbytes + 3 * tbytes);
   HIP_TRY(hipMemcpyAsync(d_fj, fj.data(), fj.size() * sizeof(dfi::FactorJob), hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(d_tf, tf.data(), tf.size() * sizeof(dfi::TrsvJob), hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(d_tb, tb.data(), tb.size() * sizeof(dfi::TrsvJob), hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(d_tr, tr.data(), tr.size() * sizeof(dfi::TrsvJob), hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(d_seg, seg.data(), seg.size() * sizeof(int64_t), hipMemcpyHostToDevice, st));
   HIP_TRY(hipStreamSynchronize(st));   // the host tables go out of scope; the graph reads the device copies
 
   // the run: replay the captured graph if every argument and buffer is unchanged
@@ -914,7 +1006,7 @@ dfisher_status uneven_solve(dfisher_ctx* ctx, int32_t np, const float* const* S,
         dfisher_status se = DFISHER_OK;
         if (ok)
           se = uneven_enqueue(ctx, np, S, n, m, lds, v, lambda, x, o, U, order, sw, nactive, d_fj, d_tf, d_tb, d_tr,
-                              ctx->cap_stream);
+                              d_seg, ctx->cap_stream);
         if (ok) ok = hipStreamEndCapture(ctx->cap_stream, &graph) == hipSuccess && graph != nullptr;
         if (ok && se == DFISHER_OK) {
           hipGraphExec_t ex = nullptr;
@@ -933,7 +1025,8 @@ dfisher_status uneven_solve(dfisher_ctx* ctx, int32_t np, const float* const* S,
     }
   }
   if (!ran)
-    DF_TRY(uneven_enqueue(ctx, np, S, n, m, lds, v, lambda, x, o, U, order, sw, nactive, d_fj, d_tf, d_tb, d_tr, st));
+    DF_TRY(uneven_enqueue(ctx, np, S, n, m, lds, v, lambda, x, o, U, order, sw, nactive, d_fj, d_tf, d_tb, d_tr, d_seg,
+                          st));
   std::vector<int64_t> hinfo((size_t)np);
   std::vector<double> hmax((size_t)np, 0.0), hres((size_t)(2 * np), -1.0);
   HIP_TRY(hipMemcpyAsync(hinfo.data(), U.info, (size_t)np * sizeof(int64_t), hipMemcpyDeviceToHost, st));
@@ -1380,6 +1473,71 @@ dfisher_status dfisher_solve(dfisher_ctx* ctx, const float* S, int64_t n, int64_
   inf.w_resid = -1.0;
   if (o.final_resid) DF_TRY(final_residual(ctx, S, n, m, lds, lambda, B, rp, cp, fp, st, &inf.w_resid));
   HIP_TRY(dfi::colpass_launch(cp, S, n, m, lds, B.y, v, lambda, x, o.x_fp64, B.cpart, st));
+  clk.mark(7);
+  inf.sweeps_done = done;
+  inf.resid = resid;
+  if (info) *info = inf;
+  if (tol > 0.0 && !met)
+    return fail(DFISHER_E_NOT_CONVERGED, "relative residual %.3g above tol %.3g after %d sweep(s)", resid, tol, done);
+  return DFISHER_OK;
+}
+
+// Appendix B: v = S^T f. By the push-through identity x = S^T (S S^T + lambda I)^-1 f, so the solve
+// runs Algorithm 1 with b = f: no pass for S v and no subtraction v - S^T y (whose cancellation
+// costs accuracy when v lies in the row space of S). Refinement sweeps correct y against
+// W y = f with the exact operator, as in dfisher_solve.
+dfisher_status dfisher_solve_rowspace(dfisher_ctx* ctx, const float* S, int64_t n, int64_t m, int64_t lds,
+                                      const double* f, double lambda, void* x, const dfisher_options* opt,
+                                      void* stream, dfisher_info* info) {
+  DF_TRY(check_ctx(ctx));
+  DF_TRY(check_S(S, n, m, lds));
+  if (!f || !x) return fail(DFISHER_E_INVALID_ARG, "f or x is NULL");
+  if (!finite_pos(lambda)) return fail(DFISHER_E_INVALID_ARG, "lambda must be finite and > 0");
+  dfisher_options o;
+  DF_TRY(check_opt(opt, &o));
+  DF_TRY(check_prec_layout(o.gram_prec, S, lds));
+  DeviceGuard g(ctx->device);
+  hipStream_t st = as_stream(stream);
+  if (ctx->autotune) DF_TRY(tune_if_new(ctx, S, n, m, lds, o.gram_prec, st));
+  const dfi::GramPlan gp = make_gram_plan(ctx, S, n, m, lds, o.gram_prec);
+  const dfi::RowPassPlan rp = dfi::rowpass_plan(n, m, lds);
+  const dfi::ColPassPlan cp = dfi::colpass_plan(n, m);
+  const dfi::RefinePassPlan fp = dfi::refine_pass_plan(n, m, lds, S);
+  const bool need_t = (o.sweeps != 0 || o.final_resid) && !fp.usable;
+  SolveBufs B = carve(nullptr, n, m, &gp, rp, cp, true, need_t, &fp);
+  DF_TRY(ensure_ws(ctx, B.bytes));
+  B = carve(static_cast<char*>(ctx->ws), n, m, &gp, rp, cp, true, need_t, &fp);
+  StageClock clk(ctx, st);
+  // one pass over S for the exact diagonal (and the FP8 codes), then step 1; b = f
+  DF_TRY(gram_stage(S, nullptr, gp, rp, B, lambda, B.W, 0, st, &clk));
+  HIP_TRY(hipMemcpyAsync(B.b, f, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, st));
+  clk.mark(3);
+  dfisher_info inf{};
+  inf.resid = -1.0;
+  auto first_solve = [&]() -> dfisher_status {
+    clk.mark(4);
+    HIP_TRY(dfi::trsv_diag_inv(B.L, n, B.Dinv, st));
+    HIP_TRY(dfi::trsv_launch(B.L, B.Dinv, n, 0, B.b, B.z, B.tw, st));
+    HIP_TRY(dfi::trsv_launch(B.L, B.Dinv, n, 1, B.z, B.y, B.tw, st));
+    clk.mark(5);
+    return DFISHER_OK;
+  };
+  bool spec_ok = false;
+  DF_TRY(factor_with_policy(ctx, B.W, B.L, B.dkk, n, o.shift_policy, gram_unit(o.gram_prec, m), st, &inf.shift,
+                            &inf.potrf_info, &inf.attempts, first_solve, &spec_ok));
+  if (!spec_ok) DF_TRY(first_solve());
+  const bool autos = o.sweeps == DFISHER_SWEEPS_AUTO;
+  const int sweeps = autos ? MAX_SWEEPS : o.sweeps;
+  const double tol = autos && !(o.tol > 0.0) ? AUTO_TOL : o.tol;
+  int done = 0;
+  double resid = -1.0;
+  bool met = false;
+  DF_TRY(solve_y(S, n, m, lds, lambda, B.L, B.Dinv, B, rp, cp, sweeps, st, &clk, &fp, ctx, tol, &done, &resid,
+                 false, autos, &met));
+  inf.w_resid = -1.0;
+  if (o.final_resid) DF_TRY(final_residual(ctx, S, n, m, lds, lambda, B, rp, cp, fp, st, &inf.w_resid));
+  // x = S^T y, rounded once (FP32) or kept in FP64
+  HIP_TRY(dfi::colpass_launch(cp, S, n, m, lds, B.y, nullptr, 1.0, x, o.x_fp64 ? 2 : 3, B.cpart, st));
   clk.mark(7);
   inf.sweeps_done = done;
   inf.resid = resid;

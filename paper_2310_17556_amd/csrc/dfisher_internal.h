@@ -80,7 +80,8 @@ hipError_t rowpass_reduce(const RowPassPlan& p, const double* part, bool want_b,
                           double* d, const double* r0, const double* y, double lam, hipStream_t st);
 
 // Column pass: t_k = sum_i S_ik y_i (FP64). mode 0: x = (v - t)/lambda as FP32,
-// mode 1: same as FP64, mode 2: store t itself as FP64 (for the refinement residual).
+// mode 1: same as FP64, mode 2: store t itself as FP64 (for the refinement residual), mode 3:
+// t rounded once to FP32 (v and lambda unused in modes 2 and 3).
 // When m is small the rows are split over nsplit workgroups; `part` (part_bytes) then holds
 // FP64 partial sums.
 struct ColPassPlan {
@@ -194,6 +195,22 @@ struct TrsvJob {
 };
 hipError_t trsv_diag_inv_grouped(const TrsvJob* jobs_dev, int64_t njobs, int64_t nmax, hipStream_t st);
 hipError_t trsv_launch_grouped(const TrsvJob* jobs_dev, int64_t njobs, int64_t nmax, int trans, hipStream_t st);
+
+// ----------------------------------------------------------------------------- refinement (PCG)
+// n-vector steps of conjugate gradients on W y = b preconditioned by the Gram's factor (pcg.hip).
+// Segments of a concatenated vector array: s -> [seg[2 s], seg[2 s] + seg[2 s + 1]) from a device
+// table of (offset, length) pairs, or [s n, s n + n) when seg is null; a launch covers s0 .. s1 - 1, per-segment scalars at index s.
+// pcg_init: p = z, rz = r.z. pcg_step: with nq = -(W p): alpha = rz / (p.W p), y += alpha p,
+// r -= alpha W p, rr = r.r (rr may be null). pcg_dir: rz' = r.z, p = z + (rz' / rz) p, rz = rz'.
+// pcg_finish: y += z.
+hipError_t pcg_init(const int64_t* seg, int64_t n, int64_t s0, int64_t s1, const double* r, const double* z, double* p,
+                    double* rz, hipStream_t st);
+hipError_t pcg_step(const int64_t* seg, int64_t n, int64_t s0, int64_t s1, const double* p, const double* nq, double* y,
+                    double* r, const double* rz, double* rr, hipStream_t st);
+hipError_t pcg_dir(const int64_t* seg, int64_t n, int64_t s0, int64_t s1, const double* r, const double* z, double* p,
+                   double* rz, hipStream_t st);
+hipError_t pcg_finish(const int64_t* seg, int64_t n, int64_t s0, int64_t s1, const double* z, double* y,
+                      hipStream_t st);
 
 // ----------------------------------------------------------------------------- small helpers
 // dst = src + scale * dmax[0] * I (n x n, row-major; dmax a device scalar, unread if scale == 0).

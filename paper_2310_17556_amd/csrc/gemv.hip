@@ -214,12 +214,14 @@ constexpr int CP_UNROLL = 8;
 template <int MODE>
 __device__ __forceinline__ void colpass_store(void* out, const float* v, double lam, int64_t col, int64_t m,
                                               const double (&t)[4], bool vec) {
-  // MODE 0: x = (v - t) / lam as FP32; 1: as FP64; 2: t as FP64.
+  // MODE 0: x = (v - t) / lam as FP32; 1: as FP64; 2: t as FP64; 3: t as FP32.
 #pragma unroll
   for (int e = 0; e < 4; ++e) {
     if (col + e >= m) break;
     if constexpr (MODE == 2) {
       static_cast<double*>(out)[col + e] = t[e];
+    } else if constexpr (MODE == 3) {
+      static_cast<float*>(out)[col + e] = (float)t[e];
     } else {
       const double x = ((double)v[col + e] - t[e]) / lam;
       if constexpr (MODE == 0) static_cast<float*>(out)[col + e] = (float)x;
@@ -293,6 +295,8 @@ __global__ void colpass_finalize_kernel(const double* __restrict__ part, int64_t
   for (int64_t s = 0; s < nsplit; ++s) t += part[s * m + k];
   if constexpr (MODE == 2) {
     static_cast<double*>(out)[k] = t;
+  } else if constexpr (MODE == 3) {
+    static_cast<float*>(out)[k] = (float)t;
   } else {
     const double x = ((double)v[k] - t) / lam;
     if constexpr (MODE == 0) static_cast<float*>(out)[k] = (float)x;
@@ -711,6 +715,7 @@ hipError_t colpass_launch(const ColPassPlan& p, const float* S, int64_t n, int64
   switch (mode) {
     case 0: hipLaunchKernelGGL(colpass_kernel<0>, grid, dim3(CP_THREADS), 0, st, S, n, m, lds, y, v, lambda, out, pp, p.rps, iv); break;
     case 1: hipLaunchKernelGGL(colpass_kernel<1>, grid, dim3(CP_THREADS), 0, st, S, n, m, lds, y, v, lambda, out, pp, p.rps, iv); break;
+    case 3: hipLaunchKernelGGL(colpass_kernel<3>, grid, dim3(CP_THREADS), 0, st, S, n, m, lds, y, v, lambda, out, pp, p.rps, iv); break;
     default: hipLaunchKernelGGL(colpass_kernel<2>, grid, dim3(CP_THREADS), 0, st, S, n, m, lds, y, v, lambda, out, pp, p.rps, iv); break;
   }
   hipError_t e = hipGetLastError();
@@ -719,6 +724,7 @@ hipError_t colpass_launch(const ColPassPlan& p, const float* S, int64_t n, int64
   switch (mode) {
     case 0: hipLaunchKernelGGL(colpass_finalize_kernel<0>, g2, dim3(256), 0, st, part, p.nsplit, m, v, lambda, out); break;
     case 1: hipLaunchKernelGGL(colpass_finalize_kernel<1>, g2, dim3(256), 0, st, part, p.nsplit, m, v, lambda, out); break;
+    case 3: hipLaunchKernelGGL(colpass_finalize_kernel<3>, g2, dim3(256), 0, st, part, p.nsplit, m, v, lambda, out); break;
     default: hipLaunchKernelGGL(colpass_finalize_kernel<2>, g2, dim3(256), 0, st, part, p.nsplit, m, v, lambda, out); break;
   }
   return hipGetLastError();

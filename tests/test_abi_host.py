@@ -83,6 +83,12 @@ def test_invalid_arguments_rejected_on_host(dfl):
         assert lib.dfisher_solve(FAKE_CTX, P, 4, 8, 8, P, 1.0, P, ctypes.byref(o), st, None) == E
     assert lib.dfisher_solve(FAKE_CTX, P, 4, 8, 8, None, 1.0, P, None, st, None) == E
     assert lib.dfisher_solve(FAKE_CTX, P, 4, 8, 8, P, 1.0, None, None, st, None) == E
+    for lam in [0.0, -1e-3, float("inf"), float("nan")]:
+        assert lib.dfisher_solve_rowspace(FAKE_CTX, P, 4, 8, 8, P, lam, P, None, st, None) == E
+    assert lib.dfisher_solve_rowspace(FAKE_CTX, P, 4, 8, 8, None, 1.0, P, None, st, None) == E
+    assert lib.dfisher_solve_rowspace(FAKE_CTX, P, 4, 8, 8, P, 1.0, None, None, st, None) == E
+    assert lib.dfisher_solve_rowspace(FAKE_CTX, P, 4, 8, 7, P, 1.0, P, None, st, None) == E
+    assert lib.dfisher_solve_rowspace(FAKE_CTX, P, 4, 8, 8, P, 1.0, P, ctypes.byref(_opts(dfl, prec=5)), st, None) == E
     i64 = ctypes.c_int64(0)
     assert lib.dfisher_potrf(FAKE_CTX, P, 0, ctypes.byref(i64), st) == E
     assert lib.dfisher_potrf(FAKE_CTX, P, 4, None, st) == E
@@ -146,7 +152,8 @@ def test_context_on_missing_device(dfl):
 
 def test_auto_sweeps_rule(dfl):
     """DFISHER_SWEEPS_AUTO's count: c = C / (sqrt(a) (1 - 1/sqrt(a))^2), a = m / n, and the smallest k
-    with c^(k+1) <= 1e-7 (C = 0.1 scaled FP8, 1e-4 split-BF16, 1e-5 FP32; a <= 4 uses (1/2)^2)."""
+    with c^(k+1) <= 1e-7 (C = 0.1 scaled FP8, 1e-4 split-BF16, 1e-5 FP32; a <= 4 uses (1/2)^2), plus
+    3 (a < 150) or 2 (a < 600) for the scaled-FP8 Gram; at most 16."""
     def rule(prec, n, m):
         a = m / n
         C = {0: 1e-5, 1: 1e-4, 2: 0.1}[prec]
@@ -158,7 +165,9 @@ def test_auto_sweeps_rule(dfl):
         while e > 1e-7 and k < 16:
             e *= c
             k += 1
-        return k
+        if prec == 2:   # outlier directions of the scaled-FP8 Gram converge after the bulk
+            k += 3 if a < 150 else (2 if a < 600 else 0)
+        return min(k, 16)
     for prec in (0, 1, 2):
         for n, m in [(4096, 4_000_000), (2048, 2_000_000), (300, 20000), (1241, 119782), (32, 1024),
                      (1000, 1000), (64, 100), (1, 777)]:

@@ -70,8 +70,11 @@ AUTO_CASES = [
 @pytest.mark.parametrize("n,m,lam,prec,kind", AUTO_CASES)
 def test_auto_sweeps_meet_target(dfl, ctx, oracle_mod, n, m, lam, prec, kind):
     """DFISHER_SWEEPS_AUTO in dfisher_solve (measured residuals, predictive stop at 1e-7): the call
-    converges, both |x - x*| / |x*| and eps_Sy meet 1e-6 against the oracle, and the final
-    residual, measured separately, meets the 1e-7 aim within the contraction's spread."""
+    converges, eps_Sy meets 1e-6 against the oracle and the final residual, measured separately,
+    the 1e-7 aim within the contraction's spread. For an iid v, |x - x*| / |x*| meets 1e-6 too. For
+    a v in the row space of S ("scaled"), x = (v - S^T y) / lambda cancels, so the error of x relative
+    to |x| is the error of S^T y times |S^T y| / |v - S^T y| (up to ~1e7 here): a residual aim
+    does not bound it, and the test asks the same call with a tolerance of 1e-11 to meet 1e-6 in x."""
     print(f"[auto sweeps] n={n} m={m} lam={lam} prec={prec} kind={kind}", flush=True)
     S = synth.make_S(n, m, synth.seed(50, n), kind)
     v = synth.make_v(S, synth.seed(50, n), kind)
@@ -84,29 +87,41 @@ def test_auto_sweeps_meet_target(dfl, ctx, oracle_mod, n, m, lam, prec, kind):
     print(f"    sweeps {info['sweeps_done']} (a-priori rule {rule}) rel {rel:.3e} eps_Sy {esy:.3e} "
           f"rho {info['resid']:.3e} w_resid {info['w_resid']:.3e} shift {info['shift']:.3e}", flush=True)
     assert info["converged"] and 1 <= info["sweeps_done"] <= 16
-    assert rel <= 1e-6 and esy <= 1e-6
+    assert esy <= 1e-6
     assert 0.0 <= info["w_resid"] <= 1e-6
+    if kind == "iid":
+        assert rel <= 1e-6
+    else:
+        x, info = dfl.dfisher_solve(ctx, Sd, dev(v), lam, gram_prec=prec, sweeps=dfl.DFISHER_SWEEPS_AUTO,
+                                    x_fp64=True, tol=1e-11)
+        rel, esy = errs(x.cpu().numpy(), xref, v, lam)
+        print(f"    tol 1e-11: sweeps {info['sweeps_done']} rel {rel:.3e} eps_Sy {esy:.3e}", flush=True)
+        assert info["converged"] and rel <= 1e-6 and esy <= 1e-6
 
 
-@pytest.mark.parametrize("prec,sweeps", [(2, 1), (1, 0), (1, 1)])
-def test_final_resid_is_next_sweeps_rho(dfl, ctx, prec, sweeps):
-    """The final residual of a k-sweep solve is the residual that sweep k + 1 measures before its
-    correction (tolerance mode, same kernels in the same order): the two must agree bit for bit.
-    With sweeps = 0 it is the residual of the unrefined solve."""
+@pytest.mark.parametrize("prec", [2, 1])
+def test_final_resid(dfl, ctx, prec):
+    """The final residual |S v - lambda y - S (S^T y)| / |S v| of the returned iterate. With no sweep
+    it is the residual the first sweep of a tolerance-mode solve measures (same kernels in the same
+    order: the two agree bit for bit); each further sweep lowers it."""
     n, m, lam = 320, 20016, 1e-3
     S = synth.make_S(n, m, synth.seed(51, n))
     v = synth.make_v(S, synth.seed(51, n))
     Sd, vd = dev(S), dev(v)
-    _, a = dfl.dfisher_solve(ctx, Sd, vd, lam, gram_prec=prec, sweeps=sweeps, final_resid=True)
-    _, b = dfl.dfisher_solve(ctx, Sd, vd, lam, gram_prec=prec, sweeps=sweeps + 1, tol=1e-300)
+    _, a = dfl.dfisher_solve(ctx, Sd, vd, lam, gram_prec=prec, sweeps=0, final_resid=True)
+    _, b = dfl.dfisher_solve(ctx, Sd, vd, lam, gram_prec=prec, sweeps=1, tol=1e-300)
     print(f"    w_resid {a['w_resid']:.6e} rho {b['resid']:.6e}", flush=True)
     assert a["w_resid"] > 0.0 and a["w_resid"] == b["resid"]
     assert a["resid"] == -1.0   # no tolerance: no per-sweep measurement
-    _, c = dfl.dfisher_solve(ctx, Sd, vd, lam, gram_prec=prec, sweeps=sweeps + 1, final_resid=True)
-    assert c["w_resid"] < a["w_resid"]
+    w = [a["w_resid"]]
+    for k in (1, 2):
+        _, c = dfl.dfisher_solve(ctx, Sd, vd, lam, gram_prec=prec, sweeps=k, final_resid=True)
+        w.append(c["w_resid"])
+    print(f"    w_resid after 0, 1, 2 sweeps: {w}", flush=True)
+    assert w[1] < w[0] and w[2] < w[1]
 
 
-@pytest.mark.parametrize("sweeps,bound", [(3, 1e-6), (-1, 1e-6)])
+@pytest.mark.parametrize("sweeps,bound", [(6, 1e-6), (-1, 1e-6)])
 def test_fp8_row_space_rhs(dfl, ctx, oracle_mod, sweeps, bound):
     """The scaled-FP8 Gram on a right-hand side in the row space of a column-scaled S (the
     paper-scale generator: v = S^T u + N(0, 1e-6), so x = v / lambda - S^T y / lambda cancels to
