@@ -236,6 +236,18 @@ DFISHER_API dfisher_status dfisher_factor_create(dfisher_ctx* ctx, const float* 
  * X is nrhs x m (row stride ldx >= m), FP32 or FP64 per the factor's options. */
 DFISHER_API dfisher_status dfisher_factor_solve(dfisher_factor* f, const float* V, int64_t nrhs, int64_t ldv,
                                     void* X, int64_t ldx, void* stream, dfisher_info* info);
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): dfisher_factor_solve for one right-hand side v (FP32,
+ * length m) into x (FP32 or FP64 per the factor's options, length m; may alias v when FP32),
+ * with the factor's sweep count. It calls no hipMalloc, hipFree or allocating routine and does not
+ * synchronise: its scratch is a 64 MiB device array built into the library, one per device,
+ * looked up when a context is created on that device and held until the process ends. Every call
+ * on a device shares that array, so calls that overlap on one device (different streams or
+ * threads) race; each call rewrites what it reads. A shape whose scratch would exceed 64 MiB, or
+ * refinement (sweeps > 0) without the one-read product (n <= 4096, m >= 16, 16-byte aligned rows
+ * of S), returns DFISHER_E_UNSUPPORTED before any device work. info may be NULL. */
+DFISHER_API dfisher_status dfisher_factor_solve_noalloc(const dfisher_factor* f, const float* v, void* x,
+                                                        void* stream, dfisher_info* info);
 /* Copy the factor's L (n x n FP64 row-major, zero strict upper triangle) to device memory. */
 DFISHER_API dfisher_status dfisher_factor_copy_L(const dfisher_factor* f, double* L, void* stream);
 DFISHER_API dfisher_status dfisher_factor_destroy(dfisher_factor* f);

@@ -24,7 +24,7 @@ __all__ = [
     "dfisher_trsv", "dfisher_apply", "dfisher_solve", "dfisher_factor_create", "dfisher_factor_solve",
     "dfisher_factor_copy_L", "dfisher_factor_destroy", "dfisher_solve_batched", "dfisher_solve_uneven",
     "dfisher_status_string", "dfisher_last_error", "dfisher_auto_sweeps", "DFISHER_SWEEPS_AUTO",
-    "dfisher_solve_rowspace",
+    "dfisher_solve_rowspace", "dfisher_factor_solve_noalloc",
 ]
 
 DFISHER_OK = 0
@@ -92,6 +92,7 @@ def _load():
         "dfisher_factor_create": ([P, P, I64, I64, I64, D, ctypes.POINTER(_Options), P, PP, ctypes.POINTER(Info)], I32),
         "dfisher_factor_solve": ([P, P, I64, I64, P, I64, P, ctypes.POINTER(Info)], I32),
         "dfisher_factor_copy_L": ([P, P, P], I32),
+        "dfisher_factor_solve_noalloc": ([P, P, P, P, ctypes.POINTER(Info)], I32),
         "dfisher_factor_destroy": ([P], I32),
         "dfisher_solve_batched": ([P, P, I64, I64, I64, ctypes.POINTER(D), I32, P, I32, I64, P, I64,
                                    ctypes.POINTER(_Options), P, ctypes.POINTER(Info)], I32),
@@ -428,6 +429,20 @@ def dfisher_factor_solve(f, V, X=None, stream=None):
     _check(_lib().dfisher_factor_solve(f.ptr, _ptr(V2), nrhs, V2.stride(0), _ptr(X2), X2.stride(0), _stream(stream),
                                     ctypes.byref(info)), "dfisher_factor_solve")
     return X2[0] if squeeze else X2
+
+
+def dfisher_factor_solve_noalloc(f, v, x, stream=None):
+    """One right-hand side through the factor without any device allocation (the library's built-in
+    scratch): x must be preallocated (length m, FP32 or FP64 per the factor's options). Returns
+    the info dict."""
+    torch = _torch()
+    m = f.m
+    _vec(v, m, torch.float32, "v")
+    _vec(x, m, torch.float64 if f.x_fp64 else torch.float32, "x")
+    info = Info()
+    _check(_lib().dfisher_factor_solve_noalloc(f.ptr, _ptr(v), _ptr(x), _stream(stream), ctypes.byref(info)),
+           "dfisher_factor_solve_noalloc")
+    return info.as_dict()
 
 
 def dfisher_factor_copy_L(f, L=None, stream=None):

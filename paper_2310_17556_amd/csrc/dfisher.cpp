@@ -15,9 +15,16 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 
 #include "dfisher_internal.h"
+
+// Scratch of dfisher_factor_solve_noalloc: one copy per device, held until the process ends. In
+// host code `scratch` only names the symbol; the device address comes from hipGetSymbolAddress
+// (once per device, in init_kernels) and is the only form passed to kernels.
+constexpr size_t NOALLOC_SCRATCH_BYTES = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[NOALLOC_SCRATCH_BYTES];
 
 namespace {
 
@@ -1064,8 +1071,27 @@ dfisher_status uneven_solve(dfisher_ctx* ctx, int32_t np, const float* const* S,
   return DFISHER_OK;
 }
 
-// Per-device kernel set-up (called with the device current). Nothing to do at present.
-dfisher_status init_kernels() { return DFISHER_OK; }
+// Per-device set-up, called with the device current: the device address of the no-alloc scratch.
+std::mutex g_scratch_mu;
+std::vector<void*> g_scratch_ptr;   // per device; null until looked up
+
+dfisher_status init_kernels() {
+  int dev = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if ((int)g_scratch_ptr.size() <= dev) g_scratch_ptr.resize((size_t)dev + 1, nullptr);
+  if (g_scratch_ptr[(size_t)dev]) return DFISHER_OK;
+  void* ptr = nullptr;
+  HIP_TRY(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+  if (!ptr) return fail(DFISHER_E_DEVICE, "no device address for the no-alloc scratch on device %d", dev);
+  g_scratch_ptr[(size_t)dev] = ptr;
+  return DFISHER_OK;
+}
+
+void* scratch_ptr(int dev) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  return dev >= 0 && (size_t)dev < g_scratch_ptr.size() ? g_scratch_ptr[(size_t)dev] : nullptr;
+}
 
 }  // namespace
 
@@ -1395,6 +1421,65 @@ dfisher_status dfisher_factor_solve(dfisher_factor* f, const float* V, int64_t n
     info->shift = f->shift;
     info->attempts = 0;
     info->sweeps_done = f->opt.sweeps;
+    info->resid = -1.0;
+    info->w_resid = -1.0;
+  }
+  return DFISHER_OK;
+}
+
+dfisher_status dfisher_factor_solve_noalloc(const dfisher_factor* f, const float* v, void* x, void* stream,
+                                            dfisher_info* info) {
+  if (!f) return fail(DFISHER_E_INVALID_ARG, "factor is NULL");
+  if (!v || !x) return fail(DFISHER_E_INVALID_ARG, "v or x is NULL");
+  dfisher_ctx* ctx = f->ctx;
+  DeviceGuard g(ctx->device);
+  hipStream_t st = as_stream(stream);
+  const int64_t n = f->n, m = f->m, lds = f->lds;
+  const int sweeps = f->opt.sweeps;
+  const dfi::RowPassPlan rp = dfi::rowpass_plan(n, m, lds);
+  const dfi::ColPassPlan cp = dfi::colpass_plan(n, m);
+  const dfi::RefinePassPlan fp = dfi::refine_pass_plan(n, m, lds, f->S);
+  if (sweeps > 0 && !fp.usable)
+    return fail(DFISHER_E_UNSUPPORTED, "the no-alloc solve refines with the one-read product only: it needs "
+                "n <= 4096, m >= 16 and 16-byte aligned rows of S (n = %lld, lds = %lld)", (long long)n,
+                (long long)lds);
+  // everything solve_y and the two passes touch, carved from the device's scratch
+  auto lay = [&](char* base, SolveBufs& B) -> size_t {
+    Carver c;
+    c.base = base;
+    B = SolveBufs{};
+    B.rpart = c.take<double>(std::max(rp.part_bytes, fp.part_bytes) / sizeof(double) + 1);
+    B.cpart = c.take<double>(cp.part_bytes / sizeof(double) + 1);
+    B.b = c.take<double>((size_t)n);
+    B.z = c.take<double>((size_t)n);
+    B.y = c.take<double>((size_t)n);
+    B.r = c.take<double>((size_t)n);
+    B.zc = c.take<double>((size_t)n);
+    B.p = c.take<double>((size_t)n);
+    B.nq = c.take<double>((size_t)n);
+    B.zero = c.take<double>((size_t)n);
+    B.tw = c.take<double>((size_t)n);
+    return c.off;
+  };
+  SolveBufs B;
+  const size_t need = lay(nullptr, B);
+  if (need > NOALLOC_SCRATCH_BYTES)
+    return fail(DFISHER_E_UNSUPPORTED, "n = %lld, m = %lld needs %zu bytes of scratch; the no-alloc solve holds %zu",
+                (long long)n, (long long)m, need, NOALLOC_SCRATCH_BYTES);
+  char* base = static_cast<char*>(scratch_ptr(ctx->device));
+  if (!base) return fail(DFISHER_E_DEVICE, "no-alloc scratch of device %d was not set up", ctx->device);
+  lay(base, B);
+  // b = S v, y = W^-1 b through the factor (+ sweeps), x = (v - S^T y) / lambda
+  HIP_TRY(dfi::rowpass_launch(rp, f->S, v, nullptr, true, false, B.rpart, st));
+  HIP_TRY(dfi::rowpass_reduce(rp, B.rpart, true, false, B.b, nullptr, nullptr, nullptr, 0.0, st));
+  int done = 0;
+  DF_TRY(solve_y(f->S, n, m, lds, f->lambda, f->L, f->Dinv, B, rp, cp, sweeps, st, nullptr, &fp, ctx, 0.0, &done));
+  HIP_TRY(dfi::colpass_launch(cp, f->S, n, m, lds, B.y, v, f->lambda, x, f->opt.x_fp64, B.cpart, st));
+  if (info) {
+    info->potrf_info = 0;
+    info->shift = f->shift;
+    info->attempts = 0;
+    info->sweeps_done = done;
     info->resid = -1.0;
     info->w_resid = -1.0;
   }
