@@ -226,6 +226,38 @@ DFISHER_API dfisher_status dfisher_solve_rowspace(dfisher_ctx* ctx, const float*
                                                   int64_t lds, const double* f, double lambda, void* x,
                                                   const dfisher_options* opt, void* stream, dfisher_info* info);
 
+/* Stochastic reconfiguration front end (Section 3): the score matrix of SR is the centered, scaled
+ * log-derivative matrix S = (O - mean O) / sqrt(n), the mean taken over the n samples (rows) for
+ * every parameter (column): S_ij = fl32((O_ij - mu_j) / sqrt(n)), mu_j = (sum_i O_ij) / n with
+ * FP64 sums and arithmetic and one rounding to FP32 (the column sums' order is the library's: S
+ * matches a sequential-sum evaluation to within one FP32 unit in the last place).
+ *   is_complex = 0: O is real, n x m FP32 (row stride ldo >= m); S is n x m FP32 (row stride
+ *     lds >= m). S may be O itself (in place: same pointer and ldo == lds), else must not overlap.
+ *   is_complex = 1: O is complex, n x m values stored as interleaved (real, imaginary) FP32 pairs,
+ *     8-byte aligned, row stride ldo >= m complex values; the real and imaginary parts are centered
+ *     separately and written as the stacked real matrix Z = [Re S; Im S] (2n x m FP32, row stride
+ *     lds >= m; rows 0..n-1 real parts, n..2n-1 imaginary parts), which must not overlap O. Z is the
+ *     score matrix of the real-part variant F = Re[S^H S] = Z^T Z (the concatenation of the real and
+ *     imaginary parts in the sample dimension): solve it with dfisher_solve (n -> 2n) and the rest of
+ *     the algorithm unchanged. It is also the input of dfisher_solve_complex.
+ * Two passes over O (column sums, then the write). Does not synchronise. */
+DFISHER_API dfisher_status dfisher_sr_center(dfisher_ctx* ctx, const float* O, int64_t n, int64_t m, int64_t ldo,
+                                             int32_t is_complex, float* S, int64_t lds, void* stream);
+
+/* Complex variant (Section 3): with a complex S every transpose of Eq. 1 and Algorithm 1 becomes a
+ * Hermitian conjugate, (S^H S + lambda I) x = v with x, v complex of length m. S = A + iB is given
+ * in the stacked real form Z = [A; B] (2n x m FP32, row stride lds; what dfisher_sr_center writes for
+ * a complex O); v and x are interleaved (real, imaginary) pairs, 8-byte aligned: v FP32, x FP32 or
+ * FP64 per opt->x_fp64. Solved as the real system of the 2n x 2m matrix [[A, -B], [B, A]], which
+ * is never formed: its Gram [[Wr, -Wi], [Wi, Wr]] + lambda I (Wr = A A^T + B B^T, Wi = B A^T -
+ * A B^T) is assembled from one Gram of Z (any opt->gram_prec; the scaled-FP8 Gram needs 16-byte
+ * aligned rows), factored in FP64 (2n x 2n), and every product with the matrix or its transpose is
+ * a pass over Z with two vectors. Options, refinement, errors and synchronisation as in
+ * dfisher_solve (residuals relative to |S v|). n <= 32767. */
+DFISHER_API dfisher_status dfisher_solve_complex(dfisher_ctx* ctx, const float* Z, int64_t n, int64_t m, int64_t lds,
+                                                 const float* v, double lambda, void* x, const dfisher_options* opt,
+                                                 void* stream, dfisher_info* info);
+
 /* Factor reuse: steps 1-2 of Algorithm 1 once (Gram + Cholesky, with the shift policy), then
  * any number of right-hand sides. The factor BORROWS S: S must stay valid and unchanged until
  * dfisher_factor_destroy. The factor keeps a pointer to ctx, which must outlive it. */

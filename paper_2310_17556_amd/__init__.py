@@ -24,7 +24,7 @@ __all__ = [
     "dfisher_trsv", "dfisher_apply", "dfisher_solve", "dfisher_factor_create", "dfisher_factor_solve",
     "dfisher_factor_copy_L", "dfisher_factor_destroy", "dfisher_solve_batched", "dfisher_solve_uneven",
     "dfisher_status_string", "dfisher_last_error", "dfisher_auto_sweeps", "DFISHER_SWEEPS_AUTO",
-    "dfisher_solve_rowspace", "dfisher_factor_solve_noalloc",
+    "dfisher_solve_rowspace", "dfisher_factor_solve_noalloc", "dfisher_sr_center", "dfisher_solve_complex",
 ]
 
 DFISHER_OK = 0
@@ -93,6 +93,9 @@ def _load():
         "dfisher_factor_solve": ([P, P, I64, I64, P, I64, P, ctypes.POINTER(Info)], I32),
         "dfisher_factor_copy_L": ([P, P, P], I32),
         "dfisher_factor_solve_noalloc": ([P, P, P, P, ctypes.POINTER(Info)], I32),
+        "dfisher_sr_center": ([P, P, I64, I64, I64, I32, P, I64, P], I32),
+        "dfisher_solve_complex": ([P, P, I64, I64, I64, P, D, P, ctypes.POINTER(_Options), P,
+                                   ctypes.POINTER(Info)], I32),
         "dfisher_factor_destroy": ([P], I32),
         "dfisher_solve_batched": ([P, P, I64, I64, I64, ctypes.POINTER(D), I32, P, I32, I64, P, I64,
                                    ctypes.POINTER(_Options), P, ctypes.POINTER(Info)], I32),
@@ -390,6 +393,54 @@ def dfisher_solve_rowspace(ctx, S, f, lam: float, gram_prec: int = DFISHER_GRAM_
                                        _stream(stream), ctypes.byref(info))
     if st != DFISHER_E_NOT_CONVERGED:
         _check(st, "dfisher_solve_rowspace")
+    d = info.as_dict()
+    d["converged"] = st == DFISHER_OK
+    return x, d
+
+
+def dfisher_sr_center(ctx, O, S=None, stream=None):
+    """Section 3: S = (O - mean over samples) / sqrt(n). O: 2-D float32 (n x m) or complex64 CUDA tensor
+    with unit column stride. Returns S (n x m float32) for a real O, or the stacked Z = [Re S; Im S]
+    (2n x m float32) for a complex O. For a real O, S may be O itself (in place)."""
+    torch = _torch()
+    if not isinstance(O, torch.Tensor) or O.dim() != 2 or not O.is_cuda or O.stride(1) != 1:
+        raise TypeError("O must be a 2-D CUDA tensor with unit column stride")
+    if O.dtype not in (torch.float32, torch.complex64):
+        raise TypeError("O must be float32 or complex64")
+    cplx = O.dtype == torch.complex64
+    n, m = O.shape
+    rows = 2 * n if cplx else n
+    if S is None:
+        S = torch.empty((rows, m), dtype=torch.float32, device=O.device)
+    if S.dtype != torch.float32 or S.dim() != 2 or tuple(S.shape) != (rows, m) or S.stride(1) != 1:
+        raise ValueError(f"S must be a ({rows}, {m}) float32 tensor with unit column stride")
+    Op = torch.view_as_real(O) if cplx else O
+    _check(_lib().dfisher_sr_center(ctx.ptr, _ptr(Op), n, m, O.stride(0), 1 if cplx else 0, _ptr(S), S.stride(0),
+                                    _stream(stream)), "dfisher_sr_center")
+    return S
+
+
+def dfisher_solve_complex(ctx, Z, v, lam: float, gram_prec: int = DFISHER_GRAM_FP32, sweeps: int = 0,
+                          shift_policy: int = DFISHER_SHIFT_ON_FAILURE, x_fp64: bool = False, x=None, stream=None,
+                          tol: float = 0.0, final_resid: bool = False):
+    """x solving (S^H S + lam I) x = v for S = A + iB given as Z = [A; B] (2n x m float32); v complex64
+    of length m; x complex64 (or complex128 with x_fp64). Returns (x, info_dict) like dfisher_solve."""
+    torch = _torch()
+    N, m, lds = _S_args(Z)
+    if N % 2:
+        raise ValueError("Z must have an even number of rows ([Re S; Im S])")
+    _vec(v, m, torch.complex64, "v")
+    dt = torch.complex128 if x_fp64 else torch.complex64
+    if x is None:
+        x = torch.empty(m, dtype=dt, device=Z.device)
+    _vec(x, m, dt, "x")
+    opt = _options(gram_prec, sweeps, shift_policy, x_fp64, final_resid)
+    opt.tol = float(tol)
+    info = Info()
+    st = _lib().dfisher_solve_complex(ctx.ptr, _ptr(Z), N // 2, m, lds, _ptr(v), float(lam), _ptr(x),
+                                      ctypes.byref(opt), _stream(stream), ctypes.byref(info))
+    if st != DFISHER_E_NOT_CONVERGED:
+        _check(st, "dfisher_solve_complex")
     d = info.as_dict()
     d["converged"] = st == DFISHER_OK
     return x, d

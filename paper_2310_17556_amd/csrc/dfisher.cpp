@@ -161,6 +161,13 @@ struct Carver {
 
 bool finite_pos(double x) { return std::isfinite(x) && x > 0.0; }
 
+// Byte ranges [a, a + abytes) and [b, b + bbytes) intersect.
+bool overlaps(const void* a, size_t abytes, const void* b, size_t bbytes) {
+  const char* pa = static_cast<const char*>(a);
+  const char* pb = static_cast<const char*>(b);
+  return pa < pb + bbytes && pb < pa + abytes;
+}
+
 dfisher_status check_ctx(dfisher_ctx* ctx) {
   if (!ctx) return fail(DFISHER_E_INVALID_ARG, "ctx is NULL");
   return DFISHER_OK;
@@ -431,11 +438,13 @@ dfisher_status w_pass(const float* S, int64_t n, int64_t m, int64_t lds, double 
 // residual of y = 0), but never less than AUTO_MIN_CONTRACTION times rho_k, so that the call
 // stops only once a measured residual is <= tol / AUTO_MIN_CONTRACTION: the measured contraction
 // of one sweep can hide a slower direction (the all-ones one above).
-dfisher_status solve_y(const float* S, int64_t n, int64_t m, int64_t lds, double lambda, const double* L,
-                       const double* Dinv, const SolveBufs& B, const dfi::RowPassPlan& rp, const dfi::ColPassPlan& cp,
-                       int sweeps, hipStream_t st, StageClock* clk = nullptr, const dfi::RefinePassPlan* fp = nullptr,
-                       dfisher_ctx* ctx = nullptr, double tol = 0.0, int* done = nullptr, double* resid = nullptr,
-                       bool initial = true, bool predict = false, bool* met = nullptr) {
+// The sweeps of solve_y for any operator: wop(u, rhs, out) enqueues out = rhs - W u (length n).
+using WOp = std::function<dfisher_status(const double* u, const double* rhs, double* out)>;
+
+dfisher_status solve_y_op(int64_t n, const double* L, const double* Dinv, const SolveBufs& B, int sweeps,
+                          hipStream_t st, const WOp& wop, StageClock* clk = nullptr, dfisher_ctx* ctx = nullptr,
+                          double tol = 0.0, int* done = nullptr, double* resid = nullptr, bool initial = true,
+                          bool predict = false, bool* met = nullptr) {
   if (initial) {   // (else the caller has formed y = L^-T L^-1 b already)
     HIP_TRY(dfi::trsv_launch(L, Dinv, n, 0, B.b, B.z, B.tw, st));
     HIP_TRY(dfi::trsv_launch(L, Dinv, n, 1, B.z, B.y, B.tw, st));
@@ -446,12 +455,12 @@ dfisher_status solve_y(const float* S, int64_t n, int64_t m, int64_t lds, double
   if (resid) *resid = -1.0;
   if (met) *met = false;
   if (sweeps > 0) {
-    double* rz = ctx ? ctx->d_scalar + 4 : nullptr;
-    double* rr = ctx ? ctx->d_scalar + 3 : nullptr;
-    if (!rz) return fail(DFISHER_E_DEVICE, "refinement needs the context's scalars");
+    if (!ctx) return fail(DFISHER_E_DEVICE, "refinement needs the context's scalars");
+    double* rz = ctx->d_scalar + 4;
+    double* rr = ctx->d_scalar + 3;
     if (measure) HIP_TRY(dfi::sumsq(B.b, n, ctx->d_scalar + 2, st));
     HIP_TRY(dfi::fill_zero(B.zero, n, st));
-    DF_TRY(w_pass(S, n, m, lds, lambda, B.y, B.b, B.r, B, rp, cp, fp, st));   // sweep 1: r = b - W y
+    DF_TRY(wop(B.y, B.b, B.r));   // sweep 1: r = b - W y
     if (measure) HIP_TRY(dfi::sumsq(B.r, n, rr, st));
     double prev = 1.0;
     for (int s = 1;; ++s) {
@@ -482,12 +491,23 @@ dfisher_status solve_y(const float* S, int64_t n, int64_t m, int64_t lds, double
       }
       if (s == 1) HIP_TRY(dfi::pcg_init(nullptr, n, 0, 1, B.r, B.zc, B.p, rz, st));
       else HIP_TRY(dfi::pcg_dir(nullptr, n, 0, 1, B.r, B.zc, B.p, rz, st));
-      DF_TRY(w_pass(S, n, m, lds, lambda, B.p, B.zero, B.nq, B, rp, cp, fp, st));   // -(W p)
+      DF_TRY(wop(B.p, B.zero, B.nq));   // -(W p)
       HIP_TRY(dfi::pcg_step(nullptr, n, 0, 1, B.p, B.nq, B.y, B.r, rz, measure ? rr : nullptr, st));
     }
   }
   if (clk) clk->mark(6);
   return DFISHER_OK;
+}
+
+dfisher_status solve_y(const float* S, int64_t n, int64_t m, int64_t lds, double lambda, const double* L,
+                       const double* Dinv, const SolveBufs& B, const dfi::RowPassPlan& rp, const dfi::ColPassPlan& cp,
+                       int sweeps, hipStream_t st, StageClock* clk = nullptr, const dfi::RefinePassPlan* fp = nullptr,
+                       dfisher_ctx* ctx = nullptr, double tol = 0.0, int* done = nullptr, double* resid = nullptr,
+                       bool initial = true, bool predict = false, bool* met = nullptr) {
+  const WOp wop = [&](const double* u, const double* rhs, double* out) {
+    return w_pass(S, n, m, lds, lambda, u, rhs, out, B, rp, cp, fp, st);
+  };
+  return solve_y_op(n, L, Dinv, B, sweeps, st, wop, clk, ctx, tol, done, resid, initial, predict, met);
 }
 
 // r = b - lambda y - S (S^T y) for the current y (FP64), then w = |r| / |b| read back to the host
@@ -1623,6 +1643,169 @@ dfisher_status dfisher_solve_rowspace(dfisher_ctx* ctx, const float* S, int64_t 
   if (o.final_resid) DF_TRY(final_residual(ctx, S, n, m, lds, lambda, B, rp, cp, fp, st, &inf.w_resid));
   // x = S^T y, rounded once (FP32) or kept in FP64
   HIP_TRY(dfi::colpass_launch(cp, S, n, m, lds, B.y, nullptr, 1.0, x, o.x_fp64 ? 2 : 3, B.cpart, st));
+  clk.mark(7);
+  inf.sweeps_done = done;
+  inf.resid = resid;
+  if (info) *info = inf;
+  if (tol > 0.0 && !met)
+    return fail(DFISHER_E_NOT_CONVERGED, "relative residual %.3g above tol %.3g after %d sweep(s)", resid, tol, done);
+  return DFISHER_OK;
+}
+
+// Section 3: S = (O - mean over the samples of O) / sqrt(n). Column sums by the column pass (FP64,
+// y = 1), then one pass that writes S (or, for a complex O, the stacked Z = [Re S; Im S]).
+dfisher_status dfisher_sr_center(dfisher_ctx* ctx, const float* O, int64_t n, int64_t m, int64_t ldo,
+                                 int32_t is_complex, float* S, int64_t lds, void* stream) {
+  DF_TRY(check_ctx(ctx));
+  if (!O || !S) return fail(DFISHER_E_INVALID_ARG, "O or S is NULL");
+  if (n < 1 || m < 1) return fail(DFISHER_E_INVALID_ARG, "n = %lld, m = %lld must be >= 1", (long long)n, (long long)m);
+  if (ldo < m || lds < m) return fail(DFISHER_E_INVALID_ARG, "ldo or lds < m");
+  if (is_complex != 0 && is_complex != 1) return fail(DFISHER_E_INVALID_ARG, "is_complex = %d not 0 or 1", is_complex);
+  const size_t obytes = (size_t)((n - 1) * ldo + m) * sizeof(float) * (is_complex ? 2 : 1);
+  const int64_t srows = is_complex ? 2 * n : n;
+  const size_t sbytes = (size_t)((srows - 1) * lds + m) * sizeof(float);
+  if (is_complex) {
+    if (reinterpret_cast<uintptr_t>(O) % 8 != 0) return fail(DFISHER_E_INVALID_ARG, "complex O must be 8-byte aligned");
+    if (overlaps(O, obytes, S, sbytes)) return fail(DFISHER_E_INVALID_ARG, "Z overlaps O (no in-place complex form)");
+  } else if (overlaps(O, obytes, S, sbytes) && !(O == S && ldo == lds)) {
+    return fail(DFISHER_E_INVALID_ARG, "S overlaps O other than in place (same pointer and stride)");
+  }
+  DeviceGuard g(ctx->device);
+  hipStream_t st = as_stream(stream);
+  const int64_t mc = is_complex ? 2 * m : m;       // FP32 columns of O as the column pass sees them
+  const int64_t ldc = is_complex ? 2 * ldo : ldo;
+  const dfi::ColPassPlan cp = dfi::colpass_plan(n, mc);
+  auto lay = [&](char* base, double** ones, double** t, double** cpart) -> size_t {
+    Carver c;
+    c.base = base;
+    *ones = c.take<double>((size_t)n);
+    *t = c.take<double>((size_t)mc);
+    *cpart = c.take<double>(cp.part_bytes / sizeof(double) + 1);
+    return c.off;
+  };
+  double *ones, *t, *cpart;
+  DF_TRY(ensure_ws(ctx, lay(nullptr, &ones, &t, &cpart)));
+  lay(static_cast<char*>(ctx->ws), &ones, &t, &cpart);
+  HIP_TRY(dfi::fill_value(ones, n, 1.0, st));
+  HIP_TRY(dfi::colpass_launch(cp, O, n, mc, ldc, ones, nullptr, 1.0, t, 2, cpart, st));
+  HIP_TRY(dfi::center_write(O, n, m, ldo, is_complex, t, S, lds, st));
+  return DFISHER_OK;
+}
+
+// Section 3, complex variant: (S^H S + lambda I) x = v with S = A + iB given in the stacked real form
+// Z = [A; B]. It is the real system of E = [[A, -B], [B, A]] (2n x 2m) with v = [Re v; Im v], solved
+// by Algorithm 1 on E: the Gram E E^T = [[Wr, -Wi], [Wi, Wr]] + lambda I assembled from Z Z^T,
+// its FP64 Cholesky, b = E v, refinement sweeps with the matrix-free E (E^T y) (two vectors per
+// pass over Z), x = (v - E^T y) / lambda. E is never formed.
+dfisher_status dfisher_solve_complex(dfisher_ctx* ctx, const float* Z, int64_t n, int64_t m, int64_t lds, const float* v,
+                                     double lambda, void* x, const dfisher_options* opt, void* stream,
+                                     dfisher_info* info) {
+  DF_TRY(check_ctx(ctx));
+  if (n > 32767) return fail(DFISHER_E_UNSUPPORTED, "n = %lld > 32767 (the real Gram is 2n x 2n)", (long long)n);
+  DF_TRY(check_S(Z, n >= 1 ? 2 * n : n, m, lds));
+  if (!v || !x) return fail(DFISHER_E_INVALID_ARG, "v or x is NULL");
+  if (reinterpret_cast<uintptr_t>(v) % 8 != 0) return fail(DFISHER_E_INVALID_ARG, "complex v must be 8-byte aligned");
+  if (!finite_pos(lambda)) return fail(DFISHER_E_INVALID_ARG, "lambda must be finite and > 0");
+  dfisher_options o;
+  DF_TRY(check_opt(opt, &o));
+  DF_TRY(check_prec_layout(o.gram_prec, Z, lds));
+  DeviceGuard g(ctx->device);
+  hipStream_t st = as_stream(stream);
+  const int64_t N = 2 * n;
+  if (ctx->autotune) DF_TRY(tune_if_new(ctx, Z, N, m, lds, o.gram_prec, st));
+  const dfi::GramPlan gp = make_gram_plan(ctx, Z, N, m, lds, o.gram_prec);
+  const dfi::RowPassPlan rp = dfi::rowpass_plan(N, m, lds);
+  const dfi::ColPassPlan cp = dfi::colpass_plan(N, m);
+  const dfi::RowMultiPlan rm = dfi::rowmulti_plan(N, m, lds);
+  constexpr int MV = dfi::MULTI_VECS;
+  struct Extra {
+    double *G, *P, *Q, *U1, *U2, *T, *Yi, *mpart;
+    float* vp;
+  };
+  auto lay = [&](char* base, SolveBufs& B, Extra& X) -> size_t {
+    B = carve(base, N, m, &gp, rp, cp, true, false, nullptr);
+    Carver c;
+    c.base = base;
+    c.off = B.bytes;
+    X.G = c.take<double>((size_t)(N * N));
+    X.P = c.take<double>((size_t)N);
+    X.Q = c.take<double>((size_t)N);
+    X.U1 = c.take<double>((size_t)N);
+    X.U2 = c.take<double>((size_t)N);
+    X.T = c.take<double>((size_t)m * MV);
+    X.Yi = c.take<double>((size_t)N * MV);
+    X.mpart = c.take<double>(rm.part_bytes / sizeof(double) + 1);
+    X.vp = c.take<float>((size_t)(2 * m));
+    return c.off;
+  };
+  SolveBufs B;
+  Extra X;
+  DF_TRY(ensure_ws(ctx, lay(nullptr, B, X)));
+  lay(static_cast<char*>(ctx->ws), B, X);
+  StageClock clk(ctx, st);
+  // Z Z^T (both triangles, exact FP64 diagonal) and the embedded W
+  DF_TRY(gram_stage(Z, nullptr, gp, rp, B, 0.0, X.G, 1, st, &clk));
+  HIP_TRY(dfi::complex_embed(X.G, n, lambda, B.W, st));
+  // b = E v = [A vr - B vi; B vr + A vi] from Z vr and Z vi (one pass over Z)
+  HIP_TRY(dfi::deinterleave(v, m, X.vp, st));
+  {
+    dfi::MultiVecs vs{};
+    vs.f[0] = X.vp;
+    vs.f[1] = X.vp + m;
+    dfi::MultiOut mo{};
+    mo.b[0] = X.P;
+    mo.b[1] = X.Q;
+    HIP_TRY(dfi::rowpass_multi_launch(rm, Z, vs, nullptr, 2, X.mpart, st));
+    HIP_TRY(dfi::rowpass_multi_reduce(rm, X.mpart, 2, mo, st));
+    HIP_TRY(dfi::complex_combine(X.P, X.Q, n, 1.0, nullptr, nullptr, 0.0, B.b, st));
+  }
+  // E^T u for u = [u1; u2]: t1 = Z^T [u1; u2], t2 = Z^T [u2; -u1], into T columns 0 and 1
+  auto et = [&](const double* u) -> dfisher_status {
+    HIP_TRY(dfi::complex_colvecs(u, n, X.U1, X.U2, st));
+    dfi::MultiCols mc{};
+    for (int c = 0; c < MV; ++c) mc.y[c] = c == 1 ? X.U2 : X.U1;
+    HIP_TRY(dfi::colpass_multi_launch(Z, N, m, lds, mc, 2, 2, X.T, X.Yi, st));
+    return DFISHER_OK;
+  };
+  // out = rhs - lambda u - E (E^T u)
+  const WOp wop = [&](const double* u, const double* rhs, double* out) -> dfisher_status {
+    DF_TRY(et(u));
+    dfi::MultiVecs none{};
+    dfi::MultiOut mo{};
+    mo.b[0] = X.P;
+    mo.b[1] = X.Q;
+    HIP_TRY(dfi::rowpass_multi_launch(rm, Z, none, X.T, 2, X.mpart, st));
+    HIP_TRY(dfi::rowpass_multi_reduce(rm, X.mpart, 2, mo, st));
+    HIP_TRY(dfi::complex_combine(X.P, X.Q, n, -1.0, rhs, u, lambda, out, st));
+    return DFISHER_OK;
+  };
+  clk.mark(3);
+  dfisher_info inf{};
+  inf.resid = -1.0;
+  DF_TRY(factor_with_policy(ctx, B.W, B.L, B.dkk, N, o.shift_policy, gram_unit(o.gram_prec, m), st, &inf.shift,
+                            &inf.potrf_info, &inf.attempts));
+  clk.mark(4);
+  HIP_TRY(dfi::trsv_diag_inv(B.L, N, B.Dinv, st));
+  const bool autos = o.sweeps == DFISHER_SWEEPS_AUTO;
+  const int sweeps = autos ? MAX_SWEEPS : o.sweeps;
+  const double tol = autos && !(o.tol > 0.0) ? AUTO_TOL : o.tol;
+  int done = 0;
+  double resid = -1.0;
+  bool met = false;
+  DF_TRY(solve_y_op(N, B.L, B.Dinv, B, sweeps, st, wop, &clk, ctx, tol, &done, &resid, true, autos, &met));
+  inf.w_resid = -1.0;
+  if (o.final_resid) {
+    DF_TRY(wop(B.y, B.b, B.r));
+    HIP_TRY(dfi::sumsq(B.b, N, ctx->d_scalar + 2, st));
+    HIP_TRY(dfi::sumsq(B.r, N, ctx->d_scalar + 3, st));
+    HIP_TRY(hipMemcpyAsync(ctx->h_scalar + 2, ctx->d_scalar + 2, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    const double bb = ctx->h_scalar[2], rr = ctx->h_scalar[3];
+    inf.w_resid = bb > 0.0 ? std::sqrt(rr / bb) : (rr > 0.0 ? INFINITY : 0.0);
+  }
+  // x = (v - E^T y) / lambda, complex interleaved
+  DF_TRY(et(B.y));
+  HIP_TRY(dfi::complex_apply(v, X.T, m, lambda, x, o.x_fp64, st));
   clk.mark(7);
   inf.sweeps_done = done;
   inf.resid = resid;

@@ -212,6 +212,26 @@ hipError_t pcg_dir(const int64_t* seg, int64_t n, int64_t s0, int64_t s1, const 
 hipError_t pcg_finish(const int64_t* seg, int64_t n, int64_t s0, int64_t s1, const double* z, double* y,
                       hipStream_t st);
 
+// ----------------------------------------------------------------------------- SR front end, complex variant
+// (sr.hip) S_ij = fl32((O_ij - t_j / n) / sqrt(n)) from the FP64 column sums t of O; cplx: O is
+// complex (interleaved FP32 pairs, row stride ldo complex elements, t interleaved) and the output is
+// the stacked Z = [Re S; Im S] (2n x m, row stride lds). Real O and S may be the same array.
+hipError_t center_write(const float* O, int64_t n, int64_t m, int64_t ldo, int cplx, const double* t, float* S,
+                        int64_t lds, hipStream_t st);
+hipError_t fill_value(double* y, int64_t n, double value, hipStream_t st);
+// interleaved complex FP32 v (m) -> out[0..m) real parts, out[m..2m) imaginary parts
+hipError_t deinterleave(const float* v, int64_t m, float* out, hipStream_t st);
+// Wh = [[Wr, -Wi], [Wi, Wr]] + lambda I (2n x 2n) from G = Z Z^T (2n x 2n, both triangles)
+hipError_t complex_embed(const double* G, int64_t n, double lambda, double* Wh, hipStream_t st);
+// out = rhs - lambda y + sgn [P_top - Q_bot; P_bot + Q_top] (each 2n; rhs, y may be null)
+hipError_t complex_combine(const double* P, const double* Q, int64_t n, double sgn, const double* rhs, const double* y,
+                           double lambda, double* out, hipStream_t st);
+// u1 = [y_top; y_bot], u2 = [y_bot; -y_top]
+hipError_t complex_colvecs(const double* y, int64_t n, double* u1, double* u2, hipStream_t st);
+// x_k = (v_k - (T[16 k] + i T[16 k + 1])) / lambda, complex interleaved, FP32 or FP64
+hipError_t complex_apply(const float* v, const double* T, int64_t m, double lambda, void* x, int x_fp64,
+                         hipStream_t st);
+
 // ----------------------------------------------------------------------------- small helpers
 // dst = src + scale * dmax[0] * I (n x n, row-major; dmax a device scalar, unread if scale == 0).
 hipError_t shift_copy(const double* src, double* dst, int64_t n, double scale, const double* dmax, hipStream_t st);
