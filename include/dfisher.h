@@ -194,7 +194,9 @@ DFISHER_API dfisher_status dfisher_potrf(dfisher_ctx* ctx, double* W, int64_t n,
 DFISHER_API dfisher_status dfisher_gemv(dfisher_ctx* ctx, const float* S, int64_t n, int64_t m, int64_t lds,
                             const float* v, double* b, void* stream);
 
-/* Triangular solves with the Cholesky factor (row-major n x n FP64, lower triangle used):
+/* Triangular solves with the Cholesky factor (row-major n x n FP64, lower triangle used), the
+ * L^-1 and L^-T of the inlined product S^T L^-T L^-1 S v (Section 2, the remark after
+ * Algorithm 1: triangular solves instead of forming Q = L^-1 S):
  * trans = 0: y = L^-1 b (forward substitution); trans = 1: y = L^-T b (back substitution).
  * b and y are FP64 device vectors of length n and may alias. */
 DFISHER_API dfisher_status dfisher_trsv(dfisher_ctx* ctx, const double* L, int64_t n, int32_t trans,
