@@ -88,8 +88,9 @@ typedef struct dfisher_options {
                             0..16 or DFISHER_SWEEPS_AUTO                                      */
   int32_t shift_policy;  /* dfisher_shift_policy                                            */
   int32_t x_fp64;        /* 0: x (and X) are float*, 1: double*                             */
-  double tol;            /* 0: run exactly `sweeps` sweeps. > 0 (dfisher_solve only; other
-                            entry points return DFISHER_E_UNSUPPORTED): after forming sweep k's
+  double tol;            /* 0: run exactly `sweeps` sweeps. > 0 (dfisher_solve, _rowspace,
+                            _complex and _uneven; other entry points return
+                            DFISHER_E_UNSUPPORTED): after forming sweep k's
                             residual r_k = S v - lambda y_k - S (S^T y_k), read
                             rho_k = |r_k|_2 / |S v|_2 (one stream synchronisation per sweep),
                             apply that sweep's correction, and stop once rho_k <= tol; with
@@ -114,9 +115,14 @@ typedef struct dfisher_options {
  *     residual expected of the corrected iterate, rho_k * max(0.1, min(1, rho_k / rho_{k-1}))
  *     with rho_{-1} = 1, is <= opt->tol (1e-7 when opt->tol is 0); at most 16 sweeps, else
  *     DFISHER_E_NOT_CONVERGED with x written. info->resid is the last rho_k.
- *   dfisher_factor_create, dfisher_solve_batched, dfisher_solve_uneven (no host round trip per
- *     sweep): the a-priori count of dfisher_auto_sweeps for each problem's shape, raised where
- *     the factorisation was shifted (the batched call uses the largest count of its lambdas). */
+ *   dfisher_solve_uneven: measured on the device, per problem, inside the captured launch
+ *     sequence (no host round trip): the same predictive test as dfisher_solve after each sweep,
+ *     with at most the a-priori count of dfisher_auto_sweeps + 2 sweeps (16 at most); a problem
+ *     that stops skips its later passes over S. DFISHER_E_NOT_CONVERGED (x written) if a problem
+ *     reached its cap without meeting the test.
+ *   dfisher_factor_create, dfisher_solve_batched (no host round trip per sweep): the a-priori
+ *     count of dfisher_auto_sweeps for each shape, raised where the factorisation was shifted
+ *     (the batched call uses the largest count of its lambdas). */
 #define DFISHER_SWEEPS_AUTO (-1)
 
 /* Defaults: FP32 Gram, 0 sweeps, shift on failure, FP32 output, no tolerance, no final residual. */

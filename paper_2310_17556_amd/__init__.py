@@ -533,8 +533,10 @@ def dfisher_solve_batched(ctx, S, lams, V, gram_prec: int = DFISHER_GRAM_FP32, s
 
 def dfisher_solve_uneven(ctx, Ss, vs, lams, gram_prec: int = DFISHER_GRAM_FP32, sweeps: int = 0,
                          shift_policy: int = DFISHER_SHIFT_ON_FAILURE, x_fp64: bool = False, xs=None, stream=None,
-                         final_resid: bool = False):
-    """Independent problems of different shapes. Returns (list of x, infos)."""
+                         final_resid: bool = False, tol: float = 0.0):
+    """Independent problems of different shapes. Returns (list of x, infos); "converged" is False in
+    every info when the library returned DFISHER_E_NOT_CONVERGED (a tolerance, given or automatic,
+    missed at some problem's sweep cap; every x is still written)."""
     torch = _torch()
     k = len(Ss)
     if not (len(vs) == len(lams) == k):
@@ -555,7 +557,13 @@ def dfisher_solve_uneven(ctx, Ss, vs, lams, gram_prec: int = DFISHER_GRAM_FP32, 
     l_arr = I64Arr(*[d[2] for d in dims])
     lam_arr = (ctypes.c_double * k)(*[float(a) for a in lams])
     opt = _options(gram_prec, sweeps, shift_policy, x_fp64, final_resid)
+    opt.tol = float(tol)
     infos = (Info * k)()
-    _check(_lib().dfisher_solve_uneven(ctx.ptr, k, s_arr, n_arr, m_arr, l_arr, v_arr, lam_arr, x_arr, ctypes.byref(opt),
-                                    _stream(stream), infos), "dfisher_solve_uneven")
-    return xs, [i.as_dict() for i in infos]
+    st = _lib().dfisher_solve_uneven(ctx.ptr, k, s_arr, n_arr, m_arr, l_arr, v_arr, lam_arr, x_arr, ctypes.byref(opt),
+                                     _stream(stream), infos)
+    if st != DFISHER_E_NOT_CONVERGED:
+        _check(st, "dfisher_solve_uneven")
+    out = [i.as_dict() for i in infos]
+    for d in out:
+        d["converged"] = st == DFISHER_OK   # the status covers every problem of the call
+    return xs, out

@@ -756,6 +756,8 @@ struct UnevenLayout {
   double *W = nullptr, *Dinv = nullptr, *dkk = nullptr, *dmax = nullptr;
   double *b = nullptr, *d = nullptr, *y = nullptr, *z = nullptr, *r = nullptr, *wk = nullptr;
   double *zc = nullptr, *p = nullptr, *nq = nullptr, *zero = nullptr, *rz = nullptr;   // refinement (PCG)
+  double *bb = nullptr, *rr = nullptr, *prev = nullptr, *resid = nullptr;   // per table entry
+  int *stop = nullptr, *done = nullptr, *met = nullptr;
   int64_t* info = nullptr;
   int32_t* flag = nullptr;
   double* res = nullptr;                   // final residuals: |b_p|^2, |r_p|^2 per problem
@@ -824,6 +826,13 @@ void uneven_layout(const dfisher_ctx* ctx, char* base, int32_t np, const float* 
   U.nq = c.take<double>((size_t)U.ntot);
   U.zero = c.take<double>((size_t)U.nmax);
   U.rz = c.take<double>((size_t)np);
+  U.bb = c.take<double>((size_t)np);
+  U.rr = c.take<double>((size_t)np);
+  U.prev = c.take<double>((size_t)np);
+  U.resid = c.take<double>((size_t)np);
+  U.stop = c.take<int>((size_t)np);
+  U.done = c.take<int>((size_t)np);
+  U.met = c.take<int>((size_t)np);
   U.info = c.take<int64_t>((size_t)np);
   U.flag = c.take<int32_t>((size_t)np);
   U.res = c.take<double>((size_t)(2 * np));
@@ -838,7 +847,8 @@ dfisher_status uneven_enqueue(dfisher_ctx* ctx, int32_t np, const float* const* 
                               const dfisher_options& o, const UnevenLayout& U, const std::vector<int32_t>& order,
                               const std::vector<int>& sw, const std::vector<int64_t>& nactive,
                               const dfi::FactorJob* fjobs, const dfi::TrsvJob* tj_fwd, const dfi::TrsvJob* tj_bwd,
-                              const dfi::TrsvJob* tj_bwd_c, const int64_t* seg, hipStream_t st) {
+                              const dfi::TrsvJob* tj_bwd_c, const int64_t* seg, const int* cap, double tol,
+                              bool predict, const std::vector<int32_t>& jpos, hipStream_t st) {
   (void)ctx;
   // Gram stage per problem, largest first: b_p = S_p v_p, d_p, W_p = S_p S_p^T + lambda_p I
   for (int32_t p : order) {
@@ -867,12 +877,15 @@ dfisher_status uneven_enqueue(dfisher_ctx* ctx, int32_t np, const float* const* 
   HIP_TRY(dfi::trsv_launch_grouped(tj_bwd, np, U.nmax, 1, st));    // wk -> y
   // out_p = rhs_p - lambda_p u_p - S_p (S_p^T u_p) (FP64 accumulation): the residual of y_p
   // (rhs = b, u = y) or -(W_p p_p) (rhs = 0, u = p)
-  auto w_pass = [&](int32_t p, const double* u, const double* rhs, bool rhs_zero, double* out) -> dfisher_status {
+  // (skip: the problem's stop flag; its fused pass then reads nothing. The column pass + row pass
+  // fallback runs regardless: its result is then unused.)
+  auto w_pass = [&](int32_t p, const double* u, const double* rhs, bool rhs_zero, double* out,
+                    const int* skip = nullptr) -> dfisher_status {
     const int64_t off = U.voff[(size_t)p];
     const double* rh = rhs_zero ? rhs : rhs + off;
     if (U.fp[(size_t)p].usable) {   // one read of S_p
-      HIP_TRY(dfi::refine_pass_launch(U.fp[(size_t)p], S[p], n[p], m[p], lds[p], u + off, U.shared.rpart, st));
-      HIP_TRY(dfi::refine_pass_reduce(U.fp[(size_t)p], U.shared.rpart, out + off, rh, u + off, lambda[p], st));
+      HIP_TRY(dfi::refine_pass_launch(U.fp[(size_t)p], S[p], n[p], m[p], lds[p], u + off, U.shared.rpart, st, skip));
+      HIP_TRY(dfi::refine_pass_reduce(U.fp[(size_t)p], U.shared.rpart, out + off, rh, u + off, lambda[p], st, skip));
       return DFISHER_OK;
     }
     HIP_TRY(dfi::colpass_launch(U.cp[(size_t)p], S[p], n[p], m[p], lds[p], u + off, nullptr, 1.0, U.shared.t, 2,
@@ -883,29 +896,45 @@ dfisher_status uneven_enqueue(dfisher_ctx* ctx, int32_t np, const float* const* 
     return DFISHER_OK;
   };
   auto residual = [&](int32_t p) -> dfisher_status { return w_pass(p, U.y, U.b, false, U.r); };
-  // the conjugate-gradient sweeps of solve_y, per problem; the job tables and the segment table
-  // list the problems by decreasing sweep count, so the problems in sweep s (sw >= s) are the
-  // first nactive[s - 1] entries and those that go on after it the first nactive[s]
+  // the conjugate-gradient sweeps of solve_y, per problem, with the stop test on the device: the job
+  // tables and the segment table list the problems by decreasing sweep cap, so the problems that
+  // may still run sweep s (cap >= s) are the first nactive[s - 1] entries; a problem that has
+  // stopped (tolerance met or cap reached) skips its passes and vector steps from then on
   const int max_sw = nactive.empty() ? 0 : (int)nactive.size();
   if (max_sw > 0) {
+    dfi::PcgControl c{};
+    c.bb = U.bb;
+    c.rr = U.rr;
+    c.prev = U.prev;
+    c.stop = U.stop;
+    c.cap = cap;
+    c.done = U.done;
+    c.resid = U.resid;
+    c.met = U.met;
+    c.tol = tol;
+    c.floor = AUTO_MIN_CONTRACTION;
+    c.predict = predict ? 1 : 0;
+    HIP_TRY(dfi::pcg_control_init(np, c, st));
     HIP_TRY(dfi::fill_zero(U.zero, U.nmax, st));
     for (int32_t p : order)
       if (sw[(size_t)p] > 0) DF_TRY(residual(p));
+    HIP_TRY(dfi::seg_sumsq(seg, 0, 0, nactive[0], U.b, U.bb, st));
+    HIP_TRY(dfi::seg_sumsq(seg, 0, 0, nactive[0], U.r, U.rr, st));
     for (int s = 1;; ++s) {
       const int64_t act = nactive[(size_t)(s - 1)];
       const int64_t cont = s < max_sw ? nactive[(size_t)s] : 0;
-      // zc = L^-T L^-1 r for the problems in this sweep
+      // zc = L^-T L^-1 r for the problems that may run this sweep
       HIP_TRY(hipMemcpyAsync(U.wk, U.r, vb, hipMemcpyDeviceToDevice, st));
       HIP_TRY(dfi::trsv_launch_grouped(tj_fwd, act, U.nmax, 0, st));     // wk -> z
       HIP_TRY(hipMemcpyAsync(U.wk, U.z, vb, hipMemcpyDeviceToDevice, st));
       HIP_TRY(dfi::trsv_launch_grouped(tj_bwd_c, act, U.nmax, 1, st));   // wk -> zc
-      HIP_TRY(dfi::pcg_finish(seg, 0, cont, act, U.zc, U.y, st));        // last sweep: y += zc
+      HIP_TRY(dfi::pcg_decide(seg, 0, 0, act, s, c, U.zc, U.y, st));      // stop: y += zc
       if (cont == 0) break;
-      if (s == 1) HIP_TRY(dfi::pcg_init(seg, 0, 0, cont, U.r, U.zc, U.p, U.rz, st));
-      else HIP_TRY(dfi::pcg_dir(seg, 0, 0, cont, U.r, U.zc, U.p, U.rz, st));
+      if (s == 1) HIP_TRY(dfi::pcg_init(seg, 0, 0, cont, U.r, U.zc, U.p, U.rz, st, U.stop));
+      else HIP_TRY(dfi::pcg_dir(seg, 0, 0, cont, U.r, U.zc, U.p, U.rz, st, U.stop));
       for (int32_t p : order)
-        if (sw[(size_t)p] > s) DF_TRY(w_pass(p, U.p, U.zero, true, U.nq));   // -(W_p p_p)
-      HIP_TRY(dfi::pcg_step(seg, 0, 0, cont, U.p, U.nq, U.y, U.r, U.rz, nullptr, st));
+        if (sw[(size_t)p] > s) DF_TRY(w_pass(p, U.p, U.zero, true, U.nq, U.stop + jpos[(size_t)p]));   // -(W_p p_p)
+      HIP_TRY(dfi::pcg_step(seg, 0, 0, cont, U.p, U.nq, U.y, U.r, U.rz, U.rr, st, U.stop));
     }
   }
   if (o.final_resid) {   // the returned iterate's residual, per problem (not applied)
@@ -927,14 +956,18 @@ dfisher_status uneven_solve(dfisher_ctx* ctx, int32_t np, const float* const* S,
                             const dfisher_options& o, hipStream_t st, dfisher_info* infos) {
   if (ctx->autotune)
     for (int32_t p = 0; p < np; ++p) DF_TRY(tune_if_new(ctx, S[p], n[p], m[p], lds[p], o.gram_prec, st));
-  // sweep count per problem (DFISHER_SWEEPS_AUTO: from its precision, shape and up-front shift)
+  // sweep cap per problem. DFISHER_SWEEPS_AUTO: the a-priori count for its precision, shape and
+  // up-front shift plus two, with the stop test measured on the device (predictive, aim tol or 1e-7);
+  // fixed sweeps: that count, stopping early on a measured tol when one is given.
+  const bool autos = o.sweeps == DFISHER_SWEEPS_AUTO;
+  const double tol = autos && !(o.tol > 0.0) ? AUTO_TOL : o.tol;
   std::vector<int> sw((size_t)np, o.sweeps);
   int max_sw = 0;
   for (int32_t p = 0; p < np; ++p) {
-    if (o.sweeps == DFISHER_SWEEPS_AUTO) {
+    if (autos) {
       const double tau_rel = o.shift_policy == DFISHER_SHIFT_ALWAYS
                                  ? 2.0 * std::sqrt((double)n[p]) * gram_unit(o.gram_prec, m[p]) : 0.0;
-      sw[(size_t)p] = auto_sweeps(o.gram_prec, n[p], m[p], tau_rel);
+      sw[(size_t)p] = std::min(MAX_SWEEPS, auto_sweeps(o.gram_prec, n[p], m[p], tau_rel) + 2);
     }
     max_sw = std::max(max_sw, sw[(size_t)p]);
   }
@@ -962,6 +995,8 @@ dfisher_status uneven_solve(dfisher_ctx* ctx, int32_t np, const float* const* S,
   std::vector<dfi::FactorJob> fj((size_t)np);
   std::vector<dfi::TrsvJob> tf((size_t)np), tb((size_t)np), tr((size_t)np);
   std::vector<int64_t> seg((size_t)(2 * np));   // refinement vectors in table order: (offset, length)
+  std::vector<int> capj((size_t)np);               // sweep cap in table order
+  std::vector<int32_t> jpos((size_t)np);           // table entry of each problem
   for (int32_t j = 0; j < np; ++j) {
     const int32_t p = jord[(size_t)j];
     const size_t q = (size_t)p;
@@ -972,22 +1007,27 @@ dfisher_status uneven_solve(dfisher_ctx* ctx, int32_t np, const float* const* S,
     tr[(size_t)j] = dfi::TrsvJob{Wp, U.Dinv + U.doff[q], n[p], U.wk + U.voff[q], U.zc + U.voff[q]};
     seg[(size_t)(2 * j)] = U.voff[q];
     seg[(size_t)(2 * j + 1)] = n[p];
+    capj[(size_t)j] = sw[q];
+    jpos[q] = j;
   }
   const size_t fbytes = align_up(fj.size() * sizeof(dfi::FactorJob));
   const size_t tbytes = align_up(tf.size() * sizeof(dfi::TrsvJob));
   const size_t sbytes = align_up(seg.size() * sizeof(int64_t));
-  DF_TRY(ensure_tbuf(ctx, fbytes + 3 * tbytes + sbytes));
+  const size_t cbytes = align_up(capj.size() * sizeof(int));
+  DF_TRY(ensure_tbuf(ctx, fbytes + 3 * tbytes + sbytes + cbytes));
   char* tb0 = static_cast<char*>(ctx->tbuf);
   auto* d_fj = reinterpret_cast<dfi::FactorJob*>(tb0);
   auto* d_tf = reinterpret_cast<dfi::TrsvJob*>(tb0 + fbytes);
   auto* d_tb = reinterpret_cast<dfi::TrsvJob*>(tb0 + fbytes + tbytes);
   auto* d_tr = reinterpret_cast<dfi::TrsvJob*>(tb0 + fbytes + 2 * tbytes);
   auto* d_seg = reinterpret_cast<int64_t*>(tb0 + fbytes + 3 * tbytes);
+  auto* d_cap = reinterpret_cast<int*>(tb0 + fbytes + 3 * tbytes + sbytes);
   HIP_TRY(hipMemcpyAsync(d_fj, fj.data(), fj.size() * sizeof(dfi::FactorJob), hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(d_tf, tf.data(), tf.size() * sizeof(dfi::TrsvJob), hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(d_tb, tb.data(), tb.size() * sizeof(dfi::TrsvJob), hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(d_tr, tr.data(), tr.size() * sizeof(dfi::TrsvJob), hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(d_seg, seg.data(), seg.size() * sizeof(int64_t), hipMemcpyHostToDevice, st));
+  HIP_TRY(hipMemcpyAsync(d_cap, capj.data(), capj.size() * sizeof(int), hipMemcpyHostToDevice, st));
   HIP_TRY(hipStreamSynchronize(st));   // the host tables go out of scope; the graph reads the device copies
 
   // the run: replay the captured graph if every argument and buffer is unchanged
@@ -1033,7 +1073,7 @@ dfisher_status uneven_solve(dfisher_ctx* ctx, int32_t np, const float* const* S,
         dfisher_status se = DFISHER_OK;
         if (ok)
           se = uneven_enqueue(ctx, np, S, n, m, lds, v, lambda, x, o, U, order, sw, nactive, d_fj, d_tf, d_tb, d_tr,
-                              d_seg, ctx->cap_stream);
+                              d_seg, d_cap, tol, autos, jpos, ctx->cap_stream);
         if (ok) ok = hipStreamEndCapture(ctx->cap_stream, &graph) == hipSuccess && graph != nullptr;
         if (ok && se == DFISHER_OK) {
           hipGraphExec_t ex = nullptr;
@@ -1053,22 +1093,31 @@ dfisher_status uneven_solve(dfisher_ctx* ctx, int32_t np, const float* const* S,
   }
   if (!ran)
     DF_TRY(uneven_enqueue(ctx, np, S, n, m, lds, v, lambda, x, o, U, order, sw, nactive, d_fj, d_tf, d_tb, d_tr, d_seg,
-                          st));
+                          d_cap, tol, autos, jpos, st));
   std::vector<int64_t> hinfo((size_t)np);
-  std::vector<double> hmax((size_t)np, 0.0), hres((size_t)(2 * np), -1.0);
+  std::vector<double> hmax((size_t)np, 0.0), hres((size_t)(2 * np), -1.0), hrho((size_t)np, -1.0);
+  std::vector<int> hdone((size_t)np, 0), hmet((size_t)np, 0);
   HIP_TRY(hipMemcpyAsync(hinfo.data(), U.info, (size_t)np * sizeof(int64_t), hipMemcpyDeviceToHost, st));
+  if (max_sw > 0) {
+    HIP_TRY(hipMemcpyAsync(hrho.data(), U.resid, (size_t)np * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(hdone.data(), U.done, (size_t)np * sizeof(int), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(hmet.data(), U.met, (size_t)np * sizeof(int), hipMemcpyDeviceToHost, st));
+  }
   if (o.shift_policy == DFISHER_SHIFT_ALWAYS)
     HIP_TRY(hipMemcpyAsync(hmax.data(), U.dmax, (size_t)np * sizeof(double), hipMemcpyDeviceToHost, st));
   if (o.final_resid)
     HIP_TRY(hipMemcpyAsync(hres.data(), U.res, (size_t)(2 * np) * sizeof(double), hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
   dfisher_status worst = DFISHER_OK;
+  bool unmet = false;
   for (int32_t p = 0; p < np; ++p) {
     dfisher_info inf{};
-    inf.resid = -1.0;
+    const size_t j = (size_t)jpos[(size_t)p];
+    inf.resid = tol > 0.0 && sw[(size_t)p] > 0 ? hrho[j] : -1.0;
     inf.potrf_info = hinfo[(size_t)p];
     inf.attempts = 1;
-    inf.sweeps_done = sw[(size_t)p];
+    inf.sweeps_done = sw[(size_t)p] > 0 ? hdone[j] : 0;
+    if (tol > 0.0 && sw[(size_t)p] > 0 && !hmet[j] && inf.potrf_info == 0) unmet = true;
     inf.w_resid = -1.0;
     if (o.final_resid) {
       const double bb = hres[(size_t)(2 * p)], rr = hres[(size_t)(2 * p + 1)];
@@ -1088,6 +1137,8 @@ dfisher_status uneven_solve(dfisher_ctx* ctx, int32_t np, const float* const* S,
     if (infos) infos[p] = inf;
   }
   if (worst != DFISHER_OK) return fail(worst, "at least one problem failed to factor (its x is not meaningful)");
+  if (unmet)
+    return fail(DFISHER_E_NOT_CONVERGED, "at least one problem's measured residual missed tol %.3g at its sweep cap", tol);
   return DFISHER_OK;
 }
 
@@ -1923,7 +1974,6 @@ dfisher_status dfisher_solve_uneven(dfisher_ctx* ctx, int32_t nprob, const float
   if (!S || !n || !m || !lds || !v || !lambda || !x) return fail(DFISHER_E_INVALID_ARG, "NULL array argument");
   dfisher_options o;
   DF_TRY(check_opt(opt, &o));
-  DF_TRY(check_no_tol(o));
   for (int32_t p = 0; p < nprob; ++p) {
     dfisher_status s = check_S(S[p], n[p], m[p], lds[p]);
     if (s != DFISHER_OK) return fail(s, "problem %d: %s", p, g_last_error.c_str());

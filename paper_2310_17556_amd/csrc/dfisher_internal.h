@@ -106,10 +106,12 @@ struct RefinePassPlan {
   size_t part_bytes;  // (ngroups + tail) * n * 8
 };
 RefinePassPlan refine_pass_plan(int64_t n, int64_t m, int64_t lds, const float* S);
+// skip (device int, may be null): when *skip != 0 at run time the kernels return at once (a
+// problem whose refinement stopped, in a launch sequence fixed in advance).
 hipError_t refine_pass_launch(const RefinePassPlan& p, const float* S, int64_t n, int64_t m, int64_t lds,
-                              const double* y, double* part, hipStream_t st);
+                              const double* y, double* part, hipStream_t st, const int* skip = nullptr);
 hipError_t refine_pass_reduce(const RefinePassPlan& p, const double* part, double* r, const double* b,
-                              const double* y, double lam, hipStream_t st);
+                              const double* y, double lam, hipStream_t st, const int* skip = nullptr);
 
 // ----------------------------------------------------------------------------- multi-vector passes
 // One pass over S for up to MULTI_VECS vectors (batched right-hand sides / damping values).
@@ -203,12 +205,35 @@ hipError_t trsv_launch_grouped(const TrsvJob* jobs_dev, int64_t njobs, int64_t n
 // pcg_init: p = z, rz = r.z. pcg_step: with nq = -(W p): alpha = rz / (p.W p), y += alpha p,
 // r -= alpha W p, rr = r.r (rr may be null). pcg_dir: rz' = r.z, p = z + (rz' / rz) p, rz = rz'.
 // pcg_finish: y += z.
+// stop (device, per segment, may be null): segments with stop[s] != 0 are left alone.
 hipError_t pcg_init(const int64_t* seg, int64_t n, int64_t s0, int64_t s1, const double* r, const double* z, double* p,
-                    double* rz, hipStream_t st);
+                    double* rz, hipStream_t st, const int* stop = nullptr);
 hipError_t pcg_step(const int64_t* seg, int64_t n, int64_t s0, int64_t s1, const double* p, const double* nq, double* y,
-                    double* r, const double* rz, double* rr, hipStream_t st);
+                    double* r, const double* rz, double* rr, hipStream_t st, const int* stop = nullptr);
 hipError_t pcg_dir(const int64_t* seg, int64_t n, int64_t s0, int64_t s1, const double* r, const double* z, double* p,
-                   double* rz, hipStream_t st);
+                   double* rz, hipStream_t st, const int* stop = nullptr);
+// out[s] = |x_s|^2
+hipError_t seg_sumsq(const int64_t* seg, int64_t n, int64_t s0, int64_t s1, const double* x, double* out,
+                     hipStream_t st);
+// Device-side stop test of refinement sweeps (per segment, no host round trip): after sweep `sweep`
+// the segment's residual rho = sqrt(rr / bb) is compared with tol (predicted as in the host test
+// when `predict`), and a segment that meets it or reaches cap[s] takes y += zc and stops.
+struct PcgControl {
+  const double* bb;   // |b_s|^2
+  const double* rr;   // |r_s|^2 of the current iterate
+  double* prev;       // rho of the previous sweep (1 at the start)
+  int* stop;          // 1 once the segment has stopped
+  const int* cap;     // sweep cap per segment
+  int* done;          // sweeps the segment ran
+  double* resid;      // its last rho
+  int* met;           // 1 if it stopped on tol
+  double tol;         // 0: stop at the cap only
+  double floor;       // least contraction a prediction assumes
+  int predict;
+};
+hipError_t pcg_decide(const int64_t* seg, int64_t n, int64_t s0, int64_t s1, int sweep, const PcgControl& c,
+                      const double* zc, double* y, hipStream_t st);
+hipError_t pcg_control_init(int64_t nseg, const PcgControl& c, hipStream_t st);
 hipError_t pcg_finish(const int64_t* seg, int64_t n, int64_t s0, int64_t s1, const double* z, double* y,
                       hipStream_t st);
 

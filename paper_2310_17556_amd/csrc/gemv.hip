@@ -177,8 +177,9 @@ rowpass_kernel(const float* __restrict__ S, int64_t n, int64_t m, int64_t lds, c
 __global__ void __launch_bounds__(256)
 rowpass_reduce_kernel(const double* __restrict__ part, int64_t n, int64_t ngroups, int want_b, int want_d,
                       double* __restrict__ b, double* __restrict__ d, const double* __restrict__ r0,
-                      const double* __restrict__ y, double lam) {
+                      const double* __restrict__ y, double lam, const int* __restrict__ skip) {
   __shared__ double red[2][16][17];
+  if (skip && *skip) return;   // a problem whose refinement has stopped (uniform)
   const int tid = threadIdx.x;
   const int ri = tid & 15, sl = tid >> 4;
   const int64_t i = (int64_t)blockIdx.x * 16 + ri;
@@ -451,8 +452,9 @@ constexpr int FR_GROUP = 2;    // workgroups (of one XCD) walking adjacent block
 template <int NCH>
 __global__ void __launch_bounds__(64 * FR_WAVES)
 refine_pass_kernel(const float* __restrict__ S, int64_t n, int64_t m, int64_t lds, const double* __restrict__ y,
-                   double* __restrict__ part) {
+                   double* __restrict__ part, const int* __restrict__ skip) {
   constexpr int ROWS = 16 * FR_WAVES;   // rows per load step of the workgroup
+  if (skip && *skip) return;   // a problem whose refinement has stopped (uniform): no read of S
   __shared__ double ys[ROWS * NCH];
   // Per-wave partials of t and t itself. Single buffers suffice: a block's partials are read
   // before its second barrier, which every wave passes before writing the next block's.
@@ -576,9 +578,10 @@ refine_pass_kernel(const float* __restrict__ S, int64_t n, int64_t m, int64_t ld
 // fixed order through LDS), then part[i] = sum_c S_ic t_c. One workgroup of 256 threads.
 __global__ void __launch_bounds__(256)
 refine_tail_kernel(const float* __restrict__ S, int64_t n, int64_t m, int64_t lds, const double* __restrict__ y,
-                   int64_t c0, double* __restrict__ part) {
+                   int64_t c0, double* __restrict__ part, const int* __restrict__ skip) {
   __shared__ double red[256][FR_COLS];
   __shared__ double tc[FR_COLS];
+  if (skip && *skip) return;
   const int tid = threadIdx.x;
   const int nt = (int)(m - c0);   // 1 .. 15
   double p[FR_COLS];
@@ -689,7 +692,7 @@ hipError_t rowpass_reduce(const RowPassPlan& p, const double* part, bool want_b,
                           const double* r0, const double* y, double lam, hipStream_t st) {
   const dim3 grid((unsigned)((p.n + 15) / 16));
   hipLaunchKernelGGL(rowpass_reduce_kernel, grid, dim3(256), 0, st, part, p.n, p.nchunk, want_b ? 1 : 0,
-                     want_d ? 1 : 0, b, d, r0, y, lam);
+                     want_d ? 1 : 0, b, d, r0, y, lam, (const int*)nullptr);
   return hipGetLastError();
 }
 
@@ -752,24 +755,24 @@ RefinePassPlan refine_pass_plan(int64_t n, int64_t m, int64_t lds, const float* 
 }
 
 hipError_t refine_pass_launch(const RefinePassPlan& p, const float* S, int64_t n, int64_t m, int64_t lds,
-                              const double* y, double* part, hipStream_t st) {
+                              const double* y, double* part, hipStream_t st, const int* skip) {
   if (!p.usable || p.n != n) return hipErrorInvalidValue;
   const dim3 grid((unsigned)p.ngroups), block(64 * FR_WAVES);
   switch (p.nch) {
-    case 8: hipLaunchKernelGGL(refine_pass_kernel<8>, grid, block, 0, st, S, n, m, lds, y, part); break;
-    case 16: hipLaunchKernelGGL(refine_pass_kernel<16>, grid, block, 0, st, S, n, m, lds, y, part); break;
-    default: hipLaunchKernelGGL(refine_pass_kernel<32>, grid, block, 0, st, S, n, m, lds, y, part); break;
+    case 8: hipLaunchKernelGGL(refine_pass_kernel<8>, grid, block, 0, st, S, n, m, lds, y, part, skip); break;
+    case 16: hipLaunchKernelGGL(refine_pass_kernel<16>, grid, block, 0, st, S, n, m, lds, y, part, skip); break;
+    default: hipLaunchKernelGGL(refine_pass_kernel<32>, grid, block, 0, st, S, n, m, lds, y, part, skip); break;
   }
   if (p.tail)
     hipLaunchKernelGGL(refine_tail_kernel, dim3(1), dim3(256), 0, st, S, n, m, lds, y, m / FR_COLS * FR_COLS,
-                       part + p.ngroups * n);
+                       part + p.ngroups * n, skip);
   return hipGetLastError();
 }
 
 hipError_t refine_pass_reduce(const RefinePassPlan& p, const double* part, double* r, const double* b,
-                              const double* y, double lam, hipStream_t st) {
+                              const double* y, double lam, hipStream_t st, const int* skip) {
   hipLaunchKernelGGL(rowpass_reduce_kernel, dim3((unsigned)((p.n + 15) / 16)), dim3(256), 0, st, part, p.n,
-                     p.ngroups + (p.tail ? 1 : 0), 1, 0, r, (double*)nullptr, b, y, lam);
+                     p.ngroups + (p.tail ? 1 : 0), 1, 0, r, (double*)nullptr, b, y, lam, skip);
   return hipGetLastError();
 }
 

@@ -41,9 +41,11 @@ __device__ __forceinline__ void segment(const int64_t* seg, int64_t n, int64_t s
 // p = z, rz = r . z
 __global__ void __launch_bounds__(PT) pcg_init_kernel(const int64_t* __restrict__ seg, int64_t n, int64_t s0,
                                                       const double* __restrict__ r, const double* __restrict__ z,
-                                                      double* __restrict__ p, double* __restrict__ rz) {
+                                                      double* __restrict__ p, double* __restrict__ rz,
+                                                      const int* __restrict__ stop) {
   __shared__ double red[PT];
   const int64_t s = s0 + blockIdx.x;
+  if (stop && stop[s]) return;
   int64_t off, len;
   segment(seg, n, s, off, len);
   double acc = 0.0;
@@ -62,9 +64,11 @@ __global__ void __launch_bounds__(PT) pcg_init_kernel(const int64_t* __restrict_
 __global__ void __launch_bounds__(PT) pcg_step_kernel(const int64_t* __restrict__ seg, int64_t n, int64_t s0,
                                                       const double* __restrict__ p, const double* __restrict__ nq,
                                                       double* __restrict__ y, double* __restrict__ r,
-                                                      const double* __restrict__ rz, double* __restrict__ rr) {
+                                                      const double* __restrict__ rz, double* __restrict__ rr,
+                                                      const int* __restrict__ stop) {
   __shared__ double red[PT];
   const int64_t s = s0 + blockIdx.x;
+  if (stop && stop[s]) return;
   int64_t off, len;
   segment(seg, n, s, off, len);
   double acc = 0.0;
@@ -87,9 +91,11 @@ __global__ void __launch_bounds__(PT) pcg_step_kernel(const int64_t* __restrict_
 // rz' = r . z; beta = rz' / rz; p = z + beta p; rz = rz'
 __global__ void __launch_bounds__(PT) pcg_dir_kernel(const int64_t* __restrict__ seg, int64_t n, int64_t s0,
                                                      const double* __restrict__ r, const double* __restrict__ z,
-                                                     double* __restrict__ p, double* __restrict__ rz) {
+                                                     double* __restrict__ p, double* __restrict__ rz,
+                                                     const int* __restrict__ stop) {
   __shared__ double red[PT];
   const int64_t s = s0 + blockIdx.x;
+  if (stop && stop[s]) return;
   int64_t off, len;
   segment(seg, n, s, off, len);
   const double rzo = rz[s];   // read before the barriers of the sum; thread 0 overwrites it after
@@ -110,26 +116,103 @@ __global__ void __launch_bounds__(PT) pcg_finish_kernel(const int64_t* __restric
   for (int64_t i = threadIdx.x; i < len; i += PT) y[off + i] += z[off + i];
 }
 
+// out[s] = x . x over segment s
+__global__ void __launch_bounds__(PT) seg_sumsq_kernel(const int64_t* __restrict__ seg, int64_t n, int64_t s0,
+                                                       const double* __restrict__ x, double* __restrict__ out) {
+  __shared__ double red[PT];
+  const int64_t s = s0 + blockIdx.x;
+  int64_t off, len;
+  segment(seg, n, s, off, len);
+  double acc = 0.0;
+  for (int64_t i = threadIdx.x; i < len; i += PT) acc = fma(x[off + i], x[off + i], acc);
+  const double t = block_sum(acc, red);
+  if (threadIdx.x == 0) out[s] = t;
+}
+
+// The stop test of one sweep for every running segment, on the device: rho = sqrt(rr / bb) (the
+// relative residual of the current iterate), expect = rho max(floor, min(1, rho / prev)) when
+// predicting, else rho; the segment stops when tol > 0 and expect <= tol, or at its sweep cap.
+// A stopping segment takes its last correction (y += zc) and records its sweep count.
+__global__ void __launch_bounds__(PT) pcg_decide_kernel(const int64_t* __restrict__ seg, int64_t n, int64_t s0, int sweep,
+                                                        PcgControl c, const double* __restrict__ zc,
+                                                        double* __restrict__ y) {
+  const int64_t s = s0 + blockIdx.x;
+  if (c.stop[s]) return;
+  const double bb = c.bb[s], rr = c.rr[s];
+  const double rho = bb > 0.0 ? sqrt(rr / bb) : (rr > 0.0 ? INFINITY : 0.0);
+  const double pv = c.prev[s];
+  const double ratio = pv > 0.0 ? fmin(1.0, rho / pv) : 0.0;
+  const double expect = c.predict ? rho * fmax(c.floor, ratio) : rho;
+  const bool met = c.tol > 0.0 && expect <= c.tol;
+  const bool last = sweep >= c.cap[s];
+  __syncthreads();   // every thread has read the scalars before thread 0 updates them
+  if (threadIdx.x == 0) {
+    c.prev[s] = rho;
+    c.resid[s] = rho;
+  }
+  if (!(met || last)) return;
+  int64_t off, len;
+  segment(seg, n, s, off, len);
+  for (int64_t i = threadIdx.x; i < len; i += PT) y[off + i] += zc[off + i];
+  if (threadIdx.x == 0) {
+    c.stop[s] = 1;
+    c.done[s] = sweep;
+    c.met[s] = met ? 1 : 0;
+  }
+}
+
+// stop[s] = (cap[s] < 1), prev = 1, done = 0, resid = -1, met = 0
+__global__ void pcg_control_init_kernel(int64_t nseg, PcgControl c) {
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= nseg) return;
+  c.stop[s] = c.cap[s] < 1 ? 1 : 0;
+  c.prev[s] = 1.0;
+  c.done[s] = 0;
+  c.resid[s] = -1.0;
+  c.met[s] = 0;
+}
+
 }  // namespace
 
-hipError_t pcg_init(const int64_t* seg, int64_t n, int64_t s0, int64_t s1, const double* r, const double* z, double* p,
-                    double* rz, hipStream_t st) {
+hipError_t seg_sumsq(const int64_t* seg, int64_t n, int64_t s0, int64_t s1, const double* x, double* out,
+                     hipStream_t st) {
   if (s1 <= s0) return hipSuccess;
-  hipLaunchKernelGGL(pcg_init_kernel, dim3((unsigned)(s1 - s0)), dim3(PT), 0, st, seg, n, s0, r, z, p, rz);
+  hipLaunchKernelGGL(seg_sumsq_kernel, dim3((unsigned)(s1 - s0)), dim3(PT), 0, st, seg, n, s0, x, out);
+  return hipGetLastError();
+}
+
+hipError_t pcg_decide(const int64_t* seg, int64_t n, int64_t s0, int64_t s1, int sweep, const PcgControl& c,
+                      const double* zc, double* y, hipStream_t st) {
+  if (s1 <= s0) return hipSuccess;
+  hipLaunchKernelGGL(pcg_decide_kernel, dim3((unsigned)(s1 - s0)), dim3(PT), 0, st, seg, n, s0, sweep, c, zc, y);
+  return hipGetLastError();
+}
+
+hipError_t pcg_control_init(int64_t nseg, const PcgControl& c, hipStream_t st) {
+  if (nseg < 1) return hipSuccess;
+  hipLaunchKernelGGL(pcg_control_init_kernel, dim3((unsigned)((nseg + 255) / 256)), dim3(256), 0, st, nseg, c);
+  return hipGetLastError();
+}
+
+hipError_t pcg_init(const int64_t* seg, int64_t n, int64_t s0, int64_t s1, const double* r, const double* z, double* p,
+                    double* rz, hipStream_t st, const int* stop) {
+  if (s1 <= s0) return hipSuccess;
+  hipLaunchKernelGGL(pcg_init_kernel, dim3((unsigned)(s1 - s0)), dim3(PT), 0, st, seg, n, s0, r, z, p, rz, stop);
   return hipGetLastError();
 }
 
 hipError_t pcg_step(const int64_t* seg, int64_t n, int64_t s0, int64_t s1, const double* p, const double* nq, double* y,
-                    double* r, const double* rz, double* rr, hipStream_t st) {
+                    double* r, const double* rz, double* rr, hipStream_t st, const int* stop) {
   if (s1 <= s0) return hipSuccess;
-  hipLaunchKernelGGL(pcg_step_kernel, dim3((unsigned)(s1 - s0)), dim3(PT), 0, st, seg, n, s0, p, nq, y, r, rz, rr);
+  hipLaunchKernelGGL(pcg_step_kernel, dim3((unsigned)(s1 - s0)), dim3(PT), 0, st, seg, n, s0, p, nq, y, r, rz, rr,
+                     stop);
   return hipGetLastError();
 }
 
 hipError_t pcg_dir(const int64_t* seg, int64_t n, int64_t s0, int64_t s1, const double* r, const double* z, double* p,
-                   double* rz, hipStream_t st) {
+                   double* rz, hipStream_t st, const int* stop) {
   if (s1 <= s0) return hipSuccess;
-  hipLaunchKernelGGL(pcg_dir_kernel, dim3((unsigned)(s1 - s0)), dim3(PT), 0, st, seg, n, s0, r, z, p, rz);
+  hipLaunchKernelGGL(pcg_dir_kernel, dim3((unsigned)(s1 - s0)), dim3(PT), 0, st, seg, n, s0, r, z, p, rz, stop);
   return hipGetLastError();
 }
 

@@ -115,8 +115,10 @@ def test_invalid_arguments_rejected_on_host(dfl):
     arrp = (ctypes.c_void_p * 1)(P.value)
     arr64 = (ctypes.c_int64 * 1)(8)
     arrn = (ctypes.c_int64 * 1)(4)
-    assert lib.dfisher_solve_uneven(FAKE_CTX, 1, arrp, arrn, arr64, arr64, arrp, lams, arrp, ctypes.byref(otol), st,
-                                    None) == U
+    # the uneven call honours a tolerance (measured on the device); a negative one is rejected
+    oneg = _opts(dfl, sweeps=2, tol=-1e-9)
+    assert lib.dfisher_solve_uneven(FAKE_CTX, 1, arrp, arrn, arr64, arr64, arrp, lams, arrp, ctypes.byref(oneg), st,
+                                    None) == E
     # the final-residual measurement is offered by dfisher_solve and dfisher_solve_uneven only
     ofin = _opts(dfl, sweeps=1, final=1)
     assert lib.dfisher_solve_batched(FAKE_CTX, P, 4, 8, 8, lams, 1, P, 1, 8, P, 8, ctypes.byref(ofin), st, None) == U
