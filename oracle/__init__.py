@@ -76,6 +76,7 @@ def _load():
             "oracle_center": ([P, I, I, I, P, I], None),
             "oracle_center_complex": ([P, I, I, I, P, I], None),
             "oracle_solve_complex": ([P, I, I, I, P, D, P, P], I),
+            "oracle_project_centered": ([P, I, I, D, P], None),
         }
         for name, (args, res) in sigs.items():
             f = getattr(lib, name)
@@ -297,6 +298,19 @@ def center_complex(O) -> np.ndarray:
     Z = np.empty((2 * n, m), dtype=np.float32)
     _load().oracle_center_complex(_p(O), n, m, m, _p(Z), m)
     return Z
+
+
+def project_centered(W, lam: float, nseg: int = 1) -> np.ndarray:
+    """Preconditioner for a centered S (Section 3): M = P W P + lam U U^T, P = I - U U^T, U the
+    normalised indicators of nseg equal contiguous segments of the n indices (1: the all-ones
+    vector; 2: the real and imaginary halves of the complex variant's real embedding)."""
+    W = np.ascontiguousarray(W, dtype=np.float64)
+    n = W.shape[0]
+    if W.shape != (n, n) or nseg < 1 or n % nseg != 0:
+        raise ValueError("W must be square with n divisible by nseg")
+    M = np.empty((n, n), dtype=np.float64)
+    _load().oracle_project_centered(_p(W), n, nseg, float(lam), _p(M))
+    return M
 
 
 def solve_complex(S, v, lam: float, return_y: bool = False):

@@ -449,6 +449,43 @@ out:
   return info;
 }
 
+/* Preconditioner of a centered score matrix (Section 3: S = (O - mean O) / sqrt(n) has columns
+ * that sum to zero over the samples, so S S^T has the all-ones vector as an exact null vector and
+ * W = S S^T + lambda I maps it to lambda times itself). Given an n x n symmetric W (full storage)
+ * and nseg equal contiguous segments of length l = n / nseg (nseg = 2 for the real embedding of
+ * the complex variant, whose two null vectors are the indicators of the real and imaginary
+ * halves), this writes
+ *     M = P W P + lambda U U^T,    P = I - U U^T,    U = [u_1 .. u_nseg],  u_s = 1_{segment s} / sqrt(l)
+ * i.e. W compressed to the complement of the indicators, with lambda on them. Computed as the
+ * definition: P formed explicitly, then the two matrix products in plain loops. */
+EXPORT void oracle_project_centered(const double* W, int64_t n, int64_t nseg, double lambda, double* M) {
+  const int64_t l = n / nseg;
+  double* P = (double*)malloc((size_t)(n * n) * sizeof(double));
+  double* T = (double*)malloc((size_t)(n * n) * sizeof(double));
+  for (int64_t i = 0; i < n; ++i)
+    for (int64_t j = 0; j < n; ++j) {
+      const double uu = (i / l == j / l) ? 1.0 / (double)l : 0.0;   /* (U U^T)_ij */
+      P[i * n + j] = (i == j ? 1.0 : 0.0) - uu;
+    }
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < n; ++i)
+    for (int64_t j = 0; j < n; ++j) {
+      double acc = 0.0;
+      for (int64_t k = 0; k < n; ++k) acc += P[i * n + k] * W[k * n + j];
+      T[i * n + j] = acc;
+    }
+#pragma omp parallel for schedule(static)
+  for (int64_t i = 0; i < n; ++i)
+    for (int64_t j = 0; j < n; ++j) {
+      double acc = 0.0;
+      for (int64_t k = 0; k < n; ++k) acc += T[i * n + k] * P[k * n + j];
+      const double uu = (i / l == j / l) ? 1.0 / (double)l : 0.0;
+      M[i * n + j] = acc + lambda * uu;
+    }
+  free(P);
+  free(T);
+}
+
 /* Number of OpenMP threads the oracle runs on (1 without OpenMP). */
 EXPORT int oracle_num_threads(void) {
   int t = 1;
