@@ -36,6 +36,7 @@ HBM_PEAK_GBS = 8000.0
 PREC_CODE = {"fp32": 0, "bf16x3": 1, "mxfp8": 2}
 DTYPE = {"fp32": "f32+f64", "bf16x3": "bf16x3+f64", "mxfp8": "fp8(e4m3,mx)+f64"}
 PASSES = {"fp32": 1, "bf16x3": 3, "mxfp8": 1}   # matrix-core products per Gram term
+CENTERED = True   # every workload's S is column-centered; passed to the library as DFISHER_CENTERED
 
 
 def log(msg: str) -> None:
@@ -193,14 +194,14 @@ def run_path(dfl, ctx, S, v, lams, prec, sweeps, steps, warmup, xbuf, shift="on_
     infos = []
     for _ in range(warmup):
         for lam in lams:
-            dfl.dfisher_solve(ctx, S, v, lam, gram_prec=PREC_CODE[prec], sweeps=sweeps, shift_policy=policy,
+            dfl.dfisher_solve(ctx, S, v, lam, gram_prec=PREC_CODE[prec], centered=CENTERED, sweeps=sweeps, shift_policy=policy,
                               x=xbuf[lam])
     torch.cuda.synchronize()
     gram_ms, stage = [], []
     t0 = time.perf_counter()
     for _ in range(steps):
         for lam in lams:
-            _, info = dfl.dfisher_solve(ctx, S, v, lam, gram_prec=PREC_CODE[prec], sweeps=sweeps,
+            _, info = dfl.dfisher_solve(ctx, S, v, lam, gram_prec=PREC_CODE[prec], centered=CENTERED, sweeps=sweeps,
                                         shift_policy=policy, x=xbuf[lam])
             t = dfl.dfisher_ctx_last_timing(ctx)
             gram_ms.append(t["gram_ms"])
@@ -233,7 +234,7 @@ def error_table(dfl, ctx, S, v, lams, xref, table, shift="on_failure"):
         for sw in sweep_list:
             row = {}
             for lam in lams:
-                _, info = dfl.dfisher_solve(ctx, S, v, lam, gram_prec=PREC_CODE[prec], sweeps=sw, shift_policy=policy,
+                _, info = dfl.dfisher_solve(ctx, S, v, lam, gram_prec=PREC_CODE[prec], centered=CENTERED, sweeps=sw, shift_policy=policy,
                                             x=x64, x_fp64=True, final_resid=True)
                 rel, esy = _errs(x64, xref[lam], v, lam)
                 row[str(lam)] = {"rel_err": rel, "eps_Sy": esy, "w_resid": info["w_resid"],
@@ -285,15 +286,15 @@ def paper_scale_leg(dfl, dev, reps, n=1024, m=1_000_000, lam=1e-3, seed=2):
     x = torch.empty(m, dtype=torch.float32, device=dev)
     x64 = torch.empty(m, dtype=torch.float64, device=dev)
     for prec, sw in [("fp32", 0), ("fp32", 1), ("mxfp8", -1), ("bf16x3", -1)]:
-        dfl.dfisher_solve(ctx, S, v, lam, gram_prec=PREC_CODE[prec], sweeps=sw, x=x)   # warmup
+        dfl.dfisher_solve(ctx, S, v, lam, gram_prec=PREC_CODE[prec], centered=CENTERED, sweeps=sw, x=x)   # warmup
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(reps):
-            _, info = dfl.dfisher_solve(ctx, S, v, lam, gram_prec=PREC_CODE[prec], sweeps=sw, x=x)
+            _, info = dfl.dfisher_solve(ctx, S, v, lam, gram_prec=PREC_CODE[prec], centered=CENTERED, sweeps=sw, x=x)
         torch.cuda.synchronize()
         el = (time.perf_counter() - t0) / reps
         rel32, _ = _errs(x, xref, v, lam)
-        _, i64 = dfl.dfisher_solve(ctx, S, v, lam, gram_prec=PREC_CODE[prec], sweeps=sw, x=x64, x_fp64=True,
+        _, i64 = dfl.dfisher_solve(ctx, S, v, lam, gram_prec=PREC_CODE[prec], centered=CENTERED, sweeps=sw, x=x64, x_fp64=True,
                                    final_resid=True)
         rel64, esy = _errs(x64, xref, v, lam)
         out["paths"][f"{prec}/{'auto' if sw < 0 else sw}"] = {
@@ -337,15 +338,15 @@ def batched_leg(dfl, dev, prec, sweeps, reps, n=2048, m=2_000_000, nlam=16, nrhs
     lams = [float(x) for x in synth.lambdas_logspaced(1e-6, 1e-1, nlam)]
     ctx = dfl.dfisher_ctx_create(0)
     X = torch.empty((nlam, nrhs, m), dtype=torch.float32, device=dev)
-    dfl.dfisher_solve_batched(ctx, S, lams, V, gram_prec=PREC_CODE[prec], sweeps=sweeps, X=X)   # warmup
+    dfl.dfisher_solve_batched(ctx, S, lams, V, gram_prec=PREC_CODE[prec], centered=CENTERED, sweeps=sweeps, X=X)   # warmup
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(reps):
-        _, infos = dfl.dfisher_solve_batched(ctx, S, lams, V, gram_prec=PREC_CODE[prec], sweeps=sweeps, X=X)
+        _, infos = dfl.dfisher_solve_batched(ctx, S, lams, V, gram_prec=PREC_CODE[prec], centered=CENTERED, sweeps=sweeps, X=X)
     torch.cuda.synchronize()
     el = (time.perf_counter() - t0) / reps
     X64 = torch.empty((nlam, nrhs, m), dtype=torch.float64, device=dev)
-    dfl.dfisher_solve_batched(ctx, S, lams, V, gram_prec=PREC_CODE[prec], sweeps=sweeps, X=X64, x_fp64=True)
+    dfl.dfisher_solve_batched(ctx, S, lams, V, gram_prec=PREC_CODE[prec], centered=CENTERED, sweeps=sweeps, X=X64, x_fp64=True)
     Ys = _batched_ref(S, V, lams)
     Yall = torch.stack([Y for Y in Ys], dim=1).reshape(n, nlam * nrhs)   # column l * nrhs + r
     lamv = torch.tensor(lams, dtype=torch.float64, device=dev)[:, None, None]
@@ -391,15 +392,15 @@ def uneven_leg(dfl, dev, prec, sweeps, reps, nprob=64, seed=5):
     lams = [float(x) for x in lams]
     ctx = dfl.dfisher_ctx_create(0)
     xs = [torch.empty(int(m), dtype=torch.float32, device=dev) for m in ms]
-    dfl.dfisher_solve_uneven(ctx, Ss, vs, lams, gram_prec=PREC_CODE[prec], sweeps=sweeps, xs=xs)   # capture
+    dfl.dfisher_solve_uneven(ctx, Ss, vs, lams, gram_prec=PREC_CODE[prec], centered=CENTERED, sweeps=sweeps, xs=xs)   # capture
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(reps):
-        _, infos = dfl.dfisher_solve_uneven(ctx, Ss, vs, lams, gram_prec=PREC_CODE[prec], sweeps=sweeps, xs=xs)
+        _, infos = dfl.dfisher_solve_uneven(ctx, Ss, vs, lams, gram_prec=PREC_CODE[prec], centered=CENTERED, sweeps=sweeps, xs=xs)
     torch.cuda.synchronize()
     el = (time.perf_counter() - t0) / reps
     x64s = [torch.empty(int(m), dtype=torch.float64, device=dev) for m in ms]
-    _, inf64 = dfl.dfisher_solve_uneven(ctx, Ss, vs, lams, gram_prec=PREC_CODE[prec], sweeps=sweeps, xs=x64s,
+    _, inf64 = dfl.dfisher_solve_uneven(ctx, Ss, vs, lams, gram_prec=PREC_CODE[prec], centered=CENTERED, sweeps=sweeps, xs=x64s,
                                         x_fp64=True, final_resid=True)
     rel32, rel64, esy, per = [], [], [], []
     for p in range(nprob):
@@ -463,9 +464,14 @@ def main() -> int:
     ap.add_argument("--leg-sweeps", type=_sweeps_arg, default=-1,
                     help="refinement sweeps of the batched and uneven legs (default 'auto': the a-priori count "
                          "per problem shape)")
+    ap.add_argument("--no-centered", action="store_true",
+                    help="do not declare S centered (the workloads' S is column-centered; the declaration "
+                         "makes the factored matrix exact along the all-ones direction)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run two device copies of 1 GiB (reference reading for the HBM byte counters)")
     args = ap.parse_args()
+    global CENTERED
+    CENTERED = not args.no_centered
 
     if args.gpus != 1:
         print(json.dumps({"error": f"--gpus {args.gpus}: this build runs on exactly one GPU; multi-GPU "
@@ -635,7 +641,8 @@ def main() -> int:
                                f"one solve per lambda in {lams}",
                    "n": n, "m": m, "lambdas": lams, "gram": args.prec,
                    "sweeps": "auto" if args.sweeps < 0 else args.sweeps, "sweeps_a_priori_rule": sweeps_resolved,
-                   "sweeps_done": sweeps_done, "shift": args.shift, "solves_per_step": len(lams)},
+                   "sweeps_done": sweeps_done, "shift": args.shift, "solves_per_step": len(lams),
+                   "centered_flag": CENTERED},
         "roofline": {"bound": "mfma", "kernel": GRAM_KERNEL[args.prec], "achieved": achieved, "peak": peak,
                      "unit": "TFLOP/s", "frac": achieved / peak, "traffic": gram_traffic(args.prec, n, m),
                      "algorithmic_flops_per_launch": algo_flops, "avg_launch_ms": gram_avg_ms,

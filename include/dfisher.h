@@ -100,8 +100,23 @@ typedef struct dfisher_options {
                             (FP64 accumulation, one more pass over S, not applied) and report
                             it in info->w_resid. dfisher_solve and dfisher_solve_uneven only
                             (other entry points return DFISHER_E_UNSUPPORTED). 0 or 1.        */
-  int32_t reserved;      /* must be 0                                                       */
+  int32_t flags;         /* bitwise OR of the DFISHER_CENTERED flag below, or 0; other bits
+                            are DFISHER_E_INVALID_ARG                                          */
 } dfisher_options;
+
+/* opt->flags: the caller declares that every column of S sums to zero over the samples (1^T S = 0),
+ * as the SR score matrix of Section 3 does (dfisher_sr_center writes one). S S^T then has the
+ * all-ones vector as a null vector, W maps it to lambda times itself, and a Gram formed from
+ * rounded inputs misses that by far more than a small lambda (for the scaled-FP8 Gram about 1e-3
+ * of the diagonal), which makes its factor a poor preconditioner along that one direction. With
+ * the flag the factored matrix is the computed W with that direction made exact,
+ *     M = P W P + lambda 1 1^T / n,   P = I - 1 1^T / n   (FP64, before the Cholesky),
+ * and for dfisher_solve_complex the same with the indicators of the A and B halves of Z (the real
+ * and imaginary halves of the real embedding). The refinement sweeps still use the exact W, so the
+ * result is the solution of Eq. 1 whether or not the declaration holds; only the convergence of
+ * the sweeps (and the sweeps-0 result, which is then M^-1 rather than the computed W^-1) changes.
+ * Honoured by dfisher_solve, _rowspace, _complex, _batched, _uneven and dfisher_factor_create. */
+#define DFISHER_CENTERED 1
 
 /* Refinement sweeps. Each sweep reads S once. Sweep 1 forms the FP64 residual r = S v - lambda y
  * - S (S^T y) of y = L^-T L^-1 S v; the sweeps after it are conjugate-gradient iterations on
@@ -125,7 +140,8 @@ typedef struct dfisher_options {
  *     (the batched call uses the largest count of its lambdas). */
 #define DFISHER_SWEEPS_AUTO (-1)
 
-/* Defaults: FP32 Gram, 0 sweeps, shift on failure, FP32 output, no tolerance, no final residual. */
+/* Defaults: FP32 Gram, 0 sweeps, shift on failure, FP32 output, no tolerance, no final residual,
+ * no flags. */
 #define DFISHER_OPTIONS_DEFAULT {DFISHER_GRAM_FP32, 0, DFISHER_SHIFT_ON_FAILURE, 0, 0.0, 0, 0}
 
 typedef struct dfisher_info {
@@ -352,8 +368,9 @@ DFISHER_API dfisher_status dfisher_ctx_load_tuning(dfisher_ctx* ctx, const char*
  * entries, and the count is the smallest k with c^(k+1) <= 1e-7; for the scaled-FP8 Gram it is
  * then raised by 3 below m/n = 150 and by 2 below m/n = 600 (directions where the Gram's error
  * exceeds W's eigenvalue, such as the all-ones direction of a column-centered S, converge only
- * after the bulk); at most 16. It is a heuristic: for a measured residual use opt->tol with
- * dfisher_solve. Returns -1 for an unknown prec or n, m < 1. */
+ * after the bulk); the solves leave that raise out when opt->flags has DFISHER_CENTERED, which
+ * makes that direction exact; at most 16. It is a heuristic: for a measured residual use opt->tol
+ * with dfisher_solve. Returns -1 for an unknown prec or n, m < 1. */
 DFISHER_API int32_t dfisher_auto_sweeps(int32_t prec, int64_t n, int64_t m);
 
 /* Static text for a status code. */

@@ -41,6 +41,7 @@ DFISHER_GRAM_MXFP8 = 2
 DFISHER_SHIFT_NONE = 0
 DFISHER_SHIFT_ON_FAILURE = 1
 DFISHER_SHIFT_ALWAYS = 2
+DFISHER_CENTERED = 1
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libdfisher.so")
@@ -49,7 +50,7 @@ LIB_PATH = os.path.join(_HERE, "libdfisher.so")
 class _Options(ctypes.Structure):
     _fields_ = [("gram_prec", ctypes.c_int32), ("sweeps", ctypes.c_int32),
                 ("shift_policy", ctypes.c_int32), ("x_fp64", ctypes.c_int32), ("tol", ctypes.c_double),
-                ("final_resid", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("final_resid", ctypes.c_int32), ("flags", ctypes.c_int32)]
 
 
 class Info(ctypes.Structure):
@@ -192,9 +193,10 @@ def _vec(t, length, dtype, name):
         raise ValueError(f"{name} must be contiguous with {length} elements")
 
 
-def _options(gram_prec, sweeps, shift_policy, x_fp64, final_resid=False):
+def _options(gram_prec, sweeps, shift_policy, x_fp64, final_resid=False, centered=False):
     o = _Options(int(gram_prec), int(sweeps), int(shift_policy), 1 if x_fp64 else 0)
     o.final_resid = 1 if final_resid else 0
+    o.flags = DFISHER_CENTERED if centered else 0
     return o
 
 
@@ -351,7 +353,7 @@ def dfisher_apply(ctx, S, v, y, lam: float, x=None, x_fp64: bool = False, stream
 
 def dfisher_solve(ctx, S, v, lam: float, gram_prec: int = DFISHER_GRAM_FP32, sweeps: int = 0,
                   shift_policy: int = DFISHER_SHIFT_ON_FAILURE, x_fp64: bool = False, x=None, stream=None,
-                  tol: float = 0.0, final_resid: bool = False):
+                  tol: float = 0.0, final_resid: bool = False, centered: bool = False):
     """x solving (S^T S + lam I) x = v. Returns (x, info_dict). With tol > 0 the refinement stops at
     the tolerance (sweeps is the cap); info_dict["converged"] is False (and x is still the result)
     when the library returns DFISHER_E_NOT_CONVERGED."""
@@ -362,7 +364,7 @@ def dfisher_solve(ctx, S, v, lam: float, gram_prec: int = DFISHER_GRAM_FP32, swe
     if x is None:
         x = torch.empty(m, dtype=dt, device=S.device)
     _vec(x, m, dt, "x")
-    opt = _options(gram_prec, sweeps, shift_policy, x_fp64, final_resid)
+    opt = _options(gram_prec, sweeps, shift_policy, x_fp64, final_resid, centered)
     opt.tol = float(tol)
     info = Info()
     st = _lib().dfisher_solve(ctx.ptr, _ptr(S), n, m, lds, _ptr(v), float(lam), _ptr(x), ctypes.byref(opt),
@@ -376,7 +378,7 @@ def dfisher_solve(ctx, S, v, lam: float, gram_prec: int = DFISHER_GRAM_FP32, swe
 
 def dfisher_solve_rowspace(ctx, S, f, lam: float, gram_prec: int = DFISHER_GRAM_FP32, sweeps: int = 0,
                            shift_policy: int = DFISHER_SHIFT_ON_FAILURE, x_fp64: bool = False, x=None, stream=None,
-                           tol: float = 0.0, final_resid: bool = False):
+                           tol: float = 0.0, final_resid: bool = False, centered: bool = False):
     """x solving (S^T S + lam I) x = S^T f for an FP64 f of length n (the right-hand side in the row
     space of S), as x = S^T (S S^T + lam I)^-1 f. Returns (x, info_dict) like dfisher_solve."""
     torch = _torch()
@@ -386,7 +388,7 @@ def dfisher_solve_rowspace(ctx, S, f, lam: float, gram_prec: int = DFISHER_GRAM_
     if x is None:
         x = torch.empty(m, dtype=dt, device=S.device)
     _vec(x, m, dt, "x")
-    opt = _options(gram_prec, sweeps, shift_policy, x_fp64, final_resid)
+    opt = _options(gram_prec, sweeps, shift_policy, x_fp64, final_resid, centered)
     opt.tol = float(tol)
     info = Info()
     st = _lib().dfisher_solve_rowspace(ctx.ptr, _ptr(S), n, m, lds, _ptr(f), float(lam), _ptr(x), ctypes.byref(opt),
@@ -422,7 +424,7 @@ def dfisher_sr_center(ctx, O, S=None, stream=None):
 
 def dfisher_solve_complex(ctx, Z, v, lam: float, gram_prec: int = DFISHER_GRAM_FP32, sweeps: int = 0,
                           shift_policy: int = DFISHER_SHIFT_ON_FAILURE, x_fp64: bool = False, x=None, stream=None,
-                          tol: float = 0.0, final_resid: bool = False):
+                          tol: float = 0.0, final_resid: bool = False, centered: bool = False):
     """x solving (S^H S + lam I) x = v for S = A + iB given as Z = [A; B] (2n x m float32); v complex64
     of length m; x complex64 (or complex128 with x_fp64). Returns (x, info_dict) like dfisher_solve."""
     torch = _torch()
@@ -434,7 +436,7 @@ def dfisher_solve_complex(ctx, Z, v, lam: float, gram_prec: int = DFISHER_GRAM_F
     if x is None:
         x = torch.empty(m, dtype=dt, device=Z.device)
     _vec(x, m, dt, "x")
-    opt = _options(gram_prec, sweeps, shift_policy, x_fp64, final_resid)
+    opt = _options(gram_prec, sweeps, shift_policy, x_fp64, final_resid, centered)
     opt.tol = float(tol)
     info = Info()
     st = _lib().dfisher_solve_complex(ctx.ptr, _ptr(Z), N // 2, m, lds, _ptr(v), float(lam), _ptr(x),
@@ -447,10 +449,11 @@ def dfisher_solve_complex(ctx, Z, v, lam: float, gram_prec: int = DFISHER_GRAM_F
 
 
 def dfisher_factor_create(ctx, S, lam: float, gram_prec: int = DFISHER_GRAM_FP32, sweeps: int = 0,
-                          shift_policy: int = DFISHER_SHIFT_ON_FAILURE, x_fp64: bool = False, stream=None):
+                          shift_policy: int = DFISHER_SHIFT_ON_FAILURE, x_fp64: bool = False, stream=None,
+                          centered: bool = False):
     """Gram + Cholesky once. Returns (factor_handle, info_dict). The handle keeps S alive."""
     n, m, lds = _S_args(S)
-    opt = _options(gram_prec, sweeps, shift_policy, x_fp64)
+    opt = _options(gram_prec, sweeps, shift_policy, x_fp64, centered=centered)
     out = ctypes.c_void_p()
     info = Info()
     _check(_lib().dfisher_factor_create(ctx.ptr, _ptr(S), n, m, lds, float(lam), ctypes.byref(opt), _stream(stream),
@@ -510,7 +513,8 @@ def dfisher_factor_destroy(f) -> None:
 
 
 def dfisher_solve_batched(ctx, S, lams, V, gram_prec: int = DFISHER_GRAM_FP32, sweeps: int = 0,
-                          shift_policy: int = DFISHER_SHIFT_ON_FAILURE, x_fp64: bool = False, X=None, stream=None):
+                          shift_policy: int = DFISHER_SHIFT_ON_FAILURE, x_fp64: bool = False, X=None, stream=None,
+                          centered: bool = False):
     """X[l, r] solves (S^T S + lams[l] I) x = V[r]. Returns (X of shape (nlam, nrhs, m), infos)."""
     torch = _torch()
     n, m, lds = _S_args(S)
@@ -524,7 +528,7 @@ def dfisher_solve_batched(ctx, S, lams, V, gram_prec: int = DFISHER_GRAM_FP32, s
         X = torch.empty((nlam, nrhs, m), dtype=dt, device=S.device)
     if X.dtype != dt or not X.is_contiguous() or tuple(X.shape) != (nlam, nrhs, m):
         raise ValueError("X must be a contiguous (nlam, nrhs, m) tensor of the output dtype")
-    opt = _options(gram_prec, sweeps, shift_policy, x_fp64)
+    opt = _options(gram_prec, sweeps, shift_policy, x_fp64, centered=centered)
     infos = (Info * nlam)()
     _check(_lib().dfisher_solve_batched(ctx.ptr, _ptr(S), n, m, lds, lam_arr, nlam, _ptr(V), nrhs, V.stride(0), _ptr(X),
                                      m, ctypes.byref(opt), _stream(stream), infos), "dfisher_solve_batched")
@@ -533,7 +537,7 @@ def dfisher_solve_batched(ctx, S, lams, V, gram_prec: int = DFISHER_GRAM_FP32, s
 
 def dfisher_solve_uneven(ctx, Ss, vs, lams, gram_prec: int = DFISHER_GRAM_FP32, sweeps: int = 0,
                          shift_policy: int = DFISHER_SHIFT_ON_FAILURE, x_fp64: bool = False, xs=None, stream=None,
-                         final_resid: bool = False, tol: float = 0.0):
+                         final_resid: bool = False, tol: float = 0.0, centered: bool = False):
     """Independent problems of different shapes. Returns (list of x, infos); "converged" is False in
     every info when the library returned DFISHER_E_NOT_CONVERGED (a tolerance, given or automatic,
     missed at some problem's sweep cap; every x is still written)."""
@@ -556,7 +560,7 @@ def dfisher_solve_uneven(ctx, Ss, vs, lams, gram_prec: int = DFISHER_GRAM_FP32, 
     m_arr = I64Arr(*[d[1] for d in dims])
     l_arr = I64Arr(*[d[2] for d in dims])
     lam_arr = (ctypes.c_double * k)(*[float(a) for a in lams])
-    opt = _options(gram_prec, sweeps, shift_policy, x_fp64, final_resid)
+    opt = _options(gram_prec, sweeps, shift_policy, x_fp64, final_resid, centered)
     opt.tol = float(tol)
     infos = (Info * k)()
     st = _lib().dfisher_solve_uneven(ctx.ptr, k, s_arr, n_arr, m_arr, l_arr, v_arr, lam_arr, x_arr, ctypes.byref(opt),

@@ -194,7 +194,7 @@ dfisher_status check_opt(const dfisher_options* opt, dfisher_options* out) {
   if (d.x_fp64 != 0 && d.x_fp64 != 1) return fail(DFISHER_E_INVALID_ARG, "x_fp64 must be 0 or 1");
   if (!std::isfinite(d.tol) || d.tol < 0.0) return fail(DFISHER_E_INVALID_ARG, "tol must be finite and >= 0");
   if (d.final_resid != 0 && d.final_resid != 1) return fail(DFISHER_E_INVALID_ARG, "final_resid must be 0 or 1");
-  if (d.reserved != 0) return fail(DFISHER_E_INVALID_ARG, "reserved must be 0");
+  if ((d.flags & ~DFISHER_CENTERED) != 0) return fail(DFISHER_E_INVALID_ARG, "unknown flags 0x%x", d.flags);
   *out = d;
   return DFISHER_OK;
 }
@@ -217,8 +217,10 @@ dfisher_status check_no_final(const dfisher_options& o) {
 // error can also exceed W's eigenvalue along a few directions (for a column-centered S, the
 // all-ones one, eigenvalue ~ lambda); the conjugate-gradient sweeps remove such directions only
 // after the bulk, which took two or three more sweeps in measurements at m/n = 78 .. 256 (none at
-// m/n ~ 1000), so the count gets 3 more below m/n = 150 and 2 more below m/n = 600. Capped at 16.
-int auto_sweeps(int prec, int64_t n, int64_t m, double tau_rel) {
+// m/n ~ 1000), so the count gets 3 more below m/n = 150 and 2 more below m/n = 600, unless the
+// caller declared S centered (DFISHER_CENTERED), which makes that direction exact in the factored
+// matrix. Capped at 16.
+int auto_sweeps(int prec, int64_t n, int64_t m, double tau_rel, bool centered = false) {
   const double a = (double)m / (double)n;
   const double C = prec == DFISHER_GRAM_MXFP8 ? 0.1 : (prec == DFISHER_GRAM_BF16X3 ? 1e-4 : 1e-5);
   const double gap = a > 4.0 ? (1.0 - 1.0 / std::sqrt(a)) * (1.0 - 1.0 / std::sqrt(a)) : 0.25;
@@ -231,9 +233,11 @@ int auto_sweeps(int prec, int64_t n, int64_t m, double tau_rel) {
     e *= c;
     ++k;
   }
-  if (prec == DFISHER_GRAM_MXFP8) k += a < 150.0 ? 3 : (a < 600.0 ? 2 : 0);
+  if (prec == DFISHER_GRAM_MXFP8 && !centered) k += a < 150.0 ? 3 : (a < 600.0 ? 2 : 0);
   return std::min(k, MAX_SWEEPS);
 }
+
+bool is_centered(const dfisher_options& o) { return (o.flags & DFISHER_CENTERED) != 0; }
 
 // Entry points that run a fixed number of sweeps reject a tolerance.
 dfisher_status check_no_tol(const dfisher_options& o) {
@@ -379,8 +383,10 @@ dfisher_status factor_with_policy(dfisher_ctx* ctx, const double* W, double* L, 
 
 // Row pass (b = S v when v != nullptr, the exact row norms, and for the scaled-FP8 Gram its codes),
 // then the Gram of `prec` reduced into W (lower triangle; upper too if mirror) with lambda added.
+// center: W becomes the centered preconditioner P W P + lambda 1 1^T / n (work: B.zc, B.nq).
 dfisher_status gram_stage(const float* S, const float* v, const dfi::GramPlan& gp, const dfi::RowPassPlan& rp,
-                          const SolveBufs& B, double lambda, double* W, int mirror, hipStream_t st, StageClock* clk) {
+                          const SolveBufs& B, double lambda, double* W, int mirror, hipStream_t st, StageClock* clk,
+                          bool center = false) {
   if (clk) clk->mark(0);
   if (gp.prec == DFISHER_GRAM_MXFP8) {
     HIP_TRY(dfi::rowpass_launch(rp, S, v, nullptr, v != nullptr, true, B.rpart, st, B.q8, B.sc8, B.ldq, true));
@@ -400,6 +406,7 @@ dfisher_status gram_stage(const float* S, const float* v, const dfi::GramPlan& g
   }
   if (clk) clk->mark(2);
   HIP_TRY(dfi::gram_reduce(gp, S, B.gpart, B.d, lambda, W, mirror, st));
+  if (center) HIP_TRY(dfi::gram_project(W, gp.n, 1, lambda, mirror, B.zc, B.nq, st));
   return DFISHER_OK;
 }
 
@@ -857,8 +864,10 @@ dfisher_status uneven_enqueue(dfisher_ctx* ctx, int32_t np, const float* const* 
     B.d = U.d + U.voff[(size_t)p];
     B.ldq = dfi::fp8_ldq(m[p]);
     if (U.gp[(size_t)p].ldh == 0) B.hi = B.lo = nullptr;   // this problem splits inside the tile kernel
+    B.zc = U.zc + U.voff[(size_t)p];   // projection work (free until the refinement)
+    B.nq = U.nq + U.voff[(size_t)p];
     DF_TRY(gram_stage(S[p], v[p], U.gp[(size_t)p], U.rp[(size_t)p], B, lambda[p], U.W + U.woff[(size_t)p], 0, st,
-                      nullptr));
+                      nullptr, is_centered(o)));
     if (o.shift_policy == DFISHER_SHIFT_ALWAYS) {
       double* Wp = U.W + U.woff[(size_t)p];
       const double scale = 2.0 * std::sqrt((double)n[p]) * gram_unit(o.gram_prec, m[p]);
@@ -967,7 +976,7 @@ dfisher_status uneven_solve(dfisher_ctx* ctx, int32_t np, const float* const* S,
     if (autos) {
       const double tau_rel = o.shift_policy == DFISHER_SHIFT_ALWAYS
                                  ? 2.0 * std::sqrt((double)n[p]) * gram_unit(o.gram_prec, m[p]) : 0.0;
-      sw[(size_t)p] = std::min(MAX_SWEEPS, auto_sweeps(o.gram_prec, n[p], m[p], tau_rel) + 2);
+      sw[(size_t)p] = std::min(MAX_SWEEPS, auto_sweeps(o.gram_prec, n[p], m[p], tau_rel, is_centered(o)) + 2);
     }
     max_sw = std::max(max_sw, sw[(size_t)p]);
   }
@@ -1444,7 +1453,7 @@ dfisher_status dfisher_factor_create(dfisher_ctx* ctx, const float* S, int64_t n
     return s;
   };
   {
-    const dfisher_status sg = gram_stage(S, nullptr, gp, rp, B, lambda, B.W, 0, st, nullptr);
+    const dfisher_status sg = gram_stage(S, nullptr, gp, rp, B, lambda, B.W, 0, st, nullptr, is_centered(o));
     if (sg != DFISHER_OK) return cleanup(sg);
   }
   dfisher_info inf{};
@@ -1454,7 +1463,8 @@ dfisher_status dfisher_factor_create(dfisher_ctx* ctx, const float* S, int64_t n
                                        &inf.attempts);
   if (o.sweeps == DFISHER_SWEEPS_AUTO) {   // resolved once, with the factored shift known
     const double wmax = (o.shift_policy != DFISHER_SHIFT_NONE) ? ctx->h_scalar[0] : 0.0;
-    f->opt.sweeps = auto_sweeps(o.gram_prec, n, m, (inf.shift > 0.0 && wmax > 0.0) ? inf.shift / wmax : 0.0);
+    f->opt.sweeps = auto_sweeps(o.gram_prec, n, m, (inf.shift > 0.0 && wmax > 0.0) ? inf.shift / wmax : 0.0,
+                                is_centered(o));
   }
   inf.sweeps_done = f->opt.sweeps;
   if (info) *info = inf;
@@ -1597,7 +1607,7 @@ dfisher_status dfisher_solve(dfisher_ctx* ctx, const float* S, int64_t n, int64_
   B = carve(static_cast<char*>(ctx->ws), n, m, &gp, rp, cp, true, need_t, &fp);
   StageClock clk(ctx, st);
   // one pass over S (b = S v, the exact diagonal |s_i|^2, the FP8 codes if used), then step 1
-  DF_TRY(gram_stage(S, v, gp, rp, B, lambda, B.W, 0, st, &clk));
+  DF_TRY(gram_stage(S, v, gp, rp, B, lambda, B.W, 0, st, &clk, is_centered(o)));
   // step 2 (with the shift policy)
   clk.mark(3);
   dfisher_info inf{};
@@ -1665,7 +1675,7 @@ dfisher_status dfisher_solve_rowspace(dfisher_ctx* ctx, const float* S, int64_t 
   B = carve(static_cast<char*>(ctx->ws), n, m, &gp, rp, cp, true, need_t, &fp);
   StageClock clk(ctx, st);
   // one pass over S for the exact diagonal (and the FP8 codes), then step 1; b = f
-  DF_TRY(gram_stage(S, nullptr, gp, rp, B, lambda, B.W, 0, st, &clk));
+  DF_TRY(gram_stage(S, nullptr, gp, rp, B, lambda, B.W, 0, st, &clk, is_centered(o)));
   HIP_TRY(hipMemcpyAsync(B.b, f, (size_t)n * sizeof(double), hipMemcpyDeviceToDevice, st));
   clk.mark(3);
   dfisher_info inf{};
@@ -1796,6 +1806,9 @@ dfisher_status dfisher_solve_complex(dfisher_ctx* ctx, const float* Z, int64_t n
   StageClock clk(ctx, st);
   // Z Z^T (both triangles, exact FP64 diagonal) and the embedded W
   DF_TRY(gram_stage(Z, nullptr, gp, rp, B, 0.0, X.G, 1, st, &clk));
+  // centered: the indicators of the A and B halves of Z are null vectors of Z Z^T, and those of
+  // the real and imaginary halves of E E^T; projecting Z Z^T makes both exact
+  if (is_centered(o)) HIP_TRY(dfi::gram_project(X.G, N, 2, 0.0, 1, X.Yi, X.Yi + 2 * N, st));
   HIP_TRY(dfi::complex_embed(X.G, n, lambda, B.W, st));
   // b = E v = [A vr - B vi; B vr + A vi] from Z vr and Z vi (one pass over Z)
   HIP_TRY(dfi::deinterleave(v, m, X.vp, st));
@@ -1917,7 +1930,7 @@ dfisher_status dfisher_solve_batched(dfisher_ctx* ctx, const float* S, int64_t n
   layout(static_cast<char*>(ctx->ws), B, Lall, Dall, dkk, dinfo, dflag, mb);
 
   // the shared Gram G = S S^T (exact diagonal, no lambda), formed once
-  DF_TRY(gram_stage(S, nullptr, gp, rp, B, 0.0, B.W, 0, st, nullptr));
+  DF_TRY(gram_stage(S, nullptr, gp, rp, B, 0.0, B.W, 0, st, nullptr, is_centered(o)));
   // every W_l = G + lambda_l I (+ the up-front shift) factored in the same launches
   const double unit = gram_unit(o.gram_prec, m);
   const double scale0 = (o.shift_policy == DFISHER_SHIFT_ALWAYS) ? 2.0 * std::sqrt((double)n) * unit : 0.0;
@@ -1952,7 +1965,8 @@ dfisher_status dfisher_solve_batched(dfisher_ctx* ctx, const float* S, int64_t n
       tau_rel = ctx->h_scalar[0] > 0.0 ? inf.shift / ctx->h_scalar[0] : 0.0;
     }
     if (inf.potrf_info != 0) worst = DFISHER_E_NOT_SPD;
-    if (o.sweeps == DFISHER_SWEEPS_AUTO) sweeps = std::max(sweeps, auto_sweeps(o.gram_prec, n, m, tau_rel));
+    if (o.sweeps == DFISHER_SWEEPS_AUTO)
+      sweeps = std::max(sweeps, auto_sweeps(o.gram_prec, n, m, tau_rel, is_centered(o)));
     linf[(size_t)l] = inf;
   }
   for (int32_t l = 0; l < nlam; ++l) {

@@ -243,6 +243,11 @@ hipError_t pcg_finish(const int64_t* seg, int64_t n, int64_t s0, int64_t s1, con
 // the stacked Z = [Re S; Im S] (2n x m, row stride lds). Real O and S may be the same array.
 hipError_t center_write(const float* O, int64_t n, int64_t m, int64_t ldo, int cplx, const double* t, float* S,
                         int64_t lds, hipStream_t st);
+// Preconditioner of a centered S: W (n x n, FP64, lower triangle; both triangles when full) becomes
+// M = P W P + lambda U U^T, U the normalised indicators of nseg (1 or 2) equal segments. r: nseg * n
+// doubles of work, c: nseg * nseg.
+hipError_t gram_project(double* W, int64_t n, int nseg, double lambda, int full, double* r, double* c,
+                        hipStream_t st);
 hipError_t fill_value(double* y, int64_t n, double value, hipStream_t st);
 // interleaved complex FP32 v (m) -> out[0..m) real parts, out[m..2m) imaginary parts
 hipError_t deinterleave(const float* v, int64_t m, float* out, hipStream_t st);

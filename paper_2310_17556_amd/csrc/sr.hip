@@ -12,6 +12,17 @@
 // from Z Z^T = [[A A^T, A B^T], [B A^T, B B^T]]:
 //   E E^T = [[Wr, -Wi], [Wi, Wr]],  Wr = A A^T + B B^T,  Wi = B A^T - A B^T,
 // and the products with E and E^T are products with Z of two vectors each, combined here.
+//
+// Centered preconditioner: a centered S has 1^T S = 0, so S S^T maps the all-ones vector to zero
+// and W maps it to lambda times itself (for the complex embedding, the indicators of the real and
+// the imaginary halves). A Gram formed from rounded inputs does not: for the scaled-FP8 Gram its
+// error along that direction is ~1e-3 of the diagonal, far above lambda, which leaves the factor a
+// poor preconditioner there and the refinement slow. The factored matrix is therefore
+//   M = P W P + lambda U U^T,  P = I - U U^T,  U = [1_seg / sqrt(l)] for nseg equal segments of l,
+// entrywise M_ij = W_ij - (r_i^(s_j) + r_j^(s_i)) / l + c^(s_i s_j) / l^2 + [s_i = s_j] lambda / l,
+// with r_i^(s) = sum over j in segment s of W_ij and c^(st) = sum over i in s of r_i^(t) (FP64,
+// fixed order). M agrees with W on the complement of the indicators and is exact on them; the
+// refinement still works with the exact W, so only its convergence changes.
 #include "dfisher_internal.h"
 
 #include <algorithm>
@@ -132,6 +143,88 @@ __global__ void complex_apply_kernel(const float* __restrict__ v, const double* 
   }
 }
 
+// r[s n + i] = sum over j in segment s (nseg <= 2: s = [j >= l]) of W_ij, W symmetric and read from its lower
+// triangle: row i up to the diagonal, then column i below it. A workgroup takes 64 rows; wave w
+// sums rows i0 + w, i0 + w + 4, ... along the row (lanes strided, then a fixed butterfly), and all
+// four waves read the column strip below (thread t: column i0 + t % 64, every fourth row from
+// i0 + 1 + t / 64), combined in a fixed order.
+__global__ void __launch_bounds__(256) seg_rowsum_kernel(const double* __restrict__ W, int64_t n, int64_t l, int nseg,
+                                                         double* __restrict__ r) {
+  __shared__ double part[4][64][2];
+  __shared__ double rowp[64][2];
+  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
+  const int64_t i0 = (int64_t)blockIdx.x * 64;
+  for (int k = wave; k < 64; k += 4) {
+    const int64_t i = i0 + k;
+    double a0 = 0.0, a1 = 0.0;
+    if (i < n) {
+      for (int64_t j = lane; j <= i; j += 64) {
+        const double w = W[i * n + j];
+        if (j < l) a0 += w; else a1 += w;
+      }
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+      a0 += __shfl_xor(a0, off);
+      a1 += __shfl_xor(a1, off);
+    }
+    if (lane == 0) {
+      rowp[k][0] = a0;
+      rowp[k][1] = a1;
+    }
+  }
+  const int64_t c = i0 + lane;
+  double b0 = 0.0, b1 = 0.0;
+  if (c < n) {
+    for (int64_t j = i0 + 1 + wave; j < n; j += 4) {
+      if (j <= c) continue;
+      const double w = W[j * n + c];
+      if (j < l) b0 += w; else b1 += w;
+    }
+  }
+  part[wave][lane][0] = b0;
+  part[wave][lane][1] = b1;
+  __syncthreads();
+  if (wave == 0 && c < n) {
+    for (int s = 0; s < nseg; ++s) {
+      const double v = rowp[lane][s] + ((part[0][lane][s] + part[1][lane][s]) + (part[2][lane][s] + part[3][lane][s]));
+      r[(int64_t)s * n + c] = v;
+    }
+  }
+}
+
+// c[s nseg + u] = sum over i in segment s of r[u n + i], one workgroup, fixed order
+__global__ void __launch_bounds__(256) seg_total_kernel(const double* __restrict__ r, int64_t n, int64_t l, int nseg,
+                                                        double* __restrict__ c) {
+  __shared__ double red[256];
+  for (int s = 0; s < nseg; ++s)
+    for (int u = 0; u < nseg; ++u) {
+      double acc = 0.0;
+      for (int64_t i = threadIdx.x; i < l; i += 256) acc += r[(int64_t)u * n + (int64_t)s * l + i];
+      red[threadIdx.x] = acc;
+      __syncthreads();
+      for (int h = 128; h > 0; h >>= 1) {
+        if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+        __syncthreads();
+      }
+      if (threadIdx.x == 0) c[s * nseg + u] = red[0];
+      __syncthreads();
+    }
+}
+
+// W <- M entrywise (lower triangle, or both when full)
+__global__ void __launch_bounds__(256) project_update_kernel(double* __restrict__ W, int64_t n, int64_t l, int nseg,
+                                                             const double* __restrict__ r, const double* __restrict__ c,
+                                                             double lambda, int full, int64_t nb) {
+  const int64_t i = (int64_t)blockIdx.x / nb;
+  const int64_t j = ((int64_t)blockIdx.x - i * nb) * 256 + threadIdx.x;
+  if (j >= n || (!full && j > i)) return;
+  const int64_t si = i < l ? 0 : 1, sj = j < l ? 0 : 1;   // nseg <= 2
+  const double inv = 1.0 / (double)l;
+  double w = W[i * n + j] - (r[sj * n + i] + r[si * n + j]) * inv + c[si * nseg + sj] * (inv * inv);
+  if (si == sj) w += lambda * inv;
+  W[i * n + j] = w;
+}
+
 unsigned blocks(int64_t n, int t) { return (unsigned)((n + t - 1) / t); }
 
 }  // namespace
@@ -144,6 +237,18 @@ hipError_t center_write(const float* O, int64_t n, int64_t m, int64_t ldo, int c
     hipLaunchKernelGGL(center_write_complex_kernel, grid, dim3(CT), 0, st, O, n, m, ldo, t, rn, S, lds);
   else
     hipLaunchKernelGGL(center_write_kernel, grid, dim3(CT), 0, st, O, n, m, ldo, t, rn, S, lds);
+  return hipGetLastError();
+}
+
+hipError_t gram_project(double* W, int64_t n, int nseg, double lambda, int full, double* r, double* c,
+                        hipStream_t st) {
+  if (n < 1 || nseg < 1 || nseg > 2 || n % nseg != 0) return hipErrorInvalidValue;
+  const int64_t l = n / nseg;
+  hipLaunchKernelGGL(seg_rowsum_kernel, dim3(blocks(n, 64)), dim3(256), 0, st, W, n, l, nseg, r);
+  hipLaunchKernelGGL(seg_total_kernel, dim3(1), dim3(256), 0, st, r, n, l, nseg, c);
+  const int64_t nb = (n + 255) / 256;
+  hipLaunchKernelGGL(project_update_kernel, dim3((unsigned)(nb * n)), dim3(256), 0, st, W, n, l, nseg, r, c, lambda,
+                     full, nb);
   return hipGetLastError();
 }
 

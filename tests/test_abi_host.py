@@ -54,8 +54,8 @@ FAKE_CTX = ctypes.c_void_p(0x1000)   # never dereferenced: every call below fail
 FAKE_DEV = ctypes.c_void_p(0x2000)
 
 
-def _opts(dfl, prec=0, sweeps=0, shift=1, x64=0, tol=0.0, final=0, reserved=0):
-    return dfl._Options(prec, sweeps, shift, x64, tol, final, reserved)
+def _opts(dfl, prec=0, sweeps=0, shift=1, x64=0, tol=0.0, final=0, flags=0):
+    return dfl._Options(prec, sweeps, shift, x64, tol, final, flags)
 
 
 def test_invalid_arguments_rejected_on_host(dfl):
@@ -79,7 +79,7 @@ def test_invalid_arguments_rejected_on_host(dfl):
         assert lib.dfisher_solve(FAKE_CTX, P, 4, 8, 8, P, lam, P, None, st, ctypes.byref(info)) == E
     for o in [_opts(dfl, prec=5), _opts(dfl, sweeps=-2), _opts(dfl, sweeps=17), _opts(dfl, shift=3),
               _opts(dfl, x64=2), _opts(dfl, tol=-1e-9), _opts(dfl, tol=float("nan")), _opts(dfl, tol=float("inf")),
-              _opts(dfl, final=2), _opts(dfl, reserved=1)]:
+              _opts(dfl, final=2), _opts(dfl, flags=2), _opts(dfl, flags=-1)]:
         assert lib.dfisher_solve(FAKE_CTX, P, 4, 8, 8, P, 1.0, P, ctypes.byref(o), st, None) == E
     assert lib.dfisher_solve(FAKE_CTX, P, 4, 8, 8, None, 1.0, P, None, st, None) == E
     assert lib.dfisher_solve(FAKE_CTX, P, 4, 8, 8, P, 1.0, None, None, st, None) == E
