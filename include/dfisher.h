@@ -127,8 +127,9 @@ typedef struct dfisher_options {
  * opt->sweeps = DFISHER_SWEEPS_AUTO lets the library choose the sweep count.
  *   dfisher_solve: measured. After each sweep's residual rho_k = |r_k| / |S v| (one stream
  *     synchronisation per sweep) the correction is applied, and the sweeps stop once the
- *     residual expected of the corrected iterate, rho_k * max(0.1, min(1, rho_k / rho_{k-1}))
- *     with rho_{-1} = 1, is <= opt->tol (1e-7 when opt->tol is 0); at most 16 sweeps, else
+ *     residual expected of the corrected iterate, rho_k * max(f, min(1, rho_k / rho_{k-1}))
+ *     with rho_{-1} = 1 and f = 0.1 (0.01 with DFISHER_CENTERED, whose projected factor leaves no
+ *     stagnating direction), is <= opt->tol (1e-7 when opt->tol is 0); at most 16 sweeps, else
  *     DFISHER_E_NOT_CONVERGED with x written. info->resid is the last rho_k.
  *   dfisher_solve_uneven: measured on the device, per problem, inside the captured launch
  *     sequence (no host round trip): the same predictive test as dfisher_solve after each sweep,

@@ -57,6 +57,9 @@ dfisher_status fail(dfisher_status s, const char* fmt, ...) {
 constexpr int MAX_SWEEPS = 16;
 constexpr double AUTO_TOL = 1e-7;   // the residual DFISHER_SWEEPS_AUTO aims for in dfisher_solve
 constexpr double AUTO_MIN_CONTRACTION = 0.1;   // least contraction a predictive stop assumes
+// ... when S is declared centered: the projected factor has no stagnating direction left, and one
+// sweep contracts the residual by 1e-3 .. 1e-2 (measured at m/n 100 .. 1000)
+constexpr double AUTO_MIN_CONTRACTION_CENTERED = 0.01;
 constexpr int MAX_SHIFT_ATTEMPTS = 10;
 
 size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -238,6 +241,9 @@ int auto_sweeps(int prec, int64_t n, int64_t m, double tau_rel, bool centered = 
 }
 
 bool is_centered(const dfisher_options& o) { return (o.flags & DFISHER_CENTERED) != 0; }
+double auto_floor(const dfisher_options& o) {
+  return is_centered(o) ? AUTO_MIN_CONTRACTION_CENTERED : AUTO_MIN_CONTRACTION;
+}
 
 // Entry points that run a fixed number of sweeps reject a tolerance.
 dfisher_status check_no_tol(const dfisher_options& o) {
@@ -440,18 +446,19 @@ dfisher_status w_pass(const float* S, int64_t n, int64_t m, int64_t lds, double 
 // rho = |r| / |b| (one synchronisation; from sweep 2 on r is the iteration's recurrence), apply
 // the correction and stop once rho <= tol. *done and *resid report the sweeps run and the last
 // rho (-1 if none was measured).
-// With `predict` the stop test is on the residual the corrected iterate is expected to have:
+// With predict > 0 the stop test is on the residual the corrected iterate is expected to have:
 // rho_k times the contraction measured over the last sweep, rho_k / rho_{k-1} (rho_{-1} = 1, the
-// residual of y = 0), but never less than AUTO_MIN_CONTRACTION times rho_k, so that the call
-// stops only once a measured residual is <= tol / AUTO_MIN_CONTRACTION: the measured contraction
-// of one sweep can hide a slower direction (the all-ones one above).
+// residual of y = 0), but never less than predict times rho_k (AUTO_MIN_CONTRACTION, or
+// AUTO_MIN_CONTRACTION_CENTERED for a declared centered S), so that the call stops only once a
+// measured residual is <= tol / predict: the measured contraction of one sweep can hide a slower
+// direction (the all-ones one above, unless the factor was projected).
 // The sweeps of solve_y for any operator: wop(u, rhs, out) enqueues out = rhs - W u (length n).
 using WOp = std::function<dfisher_status(const double* u, const double* rhs, double* out)>;
 
 dfisher_status solve_y_op(int64_t n, const double* L, const double* Dinv, const SolveBufs& B, int sweeps,
                           hipStream_t st, const WOp& wop, StageClock* clk = nullptr, dfisher_ctx* ctx = nullptr,
                           double tol = 0.0, int* done = nullptr, double* resid = nullptr, bool initial = true,
-                          bool predict = false, bool* met = nullptr) {
+                          double predict = 0.0, bool* met = nullptr) {
   if (initial) {   // (else the caller has formed y = L^-T L^-1 b already)
     HIP_TRY(dfi::trsv_launch(L, Dinv, n, 0, B.b, B.z, B.tw, st));
     HIP_TRY(dfi::trsv_launch(L, Dinv, n, 1, B.z, B.y, B.tw, st));
@@ -484,7 +491,7 @@ dfisher_status solve_y_op(int64_t n, const double* L, const double* Dinv, const 
       bool stop = s >= sweeps;
       if (measure) {
         const double expect =
-            predict ? rho * std::max(AUTO_MIN_CONTRACTION, std::min(1.0, prev > 0.0 ? rho / prev : 0.0)) : rho;
+            predict > 0.0 ? rho * std::max(predict, std::min(1.0, prev > 0.0 ? rho / prev : 0.0)) : rho;
         prev = rho;
         if (expect <= tol) {
           if (met) *met = true;
@@ -510,7 +517,7 @@ dfisher_status solve_y(const float* S, int64_t n, int64_t m, int64_t lds, double
                        const double* Dinv, const SolveBufs& B, const dfi::RowPassPlan& rp, const dfi::ColPassPlan& cp,
                        int sweeps, hipStream_t st, StageClock* clk = nullptr, const dfi::RefinePassPlan* fp = nullptr,
                        dfisher_ctx* ctx = nullptr, double tol = 0.0, int* done = nullptr, double* resid = nullptr,
-                       bool initial = true, bool predict = false, bool* met = nullptr) {
+                       bool initial = true, double predict = 0.0, bool* met = nullptr) {
   const WOp wop = [&](const double* u, const double* rhs, double* out) {
     return w_pass(S, n, m, lds, lambda, u, rhs, out, B, rp, cp, fp, st);
   };
@@ -921,7 +928,7 @@ dfisher_status uneven_enqueue(dfisher_ctx* ctx, int32_t np, const float* const* 
     c.resid = U.resid;
     c.met = U.met;
     c.tol = tol;
-    c.floor = AUTO_MIN_CONTRACTION;
+    c.floor = auto_floor(o);
     c.predict = predict ? 1 : 0;
     HIP_TRY(dfi::pcg_control_init(np, c, st));
     HIP_TRY(dfi::fill_zero(U.zero, U.nmax, st));
@@ -1635,7 +1642,7 @@ dfisher_status dfisher_solve(dfisher_ctx* ctx, const float* S, int64_t n, int64_
   double resid = -1.0;
   bool met = false;
   DF_TRY(solve_y(S, n, m, lds, lambda, B.L, B.Dinv, B, rp, cp, sweeps, st, &clk, &fp, ctx, tol, &done, &resid,
-                 false, autos, &met));
+                 false, autos ? auto_floor(o) : 0.0, &met));
   inf.w_resid = -1.0;
   if (o.final_resid) DF_TRY(final_residual(ctx, S, n, m, lds, lambda, B, rp, cp, fp, st, &inf.w_resid));
   HIP_TRY(dfi::colpass_launch(cp, S, n, m, lds, B.y, v, lambda, x, o.x_fp64, B.cpart, st));
@@ -1699,7 +1706,7 @@ dfisher_status dfisher_solve_rowspace(dfisher_ctx* ctx, const float* S, int64_t 
   double resid = -1.0;
   bool met = false;
   DF_TRY(solve_y(S, n, m, lds, lambda, B.L, B.Dinv, B, rp, cp, sweeps, st, &clk, &fp, ctx, tol, &done, &resid,
-                 false, autos, &met));
+                 false, autos ? auto_floor(o) : 0.0, &met));
   inf.w_resid = -1.0;
   if (o.final_resid) DF_TRY(final_residual(ctx, S, n, m, lds, lambda, B, rp, cp, fp, st, &inf.w_resid));
   // x = S^T y, rounded once (FP32) or kept in FP64
@@ -1856,7 +1863,8 @@ dfisher_status dfisher_solve_complex(dfisher_ctx* ctx, const float* Z, int64_t n
   int done = 0;
   double resid = -1.0;
   bool met = false;
-  DF_TRY(solve_y_op(N, B.L, B.Dinv, B, sweeps, st, wop, &clk, ctx, tol, &done, &resid, true, autos, &met));
+  DF_TRY(solve_y_op(N, B.L, B.Dinv, B, sweeps, st, wop, &clk, ctx, tol, &done, &resid, true,
+                    autos ? auto_floor(o) : 0.0, &met));
   inf.w_resid = -1.0;
   if (o.final_resid) {
     DF_TRY(wop(B.y, B.b, B.r));
