@@ -112,10 +112,13 @@ typedef struct dfisher_options {
  * the flag the factored matrix is the computed W with that direction made exact,
  *     M = P W P + lambda 1 1^T / n,   P = I - 1 1^T / n   (FP64, before the Cholesky),
  * and for dfisher_solve_complex the same with the indicators of the A and B halves of Z (the real
- * and imaginary halves of the real embedding). The refinement sweeps still use the exact W, so the
- * result is the solution of Eq. 1 whether or not the declaration holds; only the convergence of
- * the sweeps (and the sweeps-0 result, which is then M^-1 rather than the computed W^-1) changes.
- * Honoured by dfisher_solve, _rowspace, _complex, _batched, _uneven and dfisher_factor_create. */
+ * and imaginary halves of the real embedding). The declaration is checked against the computed
+ * Gram on the device: when its Rayleigh quotient along an indicator (less lambda) exceeds 1 % of
+ * its mean diagonal, S is plainly not centered and W is factored unchanged (the result is then
+ * bitwise that of the call without the flag). The refinement sweeps use the exact W either way,
+ * so only their convergence (and the sweeps-0 result, M^-1 rather than the computed W^-1) depends
+ * on the flag. Honoured by dfisher_solve, _rowspace, _complex, _batched, _uneven and
+ * dfisher_factor_create. */
 #define DFISHER_CENTERED 1
 
 /* Refinement sweeps. Each sweep reads S once. Sweep 1 forms the FP64 residual r = S v - lambda y

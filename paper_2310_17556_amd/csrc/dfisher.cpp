@@ -389,7 +389,8 @@ dfisher_status factor_with_policy(dfisher_ctx* ctx, const double* W, double* L, 
 
 // Row pass (b = S v when v != nullptr, the exact row norms, and for the scaled-FP8 Gram its codes),
 // then the Gram of `prec` reduced into W (lower triangle; upper too if mirror) with lambda added.
-// center: W becomes the centered preconditioner P W P + lambda 1 1^T / n (work: B.zc, B.nq).
+// center: W becomes the centered preconditioner P W P + lambda 1 1^T / n (work: B.gpart, B.zc), unless
+// W itself shows that S is far from centered.
 dfisher_status gram_stage(const float* S, const float* v, const dfi::GramPlan& gp, const dfi::RowPassPlan& rp,
                           const SolveBufs& B, double lambda, double* W, int mirror, hipStream_t st, StageClock* clk,
                           bool center = false) {
@@ -412,7 +413,10 @@ dfisher_status gram_stage(const float* S, const float* v, const dfi::GramPlan& g
   }
   if (clk) clk->mark(2);
   HIP_TRY(dfi::gram_reduce(gp, S, B.gpart, B.d, lambda, W, mirror, st));
-  if (center) HIP_TRY(dfi::gram_project(W, gp.n, 1, lambda, mirror, B.zc, B.nq, st));
+  if (center) {   // the Gram partials are free again: they hold the projection's tile sums
+    if (gp.part_bytes < dfi::gram_project_work_bytes(gp.n)) return fail(DFISHER_E_DEVICE, "projection work too small");
+    HIP_TRY(dfi::gram_project(W, gp.n, 1, lambda, mirror, reinterpret_cast<double*>(B.gpart), B.zc, st));
+  }
   return DFISHER_OK;
 }
 
@@ -872,7 +876,6 @@ dfisher_status uneven_enqueue(dfisher_ctx* ctx, int32_t np, const float* const* 
     B.ldq = dfi::fp8_ldq(m[p]);
     if (U.gp[(size_t)p].ldh == 0) B.hi = B.lo = nullptr;   // this problem splits inside the tile kernel
     B.zc = U.zc + U.voff[(size_t)p];   // projection work (free until the refinement)
-    B.nq = U.nq + U.voff[(size_t)p];
     DF_TRY(gram_stage(S[p], v[p], U.gp[(size_t)p], U.rp[(size_t)p], B, lambda[p], U.W + U.woff[(size_t)p], 0, st,
                       nullptr, is_centered(o)));
     if (o.shift_policy == DFISHER_SHIFT_ALWAYS) {
@@ -1815,7 +1818,10 @@ dfisher_status dfisher_solve_complex(dfisher_ctx* ctx, const float* Z, int64_t n
   DF_TRY(gram_stage(Z, nullptr, gp, rp, B, 0.0, X.G, 1, st, &clk));
   // centered: the indicators of the A and B halves of Z are null vectors of Z Z^T, and those of
   // the real and imaginary halves of E E^T; projecting Z Z^T makes both exact
-  if (is_centered(o)) HIP_TRY(dfi::gram_project(X.G, N, 2, 0.0, 1, X.Yi, X.Yi + 2 * N, st));
+  if (is_centered(o)) {
+    if (gp.part_bytes < dfi::gram_project_work_bytes(N)) return fail(DFISHER_E_DEVICE, "projection work too small");
+    HIP_TRY(dfi::gram_project(X.G, N, 2, 0.0, 1, reinterpret_cast<double*>(B.gpart), X.Yi, st));
+  }
   HIP_TRY(dfi::complex_embed(X.G, n, lambda, B.W, st));
   // b = E v = [A vr - B vi; B vr + A vi] from Z vr and Z vi (one pass over Z)
   HIP_TRY(dfi::deinterleave(v, m, X.vp, st));

@@ -244,9 +244,12 @@ hipError_t pcg_finish(const int64_t* seg, int64_t n, int64_t s0, int64_t s1, con
 hipError_t center_write(const float* O, int64_t n, int64_t m, int64_t ldo, int cplx, const double* t, float* S,
                         int64_t lds, hipStream_t st);
 // Preconditioner of a centered S: W (n x n, FP64, lower triangle; both triangles when full) becomes
-// M = P W P + lambda U U^T, U the normalised indicators of nseg (1 or 2) equal segments. r: nseg * n
-// doubles of work, c: nseg * nseg.
-hipError_t gram_project(double* W, int64_t n, int nseg, double lambda, int full, double* r, double* c,
+// M = P W P + lambda U U^T, U the normalised indicators of nseg (1 or 2) equal segments, unless
+// W's Rayleigh quotient along an indicator (less lambda) exceeds 1 % of its mean diagonal (then W
+// is left unchanged: S is not centered). work: gram_project_work_bytes(n) bytes (tile partials
+// and totals), r: nseg * n doubles.
+size_t gram_project_work_bytes(int64_t n);
+hipError_t gram_project(double* W, int64_t n, int nseg, double lambda, int full, double* work, double* r,
                         hipStream_t st);
 hipError_t fill_value(double* y, int64_t n, double value, hipStream_t st);
 // interleaved complex FP32 v (m) -> out[0..m) real parts, out[m..2m) imaginary parts

@@ -22,7 +22,8 @@
 // entrywise M_ij = W_ij - (r_i^(s_j) + r_j^(s_i)) / l + c^(s_i s_j) / l^2 + [s_i = s_j] lambda / l,
 // with r_i^(s) = sum over j in segment s of W_ij and c^(st) = sum over i in s of r_i^(t) (FP64,
 // fixed order). M agrees with W on the complement of the indicators and is exact on them; the
-// refinement still works with the exact W, so only its convergence changes.
+// refinement still works with the exact W, so only its convergence changes. W is left as it is
+// when the computed Gram is far from centered along an indicator (project_update_kernel).
 #include "dfisher_internal.h"
 
 #include <algorithm>
@@ -143,78 +144,104 @@ __global__ void complex_apply_kernel(const float* __restrict__ v, const double* 
   }
 }
 
-// r[s n + i] = sum over j in segment s (nseg <= 2: s = [j >= l]) of W_ij, W symmetric and read from its lower
-// triangle: row i up to the diagonal, then column i below it. A workgroup takes 64 rows; wave w
-// sums rows i0 + w, i0 + w + 4, ... along the row (lanes strided, then a fixed butterfly), and all
-// four waves read the column strip below (thread t: column i0 + t % 64, every fourth row from
-// i0 + 1 + t / 64), combined in a fixed order.
-__global__ void __launch_bounds__(256) seg_rowsum_kernel(const double* __restrict__ W, int64_t n, int64_t l, int nseg,
-                                                         double* __restrict__ r) {
-  __shared__ double part[4][64][2];
-  __shared__ double rowp[64][2];
-  const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-  const int64_t i0 = (int64_t)blockIdx.x * 64;
-  for (int k = wave; k < 64; k += 4) {
-    const int64_t i = i0 + k;
-    double a0 = 0.0, a1 = 0.0;
-    if (i < n) {
-      for (int64_t j = lane; j <= i; j += 64) {
-        const double w = W[i * n + j];
-        if (j < l) a0 += w; else a1 += w;
-      }
-    }
-    for (int off = 32; off > 0; off >>= 1) {
-      a0 += __shfl_xor(a0, off);
-      a1 += __shfl_xor(a1, off);
-    }
-    if (lane == 0) {
-      rowp[k][0] = a0;
-      rowp[k][1] = a1;
-    }
+// Segment row sums r[s n + i] = sum over j in segment s (nseg <= 2: s = [j >= l]) of W_ij, W
+// symmetric and read from its lower triangle, in two fixed-order steps. tile_sums_kernel: one
+// workgroup per 64 x 64 tile (ti >= tj) of the lower triangle writes, per segment, the sums of
+// its rows (over its columns j <= i) and of its columns (over its rows i > j, the transposed
+// half); seg_reduce_kernel then adds, for row i of tile row I, the row sums of tiles (I, 0 .. I)
+// and the column sums of tiles (I .. T - 1, I), in that order.
+__global__ void __launch_bounds__(256) tile_sums_kernel(const double* __restrict__ W, int64_t n, int64_t l,
+                                                        double* __restrict__ part) {
+  __shared__ double tile[64][65];
+  const int64_t t = blockIdx.x;
+  int64_t ti = (int64_t)((sqrt(8.0 * (double)t + 1.0) - 1.0) * 0.5);
+  while ((ti + 1) * (ti + 2) / 2 <= t) ++ti;
+  while (ti * (ti + 1) / 2 > t) --ti;
+  const int64_t tj = t - ti * (ti + 1) / 2;
+  for (int e = threadIdx.x; e < 64 * 64; e += 256) {
+    const int a = e >> 6, b = e & 63;
+    const int64_t i = ti * 64 + a, j = tj * 64 + b;
+    tile[a][b] = (i < n && j <= i) ? W[i * n + j] : 0.0;
   }
-  const int64_t c = i0 + lane;
-  double b0 = 0.0, b1 = 0.0;
-  if (c < n) {
-    for (int64_t j = i0 + 1 + wave; j < n; j += 4) {
-      if (j <= c) continue;
-      const double w = W[j * n + c];
-      if (j < l) b0 += w; else b1 += w;
-    }
-  }
-  part[wave][lane][0] = b0;
-  part[wave][lane][1] = b1;
   __syncthreads();
-  if (wave == 0 && c < n) {
-    for (int s = 0; s < nseg; ++s) {
-      const double v = rowp[lane][s] + ((part[0][lane][s] + part[1][lane][s]) + (part[2][lane][s] + part[3][lane][s]));
-      r[(int64_t)s * n + c] = v;
+  const int k = threadIdx.x & 63;
+  if (threadIdx.x < 64) {            // row k of the tile, over its columns
+    double a0 = 0.0, a1 = 0.0;
+    for (int b = 0; b < 64; ++b) {
+      const double w = tile[k][b];
+      if (tj * 64 + b < l) a0 += w; else a1 += w;
     }
+    part[(t * 4 + 0) * 64 + k] = a0;
+    part[(t * 4 + 1) * 64 + k] = a1;
+  } else if (threadIdx.x < 128) {    // column k of the tile, over its rows strictly below the diagonal
+    double a0 = 0.0, a1 = 0.0;
+    const int a_first = (ti == tj) ? k + 1 : 0;
+    for (int a = a_first; a < 64; ++a) {
+      const double w = tile[a][k];
+      if (ti * 64 + a < l) a0 += w; else a1 += w;
+    }
+    part[(t * 4 + 2) * 64 + k] = a0;
+    part[(t * 4 + 3) * 64 + k] = a1;
   }
 }
 
-// c[s nseg + u] = sum over i in segment s of r[u n + i], one workgroup, fixed order
-__global__ void __launch_bounds__(256) seg_total_kernel(const double* __restrict__ r, int64_t n, int64_t l, int nseg,
-                                                        double* __restrict__ c) {
+__global__ void __launch_bounds__(256) seg_reduce_kernel(const double* __restrict__ part, int64_t n, int64_t T,
+                                                         int nseg, double* __restrict__ r) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  const int64_t I = i >> 6;
+  const int a = (int)(i & 63);
+  for (int s = 0; s < nseg; ++s) {
+    double acc = 0.0;
+    for (int64_t J = 0; J <= I; ++J) acc += part[((I * (I + 1) / 2 + J) * 4 + s) * 64 + a];
+    for (int64_t K = I; K < T; ++K) acc += part[((K * (K + 1) / 2 + I) * 4 + 2 + s) * 64 + a];
+    r[(int64_t)s * n + i] = acc;
+  }
+}
+
+// c[s nseg + u] = sum over i in segment s of r[u n + i], and c[nseg nseg] = trace(W); one
+// workgroup, fixed order
+__device__ __forceinline__ double block_sum256(double v, double* red) {
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+    __syncthreads();
+  }
+  const double t = red[0];
+  __syncthreads();
+  return t;
+}
+
+__global__ void __launch_bounds__(256) seg_total_kernel(const double* __restrict__ W, const double* __restrict__ r,
+                                                        int64_t n, int64_t l, int nseg, double* __restrict__ c) {
   __shared__ double red[256];
   for (int s = 0; s < nseg; ++s)
     for (int u = 0; u < nseg; ++u) {
       double acc = 0.0;
       for (int64_t i = threadIdx.x; i < l; i += 256) acc += r[(int64_t)u * n + (int64_t)s * l + i];
-      red[threadIdx.x] = acc;
-      __syncthreads();
-      for (int h = 128; h > 0; h >>= 1) {
-        if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
-        __syncthreads();
-      }
-      if (threadIdx.x == 0) c[s * nseg + u] = red[0];
-      __syncthreads();
+      const double t = block_sum256(acc, red);
+      if (threadIdx.x == 0) c[s * nseg + u] = t;
     }
+  double acc = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += 256) acc += W[i * n + i];
+  const double t = block_sum256(acc, red);
+  if (threadIdx.x == 0) c[nseg * nseg] = t;
 }
 
-// W <- M entrywise (lower triangle, or both when full)
+// W <- M entrywise (lower triangle, or both when full), unless the declaration is implausible:
+// the computed Gram's Rayleigh quotient along some indicator, c_ss / l - lambda, exceeds
+// CENTER_GUARD times its mean diagonal. For a centered S that quotient is the Gram's rounding
+// error along the indicator (about 1e-3 of the diagonal for the scaled-FP8 Gram); a clearly
+// non-centered S would otherwise get a factor that is exact nowhere near W along it.
+constexpr double CENTER_GUARD = 0.01;
+
 __global__ void __launch_bounds__(256) project_update_kernel(double* __restrict__ W, int64_t n, int64_t l, int nseg,
                                                              const double* __restrict__ r, const double* __restrict__ c,
                                                              double lambda, int full, int64_t nb) {
+  const double dbar = c[nseg * nseg] / (double)n - lambda;
+  for (int s = 0; s < nseg; ++s)
+    if (!(c[s * nseg + s] / (double)l - lambda <= CENTER_GUARD * dbar)) return;
   const int64_t i = (int64_t)blockIdx.x / nb;
   const int64_t j = ((int64_t)blockIdx.x - i * nb) * 256 + threadIdx.x;
   if (j >= n || (!full && j > i)) return;
@@ -240,12 +267,20 @@ hipError_t center_write(const float* O, int64_t n, int64_t m, int64_t ldo, int c
   return hipGetLastError();
 }
 
-hipError_t gram_project(double* W, int64_t n, int nseg, double lambda, int full, double* r, double* c,
+size_t gram_project_work_bytes(int64_t n) {
+  const int64_t T = (n + 63) / 64;
+  return ((size_t)(T * (T + 1) / 2) * 4 * 64 + 8) * sizeof(double);
+}
+
+hipError_t gram_project(double* W, int64_t n, int nseg, double lambda, int full, double* work, double* r,
                         hipStream_t st) {
   if (n < 1 || nseg < 1 || nseg > 2 || n % nseg != 0) return hipErrorInvalidValue;
   const int64_t l = n / nseg;
-  hipLaunchKernelGGL(seg_rowsum_kernel, dim3(blocks(n, 64)), dim3(256), 0, st, W, n, l, nseg, r);
-  hipLaunchKernelGGL(seg_total_kernel, dim3(1), dim3(256), 0, st, r, n, l, nseg, c);
+  const int64_t T = (n + 63) / 64;
+  double* c = work + (size_t)(T * (T + 1) / 2) * 4 * 64;   // nseg^2 totals and the trace
+  hipLaunchKernelGGL(tile_sums_kernel, dim3((unsigned)(T * (T + 1) / 2)), dim3(256), 0, st, W, n, l, work);
+  hipLaunchKernelGGL(seg_reduce_kernel, dim3(blocks(n, 256)), dim3(256), 0, st, work, n, T, nseg, r);
+  hipLaunchKernelGGL(seg_total_kernel, dim3(1), dim3(256), 0, st, W, r, n, l, nseg, c);
   const int64_t nb = (n + 255) / 256;
   hipLaunchKernelGGL(project_update_kernel, dim3((unsigned)(nb * n)), dim3(256), 0, st, W, n, l, nseg, r, c, lambda,
                      full, nb);
