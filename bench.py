@@ -464,6 +464,7 @@ def main() -> int:
     ap.add_argument("--leg-sweeps", type=_sweeps_arg, default=-1,
                     help="refinement sweeps of the batched and uneven legs (default 'auto': the a-priori count "
                          "per problem shape)")
+    ap.add_argument("--no-auto", action="store_true", help="skip the DFISHER_SWEEPS_AUTO run of the main workload")
     ap.add_argument("--no-centered", action="store_true",
                     help="do not declare S centered (the workloads' S is column-centered; the declaration "
                          "makes the factored matrix exact along the all-ones direction)")
@@ -537,7 +538,7 @@ def main() -> int:
         log(f"[bench] fp32: {fp32['solves_per_s']:.3f} solves/s, gram {g32avg:.2f} ms")
 
     auto = None
-    if args.sweeps >= 0:
+    if args.sweeps >= 0 and not args.no_auto:
         log("[bench] same path with DFISHER_SWEEPS_AUTO (measured residuals): 1 step")
         xba = {lam: torch.empty(m, dtype=torch.float32, device=dev) for lam in lams}
         eau, gau, stau, infau = run_path(dfl, ctx, S, v, lams, args.prec, -1, 1, 0, xba, args.shift)
