@@ -1529,7 +1529,7 @@ dfisher_status dfisher_factor_solve_noalloc(const dfisher_factor* f, const float
   const int sweeps = f->opt.sweeps;
   const dfi::RowPassPlan rp = dfi::rowpass_plan(n, m, lds);
   const dfi::ColPassPlan cp = dfi::colpass_plan(n, m);
-  const dfi::RefinePassPlan fp = dfi::refine_pass_plan(n, m, lds, f->S);
+  const dfi::RefinePassPlan fp = dfi::refine_pass_plan(n, m, lds, f->S, false);   // small workspace
   if (sweeps > 0 && !fp.usable)
     return fail(DFISHER_E_UNSUPPORTED, "the no-alloc solve refines with the one-read product only: it needs "
                 "n <= 4096, m >= 16 and 16-byte aligned rows of S (n = %lld, lds = %lld)", (long long)n,

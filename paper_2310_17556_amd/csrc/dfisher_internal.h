@@ -101,15 +101,24 @@ struct RefinePassPlan {
   int64_t n;
   int nch;            // 16-byte loads per lane and block (8, 16 or 32)
   bool usable;
-  int64_t ngroups;    // workgroups (one per compute unit)
-  bool tail;          // m % 16 != 0: one more partial group for the last columns
-  size_t part_bytes;  // (ngroups + tail) * n * 8
+  int64_t ngroups;    // workgroups (one per compute unit, or per compute unit and row half)
+  bool tail;          // m % block width != 0: one more partial group for the last columns
+  bool line;          // whole-line kernels: 32-column blocks (8 lanes per 128-byte row piece)
+  int lnch;           // line, not split: loads per lane (8, 16, 32 for n <= 512, 1024, 2048)
+  bool split;         // line, rows split over workgroup pairs (2048 < n <= 4096)
+  int64_t R;          // line: blocks per workgroup (per pair when split)
+  size_t xch_off;     // split: offset (doubles) of the exchanged column partials in part
+  size_t prog_off;    // split: offset (doubles) of the pairs' progress counters (ints)
+  size_t part_bytes;  // (ngroups + tail) * n * 8 (+ the split's exchange buffers)
 };
-RefinePassPlan refine_pass_plan(int64_t n, int64_t m, int64_t lds, const float* S);
+// split_ok = false keeps the one-workgroup-per-block kernel (smaller workspace)
+RefinePassPlan refine_pass_plan(int64_t n, int64_t m, int64_t lds, const float* S, bool split_ok = true);
 // skip (device int, may be null): when *skip != 0 at run time the kernels return at once (a
-// problem whose refinement stopped, in a launch sequence fixed in advance).
+// problem whose refinement stopped, in a launch sequence fixed in advance). spin: the split
+// kernel's bound on polls for its partner's partials (< 0: the default; 0: always compute them).
 hipError_t refine_pass_launch(const RefinePassPlan& p, const float* S, int64_t n, int64_t m, int64_t lds,
-                              const double* y, double* part, hipStream_t st, const int* skip = nullptr);
+                              const double* y, double* part, hipStream_t st, const int* skip = nullptr,
+                              int spin = -1);
 hipError_t refine_pass_reduce(const RefinePassPlan& p, const double* part, double* r, const double* b,
                               const double* y, double lam, hipStream_t st, const int* skip = nullptr);
 

@@ -14,6 +14,8 @@
 //            workgroups and FP64 partials are added in fixed order by a finalize kernel.
 #include "dfisher_internal.h"
 
+#include <cstdlib>
+
 #include <algorithm>
 
 namespace dfi {
@@ -573,30 +575,206 @@ refine_pass_kernel(const float* __restrict__ S, int64_t n, int64_t m, int64_t ld
   }
 }
 
-// The last m % 16 (< 16) columns of the fused pass, as one more group of partials: t_c = sum_i
-// S_ic y_i for those columns (per-thread FP64 partials over rows tid, tid + 256, ..., then added in
-// fixed order through LDS), then part[i] = sum_c S_ic t_c. One workgroup of 256 threads.
+// ------------------------------------------------------------ fused refinement pass, whole lines
+// The same product u = S (S^T y) with whole 128-byte lines: a block is 32 columns, a row's 128
+// bytes are read by 8 lanes (16 bytes each), and a workgroup holds NCH loads per lane, 64 NCH
+// rows. For n <= 64 NCH (NCH = 8, 16, 32 for n <= 512, 1024, 2048) one workgroup holds a whole
+// block, and the workgroups walk contiguous regions of blocks. For 2048 < n <= 4096 (SPLIT)
+// the two workgroups of a pair (one XCD: w and w + 8) hold its two row halves in
+// registers (rows [0, 2048) and [2048, n); 32 loads of 16 bytes per lane, a row's 128 bytes over 8
+// lanes). Each half's column partials t_c^(h) = sum over its rows of S_ic y_i are formed in a fixed
+// order (lanes, then waves through LDS) and published in global memory with a progress counter;
+// the workgroup waits, bounded, for its partner's, and both form t_c = t_c^(0) + t_c^(1) (same bits
+// in both). A wait that runs out (the partner not resident, or far behind) is not an error: the
+// workgroup computes the partner's partial itself from S, in the same order, so the result never
+// depends on timing. Every block's partials have their own slot (nothing is overwritten during a
+// launch), and the counters are cleared before each launch. Rows of the other half get zero
+// partials, so the fixed-order reduction over workgroups is unchanged.
+constexpr int FS_COLS = 32;
+constexpr int FS_HALF = 2048;        // rows of the first half (64 rows per load step x 32 loads)
+constexpr int FS_SPIN = 4096;        // polls (s_sleep 2 each, ~0.2 ms in all) before computing it here
+
+template <int NCH, bool SPLIT>
+__global__ void __launch_bounds__(64 * FR_WAVES)
+refine_line_kernel(const float* __restrict__ S, int64_t n, int64_t m, int64_t lds, const double* __restrict__ y,
+                   double* __restrict__ part, double* __restrict__ xch, int* __restrict__ prog, int64_t R,
+                   int spin, const int* __restrict__ skip) {
+  constexpr int ROWS = 8 * FR_WAVES;   // rows per load step of the workgroup (8 per wave)
+  static_assert(!SPLIT || NCH * ROWS == FS_HALF, "a split block's first half is one workgroup's rows");
+  if (skip && *skip) return;
+  __shared__ double ys[ROWS * NCH];
+  __shared__ double tp[FR_WAVES][FS_COLS];
+  __shared__ double tf[FS_COLS];
+  __shared__ int got;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int q = lane & 7;                       // columns 4 q .. 4 q + 3 of the block
+  const int rloc = wave * 8 + (lane >> 3);      // row within a load step
+  const int64_t w = blockIdx.x;
+  // SPLIT: pair of two members on one XCD; else every workgroup walks its own region
+  const int64_t pair = SPLIT ? (w & 7) * (gridDim.x >> 4) + ((w >> 3) >> 1) : w;
+  const int h = SPLIT ? (int)((w >> 3) & 1) : 0;
+  const int64_t row0 = h ? FS_HALF : 0;
+  const int64_t nh = SPLIT ? (h ? n - FS_HALF : min<int64_t>(n, FS_HALF)) : n;   // rows of this workgroup
+  const int64_t prow0 = h ? 0 : FS_HALF;                                          // the partner's half
+  const int64_t pnh = h ? FS_HALF : n - FS_HALF;
+  for (int idx = tid; idx < ROWS * NCH; idx += 64 * FR_WAVES) ys[idx] = idx < nh ? y[row0 + idx] : 0.0;
+  __syncthreads();
+  double acc[NCH];
+#pragma unroll
+  for (int c = 0; c < NCH; ++c) acc[c] = 0.0;
+  const int64_t nblk = m / FS_COLS;
+  const int64_t b0 = pair * R, b1 = min(nblk, b0 + R);
+  const uint32_t loff = (uint32_t)(((lane >> 3) * lds + 4 * q) * 4);
+  const int rowbytes = (int)(lds * 4);
+  // load c of block blk for the rows [base, base + cnt): rows past cnt read zeros (buffer records)
+  auto load = [&](int64_t blk, int64_t base, int64_t cnt, int c, bool any) -> f32x4 {
+    const int r0 = c * ROWS + wave * 8;
+    const int rin = any ? (int)min<int64_t>(8, cnt - r0) : 0;
+    const bool in = rin > 0;
+    const float* bp = S + (in ? base + r0 : 0) * lds + blk * FS_COLS;
+    const __amdgpu_buffer_rsrc_t rs =
+        __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(bp), 0, in ? rin * rowbytes : 0, 0x00020000);
+    return __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(rs, (int)loff, 0, 0));
+  };
+  // column partials of one half from per-lane sums tq (4 columns per lane): lanes of equal q, then
+  // the waves in a fixed order; the result lands in tp / is read back by wave 0 lanes 0 .. 31
+  auto reduce_cols = [&](double* tq) {
+#pragma unroll
+    for (int o = 8; o < 64; o <<= 1)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) tq[e] += __shfl_xor(tq[e], o, 64);
+    if ((lane >> 3) == 0) {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) tp[wave][4 * q + e] = tq[e];
+    }
+    __syncthreads();
+    double v = 0.0;
+    if (wave == 0 && lane < FS_COLS)
+      v = ((tp[0][lane] + tp[1][lane]) + (tp[2][lane] + tp[3][lane])) +
+          ((tp[4][lane] + tp[5][lane]) + (tp[6][lane] + tp[7][lane]));
+    __syncthreads();
+    return v;
+  };
+  f32x4 sv[NCH];
+  int64_t blk = b0;
+  bool more = blk < b1;
+  if (more) {
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) sv[c] = load(blk, row0, nh, c, true);
+  }
+  if (more) do {
+    const int64_t k = blk - b0;           // this block's index in the pair's walk
+    const bool nmore = blk + 1 < b1;
+    double tq[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) {
+      const double yr = ys[c * ROWS + rloc];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) tq[e] = fma((double)sv[c][e], yr, tq[e]);
+    }
+    const double own = reduce_cols(tq);
+    if constexpr (!SPLIT) {
+      if (wave == 0 && lane < FS_COLS) tf[lane] = own;
+      (void)k;
+    } else {
+    double* slot = xch + ((pair * R + k) * 2) * FS_COLS;   // [h = 0 | h = 1] x 32 columns
+    // Publication without fences: an agent-scope fence writes back and invalidates the whole L2
+    // of the XCD, every block, for every workgroup. The partials and the counter are agent-scope
+    // relaxed atomics instead (device-coherent accesses that skip the non-coherent caches), the
+    // counter stored only once the partials' stores have completed (vmcnt 0), and the reader takes
+    // the partials only after it has seen the counter.
+    if (wave == 0) {
+      if (lane < FS_COLS) __hip_atomic_store(slot + h * FS_COLS + lane, own, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0): the partials are stored
+      if (lane == 0) {
+        __hip_atomic_store(prog + pair * 2 + h, (int)(k + 1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        int ok = 0;
+        for (int it = 0; it < spin; ++it) {
+          if (__hip_atomic_load(prog + pair * 2 + (1 - h), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) > k) {
+            ok = 1;
+            break;
+          }
+          __builtin_amdgcn_s_sleep(2);
+        }
+        got = ok;
+      }
+    }
+    __syncthreads();
+    double other = 0.0;
+    if (got) {
+      if (wave == 0 && lane < FS_COLS)
+        other = __hip_atomic_load(slot + (1 - h) * FS_COLS + lane, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      // the partner's partial, computed here in its order (one load in flight per lane: rare path)
+      double pq[4] = {0.0, 0.0, 0.0, 0.0};
+      for (int c = 0; c < NCH; ++c) {
+        const f32x4 v = load(blk, prow0, pnh, c, true);
+        const int64_t pr = (int64_t)c * ROWS + rloc;
+        const double yr = pr < pnh ? y[prow0 + pr] : 0.0;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) pq[e] = fma((double)v[e], yr, pq[e]);
+      }
+      other = reduce_cols(pq);
+    }
+    if (wave == 0 && lane < FS_COLS) tf[lane] = h == 0 ? own + other : other + own;
+    }
+    __syncthreads();
+    double t[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) t[e] = tf[4 * q + e];
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) {
+      asm volatile("" : "+v"(sv[c]));
+#pragma unroll
+      for (int e = 0; e < 4; ++e) acc[c] = fma((double)sv[c][e], t[e], acc[c]);
+      sv[c] = load(nmore ? blk + 1 : 0, row0, nh, c, nmore);
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    more = nmore;
+    ++blk;
+  } while (more);
+  // row partials: this half's rows from the accumulators, zeros for the other half
+#pragma unroll
+  for (int c = 0; c < NCH; ++c) {
+    double v = acc[c];
+    v += __shfl_xor(v, 1, 64);
+    v += __shfl_xor(v, 2, 64);
+    v += __shfl_xor(v, 4, 64);
+    const int64_t r = (int64_t)c * ROWS + rloc;
+    if (q == 0 && r < nh) part[w * n + row0 + r] = v;
+  }
+  if constexpr (SPLIT)
+    for (int64_t i = tid; i < n - nh; i += 64 * FR_WAVES) part[w * n + (h ? i : FS_HALF + i)] = 0.0;
+}
+
+// The last m % TW (< TW, TW = the block width) columns of the fused pass, as one more group of
+// partials: t_c = sum_i S_ic y_i for those columns (per-thread FP64 partials over rows tid,
+// tid + 256, ..., then added in fixed order through LDS), then part[i] = sum_c S_ic t_c. One
+// workgroup of 256 threads.
+template <int TW>
 __global__ void __launch_bounds__(256)
 refine_tail_kernel(const float* __restrict__ S, int64_t n, int64_t m, int64_t lds, const double* __restrict__ y,
                    int64_t c0, double* __restrict__ part, const int* __restrict__ skip) {
-  __shared__ double red[256][FR_COLS];
-  __shared__ double tc[FR_COLS];
+  __shared__ double red[256][TW];
+  __shared__ double tc[TW];
   if (skip && *skip) return;
   const int tid = threadIdx.x;
-  const int nt = (int)(m - c0);   // 1 .. 15
-  double p[FR_COLS];
+  const int nt = (int)(m - c0);   // 1 .. TW - 1
+  double p[TW];
 #pragma unroll
-  for (int c = 0; c < FR_COLS; ++c) p[c] = 0.0;
+  for (int c = 0; c < TW; ++c) p[c] = 0.0;
   for (int64_t i = tid; i < n; i += 256) {
     const double yi = y[i];
 #pragma unroll
-    for (int c = 0; c < FR_COLS; ++c)
+    for (int c = 0; c < TW; ++c)
       if (c < nt) p[c] = fma((double)S[i * lds + c0 + c], yi, p[c]);
   }
 #pragma unroll
-  for (int c = 0; c < FR_COLS; ++c) red[tid][c] = p[c];
+  for (int c = 0; c < TW; ++c) red[tid][c] = p[c];
   __syncthreads();
-  if (tid < FR_COLS) {
+  if (tid < TW) {
     double sum = 0.0;
     for (int k = 0; k < 256; ++k) sum += red[k][tid];
     tc[tid] = sum;
@@ -607,6 +785,11 @@ refine_tail_kernel(const float* __restrict__ S, int64_t n, int64_t m, int64_t ld
     for (int c = 0; c < nt; ++c) u = fma((double)S[i * lds + c0 + c], tc[c], u);
     part[i] = u;
   }
+}
+
+__global__ void zero_ints_kernel(int* __restrict__ a, int64_t k) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < k) a[i] = 0;
 }
 
 bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
@@ -733,7 +916,7 @@ hipError_t colpass_launch(const ColPassPlan& p, const float* S, int64_t n, int64
   return hipGetLastError();
 }
 
-RefinePassPlan refine_pass_plan(int64_t n, int64_t m, int64_t lds, const float* S) {
+RefinePassPlan refine_pass_plan(int64_t n, int64_t m, int64_t lds, const float* S, bool split_ok) {
   RefinePassPlan p{};
   p.n = n;
   const int64_t rows = 16 * FR_WAVES;
@@ -744,6 +927,33 @@ RefinePassPlan refine_pass_plan(int64_t n, int64_t m, int64_t lds, const float* 
   int dev = 0, cus = 0;
   if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
     cus = 256;
+  // whole-line kernels (32-column blocks): one workgroup per block for n <= 2048; rows split over a
+  // pair of workgroups for 2048 < n <= 4096 when every compute unit holds one workgroup and the
+  // pairs fit the XCD layout
+  const int64_t nblk32 = m / FS_COLS;
+  p.split = split_ok && p.usable && p.nch == 32 && n > FS_HALF && (cus % 16) == 0 && nblk32 >= cus / 2;
+  if (p.split) {
+    const int64_t npairs = cus / 2;
+    p.line = true;
+    p.ngroups = cus;
+    p.R = (nblk32 + npairs - 1) / npairs;
+    p.tail = (m % FS_COLS) != 0;
+    const size_t groups = (size_t)(p.ngroups + (p.tail ? 1 : 0)) * (size_t)n;
+    p.xch_off = groups;
+    p.prog_off = groups + (size_t)npairs * (size_t)p.R * 2 * FS_COLS;
+    p.part_bytes = p.prog_off * sizeof(double) + (size_t)(2 * npairs) * sizeof(int);
+    return p;
+  }
+  if (p.usable && n <= FS_HALF && nblk32 >= 1) {
+    p.line = true;
+    p.lnch = n <= 512 ? 8 : (n <= 1024 ? 16 : 32);
+    const int64_t per_cu = p.lnch == 8 ? 3 : (p.lnch == 16 ? 2 : 1);
+    p.ngroups = std::max<int64_t>(1, std::min<int64_t>((int64_t)cus * per_cu, nblk32));
+    p.R = (nblk32 + p.ngroups - 1) / p.ngroups;
+    p.tail = (m % FS_COLS) != 0;
+    p.part_bytes = (size_t)(p.ngroups + (p.tail ? 1 : 0)) * (size_t)n * sizeof(double);
+    return p;
+  }
   // workgroups per compute unit as the registers allow (8 waves each: 6, 4 and 2 waves per SIMD fit
   // for 8, 16 and 32 loads per lane): with small n one block is little data, and several blocks
   // per compute unit keep enough bytes in flight
@@ -755,16 +965,48 @@ RefinePassPlan refine_pass_plan(int64_t n, int64_t m, int64_t lds, const float* 
 }
 
 hipError_t refine_pass_launch(const RefinePassPlan& p, const float* S, int64_t n, int64_t m, int64_t lds,
-                              const double* y, double* part, hipStream_t st, const int* skip) {
+                              const double* y, double* part, hipStream_t st, const int* skip, int spin) {
   if (!p.usable || p.n != n) return hipErrorInvalidValue;
   const dim3 grid((unsigned)p.ngroups), block(64 * FR_WAVES);
+  if (p.split) {   // the pairs' progress counters start at zero
+    int* prog = reinterpret_cast<int*>(part + p.prog_off);
+    hipLaunchKernelGGL(zero_ints_kernel, dim3((unsigned)((p.ngroups + 255) / 256)), dim3(256), 0, st, prog,
+                       (int64_t)p.ngroups);
+    if (spin < 0) {   // DFISHER_PAIR_SPIN overrides the default bound (0: never wait for the partner)
+      const char* e = std::getenv("DFISHER_PAIR_SPIN");
+      spin = e ? std::max(0, std::atoi(e)) : FS_SPIN;
+    }
+    hipLaunchKernelGGL((refine_line_kernel<32, true>), grid, block, 0, st, S, n, m, lds, y, part, part + p.xch_off,
+                       prog, p.R, spin, skip);
+  } else if (p.line) {
+    switch (p.lnch) {
+      case 8:
+        hipLaunchKernelGGL((refine_line_kernel<8, false>), grid, block, 0, st, S, n, m, lds, y, part,
+                           (double*)nullptr, (int*)nullptr, p.R, 0, skip);
+        break;
+      case 16:
+        hipLaunchKernelGGL((refine_line_kernel<16, false>), grid, block, 0, st, S, n, m, lds, y, part,
+                           (double*)nullptr, (int*)nullptr, p.R, 0, skip);
+        break;
+      default:
+        hipLaunchKernelGGL((refine_line_kernel<32, false>), grid, block, 0, st, S, n, m, lds, y, part,
+                           (double*)nullptr, (int*)nullptr, p.R, 0, skip);
+        break;
+    }
+  }
+  if (p.line) {
+    if (p.tail)
+      hipLaunchKernelGGL(refine_tail_kernel<FS_COLS>, dim3(1), dim3(256), 0, st, S, n, m, lds, y,
+                         m / FS_COLS * FS_COLS, part + p.ngroups * n, skip);
+    return hipGetLastError();
+  }
   switch (p.nch) {
     case 8: hipLaunchKernelGGL(refine_pass_kernel<8>, grid, block, 0, st, S, n, m, lds, y, part, skip); break;
     case 16: hipLaunchKernelGGL(refine_pass_kernel<16>, grid, block, 0, st, S, n, m, lds, y, part, skip); break;
     default: hipLaunchKernelGGL(refine_pass_kernel<32>, grid, block, 0, st, S, n, m, lds, y, part, skip); break;
   }
   if (p.tail)
-    hipLaunchKernelGGL(refine_tail_kernel, dim3(1), dim3(256), 0, st, S, n, m, lds, y, m / FR_COLS * FR_COLS,
+    hipLaunchKernelGGL(refine_tail_kernel<FR_COLS>, dim3(1), dim3(256), 0, st, S, n, m, lds, y, m / FR_COLS * FR_COLS,
                        part + p.ngroups * n, skip);
   return hipGetLastError();
 }

@@ -239,3 +239,53 @@ def test_uneven_tolerance(dfl, ctx, oracle_mod):
 def rel_ok(x, xref):
     x = np.asarray(x.cpu().numpy(), dtype=np.float64)
     return float(np.linalg.norm(x - xref) / np.linalg.norm(xref)) <= 1e-6
+
+
+# The refinement product for 2048 < n <= 4096 splits the rows of each 32-column block over a pair of
+# workgroups that exchange their column partials; a workgroup whose partner's partials do not
+# arrive in time computes them itself, in the same order. DFISHER_PAIR_SPIN=0 forces that path for
+# every block: the result must be bitwise the same, and both must match the oracle (m with a tail
+# of 12 and of 17 columns, an odd n, the largest n).
+SPLIT_CASES = [(2064, 5004, 1e-3), (3001, 9617, 1e-4), (4096, 4128, 1e-2)]
+
+
+@pytest.mark.parametrize("n,m,lam", SPLIT_CASES)
+def test_split_refinement_product(dfl, ctx, oracle_mod, monkeypatch, n, m, lam):
+    print(f"[split refine] n={n} m={m} lam={lam}", flush=True)
+    S = synth.make_S(n, m, synth.seed(28, n), "iid")
+    v = synth.make_v(S, synth.seed(28, n), "iid")
+    xref = oracle_mod.solve(S, v, lam)
+    Sd, vd = dev_aligned(S), dev(v)
+    xs = {}
+    for spin in (None, "0"):
+        if spin is None:
+            monkeypatch.delenv("DFISHER_PAIR_SPIN", raising=False)
+        else:
+            monkeypatch.setenv("DFISHER_PAIR_SPIN", spin)
+        x, info = dfl.dfisher_solve(ctx, Sd, vd, lam, gram_prec=1, sweeps=2, x_fp64=True, final_resid=True)
+        xs[spin] = x.cpu().numpy()
+        print(f"    spin={spin} w_resid {info['w_resid']:.3e}", flush=True)
+        assert info["w_resid"] <= 1e-9
+    monkeypatch.delenv("DFISHER_PAIR_SPIN", raising=False)
+    e = lam * float(np.linalg.norm(xs[None] - xref)) / float(np.linalg.norm(v.astype(np.float64) - lam * xref))
+    print(f"    eps_Sy {e:.3e}", flush=True)
+    assert np.array_equal(xs[None], xs["0"])
+    assert e <= 1e-9
+
+
+def test_uneven_with_split_product(dfl, ctx, oracle_mod):
+    shapes = [(2100, 6000, 1e-3), (300, 20000, 1e-2)]
+    print(f"[split refine uneven] {shapes}", flush=True)
+    Ss, vs, lams, refs = [], [], [], []
+    for k, (n, m, lam) in enumerate(shapes):
+        S = synth.make_S(n, m, synth.seed(29, k), "iid")
+        v = synth.make_v(S, synth.seed(29, k), "iid")
+        Ss.append(dev_aligned(S))
+        vs.append(dev(v))
+        lams.append(lam)
+        refs.append((oracle_mod.solve(S, v, lam), v))
+    xs, infos = dfl.dfisher_solve_uneven(ctx, Ss, vs, lams, gram_prec=1, sweeps=2, x_fp64=True)
+    for x, (xr, v), lam in zip(xs, refs, lams):
+        e = lam * float(np.linalg.norm(x.cpu().numpy() - xr)) / float(np.linalg.norm(v.astype(np.float64) - lam * xr))
+        print(f"    eps_Sy {e:.3e}", flush=True)
+        assert e <= 1e-9

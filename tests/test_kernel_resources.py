@@ -22,6 +22,10 @@ HOT = {
     "refine_pass_kernelILi32": "gemv.hip",
     "refine_pass_kernelILi16": "gemv.hip",
     "refine_pass_kernelILi8": "gemv.hip",
+    "refine_line_kernelILi32ELb1": "gemv.hip",
+    "refine_line_kernelILi32ELb0": "gemv.hip",
+    "refine_line_kernelILi16ELb0": "gemv.hip",
+    "refine_line_kernelILi8ELb0": "gemv.hip",
     "rowpass_prep_kernelILb1ELi3": "gemv.hip",
     "colpass_kernelILi0": "gemv.hip",
     "rowpass_multi_t_kernel": "multi.hip",
