@@ -556,7 +556,7 @@ dfisher_status final_residual(dfisher_ctx* ctx, const float* S, int64_t n, int64
 // Per vector: y = W_f^-1 S v_r, `sweeps` FP64 refinement sweeps against the exact operator, then
 // x = (v_r - S^T y) / lambda_f. Needs nfac * nrhs <= 65535.
 struct MultiBufs {
-  double *Bs, *Bexp, *Y, *R, *D, *W1, *T, *Yi, *part;
+  double *Bs, *Bexp, *Y, *R, *D, *W1, *T, *T1, *Yi, *part, *part1;   // T1, part1: a second group
   double *Zc, *P, *NQ, *zero, *rz;   // refinement: M^-1 R, directions, -(W P), n zeros, r.z per vector
 };
 
@@ -569,9 +569,12 @@ MultiBufs carve_multi(Carver& c, int64_t n, int64_t m, int64_t nrhs, int64_t nve
   b.R = c.take<double>((size_t)(nvec * n));
   b.D = c.take<double>((size_t)(nvec * n));
   b.W1 = c.take<double>((size_t)(nvec * n));
+  const bool two = nvec > dfi::MULTI_VECS;   // passes take two groups of vectors at a time
   b.T = need_t ? c.take<double>((size_t)(m * dfi::MULTI_VECS)) : nullptr;
-  b.Yi = c.take<double>((size_t)(n * dfi::MULTI_VECS));
+  b.T1 = need_t && two ? c.take<double>((size_t)(m * dfi::MULTI_VECS)) : nullptr;
+  b.Yi = c.take<double>((size_t)(n * 2 * dfi::MULTI_VECS));
   b.part = c.take<double>(rm.part_bytes / sizeof(double) + 1);
+  b.part1 = need_t && two ? c.take<double>(rm.part_bytes / sizeof(double) + 1) : nullptr;
   b.Zc = c.take<double>((size_t)(nvec * n));
   b.P = c.take<double>((size_t)(nvec * n));
   b.NQ = c.take<double>((size_t)(nvec * n));
@@ -607,23 +610,39 @@ dfisher_status multi_solve(const float* S, int64_t n, int64_t m, int64_t lds, in
   // refinement: OUT_j = RHS_j - lambda_j U_j - S (S^T U_j), MV vectors per pair of passes (the
   // conjugate-gradient sweeps of solve_y, for every vector at once; RHS = B for the residual of Y,
   // RHS = 0 for -(W P))
+  // (two groups of MV vectors share each pass over S while at least MV + 1 vectors remain: every
+  // load of S then feeds twice the FP64 products)
+  auto group = [&](const double* U, const double* RHS, bool rhs_zero, double* OUT, int64_t j0, int nv,
+                   dfi::MultiCols& mc, dfi::MultiOut& mo) {
+    for (int c = 0; c < MV; ++c) mc.y[c] = U + (j0 + std::min(c, nv - 1)) * n;
+    for (int c = 0; c < nv; ++c) {
+      const int64_t j = j0 + c;
+      mo.b[c] = OUT + j * n;
+      mo.r0[c] = rhs_zero ? RHS : RHS + j * n;
+      mo.y[c] = U + j * n;
+      mo.lam[c] = lams[j / nrhs];
+    }
+  };
   auto w_pass = [&](const double* U, const double* RHS, bool rhs_zero, double* OUT) -> dfisher_status {
-    for (int64_t j0 = 0; j0 < nvec; j0 += MV) {
+    for (int64_t j0 = 0; j0 < nvec;) {
       const int nv = (int)std::min<int64_t>(MV, nvec - j0);
-      dfi::MultiCols mc{};
-      dfi::MultiOut mo{};
-      for (int c = 0; c < MV; ++c) mc.y[c] = U + (j0 + std::min(c, nv - 1)) * n;
-      for (int c = 0; c < nv; ++c) {
-        const int64_t j = j0 + c;
-        mo.b[c] = OUT + j * n;
-        mo.r0[c] = rhs_zero ? RHS : RHS + j * n;
-        mo.y[c] = U + j * n;
-        mo.lam[c] = lams[j / nrhs];
+      const int nv1 = b.T1 ? (int)std::min<int64_t>(MV, std::max<int64_t>(0, nvec - j0 - MV)) : 0;
+      dfi::MultiCols mc{}, mc1{};
+      dfi::MultiOut mo{}, mo1{};
+      group(U, RHS, rhs_zero, OUT, j0, nv, mc, mo);
+      if (nv1 > 0) {
+        group(U, RHS, rhs_zero, OUT, j0 + MV, nv1, mc1, mo1);
+        HIP_TRY(dfi::colpass_multi_launch2(S, n, m, lds, mc, nv, mc1, nv1, 2, b.T, b.T1, b.Yi, st));
+        HIP_TRY(dfi::rowpass_multi_launch2(rm, S, b.T, nv, b.T1, nv1, b.part, b.part1, st));
+        HIP_TRY(dfi::rowpass_multi_reduce(rm, b.part, nv, mo, st));
+        HIP_TRY(dfi::rowpass_multi_reduce(rm, b.part1, nv1, mo1, st));
+      } else {
+        HIP_TRY(dfi::colpass_multi_launch(S, n, m, lds, mc, nv, 2, b.T, b.Yi, st));
+        dfi::MultiVecs none{};
+        HIP_TRY(dfi::rowpass_multi_launch(rm, S, none, b.T, nv, b.part, st));
+        HIP_TRY(dfi::rowpass_multi_reduce(rm, b.part, nv, mo, st));
       }
-      HIP_TRY(dfi::colpass_multi_launch(S, n, m, lds, mc, nv, 2, b.T, b.Yi, st));
-      dfi::MultiVecs none{};
-      HIP_TRY(dfi::rowpass_multi_launch(rm, S, none, b.T, nv, b.part, st));
-      HIP_TRY(dfi::rowpass_multi_reduce(rm, b.part, nv, mo, st));
+      j0 += nv + nv1;
     }
     return DFISHER_OK;
   };
@@ -643,11 +662,9 @@ dfisher_status multi_solve(const float* S, int64_t n, int64_t m, int64_t lds, in
       HIP_TRY(dfi::pcg_step(nullptr, n, 0, nvec, b.P, b.NQ, b.Y, b.R, b.rz, nullptr, st));
     }
   }
-  // x = (v - S^T y) / lambda, MV vectors per pass
+  // x = (v - S^T y) / lambda, up to 2 MV vectors per pass
   const size_t xel = x_fp64 ? sizeof(double) : sizeof(float);
-  for (int64_t j0 = 0; j0 < nvec; j0 += MV) {
-    const int nv = (int)std::min<int64_t>(MV, nvec - j0);
-    dfi::MultiCols mc{};
+  auto apply_group = [&](int64_t j0, int nv, dfi::MultiCols& mc) {
     for (int c = 0; c < MV; ++c) {
       const int64_t j = j0 + std::min(c, nv - 1);
       mc.y[c] = b.Y + j * n;
@@ -655,7 +672,19 @@ dfisher_status multi_solve(const float* S, int64_t n, int64_t m, int64_t lds, in
       mc.x[c] = static_cast<char*>(X) + (size_t)(j * ldx) * xel;
       mc.lam[c] = lams[j / nrhs];
     }
-    HIP_TRY(dfi::colpass_multi_launch(S, n, m, lds, mc, nv, x_fp64 ? 1 : 0, nullptr, b.Yi, st));
+  };
+  for (int64_t j0 = 0; j0 < nvec;) {
+    const int nv = (int)std::min<int64_t>(MV, nvec - j0);
+    const int nv1 = (int)std::min<int64_t>(MV, std::max<int64_t>(0, nvec - j0 - MV));
+    dfi::MultiCols mc{}, mc1{};
+    apply_group(j0, nv, mc);
+    if (nv1 > 0) {
+      apply_group(j0 + MV, nv1, mc1);
+      HIP_TRY(dfi::colpass_multi_launch2(S, n, m, lds, mc, nv, mc1, nv1, x_fp64 ? 1 : 0, nullptr, nullptr, b.Yi, st));
+    } else {
+      HIP_TRY(dfi::colpass_multi_launch(S, n, m, lds, mc, nv, x_fp64 ? 1 : 0, nullptr, b.Yi, st));
+    }
+    j0 += nv + nv1;
   }
   return DFISHER_OK;
 }

@@ -157,6 +157,16 @@ hipError_t rowpass_multi_reduce(const RowMultiPlan& p, const double* part, int n
 // interleaved by row).
 hipError_t colpass_multi_launch(const float* S, int64_t n, int64_t m, int64_t lds, const MultiCols& mc, int nc,
                                 int mode, double* T, double* Yi, hipStream_t st);
+// Two groups of vectors (mc0: nc0, mc1: nc1, each 1 .. MULTI_VECS) in one pass over S: every load
+// of S feeds both groups' products. mode 2 writes T0 and T1 (each m * MULTI_VECS); Yi: scratch of
+// n * 2 * MULTI_VECS doubles.
+hipError_t colpass_multi_launch2(const float* S, int64_t n, int64_t m, int64_t lds, const MultiCols& mc0, int nc0,
+                                 const MultiCols& mc1, int nc1, int mode, double* T0, double* T1, double* Yi,
+                                 hipStream_t st);
+// The row pass over two groups' T (T0: nv0, T1: nv1 vectors) in one pass over S; partials into
+// part0 and part1 (each of the plan's part_bytes), reduced with rowpass_multi_reduce per group.
+hipError_t rowpass_multi_launch2(const RowMultiPlan& p, const float* S, const double* T0, int nv0, const double* T1,
+                                 int nv1, double* part0, double* part1, hipStream_t st);
 // y += d over len entries
 hipError_t axpy_many(double* y, const double* d, int64_t len, hipStream_t st);
 

@@ -196,15 +196,21 @@ rowpass_multi_t_kernel(const float* __restrict__ S, int64_t n, int64_t m, int64_
 // as zero.
 constexpr int RG_WAVES = 4;
 constexpr int RG_ROWS = 16 * RG_WAVES;
-constexpr int RG_STEP = 256;
 constexpr int RG_GSTRIDE = 80;                        // doubles per 4-column group in LDS (64 used)
-constexpr int RG_BUF = (RG_STEP / 4) * RG_GSTRIDE;   // doubles per LDS buffer (40 KB)
-constexpr int RG_PIECES = RG_STEP * MV / 2 / (64 * RG_WAVES);   // 16-byte pieces of T per thread and step
 
+// NG groups of up to MV vectors (T0, T1) share every load of S: with NG = 2 each 16-byte piece of
+// S feeds eight products instead of four, and the step is 128 columns so that the two groups'
+// double-buffered LDS stages (80 KB) still let two workgroups share a compute unit.
+template <int NG>
 __global__ void __launch_bounds__(64 * RG_WAVES, 2)
-rowpass_multi_tm_kernel(const float* __restrict__ S, int64_t n, int64_t m, int64_t lds, const double* __restrict__ T,
-                        int nv, int64_t cg, double* __restrict__ part, int vec) {
-  __shared__ __attribute__((aligned(16))) double tl[2][RG_BUF];
+rowpass_multi_tm_kernel(const float* __restrict__ S, int64_t n, int64_t m, int64_t lds, const double* __restrict__ T0,
+                        const double* __restrict__ T1, int nv0, int nv1, int64_t cg, double* __restrict__ part0,
+                        double* __restrict__ part1, int vec) {
+  constexpr int STEP = NG == 1 ? 256 : 128;             // columns per step
+  constexpr int BUF = (STEP / 4) * RG_GSTRIDE;          // doubles per LDS buffer and group
+  constexpr int PIECES = STEP * MV / 2 / (64 * RG_WAVES);   // 16-byte pieces of T per thread, step, group
+  constexpr int NU = STEP / 16;                         // 16-byte loads of S per lane and step
+  __shared__ __attribute__((aligned(16))) double tl[2][NG][BUF];
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -214,9 +220,9 @@ rowpass_multi_tm_kernel(const float* __restrict__ S, int64_t n, int64_t m, int64
   const int64_t c0 = g * cg;
   const int64_t c1 = min(m, c0 + cg);
   // waves whose rows lie past n still stage their share of T and meet the barriers
-  auto load_t = [&](int64_t cs, f64x2* tv) {
+  auto load_t = [&](const double* T, int64_t cs, f64x2* tv) {
 #pragma unroll
-    for (int h = 0; h < RG_PIECES; ++h) {
+    for (int h = 0; h < PIECES; ++h) {
       const int idx = 2 * (h * 64 * RG_WAVES + tid);   // double index in the step: column idx / MV, vector idx % MV
       tv[h] = (f64x2){0.0, 0.0};
       if (cs + idx / MV < c1) tv[h] = *reinterpret_cast<const f64x2*>(T + cs * MV + idx);
@@ -224,7 +230,7 @@ rowpass_multi_tm_kernel(const float* __restrict__ S, int64_t n, int64_t m, int64
   };
   auto store_t = [&](const f64x2* tv, double* tb) {
 #pragma unroll
-    for (int h = 0; h < RG_PIECES; ++h) {
+    for (int h = 0; h < PIECES; ++h) {
       const int idx = 2 * (h * 64 * RG_WAVES + tid);
       const int cl = idx / MV;
       *reinterpret_cast<f64x2*>(&tb[(cl >> 2) * RG_GSTRIDE + (cl & 3) * MV + (idx % MV)]) = tv[h];
@@ -238,47 +244,87 @@ rowpass_multi_tm_kernel(const float* __restrict__ S, int64_t n, int64_t m, int64
   const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
       const_cast<float*>(sbase), 0, rin > 0 ? (int)((int64_t)rin * lds * 4) : 0, 0x00020000);
   const uint32_t qoff = (uint32_t)((int64_t)q * lds * 4);
-  f64x4 acc = {0.0, 0.0, 0.0, 0.0};
-  f64x2 tv[RG_PIECES];
+  // NA independent accumulators per group (product j of each load into accumulator j % NA), added
+  // in a fixed order at the end: with NG = 2 a single chain of dependent products per group would
+  // leave the matrix cores waiting on each product's result
+  constexpr int NA = NG == 2 ? 2 : 1;
+  f64x4 acc[NG][NA];
+  f64x2 tv[NG][PIECES];
+#pragma unroll
+  for (int gg = 0; gg < NG; ++gg)
+#pragma unroll
+    for (int a = 0; a < NA; ++a) acc[gg][a] = (f64x4){0.0, 0.0, 0.0, 0.0};
   if (c0 < c1) {
-    load_t(c0, tv);
-    store_t(tv, tl[0]);
+#pragma unroll
+    for (int gg = 0; gg < NG; ++gg) {
+      load_t(gg ? T1 : T0, c0, tv[gg]);
+      store_t(tv[gg], tl[0][gg]);
+    }
   }
   __syncthreads();
-  int buf = 0;
-  for (int64_t cs = c0; cs < c1; cs += RG_STEP, buf ^= 1) {
-    const bool more = cs + RG_STEP < c1;
-    if (more) load_t(cs + RG_STEP, tv);   // the next step's T, stored after this step's products
-    f32x4 sv[16];
+  // S of the next step is loaded while this step's products run (NG = 2: the products of a step
+  // take about as long as the loads' latency, which would otherwise be exposed every step)
+  auto load_s = [&](int64_t cs, f32x4* sv) {
     const int kc = (int)(cs - c0);
 #pragma unroll
-    for (int u = 0; u < 16; ++u)
+    for (int u = 0; u < NU; ++u)
       sv[u] = __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(
                                             rs, (int)(qoff + 4u * (uint32_t)(kc + 16 * u + 4 * kr)), 0, 0));
-    // columns past c1 (in the group's last step only) count as zero: a select, no branch
-    const int lim = (int)min<int64_t>(c1 - cs, RG_STEP);
+  };
+  f32x4 sn[NU];
+  if (NG == 2 && c0 < c1) load_s(c0, sn);
+  int buf = 0;
+  for (int64_t cs = c0; cs < c1; cs += STEP, buf ^= 1) {
+    const bool more = cs + STEP < c1;
+    if (more) {   // the next step's T, stored after this step's products
 #pragma unroll
-    for (int u = 0; u < 16; ++u)
+      for (int gg = 0; gg < NG; ++gg) load_t(gg ? T1 : T0, cs + STEP, tv[gg]);
+    }
+    f32x4 sv[NU];
+    if constexpr (NG == 2) {
+#pragma unroll
+      for (int u = 0; u < NU; ++u) sv[u] = sn[u];
+      if (more) load_s(cs + STEP, sn);
+    } else {
+      load_s(cs, sv);
+    }
+    // columns past c1 (in the group's last step only) count as zero: a select, no branch
+    const int lim = (int)min<int64_t>(c1 - cs, STEP);
+#pragma unroll
+    for (int u = 0; u < NU; ++u)
 #pragma unroll
       for (int e = 0; e < 4; ++e) sv[u][e] = (16 * u + 4 * kr + e < lim) ? sv[u][e] : 0.f;
-    const double* tb = tl[buf];
 #pragma unroll
-    for (int u = 0; u < 16; ++u) {
+    for (int u = 0; u < NU; ++u) {
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        const double b = tb[(4 * u + kr) * RG_GSTRIDE + j * MV + q];
-        acc = __builtin_amdgcn_mfma_f64_16x16x4f64((double)sv[u][j], b, acc, 0, 0, 0);
+        const double a = (double)sv[u][j];
+#pragma unroll
+        for (int gg = 0; gg < NG; ++gg) {
+          const double b = tl[buf][gg][(4 * u + kr) * RG_GSTRIDE + j * MV + q];
+          acc[gg][j % NA] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[gg][j % NA], 0, 0, 0);
+        }
       }
       __builtin_amdgcn_sched_barrier(0);   // widen load u's values only where its products use them
     }
-    if (more) store_t(tv, tl[buf ^ 1]);   // the other buffer was last read before the previous barrier
+    if (more) {   // the other buffer was last read before the previous barrier
+#pragma unroll
+      for (int gg = 0; gg < NG; ++gg) store_t(tv[gg], tl[buf ^ 1][gg]);
+    }
     __syncthreads();
   }
-  if (q >= nv) return;
 #pragma unroll
-  for (int r = 0; r < 4; ++r) {
-    const int64_t rr = rbase + kr + 4 * r;
-    if (rr < n) part[(g * MV + q) * n + rr] = acc[r];
+  for (int gg = 0; gg < NG; ++gg) {
+    if (q >= (gg ? nv1 : nv0)) continue;
+    double* part = gg ? part1 : part0;
+    f64x4 tot = acc[gg][0];
+#pragma unroll
+    for (int a = 1; a < NA; ++a) tot += acc[gg][a];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int64_t rr = rbase + kr + 4 * r;
+      if (rr < n) part[(g * MV + q) * n + rr] = tot[r];
+    }
   }
 }
 
@@ -295,11 +341,11 @@ __global__ void rowpass_multi_reduce_kernel(const double* __restrict__ part, int
   out.b[c][i] = r0 ? (r0[i] - out.lam[c] * out.y[c][i]) - s : s;
 }
 
-// Yi[i * MV + c] = mc.y[c][i] for i < n, c < MV: the y vectors interleaved by row.
-__global__ void interleave_y_kernel(MultiCols mc, int64_t n, double* __restrict__ Yi) {
+// Yi[i * stride + off + c] = mc.y[c][i] for i < n, c < MV: the y vectors interleaved by row.
+__global__ void interleave_y_kernel(MultiCols mc, int64_t n, int stride, int off, double* __restrict__ Yi) {
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= n * MV) return;
-  Yi[idx] = mc.y[idx % MV][idx / MV];
+  Yi[(idx / MV) * stride + off + idx % MV] = mc.y[idx % MV][idx / MV];
 }
 
 // The column pass on the FP64 matrix cores: per wave 64 consecutive columns, D_j(16 vectors x 16
@@ -314,10 +360,11 @@ constexpr int CF_COLS = 64;    // columns per wave
 constexpr int CF_GROUPS = 4;   // 4-row groups per loop step
 static_assert(MV == 16, "one MFMA dimension holds the vectors");
 
-template <int MODE>
+template <int MODE, int NG>
 __global__ void __launch_bounds__(64 * CF_WAVES)
-colpass_multi_mfma_kernel(const float* __restrict__ S, int64_t n, int64_t m, int64_t lds, MultiCols mc, int nc,
-                          const double* __restrict__ Yi, double* __restrict__ T, int vec) {
+colpass_multi_mfma_kernel(const float* __restrict__ S, int64_t n, int64_t m, int64_t lds, MultiCols mc0, int nc0,
+                          MultiCols mc1, int nc1, const double* __restrict__ Yi, double* __restrict__ T0,
+                          double* __restrict__ T1, int vec) {
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int64_t c0 = ((int64_t)blockIdx.x * CF_WAVES + wave) * CF_COLS;
@@ -338,46 +385,76 @@ colpass_multi_mfma_kernel(const float* __restrict__ S, int64_t n, int64_t m, int
     }
     return v;
   };
-  auto load_y = [&](int64_t row) { return row < n ? Yi[row * MV + q] : 0.0; };
-  f64x4 acc[4];
+  // Yi holds NG groups of MV vectors per row: Yi[row (NG MV) + g MV + c]
+  auto load_y = [&](int64_t row, int gg) { return row < n ? Yi[row * (MV * NG) + gg * MV + q] : 0.0; };
+  f64x4 acc[NG][4];
 #pragma unroll
-  for (int j = 0; j < 4; ++j) acc[j] = (f64x4){0.0, 0.0, 0.0, 0.0};
-  for (int64_t i = 0; i < n; i += 4 * CF_GROUPS) {
-    f32x4 sv[CF_GROUPS];
-    double ya[CF_GROUPS];
+  for (int gg = 0; gg < NG; ++gg)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[gg][j] = (f64x4){0.0, 0.0, 0.0, 0.0};
+  // NG = 2: the next rows' S and y are loaded while this iteration's products run
+  f32x4 sn[CF_GROUPS];
+  double yn[NG][CF_GROUPS];
+  auto load_rows = [&](int64_t i, f32x4* sv, double (*ya)[CF_GROUPS]) {
 #pragma unroll
     for (int g = 0; g < CF_GROUPS; ++g) {
       sv[g] = load_s(i + 4 * g + kr);
-      ya[g] = load_y(i + 4 * g + kr);
+#pragma unroll
+      for (int gg = 0; gg < NG; ++gg) ya[gg][g] = load_y(i + 4 * g + kr, gg);
+    }
+  };
+  if (NG == 2) load_rows(0, sn, yn);
+  for (int64_t i = 0; i < n; i += 4 * CF_GROUPS) {
+    f32x4 sv[CF_GROUPS];
+    double ya[NG][CF_GROUPS];
+    if constexpr (NG == 2) {
+#pragma unroll
+      for (int g = 0; g < CF_GROUPS; ++g) {
+        sv[g] = sn[g];
+#pragma unroll
+        for (int gg = 0; gg < NG; ++gg) ya[gg][g] = yn[gg][g];
+      }
+      if (i + 4 * CF_GROUPS < n) load_rows(i + 4 * CF_GROUPS, sn, yn);
+    } else {
+      load_rows(i, sv, ya);
     }
 #pragma unroll
     for (int g = 0; g < CF_GROUPS; ++g)
 #pragma unroll
-      for (int j = 0; j < 4; ++j)
-        acc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ya[g], (double)sv[g][j], acc[j], 0, 0, 0);
+      for (int j = 0; j < 4; ++j) {
+        const double b = (double)sv[g][j];
+#pragma unroll
+        for (int gg = 0; gg < NG; ++gg) acc[gg][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(ya[gg][g], b, acc[gg][j], 0, 0, 0);
+      }
   }
-  if constexpr (MODE == 2) {
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      if (col + j >= m) continue;
+  for (int gg = 0; gg < NG; ++gg) {
+    if constexpr (MODE == 2) {
+      double* T = gg ? T1 : T0;
 #pragma unroll
-      for (int r = 0; r < 4; ++r) T[(col + j) * MV + kr + 4 * r] = acc[j][r];
-    }
-  } else {
-    // vector by vector with a uniform index into the argument arrays: vector c lives in register
-    // c / 4 of the lanes with kr = c % 4
+      for (int j = 0; j < 4; ++j) {
+        if (col + j >= m) continue;
 #pragma unroll
-    for (int c = 0; c < MV; ++c) {
-      if (c < nc && kr == (c & 3)) {
-        const float* vc = mc.v[c];
-        const double lam = mc.lam[c];
+        for (int r = 0; r < 4; ++r) T[(col + j) * MV + kr + 4 * r] = acc[gg][j][r];
+      }
+    } else {
+      const MultiCols& mc = gg ? mc1 : mc0;
+      const int nc = gg ? nc1 : nc0;
+      // vector by vector with a uniform index into the argument arrays: vector c lives in register
+      // c / 4 of the lanes with kr = c % 4
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const int64_t k = col + j;
-          if (k < m) {
-            const double x = ((double)vc[k] - acc[j][c >> 2]) / lam;
-            if constexpr (MODE == 0) static_cast<float*>(mc.x[c])[k] = (float)x;
-            else static_cast<double*>(mc.x[c])[k] = x;
+      for (int c = 0; c < MV; ++c) {
+        if (c < nc && kr == (c & 3)) {
+          const float* vc = mc.v[c];
+          const double lam = mc.lam[c];
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            const int64_t k = col + j;
+            if (k < m) {
+              const double x = ((double)vc[k] - acc[gg][j][c >> 2]) / lam;
+              if constexpr (MODE == 0) static_cast<float*>(mc.x[c])[k] = (float)x;
+              else static_cast<double*>(mc.x[c])[k] = x;
+            }
           }
         }
       }
@@ -421,14 +498,31 @@ hipError_t rowpass_multi_launch(const RowMultiPlan& p, const float* S, const Mul
   const int iv = (vec ? 1 : 0) | (vecv ? 2 : 0);
   const dim3 grid((unsigned)((p.n + RT_ROWS - 1) / RT_ROWS), (unsigned)p.nchunk);
   if (T && 16 * p.lds * 4 < ((int64_t)1 << 31) && p.chunk < ((int64_t)1 << 28))
-    hipLaunchKernelGGL(rowpass_multi_tm_kernel, dim3((unsigned)((p.n + RG_ROWS - 1) / RG_ROWS), (unsigned)p.nchunk),
-                       dim3(64 * RG_WAVES), 0, st, S, p.n, p.m, p.lds, T, nv, p.chunk, part, iv);
+    hipLaunchKernelGGL(rowpass_multi_tm_kernel<1>, dim3((unsigned)((p.n + RG_ROWS - 1) / RG_ROWS), (unsigned)p.nchunk),
+                       dim3(64 * RG_WAVES), 0, st, S, p.n, p.m, p.lds, T, (const double*)nullptr, nv, 0, p.chunk,
+                       part, (double*)nullptr, iv);
   else if (T)
     hipLaunchKernelGGL(rowpass_multi_t_kernel<false>, grid, dim3(64 * RT_WAVES), 0, st, S, p.n, p.m, p.lds, T, vs, nv,
                        p.chunk, part, iv);
   else
     hipLaunchKernelGGL(rowpass_multi_t_kernel<true>, grid, dim3(64 * RT_WAVES), 0, st, S, p.n, p.m, p.lds,
                        (const double*)nullptr, vs, nv, p.chunk, part, iv);
+  return hipGetLastError();
+}
+
+hipError_t rowpass_multi_launch2(const RowMultiPlan& p, const float* S, const double* T0, int nv0, const double* T1,
+                                 int nv1, double* part0, double* part1, hipStream_t st) {
+  if (nv0 < 1 || nv0 > MV || nv1 < 1 || nv1 > MV || !T0 || !T1) return hipErrorInvalidValue;
+  if (16 * p.lds * 4 >= ((int64_t)1 << 31) || p.chunk >= ((int64_t)1 << 28)) {   // two single-group passes
+    const MultiVecs none{};
+    const hipError_t e = rowpass_multi_launch(p, S, none, T0, nv0, part0, st);
+    if (e != hipSuccess) return e;
+    return rowpass_multi_launch(p, S, none, T1, nv1, part1, st);
+  }
+  const bool vec = ((p.lds & 3) == 0) && aligned16(S);
+  hipLaunchKernelGGL(rowpass_multi_tm_kernel<2>, dim3((unsigned)((p.n + RG_ROWS - 1) / RG_ROWS), (unsigned)p.nchunk),
+                     dim3(64 * RG_WAVES), 0, st, S, p.n, p.m, p.lds, T0, T1, nv0, nv1, p.chunk, part0, part1,
+                     vec ? 3 : 2);
   return hipGetLastError();
 }
 
@@ -444,19 +538,55 @@ hipError_t colpass_multi_launch(const float* S, int64_t n, int64_t m, int64_t ld
                                 int mode, double* T, double* Yi, hipStream_t st) {
   if (nc < 1 || nc > MV || !Yi) return hipErrorInvalidValue;
   const bool vec = ((lds & 3) == 0) && aligned16(S);
-  hipLaunchKernelGGL(interleave_y_kernel, dim3((unsigned)((n * MV + 255) / 256)), dim3(256), 0, st, mc, n, Yi);
+  hipLaunchKernelGGL(interleave_y_kernel, dim3((unsigned)((n * MV + 255) / 256)), dim3(256), 0, st, mc, n, MV, 0, Yi);
+  const dim3 grid((unsigned)((m + CF_WAVES * CF_COLS - 1) / (CF_WAVES * CF_COLS)));
+  const dim3 block(64 * CF_WAVES);
+  const double* yi = Yi;
+  const MultiCols none{};
+  double* const nul = nullptr;
+  switch (mode) {
+    case 0:
+      hipLaunchKernelGGL((colpass_multi_mfma_kernel<0, 1>), grid, block, 0, st, S, n, m, lds, mc, nc, none, 0, yi, T,
+                         nul, vec ? 1 : 0);
+      break;
+    case 1:
+      hipLaunchKernelGGL((colpass_multi_mfma_kernel<1, 1>), grid, block, 0, st, S, n, m, lds, mc, nc, none, 0, yi, T,
+                         nul, vec ? 1 : 0);
+      break;
+    case 2:
+      hipLaunchKernelGGL((colpass_multi_mfma_kernel<2, 1>), grid, block, 0, st, S, n, m, lds, mc, nc, none, 0, yi, T,
+                         nul, vec ? 1 : 0);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t colpass_multi_launch2(const float* S, int64_t n, int64_t m, int64_t lds, const MultiCols& mc0, int nc0,
+                                 const MultiCols& mc1, int nc1, int mode, double* T0, double* T1, double* Yi,
+                                 hipStream_t st) {
+  if (nc0 < 1 || nc0 > MV || nc1 < 1 || nc1 > MV || !Yi) return hipErrorInvalidValue;
+  if (mode == 2 && (!T0 || !T1)) return hipErrorInvalidValue;
+  const bool vec = ((lds & 3) == 0) && aligned16(S);
+  const unsigned ib = (unsigned)((n * MV + 255) / 256);
+  hipLaunchKernelGGL(interleave_y_kernel, dim3(ib), dim3(256), 0, st, mc0, n, 2 * MV, 0, Yi);
+  hipLaunchKernelGGL(interleave_y_kernel, dim3(ib), dim3(256), 0, st, mc1, n, 2 * MV, MV, Yi);
   const dim3 grid((unsigned)((m + CF_WAVES * CF_COLS - 1) / (CF_WAVES * CF_COLS)));
   const dim3 block(64 * CF_WAVES);
   const double* yi = Yi;
   switch (mode) {
     case 0:
-      hipLaunchKernelGGL((colpass_multi_mfma_kernel<0>), grid, block, 0, st, S, n, m, lds, mc, nc, yi, T, vec ? 1 : 0);
+      hipLaunchKernelGGL((colpass_multi_mfma_kernel<0, 2>), grid, block, 0, st, S, n, m, lds, mc0, nc0, mc1, nc1, yi,
+                         T0, T1, vec ? 1 : 0);
       break;
     case 1:
-      hipLaunchKernelGGL((colpass_multi_mfma_kernel<1>), grid, block, 0, st, S, n, m, lds, mc, nc, yi, T, vec ? 1 : 0);
+      hipLaunchKernelGGL((colpass_multi_mfma_kernel<1, 2>), grid, block, 0, st, S, n, m, lds, mc0, nc0, mc1, nc1, yi,
+                         T0, T1, vec ? 1 : 0);
       break;
     case 2:
-      hipLaunchKernelGGL((colpass_multi_mfma_kernel<2>), grid, block, 0, st, S, n, m, lds, mc, nc, yi, T, vec ? 1 : 0);
+      hipLaunchKernelGGL((colpass_multi_mfma_kernel<2, 2>), grid, block, 0, st, S, n, m, lds, mc0, nc0, mc1, nc1, yi,
+                         T0, T1, vec ? 1 : 0);
       break;
     default:
       return hipErrorInvalidValue;

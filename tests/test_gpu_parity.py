@@ -386,6 +386,7 @@ def test_batched(dfl, ctx, oracle_mod):
     (200, 12001, 12001, 5, 3, 1, 2, "on_failure"),   # 15 vectors: one ragged group of 16; unaligned rows
     (96, 8192, 8200, 2, 9, 0, 1, "on_failure"),      # 18 vectors: a full and a ragged group, padded stride
     (128, 9000, 9000, 2, 17, 1, 1, "on_failure"),    # 34 vectors; 17 right-hand sides: S V in two passes
+    (64, 7001, 7001, 4, 12, 1, 2, "on_failure"),     # 48 vectors: a two-group pass, then one group; odd stride
     (5, 3001, 3004, 3, 6, 1, 1, "on_failure"),       # fewer rows than one 16-row tile, padded stride
     (1, 2000, 2000, 2, 2, 2, 1, "on_failure"),       # n = 1 with the scaled-FP8 Gram
     (256, 65536, 65536, 3, 2, 2, 3, "always"),       # scaled-FP8 Gram with the up-front shift
