@@ -1,9 +1,9 @@
 // Blocked right-looking FP64 Cholesky W = L L^T (Algorithm 1 step 2), in place on a row-major
 // n x n matrix, lower triangle. Block size 64; per block column k:
 //   1. potf2   four waves factor the 64 x 64 diagonal block (right-looking: lane i keeps row i
-//              in registers, each wave a quarter of its columns; each column is scaled, broadcast
-//              through LDS and subtracted from the trailing columns) and form the block's inverse
-//              L_kk^-1 the same way one step behind (lane c owns column c).
+//              in registers, wave w columns 16 w .. 16 w + 15; wave w factors its 16 columns
+//              alone, then the later waves subtract them through LDS) and form the block's
+//              inverse L_kk^-1 panel by panel in the same loop (lane c owns column c).
 //   2. trsm    rows below the block: A_ik <- A_ik L_kk^-T as a product with the stored inverse,
 //              64 rows per workgroup, every output independent.
 //   3. update  trailing lower triangle A_IJ -= A_Ik A_Jk^T in 64 x 64 tiles on the FP64 matrix
@@ -27,20 +27,24 @@ constexpr int LDP = NB + 1;  // padded LDS row (doubles)
 constexpr int PW = 4;          // waves of the diagonal-block kernel
 constexpr int PC = NB / PW;    // 16 columns (factor) or rows of the inverse per wave
 
-// Diagonal block: L_kk = chol(A_kk) and Dkk = L_kk^-1, with 4 waves. Lane i holds row i of the
-// block, wave w its columns 16 w .. 16 w + 15, in registers. Right-looking: at step j the wave
-// owning column j scales it by the reciprocal square root of the pivot and publishes it in LDS
-// (column-major, so a wave reads the 16 entries l_cj it needs as 8 two-double broadcasts); after a
-// barrier every wave subtracts l_ij l_cj from its columns c > j (independent FMAs, no dependence
-// chain). The subtractions from a_ic come in the order l = 0, 1, ..., c - 1. The first pivot that
-// is not > 0 is reported as its 1-based global index (LDS flag); the block is then not stored.
-// The inverse runs one step behind in the same loop, sharing its barriers: lane c holds column c
-// of L_kk^-1, wave w its rows 16 w .. + 15; x = e_c; at step j, row q = j - 1 (whose column of L
-// and reciprocal pivot are now published) is scaled, x_q *= 1 / l_qq (owning wave, published in
-// LDS), and x_t -= l_tq x_q for t > q.
-// The step loops run over the four column groups without unrolling and unroll the 16 steps
-// inside a group, so the owners' register indices are constants and the code stays a few
-// thousand instructions (a fully unrolled 64-step body overflows the instruction cache).
+// Diagonal block: L_kk = chol(A_kk) and Dkk = L_kk^-1, with 4 waves.
+// Lane i holds row i of the block, wave w its columns 16 w .. 16 w + 15, in registers. The four
+// 16-column panels are taken in order; wave p factors its panel alone, right-looking, with no
+// barrier: at step j the pivot (lane j's entry, read across lanes) gives 1 / l_jj by the hardware
+// reciprocal square root and two Newton steps, column j is scaled, and the panel's later columns
+// c lose l_ij l_cj (l_cj read from lane c). The finished panel is published in LDS
+// (column-major), and after a barrier the waves of later panels subtract it from their columns
+// (l_ij from LDS per lane, l_cj as broadcasts). Every a_ic thus loses its products in the order
+// l = 0, 1, ..., c - 1, as in the column-by-column algorithm. The first pivot that is not > 0
+// (NaN included) is reported as its 1-based global index; the block is then not stored (later
+// steps run on garbage but index nothing out of range). Only 4 barriers per block, against one
+// per column before.
+// The inverse X = L_kk^-1 follows the same panels: lane c holds column c of X, wave w its rows
+// 16 w .. 16 w + 15 (x = e_c at the start). Once panel p of L is factored, wave p finishes its
+// rows of X by forward substitution inside the panel (x_t *= 1 / l_tt, then x_u -= l_ut x_t for
+// the panel's later rows u, with l_ut read as LDS broadcasts; nothing crosses lanes) and publishes
+// them; after the barrier the later waves subtract the panel's rows, x_u -= sum_t l_ut x_t, in
+// the panel's row order. Every x_uc thus loses its products in the order t = 0, 1, ..., u - 1.
 constexpr int LDT = NB + 1;   // padded column stride of the LDS copy of L_kk (doubles)
 
 // Lane j's value of a double (j wave-uniform): two v_readlane, no LDS round trip.
@@ -67,10 +71,10 @@ __device__ __forceinline__ double rsqrt_f64(double d) {
 __global__ void __launch_bounds__(64 * PW)
 potf2_kernel(double* __restrict__ A, int64_t n, int64_t k, int64_t* __restrict__ info, int32_t* __restrict__ flag,
              double* __restrict__ Dkk, int64_t sA, const FactorJob* __restrict__ jobs) {
-  __shared__ double lt[NB * LDT];   // l_ij at lt[j * LDT + i], filled column by column
+  __shared__ double lt[NB * LDT];   // l_ij at lt[j * LDT + i], published panel by panel
+  __shared__ double xt[NB * LDT];   // rows of L_kk^-1: x_tc at xt[t * LDT + c], published panel by panel
   __shared__ double rp[NB];         // 1 / l_jj
-  __shared__ double xs[2][NB];      // the inverse's pivot row, double-buffered
-  __shared__ int failed;
+  __shared__ int failed;            // 1-based local index of the first bad pivot, 0 if none
   const int64_t bb = blockIdx.y;
   if (jobs) {
     const FactorJob& jb = jobs[bb];
@@ -87,9 +91,9 @@ potf2_kernel(double* __restrict__ A, int64_t n, int64_t k, int64_t* __restrict__
     Dkk += bb * NB * NB;
   }
   if (*(volatile int32_t*)flag) return;
-  const int i = threadIdx.x & 63;      // row of the block (factor), column of the inverse
+  const int i = threadIdx.x & 63;      // row of the block
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform: scalar branches
-  const int c0 = w * PC;               // this wave's first column (factor) / row (inverse)
+  const int c0 = w * PC;               // this wave's first column
   const int64_t nb = min<int64_t>(NB, n - k);
   if (threadIdx.x == 0) failed = 0;
   double r[PC], x[PC];
@@ -99,72 +103,65 @@ potf2_kernel(double* __restrict__ A, int64_t n, int64_t k, int64_t* __restrict__
     double val = (c == i) ? 1.0 : 0.0;   // identity padding past nb
     if (i < nb && c < nb && c <= i) val = A[(k + i) * n + k + c];
     r[u] = val;
-    x[u] = (c == i) ? 1.0 : 0.0;
+    x[u] = (c == i) ? 1.0 : 0.0;         // row c0 + u of X, column i
   }
   __syncthreads();
 #pragma unroll 1
-  for (int jb = 0; jb < PW; ++jb) {
+  for (int p = 0; p < PW; ++p) {
+    if (w == p) {
+      int bad = 0;   // uniform
 #pragma unroll
-    for (int jj = 0; jj < PC; ++jj) {
-      const int j = jb * PC + jj;
-      // inverse row q = j - 1: owner wave qb, register qq (uniform)
-      const int qb = (jj > 0) ? jb : jb - 1;
-      constexpr int QQ_WRAP = PC - 1;
-      const int qq = (jj > 0) ? jj - 1 : QQ_WRAP;
-      if (w == jb) {   // wave-uniform: the owner of column j
+      for (int jj = 0; jj < PC; ++jj) {
+        const int j = c0 + jj;
         const double d = lane_read(r[jj], j);
-        if (!(d > 0.0)) {
-          // the first breakdown is reported; later pivots are then garbage and are ignored
-          if (i == 0 && failed == 0) {
-            *info = k + j + 1;
-            *flag = 1;
-            failed = 1;
-          }
-        } else {
-          const double rinv = rsqrt_f64(d);
-          const double ljj = d * rinv;
-          const double lij = (i > j) ? r[jj] * rinv : ((i == j) ? ljj : 0.0);
-          r[jj] = lij;
-          lt[j * LDT + i] = lij;
-          if (i == j) rp[j] = rinv;
-        }
+        if (!(d > 0.0) && bad == 0) bad = j + 1;
+        const double rinv = rsqrt_f64(d);
+        const double ljj = d * rinv;
+        const double lij = (i > j) ? r[jj] * rinv : ((i == j) ? ljj : 0.0);
+        r[jj] = lij;
+        if (i == j) rp[j] = rinv;
+#pragma unroll
+        for (int u = jj + 1; u < PC; ++u) r[u] -= lij * lane_read(lij, c0 + u);
       }
-      if (j > 0 && w == qb) {
-        const double xq = x[(jj > 0) ? jj - 1 : QQ_WRAP] * rp[j - 1];
-        x[(jj > 0) ? jj - 1 : QQ_WRAP] = xq;
-        xs[(j - 1) & 1][i] = xq;
+#pragma unroll
+      for (int u = 0; u < PC; ++u) lt[(c0 + u) * LDT + i] = r[u];
+      // the first breakdown is reported; panels after it run on garbage and are ignored
+      if (bad && i == 0 && failed == 0) failed = bad;
+      __builtin_amdgcn_s_waitcnt(0xC07F);   // lgkmcnt(0): this wave's LDS writes are readable
+      // rows c0 .. c0 + 15 of X: forward substitution inside the panel (l_ut, 1 / l_tt from LDS)
+#pragma unroll
+      for (int tt = 0; tt < PC; ++tt) {
+        x[tt] *= rp[c0 + tt];
+#pragma unroll
+        for (int u = tt + 1; u < PC; ++u) x[u] -= lt[(c0 + tt) * LDT + c0 + u] * x[tt];
       }
-      __syncthreads();
-      const double* col = lt + j * LDT + c0;   // l_cj for this wave's columns c = c0 + u
-      if (w > jb) {
-        const double lij = lt[j * LDT + i];
 #pragma unroll
-        for (int u = 0; u < PC; ++u) r[u] -= lij * col[u];
-      } else if (w == jb) {
-        const double lij = r[jj];
+      for (int u = 0; u < PC; ++u) xt[(c0 + u) * LDT + i] = x[u];
+    }
+    __syncthreads();
+    if (w > p) {   // subtract panel p from this wave's columns of L and rows of X, in panel order
+      const int p0 = p * PC;
 #pragma unroll
-        for (int u = jj + 1; u < PC; ++u) r[u] -= lij * col[u];
-      }
-      if (j > 0) {
-        const double* colq = lt + (j - 1) * LDT + c0;   // l_tq for this wave's rows t = c0 + u
-        if (w > qb) {
-          const double xq = xs[(j - 1) & 1][i];
+      for (int jj = 0; jj < PC; ++jj) {
+        const double* col = lt + (p0 + jj) * LDT;
+        const double lij = col[i];
+        const double xtc = xt[(p0 + jj) * LDT + i];   // x_tc, t = p0 + jj
 #pragma unroll
-          for (int u = 0; u < PC; ++u) x[u] -= colq[u] * xq;
-        } else if (w == qb) {
-          const double xq = x[qq];
-#pragma unroll
-          for (int u = 0; u < PC; ++u)
-            if (u > qq) x[u] -= colq[u] * xq;
+        for (int u = 0; u < PC; ++u) {
+          r[u] -= lij * col[c0 + u];
+          x[u] -= col[c0 + u] * xtc;                   // l_ut x_tc, u = c0 + u
         }
       }
     }
   }
-  // After a breakdown the remaining steps ran on garbage (finite or not, all indices in range);
-  // nothing of this block is stored. Every thread sees the flag (set before a barrier).
-  if (failed) return;
-  // the last row of the inverse has no later rows to update
-  if (w == PW - 1) x[PC - 1] *= rp[NB - 1];
+  // every panel has been published before the last barrier; failed was set before a barrier too
+  if (failed) {
+    if (threadIdx.x == 0) {
+      *info = k + failed;
+      *flag = 1;
+    }
+    return;
+  }
   // the factor's lower triangle: wave w stores rows w, w + 4, ..., lane c column c
   for (int rr = w; rr < nb; rr += PW)
     if (i <= rr) A[(k + rr) * n + k + i] = lt[i * LDT + rr];
