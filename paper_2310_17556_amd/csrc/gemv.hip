@@ -624,7 +624,15 @@ refine_line_kernel(const float* __restrict__ S, int64_t n, int64_t m, int64_t ld
   double acc[NCH];
 #pragma unroll
   for (int c = 0; c < NCH; ++c) acc[c] = 0.0;
-  const int64_t nblk = m / FS_COLS;
+  // the last block may be partial (m % 32 columns): its columns past m are zeroed after the load
+  // (they are the next row's or the padding's values, or zeros past the buffer's records)
+  const int64_t nblk = (m + FS_COLS - 1) / FS_COLS;
+  const int64_t nfull = m / FS_COLS;
+  const int cq = 4 * (lane & 7);   // this lane's first column within a block
+  auto mask_tail = [&](f32x4& v, int64_t blk) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) v[e] = (blk * FS_COLS + cq + e < m) ? v[e] : 0.f;
+  };
   const int64_t b0 = pair * R, b1 = min(nblk, b0 + R);
   const uint32_t loff = (uint32_t)(((lane >> 3) * lds + 4 * q) * 4);
   const int rowbytes = (int)(lds * 4);
@@ -666,6 +674,10 @@ refine_line_kernel(const float* __restrict__ S, int64_t n, int64_t m, int64_t ld
   }
   if (more) do {
     const int64_t k = blk - b0;           // this block's index in the pair's walk
+    if (blk == nfull) {                   // the partial last block (uniform)
+#pragma unroll
+      for (int c = 0; c < NCH; ++c) mask_tail(sv[c], blk);
+    }
     const bool nmore = blk + 1 < b1;
     double tq[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
@@ -710,7 +722,8 @@ refine_line_kernel(const float* __restrict__ S, int64_t n, int64_t m, int64_t ld
       // the partner's partial, computed here in its order (one load in flight per lane: rare path)
       double pq[4] = {0.0, 0.0, 0.0, 0.0};
       for (int c = 0; c < NCH; ++c) {
-        const f32x4 v = load(blk, prow0, pnh, c, true);
+        f32x4 v = load(blk, prow0, pnh, c, true);
+        if (blk == nfull) mask_tail(v, blk);
         const int64_t pr = (int64_t)c * ROWS + rloc;
         const double yr = pr < pnh ? y[prow0 + pr] : 0.0;
 #pragma unroll
@@ -930,14 +943,14 @@ RefinePassPlan refine_pass_plan(int64_t n, int64_t m, int64_t lds, const float* 
   // whole-line kernels (32-column blocks): one workgroup per block for n <= 2048; rows split over a
   // pair of workgroups for 2048 < n <= 4096 when every compute unit holds one workgroup and the
   // pairs fit the XCD layout
-  const int64_t nblk32 = m / FS_COLS;
+  const int64_t nblk32 = (m + FS_COLS - 1) / FS_COLS;   // the last one may be partial (masked in the kernel)
   p.split = split_ok && p.usable && p.nch == 32 && n > FS_HALF && (cus % 16) == 0 && nblk32 >= cus / 2;
   if (p.split) {
     const int64_t npairs = cus / 2;
     p.line = true;
     p.ngroups = cus;
     p.R = (nblk32 + npairs - 1) / npairs;
-    p.tail = (m % FS_COLS) != 0;
+    p.tail = false;
     const size_t groups = (size_t)(p.ngroups + (p.tail ? 1 : 0)) * (size_t)n;
     p.xch_off = groups;
     p.prog_off = groups + (size_t)npairs * (size_t)p.R * 2 * FS_COLS;
@@ -950,8 +963,8 @@ RefinePassPlan refine_pass_plan(int64_t n, int64_t m, int64_t lds, const float* 
     const int64_t per_cu = p.lnch == 8 ? 3 : (p.lnch == 16 ? 2 : 1);
     p.ngroups = std::max<int64_t>(1, std::min<int64_t>((int64_t)cus * per_cu, nblk32));
     p.R = (nblk32 + p.ngroups - 1) / p.ngroups;
-    p.tail = (m % FS_COLS) != 0;
-    p.part_bytes = (size_t)(p.ngroups + (p.tail ? 1 : 0)) * (size_t)n * sizeof(double);
+    p.tail = false;
+    p.part_bytes = (size_t)p.ngroups * (size_t)n * sizeof(double);
     return p;
   }
   // workgroups per compute unit as the registers allow (8 waves each: 6, 4 and 2 waves per SIMD fit
@@ -994,12 +1007,7 @@ hipError_t refine_pass_launch(const RefinePassPlan& p, const float* S, int64_t n
         break;
     }
   }
-  if (p.line) {
-    if (p.tail)
-      hipLaunchKernelGGL(refine_tail_kernel<FS_COLS>, dim3(1), dim3(256), 0, st, S, n, m, lds, y,
-                         m / FS_COLS * FS_COLS, part + p.ngroups * n, skip);
-    return hipGetLastError();
-  }
+  if (p.line) return hipGetLastError();   // the line kernels take the partial last block themselves
   switch (p.nch) {
     case 8: hipLaunchKernelGGL(refine_pass_kernel<8>, grid, block, 0, st, S, n, m, lds, y, part, skip); break;
     case 16: hipLaunchKernelGGL(refine_pass_kernel<16>, grid, block, 0, st, S, n, m, lds, y, part, skip); break;

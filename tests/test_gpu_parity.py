@@ -252,6 +252,7 @@ SOLVE_CASES = [
     (1040, 9000, 1e-3, 1, 2, "iid", 1e-6),      # 8 loads per lane and block
     (2064, 5004, 1e-3, 1, 2, "iid", 1e-6),      # 16 loads per lane, rows past n in the last load
     (4200, 5000, 1e-2, 1, 1, "iid", 1e-6),      # n > 4096: the two-pass refinement product
+    (40, 20, 1e-2, 0, 1, "iid", 1e-6),          # m < 32: one partial 32-column block in the fused pass
 ]
 
 
