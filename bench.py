@@ -345,6 +345,24 @@ def batched_leg(dfl, dev, prec, sweeps, reps, n=2048, m=2_000_000, nlam=16, nrhs
         _, infos = dfl.dfisher_solve_batched(ctx, S, lams, V, gram_prec=PREC_CODE[prec], centered=CENTERED, sweeps=sweeps, X=X)
     torch.cuda.synchronize()
     el = (time.perf_counter() - t0) / reps
+    # the same call enqueued without any wait (DFISHER_ASYNC, statuses on the device), captured once
+    # into a graph and replayed; no shift is needed at these lambdas, so X is bitwise the eager one
+    Xg = torch.empty_like(X)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        _, dinf = dfl.dfisher_solve_batched(ctx, S, lams, V, gram_prec=PREC_CODE[prec], centered=CENTERED,
+                                            sweeps=sweeps, X=Xg, shift_policy=dfl.DFISHER_SHIFT_NONE,
+                                            enqueue_only=True)
+    g.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        g.replay()
+    torch.cuda.synchronize()
+    elg = (time.perf_counter() - t0) / reps
+    ginfos = dfl.batch_infos(dinf)
+    graph_ok = all(i["potrf_info"] == 0 for i in ginfos) and bool(torch.equal(Xg, X))
+    del g, Xg, dinf
     X64 = torch.empty((nlam, nrhs, m), dtype=torch.float64, device=dev)
     dfl.dfisher_solve_batched(ctx, S, lams, V, gram_prec=PREC_CODE[prec], centered=CENTERED, sweeps=sweeps, X=X64, x_fp64=True)
     Ys = _batched_ref(S, V, lams)
@@ -369,6 +387,8 @@ def batched_leg(dfl, dev, prec, sweeps, reps, n=2048, m=2_000_000, nlam=16, nrhs
     return {"workload": f"batched: n={n} m={m}, {nlam} lambdas log-spaced in [1e-6, 1e-1] x {nrhs} iid right-hand "
                         "sides, one shared Gram",
             "gram": prec, "sweeps": infos[0]["sweeps_done"], "solves_per_s": nlam * nrhs / el, "ms_per_call": el * 1e3,
+            "graph_replay": {"solves_per_s": nlam * nrhs / elg, "ms_per_call": elg * 1e3,
+                             "x_bitwise_equal_to_eager": graph_ok},
             "rel_err_fp32_out": _summ(rel32), "rel_err": _summ(rel64), "eps_Sy": _summ(esy),
             "max_shift": max(i["shift"] for i in infos)}
 

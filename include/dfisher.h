@@ -20,8 +20,9 @@
  *              device work of a call is enqueued on that stream.
  *   Sync       Calls that factor W (dfisher_solve, dfisher_factor_create, dfisher_potrf,
  *              dfisher_solve_batched, dfisher_solve_uneven) synchronise the stream once per
- *              factorisation to read the Cholesky status. The others return without
- *              synchronising.
+ *              factorisation to read the Cholesky status; dfisher_solve_batched with the
+ *              DFISHER_ASYNC flag does not (its statuses stay on the device). The others return
+ *              without synchronising.
  *   Errors     Every call returns a dfisher_status and never aborts or throws. Arguments are
  *              validated on the host before any device call: null pointers, n < 1, m < 1,
  *              lds < m, lambda not finite or not > 0, and unknown enum values return
@@ -100,8 +101,8 @@ typedef struct dfisher_options {
                             (FP64 accumulation, one more pass over S, not applied) and report
                             it in info->w_resid. dfisher_solve and dfisher_solve_uneven only
                             (other entry points return DFISHER_E_UNSUPPORTED). 0 or 1.        */
-  int32_t flags;         /* bitwise OR of the DFISHER_CENTERED flag below, or 0; other bits
-                            are DFISHER_E_INVALID_ARG                                          */
+  int32_t flags;         /* bitwise OR of DFISHER_CENTERED and DFISHER_ASYNC below, or 0;
+                            other bits are DFISHER_E_INVALID_ARG                               */
 } dfisher_options;
 
 /* opt->flags: the caller declares that every column of S sums to zero over the samples (1^T S = 0),
@@ -120,6 +121,27 @@ typedef struct dfisher_options {
  * on the flag. Honoured by dfisher_solve, _rowspace, _complex, _batched, _uneven and
  * dfisher_factor_create. */
 #define DFISHER_CENTERED 1
+
+/* opt->flags: enqueue without waiting (dfisher_solve_batched only; the other entry points return
+ * DFISHER_E_UNSUPPORTED). The call puts all of its device work on `stream` and returns without
+ * synchronising or reading anything back, so that the caller can capture it into a HIP graph
+ * (stream capture on `stream`, any capture mode) and replay it. With the flag:
+ *   - infos is a DEVICE pointer to nlam records (or NULL), written by the call's last kernel;
+ *     read them after the stream has finished. A failed factorisation shows there only
+ *     (potrf_info != 0, that lambda's x unspecified): the return value reports argument,
+ *     workspace and HIP errors, never DFISHER_E_NOT_SPD.
+ *   - shift_policy must be DFISHER_SHIFT_NONE or DFISHER_SHIFT_ALWAYS; DFISHER_SHIFT_ON_FAILURE
+ *     refactors after a host-side decision and returns DFISHER_E_UNSUPPORTED. DFISHER_SWEEPS_AUTO
+ *     is the a-priori count (as without the flag when no factorisation fails).
+ *   - no autotuning runs (the context's tuning table, or the default plan, is used).
+ *   - the workspace cannot be allocated during a capture: make the same call once outside the
+ *     capture first, or the captured call returns DFISHER_E_UNSUPPORTED. A call captured on a
+ *     context fixes the context's workspace for the rest of its life, since the graph holds its
+ *     addresses: later calls on that context that need more workspace return
+ *     DFISHER_E_UNSUPPORTED. A replay uses the workspace as a call does: replays and other calls
+ *     on the context must not overlap.
+ * Results are bitwise those of the same call without the flag. */
+#define DFISHER_ASYNC 2
 
 /* Refinement sweeps. Each sweep reads S once. Sweep 1 forms the FP64 residual r = S v - lambda y
  * - S (S^T y) of y = L^-T L^-1 S v; the sweeps after it are conjugate-gradient iterations on
@@ -320,7 +342,9 @@ DFISHER_API dfisher_status dfisher_factor_destroy(dfisher_factor* f);
  * refinement residuals and x = (v - S^T y) / lambda run as passes over S that serve 16 vectors
  * each. Needs nlam * nrhs <= 65535 (else DFISHER_E_UNSUPPORTED). A factorisation that fails
  * under DFISHER_SHIFT_NONE makes the call return DFISHER_E_NOT_SPD; the x of that lambda is then
- * unspecified. Synchronises the stream once to read the factorisation statuses. */
+ * unspecified. Synchronises the stream once to read the factorisation statuses, unless
+ * opt->flags has DFISHER_ASYNC (then nothing waits, infos is a device array, and the call can be
+ * captured into a HIP graph; see DFISHER_ASYNC). */
 DFISHER_API dfisher_status dfisher_solve_batched(dfisher_ctx* ctx, const float* S, int64_t n, int64_t m, int64_t lds,
                                      const double* lambdas, int32_t nlam, const float* V, int32_t nrhs,
                                      int64_t ldv, void* X, int64_t ldx, const dfisher_options* opt,

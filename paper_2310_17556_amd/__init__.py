@@ -42,6 +42,7 @@ DFISHER_SHIFT_NONE = 0
 DFISHER_SHIFT_ON_FAILURE = 1
 DFISHER_SHIFT_ALWAYS = 2
 DFISHER_CENTERED = 1
+DFISHER_ASYNC = 2
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libdfisher.so")
@@ -99,7 +100,7 @@ def _load():
                                    ctypes.POINTER(Info)], I32),
         "dfisher_factor_destroy": ([P], I32),
         "dfisher_solve_batched": ([P, P, I64, I64, I64, ctypes.POINTER(D), I32, P, I32, I64, P, I64,
-                                   ctypes.POINTER(_Options), P, ctypes.POINTER(Info)], I32),
+                                   ctypes.POINTER(_Options), P, P], I32),   # infos: host, or device (ASYNC)
         "dfisher_solve_uneven": ([P, I32, PP, ctypes.POINTER(I64), ctypes.POINTER(I64), ctypes.POINTER(I64), PP,
                                   ctypes.POINTER(D), PP, ctypes.POINTER(_Options), P, ctypes.POINTER(Info)], I32),
         "dfisher_ctx_enable_timing": ([P, I32], I32),
@@ -514,8 +515,11 @@ def dfisher_factor_destroy(f) -> None:
 
 def dfisher_solve_batched(ctx, S, lams, V, gram_prec: int = DFISHER_GRAM_FP32, sweeps: int = 0,
                           shift_policy: int = DFISHER_SHIFT_ON_FAILURE, x_fp64: bool = False, X=None, stream=None,
-                          centered: bool = False):
-    """X[l, r] solves (S^T S + lams[l] I) x = V[r]. Returns (X of shape (nlam, nrhs, m), infos)."""
+                          centered: bool = False, enqueue_only: bool = False):
+    """X[l, r] solves (S^T S + lams[l] I) x = V[r]. Returns (X of shape (nlam, nrhs, m), infos).
+
+    enqueue_only sets DFISHER_ASYNC: nothing waits (the call may run under CUDA-graph capture) and
+    infos is then a uint8 CUDA tensor of nlam records, decoded by batch_infos() once the stream is done."""
     torch = _torch()
     n, m, lds = _S_args(S)
     if V.dtype != torch.float32 or V.dim() != 2 or V.stride(1) != 1 or V.shape[1] != m:
@@ -529,10 +533,25 @@ def dfisher_solve_batched(ctx, S, lams, V, gram_prec: int = DFISHER_GRAM_FP32, s
     if X.dtype != dt or not X.is_contiguous() or tuple(X.shape) != (nlam, nrhs, m):
         raise ValueError("X must be a contiguous (nlam, nrhs, m) tensor of the output dtype")
     opt = _options(gram_prec, sweeps, shift_policy, x_fp64, centered=centered)
+    if enqueue_only:
+        opt.flags |= DFISHER_ASYNC
+        dinfos = torch.empty((nlam, ctypes.sizeof(Info)), dtype=torch.uint8, device=S.device)
+        _check(_lib().dfisher_solve_batched(ctx.ptr, _ptr(S), n, m, lds, lam_arr, nlam, _ptr(V), nrhs, V.stride(0),
+                                            _ptr(X), m, ctypes.byref(opt), _stream(stream),
+                                            ctypes.c_void_p(dinfos.data_ptr())), "dfisher_solve_batched")
+        return X, dinfos
     infos = (Info * nlam)()
     _check(_lib().dfisher_solve_batched(ctx.ptr, _ptr(S), n, m, lds, lam_arr, nlam, _ptr(V), nrhs, V.stride(0), _ptr(X),
                                      m, ctypes.byref(opt), _stream(stream), infos), "dfisher_solve_batched")
     return X, [i.as_dict() for i in infos]
+
+
+def batch_infos(dinfos):
+    """Decode the device records of an enqueue_only batched call (after its stream has finished)."""
+    raw = bytes(dinfos.cpu().numpy().tobytes())
+    k = len(raw) // ctypes.sizeof(Info)
+    arr = (Info * k).from_buffer_copy(raw)
+    return [i.as_dict() for i in arr]
 
 
 def dfisher_solve_uneven(ctx, Ss, vs, lams, gram_prec: int = DFISHER_GRAM_FP32, sweeps: int = 0,

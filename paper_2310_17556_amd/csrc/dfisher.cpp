@@ -75,6 +75,7 @@ struct dfisher_ctx {
   hipEvent_t ev[NEV] = {};
   void* ws = nullptr;
   size_t ws_bytes = 0;
+  bool ws_frozen = false;       // a call captured into a caller's graph holds ws: never reallocated
   int64_t* h_status = nullptr;  // pinned: [0] potrf info
   double* h_scalar = nullptr;   // pinned: [0] diagonal max
   int64_t* d_info = nullptr;
@@ -133,6 +134,10 @@ void drop_graph(dfisher_ctx* ctx);
 
 dfisher_status ensure_ws(dfisher_ctx* ctx, size_t bytes) {
   if (bytes <= ctx->ws_bytes) return DFISHER_OK;
+  if (ctx->ws_frozen)
+    return fail(DFISHER_E_UNSUPPORTED,
+                "the context's workspace (%zu bytes) is held by a captured call and cannot grow to %zu bytes; "
+                "use another context", ctx->ws_bytes, bytes);
   drop_graph(ctx);   // a cached graph points into the old workspace
   if (ctx->ws) {
     HIP_TRY(hipDeviceSynchronize());
@@ -184,7 +189,8 @@ dfisher_status check_S(const float* S, int64_t n, int64_t m, int64_t lds) {
   return DFISHER_OK;
 }
 
-dfisher_status check_opt(const dfisher_options* opt, dfisher_options* out) {
+// async_ok: the entry point honours DFISHER_ASYNC (others return DFISHER_E_UNSUPPORTED for it).
+dfisher_status check_opt(const dfisher_options* opt, dfisher_options* out, bool async_ok = false) {
   dfisher_options d = DFISHER_OPTIONS_DEFAULT;
   if (opt) d = *opt;
   if (d.gram_prec != DFISHER_GRAM_FP32 && d.gram_prec != DFISHER_GRAM_BF16X3 && d.gram_prec != DFISHER_GRAM_MXFP8)
@@ -197,7 +203,10 @@ dfisher_status check_opt(const dfisher_options* opt, dfisher_options* out) {
   if (d.x_fp64 != 0 && d.x_fp64 != 1) return fail(DFISHER_E_INVALID_ARG, "x_fp64 must be 0 or 1");
   if (!std::isfinite(d.tol) || d.tol < 0.0) return fail(DFISHER_E_INVALID_ARG, "tol must be finite and >= 0");
   if (d.final_resid != 0 && d.final_resid != 1) return fail(DFISHER_E_INVALID_ARG, "final_resid must be 0 or 1");
-  if ((d.flags & ~DFISHER_CENTERED) != 0) return fail(DFISHER_E_INVALID_ARG, "unknown flags 0x%x", d.flags);
+  if ((d.flags & ~(DFISHER_CENTERED | DFISHER_ASYNC)) != 0)
+    return fail(DFISHER_E_INVALID_ARG, "unknown flags 0x%x", d.flags);
+  if ((d.flags & DFISHER_ASYNC) != 0 && !async_ok)
+    return fail(DFISHER_E_UNSUPPORTED, "DFISHER_ASYNC is honoured by dfisher_solve_batched only");
   *out = d;
   return DFISHER_OK;
 }
@@ -1190,6 +1199,30 @@ dfisher_status uneven_solve(dfisher_ctx* ctx, int32_t np, const float* const* S,
   return DFISHER_OK;
 }
 
+// The per-lambda records of an asynchronous batched call, written on the device after its
+// factorisations: status, the up-front shift scale0 * max_i G_ii (dmax from diag_max, read only
+// when scale0 != 0), one attempt, the fixed sweep count, nothing measured.
+__global__ void batch_infos_kernel(dfisher_info* __restrict__ out, int64_t nlam, const int64_t* __restrict__ info,
+                                   double scale0, const double* __restrict__ dmax, int32_t sweeps) {
+  const int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (l >= nlam) return;
+  dfisher_info r;
+  r.potrf_info = info[l];
+  r.shift = scale0 != 0.0 ? scale0 * dmax[0] : 0.0;
+  r.attempts = 1;
+  r.sweeps_done = sweeps;
+  r.resid = -1.0;
+  r.w_resid = -1.0;
+  out[l] = r;
+}
+
+hipError_t write_batch_infos(dfisher_info* out, int64_t nlam, const int64_t* info, double scale0, const double* dmax,
+                             int32_t sweeps, hipStream_t st) {
+  hipLaunchKernelGGL(batch_infos_kernel, dim3((unsigned)((nlam + 255) / 256)), dim3(256), 0, st, out, nlam, info,
+                     scale0, dmax, sweeps);
+  return hipGetLastError();
+}
+
 // Per-device set-up, called with the device current: the device address of the no-alloc scratch.
 std::mutex g_scratch_mu;
 std::vector<void*> g_scratch_ptr;   // per device; null until looked up
@@ -1935,13 +1968,22 @@ dfisher_status dfisher_solve_batched(dfisher_ctx* ctx, const float* S, int64_t n
     if (!finite_pos(lambdas[l])) return fail(DFISHER_E_INVALID_ARG, "lambdas[%d] must be finite and > 0", l);
   if ((int64_t)nlam * nrhs > 65535) return fail(DFISHER_E_UNSUPPORTED, "nlam * nrhs > 65535");
   dfisher_options o;
-  DF_TRY(check_opt(opt, &o));
+  DF_TRY(check_opt(opt, &o, true));
   DF_TRY(check_no_tol(o));
   DF_TRY(check_no_final(o));
   DF_TRY(check_prec_layout(o.gram_prec, S, lds));
+  const bool async = (o.flags & DFISHER_ASYNC) != 0;
+  if (async && o.shift_policy == DFISHER_SHIFT_ON_FAILURE)
+    return fail(DFISHER_E_UNSUPPORTED, "DFISHER_ASYNC needs shift_policy NONE or ALWAYS (ON_FAILURE decides on the host)");
   DeviceGuard g(ctx->device);
   hipStream_t st = as_stream(stream);
-  if (ctx->autotune) DF_TRY(tune_if_new(ctx, S, n, m, lds, o.gram_prec, st));
+  bool capturing = false;
+  if (async) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    HIP_TRY(hipStreamIsCapturing(st, &cs));
+    capturing = cs == hipStreamCaptureStatusActive;
+  }
+  if (ctx->autotune && !async) DF_TRY(tune_if_new(ctx, S, n, m, lds, o.gram_prec, st));
   const dfi::GramPlan gp = make_gram_plan(ctx, S, n, m, lds, o.gram_prec);
   const dfi::RowPassPlan rp = dfi::rowpass_plan(n, m, lds);
   const dfi::ColPassPlan cp = dfi::colpass_plan(n, m);
@@ -1969,7 +2011,15 @@ dfisher_status dfisher_solve_batched(dfisher_ctx* ctx, const float* S, int64_t n
   int64_t* dinfo;
   int32_t* dflag;
   MultiBufs mb;
-  DF_TRY(ensure_ws(ctx, layout(nullptr, B, Lall, Dall, dkk, dinfo, dflag, mb)));
+  const size_t need = layout(nullptr, B, Lall, Dall, dkk, dinfo, dflag, mb);
+  if (capturing) {   // no allocation inside a capture; the graph will hold the workspace's addresses
+    if (need > ctx->ws_bytes)
+      return fail(DFISHER_E_UNSUPPORTED,
+                  "the workspace must grow to %zu bytes, which cannot happen during a capture: make the same call "
+                  "once outside the capture first", need);
+    ctx->ws_frozen = true;
+  }
+  DF_TRY(ensure_ws(ctx, need));
   layout(static_cast<char*>(ctx->ws), B, Lall, Dall, dkk, dinfo, dflag, mb);
 
   // the shared Gram G = S S^T (exact diagonal, no lambda), formed once
@@ -1981,6 +2031,14 @@ dfisher_status dfisher_solve_batched(dfisher_ctx* ctx, const float* S, int64_t n
   for (int32_t l = 0; l < nlam; ++l)
     HIP_TRY(dfi::shift_add_copy(B.W, Lall + (int64_t)l * n * n, n, scale0, ctx->d_scalar, lambdas[l], st));
   HIP_TRY(dfi::potrf_launch_batched(Lall, n, nlam, n * n, dinfo, dflag, dkk, st));
+  if (async) {   // nothing read back: the sweep count is fixed a priori, the statuses go to infos on the device
+    const int sweeps = o.sweeps == DFISHER_SWEEPS_AUTO ? auto_sweeps(o.gram_prec, n, m, scale0, is_centered(o))
+                                                       : o.sweeps;
+    HIP_TRY(dfi::trsv_diag_inv_batched(Lall, n * n, n, nlam, Dall, st));
+    DF_TRY(multi_solve(S, n, m, lds, nlam, Lall, Dall, lambdas, V, nrhs, ldv, X, ldx, o.x_fp64, sweeps, rm, mb, st));
+    if (infos) HIP_TRY(write_batch_infos(infos, nlam, dinfo, scale0, ctx->d_scalar, sweeps, st));
+    return DFISHER_OK;
+  }
   std::vector<int64_t> hinfo((size_t)nlam);
   double dmax = 0.0;
   HIP_TRY(hipMemcpyAsync(hinfo.data(), dinfo, (size_t)nlam * sizeof(int64_t), hipMemcpyDeviceToHost, st));

@@ -79,7 +79,7 @@ def test_invalid_arguments_rejected_on_host(dfl):
         assert lib.dfisher_solve(FAKE_CTX, P, 4, 8, 8, P, lam, P, None, st, ctypes.byref(info)) == E
     for o in [_opts(dfl, prec=5), _opts(dfl, sweeps=-2), _opts(dfl, sweeps=17), _opts(dfl, shift=3),
               _opts(dfl, x64=2), _opts(dfl, tol=-1e-9), _opts(dfl, tol=float("nan")), _opts(dfl, tol=float("inf")),
-              _opts(dfl, final=2), _opts(dfl, flags=2), _opts(dfl, flags=-1)]:
+              _opts(dfl, final=2), _opts(dfl, flags=4), _opts(dfl, flags=-1)]:
         assert lib.dfisher_solve(FAKE_CTX, P, 4, 8, 8, P, 1.0, P, ctypes.byref(o), st, None) == E
     assert lib.dfisher_solve(FAKE_CTX, P, 4, 8, 8, None, 1.0, P, None, st, None) == E
     assert lib.dfisher_solve(FAKE_CTX, P, 4, 8, 8, P, 1.0, None, None, st, None) == E
@@ -124,6 +124,18 @@ def test_invalid_arguments_rejected_on_host(dfl):
     assert lib.dfisher_solve_batched(FAKE_CTX, P, 4, 8, 8, lams, 1, P, 1, 8, P, 8, ctypes.byref(ofin), st, None) == U
     assert lib.dfisher_factor_create(FAKE_CTX, P, 4, 8, 8, 1.0, ctypes.byref(ofin), st, ctypes.byref(out), None) == U
     assert "NULL" in dfl.dfisher_last_error() or dfl.dfisher_last_error() != ""
+    # enqueue-only (DFISHER_ASYNC) is honoured by the batched call only, and there without the
+    # host-decided shift escalation
+    oasync = _opts(dfl, sweeps=1, shift=0, flags=dfl.DFISHER_ASYNC)
+    assert lib.dfisher_solve(FAKE_CTX, P, 4, 8, 8, P, 1.0, P, ctypes.byref(oasync), st, None) == U
+    assert lib.dfisher_solve_rowspace(FAKE_CTX, P, 4, 8, 8, P, 1.0, P, ctypes.byref(oasync), st, None) == U
+    assert lib.dfisher_solve_complex(FAKE_CTX, P, 4, 8, 8, P, 1.0, P, ctypes.byref(oasync), st, None) == U
+    assert lib.dfisher_factor_create(FAKE_CTX, P, 4, 8, 8, 1.0, ctypes.byref(oasync), st, ctypes.byref(out), None) == U
+    assert lib.dfisher_solve_uneven(FAKE_CTX, 1, arrp, arrn, arr64, arr64, arrp, lams, arrp, ctypes.byref(oasync), st,
+                                    None) == U
+    oasync_fail = _opts(dfl, sweeps=1, shift=1, flags=dfl.DFISHER_ASYNC)
+    assert lib.dfisher_solve_batched(FAKE_CTX, P, 4, 8, 8, lams, 1, P, 1, 8, P, 8, ctypes.byref(oasync_fail), st,
+                                     None) == U
     # context switches and the tuning table
     assert lib.dfisher_ctx_enable_graphs(None, 1) == E
     assert lib.dfisher_ctx_enable_autotune(None, 1) == E
