@@ -234,11 +234,16 @@ def error_table(dfl, ctx, S, v, lams, xref, table, shift="on_failure"):
         for sw in sweep_list:
             row = {}
             for lam in lams:
-                _, info = dfl.dfisher_solve(ctx, S, v, lam, gram_prec=PREC_CODE[prec], centered=CENTERED, sweeps=sw, shift_policy=policy,
-                                            x=x64, x_fp64=True, final_resid=True)
+                # as called by default (the final step may take the last correction through the FP8
+                # codes), then with the measured final residual (which takes the exact step)
+                _, info = dfl.dfisher_solve(ctx, S, v, lam, gram_prec=PREC_CODE[prec], centered=CENTERED, sweeps=sw,
+                                            shift_policy=policy, x=x64, x_fp64=True)
                 rel, esy = _errs(x64, xref[lam], v, lam)
-                row[str(lam)] = {"rel_err": rel, "eps_Sy": esy, "w_resid": info["w_resid"],
-                                 "sweeps": info["sweeps_done"], "shift": info["shift"]}
+                _, infw = dfl.dfisher_solve(ctx, S, v, lam, gram_prec=PREC_CODE[prec], centered=CENTERED, sweeps=sw,
+                                            shift_policy=policy, x=x64, x_fp64=True, final_resid=True)
+                rel_x, esy_x = _errs(x64, xref[lam], v, lam)
+                row[str(lam)] = {"rel_err": rel, "eps_Sy": esy, "w_resid": infw["w_resid"],
+                                 "eps_Sy_exact_step": esy_x, "sweeps": info["sweeps_done"], "shift": info["shift"]}
             out[f"{prec}/{'auto' if sw < 0 else sw}"] = row
     del x64
     return out
@@ -543,6 +548,16 @@ def main() -> int:
     log(f"[bench] mixed: {value:.3f} solves/s, gram {gram_avg_ms:.2f} ms, stages {stage_avg}")
 
     x_mixed = {lam: xbuf[lam].clone() for lam in lams}
+    # which final step each timed solve took: the last correction through the FP8 codes, or the
+    # exact column pass over S (an untimed call that forces the latter gives the same x exactly then)
+    final_step = {}
+    xchk = torch.empty(m, dtype=torch.float32, device=dev)
+    for lam in lams:
+        dfl.dfisher_solve(ctx, S, v, lam, gram_prec=PREC_CODE[args.prec], centered=CENTERED, sweeps=args.sweeps,
+                          shift_policy=getattr(dfl, SHIFT[args.shift]), x=xchk, exact_apply=True)
+        final_step[str(lam)] = "exact" if bool(torch.equal(xchk, x_mixed[lam])) else "fp8"
+    del xchk
+    log(f"[bench] final step per lambda: {final_step}")
 
     fp32 = None
     if args.fp32_steps > 0:
@@ -605,6 +620,10 @@ def main() -> int:
     prep_write = {"mxfp8": n * ldq * (1 + 1 / 32), "bf16x3": 4.0 * n * ((m + 63) // 64 * 64), "fp32": 0.0}
     rowpass_bytes = 4.0 * n * m + 4.0 * m + 16.0 * n + prep_write[args.prec]
     apply_bytes = 4.0 * n * m + 8.0 * n + 8.0 * m
+    if args.prec == "mxfp8" and all(f == "fp8" for f in final_step.values()):
+        # the FP8 final step reads the codes and scales, T = S^T y, the column sums (centered), v,
+        # and writes x
+        apply_bytes = n * ldq * (1 + 1 / 32) + 8.0 * m * (2 if CENTERED else 1) + 4.0 * m + 4.0 * m + 8.0 * n
     timed = infos[-solves:]
     sweeps_done = {str(l): i["sweeps_done"] for l, i in timed[-len(lams):]}
     refine_bytes = sum(i["sweeps_done"] for _, i in timed) / len(timed) * (4.0 * n * m + 8.0 * n)
@@ -672,6 +691,8 @@ def main() -> int:
         "hbm": {"rowpass_GBs": gbs(rowpass_bytes, stage_avg.get("rowpass_ms")),
                 "rowpass_bytes": rowpass_bytes,
                 "apply_GBs": gbs(apply_bytes, stage_avg.get("apply_ms")),
+                "apply_bytes": apply_bytes,
+                "final_step": final_step,
                 "refine_GBs": gbs(refine_bytes, stage_avg.get("refine_ms")),
                 "refine_note": "refine_ms includes the triangular solves of every sweep",
                 "peak_GBs": HBM_PEAK_GBS},

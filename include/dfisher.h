@@ -101,8 +101,9 @@ typedef struct dfisher_options {
                             (FP64 accumulation, one more pass over S, not applied) and report
                             it in info->w_resid. dfisher_solve and dfisher_solve_uneven only
                             (other entry points return DFISHER_E_UNSUPPORTED). 0 or 1.        */
-  int32_t flags;         /* bitwise OR of DFISHER_CENTERED and DFISHER_ASYNC below, or 0;
-                            other bits are DFISHER_E_INVALID_ARG                               */
+  int32_t flags;         /* bitwise OR of DFISHER_CENTERED, DFISHER_ASYNC and
+                            DFISHER_EXACT_APPLY below, or 0; other bits are
+                            DFISHER_E_INVALID_ARG                                              */
 } dfisher_options;
 
 /* opt->flags: the caller declares that every column of S sums to zero over the samples (1^T S = 0),
@@ -142,6 +143,19 @@ typedef struct dfisher_options {
  *     on the context must not overlap.
  * Results are bitwise those of the same call without the flag. */
 #define DFISHER_ASYNC 2
+
+/* The final step x = (v - S^T y) / lambda (step 6 of Algorithm 1) of dfisher_solve with the
+ * scaled-FP8 Gram and at least one refinement sweep: the refinement passes carry S^T y_c exactly
+ * for the iterate before the last correction z (y = y_c + z), and the image S^T z of that small
+ * correction can be taken through the FP8 copy of S that the Gram already made (a quarter of the
+ * bytes of S) instead of a fourth read of S. Its error, about 3 % of |S^T z| for independent
+ * rounding errors, is estimated on the device from the row norms and z, and the FP8 image is used
+ * only while that estimate is about 1e-7 of |S^T y| or less (otherwise the exact column pass runs;
+ * nothing waits for the host either way). For a declared centered S the all-ones component of z is
+ * taken exactly, through the column sums S^T 1 the first refinement pass forms. The flag below
+ * always takes the exact pass. Needs 16-byte aligned rows and n <= 4096 (the passes that carry
+ * S^T y), opt->final_resid = 0. */
+#define DFISHER_EXACT_APPLY 4
 
 /* Refinement sweeps. Each sweep reads S once. Sweep 1 forms the FP64 residual r = S v - lambda y
  * - S (S^T y) of y = L^-T L^-1 S v; the sweeps after it are conjugate-gradient iterations on

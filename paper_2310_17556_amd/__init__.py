@@ -43,6 +43,7 @@ DFISHER_SHIFT_ON_FAILURE = 1
 DFISHER_SHIFT_ALWAYS = 2
 DFISHER_CENTERED = 1
 DFISHER_ASYNC = 2
+DFISHER_EXACT_APPLY = 4
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libdfisher.so")
@@ -354,10 +355,11 @@ def dfisher_apply(ctx, S, v, y, lam: float, x=None, x_fp64: bool = False, stream
 
 def dfisher_solve(ctx, S, v, lam: float, gram_prec: int = DFISHER_GRAM_FP32, sweeps: int = 0,
                   shift_policy: int = DFISHER_SHIFT_ON_FAILURE, x_fp64: bool = False, x=None, stream=None,
-                  tol: float = 0.0, final_resid: bool = False, centered: bool = False):
+                  tol: float = 0.0, final_resid: bool = False, centered: bool = False, exact_apply: bool = False):
     """x solving (S^T S + lam I) x = v. Returns (x, info_dict). With tol > 0 the refinement stops at
     the tolerance (sweeps is the cap); info_dict["converged"] is False (and x is still the result)
-    when the library returns DFISHER_E_NOT_CONVERGED."""
+    when the library returns DFISHER_E_NOT_CONVERGED. exact_apply sets DFISHER_EXACT_APPLY (the final
+    step never takes the last correction through the FP8 codes)."""
     torch = _torch()
     n, m, lds = _S_args(S)
     _vec(v, m, torch.float32, "v")
@@ -367,6 +369,8 @@ def dfisher_solve(ctx, S, v, lam: float, gram_prec: int = DFISHER_GRAM_FP32, swe
     _vec(x, m, dt, "x")
     opt = _options(gram_prec, sweeps, shift_policy, x_fp64, final_resid, centered)
     opt.tol = float(tol)
+    if exact_apply:
+        opt.flags |= DFISHER_EXACT_APPLY
     info = Info()
     st = _lib().dfisher_solve(ctx.ptr, _ptr(S), n, m, lds, _ptr(v), float(lam), _ptr(x), ctypes.byref(opt),
                               _stream(stream), ctypes.byref(info))

@@ -22,7 +22,7 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libdfisher.so")
 ARCH = "gfx950"
 
-SOURCES = ["dfisher.cpp", "gram.hip", "gemv.hip", "multi.hip", "potrf.hip", "trsv.hip", "pcg.hip", "sr.hip"]
+SOURCES = ["dfisher.cpp", "gram.hip", "gemv.hip", "multi.hip", "potrf.hip", "trsv.hip", "pcg.hip", "sr.hip", "apply8.hip"]
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}", "-I", INCLUDE, "-I", CSRC,
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

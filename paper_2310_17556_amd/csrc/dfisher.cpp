@@ -61,6 +61,11 @@ constexpr double AUTO_MIN_CONTRACTION = 0.1;   // least contraction a predictive
 // sweep contracts the residual by 1e-3 .. 1e-2 (measured at m/n 100 .. 1000)
 constexpr double AUTO_MIN_CONTRACTION_CENTERED = 0.01;
 constexpr int MAX_SHIFT_ATTEMPTS = 10;
+// The final step takes the last correction's image through the FP8 codes only while its expected
+// error, about 3 % of the estimate sqrt(sum_i |s_i|^2 z_i^2) / |S^T y| the device forms, stays near
+// 1e-7 of |S^T y| (ten times below the 1e-6 target; for the scaled-FP8 Gram after two sweeps at
+// m/n ~ 1000 the estimate is ~2e-6)
+constexpr double FINAL8_EST_MAX = 4e-6;
 
 size_t align_up(size_t x) { return (x + 255) & ~(size_t)255; }
 
@@ -203,7 +208,7 @@ dfisher_status check_opt(const dfisher_options* opt, dfisher_options* out, bool 
   if (d.x_fp64 != 0 && d.x_fp64 != 1) return fail(DFISHER_E_INVALID_ARG, "x_fp64 must be 0 or 1");
   if (!std::isfinite(d.tol) || d.tol < 0.0) return fail(DFISHER_E_INVALID_ARG, "tol must be finite and >= 0");
   if (d.final_resid != 0 && d.final_resid != 1) return fail(DFISHER_E_INVALID_ARG, "final_resid must be 0 or 1");
-  if ((d.flags & ~(DFISHER_CENTERED | DFISHER_ASYNC)) != 0)
+  if ((d.flags & ~(DFISHER_CENTERED | DFISHER_ASYNC | DFISHER_EXACT_APPLY)) != 0)
     return fail(DFISHER_E_INVALID_ARG, "unknown flags 0x%x", d.flags);
   if ((d.flags & DFISHER_ASYNC) != 0 && !async_ok)
     return fail(DFISHER_E_UNSUPPORTED, "DFISHER_ASYNC is honoured by dfisher_solve_batched only");
@@ -320,11 +325,20 @@ struct SolveBufs {
   int64_t ldq;
   uint16_t* hi;    // split-BF16 planes of S (n x gp->ldh each), when the Gram uses them
   uint16_t* lo;
+  // the final step through the FP8 codes (apply8.hip), when planned: S^T y carried through the
+  // passes, S^T p of the last direction, S^T 1 (centered S only), the correction in FP32, scalars
+  double* T8;
+  double* U8;
+  double* cs8;
+  float* zf8;
+  double* a8;      // [0] the last step length, [1] the correction's all-ones mean
+  int* use8;       // 1: the final step went through the codes
   size_t bytes;
 };
 
 SolveBufs carve(char* base, int64_t n, int64_t m, const dfi::GramPlan* gp, const dfi::RowPassPlan& rp,
-                const dfi::ColPassPlan& cp, bool need_L, bool need_t, const dfi::RefinePassPlan* fp = nullptr) {
+                const dfi::ColPassPlan& cp, bool need_L, bool need_t, const dfi::RefinePassPlan* fp = nullptr,
+                bool final8 = false, bool final8_cs = false) {
   Carver c;
   c.base = base;
   SolveBufs s{};
@@ -353,6 +367,12 @@ SolveBufs carve(char* base, int64_t n, int64_t m, const dfi::GramPlan* gp, const
   const bool split = gp && gp->prec == DFISHER_GRAM_BF16X3 && gp->ldh > 0;
   s.hi = split ? c.take<uint16_t>((size_t)(n * gp->ldh)) : nullptr;
   s.lo = split ? c.take<uint16_t>((size_t)(n * gp->ldh)) : nullptr;
+  s.T8 = final8 ? c.take<double>((size_t)m) : nullptr;
+  s.U8 = final8 ? c.take<double>((size_t)m) : nullptr;
+  s.cs8 = final8 && final8_cs ? c.take<double>((size_t)m) : nullptr;
+  s.zf8 = final8 ? c.take<float>((size_t)n) : nullptr;
+  s.a8 = final8 ? c.take<double>(2) : nullptr;
+  s.use8 = final8 ? c.take<int>(2) : nullptr;   // [1]: the centered projection was applied
   s.bytes = c.off;
   return s;
 }
@@ -402,7 +422,7 @@ dfisher_status factor_with_policy(dfisher_ctx* ctx, const double* W, double* L, 
 // W itself shows that S is far from centered.
 dfisher_status gram_stage(const float* S, const float* v, const dfi::GramPlan& gp, const dfi::RowPassPlan& rp,
                           const SolveBufs& B, double lambda, double* W, int mirror, hipStream_t st, StageClock* clk,
-                          bool center = false) {
+                          bool center = false, int* applied = nullptr) {
   if (clk) clk->mark(0);
   if (gp.prec == DFISHER_GRAM_MXFP8) {
     HIP_TRY(dfi::rowpass_launch(rp, S, v, nullptr, v != nullptr, true, B.rpart, st, B.q8, B.sc8, B.ldq, true));
@@ -424,7 +444,7 @@ dfisher_status gram_stage(const float* S, const float* v, const dfi::GramPlan& g
   HIP_TRY(dfi::gram_reduce(gp, S, B.gpart, B.d, lambda, W, mirror, st));
   if (center) {   // the Gram partials are free again: they hold the projection's tile sums
     if (gp.part_bytes < dfi::gram_project_work_bytes(gp.n)) return fail(DFISHER_E_DEVICE, "projection work too small");
-    HIP_TRY(dfi::gram_project(W, gp.n, 1, lambda, mirror, reinterpret_cast<double*>(B.gpart), B.zc, st));
+    HIP_TRY(dfi::gram_project(W, gp.n, 1, lambda, mirror, reinterpret_cast<double*>(B.gpart), B.zc, st, applied));
   }
   return DFISHER_OK;
 }
@@ -432,13 +452,16 @@ dfisher_status gram_stage(const float* S, const float* v, const dfi::GramPlan& g
 // out = rhs - lambda u - S (S^T u) for an n-vector u (FP64 accumulation): one read of S through the
 // fused pass when `fp` allows it, else a column pass (t = S^T u into B.t) and a row pass. With
 // rhs = b and u = y it is the residual of y; with rhs = 0 and u = p it is -(W p).
+// tout / csout (the whole-line pass only, may be null): S^T u and S^T 1 from the same read of S.
 dfisher_status w_pass(const float* S, int64_t n, int64_t m, int64_t lds, double lambda, const double* u,
                       const double* rhs, double* out, const SolveBufs& B, const dfi::RowPassPlan& rp,
-                      const dfi::ColPassPlan& cp, const dfi::RefinePassPlan* fp, hipStream_t st) {
+                      const dfi::ColPassPlan& cp, const dfi::RefinePassPlan* fp, hipStream_t st,
+                      double* tout = nullptr, double* csout = nullptr) {
   if (fp && fp->usable) {
-    HIP_TRY(dfi::refine_pass_launch(*fp, S, n, m, lds, u, B.rpart, st));
+    HIP_TRY(dfi::refine_pass_launch(*fp, S, n, m, lds, u, B.rpart, st, nullptr, -1, tout, csout));
     HIP_TRY(dfi::refine_pass_reduce(*fp, B.rpart, out, rhs, u, lambda, st));
   } else {
+    if (tout || csout) return fail(DFISHER_E_DEVICE, "S^T u requested from a pass that does not form it");
     HIP_TRY(dfi::colpass_launch(cp, S, n, m, lds, u, nullptr, 1.0, B.t, 2, B.cpart, st));
     HIP_TRY(dfi::rowpass_launch(rp, S, nullptr, B.t, true, false, B.rpart, st));
     HIP_TRY(dfi::rowpass_reduce(rp, B.rpart, true, false, out, nullptr, rhs, u, lambda, st));
@@ -465,13 +488,27 @@ dfisher_status w_pass(const float* S, int64_t n, int64_t m, int64_t lds, double 
 // AUTO_MIN_CONTRACTION_CENTERED for a declared centered S), so that the call stops only once a
 // measured residual is <= tol / predict: the measured contraction of one sweep can hide a slower
 // direction (the all-ones one above, unless the factor was projected).
-// The sweeps of solve_y for any operator: wop(u, rhs, out) enqueues out = rhs - W u (length n).
-using WOp = std::function<dfisher_status(const double* u, const double* rhs, double* out)>;
+// The sweeps of solve_y for any operator: wop(u, rhs, out, tout, csout) enqueues out = rhs - W u
+// (length n) and, where tout / csout are given, S^T u and S^T 1 from the same pass.
+using WOp = std::function<dfisher_status(const double* u, const double* rhs, double* out, double* tout,
+                                         double* csout)>;
+
+// The exact part of the final step's S^T y (apply8.hip), carried through the passes: T = S^T y of
+// the iterate (the residual pass writes S^T y_0; each conjugate-gradient pass writes S^T p into U,
+// added as T += alpha U), and S^T 1 when the all-ones component is split off. The last correction
+// is then left in B.zc for the final step, not added to y.
+struct Final8 {
+  double* T;
+  double* U;
+  double* cs;      // may be null
+  double* alpha;   // device: the last step length
+  int64_t m;
+};
 
 dfisher_status solve_y_op(int64_t n, const double* L, const double* Dinv, const SolveBufs& B, int sweeps,
                           hipStream_t st, const WOp& wop, StageClock* clk = nullptr, dfisher_ctx* ctx = nullptr,
                           double tol = 0.0, int* done = nullptr, double* resid = nullptr, bool initial = true,
-                          double predict = 0.0, bool* met = nullptr) {
+                          double predict = 0.0, bool* met = nullptr, const Final8* f8 = nullptr) {
   if (initial) {   // (else the caller has formed y = L^-T L^-1 b already)
     HIP_TRY(dfi::trsv_launch(L, Dinv, n, 0, B.b, B.z, B.tw, st));
     HIP_TRY(dfi::trsv_launch(L, Dinv, n, 1, B.z, B.y, B.tw, st));
@@ -487,7 +524,7 @@ dfisher_status solve_y_op(int64_t n, const double* L, const double* Dinv, const 
     double* rr = ctx->d_scalar + 3;
     if (measure) HIP_TRY(dfi::sumsq(B.b, n, ctx->d_scalar + 2, st));
     HIP_TRY(dfi::fill_zero(B.zero, n, st));
-    DF_TRY(wop(B.y, B.b, B.r));   // sweep 1: r = b - W y
+    DF_TRY(wop(B.y, B.b, B.r, f8 ? f8->T : nullptr, f8 ? f8->cs : nullptr));   // sweep 1: r = b - W y
     if (measure) HIP_TRY(dfi::sumsq(B.r, n, rr, st));
     double prev = 1.0;
     for (int s = 1;; ++s) {
@@ -512,14 +549,16 @@ dfisher_status solve_y_op(int64_t n, const double* L, const double* Dinv, const 
         }
       }
       if (stop) {
-        HIP_TRY(dfi::pcg_finish(nullptr, n, 0, 1, B.zc, B.y, st));
+        if (!f8) HIP_TRY(dfi::pcg_finish(nullptr, n, 0, 1, B.zc, B.y, st));   // else the final step takes zc
         if (done) *done = s;
         break;
       }
       if (s == 1) HIP_TRY(dfi::pcg_init(nullptr, n, 0, 1, B.r, B.zc, B.p, rz, st));
       else HIP_TRY(dfi::pcg_dir(nullptr, n, 0, 1, B.r, B.zc, B.p, rz, st));
-      DF_TRY(wop(B.p, B.zero, B.nq));   // -(W p)
-      HIP_TRY(dfi::pcg_step(nullptr, n, 0, 1, B.p, B.nq, B.y, B.r, rz, measure ? rr : nullptr, st));
+      DF_TRY(wop(B.p, B.zero, B.nq, f8 ? f8->U : nullptr, nullptr));   // -(W p)
+      HIP_TRY(dfi::pcg_step(nullptr, n, 0, 1, B.p, B.nq, B.y, B.r, rz, measure ? rr : nullptr, st, nullptr,
+                            f8 ? f8->alpha : nullptr));
+      if (f8) HIP_TRY(dfi::t_axpy(f8->T, f8->U, f8->alpha, f8->m, st));
     }
   }
   if (clk) clk->mark(6);
@@ -530,11 +569,11 @@ dfisher_status solve_y(const float* S, int64_t n, int64_t m, int64_t lds, double
                        const double* Dinv, const SolveBufs& B, const dfi::RowPassPlan& rp, const dfi::ColPassPlan& cp,
                        int sweeps, hipStream_t st, StageClock* clk = nullptr, const dfi::RefinePassPlan* fp = nullptr,
                        dfisher_ctx* ctx = nullptr, double tol = 0.0, int* done = nullptr, double* resid = nullptr,
-                       bool initial = true, double predict = 0.0, bool* met = nullptr) {
-  const WOp wop = [&](const double* u, const double* rhs, double* out) {
-    return w_pass(S, n, m, lds, lambda, u, rhs, out, B, rp, cp, fp, st);
+                       bool initial = true, double predict = 0.0, bool* met = nullptr, const Final8* f8 = nullptr) {
+  const WOp wop = [&](const double* u, const double* rhs, double* out, double* tout, double* csout) {
+    return w_pass(S, n, m, lds, lambda, u, rhs, out, B, rp, cp, fp, st, tout, csout);
   };
-  return solve_y_op(n, L, Dinv, B, sweeps, st, wop, clk, ctx, tol, done, resid, initial, predict, met);
+  return solve_y_op(n, L, Dinv, B, sweeps, st, wop, clk, ctx, tol, done, resid, initial, predict, met, f8);
 }
 
 // r = b - lambda y - S (S^T y) for the current y (FP64), then w = |r| / |b| read back to the host
@@ -1674,12 +1713,16 @@ dfisher_status dfisher_solve(dfisher_ctx* ctx, const float* S, int64_t n, int64_
   const dfi::ColPassPlan cp = dfi::colpass_plan(n, m);
   const dfi::RefinePassPlan fp = dfi::refine_pass_plan(n, m, lds, S);
   const bool need_t = (o.sweeps != 0 || o.final_resid) && !fp.usable;
-  SolveBufs B = carve(nullptr, n, m, &gp, rp, cp, true, need_t, &fp);
+  // the final step may take the last correction's image through the FP8 codes (apply8.hip): the
+  // codes exist, the passes can carry S^T y, there is a correction, and the caller allows it
+  const bool final8 = o.gram_prec == DFISHER_GRAM_MXFP8 && fp.usable && fp.line && o.sweeps != 0 &&
+                      !o.final_resid && (o.flags & DFISHER_EXACT_APPLY) == 0;
+  SolveBufs B = carve(nullptr, n, m, &gp, rp, cp, true, need_t, &fp, final8, is_centered(o));
   DF_TRY(ensure_ws(ctx, B.bytes));
-  B = carve(static_cast<char*>(ctx->ws), n, m, &gp, rp, cp, true, need_t, &fp);
+  B = carve(static_cast<char*>(ctx->ws), n, m, &gp, rp, cp, true, need_t, &fp, final8, is_centered(o));
   StageClock clk(ctx, st);
   // one pass over S (b = S v, the exact diagonal |s_i|^2, the FP8 codes if used), then step 1
-  DF_TRY(gram_stage(S, v, gp, rp, B, lambda, B.W, 0, st, &clk, is_centered(o)));
+  DF_TRY(gram_stage(S, v, gp, rp, B, lambda, B.W, 0, st, &clk, is_centered(o), B.cs8 ? B.use8 + 1 : nullptr));
   // step 2 (with the shift policy)
   clk.mark(3);
   dfisher_info inf{};
@@ -1706,11 +1749,24 @@ dfisher_status dfisher_solve(dfisher_ctx* ctx, const float* S, int64_t n, int64_
   int done = 0;
   double resid = -1.0;
   bool met = false;
+  const Final8 f8{B.T8, B.U8, B.cs8, B.a8, m};
   DF_TRY(solve_y(S, n, m, lds, lambda, B.L, B.Dinv, B, rp, cp, sweeps, st, &clk, &fp, ctx, tol, &done, &resid,
-                 false, autos ? auto_floor(o) : 0.0, &met));
+                 false, autos ? auto_floor(o) : 0.0, &met, final8 ? &f8 : nullptr));
   inf.w_resid = -1.0;
   if (o.final_resid) DF_TRY(final_residual(ctx, S, n, m, lds, lambda, B, rp, cp, fp, st, &inf.w_resid));
-  HIP_TRY(dfi::colpass_launch(cp, S, n, m, lds, B.y, v, lambda, x, o.x_fp64, B.cpart, st));
+  if (final8) {
+    // x = (v - T - S^T zc) / lambda with S^T zc through the codes when the device finds that
+    // accurate enough; otherwise y += zc there and the exact column pass runs (one of the two
+    // kernels returns at once)
+    // (the all-ones component is split off only where the projection was applied: a declaration
+    // the device rejected leaves the call bitwise that of the call without it)
+    HIP_TRY(dfi::final_decide(n, B.y, B.zc, B.b, B.d, lambda, B.cs8 ? B.use8 + 1 : nullptr, FINAL8_EST_MAX, B.zf8,
+                              B.a8 + 1, B.use8, st));
+    HIP_TRY(dfi::fp8_apply(B.q8, B.sc8, B.ldq, n, m, B.zf8, B.T8, B.cs8, B.a8 + 1, v, lambda, x, o.x_fp64, B.use8, st));
+    HIP_TRY(dfi::colpass_launch(cp, S, n, m, lds, B.y, v, lambda, x, o.x_fp64, B.cpart, st, B.use8));
+  } else {
+    HIP_TRY(dfi::colpass_launch(cp, S, n, m, lds, B.y, v, lambda, x, o.x_fp64, B.cpart, st));
+  }
   clk.mark(7);
   inf.sweeps_done = done;
   inf.resid = resid;
@@ -1907,7 +1963,7 @@ dfisher_status dfisher_solve_complex(dfisher_ctx* ctx, const float* Z, int64_t n
     return DFISHER_OK;
   };
   // out = rhs - lambda u - E (E^T u)
-  const WOp wop = [&](const double* u, const double* rhs, double* out) -> dfisher_status {
+  const WOp wop = [&](const double* u, const double* rhs, double* out, double*, double*) -> dfisher_status {
     DF_TRY(et(u));
     dfi::MultiVecs none{};
     dfi::MultiOut mo{};
@@ -1935,7 +1991,7 @@ dfisher_status dfisher_solve_complex(dfisher_ctx* ctx, const float* Z, int64_t n
                     autos ? auto_floor(o) : 0.0, &met));
   inf.w_resid = -1.0;
   if (o.final_resid) {
-    DF_TRY(wop(B.y, B.b, B.r));
+    DF_TRY(wop(B.y, B.b, B.r, nullptr, nullptr));
     HIP_TRY(dfi::sumsq(B.b, N, ctx->d_scalar + 2, st));
     HIP_TRY(dfi::sumsq(B.r, N, ctx->d_scalar + 3, st));
     HIP_TRY(hipMemcpyAsync(ctx->h_scalar + 2, ctx->d_scalar + 2, 2 * sizeof(double), hipMemcpyDeviceToHost, st));

@@ -90,8 +90,10 @@ struct ColPassPlan {
   size_t part_bytes;  // nsplit * m * 8 when nsplit > 1, else 0
 };
 ColPassPlan colpass_plan(int64_t n, int64_t m);
+// skip (device int, may be null): when *skip != 0 at run time the kernels return at once.
 hipError_t colpass_launch(const ColPassPlan& p, const float* S, int64_t n, int64_t m, int64_t lds, const double* y,
-                          const float* v, double lambda, void* out, int mode, double* part, hipStream_t st);
+                          const float* v, double lambda, void* out, int mode, double* part, hipStream_t st,
+                          const int* skip = nullptr);
 
 // Fused refinement pass: part[g][i] = per-workgroup partials of (S S^T y)_i with one read of S
 // (n <= 4096, m >= 16, 16-byte aligned rows; `usable` is false otherwise and
@@ -116,9 +118,11 @@ RefinePassPlan refine_pass_plan(int64_t n, int64_t m, int64_t lds, const float* 
 // skip (device int, may be null): when *skip != 0 at run time the kernels return at once (a
 // problem whose refinement stopped, in a launch sequence fixed in advance). spin: the split
 // kernel's bound on polls for its partner's partials (< 0: the default; 0: always compute them).
+// tout / csout (whole-line kernels only, may be null): the pass also writes t = S^T y and the
+// column sums S^T 1 (FP64, m entries), both from the sums it forms for the product.
 hipError_t refine_pass_launch(const RefinePassPlan& p, const float* S, int64_t n, int64_t m, int64_t lds,
                               const double* y, double* part, hipStream_t st, const int* skip = nullptr,
-                              int spin = -1);
+                              int spin = -1, double* tout = nullptr, double* csout = nullptr);
 hipError_t refine_pass_reduce(const RefinePassPlan& p, const double* part, double* r, const double* b,
                               const double* y, double lam, hipStream_t st, const int* skip = nullptr);
 
@@ -227,8 +231,10 @@ hipError_t trsv_launch_grouped(const TrsvJob* jobs_dev, int64_t njobs, int64_t n
 // stop (device, per segment, may be null): segments with stop[s] != 0 are left alone.
 hipError_t pcg_init(const int64_t* seg, int64_t n, int64_t s0, int64_t s1, const double* r, const double* z, double* p,
                     double* rz, hipStream_t st, const int* stop = nullptr);
+// alpha (may be null): the step length of each segment is also stored there.
 hipError_t pcg_step(const int64_t* seg, int64_t n, int64_t s0, int64_t s1, const double* p, const double* nq, double* y,
-                    double* r, const double* rz, double* rr, hipStream_t st, const int* stop = nullptr);
+                    double* r, const double* rz, double* rr, hipStream_t st, const int* stop = nullptr,
+                    double* alpha = nullptr);
 hipError_t pcg_dir(const int64_t* seg, int64_t n, int64_t s0, int64_t s1, const double* r, const double* z, double* p,
                    double* rz, hipStream_t st, const int* stop = nullptr);
 // out[s] = |x_s|^2
@@ -269,7 +275,8 @@ hipError_t center_write(const float* O, int64_t n, int64_t m, int64_t ldo, int c
 // and totals), r: nseg * n doubles.
 size_t gram_project_work_bytes(int64_t n);
 hipError_t gram_project(double* W, int64_t n, int nseg, double lambda, int full, double* work, double* r,
-                        hipStream_t st);
+                        hipStream_t st,
+                        int* applied = nullptr);
 hipError_t fill_value(double* y, int64_t n, double value, hipStream_t st);
 // interleaved complex FP32 v (m) -> out[0..m) real parts, out[m..2m) imaginary parts
 hipError_t deinterleave(const float* v, int64_t m, float* out, hipStream_t st);
@@ -302,5 +309,29 @@ hipError_t diag_max(const double* W, int64_t n, double* out_dev, hipStream_t st)
 hipError_t sumsq(const double* x, int64_t n, double* out_dev, hipStream_t st);
 // zero the strict upper triangle
 hipError_t zero_upper(double* A, int64_t n, hipStream_t st);
+
+// ----------------------------------------------------------------------------- final step through the FP8 codes
+// The apply x = (v - S^T y) / lambda after the last refinement correction z (apply8.hip). The passes
+// carry T = S^T y_c exactly for the iterate y_c before that correction (the residual pass writes
+// S^T y_0, each conjugate-gradient pass S^T p, added with its step length), so
+// S^T (y_c + z) = T + S^T z, and only the image of the small correction is left to take: through
+// the scaled-FP8 copy Q of S the row pass wrote (one byte per entry instead of four). That costs a
+// relative error of about 3 % of |S^T z|, which final_decide estimates and allows only while it is
+// far below the solve's target.
+// t_axpy: T += alpha[0] U (m entries).
+hipError_t t_axpy(double* T, const double* U, const double* alpha, int64_t m, hipStream_t st);
+// One workgroup. abar = mean(z) when *centered (device, may be null: not centered; the all-ones component, whose image is the exact
+// abar S^T 1 = abar cs), zf = float(z - abar); est = sqrt(sum_i d_i zf_i^2 / (y.b - lambda y.y))
+// (d_i = |s_i|^2: the expected size of Q^T zf - S^T zf over the relative rounding error, for rounding
+// errors independent between entries, against |S^T y|). use = est <= est_max; otherwise y += z
+// (the exact apply then takes the corrected iterate).
+hipError_t final_decide(int64_t n, double* y, const double* z, const double* b, const double* d, double lambda,
+                        const int* centered, double est_max, float* zf, double* abar, int* use, hipStream_t st);
+// When *use: x_j = (v_j - T_j - abar cs_j - sum_i Q_ij zf_i) / lambda (cs may be null: abar is 0
+// then), FP32 or FP64 x, codes and scales in the row pass's column-blocked layout (ldq a multiple
+// of 128). Otherwise returns at once.
+hipError_t fp8_apply(const uint8_t* q, const uint8_t* sc, int64_t ldq, int64_t n, int64_t m, const float* zf,
+                     const double* T, const double* cs, const double* abar, const float* v, double lambda, void* x,
+                     int x64, const int* use, hipStream_t st);
 
 }  // namespace dfi

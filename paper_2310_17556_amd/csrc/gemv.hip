@@ -239,7 +239,9 @@ __device__ __forceinline__ void colpass_store(void* out, const float* v, double 
 template <int MODE>
 __global__ void __launch_bounds__(CP_THREADS)
 colpass_kernel(const float* __restrict__ S, int64_t n, int64_t m, int64_t lds, const double* __restrict__ y,
-               const float* v, double lam, void* out, double* __restrict__ part, int64_t rps, int vec) {
+               const float* v, double lam, void* out, double* __restrict__ part, int64_t rps, int vec,
+               const int* __restrict__ skip) {
+  if (skip && *skip) return;
   const int64_t col = (int64_t)blockIdx.x * CP_COLS + 4 * threadIdx.x;
   const int64_t r0 = (int64_t)blockIdx.y * rps;
   const int64_t r1 = min(n, r0 + rps);
@@ -291,7 +293,8 @@ colpass_kernel(const float* __restrict__ S, int64_t n, int64_t m, int64_t lds, c
 
 template <int MODE>
 __global__ void colpass_finalize_kernel(const double* __restrict__ part, int64_t nsplit, int64_t m, const float* v,
-                                        double lam, void* out) {
+                                        double lam, void* out, const int* __restrict__ skip) {
+  if (skip && *skip) return;
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= m) return;
   double t = 0.0;
@@ -594,18 +597,20 @@ constexpr int FS_COLS = 32;
 constexpr int FS_HALF = 2048;        // rows of the first half (64 rows per load step x 32 loads)
 constexpr int FS_SPIN = 4096;        // polls (s_sleep 2 each, ~0.2 ms in all) before computing it here
 
-template <int NCH, bool SPLIT>
+template <int NCH, bool SPLIT, bool CS>
 __global__ void __launch_bounds__(64 * FR_WAVES)
 refine_line_kernel(const float* __restrict__ S, int64_t n, int64_t m, int64_t lds, const double* __restrict__ y,
                    double* __restrict__ part, double* __restrict__ xch, int* __restrict__ prog, int64_t R,
-                   int spin, const int* __restrict__ skip) {
+                   int spin, const int* __restrict__ skip, double* __restrict__ tout, double* __restrict__ csout) {
   constexpr int ROWS = 8 * FR_WAVES;   // rows per load step of the workgroup (8 per wave)
   static_assert(!SPLIT || NCH * ROWS == FS_HALF, "a split block's first half is one workgroup's rows");
   if (skip && *skip) return;
   __shared__ double ys[ROWS * NCH];
-  __shared__ double tp[FR_WAVES][FS_COLS];
-  __shared__ double tf[FS_COLS];
+  __shared__ double tp[FR_WAVES][2 * FS_COLS];   // per wave: column partials of S^T y, then of S^T 1
+  __shared__ double tf[2 * FS_COLS];
   __shared__ int got;
+  constexpr bool wcs = CS;                        // also the column sums S^T 1 into csout
+  constexpr int nl = CS ? 2 * FS_COLS : FS_COLS;  // lanes of wave 0 that carry a column value
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -646,20 +651,31 @@ refine_line_kernel(const float* __restrict__ S, int64_t n, int64_t m, int64_t ld
         __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(bp), 0, in ? rin * rowbytes : 0, 0x00020000);
     return __builtin_bit_cast(f32x4, __builtin_amdgcn_raw_buffer_load_b128(rs, (int)loff, 0, 0));
   };
-  // column partials of one half from per-lane sums tq (4 columns per lane): lanes of equal q, then
-  // the waves in a fixed order; the result lands in tp / is read back by wave 0 lanes 0 .. 31
-  auto reduce_cols = [&](double* tq) {
+  // column partials of one half from per-lane sums tq (4 columns per lane; with the column sums,
+  // cq likewise): lanes of equal q, then the waves in a fixed order; the result lands in tp / is
+  // read back by wave 0, lanes 0 .. 31 (S^T y) and 32 .. 63 (S^T 1)
+  auto reduce_cols = [&](double* tq, f32x4 cq) {
 #pragma unroll
     for (int o = 8; o < 64; o <<= 1)
 #pragma unroll
       for (int e = 0; e < 4; ++e) tq[e] += __shfl_xor(tq[e], o, 64);
+    if constexpr (CS) {
+#pragma unroll
+      for (int o = 8; o < 64; o <<= 1)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) cq[e] += __shfl_xor(cq[e], o, 64);
+    }
     if ((lane >> 3) == 0) {
 #pragma unroll
       for (int e = 0; e < 4; ++e) tp[wave][4 * q + e] = tq[e];
+      if constexpr (CS) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) tp[wave][FS_COLS + 4 * q + e] = (double)cq[e];
+      }
     }
     __syncthreads();
     double v = 0.0;
-    if (wave == 0 && lane < FS_COLS)
+    if (wave == 0 && lane < nl)
       v = ((tp[0][lane] + tp[1][lane]) + (tp[2][lane] + tp[3][lane])) +
           ((tp[4][lane] + tp[5][lane]) + (tp[6][lane] + tp[7][lane]));
     __syncthreads();
@@ -686,19 +702,28 @@ refine_line_kernel(const float* __restrict__ S, int64_t n, int64_t m, int64_t ld
 #pragma unroll
       for (int e = 0; e < 4; ++e) tq[e] = fma((double)sv[c][e], yr, tq[e]);
     }
-    const double own = reduce_cols(tq);
+    // the column sums over this lane's rows and then over the lanes in FP32 (they scale a small
+    // correction term: 1e-5 relative is plenty), over the waves in FP64
+    f32x4 cq = {0.f, 0.f, 0.f, 0.f};
+    if constexpr (CS) {
+#pragma unroll
+      for (int c = 0; c < NCH; ++c) cq += sv[c];
+    }
+    const double own = reduce_cols(tq, cq);
+    double tcol = 0.0;   // wave 0, lane < nl: this block's final value of column lane % 32
     if constexpr (!SPLIT) {
-      if (wave == 0 && lane < FS_COLS) tf[lane] = own;
+      if (wave == 0 && lane < nl) tf[lane] = own;
+      tcol = own;
       (void)k;
     } else {
-    double* slot = xch + ((pair * R + k) * 2) * FS_COLS;   // [h = 0 | h = 1] x 32 columns
+    double* slot = xch + ((pair * R + k) * 2) * (2 * FS_COLS);   // [h = 0 | h = 1] x (32 + 32 columns)
     // Publication without fences: an agent-scope fence writes back and invalidates the whole L2
     // of the XCD, every block, for every workgroup. The partials and the counter are agent-scope
     // relaxed atomics instead (device-coherent accesses that skip the non-coherent caches), the
     // counter stored only once the partials' stores have completed (vmcnt 0), and the reader takes
     // the partials only after it has seen the counter.
     if (wave == 0) {
-      if (lane < FS_COLS) __hip_atomic_store(slot + h * FS_COLS + lane, own, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (lane < nl) __hip_atomic_store(slot + h * 2 * FS_COLS + lane, own, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0): the partials are stored
       if (lane == 0) {
         __hip_atomic_store(prog + pair * 2 + h, (int)(k + 1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -716,11 +741,12 @@ refine_line_kernel(const float* __restrict__ S, int64_t n, int64_t m, int64_t ld
     __syncthreads();
     double other = 0.0;
     if (got) {
-      if (wave == 0 && lane < FS_COLS)
-        other = __hip_atomic_load(slot + (1 - h) * FS_COLS + lane, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (wave == 0 && lane < nl)
+        other = __hip_atomic_load(slot + (1 - h) * 2 * FS_COLS + lane, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     } else {
-      // the partner's partial, computed here in its order (one load in flight per lane: rare path)
+      // the partner's partials, computed here in its order (one load in flight per lane: rare path)
       double pq[4] = {0.0, 0.0, 0.0, 0.0};
+      f32x4 pc = {0.f, 0.f, 0.f, 0.f};
       for (int c = 0; c < NCH; ++c) {
         f32x4 v = load(blk, prow0, pnh, c, true);
         if (blk == nfull) mask_tail(v, blk);
@@ -728,10 +754,23 @@ refine_line_kernel(const float* __restrict__ S, int64_t n, int64_t m, int64_t ld
         const double yr = pr < pnh ? y[prow0 + pr] : 0.0;
 #pragma unroll
         for (int e = 0; e < 4; ++e) pq[e] = fma((double)v[e], yr, pq[e]);
+        if constexpr (CS) pc += v;
       }
-      other = reduce_cols(pq);
+      other = reduce_cols(pq, pc);
     }
-    if (wave == 0 && lane < FS_COLS) tf[lane] = h == 0 ? own + other : other + own;
+    tcol = h == 0 ? own + other : other + own;
+    if (wave == 0 && lane < nl) tf[lane] = tcol;
+    }
+    // the block's columns of S^T y (and S^T 1) to memory when asked: one writer per block
+    if (wave == 0 && lane < nl && (!SPLIT || h == 0)) {
+      const int64_t col = blk * FS_COLS + (lane & (FS_COLS - 1));
+      if (col < m) {
+        if (lane < FS_COLS) {
+          if (tout) tout[col] = tcol;
+        } else {
+          csout[col] = tcol;
+        }
+      }
     }
     __syncthreads();
     double t[4];
@@ -906,25 +945,26 @@ ColPassPlan colpass_plan(int64_t n, int64_t m) {
 }
 
 hipError_t colpass_launch(const ColPassPlan& p, const float* S, int64_t n, int64_t m, int64_t lds, const double* y,
-                          const float* v, double lambda, void* out, int mode, double* part, hipStream_t st) {
+                          const float* v, double lambda, void* out, int mode, double* part, hipStream_t st,
+                          const int* skip) {
   const bool vec = ((lds & 3) == 0) && aligned16(S);
   const dim3 grid((unsigned)((m + CP_COLS - 1) / CP_COLS), (unsigned)p.nsplit);
   double* pp = p.nsplit > 1 ? part : nullptr;
   const int iv = vec ? 1 : 0;
   switch (mode) {
-    case 0: hipLaunchKernelGGL(colpass_kernel<0>, grid, dim3(CP_THREADS), 0, st, S, n, m, lds, y, v, lambda, out, pp, p.rps, iv); break;
-    case 1: hipLaunchKernelGGL(colpass_kernel<1>, grid, dim3(CP_THREADS), 0, st, S, n, m, lds, y, v, lambda, out, pp, p.rps, iv); break;
-    case 3: hipLaunchKernelGGL(colpass_kernel<3>, grid, dim3(CP_THREADS), 0, st, S, n, m, lds, y, v, lambda, out, pp, p.rps, iv); break;
-    default: hipLaunchKernelGGL(colpass_kernel<2>, grid, dim3(CP_THREADS), 0, st, S, n, m, lds, y, v, lambda, out, pp, p.rps, iv); break;
+    case 0: hipLaunchKernelGGL(colpass_kernel<0>, grid, dim3(CP_THREADS), 0, st, S, n, m, lds, y, v, lambda, out, pp, p.rps, iv, skip); break;
+    case 1: hipLaunchKernelGGL(colpass_kernel<1>, grid, dim3(CP_THREADS), 0, st, S, n, m, lds, y, v, lambda, out, pp, p.rps, iv, skip); break;
+    case 3: hipLaunchKernelGGL(colpass_kernel<3>, grid, dim3(CP_THREADS), 0, st, S, n, m, lds, y, v, lambda, out, pp, p.rps, iv, skip); break;
+    default: hipLaunchKernelGGL(colpass_kernel<2>, grid, dim3(CP_THREADS), 0, st, S, n, m, lds, y, v, lambda, out, pp, p.rps, iv, skip); break;
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || p.nsplit == 1) return e;
   const dim3 g2((unsigned)((m + 255) / 256));
   switch (mode) {
-    case 0: hipLaunchKernelGGL(colpass_finalize_kernel<0>, g2, dim3(256), 0, st, part, p.nsplit, m, v, lambda, out); break;
-    case 1: hipLaunchKernelGGL(colpass_finalize_kernel<1>, g2, dim3(256), 0, st, part, p.nsplit, m, v, lambda, out); break;
-    case 3: hipLaunchKernelGGL(colpass_finalize_kernel<3>, g2, dim3(256), 0, st, part, p.nsplit, m, v, lambda, out); break;
-    default: hipLaunchKernelGGL(colpass_finalize_kernel<2>, g2, dim3(256), 0, st, part, p.nsplit, m, v, lambda, out); break;
+    case 0: hipLaunchKernelGGL(colpass_finalize_kernel<0>, g2, dim3(256), 0, st, part, p.nsplit, m, v, lambda, out, skip); break;
+    case 1: hipLaunchKernelGGL(colpass_finalize_kernel<1>, g2, dim3(256), 0, st, part, p.nsplit, m, v, lambda, out, skip); break;
+    case 3: hipLaunchKernelGGL(colpass_finalize_kernel<3>, g2, dim3(256), 0, st, part, p.nsplit, m, v, lambda, out, skip); break;
+    default: hipLaunchKernelGGL(colpass_finalize_kernel<2>, g2, dim3(256), 0, st, part, p.nsplit, m, v, lambda, out, skip); break;
   }
   return hipGetLastError();
 }
@@ -953,7 +993,7 @@ RefinePassPlan refine_pass_plan(int64_t n, int64_t m, int64_t lds, const float* 
     p.tail = false;
     const size_t groups = (size_t)(p.ngroups + (p.tail ? 1 : 0)) * (size_t)n;
     p.xch_off = groups;
-    p.prog_off = groups + (size_t)npairs * (size_t)p.R * 2 * FS_COLS;
+    p.prog_off = groups + (size_t)npairs * (size_t)p.R * 2 * (2 * FS_COLS);
     p.part_bytes = p.prog_off * sizeof(double) + (size_t)(2 * npairs) * sizeof(int);
     return p;
   }
@@ -978,8 +1018,10 @@ RefinePassPlan refine_pass_plan(int64_t n, int64_t m, int64_t lds, const float* 
 }
 
 hipError_t refine_pass_launch(const RefinePassPlan& p, const float* S, int64_t n, int64_t m, int64_t lds,
-                              const double* y, double* part, hipStream_t st, const int* skip, int spin) {
+                              const double* y, double* part, hipStream_t st, const int* skip, int spin, double* tout,
+                              double* csout) {
   if (!p.usable || p.n != n) return hipErrorInvalidValue;
+  if ((tout || csout) && !p.line) return hipErrorInvalidValue;   // only the whole-line kernels write them
   const dim3 grid((unsigned)p.ngroups), block(64 * FR_WAVES);
   if (p.split) {   // the pairs' progress counters start at zero
     int* prog = reinterpret_cast<int*>(part + p.prog_off);
@@ -989,21 +1031,37 @@ hipError_t refine_pass_launch(const RefinePassPlan& p, const float* S, int64_t n
       const char* e = std::getenv("DFISHER_PAIR_SPIN");
       spin = e ? std::max(0, std::atoi(e)) : FS_SPIN;
     }
-    hipLaunchKernelGGL((refine_line_kernel<32, true>), grid, block, 0, st, S, n, m, lds, y, part, part + p.xch_off,
-                       prog, p.R, spin, skip);
+    if (csout)
+      hipLaunchKernelGGL((refine_line_kernel<32, true, true>), grid, block, 0, st, S, n, m, lds, y, part,
+                         part + p.xch_off, prog, p.R, spin, skip, tout, csout);
+    else
+      hipLaunchKernelGGL((refine_line_kernel<32, true, false>), grid, block, 0, st, S, n, m, lds, y, part,
+                         part + p.xch_off, prog, p.R, spin, skip, tout, csout);
   } else if (p.line) {
     switch (p.lnch) {
       case 8:
-        hipLaunchKernelGGL((refine_line_kernel<8, false>), grid, block, 0, st, S, n, m, lds, y, part,
-                           (double*)nullptr, (int*)nullptr, p.R, 0, skip);
+        if (csout)
+          hipLaunchKernelGGL((refine_line_kernel<8, false, true>), grid, block, 0, st, S, n, m, lds, y, part,
+                             (double*)nullptr, (int*)nullptr, p.R, 0, skip, tout, csout);
+        else
+          hipLaunchKernelGGL((refine_line_kernel<8, false, false>), grid, block, 0, st, S, n, m, lds, y, part,
+                             (double*)nullptr, (int*)nullptr, p.R, 0, skip, tout, csout);
         break;
       case 16:
-        hipLaunchKernelGGL((refine_line_kernel<16, false>), grid, block, 0, st, S, n, m, lds, y, part,
-                           (double*)nullptr, (int*)nullptr, p.R, 0, skip);
+        if (csout)
+          hipLaunchKernelGGL((refine_line_kernel<16, false, true>), grid, block, 0, st, S, n, m, lds, y, part,
+                             (double*)nullptr, (int*)nullptr, p.R, 0, skip, tout, csout);
+        else
+          hipLaunchKernelGGL((refine_line_kernel<16, false, false>), grid, block, 0, st, S, n, m, lds, y, part,
+                             (double*)nullptr, (int*)nullptr, p.R, 0, skip, tout, csout);
         break;
       default:
-        hipLaunchKernelGGL((refine_line_kernel<32, false>), grid, block, 0, st, S, n, m, lds, y, part,
-                           (double*)nullptr, (int*)nullptr, p.R, 0, skip);
+        if (csout)
+          hipLaunchKernelGGL((refine_line_kernel<32, false, true>), grid, block, 0, st, S, n, m, lds, y, part,
+                             (double*)nullptr, (int*)nullptr, p.R, 0, skip, tout, csout);
+        else
+          hipLaunchKernelGGL((refine_line_kernel<32, false, false>), grid, block, 0, st, S, n, m, lds, y, part,
+                             (double*)nullptr, (int*)nullptr, p.R, 0, skip, tout, csout);
         break;
     }
   }

@@ -65,7 +65,7 @@ __global__ void __launch_bounds__(PT) pcg_step_kernel(const int64_t* __restrict_
                                                       const double* __restrict__ p, const double* __restrict__ nq,
                                                       double* __restrict__ y, double* __restrict__ r,
                                                       const double* __restrict__ rz, double* __restrict__ rr,
-                                                      const int* __restrict__ stop) {
+                                                      const int* __restrict__ stop, double* __restrict__ alpha) {
   __shared__ double red[PT];
   const int64_t s = s0 + blockIdx.x;
   if (stop && stop[s]) return;
@@ -75,6 +75,7 @@ __global__ void __launch_bounds__(PT) pcg_step_kernel(const int64_t* __restrict_
   for (int64_t i = threadIdx.x; i < len; i += PT) acc = fma(p[off + i], -nq[off + i], acc);
   const double pq = block_sum(acc, red);
   const double a = (pq > 0.0 && rz[s] > 0.0) ? rz[s] / pq : 0.0;
+  if (alpha && threadIdx.x == 0) alpha[s] = a;
   double acc2 = 0.0;
   for (int64_t i = threadIdx.x; i < len; i += PT) {
     y[off + i] = fma(a, p[off + i], y[off + i]);
@@ -202,10 +203,10 @@ hipError_t pcg_init(const int64_t* seg, int64_t n, int64_t s0, int64_t s1, const
 }
 
 hipError_t pcg_step(const int64_t* seg, int64_t n, int64_t s0, int64_t s1, const double* p, const double* nq, double* y,
-                    double* r, const double* rz, double* rr, hipStream_t st, const int* stop) {
+                    double* r, const double* rz, double* rr, hipStream_t st, const int* stop, double* alpha) {
   if (s1 <= s0) return hipSuccess;
   hipLaunchKernelGGL(pcg_step_kernel, dim3((unsigned)(s1 - s0)), dim3(PT), 0, st, seg, n, s0, p, nq, y, r, rz, rr,
-                     stop);
+                     stop, alpha);
   return hipGetLastError();
 }
 

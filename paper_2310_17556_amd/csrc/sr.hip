@@ -238,10 +238,14 @@ constexpr double CENTER_GUARD = 0.01;
 
 __global__ void __launch_bounds__(256) project_update_kernel(double* __restrict__ W, int64_t n, int64_t l, int nseg,
                                                              const double* __restrict__ r, const double* __restrict__ c,
-                                                             double lambda, int full, int64_t nb) {
+                                                             double lambda, int full, int64_t nb,
+                                                             int* __restrict__ applied) {
   const double dbar = c[nseg * nseg] / (double)n - lambda;
+  bool ok = true;
   for (int s = 0; s < nseg; ++s)
-    if (!(c[s * nseg + s] / (double)l - lambda <= CENTER_GUARD * dbar)) return;
+    if (!(c[s * nseg + s] / (double)l - lambda <= CENTER_GUARD * dbar)) ok = false;
+  if (applied && blockIdx.x == 0 && threadIdx.x == 0) *applied = ok ? 1 : 0;
+  if (!ok) return;
   const int64_t i = (int64_t)blockIdx.x / nb;
   const int64_t j = ((int64_t)blockIdx.x - i * nb) * 256 + threadIdx.x;
   if (j >= n || (!full && j > i)) return;
@@ -273,7 +277,7 @@ size_t gram_project_work_bytes(int64_t n) {
 }
 
 hipError_t gram_project(double* W, int64_t n, int nseg, double lambda, int full, double* work, double* r,
-                        hipStream_t st) {
+                        hipStream_t st, int* applied) {
   if (n < 1 || nseg < 1 || nseg > 2 || n % nseg != 0) return hipErrorInvalidValue;
   const int64_t l = n / nseg;
   const int64_t T = (n + 63) / 64;
@@ -283,7 +287,7 @@ hipError_t gram_project(double* W, int64_t n, int nseg, double lambda, int full,
   hipLaunchKernelGGL(seg_total_kernel, dim3(1), dim3(256), 0, st, W, r, n, l, nseg, c);
   const int64_t nb = (n + 255) / 256;
   hipLaunchKernelGGL(project_update_kernel, dim3((unsigned)(nb * n)), dim3(256), 0, st, W, n, l, nseg, r, c, lambda,
-                     full, nb);
+                     full, nb, applied);
   return hipGetLastError();
 }
 

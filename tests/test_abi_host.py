@@ -79,7 +79,7 @@ def test_invalid_arguments_rejected_on_host(dfl):
         assert lib.dfisher_solve(FAKE_CTX, P, 4, 8, 8, P, lam, P, None, st, ctypes.byref(info)) == E
     for o in [_opts(dfl, prec=5), _opts(dfl, sweeps=-2), _opts(dfl, sweeps=17), _opts(dfl, shift=3),
               _opts(dfl, x64=2), _opts(dfl, tol=-1e-9), _opts(dfl, tol=float("nan")), _opts(dfl, tol=float("inf")),
-              _opts(dfl, final=2), _opts(dfl, flags=4), _opts(dfl, flags=-1)]:
+              _opts(dfl, final=2), _opts(dfl, flags=8), _opts(dfl, flags=-1)]:
         assert lib.dfisher_solve(FAKE_CTX, P, 4, 8, 8, P, 1.0, P, ctypes.byref(o), st, None) == E
     assert lib.dfisher_solve(FAKE_CTX, P, 4, 8, 8, None, 1.0, P, None, st, None) == E
     assert lib.dfisher_solve(FAKE_CTX, P, 4, 8, 8, P, 1.0, None, None, st, None) == E

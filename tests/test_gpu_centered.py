@@ -148,12 +148,17 @@ def test_fp8_two_sweeps_centered(dfl, ctx, c3_small, lam):
     print(f"[centered fp8] n={S.shape[0]} m={S.shape[1]} lam={lam}", flush=True)
     Sd, vd = dev(S), dev(v)
     out = {}
-    for centered in (False, True):
-        x, info = dfl.dfisher_solve(ctx, Sd, vd, lam, gram_prec=2, sweeps=2, x_fp64=True, centered=centered)
+    for centered in (False, True):   # the refinement itself: the final step over S
+        x, info = dfl.dfisher_solve(ctx, Sd, vd, lam, gram_prec=2, sweeps=2, x_fp64=True, centered=centered,
+                                    exact_apply=True)
         out[centered] = eps_sy(x.cpu().numpy(), refs[lam], v, lam)
-    print(f"    eps_Sy plain {out[False]:.3e} centered {out[True]:.3e}", flush=True)
+    # as called by default, the last correction's image through the FP8 codes
+    x8, _ = dfl.dfisher_solve(ctx, Sd, vd, lam, gram_prec=2, sweeps=2, x_fp64=True, centered=True)
+    e8 = eps_sy(x8.cpu().numpy(), refs[lam], v, lam)
+    print(f"    eps_Sy plain {out[False]:.3e} centered {out[True]:.3e}, FP8 final step {e8:.3e}", flush=True)
     assert out[True] <= 1e-8
     assert out[True] <= out[False]
+    assert e8 <= 2e-7
 
 
 def test_fp8_auto_centered_needs_fewer_sweeps(dfl, ctx, c3_small):

@@ -34,6 +34,8 @@ HOT = {
     "potf2_kernel": "potrf.hip",
     "update_kernel": "potrf.hip",
     "trsm_kernel": "potrf.hip",
+    "fp8_apply_kernel": "apply8.hip",
+    "final_decide_kernel": "apply8.hip",
     "fwd_step_kernel": "trsv.hip",
     "bwd_step_kernel": "trsv.hip",
 }
