@@ -401,8 +401,8 @@ def batched_leg(dfl, dev, prec, sweeps, reps, n=2048, m=2_000_000, nlam=16, nrhs
 def uneven_leg(dfl, dev, prec, sweeps, reps, nprob=64, seed=5):
     """64 independent problems, n log-uniform in [256, 2048], m log-uniform in [1e5, 2e6],
     lambda log-uniform in [1e-5, 1e-2]: one dfisher_solve_uneven call per step. Every problem's
-    error is measured against FP64 (x and eps_Sy from an FP64-output call that also reports the
-    final residual)."""
+    error is measured against FP64 (x and eps_Sy from an FP64-output call as timed, and from one
+    that also reports the final residual, which takes the exact final pass)."""
     import torch
 
     import synth
@@ -424,19 +424,34 @@ def uneven_leg(dfl, dev, prec, sweeps, reps, nprob=64, seed=5):
         _, infos = dfl.dfisher_solve_uneven(ctx, Ss, vs, lams, gram_prec=PREC_CODE[prec], centered=CENTERED, sweeps=sweeps, xs=xs)
     torch.cuda.synchronize()
     el = (time.perf_counter() - t0) / reps
+    # which problems took the final step through the FP8 codes: a call that forces the exact final
+    # pass gives the same x exactly for the others
+    xchk = [torch.empty(int(m), dtype=torch.float32, device=dev) for m in ms]
+    dfl.dfisher_solve_uneven(ctx, Ss, vs, lams, gram_prec=PREC_CODE[prec], centered=CENTERED, sweeps=sweeps, xs=xchk,
+                             exact_apply=True)
+    fp8_final = [not bool(torch.equal(a, b)) for a, b in zip(xs, xchk)]
+    del xchk
+    # FP64 output as called (the errors of the timed configuration), then with the measured final
+    # residual (which takes the exact final pass)
     x64s = [torch.empty(int(m), dtype=torch.float64, device=dev) for m in ms]
-    _, inf64 = dfl.dfisher_solve_uneven(ctx, Ss, vs, lams, gram_prec=PREC_CODE[prec], centered=CENTERED, sweeps=sweeps, xs=x64s,
+    dfl.dfisher_solve_uneven(ctx, Ss, vs, lams, gram_prec=PREC_CODE[prec], centered=CENTERED, sweeps=sweeps, xs=x64s,
+                             x_fp64=True)
+    x64w = [torch.empty(int(m), dtype=torch.float64, device=dev) for m in ms]
+    _, inf64 = dfl.dfisher_solve_uneven(ctx, Ss, vs, lams, gram_prec=PREC_CODE[prec], centered=CENTERED, sweeps=sweeps, xs=x64w,
                                         x_fp64=True, final_resid=True)
-    rel32, rel64, esy, per = [], [], [], []
+    rel32, rel64, esy, esyx, per = [], [], [], [], []
     for p in range(nprob):
         xr = _fp64_x(Ss[p], vs[p], lams[p])
         r32, _ = _errs(xs[p], xr, vs[p], lams[p])
         r64, e = _errs(x64s[p], xr, vs[p], lams[p])
+        _, ex = _errs(x64w[p], xr, vs[p], lams[p])
         rel32.append(r32)
         rel64.append(r64)
         esy.append(e)
-        per.append([int(ns[p]), int(ms[p]), lams[p], infos[p]["sweeps_done"], r32, e, inf64[p]["w_resid"]])
+        esyx.append(ex)
+        per.append([int(ns[p]), int(ms[p]), lams[p], infos[p]["sweeps_done"], r32, e, inf64[p]["w_resid"], fp8_final[p]])
         del xr
+    del x64w
     worst = max(range(nprob), key=lambda q: esy[q])
     dfl.dfisher_ctx_destroy(ctx)
     out = {"workload": f"uneven: {nprob} problems, n log-uniform [256, 2048], m log-uniform [1e5, 2e6], "
@@ -447,9 +462,11 @@ def uneven_leg(dfl, dev, prec, sweeps, reps, nprob=64, seed=5):
            "S_GB": sum(4.0 * int(n) * int(m) for n, m in zip(ns, ms)) / 1e9,
            "gram_flops": float(sum(float(n) * (n + 1) * m for n, m in zip(ns, ms))),
            "rel_err_fp32_out": _summ(rel32), "rel_err": _summ(rel64), "eps_Sy": _summ(esy),
+           "eps_Sy_exact_final_pass": _summ(esyx),
            "w_resid": _summ([i["w_resid"] for i in inf64]),
-           "worst_problem": dict(zip(["n", "m", "lambda", "sweeps", "rel_err_fp32_out", "eps_Sy", "w_resid"],
-                                     per[worst])),
+           "fp8_final_step_problems": sum(1 for f in fp8_final if f),
+           "worst_problem": dict(zip(["n", "m", "lambda", "sweeps", "rel_err_fp32_out", "eps_Sy", "w_resid",
+                                      "fp8_final_step"], per[worst])),
            "retried": sum(1 for i in infos if i["attempts"] > 1)}
     del Ss, vs, xs, x64s
     torch.cuda.empty_cache()

@@ -560,10 +560,12 @@ def batch_infos(dinfos):
 
 def dfisher_solve_uneven(ctx, Ss, vs, lams, gram_prec: int = DFISHER_GRAM_FP32, sweeps: int = 0,
                          shift_policy: int = DFISHER_SHIFT_ON_FAILURE, x_fp64: bool = False, xs=None, stream=None,
-                         final_resid: bool = False, tol: float = 0.0, centered: bool = False):
+                         final_resid: bool = False, tol: float = 0.0, centered: bool = False,
+                         exact_apply: bool = False):
     """Independent problems of different shapes. Returns (list of x, infos); "converged" is False in
     every info when the library returned DFISHER_E_NOT_CONVERGED (a tolerance, given or automatic,
-    missed at some problem's sweep cap; every x is still written)."""
+    missed at some problem's sweep cap; every x is still written). exact_apply sets
+    DFISHER_EXACT_APPLY."""
     torch = _torch()
     k = len(Ss)
     if not (len(vs) == len(lams) == k):
@@ -585,6 +587,8 @@ def dfisher_solve_uneven(ctx, Ss, vs, lams, gram_prec: int = DFISHER_GRAM_FP32, 
     lam_arr = (ctypes.c_double * k)(*[float(a) for a in lams])
     opt = _options(gram_prec, sweeps, shift_policy, x_fp64, final_resid, centered)
     opt.tol = float(tol)
+    if exact_apply:
+        opt.flags |= DFISHER_EXACT_APPLY
     infos = (Info * k)()
     st = _lib().dfisher_solve_uneven(ctx.ptr, k, s_arr, n_arr, m_arr, l_arr, v_arr, lam_arr, x_arr, ctypes.byref(opt),
                                      _stream(stream), infos)

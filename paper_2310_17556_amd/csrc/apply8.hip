@@ -29,7 +29,8 @@ __device__ double tree_sum(double v, double* red) {
 }
 
 __global__ void t_axpy_kernel(double* __restrict__ T, const double* __restrict__ U, const double* __restrict__ alpha,
-                              int64_t m) {
+                              int64_t m, const int* __restrict__ skip) {
+  if (skip && *skip) return;
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (j < m) T[j] = fma(alpha[0], U[j], T[j]);
 }
@@ -127,8 +128,8 @@ fp8_apply_kernel(const uint8_t* __restrict__ q, const uint8_t* __restrict__ sc, 
 
 }  // namespace
 
-hipError_t t_axpy(double* T, const double* U, const double* alpha, int64_t m, hipStream_t st) {
-  hipLaunchKernelGGL(t_axpy_kernel, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, st, T, U, alpha, m);
+hipError_t t_axpy(double* T, const double* U, const double* alpha, int64_t m, hipStream_t st, const int* skip) {
+  hipLaunchKernelGGL(t_axpy_kernel, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, st, T, U, alpha, m, skip);
   return hipGetLastError();
 }
 

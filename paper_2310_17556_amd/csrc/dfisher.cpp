@@ -856,11 +856,25 @@ struct UnevenLayout {
   int64_t* info = nullptr;
   int32_t* flag = nullptr;
   double* res = nullptr;                   // final residuals: |b_p|^2, |r_p|^2 per problem
+  // the final step through the FP8 codes (apply8.hip), when every problem allows it: each problem's
+  // codes kept (not shared scratch), S^T y carried through its passes, S^T p, S^T 1 (centered)
+  bool f8 = false;
+  std::vector<int64_t> qoff, soff, moff;   // per problem: codes, scales, m-vector offsets
+  uint8_t *q8all = nullptr, *sc8all = nullptr;
+  double *T8 = nullptr, *U8 = nullptr, *cs8 = nullptr;
+  double* a8 = nullptr;                    // [table entry] step length, [np + p] the correction's mean
+  float* zf8 = nullptr;                    // ntot
+  int* use8 = nullptr;                     // [p] final step through the codes, [np + p] projection applied
   size_t bytes = 0;
 };
 
+// The uneven call keeps every problem's codes for the FP8 final step only while they take at most
+// this much memory (for the 64-problem bench batch, 34 GB)
+constexpr size_t UNEVEN_F8_MAX_CODE_BYTES = (size_t)64 << 30;
+
 void uneven_layout(const dfisher_ctx* ctx, char* base, int32_t np, const float* const* S, const int64_t* n,
-                   const int64_t* m, const int64_t* lds, int prec, int sweeps, UnevenLayout& U) {
+                   const int64_t* m, const int64_t* lds, int prec, int sweeps, UnevenLayout& U, bool want_f8 = false,
+                   bool centered = false) {
   U.gp.clear();
   U.rp.clear();
   U.cp.clear();
@@ -894,6 +908,24 @@ void uneven_layout(const dfisher_ctx* ctx, char* base, int32_t np, const float* 
     }
     if (U.gp.back().ldh > 0) planes = std::max(planes, (size_t)(n[p] * U.gp.back().ldh));
   }
+  // the FP8 final step: scaled-FP8 Gram, whole-line passes for every problem, codes within the cap
+  U.f8 = want_f8 && prec == DFISHER_GRAM_MXFP8;
+  size_t qall = 0, sall = 0;
+  int64_t mall = 0;
+  U.qoff.assign((size_t)np, 0);
+  U.soff.assign((size_t)np, 0);
+  U.moff.assign((size_t)np, 0);
+  for (int32_t p = 0; p < np && U.f8; ++p) {
+    if (!U.fp[(size_t)p].usable || !U.fp[(size_t)p].line) U.f8 = false;
+    const int64_t ldq = dfi::fp8_ldq(m[p]);
+    U.qoff[(size_t)p] = (int64_t)qall;
+    U.soff[(size_t)p] = (int64_t)sall;
+    U.moff[(size_t)p] = mall;
+    qall += align_up((size_t)(n[p] * ldq));
+    sall += align_up((size_t)(n[p] * (ldq / 32)));
+    mall += (m[p] + 31) / 32 * 32;
+  }
+  if (qall + sall > UNEVEN_F8_MAX_CODE_BYTES) U.f8 = false;
   Carver c;
   c.base = base;
   SolveBufs& B = U.shared;
@@ -902,8 +934,13 @@ void uneven_layout(const dfisher_ctx* ctx, char* base, int32_t np, const float* 
   B.rpart = c.take<double>(rpart / sizeof(double) + 1);
   B.cpart = c.take<double>(cpart / sizeof(double) + 1);
   B.t = sweeps > 0 ? c.take<double>((size_t)U.mmax) : nullptr;
-  B.q8 = q8 ? c.take<uint8_t>(q8) : nullptr;
-  B.sc8 = sc8 ? c.take<uint8_t>(sc8) : nullptr;
+  B.q8 = q8 && !U.f8 ? c.take<uint8_t>(q8) : nullptr;
+  B.sc8 = sc8 && !U.f8 ? c.take<uint8_t>(sc8) : nullptr;
+  U.q8all = U.f8 ? c.take<uint8_t>(qall) : nullptr;
+  U.sc8all = U.f8 ? c.take<uint8_t>(sall) : nullptr;
+  U.T8 = U.f8 ? c.take<double>((size_t)mall) : nullptr;
+  U.U8 = U.f8 ? c.take<double>((size_t)mall) : nullptr;
+  U.cs8 = U.f8 && centered ? c.take<double>((size_t)mall) : nullptr;
   B.hi = planes ? c.take<uint16_t>(planes) : nullptr;
   B.lo = planes ? c.take<uint16_t>(planes) : nullptr;
   U.W = c.take<double>((size_t)wtot);
@@ -931,6 +968,9 @@ void uneven_layout(const dfisher_ctx* ctx, char* base, int32_t np, const float* 
   U.info = c.take<int64_t>((size_t)np);
   U.flag = c.take<int32_t>((size_t)np);
   U.res = c.take<double>((size_t)(2 * np));
+  U.a8 = U.f8 ? c.take<double>((size_t)(2 * np)) : nullptr;
+  U.zf8 = U.f8 ? c.take<float>((size_t)U.ntot) : nullptr;
+  U.use8 = U.f8 ? c.take<int>((size_t)(2 * np)) : nullptr;
   U.bytes = c.off;
 }
 
@@ -953,8 +993,12 @@ dfisher_status uneven_enqueue(dfisher_ctx* ctx, int32_t np, const float* const* 
     B.ldq = dfi::fp8_ldq(m[p]);
     if (U.gp[(size_t)p].ldh == 0) B.hi = B.lo = nullptr;   // this problem splits inside the tile kernel
     B.zc = U.zc + U.voff[(size_t)p];   // projection work (free until the refinement)
+    if (U.f8) {   // this problem's own codes, kept for its final step
+      B.q8 = U.q8all + U.qoff[(size_t)p];
+      B.sc8 = U.sc8all + U.soff[(size_t)p];
+    }
     DF_TRY(gram_stage(S[p], v[p], U.gp[(size_t)p], U.rp[(size_t)p], B, lambda[p], U.W + U.woff[(size_t)p], 0, st,
-                      nullptr, is_centered(o)));
+                      nullptr, is_centered(o), U.cs8 ? U.use8 + np + p : nullptr));
     if (o.shift_policy == DFISHER_SHIFT_ALWAYS) {
       double* Wp = U.W + U.woff[(size_t)p];
       const double scale = 2.0 * std::sqrt((double)n[p]) * gram_unit(o.gram_prec, m[p]);
@@ -976,11 +1020,12 @@ dfisher_status uneven_enqueue(dfisher_ctx* ctx, int32_t np, const float* const* 
   // (skip: the problem's stop flag; its fused pass then reads nothing. The column pass + row pass
   // fallback runs regardless: its result is then unused.)
   auto w_pass = [&](int32_t p, const double* u, const double* rhs, bool rhs_zero, double* out,
-                    const int* skip = nullptr) -> dfisher_status {
+                    const int* skip = nullptr, double* tout = nullptr, double* csout = nullptr) -> dfisher_status {
     const int64_t off = U.voff[(size_t)p];
     const double* rh = rhs_zero ? rhs : rhs + off;
     if (U.fp[(size_t)p].usable) {   // one read of S_p
-      HIP_TRY(dfi::refine_pass_launch(U.fp[(size_t)p], S[p], n[p], m[p], lds[p], u + off, U.shared.rpart, st, skip));
+      HIP_TRY(dfi::refine_pass_launch(U.fp[(size_t)p], S[p], n[p], m[p], lds[p], u + off, U.shared.rpart, st, skip, -1,
+                                      tout, csout));
       HIP_TRY(dfi::refine_pass_reduce(U.fp[(size_t)p], U.shared.rpart, out + off, rh, u + off, lambda[p], st, skip));
       return DFISHER_OK;
     }
@@ -992,6 +1037,12 @@ dfisher_status uneven_enqueue(dfisher_ctx* ctx, int32_t np, const float* const* 
     return DFISHER_OK;
   };
   auto residual = [&](int32_t p) -> dfisher_status { return w_pass(p, U.y, U.b, false, U.r); };
+  // the first residual also carries S^T y_0 (and S^T 1) for the FP8 final step
+  auto residual0 = [&](int32_t p) -> dfisher_status {
+    if (!U.f8) return residual(p);
+    const int64_t mo = U.moff[(size_t)p];
+    return w_pass(p, U.y, U.b, false, U.r, nullptr, U.T8 + mo, U.cs8 ? U.cs8 + mo : nullptr);
+  };
   // the conjugate-gradient sweeps of solve_y, per problem, with the stop test on the device: the job
   // tables and the segment table list the problems by decreasing sweep cap, so the problems that
   // may still run sweep s (cap >= s) are the first nactive[s - 1] entries; a problem that has
@@ -1010,10 +1061,11 @@ dfisher_status uneven_enqueue(dfisher_ctx* ctx, int32_t np, const float* const* 
     c.tol = tol;
     c.floor = auto_floor(o);
     c.predict = predict ? 1 : 0;
+    c.keep = U.f8 ? 1 : 0;
     HIP_TRY(dfi::pcg_control_init(np, c, st));
     HIP_TRY(dfi::fill_zero(U.zero, U.nmax, st));
     for (int32_t p : order)
-      if (sw[(size_t)p] > 0) DF_TRY(residual(p));
+      if (sw[(size_t)p] > 0) DF_TRY(residual0(p));
     HIP_TRY(dfi::seg_sumsq(seg, 0, 0, nactive[0], U.b, U.bb, st));
     HIP_TRY(dfi::seg_sumsq(seg, 0, 0, nactive[0], U.r, U.rr, st));
     for (int s = 1;; ++s) {
@@ -1029,8 +1081,16 @@ dfisher_status uneven_enqueue(dfisher_ctx* ctx, int32_t np, const float* const* 
       if (s == 1) HIP_TRY(dfi::pcg_init(seg, 0, 0, cont, U.r, U.zc, U.p, U.rz, st, U.stop));
       else HIP_TRY(dfi::pcg_dir(seg, 0, 0, cont, U.r, U.zc, U.p, U.rz, st, U.stop));
       for (int32_t p : order)
-        if (sw[(size_t)p] > s) DF_TRY(w_pass(p, U.p, U.zero, true, U.nq, U.stop + jpos[(size_t)p]));   // -(W_p p_p)
-      HIP_TRY(dfi::pcg_step(seg, 0, 0, cont, U.p, U.nq, U.y, U.r, U.rz, U.rr, st, U.stop));
+        if (sw[(size_t)p] > s)
+          DF_TRY(w_pass(p, U.p, U.zero, true, U.nq, U.stop + jpos[(size_t)p],
+                        U.f8 ? U.U8 + U.moff[(size_t)p] : nullptr));   // -(W_p p_p)
+      HIP_TRY(dfi::pcg_step(seg, 0, 0, cont, U.p, U.nq, U.y, U.r, U.rz, U.rr, st, U.stop, U.a8));
+      if (U.f8)   // T_p += alpha_p S^T p_p for the problems that took this step
+        for (int32_t p : order)
+          if (sw[(size_t)p] > s) {
+            const int64_t mo = U.moff[(size_t)p];
+            HIP_TRY(dfi::t_axpy(U.T8 + mo, U.U8 + mo, U.a8 + jpos[(size_t)p], m[p], st, U.stop + jpos[(size_t)p]));
+          }
     }
   }
   if (o.final_resid) {   // the returned iterate's residual, per problem (not applied)
@@ -1040,10 +1100,25 @@ dfisher_status uneven_enqueue(dfisher_ctx* ctx, int32_t np, const float* const* 
       HIP_TRY(dfi::sumsq(U.r + U.voff[(size_t)p], n[p], U.res + 2 * p + 1, st));
     }
   }
-  // x_p = (v_p - S_p^T y_p) / lambda_p
-  for (int32_t p : order)
-    HIP_TRY(dfi::colpass_launch(U.cp[(size_t)p], S[p], n[p], m[p], lds[p], U.y + U.voff[(size_t)p], v[p], lambda[p],
-                                x[p], o.x_fp64, U.shared.cpart, st));
+  // x_p = (v_p - S_p^T y_p) / lambda_p: with the FP8 final step, the last correction (left in zc)
+  // through the problem's codes when the device finds that accurate enough, else y_p += zc_p and
+  // the exact column pass (one of the two returns at once)
+  for (int32_t p : order) {
+    const int64_t off = U.voff[(size_t)p];
+    const int* use = nullptr;
+    if (U.f8 && sw[(size_t)p] > 0) {
+      const int64_t mo = U.moff[(size_t)p];
+      use = U.use8 + p;
+      HIP_TRY(dfi::final_decide(n[p], U.y + off, U.zc + off, U.b + off, U.d + off, lambda[p],
+                                U.cs8 ? U.use8 + np + p : nullptr, FINAL8_EST_MAX, U.zf8 + off, U.a8 + np + p, U.use8 + p,
+                                st));
+      HIP_TRY(dfi::fp8_apply(U.q8all + U.qoff[(size_t)p], U.sc8all + U.soff[(size_t)p], dfi::fp8_ldq(m[p]), n[p], m[p],
+                             U.zf8 + off, U.T8 + mo, U.cs8 ? U.cs8 + mo : nullptr, U.a8 + np + p, v[p], lambda[p], x[p],
+                             o.x_fp64, U.use8 + p, st));
+    }
+    HIP_TRY(dfi::colpass_launch(U.cp[(size_t)p], S[p], n[p], m[p], lds[p], U.y + off, v[p], lambda[p], x[p], o.x_fp64,
+                                U.shared.cpart, st, use));
+  }
   return DFISHER_OK;
 }
 
@@ -1069,9 +1144,10 @@ dfisher_status uneven_solve(dfisher_ctx* ctx, int32_t np, const float* const* S,
   }
   UnevenLayout U;
   const int need_t = (max_sw > 0 || o.final_resid) ? 1 : 0;
-  uneven_layout(ctx, nullptr, np, S, n, m, lds, o.gram_prec, need_t, U);
+  const bool want_f8 = o.sweeps != 0 && !o.final_resid && (o.flags & DFISHER_EXACT_APPLY) == 0;
+  uneven_layout(ctx, nullptr, np, S, n, m, lds, o.gram_prec, need_t, U, want_f8, is_centered(o));
   DF_TRY(ensure_ws(ctx, U.bytes));
-  uneven_layout(ctx, static_cast<char*>(ctx->ws), np, S, n, m, lds, o.gram_prec, need_t, U);
+  uneven_layout(ctx, static_cast<char*>(ctx->ws), np, S, n, m, lds, o.gram_prec, need_t, U, want_f8, is_centered(o));
   // largest problems first (their Gram kernels fill the device; small ones follow)
   std::vector<int32_t> order((size_t)np);
   for (int32_t p = 0; p < np; ++p) order[(size_t)p] = p;

@@ -242,7 +242,8 @@ hipError_t seg_sumsq(const int64_t* seg, int64_t n, int64_t s0, int64_t s1, cons
                      hipStream_t st);
 // Device-side stop test of refinement sweeps (per segment, no host round trip): after sweep `sweep`
 // the segment's residual rho = sqrt(rr / bb) is compared with tol (predicted as in the host test
-// when `predict`), and a segment that meets it or reaches cap[s] takes y += zc and stops.
+// when `predict`), and a segment that meets it or reaches cap[s] takes y += zc and stops (with
+// `keep`, zc is left for the final step instead: final_decide adds it or takes its image).
 struct PcgControl {
   const double* bb;   // |b_s|^2
   const double* rr;   // |r_s|^2 of the current iterate
@@ -255,6 +256,7 @@ struct PcgControl {
   double tol;         // 0: stop at the cap only
   double floor;       // least contraction a prediction assumes
   int predict;
+  int keep;           // 1: a stopping segment leaves y alone (zc stays for the final step)
 };
 hipError_t pcg_decide(const int64_t* seg, int64_t n, int64_t s0, int64_t s1, int sweep, const PcgControl& c,
                       const double* zc, double* y, hipStream_t st);
@@ -318,8 +320,9 @@ hipError_t zero_upper(double* A, int64_t n, hipStream_t st);
 // the scaled-FP8 copy Q of S the row pass wrote (one byte per entry instead of four). That costs a
 // relative error of about 3 % of |S^T z|, which final_decide estimates and allows only while it is
 // far below the solve's target.
-// t_axpy: T += alpha[0] U (m entries).
-hipError_t t_axpy(double* T, const double* U, const double* alpha, int64_t m, hipStream_t st);
+// t_axpy: T += alpha[0] U (m entries); nothing when skip (device, may be null) is set.
+hipError_t t_axpy(double* T, const double* U, const double* alpha, int64_t m, hipStream_t st,
+                  const int* skip = nullptr);
 // One workgroup. abar = mean(z) when *centered (device, may be null: not centered; the all-ones component, whose image is the exact
 // abar S^T 1 = abar cs), zf = float(z - abar); est = sqrt(sum_i d_i zf_i^2 / (y.b - lambda y.y))
 // (d_i = |s_i|^2: the expected size of Q^T zf - S^T zf over the relative rounding error, for rounding

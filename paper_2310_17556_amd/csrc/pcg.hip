@@ -154,7 +154,8 @@ __global__ void __launch_bounds__(PT) pcg_decide_kernel(const int64_t* __restric
   if (!(met || last)) return;
   int64_t off, len;
   segment(seg, n, s, off, len);
-  for (int64_t i = threadIdx.x; i < len; i += PT) y[off + i] += zc[off + i];
+  if (!c.keep)
+    for (int64_t i = threadIdx.x; i < len; i += PT) y[off + i] += zc[off + i];
   if (threadIdx.x == 0) {
     c.stop[s] = 1;
     c.done[s] = sweep;

@@ -11,6 +11,9 @@ scaled-FP8 copy of S (apply8.hip), through the C ABI.
   non-centered S.
 * That it is refused where the correction is large (one sweep): x then equals the exact step's bit for
   bit.
+* The uneven call: every problem keeps its codes and takes the FP8 final step where the device allows
+  it; each problem against the oracle (1e-6) and against the exact final pass (2e-7), eager and as a
+  graph replay (bitwise equal).
 """
 import numpy as np
 import pytest
@@ -121,3 +124,32 @@ def test_final8_refused_for_a_large_correction(dfl, ctx):
     x8, _ = dfl.dfisher_solve(ctx, Sd, vd, lam, **kw)
     xe, _ = dfl.dfisher_solve(ctx, Sd, vd, lam, exact_apply=True, **kw)
     assert torch.equal(x8, xe)
+
+
+def test_final8_uneven(dfl, ctx, oracle_mod):
+    shapes = [(300, 120000, 1e-3), (160, 96000, 1e-5), (520, 140000, 1e-2)]
+    print(f"[final8 uneven] {shapes}", flush=True)
+    Ss, vs, lams, refs = [], [], [], []
+    for k, (n, m, lam) in enumerate(shapes):
+        S = synth.make_S(n, m, synth.seed(74, k), "iid")
+        v = synth.make_v(S, synth.seed(74, k), "iid")
+        Ss.append(dev_aligned(S))
+        vs.append(dev(v))
+        lams.append(lam)
+        refs.append((oracle_mod.solve(S, v, lam), v))
+    kw = dict(gram_prec=2, sweeps=-1, centered=True, x_fp64=True)
+    x8, _ = dfl.dfisher_solve_uneven(ctx, Ss, vs, lams, **kw)
+    x8 = [x.cpu().numpy() for x in x8]
+    x8b, _ = dfl.dfisher_solve_uneven(ctx, Ss, vs, lams, **kw)   # the graph replay
+    xe, _ = dfl.dfisher_solve_uneven(ctx, Ss, vs, lams, exact_apply=True, **kw)
+    taken = 0
+    for a, b, e, (xr, v), lam in zip(x8, x8b, xe, refs, lams):
+        e = e.cpu().numpy()
+        assert np.array_equal(a, b.cpu().numpy())
+        r8, e8 = eps_pair(a, xr, v, lam)
+        d = lam * np.linalg.norm(a - e) / np.linalg.norm(v.astype(np.float64) - lam * e)
+        print(f"    rel {r8:.3e} eps_Sy {e8:.3e}; vs exact step {d:.3e}", flush=True)
+        assert r8 <= 1e-6 and e8 <= 1e-6
+        assert d <= 2e-7
+        taken += 0 if np.array_equal(a, e) else 1
+    assert taken >= 1
