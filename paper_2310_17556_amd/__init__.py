@@ -519,7 +519,7 @@ def dfisher_factor_destroy(f) -> None:
 
 def dfisher_solve_batched(ctx, S, lams, V, gram_prec: int = DFISHER_GRAM_FP32, sweeps: int = 0,
                           shift_policy: int = DFISHER_SHIFT_ON_FAILURE, x_fp64: bool = False, X=None, stream=None,
-                          centered: bool = False, enqueue_only: bool = False):
+                          centered: bool = False, enqueue_only: bool = False, exact_apply: bool = False):
     """X[l, r] solves (S^T S + lams[l] I) x = V[r]. Returns (X of shape (nlam, nrhs, m), infos).
 
     enqueue_only sets DFISHER_ASYNC: nothing waits (the call may run under CUDA-graph capture) and
@@ -537,6 +537,8 @@ def dfisher_solve_batched(ctx, S, lams, V, gram_prec: int = DFISHER_GRAM_FP32, s
     if X.dtype != dt or not X.is_contiguous() or tuple(X.shape) != (nlam, nrhs, m):
         raise ValueError("X must be a contiguous (nlam, nrhs, m) tensor of the output dtype")
     opt = _options(gram_prec, sweeps, shift_policy, x_fp64, centered=centered)
+    if exact_apply:
+        opt.flags |= DFISHER_EXACT_APPLY
     if enqueue_only:
         opt.flags |= DFISHER_ASYNC
         dinfos = torch.empty((nlam, ctypes.sizeof(Info)), dtype=torch.uint8, device=S.device)

@@ -606,10 +606,27 @@ dfisher_status final_residual(dfisher_ctx* ctx, const float* S, int64_t n, int64
 struct MultiBufs {
   double *Bs, *Bexp, *Y, *R, *D, *W1, *T, *T1, *Yi, *part, *part1;   // T1, part1: a second group
   double *Zc, *P, *NQ, *zero, *rz;   // refinement: M^-1 R, directions, -(W P), n zeros, r.z per vector
+  // the final step through the FP8 codes (apply8.hip), when planned: S^T y carried per vector (Tacc)
+  // and S^T p of the last directions (Uacc), both in the passes' T layout; step lengths; the
+  // decision's bf16 corrections, means and flags; lambda per factor on the device; S^T 1 and the
+  // ones it is formed from (centered S); whether the centered projection was applied
+  double *Tacc = nullptr, *Uacc = nullptr, *alpha8 = nullptr, *abar8 = nullptr, *lamv = nullptr;
+  double *cs = nullptr, *ones = nullptr;
+  void* zb = nullptr;
+  int64_t ldz = 0;
+  int *usev = nullptr, *flag8 = nullptr, *cflag = nullptr;
+};
+
+// Where the codes of the batched call's Gram are, for the final step through them.
+struct MultiF8 {
+  const uint8_t* q;
+  const uint8_t* sc;
+  int64_t ldq;
+  const double* d;   // row norms |s_i|^2
 };
 
 MultiBufs carve_multi(Carver& c, int64_t n, int64_t m, int64_t nrhs, int64_t nvec, const dfi::RowMultiPlan& rm,
-                      bool need_t) {
+                      bool need_t, bool final8 = false, bool centered = false, int64_t nfac = 1) {
   MultiBufs b{};
   b.Bs = c.take<double>((size_t)(nrhs * n));
   b.Bexp = c.take<double>((size_t)(nvec * n));
@@ -628,15 +645,32 @@ MultiBufs carve_multi(Carver& c, int64_t n, int64_t m, int64_t nrhs, int64_t nve
   b.NQ = c.take<double>((size_t)(nvec * n));
   b.zero = c.take<double>((size_t)n);
   b.rz = c.take<double>((size_t)nvec);
+  if (final8) {
+    const int64_t ng = (nvec + dfi::MULTI_VECS - 1) / dfi::MULTI_VECS;
+    b.Tacc = c.take<double>((size_t)(ng * m * dfi::MULTI_VECS));
+    b.Uacc = c.take<double>((size_t)(ng * m * dfi::MULTI_VECS));
+    b.alpha8 = c.take<double>((size_t)nvec);
+    b.abar8 = c.take<double>((size_t)nvec);
+    b.lamv = c.take<double>((size_t)nfac);
+    b.ldz = (n + 63) / 64 * 64;
+    b.zb = c.take<uint16_t>((size_t)(nvec * b.ldz));
+    b.usev = c.take<int>((size_t)nvec);
+    b.flag8 = c.take<int>(1);
+    b.cflag = c.take<int>(1);
+    b.cs = centered ? c.take<double>((size_t)m) : nullptr;
+    b.ones = centered ? c.take<double>((size_t)n) : nullptr;
+  }
   return b;
 }
 
 dfisher_status multi_solve(const float* S, int64_t n, int64_t m, int64_t lds, int64_t nfac, const double* L,
                            const double* Dinv, const double* lams, const float* V, int64_t nrhs, int64_t ldv, void* X,
                            int64_t ldx, int x_fp64, int sweeps, const dfi::RowMultiPlan& rm, const MultiBufs& b,
-                           hipStream_t st) {
+                           hipStream_t st, const MultiF8* mf8 = nullptr) {
   constexpr int MV = dfi::MULTI_VECS;
   const int64_t nvec = nfac * nrhs;
+  const bool f8 = mf8 && sweeps > 0 && b.Tacc;   // the final step through the codes (b carved for it)
+  if (f8) HIP_TRY(dfi::put_values(b.lamv, lams, nfac, st));
   const int64_t sL = n * n;
   // B_r = S v_r, MV right-hand sides per pass over S
   for (int64_t r0 = 0; r0 < nrhs; r0 += MV) {
@@ -671,23 +705,26 @@ dfisher_status multi_solve(const float* S, int64_t n, int64_t m, int64_t lds, in
       mo.lam[c] = lams[j / nrhs];
     }
   };
-  auto w_pass = [&](const double* U, const double* RHS, bool rhs_zero, double* OUT) -> dfisher_status {
+  // tsave (may be null): the passes' T = S^T U of group g goes to tsave + g m MV and stays there
+  auto w_pass = [&](const double* U, const double* RHS, bool rhs_zero, double* OUT, double* tsave) -> dfisher_status {
     for (int64_t j0 = 0; j0 < nvec;) {
       const int nv = (int)std::min<int64_t>(MV, nvec - j0);
       const int nv1 = b.T1 ? (int)std::min<int64_t>(MV, std::max<int64_t>(0, nvec - j0 - MV)) : 0;
+      double* T0 = tsave ? tsave + (j0 / MV) * m * MV : b.T;
+      double* T1 = tsave ? tsave + (j0 / MV + 1) * m * MV : b.T1;
       dfi::MultiCols mc{}, mc1{};
       dfi::MultiOut mo{}, mo1{};
       group(U, RHS, rhs_zero, OUT, j0, nv, mc, mo);
       if (nv1 > 0) {
         group(U, RHS, rhs_zero, OUT, j0 + MV, nv1, mc1, mo1);
-        HIP_TRY(dfi::colpass_multi_launch2(S, n, m, lds, mc, nv, mc1, nv1, 2, b.T, b.T1, b.Yi, st));
-        HIP_TRY(dfi::rowpass_multi_launch2(rm, S, b.T, nv, b.T1, nv1, b.part, b.part1, st));
+        HIP_TRY(dfi::colpass_multi_launch2(S, n, m, lds, mc, nv, mc1, nv1, 2, T0, T1, b.Yi, st));
+        HIP_TRY(dfi::rowpass_multi_launch2(rm, S, T0, nv, T1, nv1, b.part, b.part1, st));
         HIP_TRY(dfi::rowpass_multi_reduce(rm, b.part, nv, mo, st));
         HIP_TRY(dfi::rowpass_multi_reduce(rm, b.part1, nv1, mo1, st));
       } else {
-        HIP_TRY(dfi::colpass_multi_launch(S, n, m, lds, mc, nv, 2, b.T, b.Yi, st));
+        HIP_TRY(dfi::colpass_multi_launch(S, n, m, lds, mc, nv, 2, T0, b.Yi, st));
         dfi::MultiVecs none{};
-        HIP_TRY(dfi::rowpass_multi_launch(rm, S, none, b.T, nv, b.part, st));
+        HIP_TRY(dfi::rowpass_multi_launch(rm, S, none, T0, nv, b.part, st));
         HIP_TRY(dfi::rowpass_multi_reduce(rm, b.part, nv, mo, st));
       }
       j0 += nv + nv1;
@@ -696,19 +733,31 @@ dfisher_status multi_solve(const float* S, int64_t n, int64_t m, int64_t lds, in
   };
   if (sweeps > 0) {
     HIP_TRY(dfi::fill_zero(b.zero, n, st));
-    DF_TRY(w_pass(b.Y, b.Bexp, false, b.R));
+    DF_TRY(w_pass(b.Y, b.Bexp, false, b.R, f8 ? b.Tacc : nullptr));
     for (int s = 1;; ++s) {
       HIP_TRY(dfi::trsv_launch_batched(L, sL, Dinv, n, nvec, nrhs, 0, b.R, b.D, b.W1, st));
       HIP_TRY(dfi::trsv_launch_batched(L, sL, Dinv, n, nvec, nrhs, 1, b.D, b.Zc, b.W1, st));
       if (s >= sweeps) {
-        HIP_TRY(dfi::axpy_many(b.Y, b.Zc, nvec * n, st));
+        if (!f8) HIP_TRY(dfi::axpy_many(b.Y, b.Zc, nvec * n, st));   // else the final step takes Zc
         break;
       }
       if (s == 1) HIP_TRY(dfi::pcg_init(nullptr, n, 0, nvec, b.R, b.Zc, b.P, b.rz, st));
       else HIP_TRY(dfi::pcg_dir(nullptr, n, 0, nvec, b.R, b.Zc, b.P, b.rz, st));
-      DF_TRY(w_pass(b.P, b.zero, true, b.NQ));
-      HIP_TRY(dfi::pcg_step(nullptr, n, 0, nvec, b.P, b.NQ, b.Y, b.R, b.rz, nullptr, st));
+      DF_TRY(w_pass(b.P, b.zero, true, b.NQ, f8 ? b.Uacc : nullptr));
+      HIP_TRY(dfi::pcg_step(nullptr, n, 0, nvec, b.P, b.NQ, b.Y, b.R, b.rz, nullptr, st, nullptr,
+                            f8 ? b.alpha8 : nullptr));
+      // the last direction's S^T p is added by the final step itself (one pass over T less)
+      if (f8 && s + 1 < sweeps) HIP_TRY(dfi::t_axpy_multi(b.Tacc, b.Uacc, b.alpha8, m, nvec, st));
     }
+  }
+  // the final step: every vector's last correction through the codes when the device allows it for
+  // all of them (then the exact passes below return at once), else Y += Zc and the exact passes
+  const int* skip = nullptr;
+  if (f8) {
+    HIP_TRY(dfi::multi_final8(mf8->q, mf8->sc, mf8->ldq, n, m, nvec, nrhs, b.Y, b.Zc, b.Bexp, mf8->d, b.lamv,
+                              b.cs ? b.cflag : nullptr, FINAL8_EST_MAX, b.zb, b.ldz, b.abar8, b.usev, b.flag8, b.Tacc,
+                              sweeps >= 2 ? b.Uacc : nullptr, b.alpha8, b.cs, V, ldv, X, ldx, x_fp64, st));
+    skip = b.flag8;
   }
   // x = (v - S^T y) / lambda, up to 2 MV vectors per pass
   const size_t xel = x_fp64 ? sizeof(double) : sizeof(float);
@@ -728,9 +777,10 @@ dfisher_status multi_solve(const float* S, int64_t n, int64_t m, int64_t lds, in
     apply_group(j0, nv, mc);
     if (nv1 > 0) {
       apply_group(j0 + MV, nv1, mc1);
-      HIP_TRY(dfi::colpass_multi_launch2(S, n, m, lds, mc, nv, mc1, nv1, x_fp64 ? 1 : 0, nullptr, nullptr, b.Yi, st));
+      HIP_TRY(dfi::colpass_multi_launch2(S, n, m, lds, mc, nv, mc1, nv1, x_fp64 ? 1 : 0, nullptr, nullptr, b.Yi, st,
+                                         skip));
     } else {
-      HIP_TRY(dfi::colpass_multi_launch(S, n, m, lds, mc, nv, x_fp64 ? 1 : 0, nullptr, b.Yi, st));
+      HIP_TRY(dfi::colpass_multi_launch(S, n, m, lds, mc, nv, x_fp64 ? 1 : 0, nullptr, b.Yi, st, skip));
     }
     j0 += nv + nv1;
   }
@@ -2122,6 +2172,8 @@ dfisher_status dfisher_solve_batched(dfisher_ctx* ctx, const float* S, int64_t n
   const dfi::RowMultiPlan rm = dfi::rowmulti_plan(n, m, lds);
   const int64_t nvec = (int64_t)nlam * nrhs;
   const size_t dinv_el = dfi::trsv_dinv_bytes(n) / sizeof(double);
+  // the final step through the codes of the Gram (apply8.hip) for every (lambda, rhs) pair
+  const bool final8 = o.gram_prec == DFISHER_GRAM_MXFP8 && o.sweeps != 0 && (o.flags & DFISHER_EXACT_APPLY) == 0;
   // workspace: the single-solve buffers (Gram stage, retry scratch), nlam factors, their block
   // inverses and statuses, and the multi-vector buffers
   auto layout = [&](char* base, SolveBufs& B, double*& Lall, double*& Dall, double*& dkk, int64_t*& dinfo,
@@ -2135,7 +2187,7 @@ dfisher_status dfisher_solve_batched(dfisher_ctx* ctx, const float* S, int64_t n
     dkk = c.take<double>((size_t)nlam * 64 * 64);
     dinfo = c.take<int64_t>((size_t)nlam);
     dflag = c.take<int32_t>((size_t)nlam);
-    mb = carve_multi(c, n, m, nrhs, nvec, rm, o.sweeps != 0);
+    mb = carve_multi(c, n, m, nrhs, nvec, rm, o.sweeps != 0, final8, is_centered(o), nlam);
     return c.off;
   };
   SolveBufs B;
@@ -2155,7 +2207,12 @@ dfisher_status dfisher_solve_batched(dfisher_ctx* ctx, const float* S, int64_t n
   layout(static_cast<char*>(ctx->ws), B, Lall, Dall, dkk, dinfo, dflag, mb);
 
   // the shared Gram G = S S^T (exact diagonal, no lambda), formed once
-  DF_TRY(gram_stage(S, nullptr, gp, rp, B, 0.0, B.W, 0, st, nullptr, is_centered(o)));
+  DF_TRY(gram_stage(S, nullptr, gp, rp, B, 0.0, B.W, 0, st, nullptr, is_centered(o), mb.cs ? mb.cflag : nullptr));
+  if (mb.cs) {   // S^T 1 for the final step (one column pass with y = 1, FP64 sums)
+    HIP_TRY(dfi::fill_value(mb.ones, n, 1.0, st));
+    HIP_TRY(dfi::colpass_launch(cp, S, n, m, lds, mb.ones, nullptr, 1.0, mb.cs, 2, B.cpart, st));
+  }
+  const MultiF8 mf8{B.q8, B.sc8, B.ldq, B.d};
   // every W_l = G + lambda_l I (+ the up-front shift) factored in the same launches
   const double unit = gram_unit(o.gram_prec, m);
   const double scale0 = (o.shift_policy == DFISHER_SHIFT_ALWAYS) ? 2.0 * std::sqrt((double)n) * unit : 0.0;
@@ -2167,7 +2224,8 @@ dfisher_status dfisher_solve_batched(dfisher_ctx* ctx, const float* S, int64_t n
     const int sweeps = o.sweeps == DFISHER_SWEEPS_AUTO ? auto_sweeps(o.gram_prec, n, m, scale0, is_centered(o))
                                                        : o.sweeps;
     HIP_TRY(dfi::trsv_diag_inv_batched(Lall, n * n, n, nlam, Dall, st));
-    DF_TRY(multi_solve(S, n, m, lds, nlam, Lall, Dall, lambdas, V, nrhs, ldv, X, ldx, o.x_fp64, sweeps, rm, mb, st));
+    DF_TRY(multi_solve(S, n, m, lds, nlam, Lall, Dall, lambdas, V, nrhs, ldv, X, ldx, o.x_fp64, sweeps, rm, mb, st,
+                           final8 ? &mf8 : nullptr));
     if (infos) HIP_TRY(write_batch_infos(infos, nlam, dinfo, scale0, ctx->d_scalar, sweeps, st));
     return DFISHER_OK;
   }
@@ -2207,7 +2265,8 @@ dfisher_status dfisher_solve_batched(dfisher_ctx* ctx, const float* S, int64_t n
     if (infos) infos[l] = linf[(size_t)l];
   }
   HIP_TRY(dfi::trsv_diag_inv_batched(Lall, n * n, n, nlam, Dall, st));
-  DF_TRY(multi_solve(S, n, m, lds, nlam, Lall, Dall, lambdas, V, nrhs, ldv, X, ldx, o.x_fp64, sweeps, rm, mb, st));
+  DF_TRY(multi_solve(S, n, m, lds, nlam, Lall, Dall, lambdas, V, nrhs, ldv, X, ldx, o.x_fp64, sweeps, rm, mb, st,
+                           final8 ? &mf8 : nullptr));
   if (worst != DFISHER_OK) return fail(worst, "at least one lambda failed to factor (its x is not meaningful)");
   return DFISHER_OK;
 }

@@ -160,13 +160,13 @@ hipError_t rowpass_multi_reduce(const RowMultiPlan& p, const double* part, int n
 // x_c = (v_c - t_c) / lam_c as FP32 / FP64. Yi: scratch of n * MULTI_VECS doubles (the y_c
 // interleaved by row).
 hipError_t colpass_multi_launch(const float* S, int64_t n, int64_t m, int64_t lds, const MultiCols& mc, int nc,
-                                int mode, double* T, double* Yi, hipStream_t st);
+                                int mode, double* T, double* Yi, hipStream_t st, const int* skip = nullptr);
 // Two groups of vectors (mc0: nc0, mc1: nc1, each 1 .. MULTI_VECS) in one pass over S: every load
 // of S feeds both groups' products. mode 2 writes T0 and T1 (each m * MULTI_VECS); Yi: scratch of
 // n * 2 * MULTI_VECS doubles.
 hipError_t colpass_multi_launch2(const float* S, int64_t n, int64_t m, int64_t lds, const MultiCols& mc0, int nc0,
                                  const MultiCols& mc1, int nc1, int mode, double* T0, double* T1, double* Yi,
-                                 hipStream_t st);
+                                 hipStream_t st, const int* skip = nullptr);
 // The row pass over two groups' T (T0: nv0, T1: nv1 vectors) in one pass over S; partials into
 // part0 and part1 (each of the plan's part_bytes), reduced with rowpass_multi_reduce per group.
 hipError_t rowpass_multi_launch2(const RowMultiPlan& p, const float* S, const double* T0, int nv0, const double* T1,
@@ -336,5 +336,23 @@ hipError_t final_decide(int64_t n, double* y, const double* z, const double* b, 
 hipError_t fp8_apply(const uint8_t* q, const uint8_t* sc, int64_t ldq, int64_t n, int64_t m, const float* zf,
                      const double* T, const double* cs, const double* abar, const float* v, double lambda, void* x,
                      int x64, const int* use, hipStream_t st);
+
+// Many vectors (the batched call): T in the multi-vector passes' layout, groups of 16 vectors
+// interleaved by column, T[(g m + j) 16 + c] for vector 16 g + c. t_axpy_multi: T += alpha_v U per
+// vector. put_values: count doubles from the host array vals to device memory through kernel
+// arguments (no copy node: safe in a captured sequence). multi_final8: per vector the decision
+// (zb = bf16(z - abar), ldz a multiple of 64 >= n, zeros past n; abar; usev), flag[0] = every
+// vector may take the codes; unless so Y += Z for every vector (the caller then runs the exact
+// passes, skipped by flag[0]); if so X_v = (V_{v mod nrhs} - T_v - abar_v cs - (Z Q)_v) / lamv[v / nrhs]
+// through the bf16 matrix cores, T_v = Tacc_v (+ alpha_v Ulast_v when Ulast is given: the last
+// direction's S^T p, added there instead of by t_axpy_multi).
+hipError_t t_axpy_multi(double* T, const double* U, const double* alpha, int64_t m, int64_t nvec, hipStream_t st);
+hipError_t put_values(double* out, const double* vals, int64_t count, hipStream_t st);
+hipError_t multi_final8(const uint8_t* q, const uint8_t* sc, int64_t ldq, int64_t n, int64_t m, int64_t nvec,
+                        int64_t nrhs, double* Y, const double* Z, const double* B, const double* d,
+                        const double* lamv, const int* centered, double est_max, void* zb, int64_t ldz,
+                        double* abar, int* usev, int* flag, const double* Tacc, const double* Ulast,
+                        const double* alpha, const double* cs, const float* V, int64_t ldv, void* X, int64_t ldx,
+                        int x64, hipStream_t st);
 
 }  // namespace dfi

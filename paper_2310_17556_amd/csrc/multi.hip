@@ -364,7 +364,8 @@ template <int MODE, int NG>
 __global__ void __launch_bounds__(64 * CF_WAVES)
 colpass_multi_mfma_kernel(const float* __restrict__ S, int64_t n, int64_t m, int64_t lds, MultiCols mc0, int nc0,
                           MultiCols mc1, int nc1, const double* __restrict__ Yi, double* __restrict__ T0,
-                          double* __restrict__ T1, int vec) {
+                          double* __restrict__ T1, int vec, const int* __restrict__ skip) {
+  if (skip && *skip) return;
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int64_t c0 = ((int64_t)blockIdx.x * CF_WAVES + wave) * CF_COLS;
@@ -535,7 +536,7 @@ hipError_t rowpass_multi_reduce(const RowMultiPlan& p, const double* part, int n
 }
 
 hipError_t colpass_multi_launch(const float* S, int64_t n, int64_t m, int64_t lds, const MultiCols& mc, int nc,
-                                int mode, double* T, double* Yi, hipStream_t st) {
+                                int mode, double* T, double* Yi, hipStream_t st, const int* skip) {
   if (nc < 1 || nc > MV || !Yi) return hipErrorInvalidValue;
   const bool vec = ((lds & 3) == 0) && aligned16(S);
   hipLaunchKernelGGL(interleave_y_kernel, dim3((unsigned)((n * MV + 255) / 256)), dim3(256), 0, st, mc, n, MV, 0, Yi);
@@ -547,15 +548,15 @@ hipError_t colpass_multi_launch(const float* S, int64_t n, int64_t m, int64_t ld
   switch (mode) {
     case 0:
       hipLaunchKernelGGL((colpass_multi_mfma_kernel<0, 1>), grid, block, 0, st, S, n, m, lds, mc, nc, none, 0, yi, T,
-                         nul, vec ? 1 : 0);
+                         nul, vec ? 1 : 0, skip);
       break;
     case 1:
       hipLaunchKernelGGL((colpass_multi_mfma_kernel<1, 1>), grid, block, 0, st, S, n, m, lds, mc, nc, none, 0, yi, T,
-                         nul, vec ? 1 : 0);
+                         nul, vec ? 1 : 0, skip);
       break;
     case 2:
       hipLaunchKernelGGL((colpass_multi_mfma_kernel<2, 1>), grid, block, 0, st, S, n, m, lds, mc, nc, none, 0, yi, T,
-                         nul, vec ? 1 : 0);
+                         nul, vec ? 1 : 0, skip);
       break;
     default:
       return hipErrorInvalidValue;
@@ -565,7 +566,7 @@ hipError_t colpass_multi_launch(const float* S, int64_t n, int64_t m, int64_t ld
 
 hipError_t colpass_multi_launch2(const float* S, int64_t n, int64_t m, int64_t lds, const MultiCols& mc0, int nc0,
                                  const MultiCols& mc1, int nc1, int mode, double* T0, double* T1, double* Yi,
-                                 hipStream_t st) {
+                                 hipStream_t st, const int* skip) {
   if (nc0 < 1 || nc0 > MV || nc1 < 1 || nc1 > MV || !Yi) return hipErrorInvalidValue;
   if (mode == 2 && (!T0 || !T1)) return hipErrorInvalidValue;
   const bool vec = ((lds & 3) == 0) && aligned16(S);
@@ -578,15 +579,15 @@ hipError_t colpass_multi_launch2(const float* S, int64_t n, int64_t m, int64_t l
   switch (mode) {
     case 0:
       hipLaunchKernelGGL((colpass_multi_mfma_kernel<0, 2>), grid, block, 0, st, S, n, m, lds, mc0, nc0, mc1, nc1, yi,
-                         T0, T1, vec ? 1 : 0);
+                         T0, T1, vec ? 1 : 0, skip);
       break;
     case 1:
       hipLaunchKernelGGL((colpass_multi_mfma_kernel<1, 2>), grid, block, 0, st, S, n, m, lds, mc0, nc0, mc1, nc1, yi,
-                         T0, T1, vec ? 1 : 0);
+                         T0, T1, vec ? 1 : 0, skip);
       break;
     case 2:
       hipLaunchKernelGGL((colpass_multi_mfma_kernel<2, 2>), grid, block, 0, st, S, n, m, lds, mc0, nc0, mc1, nc1, yi,
-                         T0, T1, vec ? 1 : 0);
+                         T0, T1, vec ? 1 : 0, skip);
       break;
     default:
       return hipErrorInvalidValue;

@@ -14,6 +14,10 @@ scaled-FP8 copy of S (apply8.hip), through the C ABI.
 * The uneven call: every problem keeps its codes and takes the FP8 final step where the device allows
   it; each problem against the oracle (1e-6) and against the exact final pass (2e-7), eager and as a
   graph replay (bitwise equal).
+* The batched call: every (lambda, rhs) pair's correction through the codes in one bf16 matrix-core
+  product, against the oracle (1e-6) and the exact final passes (2e-7), for one and several groups of
+  16 vectors, ragged m and n, FP32 and FP64 x; refused for every pair when one pair's correction is too
+  large (one sweep): then bitwise the exact passes' result.
 """
 import numpy as np
 import pytest
@@ -153,3 +157,50 @@ def test_final8_uneven(dfl, ctx, oracle_mod):
         assert d <= 2e-7
         taken += 0 if np.array_equal(a, e) else 1
     assert taken >= 1
+
+
+BATCHED_CASES = [
+    # n, m, nlam, nrhs, sweeps, x64: one partial group; 3 groups (a partial 128-vector block of the
+    # product is not reached); ragged n (not a multiple of 64) and m (not of 256)
+    (128, 128000, 3, 2, 2, True),
+    (64, 64000, 5, 7, 2, True),
+    (100, 90037, 4, 3, 3, False),
+]
+
+
+@pytest.mark.parametrize("n,m,nlam,nrhs,sweeps,x64", BATCHED_CASES)
+def test_final8_batched(dfl, ctx, oracle_mod, n, m, nlam, nrhs, sweeps, x64):
+    print(f"[final8 batched] n={n} m={m} nlam={nlam} nrhs={nrhs} sweeps={sweeps} x64={x64}", flush=True)
+    S = synth.make_S(n, m, synth.seed(75, n), "iid")
+    V = synth.make_V(m, nrhs, synth.seed(75, n))
+    lams = list(np.logspace(-6, -2, nlam))
+    Sd, Vd = dev_aligned(S), dev(V)
+    kw = dict(gram_prec=2, sweeps=sweeps, centered=True, x_fp64=x64)
+    X8, _ = dfl.dfisher_solve_batched(ctx, Sd, lams, Vd, **kw)
+    Xe, _ = dfl.dfisher_solve_batched(ctx, Sd, lams, Vd, exact_apply=True, **kw)
+    X8, Xe = X8.cpu().numpy(), Xe.cpu().numpy()
+    Xref = oracle_mod.solve_batched(S, lams, V)
+    assert not np.array_equal(X8, Xe)   # the codes were used
+    worst = 0.0
+    for li in range(nlam):
+        for r in range(nrhs):
+            r8, e8 = eps_pair(X8[li, r], Xref[li, r], V[r], lams[li])
+            d = lams[li] * np.linalg.norm(X8[li, r].astype(np.float64) - Xe[li, r]) / np.linalg.norm(
+                V[r].astype(np.float64) - lams[li] * Xe[li, r])
+            worst = max(worst, d)
+            assert r8 <= 1e-6 and e8 <= 1e-6, (li, r, r8, e8)
+            if x64:
+                assert d <= 2e-7, (li, r, d)
+    print(f"    worst |S^T (y8 - y)| / |S^T y| {worst:.3e}", flush=True)
+
+
+def test_final8_batched_refused(dfl, ctx):
+    n, m = 128, 50000
+    S = synth.make_S(n, m, synth.seed(76, n), "iid")
+    V = synth.make_V(m, 3, synth.seed(76, n))
+    lams = [1e-5, 1e-3]
+    Sd, Vd = dev_aligned(S), dev(V)
+    kw = dict(gram_prec=2, sweeps=1, centered=True, x_fp64=True)
+    X8, _ = dfl.dfisher_solve_batched(ctx, Sd, lams, Vd, **kw)
+    Xe, _ = dfl.dfisher_solve_batched(ctx, Sd, lams, Vd, exact_apply=True, **kw)
+    assert torch.equal(X8, Xe)
