@@ -7,7 +7,10 @@
 //   2. trsm    rows below the block: A_ik <- A_ik L_kk^-T as a product with the stored inverse,
 //              64 rows per workgroup, every output independent.
 //   3. update  trailing lower triangle A_IJ -= A_Ik A_Jk^T in 64 x 64 tiles on the FP64 matrix
-//              cores (v_mfma_f64_16x16x4), panels staged in LDS.
+//              cores (v_mfma_f64_16x16x4), panels staged in LDS. Its first tile is the next
+//              diagonal block, which needs no later update: that workgroup runs step 1 of the
+//              next block column on it straight away, so only block column 0 has a potf2 launch
+//              of its own and a step costs two launches.
 // A pivot d with !(d > 0) (NaN included) stores the 1-based global index in *info and raises
 // *flag; every later kernel sees the flag and returns at once, so the device work drains
 // without touching the matrix further.
@@ -68,29 +71,15 @@ __device__ __forceinline__ double rsqrt_f64(double d) {
   return y;
 }
 
-__global__ void __launch_bounds__(64 * PW)
-potf2_kernel(double* __restrict__ A, int64_t n, int64_t k, int64_t* __restrict__ info, int32_t* __restrict__ flag,
-             double* __restrict__ Dkk, int64_t sA, const FactorJob* __restrict__ jobs) {
-  __shared__ double lt[NB * LDT];   // l_ij at lt[j * LDT + i], published panel by panel
-  __shared__ double xt[NB * LDT];   // rows of L_kk^-1: x_tc at xt[t * LDT + c], published panel by panel
-  __shared__ double rp[NB];         // 1 / l_jj
-  __shared__ int failed;            // 1-based local index of the first bad pivot, 0 if none
-  const int64_t bb = blockIdx.y;
-  if (jobs) {
-    const FactorJob& jb = jobs[bb];
-    A = jb.A;
-    n = jb.n;
-    info = jb.info;
-    flag = jb.flag;
-    Dkk = jb.dkk;
-    if (k >= n) return;
-  } else {
-    A += bb * sA;
-    info += bb;
-    flag += bb;
-    Dkk += bb * NB * NB;
-  }
-  if (*(volatile int32_t*)flag) return;
+// The diagonal block's factor and inverse for block column k (the body of potf2_kernel, also run
+// by the trailing update's first tile, which produces that block). blk(i, c) reads entry (i, c)
+// of the block, c <= i < nb; lt and xt are NB x LDT doubles of LDS, rp NB doubles, failed an int
+// in LDS. The caller has checked the breakdown flag.
+template <class Blk>
+__device__ __forceinline__ void potf2_block(double* __restrict__ A, int64_t n, int64_t k, int64_t* __restrict__ info,
+                                            int32_t* __restrict__ flag, double* __restrict__ Dkk, Blk blk, double* lt,
+                                            double* xt, double* rp, int* failed_p) {
+  int& failed = *failed_p;
   const int i = threadIdx.x & 63;      // row of the block
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform: scalar branches
   const int c0 = w * PC;               // this wave's first column
@@ -101,7 +90,7 @@ potf2_kernel(double* __restrict__ A, int64_t n, int64_t k, int64_t* __restrict__
   for (int u = 0; u < PC; ++u) {
     const int c = c0 + u;
     double val = (c == i) ? 1.0 : 0.0;   // identity padding past nb
-    if (i < nb && c < nb && c <= i) val = A[(k + i) * n + k + c];
+    if (i < nb && c < nb && c <= i) val = blk(i, c);
     r[u] = val;
     x[u] = (c == i) ? 1.0 : 0.0;         // row c0 + u of X, column i
   }
@@ -168,6 +157,32 @@ potf2_kernel(double* __restrict__ A, int64_t n, int64_t k, int64_t* __restrict__
   if (k + NB >= n) return;  // no rows below: the inverse is not needed
 #pragma unroll
   for (int u = 0; u < PC; ++u) Dkk[(c0 + u) * NB + i] = x[u];   // D[t][c] = (L_kk^-1)_tc
+}
+
+__global__ void __launch_bounds__(64 * PW)
+potf2_kernel(double* __restrict__ A, int64_t n, int64_t k, int64_t* __restrict__ info, int32_t* __restrict__ flag,
+             double* __restrict__ Dkk, int64_t sA, const FactorJob* __restrict__ jobs) {
+  __shared__ double lt[NB * LDT];   // l_ij at lt[j * LDT + i], published panel by panel
+  __shared__ double xt[NB * LDT];   // rows of L_kk^-1: x_tc at xt[t * LDT + c], published panel by panel
+  __shared__ double rp[NB];         // 1 / l_jj
+  __shared__ int failed;            // 1-based local index of the first bad pivot, 0 if none
+  const int64_t bb = blockIdx.y;
+  if (jobs) {
+    const FactorJob& jb = jobs[bb];
+    A = jb.A;
+    n = jb.n;
+    info = jb.info;
+    flag = jb.flag;
+    Dkk = jb.dkk;
+    if (k >= n) return;
+  } else {
+    A += bb * sA;
+    info += bb;
+    flag += bb;
+    Dkk += bb * NB * NB;
+  }
+  if (*(volatile int32_t*)flag) return;
+  potf2_block(A, n, k, info, flag, Dkk, [&](int i, int c) { return A[(k + i) * n + k + c]; }, lt, xt, rp, &failed);
 }
 
 // Rows i in [k + NB, n): A[i][k .. k+NB) <- A[i][k .. k+NB) L_kk^-T, i.e. out_rc = sum_l A_rl D_cl.
@@ -241,19 +256,31 @@ trsm_kernel(double* __restrict__ A, int64_t n, int64_t k, const int32_t* __restr
 // of the tile as 2 x 2 blocks of 16 x 16 FP64 MFMA accumulators; K = 64 in 16 steps of 4.
 // MFMA lane layout (16x16x4 f64): A lane l = (row l%16, k l/16), B lane l = (k l/16, col l%16),
 // D lane l register r = (row l/16 + 4r, col l%16).
+// Tile 0 is the next diagonal block, A_{k+1,k+1}, final after this update: its workgroup keeps the
+// result in LDS instead of storing it and factors it at once (potf2_block for block column
+// k + NB: L_{k+1,k+1} and its inverse into Dkk, or the breakdown), so the diagonal factor of the
+// next step runs alongside the rest of this update instead of in a launch of its own. The factor
+// is the same bits as a separate potf2 launch on the stored tile would give.
 __global__ void __launch_bounds__(256)
-update_kernel(double* __restrict__ A, int64_t n, int64_t k, const int32_t* __restrict__ flag, int64_t sA,
-              const FactorJob* __restrict__ jobs) {
+update_kernel(double* __restrict__ A, int64_t n, int64_t k, int64_t* __restrict__ info, int32_t* __restrict__ flag,
+              double* __restrict__ Dkk, int64_t sA, const FactorJob* __restrict__ jobs) {
+  static_assert(LDP == LDT, "the staged tile is the diagonal factor's LDS layout");
   __shared__ double PI[NB * LDP];
   __shared__ double PJ[NB * LDP];
+  __shared__ double rp[NB];
+  __shared__ int failed;
   if (jobs) {
     const FactorJob& j = jobs[blockIdx.y];
     A = j.A;
     n = j.n;
+    info = j.info;
     flag = j.flag;
+    Dkk = j.dkk;
   } else {
     A += (int64_t)blockIdx.y * sA;
+    info += blockIdx.y;
     flag += blockIdx.y;
+    Dkk += (int64_t)blockIdx.y * NB * NB;
   }
   if (k + NB >= n) return;
   {
@@ -324,6 +351,23 @@ update_kernel(double* __restrict__ A, int64_t n, int64_t k, const int32_t* __res
         const int64_t gj = rj + wx * 32 + b * 16 + l16;
         old[a][b][r] = A[min<int64_t>(gi, n - 1) * n + min<int64_t>(gj, n - 1)];
       }
+  if (t == 0) {
+    // the next diagonal block: the updated tile to LDS (PI, free once every wave's products are
+    // done), then its factor; rows and columns past n are the factor's identity padding
+    __syncthreads();
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int li = wy * 32 + a * 16 + kq + 4 * r, lj = wx * 32 + b * 16 + l16;
+          PI[li * LDP + lj] = old[a][b][r] - acc[a][b][r];
+        }
+    __syncthreads();
+    potf2_block(A, n, k + NB, info, flag, Dkk, [&](int i, int c) { return PI[i * LDP + c]; }, PI, PJ, rp, &failed);
+    return;
+  }
   constexpr int OOB = 0x7FFFFFF0;
   const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(A + ri * n + rj, 0, OOB, 0x00020000);
 #pragma unroll
@@ -415,16 +459,14 @@ hipError_t potrf_launch_batched(double* A, int64_t n, int64_t nbatch, int64_t sA
   hipLaunchKernelGGL(clear_status_kernel, dim3((unsigned)((nbatch + 255) / 256)), dim3(256), 0, st, info_dev, flag_dev,
                      nbatch);
   const FactorJob* nj = nullptr;
-  for (int64_t k = 0; k < n; k += NB) {
-    hipLaunchKernelGGL(potf2_kernel, dim3(1, nb), dim3(64 * PW), 0, st, A, n, k, info_dev, flag_dev, dkk, sA, nj);
-    const int64_t rest = n - k - NB;
-    if (rest > 0) {
-      const int64_t rb = (rest + 63) / 64;
-      hipLaunchKernelGGL(trsm_kernel, dim3((unsigned)rb, nb), dim3(256), 0, st, A, n, k, flag_dev, (const double*)dkk, sA,
-                         nj);
-      hipLaunchKernelGGL(update_kernel, dim3((unsigned)(rb * (rb + 1) / 2), nb), dim3(256), 0, st, A, n, k, flag_dev, sA,
-                         nj);
-    }
+  // the first diagonal block alone; every later one inside the update that finishes it
+  hipLaunchKernelGGL(potf2_kernel, dim3(1, nb), dim3(64 * PW), 0, st, A, n, (int64_t)0, info_dev, flag_dev, dkk, sA, nj);
+  for (int64_t k = 0; k + NB < n; k += NB) {
+    const int64_t rb = (n - k - NB + 63) / 64;
+    hipLaunchKernelGGL(trsm_kernel, dim3((unsigned)rb, nb), dim3(256), 0, st, A, n, k, flag_dev, (const double*)dkk, sA,
+                       nj);
+    hipLaunchKernelGGL(update_kernel, dim3((unsigned)(rb * (rb + 1) / 2), nb), dim3(256), 0, st, A, n, k, info_dev,
+                       flag_dev, dkk, sA, nj);
   }
   return hipGetLastError();
 }
@@ -441,17 +483,16 @@ hipError_t potrf_launch_grouped(const FactorJob* jobs_dev, int64_t njobs, int64_
   if (njobs < 1 || njobs > 65535) return hipErrorInvalidValue;
   const unsigned nb = (unsigned)njobs;
   hipLaunchKernelGGL(clear_jobs_kernel, dim3((unsigned)((njobs + 255) / 256)), dim3(256), 0, st, jobs_dev, njobs);
-  for (int64_t k = 0; k < nmax; k += NB) {
-    hipLaunchKernelGGL(potf2_kernel, dim3(1, nb), dim3(64 * PW), 0, st, (double*)nullptr, (int64_t)0, k, (int64_t*)nullptr,
-                       (int32_t*)nullptr, (double*)nullptr, (int64_t)0, jobs_dev);
-    const int64_t rest = nmax - k - NB;
-    if (rest > 0) {
-      const int64_t rb = (rest + 63) / 64;
-      hipLaunchKernelGGL(trsm_kernel, dim3((unsigned)rb, nb), dim3(256), 0, st, (double*)nullptr, (int64_t)0, k,
-                         (const int32_t*)nullptr, (const double*)nullptr, (int64_t)0, jobs_dev);
-      hipLaunchKernelGGL(update_kernel, dim3((unsigned)(rb * (rb + 1) / 2), nb), dim3(256), 0, st, (double*)nullptr,
-                         (int64_t)0, k, (const int32_t*)nullptr, (int64_t)0, jobs_dev);
-    }
+  // the first diagonal blocks alone; every later one inside the update that finishes it (a job
+  // whose matrix ends at block column k has no update there and no block k + NB to factor)
+  hipLaunchKernelGGL(potf2_kernel, dim3(1, nb), dim3(64 * PW), 0, st, (double*)nullptr, (int64_t)0, (int64_t)0,
+                     (int64_t*)nullptr, (int32_t*)nullptr, (double*)nullptr, (int64_t)0, jobs_dev);
+  for (int64_t k = 0; k + NB < nmax; k += NB) {
+    const int64_t rb = (nmax - k - NB + 63) / 64;
+    hipLaunchKernelGGL(trsm_kernel, dim3((unsigned)rb, nb), dim3(256), 0, st, (double*)nullptr, (int64_t)0, k,
+                       (const int32_t*)nullptr, (const double*)nullptr, (int64_t)0, jobs_dev);
+    hipLaunchKernelGGL(update_kernel, dim3((unsigned)(rb * (rb + 1) / 2), nb), dim3(256), 0, st, (double*)nullptr,
+                       (int64_t)0, k, (int64_t*)nullptr, (int32_t*)nullptr, (double*)nullptr, (int64_t)0, jobs_dev);
   }
   return hipGetLastError();
 }
