@@ -2,10 +2,11 @@
 // n x n matrix, lower triangle. Block size 64; per block column k:
 //   1. potf2   four waves factor the 64 x 64 diagonal block (right-looking: lane i keeps row i
 //              in registers, wave w columns 16 w .. 16 w + 15; wave w factors its 16 columns
-//              alone, then the later waves subtract them through LDS) and form the block's
-//              inverse L_kk^-1 panel by panel in the same loop (lane c owns column c).
-//   2. trsm    rows below the block: A_ik <- A_ik L_kk^-T as a product with the stored inverse,
-//              64 rows per workgroup, every output independent.
+//              alone, then the later waves subtract them through LDS) and invert its four
+//              16 x 16 diagonal sub-blocks, each wave its own while the later waves subtract.
+//   2. trsm    rows below the block: A_ik <- A_ik L_kk^-T by blocked forward substitution over
+//              the four 16-column panels with those inverses, on the FP64 matrix cores, 64 rows
+//              per workgroup.
 //   3. update  trailing lower triangle A_IJ -= A_Ik A_Jk^T in 64 x 64 tiles on the FP64 matrix
 //              cores (v_mfma_f64_16x16x4), panels staged in LDS. Its first tile is the next
 //              diagonal block, which needs no later update: that workgroup runs step 1 of the
@@ -28,9 +29,9 @@ constexpr int NB = 64;
 constexpr int LDP = NB + 1;  // padded LDS row (doubles)
 
 constexpr int PW = 4;          // waves of the diagonal-block kernel
-constexpr int PC = NB / PW;    // 16 columns (factor) or rows of the inverse per wave
+constexpr int PC = NB / PW;    // 16 columns per wave (factor), rows and columns of a sub-block inverse
 
-// Diagonal block: L_kk = chol(A_kk) and Dkk = L_kk^-1, with 4 waves.
+// Diagonal block: L_kk = chol(A_kk) and the inverses of its 16 x 16 diagonal sub-blocks, with 4 waves.
 // Lane i holds row i of the block, wave w its columns 16 w .. 16 w + 15, in registers. The four
 // 16-column panels are taken in order; wave p factors its panel alone, right-looking, with no
 // barrier: at step j the pivot (lane j's entry, read across lanes) gives 1 / l_jj by the hardware
@@ -42,12 +43,10 @@ constexpr int PC = NB / PW;    // 16 columns (factor) or rows of the inverse per
 // (NaN included) is reported as its 1-based global index; the block is then not stored (later
 // steps run on garbage but index nothing out of range). Only 4 barriers per block, against one
 // per column before.
-// The inverse X = L_kk^-1 follows the same panels: lane c holds column c of X, wave w its rows
-// 16 w .. 16 w + 15 (x = e_c at the start). Once panel p of L is factored, wave p finishes its
-// rows of X by forward substitution inside the panel (x_t *= 1 / l_tt, then x_u -= l_ut x_t for
-// the panel's later rows u, with l_ut read as LDS broadcasts; nothing crosses lanes) and publishes
-// them; after the barrier the later waves subtract the panel's rows, x_u -= sum_t l_ut x_t, in
-// the panel's row order. Every x_uc thus loses its products in the order t = 0, 1, ..., u - 1.
+// The panel solve needs only D_p = L_pp^-1 for the four 16 x 16 diagonal sub-blocks, not the
+// whole L_kk^-1 (whose cross-panel rows, formed in the same loop, were a third of the kernel's
+// time on the serial chain): wave p forms D_p by forward substitution inside its panel after the
+// panel's barrier, in the time the later waves spend subtracting the panel.
 constexpr int LDT = NB + 1;   // padded column stride of the LDS copy of L_kk (doubles)
 
 // Lane j's value of a double (j wave-uniform): two v_readlane, no LDS round trip.
@@ -71,30 +70,50 @@ __device__ __forceinline__ double rsqrt_f64(double d) {
   return y;
 }
 
-// The diagonal block's factor and inverse for block column k (the body of potf2_kernel, also run
-// by the trailing update's first tile, which produces that block). blk(i, c) reads entry (i, c)
-// of the block, c <= i < nb; lt and xt are NB x LDT doubles of LDS, rp NB doubles, failed an int
-// in LDS. The caller has checked the breakdown flag.
+// The diagonal block's factor for block column k (the body of potf2_kernel, also run by the
+// trailing update's first tile, which produces that block), and the inverses of its four 16 x 16
+// diagonal sub-blocks for the panel solve. blk(i, c) reads entry (i, c) of the block, c <= i < nb;
+// lt is NB x LDT doubles of LDS, rp NB doubles, failed an int in LDS. The caller has checked the
+// breakdown flag.
 template <class Blk>
 __device__ __forceinline__ void potf2_block(double* __restrict__ A, int64_t n, int64_t k, int64_t* __restrict__ info,
                                             int32_t* __restrict__ flag, double* __restrict__ Dkk, Blk blk, double* lt,
-                                            double* xt, double* rp, int* failed_p) {
+                                            double* rp, int* failed_p) {
   int& failed = *failed_p;
   const int i = threadIdx.x & 63;      // row of the block
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform: scalar branches
   const int c0 = w * PC;               // this wave's first column
   const int64_t nb = min<int64_t>(NB, n - k);
+  const bool below = k + NB < n;       // rows below: the panel solve needs the sub-block inverses
   if (threadIdx.x == 0) failed = 0;
-  double r[PC], x[PC];
+  double r[PC];
 #pragma unroll
   for (int u = 0; u < PC; ++u) {
     const int c = c0 + u;
     double val = (c == i) ? 1.0 : 0.0;   // identity padding past nb
     if (i < nb && c < nb && c <= i) val = blk(i, c);
     r[u] = val;
-    x[u] = (c == i) ? 1.0 : 0.0;         // row c0 + u of X, column i
   }
   __syncthreads();
+  // D_w = L_ww^-1 (this wave's 16 x 16 diagonal sub-block) by forward substitution, lane c0 + c
+  // forming column c (x_t *= 1 / l_tt, then x_u -= l_ut x_t for the later rows u, l_ut and 1 / l_tt
+  // read from LDS as broadcasts); stored as D_w[u][c] at Dkk[(w PC + u) PC + c]. Run by the four
+  // waves together once every panel is published.
+  auto diag_inverse = [&]() {
+    double x[PC];
+#pragma unroll
+    for (int u = 0; u < PC; ++u) x[u] = (c0 + u == i) ? 1.0 : 0.0;
+#pragma unroll
+    for (int tt = 0; tt < PC; ++tt) {
+      x[tt] *= rp[c0 + tt];
+#pragma unroll
+      for (int u = tt + 1; u < PC; ++u) x[u] -= lt[(c0 + tt) * LDT + c0 + u] * x[tt];
+    }
+    if (i >= c0 && i < c0 + PC) {
+#pragma unroll
+      for (int u = 0; u < PC; ++u) Dkk[(c0 + u) * PC + (i - c0)] = x[u];
+    }
+  };
 #pragma unroll 1
   for (int p = 0; p < PW; ++p) {
     if (w == p) {
@@ -116,33 +135,20 @@ __device__ __forceinline__ void potf2_block(double* __restrict__ A, int64_t n, i
       for (int u = 0; u < PC; ++u) lt[(c0 + u) * LDT + i] = r[u];
       // the first breakdown is reported; panels after it run on garbage and are ignored
       if (bad && i == 0 && failed == 0) failed = bad;
-      __builtin_amdgcn_s_waitcnt(0xC07F);   // lgkmcnt(0): this wave's LDS writes are readable
-      // rows c0 .. c0 + 15 of X: forward substitution inside the panel (l_ut, 1 / l_tt from LDS)
-#pragma unroll
-      for (int tt = 0; tt < PC; ++tt) {
-        x[tt] *= rp[c0 + tt];
-#pragma unroll
-        for (int u = tt + 1; u < PC; ++u) x[u] -= lt[(c0 + tt) * LDT + c0 + u] * x[tt];
-      }
-#pragma unroll
-      for (int u = 0; u < PC; ++u) xt[(c0 + u) * LDT + i] = x[u];
     }
     __syncthreads();
-    if (w > p) {   // subtract panel p from this wave's columns of L and rows of X, in panel order
+    if (w > p) {   // subtract panel p from this wave's columns, in panel order
       const int p0 = p * PC;
 #pragma unroll
       for (int jj = 0; jj < PC; ++jj) {
         const double* col = lt + (p0 + jj) * LDT;
         const double lij = col[i];
-        const double xtc = xt[(p0 + jj) * LDT + i];   // x_tc, t = p0 + jj
 #pragma unroll
-        for (int u = 0; u < PC; ++u) {
-          r[u] -= lij * col[c0 + u];
-          x[u] -= col[c0 + u] * xtc;                   // l_ut x_tc, u = c0 + u
-        }
+        for (int u = 0; u < PC; ++u) r[u] -= lij * col[c0 + u];
       }
     }
   }
+  if (below) diag_inverse();   // every wave its own sub-block, all four at once
   // every panel has been published before the last barrier; failed was set before a barrier too
   if (failed) {
     if (threadIdx.x == 0) {
@@ -154,16 +160,12 @@ __device__ __forceinline__ void potf2_block(double* __restrict__ A, int64_t n, i
   // the factor's lower triangle: wave w stores rows w, w + 4, ..., lane c column c
   for (int rr = w; rr < nb; rr += PW)
     if (i <= rr) A[(k + rr) * n + k + i] = lt[i * LDT + rr];
-  if (k + NB >= n) return;  // no rows below: the inverse is not needed
-#pragma unroll
-  for (int u = 0; u < PC; ++u) Dkk[(c0 + u) * NB + i] = x[u];   // D[t][c] = (L_kk^-1)_tc
 }
 
 __global__ void __launch_bounds__(64 * PW)
 potf2_kernel(double* __restrict__ A, int64_t n, int64_t k, int64_t* __restrict__ info, int32_t* __restrict__ flag,
              double* __restrict__ Dkk, int64_t sA, const FactorJob* __restrict__ jobs) {
   __shared__ double lt[NB * LDT];   // l_ij at lt[j * LDT + i], published panel by panel
-  __shared__ double xt[NB * LDT];   // rows of L_kk^-1: x_tc at xt[t * LDT + c], published panel by panel
   __shared__ double rp[NB];         // 1 / l_jj
   __shared__ int failed;            // 1-based local index of the first bad pivot, 0 if none
   const int64_t bb = blockIdx.y;
@@ -182,16 +184,25 @@ potf2_kernel(double* __restrict__ A, int64_t n, int64_t k, int64_t* __restrict__
     Dkk += bb * NB * NB;
   }
   if (*(volatile int32_t*)flag) return;
-  potf2_block(A, n, k, info, flag, Dkk, [&](int i, int c) { return A[(k + i) * n + k + c]; }, lt, xt, rp, &failed);
+  potf2_block(A, n, k, info, flag, Dkk, [&](int i, int c) { return A[(k + i) * n + k + c]; }, lt, rp, &failed);
 }
 
-// Rows i in [k + NB, n): A[i][k .. k+NB) <- A[i][k .. k+NB) L_kk^-T, i.e. out_rc = sum_l A_rl D_cl.
-// 64 rows per workgroup, 256 threads with 4 x 4 outputs each.
+// Rows i in [k + NB, n): A[i][k .. k+NB) <- A[i][k .. k+NB) L_kk^-T, by blocked forward substitution
+// over the block's four 16-column panels: X_p = (A_p - sum_{q<p} X_q L_pq^T) D_p^T, with L_pq the
+// 16 x 16 sub-blocks of L_kk and D_p = L_pp^-1 from the diagonal-block factor. 64 rows per
+// workgroup; wave w owns rows 16 w .. 16 w + 15 through all four panels (a row of X depends only
+// on the same row of A), so after the staging of L_kk and D nothing crosses waves. Both products
+// of a panel run on the FP64 matrix cores (v_mfma_f64_16x16x4f64, K = 16 p and 16); the panel's
+// T goes through the wave's LDS to become an A operand, X_p likewise for the later panels.
+constexpr int LDD = PC + 1;   // padded row of a 16 x 16 LDS tile (doubles)
+
 __global__ void __launch_bounds__(256)
 trsm_kernel(double* __restrict__ A, int64_t n, int64_t k, const int32_t* __restrict__ flag,
             const double* __restrict__ Dkk, int64_t sA, const FactorJob* __restrict__ jobs) {
-  __shared__ double Ab[NB * LDP];
-  __shared__ double Db[NB * LDP];
+  __shared__ double Lb[NB * LDP];          // L_kk row-major (lower triangle, zeros above)
+  __shared__ double Db[PW * PC * LDD];     // D_p[u][c] at Db[(p PC + u) LDD + c]
+  __shared__ double Xw[PW][PC * LDP];      // per wave: its 16 rows of X, panel by panel
+  __shared__ double Tw[PW][PC * LDD];      // per wave: the current panel's T
   const int64_t bb = blockIdx.y;
   if (jobs) {
     const FactorJob& j = jobs[bb];
@@ -208,46 +219,71 @@ trsm_kernel(double* __restrict__ A, int64_t n, int64_t k, const int32_t* __restr
   const int64_t row0 = k + NB + (int64_t)blockIdx.x * NB;
   if (row0 >= n) return;   // grouped launches size the grid for the largest matrix
   if (*(volatile const int32_t*)flag) return;
-  // All 32 loads in flight before the first LDS store (a loop of load, wait, store pays the memory
-  // latency 16 times). A row past n loads row n - 1 of the same block instead and is zeroed.
+  const int lane = tid & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int l16 = lane & 15, kq = lane >> 4;
+  // every load in flight before the first LDS store: L_kk's lower triangle (the diagonal block is
+  // whole: rows below exist), the four D_p, and this wave's A tiles in the MFMA's D layout (lane l
+  // register r = row l/16 + 4 r, column l%16; a row past n loads row n - 1 and is not stored)
   constexpr int PER = NB * NB / 256;
-  double ag[PER], dg[PER];
+  double lg[PER], dg[PW];
 #pragma unroll
   for (int u = 0; u < PER; ++u) {
     const int r = (tid + 256 * u) / NB, c = (tid + 256 * u) % NB;
-    ag[u] = A[min<int64_t>(row0 + r, n - 1) * n + k + c];
-    dg[u] = Dkk[r * NB + c];
+    lg[u] = (c <= r) ? A[(k + r) * n + k + c] : 0.0;
   }
+#pragma unroll
+  for (int u = 0; u < PW; ++u) dg[u] = Dkk[u * PC * PC + tid];
+  f64x4 cacc[PW];
+#pragma unroll
+  for (int p = 0; p < PW; ++p)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int64_t row = row0 + wv * PC + kq + 4 * r;
+      cacc[p][r] = A[min<int64_t>(row, n - 1) * n + k + p * PC + l16];
+    }
 #pragma unroll
   for (int u = 0; u < PER; ++u) {
     const int r = (tid + 256 * u) / NB, c = (tid + 256 * u) % NB;
-    Ab[r * LDP + c] = (row0 + r < n) ? ag[u] : 0.0;
-    Db[r * LDP + c] = dg[u];
+    Lb[r * LDP + c] = lg[u];
   }
+#pragma unroll
+  for (int u = 0; u < PW; ++u) Db[(u * PC + tid / PC) * LDD + tid % PC] = dg[u];
   __syncthreads();
-  const int ty = tid / 16, tx = tid % 16;
-  double acc[4][4];
+  double* X = Xw[wv];
+  double* T = Tw[wv];
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+  for (int p = 0; p < PW; ++p) {
+    // T = A_p - X_{<p} L_{p,<p}^T: A operand lane l = (row l%16, k l/16), B operand lane l =
+    // (k l/16, column l%16) with B[k][c] = L_kk[16 p + c][k]
+    f64x4 t = cacc[p];
 #pragma unroll
-    for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
-  for (int l = 0; l < NB; ++l) {
-    double av[4], dv[4];
+    for (int kk = 0; kk < p * PC; kk += 4) {
+      const double a = -X[l16 * LDP + kk + kq];
+      const double b = Lb[(p * PC + l16) * LDP + kk + kq];
+      t = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, t, 0, 0, 0);
+    }
 #pragma unroll
-    for (int a = 0; a < 4; ++a) av[a] = Ab[(ty + 16 * a) * LDP + l];
+    for (int r = 0; r < 4; ++r) T[(kq + 4 * r) * LDD + l16] = t[r];
+    __builtin_amdgcn_s_waitcnt(0xC07F);   // lgkmcnt(0): this wave's LDS writes are readable
+    __builtin_amdgcn_wave_barrier();
+    // X_p = T D_p^T: B[k][c] = D_p[c][k]
+    f64x4 xa = (f64x4){0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-    for (int b = 0; b < 4; ++b) dv[b] = Db[(tx + 16 * b) * LDP + l];
+    for (int kk = 0; kk < PC; kk += 4) {
+      const double a = T[l16 * LDD + kk + kq];
+      const double b = Db[(p * PC + l16) * LDD + kk + kq];
+      xa = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, xa, 0, 0, 0);
+    }
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
+    for (int r = 0; r < 4; ++r) X[(kq + 4 * r) * LDP + p * PC + l16] = xa[r];
+    __builtin_amdgcn_s_waitcnt(0xC07F);
+    __builtin_amdgcn_wave_barrier();
 #pragma unroll
-      for (int b = 0; b < 4; ++b) acc[a][b] = fma(av[a], dv[b], acc[a][b]);
-  }
-#pragma unroll
-  for (int a = 0; a < 4; ++a) {
-    const int64_t gi = row0 + ty + 16 * a;
-    if (gi >= n) continue;
-#pragma unroll
-    for (int b = 0; b < 4; ++b) A[gi * n + k + tx + 16 * b] = acc[a][b];
+    for (int r = 0; r < 4; ++r) {
+      const int64_t row = row0 + wv * PC + kq + 4 * r;
+      if (row < n) A[row * n + k + p * PC + l16] = xa[r];
+    }
   }
 }
 
@@ -365,7 +401,7 @@ update_kernel(double* __restrict__ A, int64_t n, int64_t k, int64_t* __restrict_
           PI[li * LDP + lj] = old[a][b][r] - acc[a][b][r];
         }
     __syncthreads();
-    potf2_block(A, n, k + NB, info, flag, Dkk, [&](int i, int c) { return PI[i * LDP + c]; }, PI, PJ, rp, &failed);
+    potf2_block(A, n, k + NB, info, flag, Dkk, [&](int i, int c) { return PI[i * LDP + c]; }, PI, rp, &failed);
     return;
   }
   constexpr int OOB = 0x7FFFFFF0;
