@@ -196,7 +196,8 @@ struct FactorJob {
 hipError_t potrf_launch_grouped(const FactorJob* jobs_dev, int64_t njobs, int64_t nmax, hipStream_t st);
 
 // ----------------------------------------------------------------------------- triangular solves
-// Inverses of the 64 x 64 diagonal blocks of L (Dinv: trsv_dinv_bytes(n)), computed once per factor.
+// Inverses of the 64 x 64 diagonal blocks of L and their transposes (Dinv: trsv_dinv_bytes(n)),
+// computed once per factor.
 size_t trsv_dinv_bytes(int64_t n);
 hipError_t trsv_diag_inv(const double* L, int64_t n, double* Dinv, hipStream_t st);
 // y = L^-1 b (trans 0) or L^-T b (trans 1); work: n doubles, not aliasing b or y; b may alias y.

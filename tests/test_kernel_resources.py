@@ -36,8 +36,8 @@ HOT = {
     "trsm_kernel": "potrf.hip",
     "fp8_apply_kernel": "apply8.hip",
     "final_decide_kernel": "apply8.hip",
-    "fwd_step_kernel": "trsv.hip",
-    "bwd_step_kernel": "trsv.hip",
+    "fwd_step2_kernel": "trsv.hip",
+    "bwd_step2_kernel": "trsv.hip",
 }
 
 
