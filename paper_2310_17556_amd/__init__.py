@@ -566,8 +566,9 @@ def dfisher_solve_uneven(ctx, Ss, vs, lams, gram_prec: int = DFISHER_GRAM_FP32, 
                          exact_apply: bool = False):
     """Independent problems of different shapes. Returns (list of x, infos); "converged" is False in
     every info when the library returned DFISHER_E_NOT_CONVERGED (a tolerance, given or automatic,
-    missed at some problem's sweep cap; every x is still written). exact_apply sets
-    DFISHER_EXACT_APPLY."""
+    missed at some problem's sweep cap; every x is still written). When a problem fails to factor
+    the DfisherError (status DFISHER_E_NOT_SPD) carries .infos and .xs of every problem.
+    exact_apply sets DFISHER_EXACT_APPLY."""
     torch = _torch()
     k = len(Ss)
     if not (len(vs) == len(lams) == k):
@@ -594,6 +595,13 @@ def dfisher_solve_uneven(ctx, Ss, vs, lams, gram_prec: int = DFISHER_GRAM_FP32, 
     infos = (Info * k)()
     st = _lib().dfisher_solve_uneven(ctx.ptr, k, s_arr, n_arr, m_arr, l_arr, v_arr, lam_arr, x_arr, ctypes.byref(opt),
                                      _stream(stream), infos)
+    if st == DFISHER_E_NOT_SPD:
+        # every problem's record is written: the error carries them (and the x's), so that the
+        # caller can tell which problem failed to factor
+        err = DfisherError(st, "dfisher_solve_uneven")
+        err.infos = [i.as_dict() for i in infos]
+        err.xs = xs
+        raise err
     if st != DFISHER_E_NOT_CONVERGED:
         _check(st, "dfisher_solve_uneven")
     out = [i.as_dict() for i in infos]

@@ -185,6 +185,19 @@ def test_potrf_breakdown_index(dfl, ctx, oracle_mod, n, bad):
     assert dfl.dfisher_potrf(ctx, dev(Wn)) == info_nan
 
 
+def test_potrf_nan_row_in_later_block(dfl, ctx, oracle_mod):
+    """A NaN row of S past the first block: the breakdown is found by the diagonal factor that runs
+    inside a trailing update (block 1 of 4), at the oracle's 1-based index."""
+    n, row = 200, 100
+    print(f"[potrf nan row] n={n} row={row}", flush=True)
+    S = synth.make_S(n, 3 * n + 7, synth.seed(25, n))
+    S[row, 5] = np.nan
+    W = oracle_mod.gram(S, 0.5)
+    _, info_ref = oracle_mod.cholesky(W)
+    assert info_ref == row + 1
+    assert dfl.dfisher_potrf(ctx, dev(W)) == info_ref
+
+
 @pytest.mark.parametrize("n", [1, 63, 64, 65, 300, 2000])
 def test_trsv(dfl, ctx, oracle_mod, n):
     print(f"[trsv] n={n}", flush=True)
@@ -485,6 +498,37 @@ def test_uneven_grouped(dfl, ctx, oracle_mod, prec, sweeps, policy):
         print(f"    problem {p} {S.shape} rel err {err:.3e} info {infos[p]}", flush=True)
         assert err <= 1e-6
         assert infos[p]["sweeps_done"] == sweeps
+
+
+def test_uneven_breakdown_stays_in_its_problem(dfl, ctx, oracle_mod):
+    """One problem of an uneven call has a NaN row in its second block: with no shift policy it
+    reports its 1-based pivot index (found by the diagonal factor inside the grouped update) and
+    the call returns DFISHER_E_NOT_SPD, while the problems that share every grouped launch with it
+    still match Algorithm 1."""
+    shapes = [(200, 20000, 1e-3), (300, 24000, 1e-2), (150, 16000, 1e-4)]
+    bad, row = 1, 100
+    print(f"[uneven breakdown] {shapes} problem {bad} row {row}", flush=True)
+    Ss, vs = [], []
+    for k, (n, m, _) in enumerate(shapes):
+        S = synth.make_S(n, m, synth.seed(77, k), "iid", center=False)
+        v = synth.make_v(S, synth.seed(77, k), "iid")
+        if k == bad:
+            S[row, 7] = np.nan
+        Ss.append(S)
+        vs.append(v)
+    lams = [s[2] for s in shapes]
+    with pytest.raises(dfl.DfisherError) as ei:
+        dfl.dfisher_solve_uneven(ctx, [dev(S) for S in Ss], [dev(v) for v in vs], lams, gram_prec=0, sweeps=1,
+                                 shift_policy=dfl.DFISHER_SHIFT_NONE, x_fp64=True)
+    assert ei.value.status == dfl.DFISHER_E_NOT_SPD
+    infos, xs = ei.value.infos, ei.value.xs
+    assert infos[bad]["potrf_info"] == row + 1
+    for k, (S, v, lam) in enumerate(zip(Ss, vs, lams)):
+        if k == bad:
+            continue
+        assert infos[k]["potrf_info"] == 0
+        xref = oracle_mod.solve(S, v, lam)
+        assert rel(xs[k].cpu().numpy(), xref) <= 1e-6, k
 
 
 def test_uneven_graph_replays_match_eager(dfl, ctx):
