@@ -110,7 +110,7 @@ struct RefinePassPlan {
   bool split;         // line, rows split over workgroup pairs (2048 < n <= 4096)
   int64_t R;          // line: blocks per workgroup (per pair when split)
   size_t xch_off;     // split: offset (doubles) of the exchanged column partials in part
-  size_t prog_off;    // split: offset (doubles) of the pairs' progress counters (ints)
+  size_t xch_len;     // split: doubles of exchange slots (2 members x 64 values per pair and block)
   size_t part_bytes;  // (ngroups + tail) * n * 8 (+ the split's exchange buffers)
 };
 // split_ok = false keeps the one-workgroup-per-block kernel (smaller workspace)

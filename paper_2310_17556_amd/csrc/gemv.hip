@@ -586,21 +586,25 @@ refine_pass_kernel(const float* __restrict__ S, int64_t n, int64_t m, int64_t ld
 // the two workgroups of a pair (one XCD: w and w + 8) hold its two row halves in
 // registers (rows [0, 2048) and [2048, n); 32 loads of 16 bytes per lane, a row's 128 bytes over 8
 // lanes). Each half's column partials t_c^(h) = sum over its rows of S_ic y_i are formed in a fixed
-// order (lanes, then waves through LDS) and published in global memory with a progress counter;
-// the workgroup waits, bounded, for its partner's, and both form t_c = t_c^(0) + t_c^(1) (same bits
-// in both). A wait that runs out (the partner not resident, or far behind) is not an error: the
-// workgroup computes the partner's partial itself from S, in the same order, so the result never
-// depends on timing. Every block's partials have their own slot (nothing is overwritten during a
-// launch), and the counters are cleared before each launch. Rows of the other half get zero
+// order (lanes, then waves through LDS) and published in global memory; the workgroup waits,
+// bounded, for its partner's, and both form t_c = t_c^(0) + t_c^(1) (same bits in both). Every
+// block's partials have their own slot (nothing is overwritten during a launch), filled before
+// each launch with XCH_EMPTY, a NaN whose payload no arithmetic produces (a NaN from S keeps the
+// low 29 bits of its widened FP32 payload zero; a generated NaN has a zero payload), so the partner
+// polls the values themselves: one memory round trip from the store to the reader instead of a
+// store, a wait for its completion, a counter and a second load. A wait that runs out (the partner
+// not resident, or far behind) is not an error: the workgroup computes the partner's partial itself
+// from S, in the same order, so the result never depends on timing. Rows of the other half get zero
 // partials, so the fixed-order reduction over workgroups is unchanged.
 constexpr int FS_COLS = 32;
 constexpr int FS_HALF = 2048;        // rows of the first half (64 rows per load step x 32 loads)
 constexpr int FS_SPIN = 4096;        // polls (s_sleep 2 each, ~0.2 ms in all) before computing it here
+constexpr uint64_t XCH_EMPTY = 0x7FF80000DEADBEEFull;   // an exchange slot not written yet
 
 template <int NCH, bool SPLIT, bool CS>
 __global__ void __launch_bounds__(64 * FR_WAVES)
 refine_line_kernel(const float* __restrict__ S, int64_t n, int64_t m, int64_t lds, const double* __restrict__ y,
-                   double* __restrict__ part, double* __restrict__ xch, int* __restrict__ prog, int64_t R,
+                   double* __restrict__ part, double* __restrict__ xch, int64_t R,
                    int spin, const int* __restrict__ skip, double* __restrict__ tout, double* __restrict__ csout) {
   constexpr int ROWS = 8 * FR_WAVES;   // rows per load step of the workgroup (8 per wave)
   static_assert(!SPLIT || NCH * ROWS == FS_HALF, "a split block's first half is one workgroup's rows");
@@ -717,32 +721,33 @@ refine_line_kernel(const float* __restrict__ S, int64_t n, int64_t m, int64_t ld
       (void)k;
     } else {
     double* slot = xch + ((pair * R + k) * 2) * (2 * FS_COLS);   // [h = 0 | h = 1] x (32 + 32 columns)
-    // Publication without fences: an agent-scope fence writes back and invalidates the whole L2
-    // of the XCD, every block, for every workgroup. The partials and the counter are agent-scope
-    // relaxed atomics instead (device-coherent accesses that skip the non-coherent caches), the
-    // counter stored only once the partials' stores have completed (vmcnt 0), and the reader takes
-    // the partials only after it has seen the counter.
+    // Publication without fences (an agent-scope fence writes back and invalidates the whole L2 of
+    // the XCD, every block, for every workgroup): the partials are agent-scope relaxed atomics
+    // (device-coherent accesses that skip the non-coherent caches), and the partner polls the
+    // slot's values until none is XCH_EMPTY; each value is one 8-byte store, so a value read is
+    // whole.
+    double pv = 0.0;   // wave 0, lane < nl: the partner's value of this lane's column
     if (wave == 0) {
       if (lane < nl) __hip_atomic_store(slot + h * 2 * FS_COLS + lane, own, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0): the partials are stored
-      if (lane == 0) {
-        __hip_atomic_store(prog + pair * 2 + h, (int)(k + 1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        int ok = 0;
-        for (int it = 0; it < spin; ++it) {
-          if (__hip_atomic_load(prog + pair * 2 + (1 - h), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) > k) {
-            ok = 1;
-            break;
-          }
-          __builtin_amdgcn_s_sleep(2);
+      int ok = 0;
+      for (int it = 0; it < spin; ++it) {
+        bool ready = true;
+        if (lane < nl) {
+          pv = __hip_atomic_load(slot + (1 - h) * 2 * FS_COLS + lane, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          ready = (uint64_t)__double_as_longlong(pv) != XCH_EMPTY;
         }
-        got = ok;
+        if (__all(ready)) {   // wave-uniform
+          ok = 1;
+          break;
+        }
+        __builtin_amdgcn_s_sleep(2);
       }
+      if (lane == 0) got = ok;
     }
     __syncthreads();
     double other = 0.0;
     if (got) {
-      if (wave == 0 && lane < nl)
-        other = __hip_atomic_load(slot + (1 - h) * 2 * FS_COLS + lane, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      if (wave == 0 && lane < nl) other = pv;
     } else {
       // the partner's partials, computed here in its order (one load in flight per lane: rare path)
       double pq[4] = {0.0, 0.0, 0.0, 0.0};
@@ -839,9 +844,9 @@ refine_tail_kernel(const float* __restrict__ S, int64_t n, int64_t m, int64_t ld
   }
 }
 
-__global__ void zero_ints_kernel(int* __restrict__ a, int64_t k) {
+__global__ void fill_u64_kernel(uint64_t* __restrict__ a, int64_t k, uint64_t v) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < k) a[i] = 0;
+  if (i < k) a[i] = v;
 }
 
 bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15) == 0; }
@@ -993,8 +998,8 @@ RefinePassPlan refine_pass_plan(int64_t n, int64_t m, int64_t lds, const float* 
     p.tail = false;
     const size_t groups = (size_t)(p.ngroups + (p.tail ? 1 : 0)) * (size_t)n;
     p.xch_off = groups;
-    p.prog_off = groups + (size_t)npairs * (size_t)p.R * 2 * (2 * FS_COLS);
-    p.part_bytes = p.prog_off * sizeof(double) + (size_t)(2 * npairs) * sizeof(int);
+    p.xch_len = (size_t)npairs * (size_t)p.R * 2 * (2 * FS_COLS);
+    p.part_bytes = (p.xch_off + p.xch_len) * sizeof(double);
     return p;
   }
   if (p.usable && n <= FS_HALF && nblk32 >= 1) {
@@ -1023,45 +1028,45 @@ hipError_t refine_pass_launch(const RefinePassPlan& p, const float* S, int64_t n
   if (!p.usable || p.n != n) return hipErrorInvalidValue;
   if ((tout || csout) && !p.line) return hipErrorInvalidValue;   // only the whole-line kernels write them
   const dim3 grid((unsigned)p.ngroups), block(64 * FR_WAVES);
-  if (p.split) {   // the pairs' progress counters start at zero
-    int* prog = reinterpret_cast<int*>(part + p.prog_off);
-    hipLaunchKernelGGL(zero_ints_kernel, dim3((unsigned)((p.ngroups + 255) / 256)), dim3(256), 0, st, prog,
-                       (int64_t)p.ngroups);
+  if (p.split) {   // every exchange slot starts as XCH_EMPTY (a fill kernel: capturable)
+    const int64_t nx = (int64_t)p.xch_len;
+    hipLaunchKernelGGL(fill_u64_kernel, dim3((unsigned)((nx + 255) / 256)), dim3(256), 0, st,
+                       reinterpret_cast<uint64_t*>(part + p.xch_off), nx, XCH_EMPTY);
     if (spin < 0) {   // DFISHER_PAIR_SPIN overrides the default bound (0: never wait for the partner)
       const char* e = std::getenv("DFISHER_PAIR_SPIN");
       spin = e ? std::max(0, std::atoi(e)) : FS_SPIN;
     }
     if (csout)
       hipLaunchKernelGGL((refine_line_kernel<32, true, true>), grid, block, 0, st, S, n, m, lds, y, part,
-                         part + p.xch_off, prog, p.R, spin, skip, tout, csout);
+                         part + p.xch_off, p.R, spin, skip, tout, csout);
     else
       hipLaunchKernelGGL((refine_line_kernel<32, true, false>), grid, block, 0, st, S, n, m, lds, y, part,
-                         part + p.xch_off, prog, p.R, spin, skip, tout, csout);
+                         part + p.xch_off, p.R, spin, skip, tout, csout);
   } else if (p.line) {
     switch (p.lnch) {
       case 8:
         if (csout)
           hipLaunchKernelGGL((refine_line_kernel<8, false, true>), grid, block, 0, st, S, n, m, lds, y, part,
-                             (double*)nullptr, (int*)nullptr, p.R, 0, skip, tout, csout);
+                             (double*)nullptr, p.R, 0, skip, tout, csout);
         else
           hipLaunchKernelGGL((refine_line_kernel<8, false, false>), grid, block, 0, st, S, n, m, lds, y, part,
-                             (double*)nullptr, (int*)nullptr, p.R, 0, skip, tout, csout);
+                             (double*)nullptr, p.R, 0, skip, tout, csout);
         break;
       case 16:
         if (csout)
           hipLaunchKernelGGL((refine_line_kernel<16, false, true>), grid, block, 0, st, S, n, m, lds, y, part,
-                             (double*)nullptr, (int*)nullptr, p.R, 0, skip, tout, csout);
+                             (double*)nullptr, p.R, 0, skip, tout, csout);
         else
           hipLaunchKernelGGL((refine_line_kernel<16, false, false>), grid, block, 0, st, S, n, m, lds, y, part,
-                             (double*)nullptr, (int*)nullptr, p.R, 0, skip, tout, csout);
+                             (double*)nullptr, p.R, 0, skip, tout, csout);
         break;
       default:
         if (csout)
           hipLaunchKernelGGL((refine_line_kernel<32, false, true>), grid, block, 0, st, S, n, m, lds, y, part,
-                             (double*)nullptr, (int*)nullptr, p.R, 0, skip, tout, csout);
+                             (double*)nullptr, p.R, 0, skip, tout, csout);
         else
           hipLaunchKernelGGL((refine_line_kernel<32, false, false>), grid, block, 0, st, S, n, m, lds, y, part,
-                             (double*)nullptr, (int*)nullptr, p.R, 0, skip, tout, csout);
+                             (double*)nullptr, p.R, 0, skip, tout, csout);
         break;
     }
   }
