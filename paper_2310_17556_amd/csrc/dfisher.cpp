@@ -915,6 +915,11 @@ struct UnevenLayout {
   double* a8 = nullptr;                    // [table entry] step length, [np + p] the correction's mean
   float* zf8 = nullptr;                    // ntot
   int* use8 = nullptr;                     // [p] final step through the codes, [np + p] projection applied
+  // grouped whole-line passes: the problems whose fused pass is a one-workgroup-per-block line
+  // plan run their passes of a sweep in shared launches, each with its own partials
+  std::vector<char> gline;                 // per problem
+  std::vector<int64_t> loff;               // per problem: offset (doubles) of its partials in lpart
+  double* lpart = nullptr;
   size_t bytes = 0;
 };
 
@@ -976,6 +981,16 @@ void uneven_layout(const dfisher_ctx* ctx, char* base, int32_t np, const float* 
     mall += (m[p] + 31) / 32 * 32;
   }
   if (qall + sall > UNEVEN_F8_MAX_CODE_BYTES) U.f8 = false;
+  U.gline.assign((size_t)np, 0);
+  U.loff.assign((size_t)np, 0);
+  size_t lall = 0;
+  for (int32_t p = 0; p < np; ++p) {
+    const dfi::RefinePassPlan& f = U.fp[(size_t)p];
+    if (!f.usable || !f.line || f.split) continue;
+    U.gline[(size_t)p] = 1;
+    U.loff[(size_t)p] = (int64_t)lall;
+    lall += f.part_bytes / sizeof(double);
+  }
   Carver c;
   c.base = base;
   SolveBufs& B = U.shared;
@@ -1021,8 +1036,31 @@ void uneven_layout(const dfisher_ctx* ctx, char* base, int32_t np, const float* 
   U.a8 = U.f8 ? c.take<double>((size_t)(2 * np)) : nullptr;
   U.zf8 = U.f8 ? c.take<float>((size_t)U.ntot) : nullptr;
   U.use8 = U.f8 ? c.take<int>((size_t)(2 * np)) : nullptr;
+  U.lpart = lall ? c.take<double>(lall) : nullptr;
   U.bytes = c.off;
 }
+
+// Device tables of the grouped whole-line passes (uneven_solve builds them): per line class
+// (8, 16, 32 loads per lane) the residual pass's jobs and the conjugate-gradient pass's, in table
+// order (decreasing sweep cap), so that the problems that may run sweep s are a prefix; the counts
+// and workgroup / block totals of that prefix per sweep; and the residuals' jobs likewise.
+struct GroupedPasses {
+  bool on = false;
+  bool cs = false;                            // the residual pass also forms S^T 1
+  const dfi::LineJob* res[3] = {nullptr, nullptr, nullptr};
+  int nres[3] = {0, 0, 0};
+  int64_t wres[3] = {0, 0, 0};
+  const dfi::LineJob* cg[3] = {nullptr, nullptr, nullptr};
+  std::vector<int> ncg[3];                    // [class][s]: jobs with a cap > s
+  std::vector<int64_t> wcg[3];
+  const dfi::ReduceJob* rres = nullptr;
+  int nrres = 0;
+  int64_t brres = 0;
+  const dfi::ReduceJob* rcg = nullptr;
+  std::vector<int> nrcg;                      // [s]
+  std::vector<int64_t> brcg;
+};
+constexpr int LINE_CLASSES[3] = {8, 16, 32};
 
 // Enqueues the whole uneven solve on st (no host synchronisation). fjobs / tjobs: device tables.
 // sw[p]: problem p's sweep count. The job tables list the problems by decreasing sweep count, so
@@ -1033,7 +1071,8 @@ dfisher_status uneven_enqueue(dfisher_ctx* ctx, int32_t np, const float* const* 
                               const std::vector<int>& sw, const std::vector<int64_t>& nactive,
                               const dfi::FactorJob* fjobs, const dfi::TrsvJob* tj_fwd, const dfi::TrsvJob* tj_bwd,
                               const dfi::TrsvJob* tj_bwd_c, const int64_t* seg, const int* cap, double tol,
-                              bool predict, const std::vector<int32_t>& jpos, hipStream_t st) {
+                              bool predict, const std::vector<int32_t>& jpos, const GroupedPasses& G,
+                              hipStream_t st) {
   (void)ctx;
   // Gram stage per problem, largest first: b_p = S_p v_p, d_p, W_p = S_p S_p^T + lambda_p I
   for (int32_t p : order) {
@@ -1114,8 +1153,15 @@ dfisher_status uneven_enqueue(dfisher_ctx* ctx, int32_t np, const float* const* 
     c.keep = U.f8 ? 1 : 0;
     HIP_TRY(dfi::pcg_control_init(np, c, st));
     HIP_TRY(dfi::fill_zero(U.zero, U.nmax, st));
+    // the residual passes: the grouped line problems in one launch per class, the rest alone
+    if (G.on) {
+      for (int c = 0; c < 3; ++c)
+        if (G.nres[c] > 0)
+          HIP_TRY(dfi::refine_line_grouped_launch(G.res[c], G.nres[c], LINE_CLASSES[c], G.cs, G.wres[c], st));
+      if (G.nrres > 0) HIP_TRY(dfi::refine_reduce_grouped(G.rres, G.nrres, G.brres, st));
+    }
     for (int32_t p : order)
-      if (sw[(size_t)p] > 0) DF_TRY(residual0(p));
+      if (sw[(size_t)p] > 0 && !(G.on && U.gline[(size_t)p])) DF_TRY(residual0(p));
     HIP_TRY(dfi::seg_sumsq(seg, 0, 0, nactive[0], U.b, U.bb, st));
     HIP_TRY(dfi::seg_sumsq(seg, 0, 0, nactive[0], U.r, U.rr, st));
     for (int s = 1;; ++s) {
@@ -1130,8 +1176,15 @@ dfisher_status uneven_enqueue(dfisher_ctx* ctx, int32_t np, const float* const* 
       if (cont == 0) break;
       if (s == 1) HIP_TRY(dfi::pcg_init(seg, 0, 0, cont, U.r, U.zc, U.p, U.rz, st, U.stop));
       else HIP_TRY(dfi::pcg_dir(seg, 0, 0, cont, U.r, U.zc, U.p, U.rz, st, U.stop));
+      if (G.on) {   // -(W_p p_p) for the grouped line problems with a cap > s
+        for (int c = 0; c < 3; ++c)
+          if (G.ncg[c][(size_t)s] > 0)
+            HIP_TRY(dfi::refine_line_grouped_launch(G.cg[c], G.ncg[c][(size_t)s], LINE_CLASSES[c], false,
+                                                    G.wcg[c][(size_t)s], st));
+        if (G.nrcg[(size_t)s] > 0) HIP_TRY(dfi::refine_reduce_grouped(G.rcg, G.nrcg[(size_t)s], G.brcg[(size_t)s], st));
+      }
       for (int32_t p : order)
-        if (sw[(size_t)p] > s)
+        if (sw[(size_t)p] > s && !(G.on && U.gline[(size_t)p]))
           DF_TRY(w_pass(p, U.p, U.zero, true, U.nq, U.stop + jpos[(size_t)p],
                         U.f8 ? U.U8 + U.moff[(size_t)p] : nullptr));   // -(W_p p_p)
       HIP_TRY(dfi::pcg_step(seg, 0, 0, cont, U.p, U.nq, U.y, U.r, U.rz, U.rr, st, U.stop, U.a8));
@@ -1232,11 +1285,74 @@ dfisher_status uneven_solve(dfisher_ctx* ctx, int32_t np, const float* const* S,
     capj[(size_t)j] = sw[q];
     jpos[q] = j;
   }
+  // grouped whole-line passes, in table order: per class the residual jobs (cap > 0) and the
+  // conjugate-gradient jobs (cap > 1), and the matching residual-reduction jobs
+  GroupedPasses G;
+  std::vector<dfi::LineJob> lres[3], lcg[3];
+  std::vector<dfi::ReduceJob> rres, rcg;
+  std::vector<int> capcg[3], caprcg;   // each cg job's cap, for the per-sweep prefixes
+  for (int32_t j = 0; j < np; ++j) {
+    const int32_t p = jord[(size_t)j];
+    const size_t q = (size_t)p;
+    if (!U.gline[q] || sw[q] == 0) continue;
+    const dfi::RefinePassPlan& f = U.fp[q];
+    const int c = f.lnch == 8 ? 0 : (f.lnch == 16 ? 1 : 2);
+    const int64_t off = U.voff[q];
+    const int64_t mo = U.f8 ? U.moff[q] : 0;
+    double* part = U.lpart + U.loff[q];
+    const int64_t nb16 = (n[p] + 15) / 16;
+    lres[c].push_back(dfi::LineJob{S[p], U.y + off, part, U.f8 ? U.T8 + mo : nullptr, U.cs8 ? U.cs8 + mo : nullptr,
+                                   nullptr, n[p], m[p], lds[p], f.R, G.wres[c], f.ngroups});
+    G.wres[c] += f.ngroups;
+    rres.push_back(dfi::ReduceJob{part, U.b + off, U.y + off, U.r + off, nullptr, lambda[p], n[p], f.ngroups, G.brres});
+    G.brres += nb16;
+    if (sw[q] > 1) {
+      const int64_t w0 = lcg[c].empty() ? 0 : lcg[c].back().wg0 + lcg[c].back().ngroups;
+      lcg[c].push_back(dfi::LineJob{S[p], U.p + off, part, U.f8 ? U.U8 + mo : nullptr, nullptr, U.stop + j, n[p], m[p],
+                                    lds[p], f.R, w0, f.ngroups});
+      capcg[c].push_back(sw[q]);
+      const int64_t b0 = rcg.empty() ? 0 : rcg.back().blk0 + (rcg.back().n + 15) / 16;
+      rcg.push_back(dfi::ReduceJob{part, U.zero, U.p + off, U.nq + off, U.stop + j, lambda[p], n[p], f.ngroups, b0});
+      caprcg.push_back(sw[q]);
+    }
+  }
+  G.on = !rres.empty();
+  G.cs = U.cs8 != nullptr;
+  for (int c = 0; c < 3; ++c) {
+    G.nres[c] = (int)lres[c].size();
+    G.ncg[c].assign((size_t)std::max(max_sw, 1), 0);
+    G.wcg[c].assign((size_t)std::max(max_sw, 1), 0);
+    for (int s = 0; s < max_sw; ++s)
+      for (size_t k = 0; k < lcg[c].size(); ++k)
+        if (capcg[c][k] > s) {   // a prefix: the caps decrease along the table
+          G.ncg[c][(size_t)s] = (int)k + 1;
+          G.wcg[c][(size_t)s] = lcg[c][k].wg0 + lcg[c][k].ngroups;
+        }
+  }
+  G.nrres = (int)rres.size();
+  G.nrcg.assign((size_t)std::max(max_sw, 1), 0);
+  G.brcg.assign((size_t)std::max(max_sw, 1), 0);
+  for (int s = 0; s < max_sw; ++s)
+    for (size_t k = 0; k < rcg.size(); ++k)
+      if (caprcg[k] > s) {
+        G.nrcg[(size_t)s] = (int)k + 1;
+        G.brcg[(size_t)s] = rcg[k].blk0 + (rcg[k].n + 15) / 16;
+      }
+  size_t lbytes[3], lcgbytes[3];
+  size_t gbytes = 0;
+  for (int c = 0; c < 3; ++c) {
+    lbytes[c] = align_up(lres[c].size() * sizeof(dfi::LineJob));
+    lcgbytes[c] = align_up(lcg[c].size() * sizeof(dfi::LineJob));
+    gbytes += lbytes[c] + lcgbytes[c];
+  }
+  const size_t rrbytes = align_up(rres.size() * sizeof(dfi::ReduceJob));
+  const size_t rcbytes = align_up(rcg.size() * sizeof(dfi::ReduceJob));
+  gbytes += rrbytes + rcbytes;
   const size_t fbytes = align_up(fj.size() * sizeof(dfi::FactorJob));
   const size_t tbytes = align_up(tf.size() * sizeof(dfi::TrsvJob));
   const size_t sbytes = align_up(seg.size() * sizeof(int64_t));
   const size_t cbytes = align_up(capj.size() * sizeof(int));
-  DF_TRY(ensure_tbuf(ctx, fbytes + 3 * tbytes + sbytes + cbytes));
+  DF_TRY(ensure_tbuf(ctx, fbytes + 3 * tbytes + sbytes + cbytes + gbytes));
   char* tb0 = static_cast<char*>(ctx->tbuf);
   auto* d_fj = reinterpret_cast<dfi::FactorJob*>(tb0);
   auto* d_tf = reinterpret_cast<dfi::TrsvJob*>(tb0 + fbytes);
@@ -1250,6 +1366,28 @@ dfisher_status uneven_solve(dfisher_ctx* ctx, int32_t np, const float* const* S,
   HIP_TRY(hipMemcpyAsync(d_tr, tr.data(), tr.size() * sizeof(dfi::TrsvJob), hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(d_seg, seg.data(), seg.size() * sizeof(int64_t), hipMemcpyHostToDevice, st));
   HIP_TRY(hipMemcpyAsync(d_cap, capj.data(), capj.size() * sizeof(int), hipMemcpyHostToDevice, st));
+  {
+    char* gp = tb0 + fbytes + 3 * tbytes + sbytes + cbytes;
+    for (int c = 0; c < 3; ++c) {
+      auto* dres = reinterpret_cast<dfi::LineJob*>(gp);
+      auto* dcg = reinterpret_cast<dfi::LineJob*>(gp + lbytes[c]);
+      if (!lres[c].empty())
+        HIP_TRY(hipMemcpyAsync(dres, lres[c].data(), lres[c].size() * sizeof(dfi::LineJob), hipMemcpyHostToDevice, st));
+      if (!lcg[c].empty())
+        HIP_TRY(hipMemcpyAsync(dcg, lcg[c].data(), lcg[c].size() * sizeof(dfi::LineJob), hipMemcpyHostToDevice, st));
+      G.res[c] = dres;
+      G.cg[c] = dcg;
+      gp += lbytes[c] + lcgbytes[c];
+    }
+    auto* drr = reinterpret_cast<dfi::ReduceJob*>(gp);
+    auto* drc = reinterpret_cast<dfi::ReduceJob*>(gp + rrbytes);
+    if (!rres.empty())
+      HIP_TRY(hipMemcpyAsync(drr, rres.data(), rres.size() * sizeof(dfi::ReduceJob), hipMemcpyHostToDevice, st));
+    if (!rcg.empty())
+      HIP_TRY(hipMemcpyAsync(drc, rcg.data(), rcg.size() * sizeof(dfi::ReduceJob), hipMemcpyHostToDevice, st));
+    G.rres = drr;
+    G.rcg = drc;
+  }
   HIP_TRY(hipStreamSynchronize(st));   // the host tables go out of scope; the graph reads the device copies
 
   // the run: replay the captured graph if every argument and buffer is unchanged
@@ -1295,7 +1433,7 @@ dfisher_status uneven_solve(dfisher_ctx* ctx, int32_t np, const float* const* S,
         dfisher_status se = DFISHER_OK;
         if (ok)
           se = uneven_enqueue(ctx, np, S, n, m, lds, v, lambda, x, o, U, order, sw, nactive, d_fj, d_tf, d_tb, d_tr,
-                              d_seg, d_cap, tol, autos, jpos, ctx->cap_stream);
+                              d_seg, d_cap, tol, autos, jpos, G, ctx->cap_stream);
         if (ok) ok = hipStreamEndCapture(ctx->cap_stream, &graph) == hipSuccess && graph != nullptr;
         if (ok && se == DFISHER_OK) {
           hipGraphExec_t ex = nullptr;
@@ -1315,7 +1453,7 @@ dfisher_status uneven_solve(dfisher_ctx* ctx, int32_t np, const float* const* S,
   }
   if (!ran)
     DF_TRY(uneven_enqueue(ctx, np, S, n, m, lds, v, lambda, x, o, U, order, sw, nactive, d_fj, d_tf, d_tb, d_tr, d_seg,
-                          d_cap, tol, autos, jpos, st));
+                          d_cap, tol, autos, jpos, G, st));
   std::vector<int64_t> hinfo((size_t)np);
   std::vector<double> hmax((size_t)np, 0.0), hres((size_t)(2 * np), -1.0), hrho((size_t)np, -1.0);
   std::vector<int> hdone((size_t)np, 0), hmet((size_t)np, 0);

@@ -125,6 +125,34 @@ hipError_t refine_pass_launch(const RefinePassPlan& p, const float* S, int64_t n
                               int spin = -1, double* tout = nullptr, double* csout = nullptr);
 hipError_t refine_pass_reduce(const RefinePassPlan& p, const double* part, double* r, const double* b,
                               const double* y, double lam, hipStream_t st, const int* skip = nullptr);
+// Many problems' whole-line passes in one launch (plans with line && !split, all of one lnch):
+// job j runs workgroups [wg0, wg0 + ngroups) of its own plan (R blocks each) on its S, writing its
+// partials to part (ngroups x n doubles), S^T u to tout and S^T 1 to csout (cs launches) when set;
+// skip as for refine_pass_launch. Jobs sorted by wg0, contiguous; nwg = the last wg0 + ngroups.
+struct LineJob {
+  const float* S;
+  const double* u;
+  double* part;
+  double* tout;
+  double* csout;
+  const int* skip;
+  int64_t n, m, lds, R, wg0, ngroups;
+};
+hipError_t refine_line_grouped_launch(const LineJob* jobs_dev, int njobs, int nch, bool cs, int64_t nwg,
+                                      hipStream_t st);
+// Their residuals in one launch: job j owns blocks [blk0, blk0 + ceil(n / 16)) and forms
+// out = rhs - lam u - sum of its ngroups partials (refine_pass_reduce's arithmetic). nblk = the last
+// blk0 + ceil(n / 16).
+struct ReduceJob {
+  const double* part;
+  const double* rhs;
+  const double* u;
+  double* out;
+  const int* skip;
+  double lam;
+  int64_t n, ngroups, blk0;
+};
+hipError_t refine_reduce_grouped(const ReduceJob* jobs_dev, int njobs, int64_t nblk, hipStream_t st);
 
 // ----------------------------------------------------------------------------- multi-vector passes
 // One pass over S for up to MULTI_VECS vectors (batched right-hand sides / damping values).

@@ -176,15 +176,15 @@ rowpass_kernel(const float* __restrict__ S, int64_t n, int64_t m, int64_t lds, c
 // b_i = sum_g part_b[g][i] (or r0_i - lam y_i - sum_g part_b[g][i]); d_i = sum_g part_d[g][i].
 // 16 rows and 16 group lanes per 256-thread workgroup: lane s adds groups s, s + 16, ... in order,
 // and the 16 lane sums are combined by a fixed pairwise tree in LDS (many groups at small n).
-__global__ void __launch_bounds__(256)
-rowpass_reduce_kernel(const double* __restrict__ part, int64_t n, int64_t ngroups, int want_b, int want_d,
-                      double* __restrict__ b, double* __restrict__ d, const double* __restrict__ r0,
-                      const double* __restrict__ y, double lam, const int* __restrict__ skip) {
+__device__ __forceinline__ void reduce_body(const double* __restrict__ part, int64_t n, int64_t ngroups, int want_b,
+                                            int want_d, double* __restrict__ b, double* __restrict__ d,
+                                            const double* __restrict__ r0, const double* __restrict__ y, double lam,
+                                            const int* __restrict__ skip, int64_t blk) {
   __shared__ double red[2][16][17];
   if (skip && *skip) return;   // a problem whose refinement has stopped (uniform)
   const int tid = threadIdx.x;
   const int ri = tid & 15, sl = tid >> 4;
-  const int64_t i = (int64_t)blockIdx.x * 16 + ri;
+  const int64_t i = blk * 16 + ri;
   double sb = 0.0, sd = 0.0;
   if (i < n) {
     for (int64_t g = sl; g < ngroups; g += 16) {
@@ -207,6 +207,32 @@ rowpass_reduce_kernel(const double* __restrict__ part, int64_t n, int64_t ngroup
     if (want_b) b[i] = r0 ? (r0[i] - lam * y[i]) - red[0][0][ri] : red[0][0][ri];
     if (want_d) d[i] = red[1][0][ri];
   }
+}
+
+__global__ void __launch_bounds__(256)
+rowpass_reduce_kernel(const double* __restrict__ part, int64_t n, int64_t ngroups, int want_b, int want_d,
+                      double* __restrict__ b, double* __restrict__ d, const double* __restrict__ r0,
+                      const double* __restrict__ y, double lam, const int* __restrict__ skip) {
+  reduce_body(part, n, ngroups, want_b, want_d, b, d, r0, y, lam, skip, blockIdx.x);
+}
+
+// The refinement residuals of many problems in one launch: job j owns blocks [blk0_j, blk0_j +
+// ceil(n_j / 16)) and forms out = rhs - lam u - sum over its workgroups' partials, as
+// refine_pass_reduce does for one problem.
+__global__ void __launch_bounds__(256)
+refine_reduce_grouped_kernel(const ReduceJob* __restrict__ jobs, int njobs) {
+  const int64_t w = blockIdx.x;
+  int lo = 0, hi = njobs - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (jobs[mid].blk0 <= w) lo = mid;
+    else hi = mid - 1;
+  }
+  lo = __builtin_amdgcn_readfirstlane(lo);
+  const ReduceJob& j = jobs[lo];
+  const int64_t bl = w - j.blk0;
+  if (bl < 0 || bl * 16 >= j.n) return;
+  reduce_body(j.part, j.n, j.ngroups, 1, 0, j.out, nullptr, j.rhs, j.u, j.lam, j.skip, bl);
 }
 
 // ---------------------------------------------------------------------------- column pass
@@ -601,11 +627,14 @@ constexpr int FS_HALF = 2048;        // rows of the first half (64 rows per load
 constexpr int FS_SPIN = 4096;        // polls (s_sleep 2 each, ~0.2 ms in all) before computing it here
 constexpr uint64_t XCH_EMPTY = 0x7FF80000DEADBEEFull;   // an exchange slot not written yet
 
+// The pass of workgroup w of gridx (the kernel body; the grouped form below runs it for a
+// problem's share of a launch over many problems).
 template <int NCH, bool SPLIT, bool CS>
-__global__ void __launch_bounds__(64 * FR_WAVES)
-refine_line_kernel(const float* __restrict__ S, int64_t n, int64_t m, int64_t lds, const double* __restrict__ y,
-                   double* __restrict__ part, double* __restrict__ xch, int64_t R,
-                   int spin, const int* __restrict__ skip, double* __restrict__ tout, double* __restrict__ csout) {
+__device__ __forceinline__ void refine_line_body(const float* __restrict__ S, int64_t n, int64_t m, int64_t lds,
+                                                 const double* __restrict__ y, double* __restrict__ part,
+                                                 double* __restrict__ xch, int64_t R, int spin,
+                                                 const int* __restrict__ skip, double* __restrict__ tout,
+                                                 double* __restrict__ csout, int64_t w, int64_t gridx) {
   constexpr int ROWS = 8 * FR_WAVES;   // rows per load step of the workgroup (8 per wave)
   static_assert(!SPLIT || NCH * ROWS == FS_HALF, "a split block's first half is one workgroup's rows");
   if (skip && *skip) return;
@@ -620,9 +649,8 @@ refine_line_kernel(const float* __restrict__ S, int64_t n, int64_t m, int64_t ld
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int q = lane & 7;                       // columns 4 q .. 4 q + 3 of the block
   const int rloc = wave * 8 + (lane >> 3);      // row within a load step
-  const int64_t w = blockIdx.x;
   // SPLIT: pair of two members on one XCD; else every workgroup walks its own region
-  const int64_t pair = SPLIT ? (w & 7) * (gridDim.x >> 4) + ((w >> 3) >> 1) : w;
+  const int64_t pair = SPLIT ? (w & 7) * (gridx >> 4) + ((w >> 3) >> 1) : w;
   const int h = SPLIT ? (int)((w >> 3) & 1) : 0;
   const int64_t row0 = h ? FS_HALF : 0;
   const int64_t nh = SPLIT ? (h ? n - FS_HALF : min<int64_t>(n, FS_HALF)) : n;   // rows of this workgroup
@@ -804,6 +832,37 @@ refine_line_kernel(const float* __restrict__ S, int64_t n, int64_t m, int64_t ld
   }
   if constexpr (SPLIT)
     for (int64_t i = tid; i < n - nh; i += 64 * FR_WAVES) part[w * n + (h ? i : FS_HALF + i)] = 0.0;
+}
+
+template <int NCH, bool SPLIT, bool CS>
+__global__ void __launch_bounds__(64 * FR_WAVES)
+refine_line_kernel(const float* __restrict__ S, int64_t n, int64_t m, int64_t lds, const double* __restrict__ y,
+                   double* __restrict__ part, double* __restrict__ xch, int64_t R,
+                   int spin, const int* __restrict__ skip, double* __restrict__ tout, double* __restrict__ csout) {
+  refine_line_body<NCH, SPLIT, CS>(S, n, m, lds, y, part, xch, R, spin, skip, tout, csout, blockIdx.x, gridDim.x);
+}
+
+// Many problems' whole-line passes (n <= 2048, one workgroup per block) in one launch: job j owns
+// workgroups [wg0_j, wg0_j + ngroups_j) and runs them exactly as its own launch would (the same
+// partition of its blocks, its own partials), so the results are those of one launch per problem.
+// A launch per problem pays a ramp-up and a tail per problem; small problems do not fill the
+// device. Jobs are sorted by wg0; a workgroup finds its job by bisection (uniform, scalar loads).
+template <int NCH, bool CS>
+__global__ void __launch_bounds__(64 * FR_WAVES)
+refine_line_grouped_kernel(const LineJob* __restrict__ jobs, int njobs) {
+  const int64_t w = blockIdx.x;
+  int lo = 0, hi = njobs - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (jobs[mid].wg0 <= w) lo = mid;
+    else hi = mid - 1;
+  }
+  lo = __builtin_amdgcn_readfirstlane(lo);
+  const LineJob& j = jobs[lo];
+  const int64_t wl = w - j.wg0;
+  if (wl < 0 || wl >= j.ngroups) return;
+  refine_line_body<NCH, false, CS>(j.S, j.n, j.m, j.lds, j.u, j.part, nullptr, j.R, 0, j.skip, j.tout, j.csout, wl,
+                                   j.ngroups);
 }
 
 // The last m % TW (< TW, TW = the block width) columns of the fused pass, as one more group of
@@ -1086,6 +1145,35 @@ hipError_t refine_pass_reduce(const RefinePassPlan& p, const double* part, doubl
                               const double* y, double lam, hipStream_t st, const int* skip) {
   hipLaunchKernelGGL(rowpass_reduce_kernel, dim3((unsigned)((p.n + 15) / 16)), dim3(256), 0, st, part, p.n,
                      p.ngroups + (p.tail ? 1 : 0), 1, 0, r, (double*)nullptr, b, y, lam, skip);
+  return hipGetLastError();
+}
+
+hipError_t refine_line_grouped_launch(const LineJob* jobs_dev, int njobs, int nch, bool cs, int64_t nwg,
+                                      hipStream_t st) {
+  if (njobs < 1 || nwg < 1 || nwg > 0x7FFFFFFF) return hipErrorInvalidValue;
+  const dim3 grid((unsigned)nwg), block(64 * FR_WAVES);
+  switch (nch) {
+    case 8:
+      if (cs) hipLaunchKernelGGL((refine_line_grouped_kernel<8, true>), grid, block, 0, st, jobs_dev, njobs);
+      else hipLaunchKernelGGL((refine_line_grouped_kernel<8, false>), grid, block, 0, st, jobs_dev, njobs);
+      break;
+    case 16:
+      if (cs) hipLaunchKernelGGL((refine_line_grouped_kernel<16, true>), grid, block, 0, st, jobs_dev, njobs);
+      else hipLaunchKernelGGL((refine_line_grouped_kernel<16, false>), grid, block, 0, st, jobs_dev, njobs);
+      break;
+    case 32:
+      if (cs) hipLaunchKernelGGL((refine_line_grouped_kernel<32, true>), grid, block, 0, st, jobs_dev, njobs);
+      else hipLaunchKernelGGL((refine_line_grouped_kernel<32, false>), grid, block, 0, st, jobs_dev, njobs);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t refine_reduce_grouped(const ReduceJob* jobs_dev, int njobs, int64_t nblk, hipStream_t st) {
+  if (njobs < 1 || nblk < 1 || nblk > 0x7FFFFFFF) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(refine_reduce_grouped_kernel, dim3((unsigned)nblk), dim3(256), 0, st, jobs_dev, njobs);
   return hipGetLastError();
 }
 
