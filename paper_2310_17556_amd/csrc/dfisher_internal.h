@@ -205,7 +205,8 @@ hipError_t axpy_many(double* y, const double* d, int64_t len, hipStream_t st);
 // ----------------------------------------------------------------------------- Cholesky
 // In-place blocked FP64 Cholesky (row-major, lower). info_dev: device int64, 0 or 1-based
 // index of the first bad pivot. flag_dev: device int32 scratch (stop flag). dkk: device
-// scratch of 64 x 64 doubles (the current diagonal block's inverse).
+// scratch of 64 x 64 doubles (the inverses of the current diagonal block's four 16 x 16
+// diagonal sub-blocks, for the panel solve).
 constexpr size_t POTRF_DKK_BYTES = 64 * 64 * sizeof(double);
 hipError_t potrf_launch(double* A, int64_t n, int64_t* info_dev, int32_t* flag_dev, double* dkk, hipStream_t st);
 // nbatch independent factorisations in the same launches: matrix b at A + b sA, info_dev[b],

@@ -294,7 +294,7 @@ trsm_kernel(double* __restrict__ A, int64_t n, int64_t k, const int32_t* __restr
 // D lane l register r = (row l/16 + 4r, col l%16).
 // Tile 0 is the next diagonal block, A_{k+1,k+1}, final after this update: its workgroup keeps the
 // result in LDS instead of storing it and factors it at once (potf2_block for block column
-// k + NB: L_{k+1,k+1} and its inverse into Dkk, or the breakdown), so the diagonal factor of the
+// k + NB: L_{k+1,k+1} and its sub-block inverses into Dkk, or the breakdown), so the diagonal factor of the
 // next step runs alongside the rest of this update instead of in a launch of its own. The factor
 // is the same bits as a separate potf2 launch on the stored tile would give.
 __global__ void __launch_bounds__(256)
