@@ -13,7 +13,7 @@ scaled-FP8 copy of S (apply8.hip), through the C ABI.
   bit.
 * The uneven call: every problem keeps its codes and takes the FP8 final step where the device allows
   it; each problem against the oracle (1e-6) and against the exact final pass (2e-7), eager and as a
-  graph replay (bitwise equal).
+  graph replay (bitwise equal); the sizes cover the three classes of the grouped refinement passes.
 * The batched call: every (lambda, rhs) pair's correction through the codes in one bf16 matrix-core
   product, against the oracle (1e-6) and the exact final passes (2e-7), for one and several groups of
   16 vectors, ragged m and n, FP32 and FP64 x; refused for every pair when one pair's correction is too
@@ -131,7 +131,8 @@ def test_final8_refused_for_a_large_correction(dfl, ctx):
 
 
 def test_final8_uneven(dfl, ctx, oracle_mod):
-    shapes = [(300, 120000, 1e-3), (160, 96000, 1e-5), (520, 140000, 1e-2)]
+    # n = 160 and 300, 520 and 1100: the grouped refinement passes' three load-width classes
+    shapes = [(300, 120000, 1e-3), (160, 96000, 1e-5), (520, 140000, 1e-2), (1100, 150000, 1e-4)]
     print(f"[final8 uneven] {shapes}", flush=True)
     Ss, vs, lams, refs = [], [], [], []
     for k, (n, m, lam) in enumerate(shapes):
