@@ -168,10 +168,11 @@ GRAM_KERNEL = {"fp32": "gram_kernel_v2<0>", "bf16x3": "gram_kernel_split", "mxfp
 # valid only for the kernel source they were taken on (sha256 of csrc/gram.hip); see profiles/.
 GRAM_TRAFFIC = {
     ("mxfp8", 4096, 4_000_000): {
-        "gram_hip_sha256": "1de7a4294ff06263b4811e0ed56a36a10330e033bab63ad6dd8224737cced0a6",
+        "gram_hip_sha256": "ed0e1b1b8a2c47d60e3da9db03f4f431d44327d15ac2ab86941abdc907a295a7",
         # FETCH_SIZE x 2 + WRITE_SIZE x 1 (KiB -> bytes), mean of 12 launches in the latest pair of
-        # counter runs; the re-reads vary from run to run (76.9 and 80.9 GB in earlier pairs)
-        "bytes_per_launch": 92.21e9 + 1.14e9,
+        # counter runs; the re-reads vary from box to box and run to run (75.8 to 116.5 GB over
+        # four pairs)
+        "bytes_per_launch": 116.47e9 + 1.14e9,
     },
 }
 

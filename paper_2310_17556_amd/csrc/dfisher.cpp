@@ -920,6 +920,12 @@ struct UnevenLayout {
   std::vector<char> gline;                 // per problem
   std::vector<int64_t> loff;               // per problem: offset (doubles) of its partials in lpart
   double* lpart = nullptr;
+  // grouped Gram (with f8: every problem's codes are kept): one launch over all problems' work
+  // items, each problem with one slice per XCD (the launch, not the problem, fills the device) and
+  // its own partial tiles at gall + goff[p]
+  std::vector<dfi::GramPlan> gpg;
+  std::vector<int64_t> goff;               // floats
+  float* gall = nullptr;
   size_t bytes = 0;
 };
 
@@ -981,6 +987,15 @@ void uneven_layout(const dfisher_ctx* ctx, char* base, int32_t np, const float* 
     mall += (m[p] + 31) / 32 * 32;
   }
   if (qall + sall > UNEVEN_F8_MAX_CODE_BYTES) U.f8 = false;
+  U.gpg.clear();
+  U.goff.assign((size_t)np, 0);
+  size_t gall = 0;
+  for (int32_t p = 0; p < np && U.f8; ++p) {
+    U.gpg.push_back(dfi::gram_plan(n[p], m[p], lds[p], prec, true, 1));
+    U.goff[(size_t)p] = (int64_t)gall;
+    gall += std::max(U.gpg.back().part_bytes, dfi::gram_project_work_bytes(n[p])) / sizeof(float);
+    gall = (gall + 63) / 64 * 64;   // 256-byte aligned regions
+  }
   U.gline.assign((size_t)np, 0);
   U.loff.assign((size_t)np, 0);
   size_t lall = 0;
@@ -1037,6 +1052,7 @@ void uneven_layout(const dfisher_ctx* ctx, char* base, int32_t np, const float* 
   U.zf8 = U.f8 ? c.take<float>((size_t)U.ntot) : nullptr;
   U.use8 = U.f8 ? c.take<int>((size_t)(2 * np)) : nullptr;
   U.lpart = lall ? c.take<double>(lall) : nullptr;
+  U.gall = gall ? c.take<float>(gall) : nullptr;
   U.bytes = c.off;
 }
 
@@ -1059,6 +1075,9 @@ struct GroupedPasses {
   const dfi::ReduceJob* rcg = nullptr;
   std::vector<int> nrcg;                      // [s]
   std::vector<int64_t> brcg;
+  const dfi::GramJob* gram = nullptr;         // the grouped Gram's jobs (largest work item first)
+  int ngram = 0;
+  int64_t gram_nwg = 0;
 };
 constexpr int LINE_CLASSES[3] = {8, 16, 32};
 
@@ -1074,8 +1093,37 @@ dfisher_status uneven_enqueue(dfisher_ctx* ctx, int32_t np, const float* const* 
                               bool predict, const std::vector<int32_t>& jpos, const GroupedPasses& G,
                               hipStream_t st) {
   (void)ctx;
-  // Gram stage per problem, largest first: b_p = S_p v_p, d_p, W_p = S_p S_p^T + lambda_p I
+  // Gram stage, largest first: b_p = S_p v_p, d_p, W_p = S_p S_p^T + lambda_p I. With every
+  // problem's codes kept (f8): the row passes per problem, then one Gram launch over all problems'
+  // work items, then each problem's reduction, projection and shift; else the whole stage per
+  // problem.
+  if (G.ngram > 0) {
+    for (int32_t p : order) {
+      const size_t q = (size_t)p;
+      double* rpart = U.shared.rpart;
+      HIP_TRY(dfi::rowpass_launch(U.rp[q], S[p], v[p], nullptr, true, true, rpart, st, U.q8all + U.qoff[q],
+                                  U.sc8all + U.soff[q], dfi::fp8_ldq(m[p]), true));
+      HIP_TRY(dfi::rowpass_reduce(U.rp[q], rpart, true, true, U.b + U.voff[q], U.d + U.voff[q], nullptr, nullptr, 0.0,
+                                  st));
+    }
+    HIP_TRY(dfi::gram_launch_fp8_grouped(G.gram, G.ngram, G.gram_nwg, st));
+  }
   for (int32_t p : order) {
+    if (G.ngram > 0) {
+      const size_t q = (size_t)p;
+      double* Wp = U.W + U.woff[q];
+      float* gp = U.gall + U.goff[q];
+      HIP_TRY(dfi::gram_reduce(U.gpg[q], S[p], gp, U.d + U.voff[q], lambda[p], Wp, 0, st));
+      if (is_centered(o))   // the partial tiles are free again: they hold the projection's tile sums
+        HIP_TRY(dfi::gram_project(Wp, n[p], 1, lambda[p], 0, reinterpret_cast<double*>(gp), U.zc + U.voff[q], st,
+                                  U.cs8 ? U.use8 + np + p : nullptr));
+      if (o.shift_policy == DFISHER_SHIFT_ALWAYS) {
+        const double scale = 2.0 * std::sqrt((double)n[p]) * gram_unit(o.gram_prec, m[p]);
+        HIP_TRY(dfi::diag_max(Wp, n[p], U.dmax + p, st));
+        HIP_TRY(dfi::shift_add_copy(Wp, Wp, n[p], scale, U.dmax + p, 0.0, st));
+      }
+      continue;
+    }
     SolveBufs B = U.shared;
     B.b = U.b + U.voff[(size_t)p];
     B.d = U.d + U.voff[(size_t)p];
@@ -1329,6 +1377,29 @@ dfisher_status uneven_solve(dfisher_ctx* ctx, int32_t np, const float* const* S,
           G.wcg[c][(size_t)s] = lcg[c][k].wg0 + lcg[c][k].ngroups;
         }
   }
+  // the grouped Gram's jobs: largest work item (slice length) first, then more tiles first
+  std::vector<dfi::GramJob> gjobs;
+  if (U.f8) {
+    std::vector<int32_t> gord((size_t)np);
+    for (int32_t p = 0; p < np; ++p) gord[(size_t)p] = p;
+    std::stable_sort(gord.begin(), gord.end(), [&](int32_t a, int32_t b) {
+      const dfi::GramPlan &ga = U.gpg[(size_t)a], &gb = U.gpg[(size_t)b];
+      return ga.kslice != gb.kslice ? ga.kslice > gb.kslice : ga.ntri > gb.ntri;
+    });
+    int64_t w0 = 0;
+    for (int32_t p : gord) {
+      const size_t q = (size_t)p;
+      const dfi::GramPlan& g = U.gpg[q];
+      const int64_t ldq = dfi::fp8_ldq(m[p]);
+      if (g.nslice * g.kslice < ldq || (g.kslice & 63) != 0 || (g.nslice & 7) != 0)
+        return fail(DFISHER_E_DEVICE, "grouped Gram plan of problem %d does not cover its codes", (int)p);
+      gjobs.push_back(dfi::GramJob{U.q8all + U.qoff[q], U.sc8all + U.soff[q], U.gall + U.goff[q], n[p], ldq, g.ntri,
+                                   g.nslice, g.kslice, w0});
+      w0 += g.ntri * g.nslice;
+    }
+    G.ngram = (int)gjobs.size();
+    G.gram_nwg = w0;
+  }
   G.nrres = (int)rres.size();
   G.nrcg.assign((size_t)std::max(max_sw, 1), 0);
   G.brcg.assign((size_t)std::max(max_sw, 1), 0);
@@ -1347,7 +1418,8 @@ dfisher_status uneven_solve(dfisher_ctx* ctx, int32_t np, const float* const* S,
   }
   const size_t rrbytes = align_up(rres.size() * sizeof(dfi::ReduceJob));
   const size_t rcbytes = align_up(rcg.size() * sizeof(dfi::ReduceJob));
-  gbytes += rrbytes + rcbytes;
+  const size_t gjbytes = align_up(gjobs.size() * sizeof(dfi::GramJob));
+  gbytes += rrbytes + rcbytes + gjbytes;
   const size_t fbytes = align_up(fj.size() * sizeof(dfi::FactorJob));
   const size_t tbytes = align_up(tf.size() * sizeof(dfi::TrsvJob));
   const size_t sbytes = align_up(seg.size() * sizeof(int64_t));
@@ -1387,6 +1459,10 @@ dfisher_status uneven_solve(dfisher_ctx* ctx, int32_t np, const float* const* S,
       HIP_TRY(hipMemcpyAsync(drc, rcg.data(), rcg.size() * sizeof(dfi::ReduceJob), hipMemcpyHostToDevice, st));
     G.rres = drr;
     G.rcg = drc;
+    auto* dgj = reinterpret_cast<dfi::GramJob*>(gp + rrbytes + rcbytes);
+    if (!gjobs.empty())
+      HIP_TRY(hipMemcpyAsync(dgj, gjobs.data(), gjobs.size() * sizeof(dfi::GramJob), hipMemcpyHostToDevice, st));
+    G.gram = dgj;
   }
   HIP_TRY(hipStreamSynchronize(st));   // the host tables go out of scope; the graph reads the device copies
 

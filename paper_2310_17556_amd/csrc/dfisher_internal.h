@@ -42,6 +42,16 @@ hipError_t gram_launch_split(const GramPlan& p, const uint16_t* hi, const uint16
 // Scaled-FP8 Gram from the row pass's column-blocked codes and E8M0 scales (see rowpass_launch).
 hipError_t gram_launch_fp8(const GramPlan& p, const uint8_t* q, const uint8_t* sc, int64_t ldq, float* part,
                            hipStream_t st);
+// Many problems' scaled-FP8 Grams in one launch: job j (plan-checked like gram_launch_fp8: kcap =
+// its ldq) owns workgroups [wg0, wg0 + ntri nslice), wg0 a multiple of 8, jobs sorted by wg0;
+// nwg = the last wg0 + ntri nslice.
+struct GramJob {
+  const uint8_t* q;
+  const uint8_t* sc;
+  float* part;
+  int64_t n, kcap, ntri, nslice, kslice, wg0;
+};
+hipError_t gram_launch_fp8_grouped(const GramJob* jobs_dev, int njobs, int64_t nwg, hipStream_t st);
 // Row stride of the FP8 codes for m columns (a multiple of 64).
 inline int64_t fp8_ldq(int64_t m) { return (m + 127) / 128 * 128; }   // scale rows: whole 4-byte words
 // W = sum of slices (lower triangle; also upper if mirror), diagonal = d + lambda (d = FP64 row norms).

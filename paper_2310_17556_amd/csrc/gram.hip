@@ -608,12 +608,13 @@ __device__ __forceinline__ i32x8 read_frag(const uint8_t* panel, int r, int h) {
 // lgkmcnt(0) with the other counters left alone (lgkmcnt bits [11:8]).
 #define DFI_WAIT_LGKM0() __builtin_amdgcn_s_waitcnt(15 | (3 << 14) | (7 << 4))
 
-__global__ void __launch_bounds__(NT, 1)
-gram_kernel_fp8(const uint8_t* __restrict__ q, const uint8_t* __restrict__ sc, int64_t n, int64_t kcap,
-                int64_t ntri, int64_t nslice, int64_t kslice, float* __restrict__ part) {
+// The work item of workgroup w (the kernel body; the grouped form below runs it for one problem's
+// share of a launch over many problems).
+__device__ __forceinline__ void gram_fp8_body(const uint8_t* __restrict__ q, const uint8_t* __restrict__ sc, int64_t n,
+                                              int64_t kcap, int64_t ntri, int64_t nslice, int64_t kslice,
+                                              float* __restrict__ part, int64_t w) {
   __shared__ Stage stg0, stg1, stg2, stg3;
 
-  const int64_t w = blockIdx.x;
   const int64_t xcd = w & 7;
   const int64_t local = w >> 3;
   const int64_t qq = uni64(local / ntri);
@@ -814,6 +815,34 @@ gram_kernel_fp8(const uint8_t* __restrict__ q, const uint8_t* __restrict__ sc, i
         const int col = wc * WT + j * 32 + l32;
         out[row * T + col] = active ? acc[i][j][r] : 0.f;
       }
+}
+
+__global__ void __launch_bounds__(NT, 1)
+gram_kernel_fp8(const uint8_t* __restrict__ q, const uint8_t* __restrict__ sc, int64_t n, int64_t kcap,
+                int64_t ntri, int64_t nslice, int64_t kslice, float* __restrict__ part) {
+  gram_fp8_body(q, sc, n, kcap, ntri, nslice, kslice, part, blockIdx.x);
+}
+
+// Many problems' scaled-FP8 Grams in one launch: job j owns workgroups [wg0_j, wg0_j + ntri_j
+// nslice_j) and runs its (tile, slice) work items exactly as its own launch would (wg0_j a
+// multiple of 8, so each work item keeps its XCD), writing its own partial tiles. The jobs are
+// ordered by the work of one item (slice length), largest first, so the dispatcher hands the
+// largest items out first and the small ones fill the end of the launch. A workgroup finds its job
+// by bisection (uniform, scalar loads).
+__global__ void __launch_bounds__(NT, 1)
+gram_kernel_fp8_grouped(const GramJob* __restrict__ jobs, int njobs) {
+  const int64_t w = blockIdx.x;
+  int lo = 0, hi = njobs - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (jobs[mid].wg0 <= w) lo = mid;
+    else hi = mid - 1;
+  }
+  lo = __builtin_amdgcn_readfirstlane(lo);
+  const GramJob& j = jobs[lo];
+  const int64_t wl = w - j.wg0;
+  if (wl < 0 || wl >= j.ntri * j.nslice) return;
+  gram_fp8_body(j.q, j.sc, j.n, j.kcap, j.ntri, j.nslice, j.kslice, j.part, wl);
 }
 
 }  // namespace v3
@@ -1162,6 +1191,12 @@ hipError_t gram_launch_fp8(const GramPlan& p, const uint8_t* q, const uint8_t* s
   if ((ldq & 127) != 0 || ldq < p.m || p.nslice * p.kslice < ldq || (p.kslice & 63) != 0) return hipErrorInvalidValue;
   hipLaunchKernelGGL(v3::gram_kernel_fp8, grid, dim3(v3::NT), 0, st, q, sc, p.n, ldq, p.ntri, p.nslice, p.kslice,
                      part);
+  return hipGetLastError();
+}
+
+hipError_t gram_launch_fp8_grouped(const GramJob* jobs_dev, int njobs, int64_t nwg, hipStream_t st) {
+  if (njobs < 1 || nwg < 1 || nwg > 0x7FFFFFFF) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(v3::gram_kernel_fp8_grouped, dim3((unsigned)nwg), dim3(v3::NT), 0, st, jobs_dev, njobs);
   return hipGetLastError();
 }
 
